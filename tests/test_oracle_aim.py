@@ -1,0 +1,140 @@
+"""AIM pins: projection moments (exact polynomial integrals), FFT
+convolution against the literal double sum, far-part symmetry, the
+pre-correction identity and the AIM accuracy on separated pairs."""
+import math
+from itertools import product
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import aim, kernels, physics as ph, zfill
+from oracle_cases import dense_z, l2_band_params, sphere
+
+FC = 300e6
+
+
+def _aim():
+    s = sphere()
+    dt, ng = l2_band_params()
+    return aim.AIM(s, 16, 0.3 * ph.C0 / FC, dt, FC, ng), dt, ng
+
+
+_CACHE = {}
+
+
+def get_aim():
+    if "a" not in _CACHE:
+        _CACHE["a"] = _aim()
+    return _CACHE["a"]
+
+
+def _poly_mul(p, q):
+    out = {}
+    for ea, ca in p.items():
+        for eb, cb in q.items():
+            e = tuple(x + y for x, y in zip(ea, eb))
+            out[e] = out.get(e, 0.0) + ca * cb
+    return out
+
+
+def _linear(vals):
+    """Linear function with vertex values vals -> barycentric polynomial."""
+    return {(1, 0, 0): vals[0], (0, 1, 0): vals[1], (0, 0, 1): vals[2]}
+
+
+def _integrate(p, area):
+    return sum(c * 2 * area * math.factorial(a) * math.factorial(b) * math.factorial(d)
+               / math.factorial(a + b + d + 2) for (a, b, d), c in p.items())
+
+
+def test_projection_matches_moments_exactly():
+    A, _, _ = get_aim()
+    s, g = A.surf, A.grid
+    for k in (0, 17, 123, 250, 479):
+        for (a, b, c) in product(range(4), repeat=3):
+            for comp in range(4):
+                exact = 0.0
+                for half in range(2):
+                    t = s.t[k, half]
+                    V = s.tv[t]
+                    loc = (V - g.x0) / g.h - A.i0[k]            # local stencil coords of vertices
+                    p = {(0, 0, 0): 1.0}
+                    for axis, power in ((0, a), (1, b), (2, c)):
+                        for _ in range(power):
+                            p = _poly_mul(p, _linear(loc[:, axis]))
+                    if comp < 3:
+                        coef = s.s[k, half] * s.length[k] / (2 * s.area[t])
+                        lin = _linear((V[:, comp] - s.xyz[s.free[k, half], comp]) * coef)
+                        p = _poly_mul(p, lin)
+                    else:
+                        p = {e: v * s.s[k, half] * s.length[k] / s.area[t] for e, v in p.items()}
+                    exact += _integrate(p, s.area[t])
+                j = np.arange(64)
+                jx, jy, jz = j % 4, (j // 4) % 4, j // 16
+                moment = np.sum(A.L[k, comp] * jx ** a * jy ** b * jz ** c)
+                scale = np.abs(A.L[k, comp]).sum() * 27
+                assert abs(moment - exact) <= 1e-12 * scale
+
+
+def test_fft_convolution_equals_direct_sum():
+    A, dt, ng = get_aim()
+    x = W.complex_normal(1, A.surf.ns)
+    for m in range(ng + 1):
+        y1 = A.far_matvec(m, x)
+        y2 = A.far_matvec(m, x, direct=True)
+        assert np.linalg.norm(y1 - y2) <= 1e-13 * np.linalg.norm(y2)
+
+
+def test_circulant_embedding_small_grid():
+    rng = np.random.default_rng(3)
+    tab = rng.standard_normal((3, 4, 5)) + 1j * rng.standard_normal((3, 4, 5))
+    q = rng.standard_normal((3, 4, 5)) + 1j * rng.standard_normal((3, 4, 5))
+    circ = aim.circulant(tab)
+    qq = np.zeros((6, 8, 10), complex)
+    qq[:3, :4, :5] = q
+    p = np.fft.ifftn(np.fft.fftn(circ) * np.fft.fftn(qq))[:3, :4, :5]
+    ref = np.zeros_like(q)
+    for z, y, x in product(range(3), range(4), range(5)):
+        for z2, y2, x2 in product(range(3), range(4), range(5)):
+            ref[z, y, x] += tab[abs(z - z2), abs(y - y2), abs(x - x2)] * q[z2, y2, x2]
+    assert np.max(np.abs(p - ref)) < 1e-13 * np.max(np.abs(ref))
+
+
+def test_far_part_symmetric_and_pairs_match_dense():
+    A, dt, ng = get_aim()
+    for m in (0, 2):
+        Zf = A.far_dense(m)
+        assert np.linalg.norm(Zf - Zf.T) <= 1e-14 * np.linalg.norm(Zf)
+        r, c = A.rows[::37], A.cols[::37]
+        assert np.max(np.abs(A.far_pairs(m, r, c) - Zf[r, c])) <= 1e-13 * np.abs(Zf).max()
+
+
+def test_precorrection_restores_exact_near_entries():
+    A, dt, ng = get_aim()
+    Z = dense_z(dt, FC, ng)
+    s = A.surf
+
+    def exact(rows, cols, ms):
+        return zfill.assemble_pairs(s, rows, cols, [kernels.EnvelopeKernel(m, dt, FC) for m in ms])
+
+    vals = A.near_values(exact)
+    for m in range(A.mn + 1):
+        zf = A.far_pairs(m, A.rows, A.cols)
+        got = vals[m] + zf
+        ref = Z[m][A.rows, A.cols]
+        assert np.max(np.abs(got - ref)) <= 1e-12 * np.abs(Z[m]).max()
+    # beyond M_n both parts vanish on every near pair
+    if A.mn < ng:
+        assert np.abs(Z[A.mn + 1][A.rows, A.cols]).max() == 0.0
+        assert np.abs(A.far_pairs(A.mn + 1, A.rows, A.cols)).max() == 0.0
+
+
+def test_aim_far_accuracy_on_separated_pairs():
+    A, dt, ng = get_aim()
+    Z = dense_z(dt, FC, ng)
+    c = A.surf.c
+    sep = np.linalg.norm(c[:, None] - c[None], axis=2) > A.d_near
+    Zf = A.far_dense(0)
+    err = np.linalg.norm((Zf - Z[0])[sep]) / np.linalg.norm(Z[0][sep])
+    assert err < 0.05
