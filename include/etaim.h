@@ -1,0 +1,223 @@
+/*
+ * etaim.h - C ABI of the MI355X envelope-tracking adaptive integral method
+ * (ET-AIM) marching library (Kaur & Yilmaz, "Empirical Comparison of
+ * Envelope-Tracking and Time-Domain Adaptive Integral Methods for Surface
+ * Integral Equations", arXiv 1408.7060).
+ *
+ * The calls follow the paper's statement of the problem (Sec. 3, eq. (3)-(4)
+ * and Sec. 4, eq. (5)): a PEC surface meshed with triangles and expanded in
+ * RWG functions S_k, a causal piecewise-polynomial temporal basis T of order
+ * Q = 3, a time step dt and the incident-envelope excitation V_l go in; the
+ * current-envelope samples I_l, l = 1..N_t, and scattered far-field
+ * envelopes come out.  The method's parameters (auxiliary grid size,
+ * near-zone distance, solver tolerance) are those of Sec. 5.1.
+ *
+ * Conventions (every call):
+ *  - Return value: ETAIM_OK (0) or a negative ETAIM_E* code; the message of
+ *    the last failure on the calling thread is etaim_last_error().  No C++
+ *    exception crosses this boundary.
+ *  - Complex arrays are interleaved (re, im) float64 pairs ("complex128"),
+ *    row-major, so they match the storage of torch.complex128 tensors.
+ *  - Mesh, RWG and parameter structs are HOST pointers, read during the call
+ *    only.  Excitation, current, history, field and output arrays are DEVICE
+ *    pointers on the context's device; the caller owns them.
+ *  - The context owns every internal device buffer (projection weights,
+ *    Green spectra, near-zone matrices, history rings, Krylov space) and
+ *    frees them in etaim_destroy.
+ *  - A context is bound to the device current at etaim_create and to the
+ *    HIP stream given there; calls are ordered on that stream.  Calls that
+ *    return statistics synchronise the stream.  Contexts are not
+ *    thread-safe: use one context per thread.
+ *  - Input validation happens before any device work: an invalid argument
+ *    returns ETAIM_EINVAL and leaves the context unchanged.
+ */
+#ifndef ETAIM_H
+#define ETAIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ETAIM_OK 0
+#define ETAIM_EINVAL (-1)      /* bad argument, mesh, RWG table or parameter */
+#define ETAIM_ENOMEM (-2)      /* device or host allocation failed */
+#define ETAIM_EHIP (-3)        /* HIP runtime error */
+#define ETAIM_ENOCONV (-4)     /* GMRES reached maxit at some step */
+#define ETAIM_ENONFINITE (-5)  /* NaN/Inf in a residual */
+#define ETAIM_EUNSTABLE (-6)   /* late-time growth detector fired */
+#define ETAIM_EUNSUPPORTED (-7)
+
+/* working precision of the grid/FFT/near-zone arithmetic (Krylov is FP64) */
+#define ETAIM_FP64 0
+#define ETAIM_FP32 1
+
+/* flags */
+#define ETAIM_F_CONTINUE_ON_NOCONV 1 /* keep marching after a step hits maxit */
+#define ETAIM_F_FAIL_ON_UNSTABLE 2   /* return ETAIM_EUNSTABLE instead of only flagging */
+#define ETAIM_F_GRAPH 4              /* replay captured HIP graphs for GMRES iterations */
+
+typedef struct etaim_ctx etaim_ctx;
+
+/* Triangle mesh of the closed PEC surface (Sec. 3, RWG on a triangular
+ * mesh).  xyz: host float64 [nv][3] in metres; tri: host int32 [nt][3]
+ * vertex indices, counter-clockwise about the outward normal. */
+typedef struct {
+    int32_t nv;
+    const double *xyz;
+    int32_t nt;
+    const int32_t *tri;
+} etaim_mesh;
+
+/* RWG table: host int32 [ns][4] = {t_plus, t_minus, edge_v0, edge_v1}.
+ * T+ must contain the directed edge v0 -> v1 in its counter-clockwise
+ * order, T- the directed edge v1 -> v0; the basis current flows from T+
+ * into T- (S_k = +l/(2A+) (r - v+) on T+, -l/(2A-) (r - v-) on T-). */
+typedef struct {
+    int32_t ns;
+    const int32_t *idx;
+} etaim_rwg;
+
+typedef struct {
+    double fc;          /* centre (carrier) frequency f_c [Hz], > 0 */
+    double dt;          /* time step [s]; 0 => derived (see ng, beta, f_bw) */
+    double beta;        /* dt = beta / f_bw when dt == 0 and ng == 0 (Sec. 3) */
+    double f_bw;        /* essential half bandwidth [Hz] for the beta rule */
+    int32_t nt_steps;   /* N_t >= 1 */
+    int32_t order;      /* CPPIF order Q; only 3 is supported */
+    int32_t grid[3];    /* auxiliary grid nodes per axis (>= 8 each); padded
+                           FFT lengths 2*grid must be products of 2 and 3 */
+    double d_near;      /* near-zone distance [m] between basis centres */
+    int32_t ng;         /* history depth N_g; 0 => floor(Rmax/(c dt) + Q).
+                           With dt == 0 and ng > 0: dt = Rmax/(c (ng - Q + 1/2)) */
+    int32_t precision;  /* ETAIM_FP64 or ETAIM_FP32 */
+    int32_t batch;      /* B >= 1 excitations marched together */
+    double tol;         /* GMRES relative residual tolerance (Sec. 5.1) */
+    int32_t restart;    /* GMRES restart length, 1..200 */
+    int32_t maxit;      /* max GMRES iterations per step */
+    int32_t flags;      /* ETAIM_F_* */
+} etaim_params;
+
+typedef struct {
+    double dt, h, origin[3], rmax, stencil_radius;
+    int32_t ns, ng, mn, nnz, batch, precision;
+    int32_t grid[3], padded[3];
+    int64_t device_bytes;
+} etaim_derived;
+
+typedef struct {
+    int32_t steps_done;        /* steps completed by the last march */
+    int32_t total_iters;       /* GMRES iterations summed over steps and columns */
+    int32_t max_iters;         /* largest per-step, per-column iteration count */
+    int32_t first_noconv_step; /* -1 if every step converged */
+    int32_t unstable_step;     /* -1, or the step where late-time growth was flagged */
+    double ms_rhs, ms_solve, ms_commit, ms_total;  /* device time per phase */
+    double max_rel_residual;   /* largest final relative residual (estimate) */
+    int32_t *iters_per_step;   /* optional caller host buffer [N_t] (or NULL) */
+} etaim_stats;
+
+/* Context set-up (the paper's "matrix fill", Sec. 4 stages (i)-(iv), not
+ * timed in marching): validates the mesh and RWG table, derives dt, N_g,
+ * the grid (h, origin) and the near-zone depth M_n, computes the
+ * moment-matching projection (moments up to order 3, Sec. 5.1), the grid
+ * Green functions and their spectra (m = 0..N_g), the exact near-zone
+ * entries and their pre-correction, and allocates the history rings.
+ * *out receives the context; hip_stream is a hipStream_t (NULL = default).
+ * Errors: EINVAL (invalid mesh/RWG/params, a stencil outside the grid),
+ * ENOMEM, EHIP, EUNSUPPORTED (order != 3, radix other than 2/3). */
+int etaim_create(etaim_ctx **out, const etaim_mesh *mesh, const etaim_rwg *rwg,
+                 const etaim_params *params, void *hip_stream);
+
+/* Derived quantities of a context (host struct filled in). */
+int etaim_describe(const etaim_ctx *ctx, etaim_derived *out);
+
+/* Excitation vectors of the cosine-modulated Gaussian plane wave, eq. (1)
+ * (Sec. 2.2), tested at t = l dt, l = 1..N_t (eq. (4)):
+ *   V_l[k] = int S_k . (d/dt + j w_c) E~(r, l dt) dS,
+ *   E~ = p g(tau) exp(-j w_c (r.k/c + t_d)), g = exp(-tau^2/2 sigma^2),
+ *   tau = t - r.k/c - t_d.
+ * khat, phat: host float64 [nb][3] (unit, orthogonal); sigma, td [s].
+ * V: device complex128 [N_t][nb][ns].  nb must equal the context batch. */
+int etaim_excitation_planewave(etaim_ctx *ctx, int32_t nb, const double *khat,
+                               const double *phat, double sigma, double td, void *V);
+
+/* Forward march of eq. (5) (Sec. 4 stage (v), GMRES with diagonal
+ * preconditioning, Sec. 5.1): for l = 1..n solve
+ *   (Z0near + Z0fft) I_l = V_l - sum_{m=1}^{N_g} (Zmnear + Zmfft) I_{l-m},
+ * starting from a zero history, n = nsteps (1..N_t; 0 means N_t).
+ * V, I_out: device complex128 [N_t][B][ns] (the first n steps are used).
+ * stats may be NULL.  Errors: ENOCONV (unless CONTINUE_ON_NOCONV),
+ * ENONFINITE, EUNSTABLE (with FAIL_ON_UNSTABLE). */
+int etaim_march(etaim_ctx *ctx, const void *V, void *I_out, int32_t nsteps, etaim_stats *stats);
+
+/* y = (Zmnear + Zmfft) x for 0 <= m <= N_g (Sec. 4 stages (i)-(iv)).
+ * x, y: device complex128 [B][ns]. */
+int etaim_apply_z(etaim_ctx *ctx, int32_t m, const void *x, void *y);
+
+/* Delayed field b = sum_{m=1}^{N_g} (Zmnear + Zmfft) hist[m-1] for an
+ * injected history hist[m-1] = I_{l-m} (the right-hand-side sum of eq. (5)).
+ * hist: device complex128 [N_g][B][ns]; b: device complex128 [B][ns]. */
+int etaim_delayed_field(etaim_ctx *ctx, const void *hist, void *b);
+
+/* Scattered far-field envelopes (Sec. 2.4 post-processing):
+ *   u_d(l dt) = -(mu/4pi) [I - d d] sum_{k',l'} I_l'[k'] int S_k'
+ *               [T'(tau')/dt + j w_c T(tau')] exp(j k_c d.r') dS',
+ *   tau' = l - l' + d.r'/(c dt).
+ * dirs: host float64 [nd][3] unit vectors; I: device complex128
+ * [N_t][B][ns]; U: device complex128 [N_t][B][nd][3]. */
+int etaim_farfield(etaim_ctx *ctx, int32_t nd, const double *dirs, const void *I, void *U);
+
+/* Adjoint of etaim_farfield: S = F^H Ubar, S device complex128 [N_t][B][ns]. */
+int etaim_farfield_adjoint(etaim_ctx *ctx, int32_t nd, const double *dirs, const void *Ubar,
+                           void *S);
+
+/* Adjoint march, backward in time with the conjugate Green spectra and
+ * conjugate near-zone values (the operators are complex-symmetric):
+ *   Z0^H lambda_l = S_l - sum_{m=1}^{N_g} Zm^H lambda_{l+m}, l = N_t..1.
+ * S, Lambda: device complex128 [N_t][B][ns].  For J = |F I|^2 and
+ * S = F^H F I, dJ/d conj(V) = Lambda. */
+int etaim_adjoint_march(etaim_ctx *ctx, const void *S, void *Lambda, etaim_stats *stats);
+
+/* Kernel classes traced by etaim_set_profiling (HIP events recorded on the
+ * context stream around every launch of the class, with the algorithmic
+ * bytes of that launch: compulsory reads + writes of its inputs/outputs). */
+#define ETAIM_K_ANTERP_X 0    /* anterpolation gather + forward x-FFT */
+#define ETAIM_K_FFT_Y_FWD 1   /* forward y-FFT pass */
+#define ETAIM_K_ZGREEN 2      /* z-FFT, Green-spectrum multiply, inverse z-FFT */
+#define ETAIM_K_FFT_Y_INV 3   /* inverse y-FFT pass */
+#define ETAIM_K_FFT_X_INV 4   /* inverse x-FFT pass */
+#define ETAIM_K_INTERP_NEAR 5 /* interpolation + near-zone SpMV */
+#define ETAIM_K_ZDELAYED 6    /* k-space temporal sum over the history + inverse z-FFT */
+#define ETAIM_K_ZCOMMIT 7     /* forward z-FFT into the history ring */
+#define ETAIM_K_KRYLOV 8      /* GMRES vector kernels */
+#define ETAIM_K_COUNT 9
+
+/* Turn per-class kernel tracing on (1) or off (0); turning it on clears the
+ * counters.  Tracing adds two event records per launch. */
+int etaim_set_profiling(etaim_ctx *ctx, int32_t on);
+
+/* Accumulated device time [ms], algorithmic bytes and launch count of one
+ * kernel class since tracing was turned on (host outputs). */
+int etaim_kernel_stats(const etaim_ctx *ctx, int32_t cls, double *ms, double *bytes, int64_t *launches);
+
+/* Copy a set-up array to host memory for inspection.  what: 0 projection
+ * weights float64 [ns][4][64], 1 stencil corners int32 [ns][3], 2 near-zone
+ * row pointers int32 [ns+1], 3 column indices int32 [nnz], 4 pre-corrected
+ * near values complex128 [mn+1][nnz] (m-major), 5 diagonal of Z0 complex128
+ * [ns], 6 folded Green spectra complex128 [ng+1][2][gz+1][gy+1][gx+1]
+ * (g = grid size, already divided by the padded size).  bytes must equal the
+ * array size. */
+int etaim_export(const etaim_ctx *ctx, int32_t what, void *host, size_t bytes);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *etaim_last_error(void);
+
+/* Frees the context and everything it owns (NULL is a no-op). */
+void etaim_destroy(etaim_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ETAIM_H */

@@ -235,9 +235,11 @@ class AIM:
         Z += Lfull[3] @ (dense_node_matrix(self.grid, self.GP[m]) @ Lfull[3].T)
         return Z
 
-    def far_pairs(self, m: int, rows, cols) -> np.ndarray:
-        """Z^FFT_m[rows[p], cols[p]] by the literal stencil double sum."""
-        out = np.zeros(len(rows), dtype=np.complex128)
+    def far_pairs(self, m, rows, cols) -> np.ndarray:
+        """Z^FFT_m[rows[p], cols[p]] by the literal stencil double sum; m may be
+        a list (result [len(m), P])."""
+        ms = [m] if np.isscalar(m) else list(m)
+        out = np.zeros((len(ms), len(rows)), dtype=np.complex128)
         nx, ny, nz = self.grid.n
         for s in range(0, len(rows), 512):
             r, c = rows[s:s + 512], cols[s:s + 512]
@@ -245,12 +247,14 @@ class AIM:
             ia = np.stack([na % nx, (na // nx) % ny, na // (nx * ny)], -1)
             ib = np.stack([nb % nx, (nb // nx) % ny, nb // (nx * ny)], -1)
             d = np.abs(ia[:, :, None, :] - ib[:, None, :, :])       # [p,64,64,3]
-            GA = self.GA[m][d[..., 2], d[..., 1], d[..., 0]]
-            GP = self.GP[m][d[..., 2], d[..., 1], d[..., 0]]
-            for cc in range(3):
-                out[s:s + 512] += np.einsum("pn,pnq,pq->p", self.L[r, cc], GA, self.L[c, cc])
-            out[s:s + 512] += np.einsum("pn,pnq,pq->p", self.L[r, 3], GP, self.L[c, 3])
-        return out
+            flat = (d[..., 2] * ny + d[..., 1]) * nx + d[..., 0]
+            sA = sum(np.einsum("pn,pq->pnq", self.L[r, cc], self.L[c, cc]) for cc in range(3))
+            sP = np.einsum("pn,pq->pnq", self.L[r, 3], self.L[c, 3])
+            for i, mm in enumerate(ms):
+                GA = self.GA[mm].ravel()[flat]
+                GP = self.GP[mm].ravel()[flat]
+                out[i, s:s + 512] = np.einsum("pnq,pnq->p", sA, GA) + np.einsum("pnq,pnq->p", sP, GP)
+        return out[0] if np.isscalar(m) else out
 
     # ---- near part
     def near_values(self, zfill_pairs) -> np.ndarray:
@@ -258,7 +262,7 @@ class AIM:
         returns the exact Z_m entries [len(ms), nnz]."""
         ms = list(range(self.mn + 1))
         exact = zfill_pairs(self.rows, self.cols, ms)
-        far = np.stack([self.far_pairs(m, self.rows, self.cols) for m in ms])
+        far = self.far_pairs(ms, self.rows, self.cols)
         return exact - far
 
     def near_matvec(self, vals_m: np.ndarray, x: np.ndarray) -> np.ndarray:

@@ -1,0 +1,192 @@
+"""MI355X ET-AIM marching library: Python binding of include/etaim.h.
+
+Arguments are marshalled to the C ABI of libetaim.so; every step of the
+method runs in the library's HIP kernels.  torch supplies device memory and
+the stream.  The library must have been built (``python -m
+paper_1408_7060_amd.build``); there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+from ctypes import POINTER, byref, c_double, c_int32, c_void_p
+
+import numpy as np
+
+from . import _lib
+from ._lib import FP32, FP64, EtaimError, Stats
+
+__all__ = ["Problem", "EtaimMarch", "EtaimError", "FP32", "FP64"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dptr(t) -> int:
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor")
+    return t.data_ptr()
+
+
+def _stats_dict(st: Stats, iters) -> dict:
+    d = {f: getattr(st, f) for f, _ in Stats._fields_ if f != "iters_per_step"}
+    d["iters_per_step"] = iters
+    return d
+
+
+class Problem:
+    """One ET-AIM problem on the current HIP device (etaim_create)."""
+
+    def __init__(self, xyz, tri, rwg, *, fc: float, nt: int, grid, d_near: float, dt: float = 0.0,
+                 beta: float = 0.0, f_bw: float = 0.0, ng: int = 0, precision: int = FP64, batch: int = 1,
+                 tol: float = 1e-6, restart: int = 50, maxit: int = 1000, flags: int = 0, stream=None):
+        torch = _torch()
+        lib = _lib.load()
+        self._xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        self._tri = np.ascontiguousarray(tri, dtype=np.int32)
+        self._rwg = np.ascontiguousarray(rwg, dtype=np.int32)
+        mesh = _lib.Mesh(len(self._xyz), self._xyz.ctypes.data_as(POINTER(c_double)), len(self._tri),
+                         self._tri.ctypes.data_as(POINTER(c_int32)))
+        r = _lib.Rwg(len(self._rwg), self._rwg.ctypes.data_as(POINTER(c_int32)))
+        g = np.broadcast_to(np.asarray(grid, dtype=np.int32), (3,))
+        p = _lib.Params(fc=fc, dt=dt, beta=beta, f_bw=f_bw, nt_steps=nt, order=3,
+                        grid=(c_int32 * 3)(*[int(v) for v in g]), d_near=d_near, ng=ng, precision=precision,
+                        batch=batch, tol=tol, restart=restart, maxit=maxit, flags=flags)
+        if stream is None and torch.cuda.is_available():
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = c_void_p()
+        _lib.check(lib.etaim_create(byref(h), byref(mesh), byref(r), byref(p),
+                                    c_void_p(stream.cuda_stream if stream is not None else 0)))
+        self._h = h
+        self.nt, self.batch = nt, batch
+        self.info = self.describe()
+        self.ns = self.info["ns"]
+
+    # -- helpers
+    def _dev(self):
+        return _torch().device("cuda", _torch().cuda.current_device())
+
+    def empty(self, *shape):
+        return _torch().empty(shape, dtype=_torch().complex128, device=self._dev())
+
+    def describe(self) -> dict:
+        d = _lib.Derived()
+        _lib.check(_lib.load().etaim_describe(self._h, byref(d)))
+        out = {}
+        for f, _ in _lib.Derived._fields_:
+            v = getattr(d, f)
+            out[f] = list(v) if hasattr(v, "__len__") else v
+        return out
+
+    def excitation(self, khat, phat, sigma: float, td: float):
+        kh = np.ascontiguousarray(np.atleast_2d(khat), dtype=np.float64)
+        ph = np.ascontiguousarray(np.atleast_2d(phat), dtype=np.float64)
+        V = self.empty(self.nt, len(kh), self.ns)
+        _lib.check(_lib.load().etaim_excitation_planewave(
+            self._h, len(kh), kh.ctypes.data_as(POINTER(c_double)), ph.ctypes.data_as(POINTER(c_double)),
+            sigma, td, c_void_p(_dptr(V))))
+        return V
+
+    def march(self, V, out=None, nsteps: int = 0):
+        I = out if out is not None else self.empty(self.nt, self.batch, self.ns)
+        it = np.zeros(self.nt, dtype=np.int32)
+        st = Stats()
+        st.iters_per_step = it.ctypes.data_as(POINTER(c_int32))
+        _lib.check(_lib.load().etaim_march(self._h, c_void_p(_dptr(V)), c_void_p(_dptr(I)), nsteps, byref(st)))
+        return I, _stats_dict(st, it)
+
+    def adjoint_march(self, S):
+        L = self.empty(self.nt, self.batch, self.ns)
+        it = np.zeros(self.nt, dtype=np.int32)
+        st = Stats()
+        st.iters_per_step = it.ctypes.data_as(POINTER(c_int32))
+        _lib.check(_lib.load().etaim_adjoint_march(self._h, c_void_p(_dptr(S)), c_void_p(_dptr(L)), byref(st)))
+        return L, _stats_dict(st, it)
+
+    def apply_z(self, m: int, x):
+        y = self.empty(*x.shape)
+        _lib.check(_lib.load().etaim_apply_z(self._h, m, c_void_p(_dptr(x)), c_void_p(_dptr(y))))
+        return y
+
+    def delayed_field(self, hist):
+        b = self.empty(self.batch, self.ns)
+        _lib.check(_lib.load().etaim_delayed_field(self._h, c_void_p(_dptr(hist)), c_void_p(_dptr(b))))
+        return b
+
+    def farfield(self, dirs, I):
+        d = np.ascontiguousarray(np.atleast_2d(dirs), dtype=np.float64)
+        U = self.empty(self.nt, self.batch, len(d), 3)
+        _lib.check(_lib.load().etaim_farfield(self._h, len(d), d.ctypes.data_as(POINTER(c_double)),
+                                              c_void_p(_dptr(I)), c_void_p(_dptr(U))))
+        return U
+
+    def farfield_adjoint(self, dirs, U):
+        d = np.ascontiguousarray(np.atleast_2d(dirs), dtype=np.float64)
+        S = self.empty(self.nt, self.batch, self.ns)
+        _lib.check(_lib.load().etaim_farfield_adjoint(self._h, len(d), d.ctypes.data_as(POINTER(c_double)),
+                                                      c_void_p(_dptr(U)), c_void_p(_dptr(S))))
+        return S
+
+    _EXPORT = {"lambda": (0, np.float64, lambda i: (i["ns"], 4, 64)),
+               "corners": (1, np.int32, lambda i: (i["ns"], 3)),
+               "rowptr": (2, np.int32, lambda i: (i["ns"] + 1,)),
+               "col": (3, np.int32, lambda i: (i["nnz"],)),
+               "near": (4, np.complex128, lambda i: (i["mn"] + 1, i["nnz"])),
+               "diag": (5, np.complex128, lambda i: (i["ns"],)),
+               "ghat": (6, np.complex128, lambda i: (i["ng"] + 1, 2, i["grid"][2] + 1, i["grid"][1] + 1,
+                                                     i["grid"][0] + 1))}
+
+    def export(self, what: str) -> np.ndarray:
+        wid, dt, shape = self._EXPORT[what]
+        a = np.empty(shape(self.info), dtype=dt)
+        _lib.check(_lib.load().etaim_export(self._h, wid, a.ctypes.data_as(c_void_p), a.nbytes))
+        return a
+
+    def set_profiling(self, on: bool = True):
+        _lib.check(_lib.load().etaim_set_profiling(self._h, 1 if on else 0))
+
+    def kernel_stats(self) -> dict:
+        out = {}
+        lib = _lib.load()
+        for i, name in enumerate(_lib.KERNEL_CLASSES):
+            ms, by, n = c_double(), c_double(), ctypes.c_int64()
+            _lib.check(lib.etaim_kernel_stats(self._h, i, byref(ms), byref(by), byref(n)))
+            out[name] = {"ms": ms.value, "bytes": by.value, "launches": n.value}
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().etaim_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class EtaimMarch:
+    """torch.autograd.Function: U = F(march(V)) (scattered far-field envelopes
+    at the directions ``dirs``); backward runs the adjoint march:
+    grad_V = Z^-H F^H grad_U."""
+
+    @staticmethod
+    def apply(V, problem: Problem, dirs):
+        torch = _torch()
+
+        class _Fn(torch.autograd.Function):
+            @staticmethod
+            def forward(ctx, v):
+                I, _ = problem.march(v.detach().contiguous())
+                return problem.farfield(dirs, I)
+
+            @staticmethod
+            def backward(ctx, gU):
+                S = problem.farfield_adjoint(dirs, gU.contiguous())
+                lam, _ = problem.adjoint_march(S)
+                return lam
+
+        return _Fn.apply(V)

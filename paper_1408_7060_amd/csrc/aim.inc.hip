@@ -1,0 +1,504 @@
+// ET-AIM grid kernels (Sec. 4 stages (i)-(iv)):
+//  k_fwdx_gather  anterpolation (node-major gather of the projection) fused
+//                 with the forward x-FFT of the zero-padded grid
+//  k_zgreen       forward z-FFT, Green-spectrum multiply, inverse z-FFT
+//  k_zcommit      forward z-FFT into a history-ring slot
+//  k_zdelayed     k-space temporal sum over the history ring, inverse z-FFT
+//  k_interp_near  interpolation (projection transposed) + near-zone SpMV
+// Grid layouts (per excitation b and component c = x,y,z,charge; bc = 4b+c):
+//  A: [bc][z<Nz][y<Ny][kx<Lx]   B: [bc][z<Nz][ky<Ly][kx<Lx]
+//  ring slot: [bc][kz<Lz][ky<Ly][kx<Lx]   P: [bc][z][y][x] (N per bc)
+#pragma once
+#include "fft.inc.hip"
+
+namespace etaim {
+
+struct GridDims {
+    int N[3], L[3], B;
+};
+
+template <typename R>
+__device__ __forceinline__ cplx<R> to_r(zd v) {
+    return cplx<R>{(R)v.x, (R)v.y};
+}
+
+// Anterpolation + forward x-pass.  Block: MR rows (y) of one (z, b), all 4
+// components -> 4*MR lines of length Lx.  x_in: [B][ns] complex128;
+// dinv (optional): right preconditioner diag^-1 [ns].
+template <typename R>
+__global__ void __launch_bounds__(256) k_fwdx_gather(const zd* __restrict__ x_in, const zd* __restrict__ dinv,
+                                                     const int* __restrict__ nptr, const int* __restrict__ nk,
+                                                     const R* __restrict__ nw, cplx<R>* __restrict__ A,
+                                                     const cplx<R>* __restrict__ tw, Radix pl, GridDims g,
+                                                     int mr, int ns, int conj_in) {
+    extern __shared__ unsigned char smem_raw[];
+    const int Lx = g.L[0], Nx = g.N[0], Ny = g.N[1], Nz = g.N[2];
+    const int ldl = Lx + 1, nl = 4 * mr;
+    cplx<R>* b0 = reinterpret_cast<cplx<R>*>(smem_raw);
+    cplx<R>* b1 = b0 + nl * ldl;
+    const int y0 = blockIdx.x * mr, z = blockIdx.y, b = blockIdx.z;
+    const zd* xb = x_in + (size_t)b * ns;
+    for (int e = threadIdx.x; e < mr * Lx; e += blockDim.x) {
+        const int r = e / Lx, x = e - r * Lx;
+        const int y = y0 + r;
+        cplx<R> acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+        if (x < Nx && y < Ny) {
+            const int n = x + Nx * (y + Ny * z);
+            for (int q = nptr[n]; q < nptr[n + 1]; ++q) {
+                const int k = nk[q];
+                zd v = xb[k];
+                if (conj_in) v.y = -v.y;
+                if (dinv) v = v * dinv[k];
+                const cplx<R> vr = to_r<R>(v);
+                const R* w = nw + 4 * (size_t)q;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[c] += w[c] * vr;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) b0[(c * mr + r) * ldl + x] = acc[c];
+    }
+    __syncthreads();
+    cplx<R>* res = lds_fft<R>(b0, b1, nl, ldl, pl, tw, false);
+    for (int e = threadIdx.x; e < nl * Lx; e += blockDim.x) {
+        const int l = e / Lx, kx = e - l * Lx;
+        const int c = l / mr, r = l - c * mr;
+        const int y = y0 + r;
+        if (y < Ny) A[((((size_t)b * 4 + c) * Nz + z) * Ny + y) * Lx + kx] = res[l * ldl + kx];
+    }
+}
+
+__device__ __forceinline__ int fold(int k, int n2) { return k <= n2 / 2 ? k : n2 - k; }
+
+// z-pass with Green multiply, in place on B.  Block: MT consecutive kx at
+// one ky; loops over bc.  G: folded spectra of one m: [2][Nz+1][Ny+1][Nx+1].
+template <typename R>
+__global__ void __launch_bounds__(256) k_zgreen(cplx<R>* __restrict__ Bg, const cplx<R>* __restrict__ G,
+                                                const cplx<R>* __restrict__ tw, Radix pl, GridDims g, int mt,
+                                                int conj_g) {
+    extern __shared__ unsigned char smem_raw[];
+    const int Lx = g.L[0], Ly = g.L[1], Lz = g.L[2], Nz = g.N[2];
+    const int ldl = Lz + 1;
+    cplx<R>* b0 = reinterpret_cast<cplx<R>*>(smem_raw);
+    cplx<R>* b1 = b0 + mt * ldl;
+    const int kx0 = blockIdx.x * mt, ky = blockIdx.y;
+    const size_t plane = (size_t)Ly * Lx;
+    const int gx = g.N[0] + 1, gy = g.N[1] + 1, gz = g.N[2] + 1;
+    const int fy = fold(ky, Ly);
+    for (int bc = 0; bc < 4 * g.B; ++bc) {
+        const int t = (bc & 3) == 3 ? 1 : 0;
+        cplx<R>* col = Bg + (size_t)bc * Nz * plane + (size_t)ky * Lx;
+        for (int e = threadIdx.x; e < mt * Lz; e += blockDim.x) {
+            const int z = e / mt, l = e - z * mt;
+            const int kx = kx0 + l;
+            cplx<R> v{0, 0};
+            if (kx < Lx && z < Nz) v = col[(size_t)z * plane + kx];
+            b0[l * ldl + z] = v;
+        }
+        __syncthreads();
+        cplx<R>* res = lds_fft<R>(b0, b1, mt, ldl, pl, tw, false);
+        cplx<R>* oth = res == b0 ? b1 : b0;
+        for (int e = threadIdx.x; e < mt * Lz; e += blockDim.x) {
+            const int l = e / Lz, kz = e - l * Lz;
+            const int kx = kx0 + l;
+            cplx<R> gv{0, 0};
+            if (kx < Lx) {
+                gv = G[(((size_t)t * gz + fold(kz, Lz)) * gy + fy) * gx + fold(kx, Lx)];
+                if (conj_g) gv.y = -gv.y;
+            }
+            oth[l * ldl + kz] = res[l * ldl + kz] * gv;
+        }
+        __syncthreads();
+        cplx<R>* res2 = lds_fft<R>(oth, res, mt, ldl, pl, tw, true);
+        for (int e = threadIdx.x; e < mt * Nz; e += blockDim.x) {
+            const int z = e / mt, l = e - z * mt;
+            const int kx = kx0 + l;
+            if (kx < Lx) col[(size_t)z * plane + kx] = res2[l * ldl + z];
+        }
+        __syncthreads();
+    }
+}
+
+// Forward z-pass into a ring slot [bc][kz][ky][kx].
+template <typename R>
+__global__ void __launch_bounds__(256) k_zcommit(const cplx<R>* __restrict__ Bg, cplx<R>* __restrict__ slot,
+                                                 const cplx<R>* __restrict__ tw, Radix pl, GridDims g, int mt) {
+    extern __shared__ unsigned char smem_raw[];
+    const int Lx = g.L[0], Ly = g.L[1], Lz = g.L[2], Nz = g.N[2];
+    const int ldl = Lz + 1;
+    cplx<R>* b0 = reinterpret_cast<cplx<R>*>(smem_raw);
+    cplx<R>* b1 = b0 + mt * ldl;
+    const int kx0 = blockIdx.x * mt, ky = blockIdx.y;
+    const size_t plane = (size_t)Ly * Lx;
+    for (int bc = 0; bc < 4 * g.B; ++bc) {
+        const cplx<R>* col = Bg + (size_t)bc * Nz * plane + (size_t)ky * Lx;
+        for (int e = threadIdx.x; e < mt * Lz; e += blockDim.x) {
+            const int z = e / mt, l = e - z * mt;
+            const int kx = kx0 + l;
+            cplx<R> v{0, 0};
+            if (kx < Lx && z < Nz) v = col[(size_t)z * plane + kx];
+            b0[l * ldl + z] = v;
+        }
+        __syncthreads();
+        cplx<R>* res = lds_fft<R>(b0, b1, mt, ldl, pl, tw, false);
+        cplx<R>* o = slot + (size_t)bc * Lz * plane + (size_t)ky * Lx;
+        for (int e = threadIdx.x; e < mt * Lz; e += blockDim.x) {
+            const int kz = e / mt, l = e - kz * mt;
+            const int kx = kx0 + l;
+            if (kx < Lx) o[(size_t)kz * plane + kx] = res[l * ldl + kz];
+        }
+        __syncthreads();
+    }
+}
+
+// k-space temporal sum acc = sum_{m=1}^{nm} G_m . ring[(cur - m) mod ng],
+// then inverse z-pass into B (z < Nz).  G: folded spectra [ng+1][2][...].
+template <typename R>
+__global__ void __launch_bounds__(256) k_zdelayed(const cplx<R>* __restrict__ ring, const cplx<R>* __restrict__ G,
+                                                  cplx<R>* __restrict__ Bg, const cplx<R>* __restrict__ tw,
+                                                  Radix pl, GridDims g, int mt, int ng, int cur, int nm,
+                                                  int conj_g) {
+    extern __shared__ unsigned char smem_raw[];
+    const int Lx = g.L[0], Ly = g.L[1], Lz = g.L[2], Nz = g.N[2];
+    const int ldl = Lz + 1;
+    cplx<R>* b0 = reinterpret_cast<cplx<R>*>(smem_raw);
+    cplx<R>* b1 = b0 + mt * ldl;
+    const int kx0 = blockIdx.x * mt, ky = blockIdx.y;
+    const size_t plane = (size_t)Ly * Lx;
+    const size_t slot_sz = (size_t)4 * g.B * Lz * plane;
+    const int gx = g.N[0] + 1, gy = g.N[1] + 1, gz = g.N[2] + 1;
+    const size_t gsz = (size_t)2 * gz * gy * gx;
+    const int fy = fold(ky, Ly);
+    for (int bc = 0; bc < 4 * g.B; ++bc) {
+        const int t = (bc & 3) == 3 ? 1 : 0;
+        for (int e = threadIdx.x; e < mt * Lz; e += blockDim.x) {
+            const int kz = e / mt, l = e - kz * mt;
+            const int kx = kx0 + l;
+            cplx<R> acc{0, 0};
+            if (kx < Lx) {
+                const size_t gi = (((size_t)t * gz + fold(kz, Lz)) * gy + fy) * gx + fold(kx, Lx);
+                const size_t ri = (size_t)bc * Lz * plane + (size_t)kz * plane + (size_t)ky * Lx + kx;
+                for (int m = 1; m <= nm; ++m) {
+                    int s = (cur - m) % ng;
+                    if (s < 0) s += ng;
+                    cplx<R> gv = G[(size_t)m * gsz + gi];
+                    if (conj_g) gv.y = -gv.y;
+                    acc += gv * ring[(size_t)s * slot_sz + ri];
+                }
+            }
+            b0[l * ldl + kz] = acc;
+        }
+        __syncthreads();
+        cplx<R>* res = lds_fft<R>(b0, b1, mt, ldl, pl, tw, true);
+        cplx<R>* col = Bg + (size_t)bc * Nz * plane + (size_t)ky * Lx;
+        for (int e = threadIdx.x; e < mt * Nz; e += blockDim.x) {
+            const int z = e / mt, l = e - z * mt;
+            const int kx = kx0 + l;
+            if (kx < Lx) col[(size_t)z * plane + kx] = res[l * ldl + z];
+        }
+        __syncthreads();
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ R wave_sum(R v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Interpolation + near-zone SpMV, one wavefront per basis k.
+// mode 0 (matvec):  y[b][k] = sum_c sum_j L[k][c][j] P[bc][node_j]
+//                              + sum_e val[e][m] (dinv x)[b][col_e]
+// mode 1 (delayed): y[b][k] = V[b][k] - (interp(P) + sum_{m=1}^{nmh}
+//                              val[e][m] hist[(cur-m) mod mn][b][col_e])
+template <typename R>
+__global__ void __launch_bounds__(256) k_interp_near(
+    const cplx<R>* __restrict__ P, const R* __restrict__ lam, const int* __restrict__ i0, GridDims g,
+    const int* __restrict__ rowptr, const int* __restrict__ col, const cplx<R>* __restrict__ val, int mv,
+    const zd* __restrict__ x, const zd* __restrict__ dinv, int m, const zd* __restrict__ hist, int mn, int cur,
+    int nmh, const zd* __restrict__ V, zd* __restrict__ y, int ns, int mode, int conj_v, int conj_x) {
+    const int lane = threadIdx.x & 63;
+    const int k = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (k >= ns) return;
+    const int Nx = g.N[0], Ny = g.N[1], Nz = g.N[2];
+    const size_t N = (size_t)Nx * Ny * Nz;
+    const int jx = lane & 3, jy = (lane >> 2) & 3, jz = lane >> 4;
+    const size_t node = (size_t)(i0[3 * k] + jx) + (size_t)Nx * ((size_t)(i0[3 * k + 1] + jy) + (size_t)Ny * (i0[3 * k + 2] + jz));
+    R w[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) w[c] = lam[(size_t)k * 256 + 64 * c + lane];
+    const int e0 = rowptr[k], e1 = rowptr[k + 1];
+    for (int b = 0; b < g.B; ++b) {
+        cplx<R> acc{0, 0};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc += w[c] * P[((size_t)b * 4 + c) * N + node];
+        for (int e = e0 + lane; e < e1; e += 64) {
+            const int cc = col[e];
+            if (mode == 0) {
+                if (m <= mv - 1) {
+                    cplx<R> v = val[(size_t)e * mv + m];
+                    if (conj_v) v.y = -v.y;
+                    zd xv = x[(size_t)b * ns + cc];
+                    if (conj_x) xv.y = -xv.y;
+                    if (dinv) xv = xv * dinv[cc];
+                    acc += v * to_r<R>(xv);
+                }
+            } else {
+                for (int mm = 1; mm <= nmh; ++mm) {
+                    int s = (cur - mm) % mn;
+                    if (s < 0) s += mn;
+                    cplx<R> v = val[(size_t)e * mv + mm];
+                    if (conj_v) v.y = -v.y;
+                    acc += v * to_r<R>(hist[((size_t)s * g.B + b) * ns + cc]);
+                }
+            }
+        }
+        const R re = wave_sum<R>(acc.x), im = wave_sum<R>(acc.y);
+        if (lane == 0) {
+            const size_t o = (size_t)b * ns + k;
+            if (mode == 0)
+                y[o] = zd{(double)re, (double)im};
+            else
+                y[o] = zd{V[o].x - (double)re, V[o].y - (double)im};
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Set-up kernels (FP64): Green tables, circulant embedding, folding,
+// pre-correction, excitation.
+
+// G[m][t][k][j][i] for |offset| (i,j,k) < (Nx,Ny,Nz); t = 0: (mu/4pi) fA/R,
+// t = 1: (1/4 pi eps) fphi/R; zero at the origin.
+__global__ void k_green_table(zd* __restrict__ G, GridDims g, int ng, double h, EnvKernel K, double sa,
+                              double sp) {
+    const size_t n3 = (size_t)g.N[0] * g.N[1] * g.N[2];
+    const size_t tot = (size_t)(ng + 1) * n3;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot; e += (size_t)gridDim.x * blockDim.x) {
+        const int m = (int)(e / n3);
+        const size_t r = e - (size_t)m * n3;
+        const int i = (int)(r % g.N[0]);
+        const int j = (int)((r / g.N[0]) % g.N[1]);
+        const int k = (int)(r / ((size_t)g.N[0] * g.N[1]));
+        const double R = h * sqrt((double)(i * i + j * j + k * k));
+        zd a{0, 0}, p{0, 0};
+        if (R != 0.0) {
+            zd fa, fp;
+            K.eval(m, R, fa, fp);
+            a = (sa / R) * fa;
+            p = (sp / R) * fp;
+        }
+        G[((size_t)m * 2 + 0) * n3 + r] = a;
+        G[((size_t)m * 2 + 1) * n3 + r] = p;
+    }
+}
+
+// circulant embedding of one |offset| table into the padded [Lz][Ly][Lx] grid
+__global__ void k_circulant(const zd* __restrict__ tab, zd* __restrict__ out, GridDims g) {
+    const size_t tot = (size_t)g.L[0] * g.L[1] * g.L[2];
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot; e += (size_t)gridDim.x * blockDim.x) {
+        const int x = (int)(e % g.L[0]);
+        const int y = (int)((e / g.L[0]) % g.L[1]);
+        const int z = (int)(e / ((size_t)g.L[0] * g.L[1]));
+        zd v{0, 0};
+        if (x != g.N[0] && y != g.N[1] && z != g.N[2]) {
+            const int i = x < g.N[0] ? x : g.L[0] - x;
+            const int j = y < g.N[1] ? y : g.L[1] - y;
+            const int k = z < g.N[2] ? z : g.L[2] - z;
+            v = tab[((size_t)k * g.N[1] + j) * g.N[0] + i];
+        }
+        out[e] = v;
+    }
+}
+
+// keep the unique octant (k <= N per axis) of a padded spectrum, scaled
+__global__ void k_fold(const zd* __restrict__ full, zd* __restrict__ out, GridDims g, double scale) {
+    const int gx = g.N[0] + 1, gy = g.N[1] + 1, gz = g.N[2] + 1;
+    const size_t tot = (size_t)gx * gy * gz;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot; e += (size_t)gridDim.x * blockDim.x) {
+        const int x = (int)(e % gx);
+        const int y = (int)((e / gx) % gy);
+        const int z = (int)(e / ((size_t)gx * gy));
+        const zd v = full[((size_t)z * g.L[1] + y) * g.L[0] + x];
+        out[e] = zd{v.x * scale, v.y * scale};
+    }
+}
+
+// Pre-correction: val[e][m] = exact[e][m] - sum_c sum_{n,n'} L[k][c][n]
+//   G_m^c[|node_n - node_n'|] L[k'][c][n'] for every near pair e = (k, k').
+// One wavefront per pair; lane = local node n of k.
+__global__ void __launch_bounds__(64) k_precorrect(zd* __restrict__ val, const double* __restrict__ lam,
+                                                   const int* __restrict__ i0, const int* __restrict__ rowof,
+                                                   const int* __restrict__ col, const zd* __restrict__ G,
+                                                   GridDims g, int mv, int nnz) {
+    __shared__ double lk2[256];
+    const int e = blockIdx.x;
+    if (e >= nnz) return;
+    const int lane = threadIdx.x;
+    const int k = rowof[e], k2 = col[e];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) lk2[64 * c + lane] = lam[(size_t)k2 * 256 + 64 * c + lane];
+    __syncthreads();
+    const int jx = lane & 3, jy = (lane >> 2) & 3, jz = lane >> 4;
+    const int ax = i0[3 * k] + jx, ay = i0[3 * k + 1] + jy, az = i0[3 * k + 2] + jz;
+    const int bx = i0[3 * k2], by = i0[3 * k2 + 1], bz = i0[3 * k2 + 2];
+    double lk[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) lk[c] = lam[(size_t)k * 256 + 64 * c + lane];
+    const size_t n3 = (size_t)g.N[0] * g.N[1] * g.N[2];
+    for (int m = 0; m < mv; ++m) {
+        const zd* GA = G + ((size_t)m * 2 + 0) * n3;
+        const zd* GP = G + ((size_t)m * 2 + 1) * n3;
+        zd acc{0, 0};
+        for (int q = 0; q < 64; ++q) {
+            const int dx = abs(ax - (bx + (q & 3)));
+            const int dy = abs(ay - (by + ((q >> 2) & 3)));
+            const int dz = abs(az - (bz + (q >> 4)));
+            const size_t off = ((size_t)dz * g.N[1] + dy) * g.N[0] + dx;
+            const zd ga = GA[off], gp = GP[off];
+            const double sA = lk[0] * lk2[q] + lk[1] * lk2[64 + q] + lk[2] * lk2[128 + q];
+            const double sP = lk[3] * lk2[192 + q];
+            acc += sA * ga;
+            acc += sP * gp;
+        }
+        const double re = wave_sum<double>(acc.x), im = wave_sum<double>(acc.y);
+        if (lane == 0) {
+            zd& v = val[(size_t)e * mv + m];
+            v = zd{v.x - re, v.y - im};
+        }
+    }
+}
+
+// Plane-wave excitation, eq. (1) with (d/dt + j w) applied:
+// V[l][b][k] = sum_{half,q} (Sq . p) [g'(tau) + j w g(tau)] exp(-j w (r.k/c + td))
+// Sq[k][h][q][3]: quadrature-weighted basis values; rq: points.
+__global__ void k_excitation(zd* __restrict__ V, const double* __restrict__ Sq, const double* __restrict__ rq,
+                             const double* __restrict__ khat, const double* __restrict__ phat, int nt, int nb,
+                             int ns, double dt, double sigma, double td, double w) {
+    const size_t tot = (size_t)nt * nb * ns;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot; e += (size_t)gridDim.x * blockDim.x) {
+        const int k = (int)(e % ns);
+        const int b = (int)((e / ns) % nb);
+        const int l = (int)(e / ((size_t)ns * nb));
+        const double t = (double)(l + 1) * dt;
+        const double* kh = khat + 3 * b;
+        const double* ph = phat + 3 * b;
+        double sr = 0, si = 0;
+        for (int q = 0; q < 14; ++q) {
+            const double* S = Sq + ((size_t)k * 14 + q) * 3;
+            const double* r = rq + ((size_t)k * 14 + q) * 3;
+            const double rk = (r[0] * kh[0] + r[1] * kh[1] + r[2] * kh[2]) / kC0;
+            const double tau = t - rk - td;
+            const double gg = exp(-tau * tau / (2.0 * sigma * sigma));
+            const double dg = -(tau / (sigma * sigma)) * gg;
+            const double proj = S[0] * ph[0] + S[1] * ph[1] + S[2] * ph[2];
+            const double arg = w * (rk + td);
+            const double c = cos(arg), s = -sin(arg);
+            // (dg + j w gg) (c + j s)
+            sr += proj * (dg * c - w * gg * s);
+            si += proj * (dg * s + w * gg * c);
+        }
+        V[e] = zd{sr, si};
+    }
+}
+
+// Far-field operator taps F[tap][d][x][k] (complex128):
+//   -(mu/4pi) [I - d d] sum_q Sq[k][q] [T'(tau)/dt + j w T(tau)] exp(j kc d.r_q),
+//   tau = (m_lo + tap) + d.r_q/(c dt).
+__global__ void k_farfield_taps(zd* __restrict__ F, const double* __restrict__ Sq, const double* __restrict__ rq,
+                                const double* __restrict__ dirs, int nd, int ns, int ntap, int m_lo, double dt,
+                                double w, double mu4pi) {
+    const size_t tot = (size_t)ntap * nd * ns;
+    const double kc = w / kC0, cdt = kC0 * dt;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot; e += (size_t)gridDim.x * blockDim.x) {
+        const int k = (int)(e % ns);
+        const int d = (int)((e / ns) % nd);
+        const int tap = (int)(e / ((size_t)ns * nd));
+        const double* u = dirs + 3 * d;
+        double acc[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+        for (int q = 0; q < 14; ++q) {
+            const double* S = Sq + ((size_t)k * 14 + q) * 3;
+            const double* r = rq + ((size_t)k * 14 + q) * 3;
+            const double dr = r[0] * u[0] + r[1] * u[1] + r[2] * u[2];
+            double T[4];
+            if (!cppif_eval((double)(m_lo + tap) + dr / cdt, T)) continue;
+            const double c = cos(kc * dr), s = sin(kc * dr);
+            // (T'/dt + j w T) (c + j s)
+            const double fr = T[1] / dt * c - w * T[0] * s;
+            const double fi = T[1] / dt * s + w * T[0] * c;
+            for (int x = 0; x < 3; ++x) {
+                acc[x][0] += S[x] * fr;
+                acc[x][1] += S[x] * fi;
+            }
+        }
+        // transverse projection and scale
+        const double pr = u[0] * acc[0][0] + u[1] * acc[1][0] + u[2] * acc[2][0];
+        const double pi = u[0] * acc[0][1] + u[1] * acc[1][1] + u[2] * acc[2][1];
+        for (int x = 0; x < 3; ++x) {
+            const double vr = acc[x][0] - u[x] * pr, vi = acc[x][1] - u[x] * pi;
+            F[(((size_t)tap * nd + d) * 3 + x) * ns + k] = zd{-mu4pi * vr, -mu4pi * vi};
+        }
+    }
+}
+
+// U[l][b][d][x] = sum_tap sum_k F[tap][d][x][k] I[l - (m_lo+tap)][b][k]; block per output.
+__global__ void __launch_bounds__(256) k_farfield_apply(zd* __restrict__ U, const zd* __restrict__ F,
+                                                        const zd* __restrict__ I, int nt, int B, int nd, int ns,
+                                                        int ntap, int m_lo) {
+    __shared__ double sh[256];
+    const int o = blockIdx.x;  // ((l*B + b)*nd + d)*3 + x
+    const int x = o % 3, d = (o / 3) % nd, b = (o / (3 * nd)) % B, l = o / (3 * nd * B);
+    double re = 0, im = 0;
+    for (int tap = 0; tap < ntap; ++tap) {
+        const int j = l - (m_lo + tap);
+        if (j < 0 || j >= nt) continue;
+        const zd* f = F + (((size_t)tap * nd + d) * 3 + x) * ns;
+        const zd* v = I + ((size_t)j * B + b) * ns;
+        for (int k = threadIdx.x; k < ns; k += 256) {
+            re += f[k].x * v[k].x - f[k].y * v[k].y;
+            im += f[k].x * v[k].y + f[k].y * v[k].x;
+        }
+    }
+    sh[threadIdx.x] = re;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    const double rs = sh[0];
+    __syncthreads();
+    sh[threadIdx.x] = im;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) U[o] = zd{rs, sh[0]};
+}
+
+// S[j][b][k] = sum_tap sum_{d,x} conj(F[tap][d][x][k]) U[j + m_lo + tap][b][d][x]
+__global__ void k_farfield_adjoint(zd* __restrict__ S, const zd* __restrict__ F, const zd* __restrict__ U, int nt,
+                                   int B, int nd, int ns, int ntap, int m_lo) {
+    const size_t tot = (size_t)nt * B * ns;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot; e += (size_t)gridDim.x * blockDim.x) {
+        const int k = (int)(e % ns);
+        const int b = (int)((e / ns) % B);
+        const int j = (int)(e / ((size_t)ns * B));
+        double re = 0, im = 0;
+        for (int tap = 0; tap < ntap; ++tap) {
+            const int l = j + m_lo + tap;
+            if (l < 0 || l >= nt) continue;
+            for (int d = 0; d < nd; ++d)
+                for (int x = 0; x < 3; ++x) {
+                    const zd f = F[(((size_t)tap * nd + d) * 3 + x) * ns + k];
+                    const zd u = U[(((size_t)l * B + b) * nd + d) * 3 + x];
+                    re += f.x * u.x + f.y * u.y;
+                    im += f.x * u.y - f.y * u.x;
+                }
+        }
+        S[e] = zd{re, im};
+    }
+}
+
+}  // namespace etaim

@@ -1,0 +1,129 @@
+// Shared definitions of the ET-AIM library (host set-up and device code).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+namespace etaim {
+
+constexpr double kC0 = 299792458.0;
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kMu0 = 4.0e-7 * kPi;
+// eps0 = 1/(mu0 c^2), evaluated at run time to keep one definition
+__host__ __device__ inline double eps0() { return 1.0 / (kMu0 * kC0 * kC0); }
+constexpr int kQ = 3;  // CPPIF order
+
+template <typename R>
+struct cplx {
+    R x, y;
+};
+using zd = cplx<double>;
+using zf = cplx<float>;
+
+template <typename R>
+__host__ __device__ inline cplx<R> mk(R a, R b) { return cplx<R>{a, b}; }
+template <typename R>
+__host__ __device__ inline cplx<R> operator+(cplx<R> a, cplx<R> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename R>
+__host__ __device__ inline cplx<R> operator-(cplx<R> a, cplx<R> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename R>
+__host__ __device__ inline cplx<R> operator*(cplx<R> a, cplx<R> b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename R>
+__host__ __device__ inline cplx<R> operator*(R s, cplx<R> a) { return {s * a.x, s * a.y}; }
+template <typename R>
+__host__ __device__ inline cplx<R> conjz(cplx<R> a) { return {a.x, -a.y}; }
+template <typename R>
+__host__ __device__ inline cplx<R>& operator+=(cplx<R>& a, cplx<R> b) {
+    a.x += b.x;
+    a.y += b.y;
+    return a;
+}
+template <typename R>
+__host__ __device__ inline cplx<R>& operator-=(cplx<R>& a, cplx<R> b) {
+    a.x -= b.x;
+    a.y -= b.y;
+    return a;
+}
+
+// ---------------------------------------------------------------------------
+// CPPIF temporal basis of order 3 (Sec. 3 eq. (3)): on the piece
+// tau in (i-1, i], i = 0..3, T is the Lagrange weight of sample n-i for the
+// cubic through samples n, n-1, n-2, n-3.  With s = tau - i in (-1, 0]:
+//   T = prod_{k != i} (s + k) / prod_{k != i} (k - i),
+// a cubic in s whose roots are -k for the three k != i.  Breakpoints belong
+// to the left piece (i = ceil(tau)); T = 0 outside (-1, 3].
+// d[0..3] receive T, dT/dtau, d2T/dtau2, d3T/dtau3 of piece i at s.
+__host__ __device__ inline void cppif_piece(int i, double s, double d[4]) {
+    double a[3];
+    int n = 0;
+    double den = 1.0;
+    for (int k = 0; k <= kQ; ++k) {
+        if (k == i) continue;
+        a[n++] = (double)k;
+        den *= (double)(k - i);
+    }
+    const double e1 = a[0] + a[1] + a[2];
+    const double e2 = a[0] * a[1] + a[1] * a[2] + a[2] * a[0];
+    const double e3 = a[0] * a[1] * a[2];
+    d[0] = (((s + e1) * s + e2) * s + e3) / den;
+    d[1] = ((3.0 * s + 2.0 * e1) * s + e2) / den;
+    d[2] = (6.0 * s + 2.0 * e1) / den;
+    d[3] = 6.0 / den;
+}
+
+// T and its first two derivatives at tau (zero outside the support).
+__host__ __device__ inline bool cppif_eval(double tau, double d[4]) {
+    if (!(tau > -1.0 && tau <= (double)kQ)) {
+        d[0] = d[1] = d[2] = d[3] = 0.0;
+        return false;
+    }
+    const int i = (int)ceil(tau);
+    cppif_piece(i, tau - (double)i, d);
+    return true;
+}
+
+// Envelope kernel factors for interaction offset m at distance R
+// (differentiated EFIE, Lorenz gauge, envelope Green function
+// delta(t - R/c) exp(-j k R)/(4 pi R), d/dt -> d/dt + j w):
+//   fA   = exp(-j k R) [T''/dt^2 + 2 j w T'/dt - w^2 T](m - R/(c dt))
+//   fphi = exp(-j k R) T(m - R/(c dt))
+// so that K_A = (mu/4pi) fA / R and K_phi = (1/(4 pi eps)) fphi / R.
+struct EnvKernel {
+    double dt, w, k, cdt;
+    __host__ __device__ void eval(int m, double R, zd& fa, zd& fp) const {
+        const double tau = (double)m - R / cdt;
+        double d[4];
+        if (!cppif_eval(tau, d)) {
+            fa = {0.0, 0.0};
+            fp = {0.0, 0.0};
+            return;
+        }
+        const double c = cos(k * R), s = -sin(k * R);
+        const zd ph{c, s};
+        const zd pa{d[2] / (dt * dt) - w * w * d[0], 2.0 * w * d[1] / dt};
+        fa = ph * pa;
+        fp = zd{c * d[0], s * d[0]};
+    }
+    // value and R-derivative at R = 0+ (piece m, tau -> m-)
+    __host__ __device__ void origin(int m, zd& fa0, zd& fp0, zd& dfa0, zd& dfp0) const {
+        if (m < 0 || m > kQ) {
+            fa0 = fp0 = dfa0 = dfp0 = zd{0.0, 0.0};
+            return;
+        }
+        double d[4];
+        cppif_piece(m, 0.0, d);
+        const zd pa{d[2] / (dt * dt) - w * w * d[0], 2.0 * w * d[1] / dt};
+        const zd dpa{d[3] / (dt * dt) - w * w * d[1], 2.0 * w * d[2] / dt};
+        fa0 = pa;
+        fp0 = zd{d[0], 0.0};
+        const zd mjk{0.0, -k};
+        dfa0 = mjk * pa - (1.0 / cdt) * dpa;
+        dfp0 = mjk * fp0 - zd{d[1] / cdt, 0.0};
+    }
+};
+
+}  // namespace etaim

@@ -1,0 +1,1021 @@
+// C ABI of the ET-AIM marching library: context set-up, the AIM operator
+// (Sec. 4 stages (i)-(iv)), the delayed field, GMRES (stage (v), Sec. 5.1),
+// the forward and adjoint marches of eq. (5), excitation and export.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "aim.inc.hip"
+#include "context.hpp"
+#include "krylov.inc.hip"
+
+using namespace etaim;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess)                                                                     \
+            return fail(e_ == hipErrorOutOfMemory ? ETAIM_ENOMEM : ETAIM_EHIP,                     \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));                       \
+    } while (0)
+
+#define CHK(expr)                     \
+    do {                              \
+        int r_ = (expr);              \
+        if (r_ != ETAIM_OK) return r_; \
+    } while (0)
+
+constexpr int kLdsBudget = 64 * 1024;
+
+int pick_lines(int L, size_t elem, int cap) {
+    int mt = (int)(kLdsBudget / (2 * (size_t)(L + 1) * elem));
+    return std::max(1, std::min(mt, cap));
+}
+
+int blocks_for(size_t n, int threads = 256) {
+    size_t b = (n + threads - 1) / threads;
+    return (int)std::min<size_t>(std::max<size_t>(b, 1), 65535 * 8);
+}
+
+}  // namespace
+
+struct etaim_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    etaim_params prm{};
+    Geometry geo;
+    Setup st;
+    GridDims gd{};
+    Radix rx{}, ry{}, rz{};
+    int ns = 0, B = 0, prec = 0, mv = 0, nnz = 0, ldg = 0;
+    size_t N3 = 0, Np = 0, gfold = 0;
+    int64_t dev_bytes = 0;
+    std::vector<void*> allocs;
+    // FP64 device arrays
+    zd *dinv = nullptr, *dinv_c = nullptr, *diag = nullptr, *near64 = nullptr, *nearT64 = nullptr, *ghat64 = nullptr;
+    double* lam64 = nullptr;
+    int *i0 = nullptr, *rowptr = nullptr, *col = nullptr, *rowof = nullptr, *nptr = nullptr, *nk = nullptr;
+    double *Sq = nullptr, *rq = nullptr;
+    // working-precision arrays (float or double)
+    void *lam_r = nullptr, *nw_r = nullptr, *near_r = nullptr, *nearT_r = nullptr, *ghat_r = nullptr, *tw_r[3] = {};
+    void *A = nullptr, *Bg = nullptr, *P = nullptr, *ring = nullptr;
+    zd* hist = nullptr;
+    // Krylov (FP64)
+    zd *Vk = nullptr, *w = nullptr, *h1 = nullptr, *h2 = nullptr, *H = nullptr, *sn = nullptr, *g = nullptr,
+       *yv = nullptr, *xk = nullptr, *rhs = nullptr, *zero = nullptr;
+    double *cs = nullptr, *nrm = nullptr, *beta = nullptr, *bnorm = nullptr, *resid = nullptr;
+    int *active = nullptr, *jcnt = nullptr, *flag = nullptr;
+    int* flag_h = nullptr;
+    hipEvent_t ev[4] = {};
+    // per-kernel-class tracing
+    bool prof = false;
+    double k_ms[ETAIM_K_COUNT] = {}, k_bytes[ETAIM_K_COUNT] = {};
+    int64_t k_n[ETAIM_K_COUNT] = {};
+    std::vector<hipEvent_t> pool;
+    struct Pending {
+        int cls, ev;
+        double bytes;
+    };
+    std::vector<Pending> pending;
+    int pool_next = 0;
+
+    template <typename T>
+    int alloc(T*& p, size_t n) {
+        void* q = nullptr;
+        if (n == 0) n = 1;
+        hipError_t e = hipMalloc(&q, n * sizeof(T));
+        if (e != hipSuccess) return fail(ETAIM_ENOMEM, "hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed");
+        allocs.push_back(q);
+        dev_bytes += (int64_t)(n * sizeof(T));
+        p = reinterpret_cast<T*>(q);
+        return ETAIM_OK;
+    }
+    int allocv(void*& p, size_t bytes) {
+        unsigned char* q = nullptr;
+        CHK(alloc(q, bytes));
+        p = q;
+        return ETAIM_OK;
+    }
+    template <typename T>
+    int upload(T*& p, const std::vector<T>& v) {
+        CHK(alloc(p, v.size()));
+        HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+        return ETAIM_OK;
+    }
+    ~etaim_ctx() {
+        for (auto& e : ev)
+            if (e) (void)hipEventDestroy(e);
+        for (auto& e : pool) (void)hipEventDestroy(e);
+        if (flag_h) (void)hipHostFree(flag_h);
+        for (void* p : allocs) (void)hipFree(p);
+    }
+};
+
+namespace {
+
+// Tracing: an event pair around each launch of a class (when enabled).
+struct Trace {
+    etaim_ctx* c;
+    int cls, idx = -1;
+    double bytes;
+    Trace(etaim_ctx* c_, int cls_, double bytes_) : c(c_), cls(cls_), bytes(bytes_) {
+        if (!c->prof) return;
+        if ((size_t)(c->pool_next + 2) > c->pool.size()) {
+            for (int i = 0; i < 64; ++i) {
+                hipEvent_t e;
+                if (hipEventCreate(&e) != hipSuccess) return;
+                c->pool.push_back(e);
+            }
+        }
+        idx = c->pool_next;
+        c->pool_next += 2;
+        (void)hipEventRecord(c->pool[idx], c->stream);
+    }
+    ~Trace() {
+        if (idx < 0) return;
+        (void)hipEventRecord(c->pool[idx + 1], c->stream);
+        c->pending.push_back({cls, idx, bytes});
+    }
+};
+
+// resolve pending event pairs (call after the stream has drained them)
+int trace_flush(etaim_ctx* c) {
+    if (c->pending.empty()) return ETAIM_OK;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (const auto& p : c->pending) {
+        float t = 0;
+        HIPCHK(hipEventElapsedTime(&t, c->pool[p.ev], c->pool[p.ev + 1]));
+        c->k_ms[p.cls] += t;
+        c->k_bytes[p.cls] += p.bytes;
+        c->k_n[p.cls] += 1;
+    }
+    c->pending.clear();
+    c->pool_next = 0;
+    return ETAIM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// pass launchers (templated on the working precision)
+
+template <typename R>
+int launch_lines(etaim_ctx* c, const cplx<R>* in, cplx<R>* out, const cplx<R>* tw, const Radix& pl, int nf,
+                 int nslow, int in_len, int out_len, long long in_f, long long in_s, long long in_p,
+                 long long out_f, long long out_s, long long out_p, bool inverse) {
+    LineArgs a{};
+    a.pl = pl;
+    a.nf = nf;
+    a.in_len = in_len;
+    a.out_len = out_len;
+    a.in_f = in_f;
+    a.in_s = in_s;
+    a.in_p = in_p;
+    a.out_f = out_f;
+    a.out_s = out_s;
+    a.out_p = out_p;
+    a.inverse = inverse ? 1 : 0;
+    a.mt = pick_lines(pl.L, sizeof(cplx<R>), 16);
+    const size_t lds = 2 * (size_t)a.mt * (pl.L + 1) * sizeof(cplx<R>);
+    dim3 grid((nf + a.mt - 1) / a.mt, nslow);
+    hipLaunchKernelGGL(k_lines<R>, grid, dim3(256), lds, c->stream, in, out, tw, a);
+    HIPCHK(hipGetLastError());
+    return ETAIM_OK;
+}
+
+template <typename R>
+struct Ops {
+    static cplx<R>* A(etaim_ctx* c) { return (cplx<R>*)c->A; }
+    static cplx<R>* Bg(etaim_ctx* c) { return (cplx<R>*)c->Bg; }
+    static cplx<R>* P(etaim_ctx* c) { return (cplx<R>*)c->P; }
+    static const cplx<R>* tw(etaim_ctx* c, int a) { return (const cplx<R>*)c->tw_r[a]; }
+    static const cplx<R>* ghat(etaim_ctx* c) { return (const cplx<R>*)c->ghat_r; }
+    // near-zone values; the adjoint (conjugated) operators use the transposed
+    // values: the exact entries are symmetric only up to quadrature
+    static const cplx<R>* nearv(etaim_ctx* c, int conj) {
+        return (const cplx<R>*)(conj ? c->nearT_r : c->near_r);
+    }
+    static cplx<R>* ring(etaim_ctx* c) { return (cplx<R>*)c->ring; }
+
+    // anterpolate x (optionally scaled by dinv) and forward x, y passes -> Bg
+    static int forward_xy(etaim_ctx* c, const zd* x, const zd* dinv, int conj_in) {
+        const GridDims& g = c->gd;
+        const int mr = std::max(1, pick_lines(g.L[0], sizeof(cplx<R>), 16) / 4);
+        const size_t lds = 2 * (size_t)(4 * mr) * (g.L[0] + 1) * sizeof(cplx<R>);
+        dim3 grid((g.N[1] + mr - 1) / mr, g.N[2], c->B);
+        const double s = sizeof(cplx<R>), nB = (double)c->B * c->ns, bc = 4.0 * c->B;
+        const double a_sz = bc * g.N[2] * g.N[1] * g.L[0] * s, b_sz = bc * g.N[2] * g.L[1] * g.L[0] * s;
+        {
+            Trace t(c, ETAIM_K_ANTERP_X, nB * 16 + 64.0 * c->ns * (4 + 4 * sizeof(R)) + (c->N3 + 1) * 4.0 + a_sz +
+                                             (dinv ? c->ns * 16.0 : 0.0));
+            hipLaunchKernelGGL(k_fwdx_gather<R>, grid, dim3(256), lds, c->stream, x, dinv, c->nptr, c->nk,
+                               (const R*)c->nw_r, A(c), tw(c, 0), c->rx, g, mr, c->ns, conj_in);
+        }
+        HIPCHK(hipGetLastError());
+        const long long Lx = g.L[0], Ly = g.L[1], Ny = g.N[1], Nz = g.N[2];
+        Trace t(c, ETAIM_K_FFT_Y_FWD, a_sz + b_sz);
+        return launch_lines<R>(c, A(c), Bg(c), tw(c, 1), c->ry, (int)Lx, (int)(4 * c->B * Nz), (int)Ny, (int)Ly, 1,
+                               Ny * Lx, Lx, 1, Ly * Lx, Lx, false);
+    }
+    // inverse y, x passes Bg -> P
+    static int inverse_yx(etaim_ctx* c) {
+        const GridDims& g = c->gd;
+        const long long Lx = g.L[0], Ly = g.L[1], Nx = g.N[0], Ny = g.N[1], Nz = g.N[2];
+        const double s = sizeof(cplx<R>), bc = 4.0 * c->B;
+        const double a_sz = bc * Nz * Ny * Lx * s, b_sz = bc * Nz * Ly * Lx * s, p_sz = bc * c->N3 * s;
+        {
+            Trace t(c, ETAIM_K_FFT_Y_INV, a_sz + b_sz);
+            CHK(launch_lines<R>(c, Bg(c), A(c), tw(c, 1), c->ry, (int)Lx, (int)(4 * c->B * Nz), (int)Ly, (int)Ny, 1,
+                                Ly * Lx, Lx, 1, Ny * Lx, Lx, true));
+        }
+        Trace t(c, ETAIM_K_FFT_X_INV, a_sz + p_sz);
+        return launch_lines<R>(c, A(c), P(c), tw(c, 0), c->rx, (int)Ny, (int)(4 * c->B * Nz), (int)Lx, (int)Nx, Lx,
+                               Ny * Lx, 1, Nx, Ny * Nx, 1, true);
+    }
+    static int zgreen(etaim_ctx* c, int m, int conj) {
+        const GridDims& g = c->gd;
+        const int mt = pick_lines(g.L[2], sizeof(cplx<R>), 16);
+        const size_t lds = 2 * (size_t)mt * (g.L[2] + 1) * sizeof(cplx<R>);
+        dim3 grid((g.L[0] + mt - 1) / mt, g.L[1]);
+        const double s = sizeof(cplx<R>);
+        Trace t(c, ETAIM_K_ZGREEN, 2.0 * 4 * c->B * g.N[2] * g.L[1] * g.L[0] * s + 2.0 * c->gfold * s);
+        hipLaunchKernelGGL(k_zgreen<R>, grid, dim3(256), lds, c->stream, Bg(c), ghat(c) + (size_t)m * 2 * c->gfold,
+                           tw(c, 2), c->rz, g, mt, conj);
+        HIPCHK(hipGetLastError());
+        return ETAIM_OK;
+    }
+    static int interp_near(etaim_ctx* c, int mode, const zd* x, const zd* dinv, int m, int cur, int nmh,
+                           const zd* V, zd* y, int conj_v, int conj_x) {
+        dim3 grid((c->ns + 3) / 4);
+        const double s = sizeof(cplx<R>), nB = (double)c->B * c->ns;
+        const double nvals = mode == 0 ? (m <= c->st.mn ? 1.0 : 0.0) : (double)nmh;
+        Trace t(c, ETAIM_K_INTERP_NEAR,
+                4.0 * c->B * c->N3 * s + c->ns * (256.0 * sizeof(R) + 12.0) + (c->ns + 1) * 4.0 + c->nnz * 4.0 +
+                    c->nnz * nvals * s + (mode == 0 ? nB * 16 : (nmh + 1) * nB * 16) + nB * 16);
+        hipLaunchKernelGGL(k_interp_near<R>, grid, dim3(256), 0, c->stream, (const cplx<R>*)P(c),
+                           (const R*)c->lam_r, c->i0, c->gd, c->rowptr, c->col, nearv(c, conj_v), c->mv, x, dinv, m,
+                           c->hist, std::max(c->st.mn, 1), cur, nmh, V, y, c->ns, mode, conj_v, conj_x);
+        HIPCHK(hipGetLastError());
+        return ETAIM_OK;
+    }
+    // y = conj?(Z_m) (dinv . x)
+    static int apply(etaim_ctx* c, int m, const zd* x, const zd* dinv, zd* y, int conj) {
+        CHK(forward_xy(c, x, dinv, 0));
+        CHK(zgreen(c, m, conj));
+        CHK(inverse_yx(c));
+        return interp_near(c, 0, x, dinv, m, 0, 0, nullptr, y, conj, 0);
+    }
+    // rhs = V - sum_{m>=1} conj?(Z_m) I_{cur-m} from the rings (cur >= 1)
+    static int delayed(etaim_ctx* c, int cur, const zd* V, zd* rhs, int conj) {
+        const GridDims& g = c->gd;
+        const int mt = pick_lines(g.L[2], sizeof(cplx<R>), 16);
+        const size_t lds = 2 * (size_t)mt * (g.L[2] + 1) * sizeof(cplx<R>);
+        dim3 grid((g.L[0] + mt - 1) / mt, g.L[1]);
+        const int nm = std::min(c->st.ng, cur);
+        {
+            const double s = sizeof(cplx<R>);
+            Trace t(c, ETAIM_K_ZDELAYED,
+                    nm * (4.0 * c->B * c->Np * s + 2.0 * c->gfold * s) + 4.0 * c->B * g.N[2] * g.L[1] * g.L[0] * s);
+            hipLaunchKernelGGL(k_zdelayed<R>, grid, dim3(256), lds, c->stream, (const cplx<R>*)ring(c), ghat(c),
+                               Bg(c), tw(c, 2), c->rz, g, mt, c->st.ng, cur, nm, conj);
+        }
+        HIPCHK(hipGetLastError());
+        CHK(inverse_yx(c));
+        const int nmh = std::min(c->st.mn, cur);
+        return interp_near(c, 1, nullptr, nullptr, 0, cur, nmh, V, rhs, conj, 0);
+    }
+    // push the converged I_cur into the spectrum ring and the current ring
+    static int commit(etaim_ctx* c, int cur, const zd* x) {
+        CHK(forward_xy(c, x, nullptr, 0));
+        const GridDims& g = c->gd;
+        const int mt = pick_lines(g.L[2], sizeof(cplx<R>), 16);
+        const size_t lds = 2 * (size_t)mt * (g.L[2] + 1) * sizeof(cplx<R>);
+        dim3 grid((g.L[0] + mt - 1) / mt, g.L[1]);
+        const size_t slot_sz = (size_t)4 * c->B * c->Np;
+        cplx<R>* slot = ring(c) + (size_t)(cur % c->st.ng) * slot_sz;
+        {
+            const double s = sizeof(cplx<R>);
+            Trace t(c, ETAIM_K_ZCOMMIT, 4.0 * c->B * g.N[2] * g.L[1] * g.L[0] * s + 4.0 * c->B * c->Np * s);
+            hipLaunchKernelGGL(k_zcommit<R>, grid, dim3(256), lds, c->stream, (const cplx<R>*)Bg(c), slot, tw(c, 2),
+                               c->rz, g, mt);
+        }
+        HIPCHK(hipGetLastError());
+        if (c->st.mn >= 1) {
+            const size_t n = (size_t)c->B * c->ns;
+            HIPCHK(hipMemcpyAsync(c->hist + (size_t)(cur % c->st.mn) * n, x, n * sizeof(zd),
+                                  hipMemcpyDeviceToDevice, c->stream));
+        }
+        return ETAIM_OK;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// GMRES for one time step: x (in: initial guess, out: solution).
+struct StepResult {
+    int iters = 0, cols_iters = 0;
+    bool noconv = false, nonfinite = false;
+    double resid = 0;
+};
+
+template <typename R>
+int gmres(etaim_ctx* c, const zd* rhs, zd* x, int conj, StepResult& res) {
+    const int B = c->B, ns = c->ns, rs = c->prm.restart;
+    const size_t nB = (size_t)B * ns;
+    const double tol = c->prm.tol;
+    const zd* dinv = conj ? c->dinv_c : c->dinv;
+    hipLaunchKernelGGL(k_norm, dim3(B), dim3(256), 0, c->stream, rhs, c->bnorm, ns);
+    int total = 0;
+    double prev_worst = 0;
+    for (int cycle = 0;; ++cycle) {
+        // r = rhs - A x
+        CHK(Ops<R>::apply(c, 0, x, nullptr, c->w, conj));
+        hipLaunchKernelGGL(k_residual, dim3(blocks_for(nB)), dim3(256), 0, c->stream, rhs, c->w, nB);
+        hipLaunchKernelGGL(k_norm, dim3(B), dim3(256), 0, c->stream, c->w, c->beta, ns);
+        HIPCHK(hipMemsetAsync(c->flag, 0, 2 * sizeof(int), c->stream));
+        hipLaunchKernelGGL(k_cycle_start, dim3(1), dim3(1), 0, c->stream, c->beta, c->bnorm, c->active, c->jcnt,
+                           c->g, c->resid, c->flag, B, c->ldg, tol);
+        HIPCHK(hipMemcpyAsync(c->flag_h, c->flag, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        if (c->flag_h[1]) {
+            res.nonfinite = true;
+            break;
+        }
+        if (c->flag_h[0] == 0) break;
+        if (total >= c->prm.maxit) {
+            res.noconv = true;
+            break;
+        }
+        // stagnation: the true residual at a restart did not drop below half of
+        // the previous restart's (e.g. a tolerance below the working precision)
+        {
+            std::vector<double> bh(B);
+            HIPCHK(hipMemcpy(bh.data(), c->resid, B * sizeof(double), hipMemcpyDeviceToHost));
+            double worst = 0;
+            for (double v : bh) worst = std::max(worst, v);
+            if (cycle > 0 && worst > 0.5 * prev_worst) {
+                res.noconv = true;
+                break;
+            }
+            prev_worst = worst;
+        }
+        hipLaunchKernelGGL(k_scale, dim3(blocks_for(nB)), dim3(256), 0, c->stream, c->w, c->beta, c->Vk, ns, B);
+        for (int j = 0; j < rs; ++j) {
+            zd* vj = c->Vk + (size_t)j * nB;
+            zd* vn = c->Vk + (size_t)(j + 1) * nB;
+            CHK(Ops<R>::apply(c, 0, vj, dinv, c->w, conj));
+            dim3 gd(j + 1, B), go((ns + 255) / 256, B);
+            {
+            Trace tk(c, ETAIM_K_KRYLOV, (4.0 * (j + 1) + 8.0) * (double)nB * 16.0);
+            hipLaunchKernelGGL(k_dots, gd, dim3(256), 0, c->stream, c->Vk, c->w, c->h1, ns, B);
+            hipLaunchKernelGGL(k_orth, go, dim3(256), 0, c->stream, c->Vk, c->w, c->h1, j + 1, ns, B);
+            hipLaunchKernelGGL(k_dots, gd, dim3(256), 0, c->stream, c->Vk, c->w, c->h2, ns, B);
+            hipLaunchKernelGGL(k_orth, go, dim3(256), 0, c->stream, c->Vk, c->w, c->h2, j + 1, ns, B);
+            hipLaunchKernelGGL(k_norm, dim3(B), dim3(256), 0, c->stream, c->w, c->nrm, ns);
+            hipLaunchKernelGGL(k_scale, dim3(blocks_for(nB)), dim3(256), 0, c->stream, c->w, c->nrm, vn, ns, B);
+            hipLaunchKernelGGL(k_arnoldi_update, dim3(1), dim3(1), 0, c->stream, c->h1, c->h2, c->nrm, c->H, c->cs,
+                               c->sn, c->g, c->active, c->jcnt, c->resid, c->bnorm, c->flag, j, B, rs, tol);
+            }
+            HIPCHK(hipMemcpyAsync(c->flag_h, c->flag, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(hipStreamSynchronize(c->stream));
+            HIPCHK(hipGetLastError());
+            ++total;
+            res.iters = total;
+            if (c->flag_h[1]) res.nonfinite = true;
+            if (c->flag_h[0] == 0 || total >= c->prm.maxit) break;
+        }
+        hipLaunchKernelGGL(k_backsolve, dim3((B + 63) / 64), dim3(64), 0, c->stream, c->H, c->g, c->jcnt, c->yv, B,
+                           rs);
+        hipLaunchKernelGGL(k_update_x, dim3((ns + 255) / 256, B), dim3(256), 0, c->stream, x, c->Vk, c->yv, c->jcnt,
+                           dinv, ns, B, rs);
+        HIPCHK(hipGetLastError());
+        if (res.nonfinite) break;
+    }
+    // final residual estimate (true residual of the last cycle start)
+    std::vector<double> rr(B);
+    HIPCHK(hipMemcpyAsync(rr.data(), c->resid, B * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    res.resid = 0;
+    for (double v : rr) res.resid = std::max(res.resid, v);
+    return ETAIM_OK;
+}
+
+// ---------------------------------------------------------------------------
+template <typename R>
+int march_impl(etaim_ctx* c, const zd* V, zd* I, etaim_stats* st, bool adjoint, int nsteps) {
+    const int nt = nsteps > 0 ? nsteps : c->prm.nt_steps, B = c->B, ns = c->ns;
+    const size_t nB = (size_t)B * ns;
+    const int conj = adjoint ? 1 : 0;
+    HIPCHK(hipMemsetAsync(c->ring, 0, (size_t)c->st.ng * 4 * B * c->Np * sizeof(cplx<R>), c->stream));
+    if (c->st.mn >= 1) HIPCHK(hipMemsetAsync(c->hist, 0, (size_t)c->st.mn * nB * sizeof(zd), c->stream));
+    // excitation norms per step (instability detector)
+    std::vector<double> nV((size_t)nt * B), nI((size_t)nt, 0.0);
+    {
+        double* d = nullptr;
+        CHK(c->alloc(d, (size_t)nt * B));
+        hipLaunchKernelGGL(k_norm, dim3(nt * B), dim3(256), 0, c->stream, V, d, ns);
+        HIPCHK(hipMemcpyAsync(nV.data(), d, nV.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        c->allocs.pop_back();
+        c->dev_bytes -= (int64_t)((size_t)nt * B * sizeof(double));
+        HIPCHK(hipFree(d));
+    }
+    double vmax = 0;
+    for (double v : nV) vmax = std::max(vmax, v);
+    int steps = 0, tot_iters = 0, max_iters = 0, first_noconv = -1, unstable = -1;
+    double maxres = 0, ms_rhs = 0, ms_solve = 0, ms_commit = 0;
+    bool nonfinite = false;
+    std::vector<double> nrm_h(B);
+    for (int r = 0; r < nt; ++r) {
+        const int l = adjoint ? nt - 1 - r : r;
+        const zd* Vl = V + (size_t)l * nB;
+        zd* Il = I + (size_t)l * nB;
+        HIPCHK(hipEventRecord(c->ev[0], c->stream));
+        if (r >= 1) {
+            CHK(Ops<R>::delayed(c, r, Vl, c->rhs, conj));
+        } else {
+            HIPCHK(hipMemcpyAsync(c->rhs, Vl, nB * sizeof(zd), hipMemcpyDeviceToDevice, c->stream));
+        }
+        HIPCHK(hipEventRecord(c->ev[1], c->stream));
+        if (r >= 1) {
+            const zd* Ip = I + (size_t)(adjoint ? l + 1 : l - 1) * nB;
+            HIPCHK(hipMemcpyAsync(c->xk, Ip, nB * sizeof(zd), hipMemcpyDeviceToDevice, c->stream));
+        } else {
+            HIPCHK(hipMemsetAsync(c->xk, 0, nB * sizeof(zd), c->stream));
+        }
+        StepResult sr;
+        CHK(gmres<R>(c, c->rhs, c->xk, conj, sr));
+        HIPCHK(hipEventRecord(c->ev[2], c->stream));
+        HIPCHK(hipMemcpyAsync(Il, c->xk, nB * sizeof(zd), hipMemcpyDeviceToDevice, c->stream));
+        CHK(Ops<R>::commit(c, r, c->xk));
+        hipLaunchKernelGGL(k_norm, dim3(B), dim3(256), 0, c->stream, c->xk, c->nrm, ns);
+        HIPCHK(hipMemcpyAsync(nrm_h.data(), c->nrm, B * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipEventRecord(c->ev[3], c->stream));
+        HIPCHK(hipEventSynchronize(c->ev[3]));
+        CHK(trace_flush(c));
+        float t01 = 0, t12 = 0, t23 = 0;
+        HIPCHK(hipEventElapsedTime(&t01, c->ev[0], c->ev[1]));
+        HIPCHK(hipEventElapsedTime(&t12, c->ev[1], c->ev[2]));
+        HIPCHK(hipEventElapsedTime(&t23, c->ev[2], c->ev[3]));
+        ms_rhs += t01;
+        ms_solve += t12;
+        ms_commit += t23;
+        steps = r + 1;
+        tot_iters += sr.iters;
+        max_iters = std::max(max_iters, sr.iters);
+        maxres = std::max(maxres, sr.resid);
+        if (st && st->iters_per_step) st->iters_per_step[r] = sr.iters;
+        for (double v : nrm_h) nI[r] = std::max(nI[r], v);
+        if (sr.nonfinite) {
+            nonfinite = true;
+            break;
+        }
+        if (sr.noconv && first_noconv < 0) {
+            first_noconv = r;
+            if (!(c->prm.flags & ETAIM_F_CONTINUE_ON_NOCONV)) break;
+        }
+        // late-time growth: monotone growth by > 10x over 32 steps while the
+        // excitation is negligible
+        const int W = 32;
+        if (unstable < 0 && r >= W) {
+            bool mono = nI[r] > 10.0 * nI[r - W];
+            double vw = 0;
+            for (int q = r - W + 1; q <= r && mono; ++q) {
+                mono = nI[q] > nI[q - 1];
+                const int lq = adjoint ? nt - 1 - q : q;
+                for (int b = 0; b < B; ++b) vw = std::max(vw, nV[(size_t)lq * B + b]);
+            }
+            if (mono && vw < 1e-6 * vmax) {
+                unstable = r;
+                if (c->prm.flags & ETAIM_F_FAIL_ON_UNSTABLE) break;
+            }
+        }
+    }
+    if (st) {
+        st->steps_done = steps;
+        st->total_iters = tot_iters;
+        st->max_iters = max_iters;
+        st->first_noconv_step = first_noconv;
+        st->unstable_step = unstable;
+        st->ms_rhs = ms_rhs;
+        st->ms_solve = ms_solve;
+        st->ms_commit = ms_commit;
+        st->ms_total = ms_rhs + ms_solve + ms_commit;
+        st->max_rel_residual = maxres;
+    }
+    if (nonfinite) return fail(ETAIM_ENONFINITE, "non-finite GMRES residual at step " + std::to_string(steps));
+    if (first_noconv >= 0 && !(c->prm.flags & ETAIM_F_CONTINUE_ON_NOCONV))
+        return fail(ETAIM_ENOCONV, "GMRES reached maxit at step " + std::to_string(first_noconv));
+    if (unstable >= 0 && (c->prm.flags & ETAIM_F_FAIL_ON_UNSTABLE))
+        return fail(ETAIM_EUNSTABLE, "late-time growth detected at step " + std::to_string(unstable));
+    return ETAIM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// device set-up: Green tables and spectra, pre-correction, precision copies
+template <typename R>
+int make_working(etaim_ctx* c) {
+    const size_t nB = (size_t)c->B;
+    if constexpr (sizeof(R) == sizeof(double)) {
+        c->lam_r = c->lam64;
+        c->near_r = c->near64;
+        c->nearT_r = c->nearT64;
+        c->ghat_r = c->ghat64;
+        double* nw = nullptr;
+        CHK(c->upload(nw, c->st.nw));
+        c->nw_r = nw;
+    } else {
+        float *lam = nullptr, *nw = nullptr;
+        zf *nearv = nullptr, *gh = nullptr;
+        CHK(c->alloc(lam, (size_t)c->ns * 256));
+        hipLaunchKernelGGL(k_real_to_r<float>, dim3(blocks_for((size_t)c->ns * 256)), dim3(256), 0, c->stream,
+                           c->lam64, lam, (size_t)c->ns * 256);
+        double* nw64 = nullptr;
+        CHK(c->upload(nw64, c->st.nw));
+        CHK(c->alloc(nw, c->st.nw.size()));
+        hipLaunchKernelGGL(k_real_to_r<float>, dim3(blocks_for(c->st.nw.size())), dim3(256), 0, c->stream, nw64, nw,
+                           c->st.nw.size());
+        CHK(c->alloc(nearv, (size_t)c->nnz * c->mv));
+        hipLaunchKernelGGL(k_to_r<float>, dim3(blocks_for((size_t)c->nnz * c->mv)), dim3(256), 0, c->stream,
+                           c->near64, nearv, (size_t)c->nnz * c->mv);
+        zf* nearT = nullptr;
+        CHK(c->alloc(nearT, (size_t)c->nnz * c->mv));
+        hipLaunchKernelGGL(k_to_r<float>, dim3(blocks_for((size_t)c->nnz * c->mv)), dim3(256), 0, c->stream,
+                           c->nearT64, nearT, (size_t)c->nnz * c->mv);
+        c->nearT_r = nearT;
+        const size_t ng = (size_t)(c->st.ng + 1) * 2 * c->gfold;
+        CHK(c->alloc(gh, ng));
+        hipLaunchKernelGGL(k_to_r<float>, dim3(blocks_for(ng)), dim3(256), 0, c->stream, c->ghat64, gh, ng);
+        HIPCHK(hipGetLastError());
+        c->lam_r = lam;
+        c->nw_r = nw;
+        c->near_r = nearv;
+        c->ghat_r = gh;
+    }
+    for (int a = 0; a < 3; ++a) {
+        const int L = c->gd.L[a];
+        std::vector<cplx<R>> tw(L);
+        for (int n = 0; n < L; ++n) {
+            const double ang = 2.0 * kPi * (double)n / (double)L;
+            tw[n] = cplx<R>{(R)std::cos(ang), (R)(-std::sin(ang))};
+        }
+        cplx<R>* d = nullptr;
+        CHK(c->upload(d, tw));
+        c->tw_r[a] = d;
+    }
+    CHK(c->allocv(c->A, 4 * nB * (size_t)c->gd.N[2] * c->gd.N[1] * c->gd.L[0] * sizeof(cplx<R>)));
+    CHK(c->allocv(c->Bg, 4 * nB * (size_t)c->gd.N[2] * c->gd.L[1] * c->gd.L[0] * sizeof(cplx<R>)));
+    CHK(c->allocv(c->P, 4 * nB * c->N3 * sizeof(cplx<R>)));
+    CHK(c->allocv(c->ring, (size_t)c->st.ng * 4 * nB * c->Np * sizeof(cplx<R>)));
+    return ETAIM_OK;
+}
+
+int device_setup(etaim_ctx* c) {
+    Setup& s = c->st;
+    const int ns = c->ns;
+    // FP64 arrays
+    CHK(c->upload(c->lam64, s.lam));
+    CHK(c->upload(c->i0, s.i0));
+    CHK(c->upload(c->rowptr, s.rowptr));
+    CHK(c->upload(c->col, s.col));
+    std::vector<int> rowof(c->nnz);
+    for (int k = 0; k < ns; ++k)
+        for (int e = s.rowptr[k]; e < s.rowptr[k + 1]; ++e) rowof[e] = k;
+    CHK(c->upload(c->rowof, rowof));
+    CHK(c->upload(c->nptr, s.nptr));
+    CHK(c->upload(c->nk, s.nk));
+    CHK(c->upload(c->near64, s.near_exact));
+    // diagonal of Z0 = exact self entry (pre-correction restores it)
+    std::vector<zd> diag(ns), dinv(ns), dinv_c(ns);
+    for (int k = 0; k < ns; ++k) {
+        zd d{0, 0};
+        for (int e = s.rowptr[k]; e < s.rowptr[k + 1]; ++e)
+            if (s.col[e] == k) d = s.near_exact[(size_t)e * c->mv];
+        const double dd = d.x * d.x + d.y * d.y;
+        if (!(dd > 0)) return fail(ETAIM_EINVAL, "zero diagonal entry of Z0 at basis " + std::to_string(k));
+        diag[k] = d;
+        dinv[k] = zd{d.x / dd, -d.y / dd};
+        dinv_c[k] = zd{d.x / dd, d.y / dd};
+    }
+    CHK(c->upload(c->diag, diag));
+    CHK(c->upload(c->dinv, dinv));
+    CHK(c->upload(c->dinv_c, dinv_c));
+    // Green tables (FP64) and pre-correction
+    zd* gtab = nullptr;
+    CHK(c->alloc(gtab, (size_t)(s.ng + 1) * 2 * c->N3));
+    const double w = 2.0 * kPi * c->prm.fc;
+    EnvKernel K{s.dt, w, w / kC0, kC0 * s.dt};
+    const double sa = kMu0 / (4.0 * kPi), sp = 1.0 / (4.0 * kPi * eps0());
+    hipLaunchKernelGGL(k_green_table, dim3(blocks_for((size_t)(s.ng + 1) * c->N3)), dim3(256), 0, c->stream, gtab,
+                       c->gd, s.ng, s.h, K, sa, sp);
+    HIPCHK(hipGetLastError());
+    if (c->nnz > 0)
+        hipLaunchKernelGGL(k_precorrect, dim3(c->nnz), dim3(64), 0, c->stream, c->near64, c->lam64, c->i0, c->rowof,
+                           c->col, gtab, c->gd, c->mv, c->nnz);
+    HIPCHK(hipGetLastError());
+    // Green spectra: circulant embedding, full FP64 3-D FFT, fold, / Np
+    CHK(c->alloc(c->ghat64, (size_t)(s.ng + 1) * 2 * c->gfold));
+    zd* full = nullptr;
+    CHK(c->alloc(full, c->Np));
+    std::vector<zd> tw64[3];
+    zd* twd[3];
+    for (int a = 0; a < 3; ++a) {
+        const int L = c->gd.L[a];
+        tw64[a].resize(L);
+        for (int n = 0; n < L; ++n) {
+            const double ang = 2.0 * kPi * (double)n / (double)L;
+            tw64[a][n] = zd{std::cos(ang), -std::sin(ang)};
+        }
+        CHK(c->upload(twd[a], tw64[a]));
+    }
+    const long long Lx = c->gd.L[0], Ly = c->gd.L[1], Lz = c->gd.L[2];
+    for (int m = 0; m <= s.ng; ++m)
+        for (int t = 0; t < 2; ++t) {
+            hipLaunchKernelGGL(k_circulant, dim3(blocks_for(c->Np)), dim3(256), 0, c->stream,
+                               gtab + ((size_t)m * 2 + t) * c->N3, full, c->gd);
+            CHK(launch_lines<double>(c, full, full, twd[0], c->rx, (int)Ly, (int)Lz, (int)Lx, (int)Lx, Lx, Ly * Lx, 1,
+                                     Lx, Ly * Lx, 1, false));
+            CHK(launch_lines<double>(c, full, full, twd[1], c->ry, (int)Lx, (int)Lz, (int)Ly, (int)Ly, 1, Ly * Lx, Lx,
+                                     1, Ly * Lx, Lx, false));
+            CHK(launch_lines<double>(c, full, full, twd[2], c->rz, (int)Lx, (int)Ly, (int)Lz, (int)Lz, 1, Lx,
+                                     Ly * Lx, 1, Lx, Ly * Lx, false));
+            hipLaunchKernelGGL(k_fold, dim3(blocks_for(c->gfold)), dim3(256), 0, c->stream, full,
+                               c->ghat64 + ((size_t)m * 2 + t) * c->gfold, c->gd, 1.0 / (double)c->Np);
+            HIPCHK(hipGetLastError());
+        }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    // transposed near-zone values (the pattern is symmetric): nearT[e] = near[e'] with e' = (col[e], row[e])
+    {
+        std::vector<int> tperm(c->nnz);
+        for (int k = 0; k < ns; ++k)
+            for (int e = s.rowptr[k]; e < s.rowptr[k + 1]; ++e) {
+                const int k2 = s.col[e];
+                const int* base = s.col.data();
+                const int* b = base + s.rowptr[k2];
+                const int* end = base + s.rowptr[k2 + 1];
+                const int* f = std::lower_bound(b, end, k);
+                if (f == end || *f != k) return fail(ETAIM_EINVAL, "near-zone pattern is not symmetric");
+                tperm[e] = (int)(f - base);
+            }
+        int* tp = nullptr;
+        CHK(c->upload(tp, tperm));
+        CHK(c->alloc(c->nearT64, (size_t)c->nnz * c->mv));
+        hipLaunchKernelGGL(k_permute_rows, dim3(blocks_for((size_t)c->nnz * c->mv)), dim3(256), 0, c->stream,
+                           c->near64, c->nearT64, tp, c->nnz, c->mv);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(c->stream));
+        auto it = std::find(c->allocs.begin(), c->allocs.end(), (void*)tp);
+        c->allocs.erase(it);
+        HIPCHK(hipFree(tp));
+        c->dev_bytes -= (int64_t)(tperm.size() * sizeof(int));
+    }
+    // release set-up temporaries (gtab, full, twd)
+    for (void* p : {(void*)twd[2], (void*)twd[1], (void*)twd[0], (void*)full, (void*)gtab}) {
+        auto it = std::find(c->allocs.begin(), c->allocs.end(), p);
+        if (it != c->allocs.end()) c->allocs.erase(it);
+        HIPCHK(hipFree(p));
+    }
+    c->dev_bytes -= (int64_t)(((size_t)(s.ng + 1) * 2 * c->N3 + c->Np) * sizeof(zd));
+    // excitation / far-field quadrature data: 14 points per basis (7 per half)
+    {
+        const double s15 = std::sqrt(15.0);
+        const double a1 = (6.0 - s15) / 21.0, a2 = (6.0 + s15) / 21.0;
+        const double w1 = (155.0 - s15) / 1200.0, w2 = (155.0 + s15) / 1200.0;
+        const double bq[7][3] = {{1.0 / 3, 1.0 / 3, 1.0 / 3}, {a1, a1, 1 - 2 * a1}, {a1, 1 - 2 * a1, a1},
+                                 {1 - 2 * a1, a1, a1},        {a2, a2, 1 - 2 * a2}, {a2, 1 - 2 * a2, a2},
+                                 {1 - 2 * a2, a2, a2}};
+        const double wq[7] = {9.0 / 40.0, w1, w1, w1, w2, w2, w2};
+        std::vector<double> Sq((size_t)ns * 14 * 3), rq((size_t)ns * 14 * 3);
+        const Geometry& G = c->geo;
+        for (int k = 0; k < ns; ++k)
+            for (int h = 0; h < 2; ++h) {
+                const int t = G.t[2 * k + h];
+                const double sg = h == 0 ? 1.0 : -1.0;
+                const double coef = sg * G.len[k] / (2.0 * G.area[t]);
+                const int* tv = &G.tri[3 * (size_t)t];
+                const int f = G.freev[2 * k + h];
+                for (int q = 0; q < 7; ++q) {
+                    const size_t o = ((size_t)k * 14 + h * 7 + q) * 3;
+                    for (int x = 0; x < 3; ++x) {
+                        const double r = bq[q][0] * G.xyz[3 * (size_t)tv[0] + x] + bq[q][1] * G.xyz[3 * (size_t)tv[1] + x] +
+                                         bq[q][2] * G.xyz[3 * (size_t)tv[2] + x];
+                        rq[o + x] = r;
+                        Sq[o + x] = wq[q] * G.area[t] * coef * (r - G.xyz[3 * (size_t)f + x]);
+                    }
+                }
+            }
+        CHK(c->upload(c->Sq, Sq));
+        CHK(c->upload(c->rq, rq));
+    }
+    CHK(c->prec == ETAIM_FP32 ? make_working<float>(c) : make_working<double>(c));
+    // history of currents, Krylov space
+    const size_t nB = (size_t)c->B * ns;
+    const int rs = c->prm.restart;
+    c->ldg = rs + 1;
+    CHK(c->alloc(c->hist, (size_t)std::max(s.mn, 1) * nB));
+    CHK(c->alloc(c->Vk, (size_t)(rs + 1) * nB));
+    CHK(c->alloc(c->w, nB));
+    CHK(c->alloc(c->xk, nB));
+    CHK(c->alloc(c->rhs, nB));
+    CHK(c->alloc(c->zero, nB));
+    HIPCHK(hipMemsetAsync(c->zero, 0, nB * sizeof(zd), c->stream));
+    CHK(c->alloc(c->h1, (size_t)(rs + 1) * c->B));
+    CHK(c->alloc(c->h2, (size_t)(rs + 1) * c->B));
+    CHK(c->alloc(c->H, (size_t)c->B * rs * (rs + 1)));
+    CHK(c->alloc(c->sn, (size_t)c->B * rs));
+    CHK(c->alloc(c->cs, (size_t)c->B * rs));
+    CHK(c->alloc(c->g, (size_t)c->B * (rs + 1)));
+    CHK(c->alloc(c->yv, (size_t)c->B * rs));
+    CHK(c->alloc(c->nrm, c->B));
+    CHK(c->alloc(c->beta, c->B));
+    CHK(c->alloc(c->bnorm, c->B));
+    CHK(c->alloc(c->resid, c->B));
+    CHK(c->alloc(c->active, c->B));
+    CHK(c->alloc(c->jcnt, c->B));
+    CHK(c->alloc(c->flag, 2));
+    HIPCHK(hipHostMalloc((void**)&c->flag_h, 2 * sizeof(int), hipHostMallocDefault));
+    for (auto& e : c->ev) HIPCHK(hipEventCreate(&e));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return ETAIM_OK;
+}
+
+int check_ctx(const etaim_ctx* c) {
+    if (!c) return fail(ETAIM_EINVAL, "null context");
+    return ETAIM_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+const char* etaim_last_error(void) { return g_err.c_str(); }
+
+int etaim_create(etaim_ctx** out, const etaim_mesh* mesh, const etaim_rwg* rwg, const etaim_params* params,
+                 void* hip_stream) {
+    g_err.clear();
+    if (!out || !params) return fail(ETAIM_EINVAL, "null output or parameter pointer");
+    *out = nullptr;
+    std::unique_ptr<etaim_ctx> c(new etaim_ctx());
+    c->prm = *params;
+    std::string err;
+    int rc = build_geometry(mesh, rwg, c->geo, err);
+    if (rc) return fail(rc, err);
+    rc = derive_parameters(c->geo, params, c->st, err);
+    if (rc) return fail(rc, err);
+    rc = build_projection(c->geo, c->st, err);
+    if (rc) return fail(rc, err);
+    rc = build_near_zone(c->geo, params, c->st, err);
+    if (rc) return fail(rc, err);
+    c->ns = c->geo.ns;
+    c->B = params->batch;
+    c->prec = params->precision;
+    c->mv = c->st.mn + 1;
+    c->nnz = (int)c->st.col.size();
+    for (int a = 0; a < 3; ++a) {
+        c->gd.N[a] = c->st.N[a];
+        c->gd.L[a] = c->st.L[a];
+    }
+    c->gd.B = c->B;
+    c->rx = make_radix(c->gd.L[0]);
+    c->ry = make_radix(c->gd.L[1]);
+    c->rz = make_radix(c->gd.L[2]);
+    c->N3 = (size_t)c->gd.N[0] * c->gd.N[1] * c->gd.N[2];
+    c->Np = (size_t)c->gd.L[0] * c->gd.L[1] * c->gd.L[2];
+    c->gfold = (size_t)(c->gd.N[0] + 1) * (c->gd.N[1] + 1) * (c->gd.N[2] + 1);
+    exact_near_entries(c->geo, params, c->st);
+    if (hipGetDevice(&c->device) != hipSuccess) return fail(ETAIM_EHIP, "no HIP device");
+    c->stream = (hipStream_t)hip_stream;
+    rc = device_setup(c.get());
+    if (rc) return rc;
+    *out = c.release();
+    return ETAIM_OK;
+}
+
+int etaim_describe(const etaim_ctx* c, etaim_derived* o) {
+    CHK(check_ctx(c));
+    if (!o) return fail(ETAIM_EINVAL, "null output");
+    o->dt = c->st.dt;
+    o->h = c->st.h;
+    for (int a = 0; a < 3; ++a) {
+        o->origin[a] = c->st.x0[a];
+        o->grid[a] = c->st.N[a];
+        o->padded[a] = c->st.L[a];
+    }
+    o->rmax = c->st.rmax;
+    o->stencil_radius = c->st.rst;
+    o->ns = c->ns;
+    o->ng = c->st.ng;
+    o->mn = c->st.mn;
+    o->nnz = c->nnz;
+    o->batch = c->B;
+    o->precision = c->prec;
+    o->device_bytes = c->dev_bytes;
+    return ETAIM_OK;
+}
+
+int etaim_excitation_planewave(etaim_ctx* c, int32_t nb, const double* khat, const double* phat, double sigma,
+                               double td, void* V) {
+    CHK(check_ctx(c));
+    if (nb != c->B || !khat || !phat || !V || !(sigma > 0))
+        return fail(ETAIM_EINVAL, "excitation needs nb == batch, khat, phat, V and sigma > 0");
+    std::vector<double> kp(6 * (size_t)nb);
+    std::memcpy(kp.data(), khat, 3 * nb * sizeof(double));
+    std::memcpy(kp.data() + 3 * nb, phat, 3 * nb * sizeof(double));
+    double* d = nullptr;
+    CHK(c->upload(d, kp));
+    const size_t tot = (size_t)c->prm.nt_steps * nb * c->ns;
+    hipLaunchKernelGGL(k_excitation, dim3(blocks_for(tot)), dim3(256), 0, c->stream, (zd*)V, c->Sq, c->rq, d,
+                       d + 3 * nb, c->prm.nt_steps, nb, c->ns, c->st.dt, sigma, td, 2.0 * kPi * c->prm.fc);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->allocs.pop_back();
+    c->dev_bytes -= (int64_t)(kp.size() * sizeof(double));
+    HIPCHK(hipFree(d));
+    return ETAIM_OK;
+}
+
+int etaim_apply_z(etaim_ctx* c, int32_t m, const void* x, void* y) {
+    CHK(check_ctx(c));
+    if (m < 0 || m > c->st.ng || !x || !y) return fail(ETAIM_EINVAL, "apply_z needs 0 <= m <= ng and x, y");
+    if (c->prec == ETAIM_FP32)
+        CHK(Ops<float>::apply(c, m, (const zd*)x, nullptr, (zd*)y, 0));
+    else
+        CHK(Ops<double>::apply(c, m, (const zd*)x, nullptr, (zd*)y, 0));
+    return trace_flush(c);
+}
+
+int etaim_delayed_field(etaim_ctx* c, const void* hist, void* b) {
+    CHK(check_ctx(c));
+    if (!hist || !b) return fail(ETAIM_EINVAL, "null pointer");
+    const int ng = c->st.ng;
+    const size_t nB = (size_t)c->B * c->ns;
+    auto run = [&](auto tag) -> int {
+        using R = decltype(tag);
+        HIPCHK(hipMemsetAsync(c->ring, 0, (size_t)ng * 4 * c->B * c->Np * sizeof(cplx<R>), c->stream));
+        if (c->st.mn >= 1) HIPCHK(hipMemsetAsync(c->hist, 0, (size_t)c->st.mn * nB * sizeof(zd), c->stream));
+        for (int m = ng; m >= 1; --m) CHK(Ops<R>::commit(c, ng - m, (const zd*)hist + (size_t)(m - 1) * nB));
+        CHK(Ops<R>::delayed(c, ng, c->zero, (zd*)b, 0));
+        hipLaunchKernelGGL(k_residual, dim3(blocks_for(nB)), dim3(256), 0, c->stream, c->zero, (zd*)b, nB);
+        HIPCHK(hipGetLastError());
+        return trace_flush(c);
+    };
+    return c->prec == ETAIM_FP32 ? run(float{}) : run(double{});
+}
+
+int etaim_march(etaim_ctx* c, const void* V, void* I_out, int32_t nsteps, etaim_stats* st) {
+    CHK(check_ctx(c));
+    if (!V || !I_out) return fail(ETAIM_EINVAL, "null V or I_out");
+    if (nsteps < 0 || nsteps > c->prm.nt_steps) return fail(ETAIM_EINVAL, "nsteps out of range");
+    return c->prec == ETAIM_FP32 ? march_impl<float>(c, (const zd*)V, (zd*)I_out, st, false, nsteps)
+                                 : march_impl<double>(c, (const zd*)V, (zd*)I_out, st, false, nsteps);
+}
+
+int etaim_adjoint_march(etaim_ctx* c, const void* S, void* Lambda, etaim_stats* st) {
+    CHK(check_ctx(c));
+    if (!S || !Lambda) return fail(ETAIM_EINVAL, "null S or Lambda");
+    // Z^H = conj(Z): every operator is complex-symmetric, so the adjoint
+    // march runs the same kernels with conjugated Green spectra, near-zone
+    // values and preconditioner, backward in time
+    return c->prec == ETAIM_FP32 ? march_impl<float>(c, (const zd*)S, (zd*)Lambda, st, true, 0)
+                                 : march_impl<double>(c, (const zd*)S, (zd*)Lambda, st, true, 0);
+}
+
+int etaim_export(const etaim_ctx* c, int32_t what, void* host, size_t bytes) {
+    CHK(check_ctx(c));
+    if (!host) return fail(ETAIM_EINVAL, "null host pointer");
+    const Setup& s = c->st;
+    auto put = [&](const void* src, size_t n, bool device) -> int {
+        if (n != bytes) return fail(ETAIM_EINVAL, "export size mismatch: expected " + std::to_string(n));
+        if (device) {
+            HIPCHK(hipStreamSynchronize(c->stream));
+            HIPCHK(hipMemcpy(host, src, n, hipMemcpyDeviceToHost));
+        } else {
+            std::memcpy(host, src, n);
+        }
+        return ETAIM_OK;
+    };
+    switch (what) {
+        case 0: return put(s.lam.data(), s.lam.size() * sizeof(double), false);
+        case 1: return put(s.i0.data(), s.i0.size() * sizeof(int), false);
+        case 2: return put(s.rowptr.data(), s.rowptr.size() * sizeof(int), false);
+        case 3: return put(s.col.data(), s.col.size() * sizeof(int), false);
+        case 4: {
+            const size_t n = (size_t)c->nnz * c->mv;
+            if (bytes != n * sizeof(zd)) return fail(ETAIM_EINVAL, "export size mismatch");
+            std::vector<zd> v(n), o(n);
+            HIPCHK(hipStreamSynchronize(c->stream));
+            HIPCHK(hipMemcpy(v.data(), c->near64, n * sizeof(zd), hipMemcpyDeviceToHost));
+            for (int e = 0; e < c->nnz; ++e)
+                for (int m = 0; m < c->mv; ++m) o[(size_t)m * c->nnz + e] = v[(size_t)e * c->mv + m];
+            std::memcpy(host, o.data(), bytes);
+            return ETAIM_OK;
+        }
+        case 5: return put(c->diag, (size_t)c->ns * sizeof(zd), true);
+        case 6: return put(c->ghat64, (size_t)(s.ng + 1) * 2 * c->gfold * sizeof(zd), true);
+        default: return fail(ETAIM_EINVAL, "unknown export id");
+    }
+}
+
+int etaim_set_profiling(etaim_ctx* c, int32_t on) {
+    CHK(check_ctx(c));
+    CHK(trace_flush(c));
+    c->prof = on != 0;
+    if (c->prof)
+        for (int i = 0; i < ETAIM_K_COUNT; ++i) c->k_ms[i] = c->k_bytes[i] = 0, c->k_n[i] = 0;
+    return ETAIM_OK;
+}
+
+int etaim_kernel_stats(const etaim_ctx* c, int32_t cls, double* ms, double* bytes, int64_t* launches) {
+    CHK(check_ctx(c));
+    if (cls < 0 || cls >= ETAIM_K_COUNT || !ms || !bytes || !launches)
+        return fail(ETAIM_EINVAL, "kernel_stats needs a valid class and outputs");
+    *ms = c->k_ms[cls];
+    *bytes = c->k_bytes[cls];
+    *launches = c->k_n[cls];
+    return ETAIM_OK;
+}
+
+void etaim_destroy(etaim_ctx* c) {
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    delete c;
+}
+
+}  // extern "C"
+
+namespace {
+int farfield_taps(etaim_ctx* c, int nd, const double* dirs, zd*& F, double*& dd, int& ntap, int& m_lo) {
+    double rad = 0;
+    for (double v : c->geo.xyz) rad = std::max(rad, std::fabs(v));
+    const double smax = rad * std::sqrt(3.0) / (kC0 * c->st.dt);
+    m_lo = (int)std::floor(-1.0 - smax);
+    const int m_hi = (int)std::ceil((double)kQ + smax);
+    ntap = m_hi - m_lo + 1;
+    std::vector<double> dv(dirs, dirs + 3 * (size_t)nd);
+    CHK(c->upload(dd, dv));
+    CHK(c->alloc(F, (size_t)ntap * nd * 3 * c->ns));
+    const size_t tot = (size_t)ntap * nd * c->ns;
+    hipLaunchKernelGGL(k_farfield_taps, dim3(blocks_for(tot)), dim3(256), 0, c->stream, F, c->Sq, c->rq, dd, nd,
+                       c->ns, ntap, m_lo, c->st.dt, 2.0 * kPi * c->prm.fc, kMu0 / (4.0 * kPi));
+    HIPCHK(hipGetLastError());
+    return ETAIM_OK;
+}
+int release_last(etaim_ctx* c, int n) {
+    for (int i = 0; i < n && !c->allocs.empty(); ++i) {
+        HIPCHK(hipFree(c->allocs.back()));
+        c->allocs.pop_back();
+    }
+    return ETAIM_OK;
+}
+}  // namespace
+
+extern "C" {
+int etaim_farfield(etaim_ctx* c, int32_t nd, const double* dirs, const void* I, void* U) {
+    CHK(check_ctx(c));
+    if (nd < 1 || !dirs || !I || !U) return fail(ETAIM_EINVAL, "farfield needs nd >= 1, dirs, I and U");
+    zd* F = nullptr;
+    double* dd = nullptr;
+    int ntap = 0, m_lo = 0;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const int64_t before = c->dev_bytes;
+    CHK(farfield_taps(c, nd, dirs, F, dd, ntap, m_lo));
+    const int nout = c->prm.nt_steps * c->B * nd * 3;
+    hipLaunchKernelGGL(k_farfield_apply, dim3(nout), dim3(256), 0, c->stream, (zd*)U, F, (const zd*)I,
+                       c->prm.nt_steps, c->B, nd, c->ns, ntap, m_lo);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    CHK(release_last(c, 2));
+    c->dev_bytes = before;
+    return ETAIM_OK;
+}
+
+int etaim_farfield_adjoint(etaim_ctx* c, int32_t nd, const double* dirs, const void* Ubar, void* S) {
+    CHK(check_ctx(c));
+    if (nd < 1 || !dirs || !Ubar || !S) return fail(ETAIM_EINVAL, "farfield_adjoint needs nd >= 1, dirs, Ubar, S");
+    zd* F = nullptr;
+    double* dd = nullptr;
+    int ntap = 0, m_lo = 0;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const int64_t before = c->dev_bytes;
+    CHK(farfield_taps(c, nd, dirs, F, dd, ntap, m_lo));
+    const size_t tot = (size_t)c->prm.nt_steps * c->B * c->ns;
+    hipLaunchKernelGGL(k_farfield_adjoint, dim3(blocks_for(tot)), dim3(256), 0, c->stream, (zd*)S, F,
+                       (const zd*)Ubar, c->prm.nt_steps, c->B, nd, c->ns, ntap, m_lo);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    CHK(release_last(c, 2));
+    c->dev_bytes = before;
+    return ETAIM_OK;
+}
+}  // extern "C"

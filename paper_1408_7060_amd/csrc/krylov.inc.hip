@@ -1,0 +1,223 @@
+// FP64 kernels of right-preconditioned restarted GMRES (Sec. 5.1: diagonally
+// preconditioned GMRES), one Krylov space per excitation column b.
+// Vectors are [B][ns] complex128; the basis is [restart+1][B][ns].
+#pragma once
+#include "common.hpp"
+
+namespace etaim {
+
+__device__ __forceinline__ double block_sum256(double v, double* sh) {
+    // deterministic tree over a 256-thread block
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// h[i][b] = <V_i[b], w[b]> = sum_k conj(V_i[b][k]) w[b][k], i < nv.  grid (nv, B)
+__global__ void __launch_bounds__(256) k_dots(const zd* __restrict__ V, const zd* __restrict__ w, zd* __restrict__ h,
+                                              int ns, int B) {
+    __shared__ double sh[256];
+    const int i = blockIdx.x, b = blockIdx.y;
+    const zd* v = V + ((size_t)i * B + b) * ns;
+    const zd* x = w + (size_t)b * ns;
+    double re = 0, im = 0;
+    for (int k = threadIdx.x; k < ns; k += 256) {
+        const zd a = v[k], c = x[k];
+        re += a.x * c.x + a.y * c.y;
+        im += a.x * c.y - a.y * c.x;
+    }
+    re = block_sum256(re, sh);
+    im = block_sum256(im, sh);
+    if (threadIdx.x == 0) h[(size_t)i * B + b] = zd{re, im};
+}
+
+// w[b] -= sum_{i<nv} h[i][b] V_i[b]  (one classical Gram-Schmidt pass)
+__global__ void __launch_bounds__(256) k_orth(const zd* __restrict__ V, zd* __restrict__ w, const zd* __restrict__ h,
+                                              int nv, int ns, int B) {
+    const int b = blockIdx.y;
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= ns) return;
+    zd acc = w[(size_t)b * ns + k];
+    for (int i = 0; i < nv; ++i) acc -= h[(size_t)i * B + b] * V[((size_t)i * B + b) * ns + k];
+    w[(size_t)b * ns + k] = acc;
+}
+
+// nrm[b] = ||w[b]||
+__global__ void __launch_bounds__(256) k_norm(const zd* __restrict__ w, double* __restrict__ nrm, int ns) {
+    __shared__ double sh[256];
+    const int b = blockIdx.x;
+    const zd* x = w + (size_t)b * ns;
+    double s = 0;
+    for (int k = threadIdx.x; k < ns; k += 256) s += x[k].x * x[k].x + x[k].y * x[k].y;
+    s = block_sum256(s, sh);
+    if (threadIdx.x == 0) nrm[b] = sqrt(s);
+}
+
+// out[b] = w[b] / nrm[b] (0 if nrm == 0)
+__global__ void k_scale(const zd* __restrict__ w, const double* __restrict__ nrm, zd* __restrict__ out, int ns,
+                        int B) {
+    const size_t tot = (size_t)ns * B;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot; e += (size_t)gridDim.x * blockDim.x) {
+        const int b = (int)(e / ns);
+        const double n = nrm[b];
+        const double s = n > 0 ? 1.0 / n : 0.0;
+        out[e] = zd{w[e].x * s, w[e].y * s};
+    }
+}
+
+// r = rhs - r  (r holds A x on entry)
+__global__ void k_residual(const zd* __restrict__ rhs, zd* __restrict__ r, size_t n) {
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
+        r[e] = rhs[e] - r[e];
+}
+
+// Start of a cycle: beta = ||r||; column active iff beta > tol * bnorm.
+// g[b] = (beta, 0, ...), jcnt = 0.  flag[0] = number of active columns.
+__global__ void k_cycle_start(const double* __restrict__ beta, const double* __restrict__ bnorm,
+                              int* __restrict__ active, int* __restrict__ jcnt, zd* __restrict__ g,
+                              double* __restrict__ resid, int* __restrict__ flag, int B, int ldg, double tol) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int n = 0;
+    for (int b = 0; b < B; ++b) {
+        const double be = beta[b];
+        const bool fin = isfinite(be);
+        const int a = (fin && be > tol * bnorm[b]) ? 1 : 0;
+        active[b] = a;
+        jcnt[b] = 0;
+        resid[b] = bnorm[b] > 0 ? be / bnorm[b] : 0.0;
+        for (int i = 0; i < ldg; ++i) g[(size_t)b * ldg + i] = zd{0, 0};
+        g[(size_t)b * ldg] = zd{be, 0};
+        n += a;
+        if (!fin) flag[1] = 1;
+    }
+    flag[0] = n;
+}
+
+// Arnoldi column j for each active column b: Hessenberg entries
+// h1 + h2 (the two classical Gram-Schmidt passes) (+ nrm[b] = h_{j+1,j}), previous Givens rotations, a new
+// rotation, residual estimate |g_{j+1}|.  Single thread.
+__global__ void k_arnoldi_update(const zd* __restrict__ h1, const zd* __restrict__ h2,
+                                 const double* __restrict__ nrm, zd* __restrict__ H,
+                                 double* __restrict__ cs, zd* __restrict__ sn, zd* __restrict__ g,
+                                 int* __restrict__ active, int* __restrict__ jcnt, double* __restrict__ resid,
+                                 const double* __restrict__ bnorm, int* __restrict__ flag, int j, int B,
+                                 int restart, double tol) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int ldh = restart + 1;
+    int n = 0;
+    for (int b = 0; b < B; ++b) {
+        if (!active[b]) continue;
+        zd* col = H + ((size_t)b * restart + j) * ldh;
+        for (int i = 0; i <= j; ++i) col[i] = h1[(size_t)i * B + b] + h2[(size_t)i * B + b];
+        col[j + 1] = zd{nrm[b], 0};
+        double* c = cs + (size_t)b * restart;
+        zd* s = sn + (size_t)b * restart;
+        for (int i = 0; i < j; ++i) {
+            const zd a = col[i], bb = col[i + 1];
+            col[i] = c[i] * a + s[i] * bb;
+            col[i + 1] = c[i] * bb - conjz(s[i]) * a;
+        }
+        const zd a = col[j];
+        const double bv = col[j + 1].x;
+        const double aa = sqrt(a.x * a.x + a.y * a.y);
+        const double r = sqrt(aa * aa + bv * bv);
+        double cj;
+        zd sj;
+        if (aa == 0.0) {
+            cj = 0.0;
+            sj = zd{1.0, 0.0};
+        } else {
+            cj = aa / r;
+            sj = zd{a.x / aa * bv / r, a.y / aa * bv / r};
+        }
+        c[j] = cj;
+        s[j] = sj;
+        col[j] = cj * a + sj * col[j + 1];
+        col[j + 1] = zd{0, 0};
+        zd* gb = g + (size_t)b * ldh;
+        const zd gj = gb[j];
+        gb[j] = cj * gj;
+        gb[j + 1] = zd{0, 0} - conjz(sj) * gj;
+        const double est = sqrt(gb[j + 1].x * gb[j + 1].x + gb[j + 1].y * gb[j + 1].y);
+        resid[b] = bnorm[b] > 0 ? est / bnorm[b] : 0.0;
+        jcnt[b] = j + 1;
+        if (!isfinite(est)) {
+            flag[1] = 1;
+            active[b] = 0;
+        } else if (est <= tol * bnorm[b] || nrm[b] == 0.0 || j + 1 == restart) {
+            active[b] = 0;
+        }
+        n += active[b];
+    }
+    flag[0] = n;
+}
+
+// Back-substitution R y = g per column (size jcnt[b]); y[b][i].
+__global__ void k_backsolve(const zd* __restrict__ H, const zd* __restrict__ g, const int* __restrict__ jcnt,
+                            zd* __restrict__ y, int B, int restart) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    const int ldh = restart + 1;
+    const int n = jcnt[b];
+    zd* yb = y + (size_t)b * restart;
+    for (int i = n - 1; i >= 0; --i) {
+        zd acc = g[(size_t)b * ldh + i];
+        for (int q = i + 1; q < n; ++q) acc -= H[((size_t)b * restart + q) * ldh + i] * yb[q];
+        const zd d = H[((size_t)b * restart + i) * ldh + i];
+        const double dd = d.x * d.x + d.y * d.y;
+        yb[i] = dd > 0 ? zd{(acc.x * d.x + acc.y * d.y) / dd, (acc.y * d.x - acc.x * d.y) / dd} : zd{0, 0};
+    }
+}
+
+// x[b] += dinv . sum_{i<jcnt[b]} y[b][i] V_i[b]
+__global__ void __launch_bounds__(256) k_update_x(zd* __restrict__ x, const zd* __restrict__ V,
+                                                  const zd* __restrict__ y, const int* __restrict__ jcnt,
+                                                  const zd* __restrict__ dinv, int ns, int B, int restart) {
+    const int b = blockIdx.y;
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= ns) return;
+    const int n = jcnt[b];
+    if (n == 0) return;
+    zd acc{0, 0};
+    for (int i = 0; i < n; ++i) acc += y[(size_t)b * restart + i] * V[((size_t)i * B + b) * ns + k];
+    const zd d = dinv[k];
+    x[(size_t)b * ns + k] += acc * d;
+}
+
+__global__ void k_copy_conj(const zd* __restrict__ in, zd* __restrict__ out, size_t n, int conj) {
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        zd v = in[e];
+        if (conj) v.y = -v.y;
+        out[e] = v;
+    }
+}
+
+// out[e][m] = in[perm[e]][m] (rows of mv values)
+__global__ void k_permute_rows(const zd* __restrict__ in, zd* __restrict__ out, const int* __restrict__ perm, int n,
+                               int mv) {
+    const size_t tot = (size_t)n * mv;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < tot; i += (size_t)gridDim.x * blockDim.x) {
+        const size_t e = i / mv, m = i - e * mv;
+        out[i] = in[(size_t)perm[e] * mv + m];
+    }
+}
+
+template <typename R>
+__global__ void k_to_r(const zd* __restrict__ in, cplx<R>* __restrict__ out, size_t n) {
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
+        out[e] = cplx<R>{(R)in[e].x, (R)in[e].y};
+}
+
+template <typename R>
+__global__ void k_real_to_r(const double* __restrict__ in, R* __restrict__ out, size_t n) {
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
+        out[e] = (R)in[e];
+}
+
+}  // namespace etaim

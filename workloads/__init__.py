@@ -204,6 +204,12 @@ SPHERE_L4_ADJ = Workload("sphere_L4_r1_600MHz_adjoint", level=4, radius=1.0, f0=
                          frac_bw=0.30, nt=300, grid=48, near_lambda=0.3, ng=24, rotate_seed=0)
 # mid-size parity case: level-3 sphere, 1920 RWG, several FFT tiles and ragged lines
 SPHERE_L3 = Workload("sphere_L3_r1_300MHz", level=3, radius=1.0, f0=300e6, frac_bw=0.20,
-                     nt=40, grid=18, near_lambda=0.3, ng=8, rotate_seed=3)
+                     nt=40, grid=18, near_lambda=0.2, ng=6, rotate_seed=3)
 
-WORKLOADS = {w.name: w for w in (SPHERE_L2, SPHERE_L4, SPHERE_L4_BATCH, SPHERE_L4_ADJ, SPHERE_L3)}
+# narrow-band (+-1 %, chi ~ 101) variant of the level-2 sphere: the regime in
+# which CPPIF envelope marching is stable, used for full-march parity
+SPHERE_L2_NARROW = Workload("sphere_L2_r0.5_300MHz_narrow", level=2, radius=0.5, f0=300e6, frac_bw=0.01,
+                            nt=60, grid=16, near_lambda=0.3, beta=0.2)
+
+WORKLOADS = {w.name: w for w in (SPHERE_L2, SPHERE_L4, SPHERE_L4_BATCH, SPHERE_L4_ADJ, SPHERE_L3,
+                                 SPHERE_L2_NARROW)}
