@@ -71,7 +71,7 @@ __global__ void __launch_bounds__(256) k_fwdx_gather(const zd* __restrict__ x_in
 __device__ __forceinline__ int fold(int k, int n2) { return k <= n2 / 2 ? k : n2 - k; }
 
 // z-pass with Green multiply, in place on B.  Block: MT consecutive kx at
-// one ky; loops over bc.  G: folded spectra of one m: [2][Nz+1][Ny+1][Nx+1].
+// one ky of one component grid bc = blockIdx.z.  G: folded spectra of one m: [2][Nz+1][Ny+1][Nx+1].
 template <typename R>
 __global__ void __launch_bounds__(256) k_zgreen(cplx<R>* __restrict__ Bg, const cplx<R>* __restrict__ G,
                                                 const cplx<R>* __restrict__ tw, Radix pl, GridDims g, int mt,
@@ -85,7 +85,8 @@ __global__ void __launch_bounds__(256) k_zgreen(cplx<R>* __restrict__ Bg, const 
     const size_t plane = (size_t)Ly * Lx;
     const int gx = g.N[0] + 1, gy = g.N[1] + 1, gz = g.N[2] + 1;
     const int fy = fold(ky, Ly);
-    for (int bc = 0; bc < 4 * g.B; ++bc) {
+    {
+        const int bc = blockIdx.z;
         const int t = (bc & 3) == 3 ? 1 : 0;
         cplx<R>* col = Bg + (size_t)bc * Nz * plane + (size_t)ky * Lx;
         for (int e = threadIdx.x; e < mt * Lz; e += blockDim.x) {
@@ -95,18 +96,32 @@ __global__ void __launch_bounds__(256) k_zgreen(cplx<R>* __restrict__ Bg, const 
             if (kx < Lx && z < Nz) v = col[(size_t)z * plane + kx];
             b0[l * ldl + z] = v;
         }
+        // Green values of this thread's elements, fetched before the FFT
+        constexpr int kMaxG = 8;
+        cplx<R> gpre[kMaxG];
+#pragma unroll
+        for (int q = 0; q < kMaxG; ++q) {
+            const int e = threadIdx.x + q * blockDim.x;
+            gpre[q] = cplx<R>{0, 0};
+            if (e < mt * Lz) {
+                const int l = e / Lz, kz = e - l * Lz;
+                const int kx = kx0 + l;
+                if (kx < Lx) {
+                    gpre[q] = G[(((size_t)t * gz + fold(kz, Lz)) * gy + fy) * gx + fold(kx, Lx)];
+                    if (conj_g) gpre[q].y = -gpre[q].y;
+                }
+            }
+        }
         __syncthreads();
         cplx<R>* res = lds_fft<R>(b0, b1, mt, ldl, pl, tw, false);
         cplx<R>* oth = res == b0 ? b1 : b0;
-        for (int e = threadIdx.x; e < mt * Lz; e += blockDim.x) {
-            const int l = e / Lz, kz = e - l * Lz;
-            const int kx = kx0 + l;
-            cplx<R> gv{0, 0};
-            if (kx < Lx) {
-                gv = G[(((size_t)t * gz + fold(kz, Lz)) * gy + fy) * gx + fold(kx, Lx)];
-                if (conj_g) gv.y = -gv.y;
+#pragma unroll
+        for (int q = 0; q < kMaxG; ++q) {
+            const int e = threadIdx.x + q * blockDim.x;
+            if (e < mt * Lz) {
+                const int l = e / Lz, kz = e - l * Lz;
+                oth[l * ldl + kz] = res[l * ldl + kz] * gpre[q];
             }
-            oth[l * ldl + kz] = res[l * ldl + kz] * gv;
         }
         __syncthreads();
         cplx<R>* res2 = lds_fft<R>(oth, res, mt, ldl, pl, tw, true);
@@ -115,7 +130,6 @@ __global__ void __launch_bounds__(256) k_zgreen(cplx<R>* __restrict__ Bg, const 
             const int kx = kx0 + l;
             if (kx < Lx) col[(size_t)z * plane + kx] = res2[l * ldl + z];
         }
-        __syncthreads();
     }
 }
 
@@ -130,7 +144,8 @@ __global__ void __launch_bounds__(256) k_zcommit(const cplx<R>* __restrict__ Bg,
     cplx<R>* b1 = b0 + mt * ldl;
     const int kx0 = blockIdx.x * mt, ky = blockIdx.y;
     const size_t plane = (size_t)Ly * Lx;
-    for (int bc = 0; bc < 4 * g.B; ++bc) {
+    {
+        const int bc = blockIdx.z;
         const cplx<R>* col = Bg + (size_t)bc * Nz * plane + (size_t)ky * Lx;
         for (int e = threadIdx.x; e < mt * Lz; e += blockDim.x) {
             const int z = e / mt, l = e - z * mt;
@@ -147,7 +162,6 @@ __global__ void __launch_bounds__(256) k_zcommit(const cplx<R>* __restrict__ Bg,
             const int kx = kx0 + l;
             if (kx < Lx) o[(size_t)kz * plane + kx] = res[l * ldl + kz];
         }
-        __syncthreads();
     }
 }
 
@@ -169,7 +183,8 @@ __global__ void __launch_bounds__(256) k_zdelayed(const cplx<R>* __restrict__ ri
     const int gx = g.N[0] + 1, gy = g.N[1] + 1, gz = g.N[2] + 1;
     const size_t gsz = (size_t)2 * gz * gy * gx;
     const int fy = fold(ky, Ly);
-    for (int bc = 0; bc < 4 * g.B; ++bc) {
+    {
+        const int bc = blockIdx.z;
         const int t = (bc & 3) == 3 ? 1 : 0;
         for (int e = threadIdx.x; e < mt * Lz; e += blockDim.x) {
             const int kz = e / mt, l = e - kz * mt;
@@ -196,7 +211,6 @@ __global__ void __launch_bounds__(256) k_zdelayed(const cplx<R>* __restrict__ ri
             const int kx = kx0 + l;
             if (kx < Lx) col[(size_t)z * plane + kx] = res[l * ldl + z];
         }
-        __syncthreads();
     }
 }
 

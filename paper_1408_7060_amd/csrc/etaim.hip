@@ -245,9 +245,10 @@ struct Ops {
     }
     static int zgreen(etaim_ctx* c, int m, int conj) {
         const GridDims& g = c->gd;
-        const int mt = pick_lines(g.L[2], sizeof(cplx<R>), 16);
+        // k_zgreen prefetches at most 8 Green values per thread (256 threads)
+        const int mt = std::max(1, std::min(pick_lines(g.L[2], sizeof(cplx<R>), 16), 2048 / g.L[2]));
         const size_t lds = 2 * (size_t)mt * (g.L[2] + 1) * sizeof(cplx<R>);
-        dim3 grid((g.L[0] + mt - 1) / mt, g.L[1]);
+        dim3 grid((g.L[0] + mt - 1) / mt, g.L[1], 4 * c->B);
         const double s = sizeof(cplx<R>);
         Trace t(c, ETAIM_K_ZGREEN, 2.0 * 4 * c->B * g.N[2] * g.L[1] * g.L[0] * s + 2.0 * c->gfold * s);
         hipLaunchKernelGGL(k_zgreen<R>, grid, dim3(256), lds, c->stream, Bg(c), ghat(c) + (size_t)m * 2 * c->gfold,
@@ -281,7 +282,7 @@ struct Ops {
         const GridDims& g = c->gd;
         const int mt = pick_lines(g.L[2], sizeof(cplx<R>), 16);
         const size_t lds = 2 * (size_t)mt * (g.L[2] + 1) * sizeof(cplx<R>);
-        dim3 grid((g.L[0] + mt - 1) / mt, g.L[1]);
+        dim3 grid((g.L[0] + mt - 1) / mt, g.L[1], 4 * c->B);
         const int nm = std::min(c->st.ng, cur);
         {
             const double s = sizeof(cplx<R>);
@@ -301,7 +302,7 @@ struct Ops {
         const GridDims& g = c->gd;
         const int mt = pick_lines(g.L[2], sizeof(cplx<R>), 16);
         const size_t lds = 2 * (size_t)mt * (g.L[2] + 1) * sizeof(cplx<R>);
-        dim3 grid((g.L[0] + mt - 1) / mt, g.L[1]);
+        dim3 grid((g.L[0] + mt - 1) / mt, g.L[1], 4 * c->B);
         const size_t slot_sz = (size_t)4 * c->B * c->Np;
         cplx<R>* slot = ring(c) + (size_t)(cur % c->st.ng) * slot_sz;
         {
@@ -342,8 +343,8 @@ int gmres(etaim_ctx* c, const zd* rhs, zd* x, int conj, StepResult& res) {
         CHK(Ops<R>::apply(c, 0, x, nullptr, c->w, conj));
         hipLaunchKernelGGL(k_residual, dim3(blocks_for(nB)), dim3(256), 0, c->stream, rhs, c->w, nB);
         hipLaunchKernelGGL(k_norm, dim3(B), dim3(256), 0, c->stream, c->w, c->beta, ns);
-        HIPCHK(hipMemsetAsync(c->flag, 0, 2 * sizeof(int), c->stream));
-        hipLaunchKernelGGL(k_cycle_start, dim3(1), dim3(1), 0, c->stream, c->beta, c->bnorm, c->active, c->jcnt,
+        hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, c->stream, c->flag, 2, 0);
+        hipLaunchKernelGGL(k_cycle_start, dim3(1), dim3(256), 0, c->stream, c->beta, c->bnorm, c->active, c->jcnt,
                            c->g, c->resid, c->flag, B, c->ldg, tol);
         HIPCHK(hipMemcpyAsync(c->flag_h, c->flag, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
@@ -383,7 +384,8 @@ int gmres(etaim_ctx* c, const zd* rhs, zd* x, int conj, StepResult& res) {
             hipLaunchKernelGGL(k_orth, go, dim3(256), 0, c->stream, c->Vk, c->w, c->h2, j + 1, ns, B);
             hipLaunchKernelGGL(k_norm, dim3(B), dim3(256), 0, c->stream, c->w, c->nrm, ns);
             hipLaunchKernelGGL(k_scale, dim3(blocks_for(nB)), dim3(256), 0, c->stream, c->w, c->nrm, vn, ns, B);
-            hipLaunchKernelGGL(k_arnoldi_update, dim3(1), dim3(1), 0, c->stream, c->h1, c->h2, c->nrm, c->H, c->cs,
+            hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, c->stream, c->flag, 2, 0);
+            hipLaunchKernelGGL(k_arnoldi_update, dim3(1), dim3(256), 0, c->stream, c->h1, c->h2, c->nrm, c->H, c->cs,
                                c->sn, c->g, c->active, c->jcnt, c->resid, c->bnorm, c->flag, j, B, rs, tol);
             }
             HIPCHK(hipMemcpyAsync(c->flag_h, c->flag, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));

@@ -78,13 +78,14 @@ __global__ void k_residual(const zd* __restrict__ rhs, zd* __restrict__ r, size_
 }
 
 // Start of a cycle: beta = ||r||; column active iff beta > tol * bnorm.
-// g[b] = (beta, 0, ...), jcnt = 0.  flag[0] = number of active columns.
-__global__ void k_cycle_start(const double* __restrict__ beta, const double* __restrict__ bnorm,
-                              int* __restrict__ active, int* __restrict__ jcnt, zd* __restrict__ g,
-                              double* __restrict__ resid, int* __restrict__ flag, int B, int ldg, double tol) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    int n = 0;
-    for (int b = 0; b < B; ++b) {
+// g[b] = (beta, 0, ...), jcnt = 0.  flag[0] = number of active columns,
+// flag[1] set on a non-finite residual.  One block, one thread per column
+// (strided); flag must be zero on entry.
+__global__ void __launch_bounds__(256) k_cycle_start(const double* __restrict__ beta, const double* __restrict__ bnorm,
+                                                     int* __restrict__ active, int* __restrict__ jcnt,
+                                                     zd* __restrict__ g, double* __restrict__ resid,
+                                                     int* __restrict__ flag, int B, int ldg, double tol) {
+    for (int b = threadIdx.x; b < B; b += blockDim.x) {
         const double be = beta[b];
         const bool fin = isfinite(be);
         const int a = (fin && be > tol * bnorm[b]) ? 1 : 0;
@@ -93,25 +94,24 @@ __global__ void k_cycle_start(const double* __restrict__ beta, const double* __r
         resid[b] = bnorm[b] > 0 ? be / bnorm[b] : 0.0;
         for (int i = 0; i < ldg; ++i) g[(size_t)b * ldg + i] = zd{0, 0};
         g[(size_t)b * ldg] = zd{be, 0};
-        n += a;
-        if (!fin) flag[1] = 1;
+        if (a) atomicAdd(&flag[0], 1);
+        if (!fin) atomicOr(&flag[1], 1);
     }
-    flag[0] = n;
 }
 
 // Arnoldi column j for each active column b: Hessenberg entries
-// h1 + h2 (the two classical Gram-Schmidt passes) (+ nrm[b] = h_{j+1,j}), previous Givens rotations, a new
-// rotation, residual estimate |g_{j+1}|.  Single thread.
-__global__ void k_arnoldi_update(const zd* __restrict__ h1, const zd* __restrict__ h2,
-                                 const double* __restrict__ nrm, zd* __restrict__ H,
-                                 double* __restrict__ cs, zd* __restrict__ sn, zd* __restrict__ g,
-                                 int* __restrict__ active, int* __restrict__ jcnt, double* __restrict__ resid,
-                                 const double* __restrict__ bnorm, int* __restrict__ flag, int j, int B,
-                                 int restart, double tol) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// h1 + h2 (the two classical Gram-Schmidt passes) and h_{j+1,j} = nrm[b],
+// previous Givens rotations, a new rotation, residual estimate |g_{j+1}|.
+// One block, one thread per column (strided); flag must be zero on entry.
+__global__ void __launch_bounds__(256) k_arnoldi_update(const zd* __restrict__ h1, const zd* __restrict__ h2,
+                                                        const double* __restrict__ nrm, zd* __restrict__ H,
+                                                        double* __restrict__ cs, zd* __restrict__ sn,
+                                                        zd* __restrict__ g, int* __restrict__ active,
+                                                        int* __restrict__ jcnt, double* __restrict__ resid,
+                                                        const double* __restrict__ bnorm, int* __restrict__ flag,
+                                                        int j, int B, int restart, double tol) {
     const int ldh = restart + 1;
-    int n = 0;
-    for (int b = 0; b < B; ++b) {
+    for (int b = threadIdx.x; b < B; b += blockDim.x) {
         if (!active[b]) continue;
         zd* col = H + ((size_t)b * restart + j) * ldh;
         for (int i = 0; i <= j; ++i) col[i] = h1[(size_t)i * B + b] + h2[(size_t)i * B + b];
@@ -148,14 +148,13 @@ __global__ void k_arnoldi_update(const zd* __restrict__ h1, const zd* __restrict
         resid[b] = bnorm[b] > 0 ? est / bnorm[b] : 0.0;
         jcnt[b] = j + 1;
         if (!isfinite(est)) {
-            flag[1] = 1;
+            atomicOr(&flag[1], 1);
             active[b] = 0;
         } else if (est <= tol * bnorm[b] || nrm[b] == 0.0 || j + 1 == restart) {
             active[b] = 0;
         }
-        n += active[b];
+        if (active[b]) atomicAdd(&flag[0], 1);
     }
-    flag[0] = n;
 }
 
 // Back-substitution R y = g per column (size jcnt[b]); y[b][i].
@@ -196,6 +195,10 @@ __global__ void k_copy_conj(const zd* __restrict__ in, zd* __restrict__ out, siz
         if (conj) v.y = -v.y;
         out[e] = v;
     }
+}
+
+__global__ void k_fill_int(int* __restrict__ p, int n, int v) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = v;
 }
 
 // out[e][m] = in[perm[e]][m] (rows of mv values)

@@ -172,8 +172,6 @@ int build_geometry(const etaim_mesh* m, const etaim_rwg* r, Geometry& g, std::st
         g.nrm[3 * t] = nn.x;
         g.nrm[3 * t + 1] = nn.y;
         g.nrm[3 * t + 2] = nn.z;
-        const V3 ce = (1.0 / 3.0) * V3{0, 0, 0};
-        (void)ce;
         g.cen[3 * t] = (a.x + b.x + c.x) / 3.0;
         g.cen[3 * t + 1] = (a.y + b.y + c.y) / 3.0;
         g.cen[3 * t + 2] = (a.z + b.z + c.z) / 3.0;
@@ -282,6 +280,10 @@ int derive_parameters(const Geometry& g, const etaim_params* p, Setup& s, std::s
             return ETAIM_EINVAL;
         }
         s.L[a] = 2 * s.N[a];
+        if (s.L[a] > 2048) {
+            err = "padded FFT length above 2048 is not supported";
+            return ETAIM_EUNSUPPORTED;
+        }
         if (!radix23(s.L[a])) {
             err = "padded FFT length 2*grid must be a product of 2 and 3";
             return ETAIM_EUNSUPPORTED;
