@@ -34,7 +34,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-FFT_CLASSES = ("anterp_x", "fft_y_fwd", "zgreen", "fft_y_inv", "fft_x_inv", "interp_near", "zdelayed", "zcommit")
+CSRC = os.path.join(ROOT, "paper_1408_7060_amd", "csrc")
+FFT_CLASSES = ("anterp_x", "yz_green", "fft_x_inv", "interp_near", "yz_delayed", "yz_commit")
 
 
 def log(*a):
@@ -86,6 +87,30 @@ def cpu_baseline(wl, iters_per_step, budget_s=20.0):
                       f"near-zone values zero (cost is value-independent)"}
 
 
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(name.encode() + f.read())
+    return h.hexdigest()
+
+
+def hbm_traffic(workload: str, kernel: str):
+    """Measured HBM bytes per launch of `kernel` (FETCH_SIZE + WRITE_SIZE,
+    calibrated on a plain copy), from profiles/hbm_traffic_<workload>.json;
+    None if absent or taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    k = rec.get("kernels", {}).get(kernel)
+    if k is None or rec.get("source_sha256") != kernel_source_hash():
+        return None
+    return k["bytes_per_launch"]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,6 +119,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--workload", default="batch", choices=["batch", "single"])
+    ap.add_argument("--calib-copy", type=int, default=0,
+                    help="first copy this many MiB device-to-device (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is design-only"}))
@@ -106,6 +133,14 @@ def main():
     K = args.steps or wl.nt
     nt = max(K, args.warmup, 1)
     torch.cuda.set_device(0)
+    if args.calib_copy:
+        n = args.calib_copy * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {args.calib_copy} MiB done")
+        del src, dst
     log(f"[bench] set-up {wl.name}: B={wl.batch} nt={nt}")
     t = time.perf_counter()
     P = make_problem(wl, FP32, wl.batch, nt, 1e-5)
@@ -135,8 +170,9 @@ def main():
     dom = max(FFT_CLASSES, key=lambda n: ks[n]["ms"])
     d = ks[dom]
     achieved = d["bytes"] / d["launches"] / (d["ms"] / d["launches"] / 1e3) / 1e9
+    traffic = hbm_traffic(wl.name, dom)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
             "bytes_per_launch": d["bytes"] / d["launches"], "avg_launch_ms": d["ms"] / d["launches"]}
     out = {"metric": "ET-AIM time-steps/s & FFT-matvec HBM GB/s, FP32 batched vs FP64, 1 MI355X",
            "value": round(steps_s, 4), "unit": "time-steps/s", "n_gpus": 1, "steps": K, "warmup": args.warmup,

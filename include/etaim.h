@@ -184,15 +184,13 @@ int etaim_adjoint_march(etaim_ctx *ctx, const void *S, void *Lambda, etaim_stats
  * context stream around every launch of the class, with the algorithmic
  * bytes of that launch: compulsory reads + writes of its inputs/outputs). */
 #define ETAIM_K_ANTERP_X 0    /* anterpolation gather + forward x-FFT */
-#define ETAIM_K_FFT_Y_FWD 1   /* forward y-FFT pass */
-#define ETAIM_K_ZGREEN 2      /* z-FFT, Green-spectrum multiply, inverse z-FFT */
-#define ETAIM_K_FFT_Y_INV 3   /* inverse y-FFT pass */
-#define ETAIM_K_FFT_X_INV 4   /* inverse x-FFT pass */
-#define ETAIM_K_INTERP_NEAR 5 /* interpolation + near-zone SpMV */
-#define ETAIM_K_ZDELAYED 6    /* k-space temporal sum over the history + inverse z-FFT */
-#define ETAIM_K_ZCOMMIT 7     /* forward z-FFT into the history ring */
-#define ETAIM_K_KRYLOV 8      /* GMRES vector kernels */
-#define ETAIM_K_COUNT 9
+#define ETAIM_K_YZ_GREEN 1    /* per x-frequency plane: 2-D FFT, Green multiply, inverse 2-D FFT */
+#define ETAIM_K_FFT_X_INV 2   /* inverse x-FFT pass */
+#define ETAIM_K_INTERP_NEAR 3 /* interpolation + near-zone SpMV */
+#define ETAIM_K_YZ_DELAYED 4  /* k-space temporal sum over the history + inverse 2-D FFT */
+#define ETAIM_K_YZ_COMMIT 5   /* forward 2-D FFT into the history ring */
+#define ETAIM_K_KRYLOV 6      /* GMRES vector kernels */
+#define ETAIM_K_COUNT 7
 
 /* Turn per-class kernel tracing on (1) or off (0); turning it on clears the
  * counters.  Tracing adds two event records per launch. */

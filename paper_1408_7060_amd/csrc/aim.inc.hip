@@ -1,13 +1,15 @@
 // ET-AIM grid kernels (Sec. 4 stages (i)-(iv)):
 //  k_fwdx_gather  anterpolation (node-major gather of the projection) fused
 //                 with the forward x-FFT of the zero-padded grid
-//  k_zgreen       forward z-FFT, Green-spectrum multiply, inverse z-FFT
-//  k_zcommit      forward z-FFT into a history-ring slot
-//  k_zdelayed     k-space temporal sum over the history ring, inverse z-FFT
+//  k_yz_green     per x-frequency plane: 2-D (y,z) FFT, Green-spectrum
+//                 multiply, inverse 2-D FFT, all in LDS
+//  k_yz_commit    per plane: forward 2-D FFT into a history-ring slot
+//  k_yz_delayed   per plane: k-space temporal sum over the history ring,
+//                 inverse 2-D FFT
 //  k_interp_near  interpolation (projection transposed) + near-zone SpMV
 // Grid layouts (per excitation b and component c = x,y,z,charge; bc = 4b+c):
-//  A: [bc][z<Nz][y<Ny][kx<Lx]   B: [bc][z<Nz][ky<Ly][kx<Lx]
-//  ring slot: [bc][kz<Lz][ky<Ly][kx<Lx]   P: [bc][z][y][x] (N per bc)
+//  A: [bc][kx<Lx][z<Nz][y<Ny] (x-transformed, plane-major)
+//  ring slot: [bc][kx<Lx][kz<Lz][ky<Ly]   P: [bc][z][y][x] (N per bc)
 #pragma once
 #include "fft.inc.hip"
 
@@ -22,20 +24,22 @@ __device__ __forceinline__ cplx<R> to_r(zd v) {
     return cplx<R>{(R)v.x, (R)v.y};
 }
 
-// Anterpolation + forward x-pass.  Block: MR rows (y) of one (z, b), all 4
-// components -> 4*MR lines of length Lx.  x_in: [B][ns] complex128;
-// dinv (optional): right preconditioner diag^-1 [ns].
+// Anterpolation + forward x-pass.  Block (512 threads): MR rows (y) of one
+// (z, b), all 4 components -> 4*MR lines of length Lx, transformed in place
+// in LDS.  x_in: [B][ns] complex128; dinv (optional): right preconditioner
+// diag^-1 [ns].  Output in the plane-major layout A[bc][kx][z][y] (runs of
+// MR consecutive y).
 template <typename R>
-__global__ void __launch_bounds__(256) k_fwdx_gather(const zd* __restrict__ x_in, const zd* __restrict__ dinv,
-                                                     const int* __restrict__ nptr, const int* __restrict__ nk,
-                                                     const R* __restrict__ nw, cplx<R>* __restrict__ A,
-                                                     const cplx<R>* __restrict__ tw, Radix pl, GridDims g,
-                                                     int mr, int ns, int conj_in) {
+__global__ void __launch_bounds__(kPlaneThreads) k_fwdx_gather(
+    const zd* __restrict__ x_in, const zd* __restrict__ dinv, const int* __restrict__ nptr,
+    const int* __restrict__ nk, const R* __restrict__ nw, cplx<R>* __restrict__ A, const cplx<R>* __restrict__ tw_g,
+    Radix pl, GridDims g, int mr, int ns, int conj_in) {
     extern __shared__ unsigned char smem_raw[];
     const int Lx = g.L[0], Nx = g.N[0], Ny = g.N[1], Nz = g.N[2];
     const int ldl = Lx + 1, nl = 4 * mr;
-    cplx<R>* b0 = reinterpret_cast<cplx<R>*>(smem_raw);
-    cplx<R>* b1 = b0 + nl * ldl;
+    cplx<R>* buf = reinterpret_cast<cplx<R>*>(smem_raw);
+    cplx<R>* tw = buf + nl * ldl;
+    for (int i = threadIdx.x; i < Lx; i += blockDim.x) tw[i] = tw_g[i];
     const int y0 = blockIdx.x * mr, z = blockIdx.y, b = blockIdx.z;
     const zd* xb = x_in + (size_t)b * ns;
     for (int e = threadIdx.x; e < mr * Lx; e += blockDim.x) {
@@ -56,162 +60,158 @@ __global__ void __launch_bounds__(256) k_fwdx_gather(const zd* __restrict__ x_in
             }
         }
 #pragma unroll
-        for (int c = 0; c < 4; ++c) b0[(c * mr + r) * ldl + x] = acc[c];
+        for (int c = 0; c < 4; ++c) buf[(c * mr + r) * ldl + x] = acc[c];
     }
     __syncthreads();
-    cplx<R>* res = lds_fft<R>(b0, b1, nl, ldl, pl, tw, false);
+    plane_fft<R>(buf, nl, ldl, 1, pl, tw, false);
+    const size_t plane = (size_t)Nz * Ny;
     for (int e = threadIdx.x; e < nl * Lx; e += blockDim.x) {
-        const int l = e / Lx, kx = e - l * Lx;
-        const int c = l / mr, r = l - c * mr;
+        const int r = e % mr, rest = e / mr;
+        const int kx = rest % Lx, c = rest / Lx;
         const int y = y0 + r;
-        if (y < Ny) A[((((size_t)b * 4 + c) * Nz + z) * Ny + y) * Lx + kx] = res[l * ldl + kx];
+        if (y < Ny) A[(((size_t)b * 4 + c) * Lx + kx) * plane + (size_t)z * Ny + y] = buf[(c * mr + r) * ldl + kx];
     }
 }
 
 __device__ __forceinline__ int fold(int k, int n2) { return k <= n2 / 2 ? k : n2 - k; }
 
-// z-pass with Green multiply, in place on B.  Block: MT consecutive kx at
-// one ky of one component grid bc = blockIdx.z.  G: folded spectra of one m: [2][Nz+1][Ny+1][Nx+1].
+// Shared shapes of the plane kernels: one block per (kx, bc) holds the
+// (y, z) plane of one x-frequency as buf[z * ldp + y], z in [0, Lz),
+// y in [0, Ly), ldp = Ly + 1.  A plane of the x-transformed grid is
+// A[bc][kx][z < Nz][y < Ny]; a ring slot plane is [bc][kx][kz][ky].
 template <typename R>
-__global__ void __launch_bounds__(256) k_zgreen(cplx<R>* __restrict__ Bg, const cplx<R>* __restrict__ G,
-                                                const cplx<R>* __restrict__ tw, Radix pl, GridDims g, int mt,
-                                                int conj_g) {
-    extern __shared__ unsigned char smem_raw[];
-    const int Lx = g.L[0], Ly = g.L[1], Lz = g.L[2], Nz = g.N[2];
-    const int ldl = Lz + 1;
-    cplx<R>* b0 = reinterpret_cast<cplx<R>*>(smem_raw);
-    cplx<R>* b1 = b0 + mt * ldl;
-    const int kx0 = blockIdx.x * mt, ky = blockIdx.y;
-    const size_t plane = (size_t)Ly * Lx;
-    const int gx = g.N[0] + 1, gy = g.N[1] + 1, gz = g.N[2] + 1;
-    const int fy = fold(ky, Ly);
-    {
-        const int bc = blockIdx.z;
-        const int t = (bc & 3) == 3 ? 1 : 0;
-        cplx<R>* col = Bg + (size_t)bc * Nz * plane + (size_t)ky * Lx;
-        for (int e = threadIdx.x; e < mt * Lz; e += blockDim.x) {
-            const int z = e / mt, l = e - z * mt;
-            const int kx = kx0 + l;
-            cplx<R> v{0, 0};
-            if (kx < Lx && z < Nz) v = col[(size_t)z * plane + kx];
-            b0[l * ldl + z] = v;
-        }
-        // Green values of this thread's elements, fetched before the FFT
-        constexpr int kMaxG = 8;
-        cplx<R> gpre[kMaxG];
-#pragma unroll
-        for (int q = 0; q < kMaxG; ++q) {
-            const int e = threadIdx.x + q * blockDim.x;
-            gpre[q] = cplx<R>{0, 0};
-            if (e < mt * Lz) {
-                const int l = e / Lz, kz = e - l * Lz;
-                const int kx = kx0 + l;
-                if (kx < Lx) {
-                    gpre[q] = G[(((size_t)t * gz + fold(kz, Lz)) * gy + fy) * gx + fold(kx, Lx)];
-                    if (conj_g) gpre[q].y = -gpre[q].y;
-                }
-            }
-        }
-        __syncthreads();
-        cplx<R>* res = lds_fft<R>(b0, b1, mt, ldl, pl, tw, false);
-        cplx<R>* oth = res == b0 ? b1 : b0;
-#pragma unroll
-        for (int q = 0; q < kMaxG; ++q) {
-            const int e = threadIdx.x + q * blockDim.x;
-            if (e < mt * Lz) {
-                const int l = e / Lz, kz = e - l * Lz;
-                oth[l * ldl + kz] = res[l * ldl + kz] * gpre[q];
-            }
-        }
-        __syncthreads();
-        cplx<R>* res2 = lds_fft<R>(oth, res, mt, ldl, pl, tw, true);
-        for (int e = threadIdx.x; e < mt * Nz; e += blockDim.x) {
-            const int z = e / mt, l = e - z * mt;
-            const int kx = kx0 + l;
-            if (kx < Lx) col[(size_t)z * plane + kx] = res2[l * ldl + z];
-        }
+__device__ __forceinline__ void plane_load(cplx<R>* buf, const cplx<R>* __restrict__ src, const GridDims& g) {
+    const int Ly = g.L[1], Lz = g.L[2], Ny = g.N[1], Nz = g.N[2], ldp = Ly + 1;
+    for (int e = threadIdx.x; e < Lz * Ly; e += blockDim.x) {
+        const int z = e / Ly, y = e - z * Ly;
+        buf[z * ldp + y] = (z < Nz && y < Ny) ? src[z * Ny + y] : cplx<R>{0, 0};
+    }
+    __syncthreads();
+}
+
+template <typename R>
+__device__ __forceinline__ void plane_store(const cplx<R>* buf, cplx<R>* __restrict__ dst, const GridDims& g) {
+    const int Ly = g.L[1], Ny = g.N[1], Nz = g.N[2], ldp = Ly + 1;
+    for (int e = threadIdx.x; e < Nz * Ny; e += blockDim.x) {
+        const int z = e / Ny, y = e - z * Ny;
+        dst[e] = buf[z * ldp + y];
     }
 }
 
-// Forward z-pass into a ring slot [bc][kz][ky][kx].
+// forward y (rows z < Nz), forward z (all Ly columns)
 template <typename R>
-__global__ void __launch_bounds__(256) k_zcommit(const cplx<R>* __restrict__ Bg, cplx<R>* __restrict__ slot,
-                                                 const cplx<R>* __restrict__ tw, Radix pl, GridDims g, int mt) {
+__device__ __forceinline__ void plane_forward(cplx<R>* buf, const GridDims& g, const Radix& ry, const Radix& rz,
+                                              const cplx<R>* twy, const cplx<R>* twz) {
+    const int ldp = g.L[1] + 1;
+    plane_fft<R>(buf, g.N[2], ldp, 1, ry, twy, false);
+    plane_fft<R>(buf, g.L[1], 1, ldp, rz, twz, false);
+}
+
+// inverse z (all Ly columns), inverse y (rows z < Nz)
+template <typename R>
+__device__ __forceinline__ void plane_inverse(cplx<R>* buf, const GridDims& g, const Radix& ry, const Radix& rz,
+                                              const cplx<R>* twy, const cplx<R>* twz) {
+    const int ldp = g.L[1] + 1;
+    plane_fft<R>(buf, g.L[1], 1, ldp, rz, twz, true);
+    plane_fft<R>(buf, g.N[2], ldp, 1, ry, twy, true);
+}
+
+// LDS of a plane kernel: the plane, then the y and z twiddle tables.
+template <typename R>
+__device__ __forceinline__ void plane_smem(const GridDims& g, const cplx<R>* __restrict__ twy_g,
+                                           const cplx<R>* __restrict__ twz_g, cplx<R>*& buf, cplx<R>*& twy,
+                                           cplx<R>*& twz) {
     extern __shared__ unsigned char smem_raw[];
-    const int Lx = g.L[0], Ly = g.L[1], Lz = g.L[2], Nz = g.N[2];
-    const int ldl = Lz + 1;
-    cplx<R>* b0 = reinterpret_cast<cplx<R>*>(smem_raw);
-    cplx<R>* b1 = b0 + mt * ldl;
-    const int kx0 = blockIdx.x * mt, ky = blockIdx.y;
-    const size_t plane = (size_t)Ly * Lx;
-    {
-        const int bc = blockIdx.z;
-        const cplx<R>* col = Bg + (size_t)bc * Nz * plane + (size_t)ky * Lx;
-        for (int e = threadIdx.x; e < mt * Lz; e += blockDim.x) {
-            const int z = e / mt, l = e - z * mt;
-            const int kx = kx0 + l;
-            cplx<R> v{0, 0};
-            if (kx < Lx && z < Nz) v = col[(size_t)z * plane + kx];
-            b0[l * ldl + z] = v;
-        }
-        __syncthreads();
-        cplx<R>* res = lds_fft<R>(b0, b1, mt, ldl, pl, tw, false);
-        cplx<R>* o = slot + (size_t)bc * Lz * plane + (size_t)ky * Lx;
-        for (int e = threadIdx.x; e < mt * Lz; e += blockDim.x) {
-            const int kz = e / mt, l = e - kz * mt;
-            const int kx = kx0 + l;
-            if (kx < Lx) o[(size_t)kz * plane + kx] = res[l * ldl + kz];
-        }
+    buf = reinterpret_cast<cplx<R>*>(smem_raw);
+    twy = buf + (size_t)g.L[2] * (g.L[1] + 1);
+    twz = twy + g.L[1];
+    for (int i = threadIdx.x; i < g.L[1]; i += blockDim.x) twy[i] = twy_g[i];
+    for (int i = threadIdx.x; i < g.L[2]; i += blockDim.x) twz[i] = twz_g[i];
+}
+
+// Matvec y/z stage, in place on A: one block per plane (kx, bc): 2-D FFT of
+// the zero-padded plane, multiply by the folded Green spectrum
+// G[t][kx'][kz'][ky'] of one m, inverse 2-D FFT, keep y < Ny, z < Nz.
+template <typename R>
+__global__ void __launch_bounds__(kPlaneThreads) k_yz_green(cplx<R>* __restrict__ A, const cplx<R>* __restrict__ G,
+                                                            const cplx<R>* __restrict__ twy_g,
+                                                            const cplx<R>* __restrict__ twz_g, Radix ry, Radix rz,
+                                                            GridDims g, int conj_g) {
+    cplx<R>*buf, *twy, *twz;
+    plane_smem<R>(g, twy_g, twz_g, buf, twy, twz);
+    const int kx = blockIdx.x, bc = blockIdx.y;
+    const int Lx = g.L[0], Ly = g.L[1], Lz = g.L[2], ldp = Ly + 1;
+    const int gx = g.N[0] + 1, gy = g.N[1] + 1, gz = g.N[2] + 1;
+    cplx<R>* pl = A + ((size_t)bc * Lx + kx) * ((size_t)g.N[2] * g.N[1]);
+    plane_load<R>(buf, pl, g);
+    plane_forward<R>(buf, g, ry, rz, twy, twz);
+    const int t = (bc & 3) == 3 ? 1 : 0;
+    const cplx<R>* Gk = G + ((size_t)t * gx + fold(kx, Lx)) * ((size_t)gz * gy);
+    for (int e = threadIdx.x; e < Lz * Ly; e += blockDim.x) {
+        const int kz = e / Ly, ky = e - kz * Ly;
+        cplx<R> gv = Gk[(size_t)fold(kz, Lz) * gy + fold(ky, Ly)];
+        if (conj_g) gv.y = -gv.y;
+        buf[kz * ldp + ky] = buf[kz * ldp + ky] * gv;
+    }
+    __syncthreads();
+    plane_inverse<R>(buf, g, ry, rz, twy, twz);
+    plane_store<R>(buf, pl, g);
+}
+
+// Commit y/z stage: forward 2-D FFT of the plane into a ring slot plane.
+template <typename R>
+__global__ void __launch_bounds__(kPlaneThreads) k_yz_commit(const cplx<R>* __restrict__ A, cplx<R>* __restrict__ slot,
+                                                             const cplx<R>* __restrict__ twy_g,
+                                                             const cplx<R>* __restrict__ twz_g, Radix ry, Radix rz,
+                                                             GridDims g) {
+    cplx<R>*buf, *twy, *twz;
+    plane_smem<R>(g, twy_g, twz_g, buf, twy, twz);
+    const int kx = blockIdx.x, bc = blockIdx.y;
+    const int Lx = g.L[0], Ly = g.L[1], Lz = g.L[2], ldp = Ly + 1;
+    plane_load<R>(buf, A + ((size_t)bc * Lx + kx) * ((size_t)g.N[2] * g.N[1]), g);
+    plane_forward<R>(buf, g, ry, rz, twy, twz);
+    cplx<R>* o = slot + ((size_t)bc * Lx + kx) * ((size_t)Lz * Ly);
+    for (int e = threadIdx.x; e < Lz * Ly; e += blockDim.x) {
+        const int kz = e / Ly, ky = e - kz * Ly;
+        o[e] = buf[kz * ldp + ky];
     }
 }
 
-// k-space temporal sum acc = sum_{m=1}^{nm} G_m . ring[(cur - m) mod ng],
-// then inverse z-pass into B (z < Nz).  G: folded spectra [ng+1][2][...].
+// Delayed-field y/z stage: k-space temporal sum over the history ring
+// acc = sum_{m=1}^{nm} G_m . ring[(cur - m) mod ng], inverse 2-D FFT, plane
+// y < Ny, z < Nz written to A.  G: folded spectra [ng+1][2][gx][gz][gy].
 template <typename R>
-__global__ void __launch_bounds__(256) k_zdelayed(const cplx<R>* __restrict__ ring, const cplx<R>* __restrict__ G,
-                                                  cplx<R>* __restrict__ Bg, const cplx<R>* __restrict__ tw,
-                                                  Radix pl, GridDims g, int mt, int ng, int cur, int nm,
-                                                  int conj_g) {
-    extern __shared__ unsigned char smem_raw[];
-    const int Lx = g.L[0], Ly = g.L[1], Lz = g.L[2], Nz = g.N[2];
-    const int ldl = Lz + 1;
-    cplx<R>* b0 = reinterpret_cast<cplx<R>*>(smem_raw);
-    cplx<R>* b1 = b0 + mt * ldl;
-    const int kx0 = blockIdx.x * mt, ky = blockIdx.y;
-    const size_t plane = (size_t)Ly * Lx;
-    const size_t slot_sz = (size_t)4 * g.B * Lz * plane;
+__global__ void __launch_bounds__(kPlaneThreads) k_yz_delayed(const cplx<R>* __restrict__ ring,
+                                                              const cplx<R>* __restrict__ G, cplx<R>* __restrict__ A,
+                                                              const cplx<R>* __restrict__ twy_g,
+                                                              const cplx<R>* __restrict__ twz_g, Radix ry, Radix rz,
+                                                              GridDims g, int ng, int cur, int nm, int conj_g) {
+    cplx<R>*buf, *twy, *twz;
+    plane_smem<R>(g, twy_g, twz_g, buf, twy, twz);
+    const int kx = blockIdx.x, bc = blockIdx.y;
+    const int Lx = g.L[0], Ly = g.L[1], Lz = g.L[2], ldp = Ly + 1;
     const int gx = g.N[0] + 1, gy = g.N[1] + 1, gz = g.N[2] + 1;
-    const size_t gsz = (size_t)2 * gz * gy * gx;
-    const int fy = fold(ky, Ly);
-    {
-        const int bc = blockIdx.z;
-        const int t = (bc & 3) == 3 ? 1 : 0;
-        for (int e = threadIdx.x; e < mt * Lz; e += blockDim.x) {
-            const int kz = e / mt, l = e - kz * mt;
-            const int kx = kx0 + l;
-            cplx<R> acc{0, 0};
-            if (kx < Lx) {
-                const size_t gi = (((size_t)t * gz + fold(kz, Lz)) * gy + fy) * gx + fold(kx, Lx);
-                const size_t ri = (size_t)bc * Lz * plane + (size_t)kz * plane + (size_t)ky * Lx + kx;
-                for (int m = 1; m <= nm; ++m) {
-                    int s = (cur - m) % ng;
-                    if (s < 0) s += ng;
-                    cplx<R> gv = G[(size_t)m * gsz + gi];
-                    if (conj_g) gv.y = -gv.y;
-                    acc += gv * ring[(size_t)s * slot_sz + ri];
-                }
-            }
-            b0[l * ldl + kz] = acc;
+    const size_t gsz = (size_t)2 * gx * gy * gz;
+    const size_t slot_sz = (size_t)4 * g.B * Lx * Lz * Ly;
+    const int t = (bc & 3) == 3 ? 1 : 0;
+    const size_t goff = ((size_t)t * gx + fold(kx, Lx)) * ((size_t)gz * gy);
+    const size_t roff = ((size_t)bc * Lx + kx) * ((size_t)Lz * Ly);
+    for (int e = threadIdx.x; e < Lz * Ly; e += blockDim.x) {
+        const int kz = e / Ly, ky = e - kz * Ly;
+        const size_t gi = goff + (size_t)fold(kz, Lz) * gy + fold(ky, Ly);
+        cplx<R> acc{0, 0};
+        for (int m = 1; m <= nm; ++m) {
+            int s = (cur - m) % ng;
+            if (s < 0) s += ng;
+            cplx<R> gv = G[(size_t)m * gsz + gi];
+            if (conj_g) gv.y = -gv.y;
+            acc += gv * ring[(size_t)s * slot_sz + roff + e];
         }
-        __syncthreads();
-        cplx<R>* res = lds_fft<R>(b0, b1, mt, ldl, pl, tw, true);
-        cplx<R>* col = Bg + (size_t)bc * Nz * plane + (size_t)ky * Lx;
-        for (int e = threadIdx.x; e < mt * Nz; e += blockDim.x) {
-            const int z = e / mt, l = e - z * mt;
-            const int kx = kx0 + l;
-            if (kx < Lx) col[(size_t)z * plane + kx] = res[l * ldl + z];
-        }
+        buf[kz * ldp + ky] = acc;
     }
+    __syncthreads();
+    plane_inverse<R>(buf, g, ry, rz, twy, twz);
+    plane_store<R>(buf, A + ((size_t)bc * Lx + kx) * ((size_t)g.N[2] * g.N[1]), g);
 }
 
 template <typename R>
@@ -326,14 +326,15 @@ __global__ void k_circulant(const zd* __restrict__ tab, zd* __restrict__ out, Gr
     }
 }
 
-// keep the unique octant (k <= N per axis) of a padded spectrum, scaled
+// keep the unique octant (k <= N per axis) of a padded spectrum [kz][ky][kx],
+// scaled, in the plane-major layout out[kx'][kz'][ky']
 __global__ void k_fold(const zd* __restrict__ full, zd* __restrict__ out, GridDims g, double scale) {
     const int gx = g.N[0] + 1, gy = g.N[1] + 1, gz = g.N[2] + 1;
     const size_t tot = (size_t)gx * gy * gz;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot; e += (size_t)gridDim.x * blockDim.x) {
-        const int x = (int)(e % gx);
-        const int y = (int)((e / gx) % gy);
-        const int z = (int)(e / ((size_t)gx * gy));
+        const int y = (int)(e % gy);
+        const int z = (int)((e / gy) % gz);
+        const int x = (int)(e / ((size_t)gy * gz));
         const zd v = full[((size_t)z * g.L[1] + y) * g.L[0] + x];
         out[e] = zd{v.x * scale, v.y * scale};
     }

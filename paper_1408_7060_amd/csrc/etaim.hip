@@ -60,7 +60,7 @@ struct etaim_ctx {
     Setup st;
     GridDims gd{};
     Radix rx{}, ry{}, rz{};
-    int ns = 0, B = 0, prec = 0, mv = 0, nnz = 0, ldg = 0;
+    int ns = 0, B = 0, prec = 0, mv = 0, nnz = 0, ldg = 0, ncu = 256;
     size_t N3 = 0, Np = 0, gfold = 0;
     int64_t dev_bytes = 0;
     std::vector<void*> allocs;
@@ -71,7 +71,7 @@ struct etaim_ctx {
     double *Sq = nullptr, *rq = nullptr;
     // working-precision arrays (float or double)
     void *lam_r = nullptr, *nw_r = nullptr, *near_r = nullptr, *nearT_r = nullptr, *ghat_r = nullptr, *tw_r[3] = {};
-    void *A = nullptr, *Bg = nullptr, *P = nullptr, *ring = nullptr;
+    void *A = nullptr, *P = nullptr, *ring = nullptr;
     zd* hist = nullptr;
     // Krylov (FP64)
     zd *Vk = nullptr, *w = nullptr, *h1 = nullptr, *h2 = nullptr, *H = nullptr, *sn = nullptr, *g = nullptr,
@@ -171,10 +171,22 @@ int trace_flush(etaim_ctx* c) {
 // pass launchers (templated on the working precision)
 
 template <typename R>
+int lines_per_block(const Radix& pl) {
+    int mt = 64;
+    while (mt > 1 && ((size_t)mt * (pl.L + 1) + pl.L) * sizeof(cplx<R>) > (size_t)kLdsBudget) mt /= 2;
+    while (mt > 1 && !plane_fits(mt, pl)) mt /= 2;
+    return mt;
+}
+
+template <typename R>
 int launch_lines(etaim_ctx* c, const cplx<R>* in, cplx<R>* out, const cplx<R>* tw, const Radix& pl, int nf,
                  int nslow, int in_len, int out_len, long long in_f, long long in_s, long long in_p,
-                 long long out_f, long long out_s, long long out_p, bool inverse) {
+                 long long out_f, long long out_s, long long out_p, bool inverse, int ns0 = 0,
+                 long long in_s1 = 0, long long out_s1 = 0) {
     LineArgs a{};
+    a.ns0 = ns0 > 0 ? ns0 : nslow;
+    a.in_s1 = in_s1;
+    a.out_s1 = out_s1;
     a.pl = pl;
     a.nf = nf;
     a.in_len = in_len;
@@ -186,10 +198,10 @@ int launch_lines(etaim_ctx* c, const cplx<R>* in, cplx<R>* out, const cplx<R>* t
     a.out_s = out_s;
     a.out_p = out_p;
     a.inverse = inverse ? 1 : 0;
-    a.mt = pick_lines(pl.L, sizeof(cplx<R>), 16);
-    const size_t lds = 2 * (size_t)a.mt * (pl.L + 1) * sizeof(cplx<R>);
+    a.mt = lines_per_block<R>(pl);
+    const size_t lds = ((size_t)a.mt * (pl.L + 1) + pl.L) * sizeof(cplx<R>);
     dim3 grid((nf + a.mt - 1) / a.mt, nslow);
-    hipLaunchKernelGGL(k_lines<R>, grid, dim3(256), lds, c->stream, in, out, tw, a);
+    hipLaunchKernelGGL(k_lines<R>, grid, dim3(kPlaneThreads), lds, c->stream, in, out, tw, a);
     HIPCHK(hipGetLastError());
     return ETAIM_OK;
 }
@@ -197,7 +209,6 @@ int launch_lines(etaim_ctx* c, const cplx<R>* in, cplx<R>* out, const cplx<R>* t
 template <typename R>
 struct Ops {
     static cplx<R>* A(etaim_ctx* c) { return (cplx<R>*)c->A; }
-    static cplx<R>* Bg(etaim_ctx* c) { return (cplx<R>*)c->Bg; }
     static cplx<R>* P(etaim_ctx* c) { return (cplx<R>*)c->P; }
     static const cplx<R>* tw(etaim_ctx* c, int a) { return (const cplx<R>*)c->tw_r[a]; }
     static const cplx<R>* ghat(etaim_ctx* c) { return (const cplx<R>*)c->ghat_r; }
@@ -208,51 +219,50 @@ struct Ops {
     }
     static cplx<R>* ring(etaim_ctx* c) { return (cplx<R>*)c->ring; }
 
-    // anterpolate x (optionally scaled by dinv) and forward x, y passes -> Bg
-    static int forward_xy(etaim_ctx* c, const zd* x, const zd* dinv, int conj_in) {
+    // anterpolate x (optionally scaled by dinv) and forward x pass -> A
+    static int gather_rows(etaim_ctx* c) {
+        // 4 * mr lines of length Lx in one LDS buffer (in-place FFT)
+        const int Lx = c->gd.L[0];
+        int mr = sizeof(R) == 4 ? 16 : 8;
+        while (mr > 1 && !plane_fits(4 * mr, c->rx)) mr /= 2;
+        (void)Lx;
+        return mr;
+    }
+    static size_t gather_lds(etaim_ctx* c) {
+        return ((size_t)4 * gather_rows(c) * (c->gd.L[0] + 1) + c->gd.L[0]) * sizeof(cplx<R>);
+    }
+    static int forward_x(etaim_ctx* c, const zd* x, const zd* dinv, int conj_in) {
         const GridDims& g = c->gd;
-        const int mr = std::max(1, pick_lines(g.L[0], sizeof(cplx<R>), 16) / 4);
-        const size_t lds = 2 * (size_t)(4 * mr) * (g.L[0] + 1) * sizeof(cplx<R>);
+        const int mr = gather_rows(c);
         dim3 grid((g.N[1] + mr - 1) / mr, g.N[2], c->B);
-        const double s = sizeof(cplx<R>), nB = (double)c->B * c->ns, bc = 4.0 * c->B;
-        const double a_sz = bc * g.N[2] * g.N[1] * g.L[0] * s, b_sz = bc * g.N[2] * g.L[1] * g.L[0] * s;
-        {
-            Trace t(c, ETAIM_K_ANTERP_X, nB * 16 + 64.0 * c->ns * (4 + 4 * sizeof(R)) + (c->N3 + 1) * 4.0 + a_sz +
-                                             (dinv ? c->ns * 16.0 : 0.0));
-            hipLaunchKernelGGL(k_fwdx_gather<R>, grid, dim3(256), lds, c->stream, x, dinv, c->nptr, c->nk,
-                               (const R*)c->nw_r, A(c), tw(c, 0), c->rx, g, mr, c->ns, conj_in);
-        }
+        const double s = sizeof(cplx<R>), nB = (double)c->B * c->ns;
+        const double a_sz = 4.0 * c->B * g.L[0] * g.N[2] * g.N[1] * s;
+        Trace t(c, ETAIM_K_ANTERP_X, nB * 16 + 64.0 * c->ns * (4 + 4 * sizeof(R)) + (c->N3 + 1) * 4.0 + a_sz +
+                                         (dinv ? c->ns * 16.0 : 0.0));
+        hipLaunchKernelGGL(k_fwdx_gather<R>, grid, dim3(kPlaneThreads), gather_lds(c), c->stream, x, dinv, c->nptr,
+                           c->nk, (const R*)c->nw_r, A(c), tw(c, 0), c->rx, g, mr, c->ns, conj_in);
         HIPCHK(hipGetLastError());
-        const long long Lx = g.L[0], Ly = g.L[1], Ny = g.N[1], Nz = g.N[2];
-        Trace t(c, ETAIM_K_FFT_Y_FWD, a_sz + b_sz);
-        return launch_lines<R>(c, A(c), Bg(c), tw(c, 1), c->ry, (int)Lx, (int)(4 * c->B * Nz), (int)Ny, (int)Ly, 1,
-                               Ny * Lx, Lx, 1, Ly * Lx, Lx, false);
+        return ETAIM_OK;
     }
-    // inverse y, x passes Bg -> P
-    static int inverse_yx(etaim_ctx* c) {
+    // inverse x pass A[bc][kx][z][y] -> P[bc][z][y][x]
+    static int inverse_x(etaim_ctx* c) {
         const GridDims& g = c->gd;
-        const long long Lx = g.L[0], Ly = g.L[1], Nx = g.N[0], Ny = g.N[1], Nz = g.N[2];
+        const long long Lx = g.L[0], Nx = g.N[0], Ny = g.N[1], Nz = g.N[2];
         const double s = sizeof(cplx<R>), bc = 4.0 * c->B;
-        const double a_sz = bc * Nz * Ny * Lx * s, b_sz = bc * Nz * Ly * Lx * s, p_sz = bc * c->N3 * s;
-        {
-            Trace t(c, ETAIM_K_FFT_Y_INV, a_sz + b_sz);
-            CHK(launch_lines<R>(c, Bg(c), A(c), tw(c, 1), c->ry, (int)Lx, (int)(4 * c->B * Nz), (int)Ly, (int)Ny, 1,
-                                Ly * Lx, Lx, 1, Ny * Lx, Lx, true));
-        }
-        Trace t(c, ETAIM_K_FFT_X_INV, a_sz + p_sz);
-        return launch_lines<R>(c, A(c), P(c), tw(c, 0), c->rx, (int)Ny, (int)(4 * c->B * Nz), (int)Lx, (int)Nx, Lx,
-                               Ny * Lx, 1, Nx, Ny * Nx, 1, true);
+        Trace t(c, ETAIM_K_FFT_X_INV, bc * Lx * Nz * Ny * s + bc * c->N3 * s);
+        return launch_lines<R>(c, A(c), P(c), tw(c, 0), c->rx, (int)Ny, (int)(4 * c->B * Nz), (int)Lx, (int)Nx, 1,
+                               Ny, Nz * Ny, Nx, Ny * Nx, 1, true, (int)Nz, Lx * Nz * Ny, Nz * Ny * Nx);
     }
-    static int zgreen(etaim_ctx* c, int m, int conj) {
+    static size_t plane_lds(etaim_ctx* c) {
+        return ((size_t)c->gd.L[2] * (c->gd.L[1] + 1) + c->gd.L[1] + c->gd.L[2]) * sizeof(cplx<R>);
+    }
+    static int yz_green(etaim_ctx* c, int m, int conj) {
         const GridDims& g = c->gd;
-        // k_zgreen prefetches at most 8 Green values per thread (256 threads)
-        const int mt = std::max(1, std::min(pick_lines(g.L[2], sizeof(cplx<R>), 16), 2048 / g.L[2]));
-        const size_t lds = 2 * (size_t)mt * (g.L[2] + 1) * sizeof(cplx<R>);
-        dim3 grid((g.L[0] + mt - 1) / mt, g.L[1], 4 * c->B);
+        dim3 grid(g.L[0], 4 * c->B);
         const double s = sizeof(cplx<R>);
-        Trace t(c, ETAIM_K_ZGREEN, 2.0 * 4 * c->B * g.N[2] * g.L[1] * g.L[0] * s + 2.0 * c->gfold * s);
-        hipLaunchKernelGGL(k_zgreen<R>, grid, dim3(256), lds, c->stream, Bg(c), ghat(c) + (size_t)m * 2 * c->gfold,
-                           tw(c, 2), c->rz, g, mt, conj);
+        Trace t(c, ETAIM_K_YZ_GREEN, 2.0 * 4 * c->B * g.L[0] * g.N[2] * g.N[1] * s + 2.0 * c->gfold * s);
+        hipLaunchKernelGGL(k_yz_green<R>, grid, dim3(kPlaneThreads), plane_lds(c), c->stream, A(c),
+                           ghat(c) + (size_t)m * 2 * c->gfold, tw(c, 1), tw(c, 2), c->ry, c->rz, g, conj);
         HIPCHK(hipGetLastError());
         return ETAIM_OK;
     }
@@ -272,44 +282,39 @@ struct Ops {
     }
     // y = conj?(Z_m) (dinv . x)
     static int apply(etaim_ctx* c, int m, const zd* x, const zd* dinv, zd* y, int conj) {
-        CHK(forward_xy(c, x, dinv, 0));
-        CHK(zgreen(c, m, conj));
-        CHK(inverse_yx(c));
+        CHK(forward_x(c, x, dinv, 0));
+        CHK(yz_green(c, m, conj));
+        CHK(inverse_x(c));
         return interp_near(c, 0, x, dinv, m, 0, 0, nullptr, y, conj, 0);
     }
     // rhs = V - sum_{m>=1} conj?(Z_m) I_{cur-m} from the rings (cur >= 1)
     static int delayed(etaim_ctx* c, int cur, const zd* V, zd* rhs, int conj) {
         const GridDims& g = c->gd;
-        const int mt = pick_lines(g.L[2], sizeof(cplx<R>), 16);
-        const size_t lds = 2 * (size_t)mt * (g.L[2] + 1) * sizeof(cplx<R>);
-        dim3 grid((g.L[0] + mt - 1) / mt, g.L[1], 4 * c->B);
         const int nm = std::min(c->st.ng, cur);
         {
             const double s = sizeof(cplx<R>);
-            Trace t(c, ETAIM_K_ZDELAYED,
-                    nm * (4.0 * c->B * c->Np * s + 2.0 * c->gfold * s) + 4.0 * c->B * g.N[2] * g.L[1] * g.L[0] * s);
-            hipLaunchKernelGGL(k_zdelayed<R>, grid, dim3(256), lds, c->stream, (const cplx<R>*)ring(c), ghat(c),
-                               Bg(c), tw(c, 2), c->rz, g, mt, c->st.ng, cur, nm, conj);
+            Trace t(c, ETAIM_K_YZ_DELAYED,
+                    nm * (4.0 * c->B * c->Np * s + 2.0 * c->gfold * s) + 4.0 * c->B * g.L[0] * g.N[2] * g.N[1] * s);
+            hipLaunchKernelGGL(k_yz_delayed<R>, dim3(g.L[0], 4 * c->B), dim3(kPlaneThreads), plane_lds(c), c->stream,
+                               (const cplx<R>*)ring(c), ghat(c), A(c), tw(c, 1), tw(c, 2), c->ry, c->rz, g,
+                               c->st.ng, cur, nm, conj);
         }
         HIPCHK(hipGetLastError());
-        CHK(inverse_yx(c));
+        CHK(inverse_x(c));
         const int nmh = std::min(c->st.mn, cur);
         return interp_near(c, 1, nullptr, nullptr, 0, cur, nmh, V, rhs, conj, 0);
     }
     // push the converged I_cur into the spectrum ring and the current ring
     static int commit(etaim_ctx* c, int cur, const zd* x) {
-        CHK(forward_xy(c, x, nullptr, 0));
+        CHK(forward_x(c, x, nullptr, 0));
         const GridDims& g = c->gd;
-        const int mt = pick_lines(g.L[2], sizeof(cplx<R>), 16);
-        const size_t lds = 2 * (size_t)mt * (g.L[2] + 1) * sizeof(cplx<R>);
-        dim3 grid((g.L[0] + mt - 1) / mt, g.L[1], 4 * c->B);
         const size_t slot_sz = (size_t)4 * c->B * c->Np;
         cplx<R>* slot = ring(c) + (size_t)(cur % c->st.ng) * slot_sz;
         {
             const double s = sizeof(cplx<R>);
-            Trace t(c, ETAIM_K_ZCOMMIT, 4.0 * c->B * g.N[2] * g.L[1] * g.L[0] * s + 4.0 * c->B * c->Np * s);
-            hipLaunchKernelGGL(k_zcommit<R>, grid, dim3(256), lds, c->stream, (const cplx<R>*)Bg(c), slot, tw(c, 2),
-                               c->rz, g, mt);
+            Trace t(c, ETAIM_K_YZ_COMMIT, 4.0 * c->B * g.L[0] * g.N[2] * g.N[1] * s + 4.0 * c->B * c->Np * s);
+            hipLaunchKernelGGL(k_yz_commit<R>, dim3(g.L[0], 4 * c->B), dim3(kPlaneThreads), plane_lds(c), c->stream,
+                               (const cplx<R>*)A(c), slot, tw(c, 1), tw(c, 2), c->ry, c->rz, g);
         }
         HIPCHK(hipGetLastError());
         if (c->st.mn >= 1) {
@@ -317,6 +322,15 @@ struct Ops {
             HIPCHK(hipMemcpyAsync(c->hist + (size_t)(cur % c->st.mn) * n, x, n * sizeof(zd),
                                   hipMemcpyDeviceToDevice, c->stream));
         }
+        return ETAIM_OK;
+    }
+    // allow the plane kernels and the gather their dynamic LDS
+    static int set_lds(etaim_ctx* c) {
+        const int bytes = (int)plane_lds(c);
+        for (const void* f : {(const void*)k_yz_green<R>, (const void*)k_yz_commit<R>, (const void*)k_yz_delayed<R>})
+            HIPCHK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+        HIPCHK(hipFuncSetAttribute((const void*)k_fwdx_gather<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)gather_lds(c)));
         return ETAIM_OK;
     }
 };
@@ -576,9 +590,14 @@ int make_working(etaim_ctx* c) {
         c->tw_r[a] = d;
     }
     CHK(c->allocv(c->A, 4 * nB * (size_t)c->gd.N[2] * c->gd.N[1] * c->gd.L[0] * sizeof(cplx<R>)));
-    CHK(c->allocv(c->Bg, 4 * nB * (size_t)c->gd.N[2] * c->gd.L[1] * c->gd.L[0] * sizeof(cplx<R>)));
     CHK(c->allocv(c->P, 4 * nB * c->N3 * sizeof(cplx<R>)));
     CHK(c->allocv(c->ring, (size_t)c->st.ng * 4 * nB * c->Np * sizeof(cplx<R>)));
+    // plane kernels: LDS and per-thread register staging limits
+    const size_t lds = Ops<R>::plane_lds(c);
+    if (lds > 160 * 1024 || Ops<R>::gather_lds(c) > 160 * 1024 || !plane_fits(c->gd.N[2], c->ry) ||
+        !plane_fits(c->gd.L[1], c->rz) || !plane_fits(4, c->rx))
+        return fail(ETAIM_EUNSUPPORTED, "the padded (y, z) plane does not fit the LDS plane kernels");
+    CHK(Ops<R>::set_lds(c));
     return ETAIM_OK;
 }
 
@@ -797,6 +816,8 @@ int etaim_create(etaim_ctx** out, const etaim_mesh* mesh, const etaim_rwg* rwg, 
     c->gfold = (size_t)(c->gd.N[0] + 1) * (c->gd.N[1] + 1) * (c->gd.N[2] + 1);
     exact_near_entries(c->geo, params, c->st);
     if (hipGetDevice(&c->device) != hipSuccess) return fail(ETAIM_EHIP, "no HIP device");
+    if (hipDeviceGetAttribute(&c->ncu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || c->ncu < 1)
+        c->ncu = 256;
     c->stream = (hipStream_t)hip_stream;
     rc = device_setup(c.get());
     if (rc) return rc;
@@ -924,7 +945,23 @@ int etaim_export(const etaim_ctx* c, int32_t what, void* host, size_t bytes) {
             return ETAIM_OK;
         }
         case 5: return put(c->diag, (size_t)c->ns * sizeof(zd), true);
-        case 6: return put(c->ghat64, (size_t)(s.ng + 1) * 2 * c->gfold * sizeof(zd), true);
+        case 6: {
+            // stored plane-major [m][t][kx][kz][ky]; exported as [m][t][kz][ky][kx]
+            const size_t n = (size_t)(s.ng + 1) * 2 * c->gfold;
+            if (bytes != n * sizeof(zd)) return fail(ETAIM_EINVAL, "export size mismatch");
+            std::vector<zd> v(n);
+            HIPCHK(hipStreamSynchronize(c->stream));
+            HIPCHK(hipMemcpy(v.data(), c->ghat64, n * sizeof(zd), hipMemcpyDeviceToHost));
+            const int gx = c->gd.N[0] + 1, gy = c->gd.N[1] + 1, gz = c->gd.N[2] + 1;
+            zd* o = (zd*)host;
+            for (size_t mt = 0; mt < (size_t)(s.ng + 1) * 2; ++mt)
+                for (int x = 0; x < gx; ++x)
+                    for (int z = 0; z < gz; ++z)
+                        for (int y = 0; y < gy; ++y)
+                            o[mt * c->gfold + ((size_t)z * gy + y) * gx + x] =
+                                v[mt * c->gfold + ((size_t)x * gz + z) * gy + y];
+            return ETAIM_OK;
+        }
         default: return fail(ETAIM_EINVAL, "unknown export id");
     }
 }

@@ -1,9 +1,9 @@
-// Radix-2/3/4 Stockham FFT of many lines held in LDS, and the line-pass
+// Mixed-radix (2, 3, 4, 6, 8, 12, 16) Stockham FFT of many lines held in LDS, and the line-pass
 // kernel built on it.  Each pass of radix R with p = product of the radices
 // already done maps butterfly i (k = i mod p) to
 //   inputs  x[i + j L/R], twiddled by w^(j k L/(pR)), w = exp(-2 pi i/L)
 //   outputs y[(i - k) R + k + j p]
-// (self-sorting, no bit reversal).  Two LDS buffers ping-pong between passes.
+// (self-sorting, no bit reversal), in place in one LDS buffer.
 #pragma once
 #include "common.hpp"
 
@@ -13,21 +13,25 @@ struct Radix {
     int L, n, r[16];
 };
 
+// Radix plan: fewest passes first (16, 12, 8, 6, 4, 3, 2).
 inline Radix make_radix(int L) {
     Radix p{};
     p.L = L;
     int n = L;
-    while (n % 4 == 0) {
-        p.r[p.n++] = 4;
-        n /= 4;
-    }
-    while (n % 2 == 0) {
-        p.r[p.n++] = 2;
-        n /= 2;
-    }
-    while (n % 3 == 0) {
-        p.r[p.n++] = 3;
-        n /= 3;
+    const int order[7] = {16, 12, 8, 6, 4, 3, 2};
+    while (n > 1) {
+        bool found = false;
+        for (int r : order)
+            if (n % r == 0) {
+                p.r[p.n++] = r;
+                n /= r;
+                found = true;
+                break;
+            }
+        if (!found || p.n >= 16) {
+            p.n = 0;  // unsupported factor: caller checks p.n
+            return p;
+        }
     }
     return p;
 }
@@ -36,6 +40,76 @@ template <typename R>
 __device__ __forceinline__ cplx<R> mul_i(cplx<R> a, bool inverse) {
     // multiply by -i (forward) or +i (inverse)
     return inverse ? cplx<R>{-a.y, a.x} : cplx<R>{a.y, -a.x};
+}
+
+// exp(-2 pi i m / 48) for m = 0..47 written as (cos, sin) of multiples of
+// 7.5 degrees: covers the twiddles of every composite codelet below
+// (N = 6, 8, 12, 16 all divide 48).
+__device__ __forceinline__ void w48(int m, double& c, double& s) {
+    // cos(k * pi / 24), k = 0..12 (quarter wave), exact decimal expansions
+    const double q[13] = {1.0,
+                          0.99144486137381041114,
+                          0.96592582628906828675,
+                          0.92387953251128675613,
+                          0.86602540378443864676,
+                          0.79335334029123516458,
+                          0.70710678118654752440,
+                          0.60876142900872063942,
+                          0.5,
+                          0.38268343236508977173,
+                          0.25881904510252076235,
+                          0.13052619222005159155,
+                          0.0};
+    m %= 48;
+    // angle = 2 pi m / 48 = m * 7.5 deg = m * pi / 24
+    const int quad = m / 12, r = m % 12;
+    double cr = q[r], sr = q[12 - r];
+    // rotate by quad * 90 degrees
+    for (int i = 0; i < quad; ++i) {
+        const double t = cr;
+        cr = -sr;
+        sr = t;
+    }
+    c = cr;
+    s = -sr;  // exp(-i angle)
+}
+
+template <typename R, int RAD>
+__device__ __forceinline__ void dft_small(cplx<R> (&u)[RAD], bool inverse);
+
+// composite codelet of size N1*N2 in registers: X[k2 + N2 k1] =
+// sum_n1 W_N1^{n1 k1} W_N^{n1 k2} sum_n2 W_N2^{n2 k2} x[n1 + N1 n2]
+template <typename R, int N1, int N2>
+__device__ __forceinline__ void dft_composite(cplx<R> (&u)[N1 * N2], bool inverse) {
+    constexpr int N = N1 * N2;
+    cplx<R> y[N1][N2];
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) {
+        cplx<R> v[N2];
+#pragma unroll
+        for (int n2 = 0; n2 < N2; ++n2) v[n2] = u[n1 + N1 * n2];
+        dft_small<R, N2>(v, inverse);
+#pragma unroll
+        for (int k2 = 0; k2 < N2; ++k2) {
+            if (n1 * k2 != 0) {
+                double c, s;
+                w48((48 / N) * n1 * k2, c, s);
+                const cplx<R> w{(R)c, (R)(inverse ? -s : s)};
+                y[n1][k2] = v[k2] * w;
+            } else {
+                y[n1][k2] = v[k2];
+            }
+        }
+    }
+#pragma unroll
+    for (int k2 = 0; k2 < N2; ++k2) {
+        cplx<R> v[N1];
+#pragma unroll
+        for (int n1 = 0; n1 < N1; ++n1) v[n1] = y[n1][k2];
+        dft_small<R, N1>(v, inverse);
+#pragma unroll
+        for (int k1 = 0; k1 < N1; ++k1) u[k2 + N2 * k1] = v[k1];
+    }
 }
 
 template <typename R, int RAD>
@@ -53,91 +127,155 @@ __device__ __forceinline__ void dft_small(cplx<R> (&u)[RAD], bool inverse) {
         u[0] = u[0] + t;
         u[1] = m + id;
         u[2] = m - id;
-    } else {
+    } else if constexpr (RAD == 4) {
         const cplx<R> a = u[0] + u[2], b = u[0] - u[2];
         const cplx<R> c = u[1] + u[3], d = mul_i(u[1] - u[3], inverse);
         u[0] = a + c;
         u[2] = a - c;
         u[1] = b + d;
         u[3] = b - d;
+    } else if constexpr (RAD == 6) {
+        dft_composite<R, 2, 3>(u, inverse);
+    } else if constexpr (RAD == 8) {
+        dft_composite<R, 2, 4>(u, inverse);
+    } else if constexpr (RAD == 12) {
+        dft_composite<R, 4, 3>(u, inverse);
+    } else {
+        static_assert(RAD == 16, "unsupported radix");
+        dft_composite<R, 4, 4>(u, inverse);
     }
 }
 
-template <typename R, int RAD>
-__device__ __forceinline__ void stockham_pass(const cplx<R>* __restrict__ src, cplx<R>* __restrict__ dst,
-                                              int nl, int L, int ldl, int p,
-                                              const cplx<R>* __restrict__ tw, bool inverse) {
-    const int nb = L / RAD;
-    const int tstep = L / (p * RAD);
-    for (int e = threadIdx.x; e < nl * nb; e += blockDim.x) {
-        const int line = e / nb;
-        const int i = e - line * nb;
-        const int k = i % p;
-        const cplx<R>* s = src + line * ldl;
-        cplx<R>* d = dst + line * ldl;
-        cplx<R> u[RAD];
+// ---------------------------------------------------------------------------
+// In-place FFT of nl lines held in one LDS buffer: element (line, point) at
+// buf[line*lstride + point*pstride].  A pass of radix RAD has nl * L/RAD
+// butterflies e = i*nl + line (line fastest), so the lanes of a wavefront
+// touch consecutive lines: with a line stride of 1 (columns) or an odd
+// stride L+1 (rows) the LDS accesses spread over all banks for every
+// butterfly index i and output position.  Thread tid owns e = tid + q*blockDim,
+// q < NPT; (line, i) advance incrementally (no division per butterfly).
+// Inputs are staged in registers, the block synchronises, and outputs are
+// written to the same buffer.  plane_fits() is the host-side condition.
+constexpr int kPlaneThreads = 1024;
+// butterflies per thread per pass, by radix: nl * L <= 12288 fits every radix
+__host__ __device__ constexpr int plane_npt(int r) {
+    return r == 16 ? 1 : r == 12 ? 1 : r == 8 ? 2 : r == 6 ? 2 : r == 4 ? 3 : r == 3 ? 4 : 6;
+}
+
+template <typename R, int RAD, int NPT>
+__device__ __forceinline__ void plane_pass(cplx<R>* buf, int nl, int lstride, int pstride, int L, int p,
+                                           const cplx<R>* tw, bool inverse) {
+    const int nb = L / RAD, tstep = L / (p * RAD);
+    const int dl = blockDim.x % nl, di = blockDim.x / nl;
+    const int line0 = threadIdx.x % nl, i0 = threadIdx.x / nl;
+    const bool pow2 = (p & (p - 1)) == 0;
+    cplx<R> u[NPT][RAD];
+    {
+        int line = line0, i = i0;
 #pragma unroll
-        for (int j = 0; j < RAD; ++j) u[j] = s[i + j * nb];
-        if (k) {
+        for (int q = 0; q < NPT; ++q) {
+            if (i < nb) {
+                const cplx<R>* src = buf + line * lstride + i * pstride;
 #pragma unroll
-            for (int j = 1; j < RAD; ++j) {
-                cplx<R> w = tw[j * k * tstep];
-                if (inverse) w.y = -w.y;
-                u[j] = u[j] * w;
+                for (int j = 0; j < RAD; ++j) u[q][j] = src[j * nb * pstride];
+            }
+            line += dl;
+            i += di;
+            if (line >= nl) {
+                line -= nl;
+                ++i;
             }
         }
-        dft_small<R, RAD>(u, inverse);
-        const int base = (i - k) * RAD + k;
-#pragma unroll
-        for (int j = 0; j < RAD; ++j) d[base + j * p] = u[j];
     }
+    __syncthreads();
+    {
+        int line = line0, i = i0;
+#pragma unroll
+        for (int q = 0; q < NPT; ++q) {
+            if (i < nb) {
+                const int k = pow2 ? (i & (p - 1)) : i % p;
+                if (k) {
+#pragma unroll
+                    for (int j = 1; j < RAD; ++j) {
+                        cplx<R> w = tw[j * k * tstep];
+                        if (inverse) w.y = -w.y;
+                        u[q][j] = u[q][j] * w;
+                    }
+                }
+                dft_small<R, RAD>(u[q], inverse);
+                cplx<R>* dst = buf + line * lstride + ((i - k) * RAD + k) * pstride;
+#pragma unroll
+                for (int j = 0; j < RAD; ++j) dst[j * p * pstride] = u[q][j];
+            }
+            line += dl;
+            i += di;
+            if (line >= nl) {
+                line -= nl;
+                ++i;
+            }
+        }
+    }
+    __syncthreads();
 }
 
-// FFT of nl lines of length pl.L stored at a[line*ldl + point]; returns the
-// buffer holding the result (a or b).  Must be called by the whole block.
 template <typename R>
-__device__ cplx<R>* lds_fft(cplx<R>* a, cplx<R>* b, int nl, int ldl, const Radix& pl,
-                            const cplx<R>* __restrict__ tw, bool inverse) {
+__device__ void plane_fft(cplx<R>* buf, int nl, int lstride, int pstride, const Radix& pl, const cplx<R>* tw,
+                          bool inverse) {
     int p = 1;
     for (int s = 0; s < pl.n; ++s) {
         const int r = pl.r[s];
-        if (r == 4)
-            stockham_pass<R, 4>(a, b, nl, pl.L, ldl, p, tw, inverse);
-        else if (r == 2)
-            stockham_pass<R, 2>(a, b, nl, pl.L, ldl, p, tw, inverse);
-        else
-            stockham_pass<R, 3>(a, b, nl, pl.L, ldl, p, tw, inverse);
-        __syncthreads();
-        cplx<R>* t = a;
-        a = b;
-        b = t;
+        switch (r) {
+            case 16: plane_pass<R, 16, plane_npt(16)>(buf, nl, lstride, pstride, pl.L, p, tw, inverse); break;
+            case 12: plane_pass<R, 12, plane_npt(12)>(buf, nl, lstride, pstride, pl.L, p, tw, inverse); break;
+            case 8: plane_pass<R, 8, plane_npt(8)>(buf, nl, lstride, pstride, pl.L, p, tw, inverse); break;
+            case 6: plane_pass<R, 6, plane_npt(6)>(buf, nl, lstride, pstride, pl.L, p, tw, inverse); break;
+            case 4: plane_pass<R, 4, plane_npt(4)>(buf, nl, lstride, pstride, pl.L, p, tw, inverse); break;
+            case 3: plane_pass<R, 3, plane_npt(3)>(buf, nl, lstride, pstride, pl.L, p, tw, inverse); break;
+            default: plane_pass<R, 2, plane_npt(2)>(buf, nl, lstride, pstride, pl.L, p, tw, inverse); break;
+        }
         p *= r;
     }
-    return a;
+}
+
+// host check: every pass of an FFT of nl lines of length pl.L fits the
+// per-thread register staging of kPlaneThreads threads
+inline bool plane_fits(int nl, const Radix& pl) {
+    if (pl.n == 0) return false;
+    for (int s = 0; s < pl.n; ++s) {
+        const int r = pl.r[s];
+        const long tot = (long)nl * (pl.L / r);
+        if (tot > (long)plane_npt(r) * kPlaneThreads) return false;
+    }
+    return true;
 }
 
 // Generic pass: lines indexed by (f, s), f in [0,nf) grouped MT per block
-// (blockIdx.x), s = blockIdx.y.  Element (line, point) lives at
-// base + f*in_f + s*in_s + point*in_p.  Points >= in_len load as zero; the
-// first out_len outputs are stored.
+// (blockIdx.x), s = blockIdx.y = s1*ns0 + s0.  Element (line, point) lives at
+// base + f*in_f + s0*in_s + s1*in_s1 + point*in_p.  Points >= in_len load as
+// zero; the first out_len outputs are stored.  The MT lines are transformed
+// in place in LDS (plane_fft, kPlaneThreads threads).
 struct LineArgs {
     Radix pl;
     int nf, in_len, out_len, mt;
     long long in_f, in_s, in_p, out_f, out_s, out_p;
     int inverse;
+    // slow index s = s1 * ns0 + s0 -> offset s0 * in_s + s1 * in_s1 (same for out)
+    int ns0;
+    long long in_s1, out_s1;
 };
 
 template <typename R>
-__global__ void __launch_bounds__(256) k_lines(const cplx<R>* in, cplx<R>* out,
-                                               const cplx<R>* __restrict__ tw, LineArgs a) {
+__global__ void __launch_bounds__(kPlaneThreads) k_lines(const cplx<R>* in, cplx<R>* out,
+                                                         const cplx<R>* __restrict__ tw_g, LineArgs a) {
     extern __shared__ unsigned char smem_raw[];
     const int L = a.pl.L, ldl = L + 1, mt = a.mt;
-    cplx<R>* b0 = reinterpret_cast<cplx<R>*>(smem_raw);
-    cplx<R>* b1 = b0 + mt * ldl;
+    cplx<R>* buf = reinterpret_cast<cplx<R>*>(smem_raw);
+    cplx<R>* tw = buf + mt * ldl;
+    for (int i = threadIdx.x; i < L; i += blockDim.x) tw[i] = tw_g[i];
     const int f0 = blockIdx.x * mt;
-    const long long s = blockIdx.y;
-    const cplx<R>* ibase = in + s * a.in_s;
-    cplx<R>* obase = out + s * a.out_s;
+    const long long s0 = blockIdx.y % a.ns0, s1 = blockIdx.y / a.ns0;
+    const cplx<R>* ibase = in + s0 * a.in_s + s1 * a.in_s1;
+    cplx<R>* obase = out + s0 * a.out_s + s1 * a.out_s1;
     const int tot = mt * L;
     if (a.in_p == 1) {
         for (int e = threadIdx.x; e < tot; e += blockDim.x) {
@@ -145,7 +283,7 @@ __global__ void __launch_bounds__(256) k_lines(const cplx<R>* in, cplx<R>* out,
             const int f = f0 + l;
             cplx<R> v{(R)0, (R)0};
             if (f < a.nf && p < a.in_len) v = ibase[f * a.in_f + p];
-            b0[l * ldl + p] = v;
+            buf[l * ldl + p] = v;
         }
     } else {
         for (int e = threadIdx.x; e < tot; e += blockDim.x) {
@@ -153,23 +291,23 @@ __global__ void __launch_bounds__(256) k_lines(const cplx<R>* in, cplx<R>* out,
             const int f = f0 + l;
             cplx<R> v{(R)0, (R)0};
             if (f < a.nf && p < a.in_len) v = ibase[f * a.in_f + p * a.in_p];
-            b0[l * ldl + p] = v;
+            buf[l * ldl + p] = v;
         }
     }
     __syncthreads();
-    cplx<R>* res = lds_fft<R>(b0, b1, mt, ldl, a.pl, tw, a.inverse != 0);
+    plane_fft<R>(buf, mt, ldl, 1, a.pl, tw, a.inverse != 0);
     const int tot_o = mt * a.out_len;
     if (a.out_p == 1) {
         for (int e = threadIdx.x; e < tot_o; e += blockDim.x) {
             const int l = e / a.out_len, p = e - l * a.out_len;
             const int f = f0 + l;
-            if (f < a.nf) obase[f * a.out_f + p] = res[l * ldl + p];
+            if (f < a.nf) obase[f * a.out_f + p] = buf[l * ldl + p];
         }
     } else {
         for (int e = threadIdx.x; e < tot_o; e += blockDim.x) {
             const int p = e / mt, l = e - p * mt;
             const int f = f0 + l;
-            if (f < a.nf) obase[f * a.out_f + p * a.out_p] = res[l * ldl + p];
+            if (f < a.nf) obase[f * a.out_f + p * a.out_p] = buf[l * ldl + p];
         }
     }
 }
