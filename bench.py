@@ -5,6 +5,9 @@ incidence directions with random polarisation, f0 = 600 MHz +-10 %,
 48^3 grid padded to 96^3, N_g = 24, near zone 0.3 lambda, FP32 grid
 arithmetic with FP64 GMRES (tol 1e-5), all 32 directions batched.
 
+Before timing, the library's autotuner picks the FFT radix plans, launch
+shapes and GMRES schedule for this problem (--tune-ms budget, untimed).
+
 A "step" is one time step of the batched march: delayed field (k-space
 temporal sum over the history + inverse FFT + interpolation + near history),
 the GMRES solve (one AIM matvec per iteration) and the commit (anterpolation
@@ -42,13 +45,13 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_problem(wl, precision, batch, nt, tol):
+def make_problem(wl, precision, batch, nt, tol, flags=1, sync_every=1):
     import workloads as W  # noqa: F401
     from paper_1408_7060_amd import Problem
     xyz, tri, rwg = wl.mesh()
     d_near = wl.near_lambda * 299_792_458.0 / wl.f0
     kw = dict(fc=wl.f0, nt=nt, grid=wl.grid, d_near=d_near, precision=precision, batch=batch, tol=tol,
-              restart=50, maxit=2000, flags=1)
+              restart=50, maxit=2000, flags=flags, sync_every=sync_every)
     if wl.ng:
         kw["ng"] = wl.ng
     else:
@@ -119,6 +122,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--workload", default="batch", choices=["batch", "single"])
+    ap.add_argument("--sync-every", type=int, default=4,
+                    help="Arnoldi steps enqueued per host convergence check")
+    ap.add_argument("--graph", action="store_true",
+                    help="also time the march with Arnoldi steps replayed from HIP graphs (profiling off)")
+    ap.add_argument("--tune-ms", type=int, default=4000,
+                    help="autotuner budget before timing (0: keep the library's default shapes)")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="first copy this many MiB device-to-device (counter calibration)")
     args = ap.parse_args()
@@ -128,6 +137,7 @@ def main():
     import torch
     import workloads as W
     from paper_1408_7060_amd import FP32, FP64
+    from paper_1408_7060_amd._lib import F_GRAPH
 
     wl = W.SPHERE_L4_BATCH if args.workload == "batch" else W.SPHERE_L4
     K = args.steps or wl.nt
@@ -143,8 +153,13 @@ def main():
         del src, dst
     log(f"[bench] set-up {wl.name}: B={wl.batch} nt={nt}")
     t = time.perf_counter()
-    P = make_problem(wl, FP32, wl.batch, nt, 1e-5)
+    P = make_problem(wl, FP32, wl.batch, nt, 1e-5, sync_every=args.sync_every)
     log(f"[bench] set-up {time.perf_counter() - t:.1f} s, info {P.info}")
+    tuning = None
+    if args.tune_ms:
+        t = time.perf_counter()
+        tuning = P.autotune(budget_ms=args.tune_ms)
+        log(f"[bench] autotune {time.perf_counter() - t:.1f} s: {tuning}")
     kh, pp = wl.incidence()
     V = P.excitation(kh, pp, wl.sigma, wl.td)
     if args.warmup:
@@ -179,16 +194,34 @@ def main():
            "ms_per_step": round(1e3 * wall / K, 3), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "fp32 (grid/FFT/near) + fp64 (GMRES)", "data": "synthetic",
            "config": {"workload": wl.name, "ns": P.ns, "batch": wl.batch, "grid": wl.grid,
+                      "sync_every": args.sync_every,
                       "padded": 2 * wl.grid, "ng": P.info["ng"], "mn": P.info["mn"], "nt": K, "tol": 1e-5,
                       "parallelism": "1 GPU"},
            "direction_steps_per_s": round(steps_s * wl.batch, 3),
            "gmres_iters_per_step": round(iters, 2),
            "roofline": roof,
+           "tuning": tuning,
            "kernels": {n: {"ms": round(v["ms"], 2), "launches": v["launches"],
                            "GBps": round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1)} for n, v in ks.items()
                        if v["launches"]}}
     I32_0 = I32[:, 0].cpu().numpy()
     P.close()
+    if args.graph or (tuning and tuning["graph"]):
+        Pg = make_problem(wl, FP32, wl.batch, nt, 1e-5, flags=1 | F_GRAPH, sync_every=args.sync_every)
+        if tuning:
+            Pg.set_tuning(dict(tuning, graph=1))
+        if args.warmup:
+            Pg.march(V, nsteps=args.warmup)
+        torch.cuda.synchronize()
+        g0 = time.perf_counter()
+        Ig, stg = Pg.march(V, nsteps=K)
+        torch.cuda.synchronize()
+        wg = time.perf_counter() - g0
+        out["graph"] = {"time_steps_per_s": round(K / wg, 4), "gmres_iters_per_step": round(stg["total_iters"] / K, 2),
+                        "max_abs_diff_vs_eager": float((Ig[:, 0].cpu().numpy() - I32_0).__abs__().max())}
+        log(f"[bench] graph replay: {K / wg:.2f} steps/s")
+        Pg.close()
+        del Ig
     del V, I32
     torch.cuda.empty_cache()
     if not args.no_fp64:

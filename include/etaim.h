@@ -57,7 +57,9 @@ extern "C" {
 /* flags */
 #define ETAIM_F_CONTINUE_ON_NOCONV 1 /* keep marching after a step hits maxit */
 #define ETAIM_F_FAIL_ON_UNSTABLE 2   /* return ETAIM_EUNSTABLE instead of only flagging */
-#define ETAIM_F_GRAPH 4              /* replay captured HIP graphs for GMRES iterations */
+#define ETAIM_F_GRAPH 4              /* capture each Arnoldi step j of the batched GMRES once as a
+                                        HIP graph and replay it (device-side gating, see sync_every);
+                                        while profiling is on the same steps run as direct launches */
 
 typedef struct etaim_ctx etaim_ctx;
 
@@ -98,6 +100,9 @@ typedef struct {
     int32_t restart;    /* GMRES restart length, 1..200 */
     int32_t maxit;      /* max GMRES iterations per step */
     int32_t flags;      /* ETAIM_F_* */
+    int32_t sync_every; /* Arnoldi steps enqueued per host convergence check; 0 or 1 => check after
+                           every step.  Steps enqueued past convergence return at once on the
+                           device (a gate flag), so results do not depend on it. */
 } etaim_params;
 
 typedef struct {
@@ -199,6 +204,45 @@ int etaim_set_profiling(etaim_ctx *ctx, int32_t on);
 /* Accumulated device time [ms], algorithmic bytes and launch count of one
  * kernel class since tracing was turned on (host outputs). */
 int etaim_kernel_stats(const etaim_ctx *ctx, int32_t cls, double *ms, double *bytes, int64_t *launches);
+
+/* Launch shapes and schedule of the batched march.  They change speed
+ * only: every admissible setting computes the same operator (the FFT plans
+ * differ in rounding order only, the schedules not at all). */
+typedef struct {
+    int32_t radix[3][8];     /* FFT radix plan per axis x, y, z: pass radices in order
+                                (each 2, 3, 4, 6, 8, 12 or 16), product = padded length,
+                                0-terminated */
+    int32_t gather_rows;     /* grid rows per anterpolation block (>= 1) */
+    int32_t lines_per_block; /* lines per block of the inverse x pass (>= 1) */
+    int32_t interp_waves;    /* bases (one wavefront each) per interpolation block, 1..4 */
+    int32_t sync_every;      /* Arnoldi steps per host convergence check, 1..restart */
+    int32_t graph;           /* 1: replay captured Arnoldi steps (ETAIM_F_GRAPH) */
+    double apply_ms;         /* out: measured matvec time [ms] (0 if not measured) */
+    double solve_ms;         /* out: measured GMRES solve of the tuning right-hand side [ms] (0 if not
+                                measured) */
+} etaim_tuning;
+
+/* Autotuner of the batching form: times the admissible radix plans, launch
+ * shapes and GMRES schedules on this context (AIM matvecs on a seeded
+ * random vector; GMRES solves of a seeded right-hand side with zero history),
+ * checks each candidate's matvec against the current setting (relative L2
+ * <= 1e-4 in FP32, 1e-10 in FP64; others are skipped), and keeps the fastest.
+ * budget_ms bounds the timing work (>= 1; candidates are tried in order of
+ * expected benefit).  cache_path (host string or NULL): a JSON-lines file; a
+ * record whose key matches this problem's shape (precision, batch, ns,
+ * grid, near-zone size, restart) is applied without timing, otherwise the
+ * result is appended.  out (host, may be NULL) receives the setting.  Must
+ * not run while a march is in flight on the context's stream.  Errors:
+ * EINVAL (budget < 1), EHIP, or the cache file cannot be written (EINVAL). */
+int etaim_autotune(etaim_ctx *ctx, int32_t budget_ms, const char *cache_path, etaim_tuning *out);
+
+/* Current setting (host out). */
+int etaim_get_tuning(const etaim_ctx *ctx, etaim_tuning *out);
+
+/* Apply a setting; EINVAL if a radix plan does not multiply to the padded
+ * length or uses another radix, EUNSUPPORTED if a plan or shape does not fit
+ * the kernels' LDS and register staging. */
+int etaim_set_tuning(etaim_ctx *ctx, const etaim_tuning *t);
 
 /* Copy a set-up array to host memory for inspection.  what: 0 projection
  * weights float64 [ns][4][64], 1 stencil corners int32 [ns][3], 2 near-zone

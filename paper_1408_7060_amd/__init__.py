@@ -40,7 +40,8 @@ class Problem:
 
     def __init__(self, xyz, tri, rwg, *, fc: float, nt: int, grid, d_near: float, dt: float = 0.0,
                  beta: float = 0.0, f_bw: float = 0.0, ng: int = 0, precision: int = FP64, batch: int = 1,
-                 tol: float = 1e-6, restart: int = 50, maxit: int = 1000, flags: int = 0, stream=None):
+                 tol: float = 1e-6, restart: int = 50, maxit: int = 1000, flags: int = 0, sync_every: int = 1,
+                 stream=None):
         torch = _torch()
         lib = _lib.load()
         self._xyz = np.ascontiguousarray(xyz, dtype=np.float64)
@@ -52,7 +53,8 @@ class Problem:
         g = np.broadcast_to(np.asarray(grid, dtype=np.int32), (3,))
         p = _lib.Params(fc=fc, dt=dt, beta=beta, f_bw=f_bw, nt_steps=nt, order=3,
                         grid=(c_int32 * 3)(*[int(v) for v in g]), d_near=d_near, ng=ng, precision=precision,
-                        batch=batch, tol=tol, restart=restart, maxit=maxit, flags=flags)
+                        batch=batch, tol=tol, restart=restart, maxit=maxit, flags=flags,
+                        sync_every=sync_every)
         if stream is None and torch.cuda.is_available():
             stream = torch.cuda.current_stream()
         self.stream = stream
@@ -155,6 +157,34 @@ class Problem:
             _lib.check(lib.etaim_kernel_stats(self._h, i, byref(ms), byref(by), byref(n)))
             out[name] = {"ms": ms.value, "bytes": by.value, "launches": n.value}
         return out
+
+    @staticmethod
+    def _tuning_dict(t) -> dict:
+        d = {ax: [v for v in t.radix[a] if v] for a, ax in enumerate(("radix_x", "radix_y", "radix_z"))}
+        for f in ("gather_rows", "lines_per_block", "interp_waves", "sync_every", "graph", "apply_ms", "solve_ms"):
+            d[f] = getattr(t, f)
+        return d
+
+    def autotune(self, budget_ms: int = 3000, cache: str | None = None) -> dict:
+        """Time the admissible FFT plans, launch shapes and GMRES schedules on
+        this problem and keep the fastest (etaim_autotune)."""
+        t = _lib.Tuning()
+        _lib.check(_lib.load().etaim_autotune(self._h, int(budget_ms), cache.encode() if cache else None, byref(t)))
+        return self._tuning_dict(t)
+
+    def tuning(self) -> dict:
+        t = _lib.Tuning()
+        _lib.check(_lib.load().etaim_get_tuning(self._h, byref(t)))
+        return self._tuning_dict(t)
+
+    def set_tuning(self, d: dict):
+        t = _lib.Tuning()
+        for a, ax in enumerate(("radix_x", "radix_y", "radix_z")):
+            for i, v in enumerate(d[ax]):
+                t.radix[a][i] = int(v)
+        for f in ("gather_rows", "lines_per_block", "interp_waves", "sync_every", "graph"):
+            setattr(t, f, int(d[f]))
+        _lib.check(_lib.load().etaim_set_tuning(self._h, byref(t)))
 
     def close(self):
         if getattr(self, "_h", None):

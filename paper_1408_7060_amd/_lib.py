@@ -26,7 +26,7 @@ class Params(ctypes.Structure):
     _fields_ = [("fc", c_double), ("dt", c_double), ("beta", c_double), ("f_bw", c_double),
                 ("nt_steps", c_int32), ("order", c_int32), ("grid", c_int32 * 3), ("d_near", c_double),
                 ("ng", c_int32), ("precision", c_int32), ("batch", c_int32), ("tol", c_double),
-                ("restart", c_int32), ("maxit", c_int32), ("flags", c_int32)]
+                ("restart", c_int32), ("maxit", c_int32), ("flags", c_int32), ("sync_every", c_int32)]
 
 
 class Derived(ctypes.Structure):
@@ -41,6 +41,12 @@ class Stats(ctypes.Structure):
                 ("first_noconv_step", c_int32), ("unstable_step", c_int32), ("ms_rhs", c_double),
                 ("ms_solve", c_double), ("ms_commit", c_double), ("ms_total", c_double),
                 ("max_rel_residual", c_double), ("iters_per_step", POINTER(c_int32))]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("radix", (c_int32 * 8) * 3), ("gather_rows", c_int32), ("lines_per_block", c_int32),
+                ("interp_waves", c_int32), ("sync_every", c_int32), ("graph", c_int32), ("apply_ms", c_double),
+                ("solve_ms", c_double)]
 
 
 # name -> (restype, argtypes); every entry point the header declares
@@ -58,6 +64,9 @@ SIGNATURES = {
     "etaim_export": (c_int32, [c_void_p, c_int32, c_void_p, c_size_t]),
     "etaim_set_profiling": (c_int32, [c_void_p, c_int32]),
     "etaim_kernel_stats": (c_int32, [c_void_p, c_int32, POINTER(c_double), POINTER(c_double), POINTER(c_int64)]),
+    "etaim_autotune": (c_int32, [c_void_p, c_int32, c_char_p, POINTER(Tuning)]),
+    "etaim_get_tuning": (c_int32, [c_void_p, POINTER(Tuning)]),
+    "etaim_set_tuning": (c_int32, [c_void_p, POINTER(Tuning)]),
     "etaim_last_error": (c_char_p, []),
     "etaim_destroy": (None, [c_void_p]),
 }

@@ -33,7 +33,8 @@ template <typename R>
 __global__ void __launch_bounds__(kPlaneThreads) k_fwdx_gather(
     const zd* __restrict__ x_in, const zd* __restrict__ dinv, const int* __restrict__ nptr,
     const int* __restrict__ nk, const R* __restrict__ nw, cplx<R>* __restrict__ A, const cplx<R>* __restrict__ tw_g,
-    Radix pl, GridDims g, int mr, int ns, int conj_in) {
+    Radix pl, GridDims g, int mr, int ns, int conj_in, const int* __restrict__ gate) {
+    if (gated_off(gate)) return;
     extern __shared__ unsigned char smem_raw[];
     const int Lx = g.L[0], Nx = g.N[0], Ny = g.N[1], Nz = g.N[2];
     const int ldl = Lx + 1, nl = 4 * mr;
@@ -136,7 +137,8 @@ template <typename R>
 __global__ void __launch_bounds__(kPlaneThreads) k_yz_green(cplx<R>* __restrict__ A, const cplx<R>* __restrict__ G,
                                                             const cplx<R>* __restrict__ twy_g,
                                                             const cplx<R>* __restrict__ twz_g, Radix ry, Radix rz,
-                                                            GridDims g, int conj_g) {
+                                                            GridDims g, int conj_g, const int* __restrict__ gate) {
+    if (gated_off(gate)) return;
     cplx<R>*buf, *twy, *twz;
     plane_smem<R>(g, twy_g, twz_g, buf, twy, twz);
     const int kx = blockIdx.x, bc = blockIdx.y;
@@ -228,13 +230,22 @@ __device__ __forceinline__ R wave_sum(R v) {
 //                              val[e][m] hist[(cur-m) mod mn][b][col_e])
 template <typename R>
 __global__ void __launch_bounds__(256) k_interp_near(
-    const cplx<R>* __restrict__ P, const R* __restrict__ lam, const int* __restrict__ i0, GridDims g,
+    const cplx<R>* __restrict__ P, const R* __restrict__ lam, const int* __restrict__ i0,
+    const int* __restrict__ order, GridDims g,
     const int* __restrict__ rowptr, const int* __restrict__ col, const cplx<R>* __restrict__ val, int mv,
     const zd* __restrict__ x, const zd* __restrict__ dinv, int m, const zd* __restrict__ hist, int mn, int cur,
-    int nmh, const zd* __restrict__ V, zd* __restrict__ y, int ns, int mode, int conj_v, int conj_x) {
+    int nmh, const zd* __restrict__ V, zd* __restrict__ y, int ns, int mode, int conj_v, int conj_x,
+    const int* __restrict__ gate) {
+    if (gated_off(gate)) return;
     const int lane = threadIdx.x & 63;
-    const int k = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (k >= ns) return;
+    // consecutive blocks land on different XCDs (round-robin dispatch), so
+    // give each XCD one contiguous run of the Morton-ordered bases: its L2
+    // then holds one surface patch of the grid
+    const int per = gridDim.x / kXcds;
+    const int lb = (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+    const int slot = lb * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (slot >= ns) return;
+    const int k = order[slot];
     const int Nx = g.N[0], Ny = g.N[1], Nz = g.N[2];
     const size_t N = (size_t)Nx * Ny * Nz;
     const int jx = lane & 3, jy = (lane >> 2) & 3, jz = lane >> 4;

@@ -10,6 +10,14 @@ namespace etaim {
 
 constexpr double kC0 = 299792458.0;
 constexpr double kPi = 3.14159265358979323846;
+// MI355X: 8 XCDs, each with its own L2; consecutive workgroups of a launch
+// are dispatched to the XCDs round-robin
+constexpr int kXcds = 8;
+
+// Device-side gate of the batched GMRES iteration: kernels of an Arnoldi
+// step that are launched ahead of the host's convergence check (or replayed
+// from a captured graph) return at once when the step is not live.
+__device__ __forceinline__ bool gated_off(const int* gate) { return gate != nullptr && *gate == 0; }
 constexpr double kMu0 = 4.0e-7 * kPi;
 // eps0 = 1/(mu0 c^2), evaluated at run time to keep one definition
 __host__ __device__ inline double eps0() { return 1.0 / (kMu0 * kC0 * kC0); }

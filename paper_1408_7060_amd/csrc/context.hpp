@@ -37,6 +37,7 @@ struct Setup {
     int ng = 0, mn = 0, N[3] = {0, 0, 0}, L[3] = {0, 0, 0};
     std::vector<double> lam;        // [ns][4][64] projection weights
     std::vector<int> i0;            // [ns][3] stencil corners
+    std::vector<int> order;         // [ns] bases sorted by the Morton code of their stencil corner
     std::vector<int> rowptr, col;   // near-zone CSR (row-major, sorted columns)
     std::vector<zd> near_exact;     // [nnz][mn+1] exact Z_m entries (m fastest)
     // node-major transpose of the projection (anterpolation gather)

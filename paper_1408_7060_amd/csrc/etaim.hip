@@ -1,6 +1,8 @@
 // C ABI of the ET-AIM marching library: context set-up, the AIM operator
 // (Sec. 4 stages (i)-(iv)), the delayed field, GMRES (stage (v), Sec. 5.1),
 // the forward and adjoint marches of eq. (5), excitation and export.
+#include <chrono>
+#include <cstdlib>
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -67,7 +69,7 @@ struct etaim_ctx {
     // FP64 device arrays
     zd *dinv = nullptr, *dinv_c = nullptr, *diag = nullptr, *near64 = nullptr, *nearT64 = nullptr, *ghat64 = nullptr;
     double* lam64 = nullptr;
-    int *i0 = nullptr, *rowptr = nullptr, *col = nullptr, *rowof = nullptr, *nptr = nullptr, *nk = nullptr;
+    int *i0 = nullptr, *korder = nullptr, *rowptr = nullptr, *col = nullptr, *rowof = nullptr, *nptr = nullptr, *nk = nullptr;
     double *Sq = nullptr, *rq = nullptr;
     // working-precision arrays (float or double)
     void *lam_r = nullptr, *nw_r = nullptr, *near_r = nullptr, *nearT_r = nullptr, *ghat_r = nullptr, *tw_r[3] = {};
@@ -79,6 +81,13 @@ struct etaim_ctx {
     double *cs = nullptr, *nrm = nullptr, *beta = nullptr, *bnorm = nullptr, *resid = nullptr;
     int *active = nullptr, *jcnt = nullptr, *flag = nullptr;
     int* flag_h = nullptr;
+    // batched-GMRES schedule: steps per host check, captured Arnoldi steps
+    int sync_every = 1;
+    bool use_graph = false, capturing = false;
+    hipStream_t cap_stream = nullptr;
+    std::vector<hipGraphExec_t> graphs[2];  // [conj][j]
+    // launch shapes (0 = automatic); the autotuner sets them
+    int gather_rows_t = 0, lines_x_t = 0, interp_waves = 4;
     hipEvent_t ev[4] = {};
     // per-kernel-class tracing
     bool prof = false;
@@ -120,6 +129,10 @@ struct etaim_ctx {
             if (e) (void)hipEventDestroy(e);
         for (auto& e : pool) (void)hipEventDestroy(e);
         if (flag_h) (void)hipHostFree(flag_h);
+        for (auto& v : graphs)
+            for (auto& x : v)
+                if (x) (void)hipGraphExecDestroy(x);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
         for (void* p : allocs) (void)hipFree(p);
     }
 };
@@ -132,7 +145,7 @@ struct Trace {
     int cls, idx = -1;
     double bytes;
     Trace(etaim_ctx* c_, int cls_, double bytes_) : c(c_), cls(cls_), bytes(bytes_) {
-        if (!c->prof) return;
+        if (!c->prof || c->capturing) return;
         if ((size_t)(c->pool_next + 2) > c->pool.size()) {
             for (int i = 0; i < 64; ++i) {
                 hipEvent_t e;
@@ -182,8 +195,9 @@ template <typename R>
 int launch_lines(etaim_ctx* c, const cplx<R>* in, cplx<R>* out, const cplx<R>* tw, const Radix& pl, int nf,
                  int nslow, int in_len, int out_len, long long in_f, long long in_s, long long in_p,
                  long long out_f, long long out_s, long long out_p, bool inverse, int ns0 = 0,
-                 long long in_s1 = 0, long long out_s1 = 0) {
+                 long long in_s1 = 0, long long out_s1 = 0, const int* gate = nullptr, int mt = 0) {
     LineArgs a{};
+    a.gate = gate;
     a.ns0 = ns0 > 0 ? ns0 : nslow;
     a.in_s1 = in_s1;
     a.out_s1 = out_s1;
@@ -198,7 +212,7 @@ int launch_lines(etaim_ctx* c, const cplx<R>* in, cplx<R>* out, const cplx<R>* t
     a.out_s = out_s;
     a.out_p = out_p;
     a.inverse = inverse ? 1 : 0;
-    a.mt = lines_per_block<R>(pl);
+    a.mt = mt > 0 ? mt : lines_per_block<R>(pl);
     const size_t lds = ((size_t)a.mt * (pl.L + 1) + pl.L) * sizeof(cplx<R>);
     dim3 grid((nf + a.mt - 1) / a.mt, nslow);
     hipLaunchKernelGGL(k_lines<R>, grid, dim3(kPlaneThreads), lds, c->stream, in, out, tw, a);
@@ -223,6 +237,7 @@ struct Ops {
     static int gather_rows(etaim_ctx* c) {
         // 4 * mr lines of length Lx in one LDS buffer (in-place FFT)
         const int Lx = c->gd.L[0];
+        if (c->gather_rows_t > 0) return c->gather_rows_t;
         int mr = sizeof(R) == 4 ? 16 : 8;
         while (mr > 1 && !plane_fits(4 * mr, c->rx)) mr /= 2;
         (void)Lx;
@@ -231,7 +246,7 @@ struct Ops {
     static size_t gather_lds(etaim_ctx* c) {
         return ((size_t)4 * gather_rows(c) * (c->gd.L[0] + 1) + c->gd.L[0]) * sizeof(cplx<R>);
     }
-    static int forward_x(etaim_ctx* c, const zd* x, const zd* dinv, int conj_in) {
+    static int forward_x(etaim_ctx* c, const zd* x, const zd* dinv, int conj_in, const int* gate = nullptr) {
         const GridDims& g = c->gd;
         const int mr = gather_rows(c);
         dim3 grid((g.N[1] + mr - 1) / mr, g.N[2], c->B);
@@ -240,52 +255,56 @@ struct Ops {
         Trace t(c, ETAIM_K_ANTERP_X, nB * 16 + 64.0 * c->ns * (4 + 4 * sizeof(R)) + (c->N3 + 1) * 4.0 + a_sz +
                                          (dinv ? c->ns * 16.0 : 0.0));
         hipLaunchKernelGGL(k_fwdx_gather<R>, grid, dim3(kPlaneThreads), gather_lds(c), c->stream, x, dinv, c->nptr,
-                           c->nk, (const R*)c->nw_r, A(c), tw(c, 0), c->rx, g, mr, c->ns, conj_in);
+                           c->nk, (const R*)c->nw_r, A(c), tw(c, 0), c->rx, g, mr, c->ns, conj_in, gate);
         HIPCHK(hipGetLastError());
         return ETAIM_OK;
     }
     // inverse x pass A[bc][kx][z][y] -> P[bc][z][y][x]
-    static int inverse_x(etaim_ctx* c) {
+    static int inverse_x(etaim_ctx* c, const int* gate = nullptr) {
         const GridDims& g = c->gd;
         const long long Lx = g.L[0], Nx = g.N[0], Ny = g.N[1], Nz = g.N[2];
         const double s = sizeof(cplx<R>), bc = 4.0 * c->B;
         Trace t(c, ETAIM_K_FFT_X_INV, bc * Lx * Nz * Ny * s + bc * c->N3 * s);
         return launch_lines<R>(c, A(c), P(c), tw(c, 0), c->rx, (int)Ny, (int)(4 * c->B * Nz), (int)Lx, (int)Nx, 1,
-                               Ny, Nz * Ny, Nx, Ny * Nx, 1, true, (int)Nz, Lx * Nz * Ny, Nz * Ny * Nx);
+                               Ny, Nz * Ny, Nx, Ny * Nx, 1, true, (int)Nz, Lx * Nz * Ny, Nz * Ny * Nx, gate,
+                               c->lines_x_t);
     }
     static size_t plane_lds(etaim_ctx* c) {
         return ((size_t)c->gd.L[2] * (c->gd.L[1] + 1) + c->gd.L[1] + c->gd.L[2]) * sizeof(cplx<R>);
     }
-    static int yz_green(etaim_ctx* c, int m, int conj) {
+    static int yz_green(etaim_ctx* c, int m, int conj, const int* gate = nullptr) {
         const GridDims& g = c->gd;
         dim3 grid(g.L[0], 4 * c->B);
         const double s = sizeof(cplx<R>);
         Trace t(c, ETAIM_K_YZ_GREEN, 2.0 * 4 * c->B * g.L[0] * g.N[2] * g.N[1] * s + 2.0 * c->gfold * s);
         hipLaunchKernelGGL(k_yz_green<R>, grid, dim3(kPlaneThreads), plane_lds(c), c->stream, A(c),
-                           ghat(c) + (size_t)m * 2 * c->gfold, tw(c, 1), tw(c, 2), c->ry, c->rz, g, conj);
+                           ghat(c) + (size_t)m * 2 * c->gfold, tw(c, 1), tw(c, 2), c->ry, c->rz, g, conj, gate);
         HIPCHK(hipGetLastError());
         return ETAIM_OK;
     }
     static int interp_near(etaim_ctx* c, int mode, const zd* x, const zd* dinv, int m, int cur, int nmh,
-                           const zd* V, zd* y, int conj_v, int conj_x) {
-        dim3 grid((c->ns + 3) / 4);
+                           const zd* V, zd* y, int conj_v, int conj_x, const int* gate = nullptr) {
+        // whole multiple of the XCD count: the kernel's block -> basis map is a bijection
+        const int wpb = c->interp_waves;
+        dim3 grid(((c->ns + wpb - 1) / wpb + kXcds - 1) / kXcds * kXcds);
         const double s = sizeof(cplx<R>), nB = (double)c->B * c->ns;
         const double nvals = mode == 0 ? (m <= c->st.mn ? 1.0 : 0.0) : (double)nmh;
         Trace t(c, ETAIM_K_INTERP_NEAR,
                 4.0 * c->B * c->N3 * s + c->ns * (256.0 * sizeof(R) + 12.0) + (c->ns + 1) * 4.0 + c->nnz * 4.0 +
                     c->nnz * nvals * s + (mode == 0 ? nB * 16 : (nmh + 1) * nB * 16) + nB * 16);
-        hipLaunchKernelGGL(k_interp_near<R>, grid, dim3(256), 0, c->stream, (const cplx<R>*)P(c),
-                           (const R*)c->lam_r, c->i0, c->gd, c->rowptr, c->col, nearv(c, conj_v), c->mv, x, dinv, m,
-                           c->hist, std::max(c->st.mn, 1), cur, nmh, V, y, c->ns, mode, conj_v, conj_x);
+        hipLaunchKernelGGL(k_interp_near<R>, grid, dim3(64 * wpb), 0, c->stream, (const cplx<R>*)P(c),
+                           (const R*)c->lam_r, c->i0, c->korder, c->gd, c->rowptr, c->col, nearv(c, conj_v), c->mv, x, dinv, m,
+                           c->hist, std::max(c->st.mn, 1), cur, nmh, V, y, c->ns, mode, conj_v, conj_x, gate);
         HIPCHK(hipGetLastError());
         return ETAIM_OK;
     }
     // y = conj?(Z_m) (dinv . x)
-    static int apply(etaim_ctx* c, int m, const zd* x, const zd* dinv, zd* y, int conj) {
-        CHK(forward_x(c, x, dinv, 0));
-        CHK(yz_green(c, m, conj));
-        CHK(inverse_x(c));
-        return interp_near(c, 0, x, dinv, m, 0, 0, nullptr, y, conj, 0);
+    static int apply(etaim_ctx* c, int m, const zd* x, const zd* dinv, zd* y, int conj,
+                     const int* gate = nullptr) {
+        CHK(forward_x(c, x, dinv, 0, gate));
+        CHK(yz_green(c, m, conj, gate));
+        CHK(inverse_x(c, gate));
+        return interp_near(c, 0, x, dinv, m, 0, 0, nullptr, y, conj, 0, gate);
     }
     // rhs = V - sum_{m>=1} conj?(Z_m) I_{cur-m} from the rings (cur >= 1)
     static int delayed(etaim_ctx* c, int cur, const zd* V, zd* rhs, int conj) {
@@ -329,35 +348,108 @@ struct Ops {
         const int bytes = (int)plane_lds(c);
         for (const void* f : {(const void*)k_yz_green<R>, (const void*)k_yz_commit<R>, (const void*)k_yz_delayed<R>})
             HIPCHK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+        // the gather's LDS grows with its tuned row count
         HIPCHK(hipFuncSetAttribute((const void*)k_fwdx_gather<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)gather_lds(c)));
+                                   160 * 1024));
         return ETAIM_OK;
     }
 };
 
 // ---------------------------------------------------------------------------
-// GMRES for one time step: x (in: initial guess, out: solution).
+// Outcome of one time step's solve.
 struct StepResult {
     int iters = 0, cols_iters = 0;
     bool noconv = false, nonfinite = false;
     double resid = 0;
 };
 
+// One Arnoldi step j for every active column: matvec, two classical
+// Gram-Schmidt passes, norm, scale, Givens update (flag[0] = columns still
+// active afterwards).  With a gate every kernel first checks the step's
+// live flag (k_gate), so steps can be enqueued ahead of the host's
+// convergence check or replayed from a captured graph.
+template <typename R>
+int arnoldi_step(etaim_ctx* c, int j, int conj, const int* gate) {
+    const int B = c->B, ns = c->ns, rs = c->prm.restart;
+    const size_t nB = (size_t)B * ns;
+    const zd* dinv = conj ? c->dinv_c : c->dinv;
+    zd* vj = c->Vk + (size_t)j * nB;
+    zd* vn = c->Vk + (size_t)(j + 1) * nB;
+    if (gate) hipLaunchKernelGGL(k_gate, dim3(1), dim3(64), 0, c->stream, c->flag);
+    CHK(Ops<R>::apply(c, 0, vj, dinv, c->w, conj, gate));
+    dim3 gd(j + 1, B), go((ns + 255) / 256, B);
+    Trace tk(c, ETAIM_K_KRYLOV, (4.0 * (j + 1) + 8.0) * (double)nB * 16.0);
+    hipLaunchKernelGGL(k_dots, gd, dim3(256), 0, c->stream, c->Vk, c->w, c->h1, ns, B, gate);
+    hipLaunchKernelGGL(k_orth, go, dim3(256), 0, c->stream, c->Vk, c->w, c->h1, j + 1, ns, B, gate);
+    hipLaunchKernelGGL(k_dots, gd, dim3(256), 0, c->stream, c->Vk, c->w, c->h2, ns, B, gate);
+    hipLaunchKernelGGL(k_orth, go, dim3(256), 0, c->stream, c->Vk, c->w, c->h2, j + 1, ns, B, gate);
+    hipLaunchKernelGGL(k_norm, dim3(B), dim3(256), 0, c->stream, c->w, c->nrm, ns, gate);
+    hipLaunchKernelGGL(k_scale, dim3(blocks_for(nB)), dim3(256), 0, c->stream, c->w, c->nrm, vn, ns, B, gate);
+    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, c->stream, c->flag, 1, 0, gate);
+    hipLaunchKernelGGL(k_arnoldi_update, dim3(1), dim3(256), 0, c->stream, c->h1, c->h2, c->nrm, c->H, c->cs, c->sn,
+                       c->g, c->active, c->jcnt, c->resid, c->bnorm, c->flag, j, B, rs, c->prm.tol, gate);
+    HIPCHK(hipGetLastError());
+    return ETAIM_OK;
+}
+
+// Arnoldi step j as a replayed HIP graph, captured on first use (per
+// direction of the operator).  Capture runs on a private stream; replays
+// go to the context's stream.
+template <typename R>
+int arnoldi_step_graph(etaim_ctx* c, int j, int conj) {
+    auto& v = c->graphs[conj];
+    if (v.size() < (size_t)c->prm.restart) v.resize(c->prm.restart, nullptr);
+    if (!v[j]) {
+        if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        hipStream_t user = c->stream;
+        c->stream = c->cap_stream;
+        c->capturing = true;
+        const hipError_t e0 = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+        const int rc = e0 == hipSuccess ? arnoldi_step<R>(c, j, conj, c->flag + 2) : (int)ETAIM_EHIP;
+        hipGraph_t g = nullptr;
+        const hipError_t e1 = e0 == hipSuccess ? hipStreamEndCapture(c->stream, &g) : e0;
+        c->stream = user;
+        c->capturing = false;
+        if (rc != ETAIM_OK || e1 != hipSuccess || !g) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc != ETAIM_OK ? rc : fail(ETAIM_EHIP, std::string("graph capture failed: ") +
+                                                              hipGetErrorString(e1));
+        }
+        hipGraphExec_t x = nullptr;
+        const hipError_t e2 = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e2 != hipSuccess) return fail(ETAIM_EHIP, std::string("graph instantiation failed: ") + hipGetErrorString(e2));
+        v[j] = x;
+    }
+    HIPCHK(hipGraphLaunch(v[j], c->stream));
+    return ETAIM_OK;
+}
+
+// GMRES for one time step: x (in: initial guess, out: solution).
+// Every column b of the batch has its own Krylov space; columns leave the
+// iteration as they converge (device-side masks).
 template <typename R>
 int gmres(etaim_ctx* c, const zd* rhs, zd* x, int conj, StepResult& res) {
     const int B = c->B, ns = c->ns, rs = c->prm.restart;
     const size_t nB = (size_t)B * ns;
     const double tol = c->prm.tol;
     const zd* dinv = conj ? c->dinv_c : c->dinv;
-    hipLaunchKernelGGL(k_norm, dim3(B), dim3(256), 0, c->stream, rhs, c->bnorm, ns);
+    // gated schedule: several steps per host check, or graph replays (direct
+    // gated launches while profiling, so that every kernel is traced)
+    const bool graph = c->use_graph && !c->prof;
+    const bool gated = graph || c->sync_every > 1;
+    const int chunk = gated ? std::max(c->sync_every, 1) : 1;
+    hipLaunchKernelGGL(k_norm, dim3(B), dim3(256), 0, c->stream, rhs, c->bnorm, ns, nullptr);
     int total = 0;
     double prev_worst = 0;
     for (int cycle = 0;; ++cycle) {
         // r = rhs - A x
         CHK(Ops<R>::apply(c, 0, x, nullptr, c->w, conj));
         hipLaunchKernelGGL(k_residual, dim3(blocks_for(nB)), dim3(256), 0, c->stream, rhs, c->w, nB);
-        hipLaunchKernelGGL(k_norm, dim3(B), dim3(256), 0, c->stream, c->w, c->beta, ns);
-        hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, c->stream, c->flag, 2, 0);
+        hipLaunchKernelGGL(k_norm, dim3(B), dim3(256), 0, c->stream, c->w, c->beta, ns, nullptr);
+        hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, c->stream, c->flag, 4, 0, nullptr);
+        hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, c->stream, c->flag + 4, 1,
+                           std::max(c->prm.maxit - total, 0), nullptr);
         hipLaunchKernelGGL(k_cycle_start, dim3(1), dim3(256), 0, c->stream, c->beta, c->bnorm, c->active, c->jcnt,
                            c->g, c->resid, c->flag, B, c->ldg, tol);
         HIPCHK(hipMemcpyAsync(c->flag_h, c->flag, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
@@ -384,31 +476,32 @@ int gmres(etaim_ctx* c, const zd* rhs, zd* x, int conj, StepResult& res) {
             }
             prev_worst = worst;
         }
-        hipLaunchKernelGGL(k_scale, dim3(blocks_for(nB)), dim3(256), 0, c->stream, c->w, c->beta, c->Vk, ns, B);
-        for (int j = 0; j < rs; ++j) {
-            zd* vj = c->Vk + (size_t)j * nB;
-            zd* vn = c->Vk + (size_t)(j + 1) * nB;
-            CHK(Ops<R>::apply(c, 0, vj, dinv, c->w, conj));
-            dim3 gd(j + 1, B), go((ns + 255) / 256, B);
-            {
-            Trace tk(c, ETAIM_K_KRYLOV, (4.0 * (j + 1) + 8.0) * (double)nB * 16.0);
-            hipLaunchKernelGGL(k_dots, gd, dim3(256), 0, c->stream, c->Vk, c->w, c->h1, ns, B);
-            hipLaunchKernelGGL(k_orth, go, dim3(256), 0, c->stream, c->Vk, c->w, c->h1, j + 1, ns, B);
-            hipLaunchKernelGGL(k_dots, gd, dim3(256), 0, c->stream, c->Vk, c->w, c->h2, ns, B);
-            hipLaunchKernelGGL(k_orth, go, dim3(256), 0, c->stream, c->Vk, c->w, c->h2, j + 1, ns, B);
-            hipLaunchKernelGGL(k_norm, dim3(B), dim3(256), 0, c->stream, c->w, c->nrm, ns);
-            hipLaunchKernelGGL(k_scale, dim3(blocks_for(nB)), dim3(256), 0, c->stream, c->w, c->nrm, vn, ns, B);
-            hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, c->stream, c->flag, 2, 0);
-            hipLaunchKernelGGL(k_arnoldi_update, dim3(1), dim3(256), 0, c->stream, c->h1, c->h2, c->nrm, c->H, c->cs,
-                               c->sn, c->g, c->active, c->jcnt, c->resid, c->bnorm, c->flag, j, B, rs, tol);
+        hipLaunchKernelGGL(k_scale, dim3(blocks_for(nB)), dim3(256), 0, c->stream, c->w, c->beta, c->Vk, ns, B,
+                           nullptr);
+        const int base = total;
+        for (int j0 = 0; j0 < rs; j0 += chunk) {
+            const int j1 = std::min(j0 + chunk, rs);
+            std::vector<size_t> mark(j1 - j0);
+            for (int j = j0; j < j1; ++j) {
+                mark[j - j0] = c->pending.size();
+                if (graph)
+                    CHK(arnoldi_step_graph<R>(c, j, conj));
+                else
+                    CHK(arnoldi_step<R>(c, j, conj, gated ? c->flag + 2 : nullptr));
             }
-            HIPCHK(hipMemcpyAsync(c->flag_h, c->flag, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(hipMemcpyAsync(c->flag_h, c->flag, 5 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
             HIPCHK(hipStreamSynchronize(c->stream));
             HIPCHK(hipGetLastError());
-            ++total;
+            if (gated) {
+                // steps enqueued past convergence did no work (the gate is
+                // monotone, so they are the chunk's last): drop their traces
+                const int live = base + c->flag_h[3] - total;
+                if (live >= 0 && live < j1 - j0) c->pending.resize(mark[live]);
+            }
+            total = gated ? base + c->flag_h[3] : total + 1;
             res.iters = total;
             if (c->flag_h[1]) res.nonfinite = true;
-            if (c->flag_h[0] == 0 || total >= c->prm.maxit) break;
+            if (c->flag_h[0] == 0 || c->flag_h[1] || total >= c->prm.maxit) break;
         }
         hipLaunchKernelGGL(k_backsolve, dim3((B + 63) / 64), dim3(64), 0, c->stream, c->H, c->g, c->jcnt, c->yv, B,
                            rs);
@@ -439,7 +532,7 @@ int march_impl(etaim_ctx* c, const zd* V, zd* I, etaim_stats* st, bool adjoint, 
     {
         double* d = nullptr;
         CHK(c->alloc(d, (size_t)nt * B));
-        hipLaunchKernelGGL(k_norm, dim3(nt * B), dim3(256), 0, c->stream, V, d, ns);
+        hipLaunchKernelGGL(k_norm, dim3(nt * B), dim3(256), 0, c->stream, V, d, ns, nullptr);
         HIPCHK(hipMemcpyAsync(nV.data(), d, nV.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
         c->allocs.pop_back();
@@ -474,7 +567,7 @@ int march_impl(etaim_ctx* c, const zd* V, zd* I, etaim_stats* st, bool adjoint, 
         HIPCHK(hipEventRecord(c->ev[2], c->stream));
         HIPCHK(hipMemcpyAsync(Il, c->xk, nB * sizeof(zd), hipMemcpyDeviceToDevice, c->stream));
         CHK(Ops<R>::commit(c, r, c->xk));
-        hipLaunchKernelGGL(k_norm, dim3(B), dim3(256), 0, c->stream, c->xk, c->nrm, ns);
+        hipLaunchKernelGGL(k_norm, dim3(B), dim3(256), 0, c->stream, c->xk, c->nrm, ns, nullptr);
         HIPCHK(hipMemcpyAsync(nrm_h.data(), c->nrm, B * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipEventRecord(c->ev[3], c->stream));
         HIPCHK(hipEventSynchronize(c->ev[3]));
@@ -607,6 +700,7 @@ int device_setup(etaim_ctx* c) {
     // FP64 arrays
     CHK(c->upload(c->lam64, s.lam));
     CHK(c->upload(c->i0, s.i0));
+    CHK(c->upload(c->korder, s.order));
     CHK(c->upload(c->rowptr, s.rowptr));
     CHK(c->upload(c->col, s.col));
     std::vector<int> rowof(c->nnz);
@@ -763,12 +857,14 @@ int device_setup(etaim_ctx* c) {
     CHK(c->alloc(c->resid, c->B));
     CHK(c->alloc(c->active, c->B));
     CHK(c->alloc(c->jcnt, c->B));
-    CHK(c->alloc(c->flag, 2));
-    HIPCHK(hipHostMalloc((void**)&c->flag_h, 2 * sizeof(int), hipHostMallocDefault));
+    CHK(c->alloc(c->flag, 8));
+    HIPCHK(hipHostMalloc((void**)&c->flag_h, 8 * sizeof(int), hipHostMallocDefault));
     for (auto& e : c->ev) HIPCHK(hipEventCreate(&e));
     HIPCHK(hipStreamSynchronize(c->stream));
     return ETAIM_OK;
 }
+
+#include "tune.inc.hip"
 
 int check_ctx(const etaim_ctx* c) {
     if (!c) return fail(ETAIM_EINVAL, "null context");
@@ -800,6 +896,8 @@ int etaim_create(etaim_ctx** out, const etaim_mesh* mesh, const etaim_rwg* rwg, 
     if (rc) return fail(rc, err);
     c->ns = c->geo.ns;
     c->B = params->batch;
+    c->sync_every = std::max(params->sync_every, 1);
+    c->use_graph = (params->flags & ETAIM_F_GRAPH) != 0;
     c->prec = params->precision;
     c->mv = c->st.mn + 1;
     c->nnz = (int)c->st.col.size();
@@ -982,6 +1080,61 @@ int etaim_kernel_stats(const etaim_ctx* c, int32_t cls, double* ms, double* byte
     *ms = c->k_ms[cls];
     *bytes = c->k_bytes[cls];
     *launches = c->k_n[cls];
+    return ETAIM_OK;
+}
+
+int etaim_autotune(etaim_ctx* c, int32_t budget_ms, const char* cache_path, etaim_tuning* out) {
+    g_err.clear();
+    CHK(check_ctx(c));
+    if (budget_ms < 1) return fail(ETAIM_EINVAL, "budget_ms must be >= 1");
+    const std::string key = tune_key(c);
+    etaim_tuning t{};
+    if (cache_path && cache_lookup(cache_path, key, t)) {
+        Shape s;
+        CHK(shape_from_c(c, &t, s));
+        const bool ok = c->prec == ETAIM_FP32 ? shape_fits<float>(c, s) : shape_fits<double>(c, s);
+        if (ok) {
+            put_shape(c, s);
+            if (out) *out = t;
+            return ETAIM_OK;
+        }
+        // a record that no longer fits the kernels: tune again
+    }
+    const Shape saved = get_shape(c);
+    const bool prof = c->prof;
+    const int rc = c->prec == ETAIM_FP32 ? autotune_impl<float>(c, budget_ms, &t)
+                                         : autotune_impl<double>(c, budget_ms, &t);
+    c->prof = prof;
+    if (rc != ETAIM_OK) {
+        put_shape(c, saved);
+        return rc;
+    }
+    if (cache_path) CHK(cache_append(cache_path, key, t));
+    if (out) *out = t;
+    return ETAIM_OK;
+}
+
+int etaim_get_tuning(const etaim_ctx* c, etaim_tuning* out) {
+    g_err.clear();
+    CHK(check_ctx(c));
+    if (!out) return fail(ETAIM_EINVAL, "null output");
+    *out = etaim_tuning{};
+    if (c->prec == ETAIM_FP32)
+        shape_to_c<float>(c, get_shape(c), out);
+    else
+        shape_to_c<double>(c, get_shape(c), out);
+    return ETAIM_OK;
+}
+
+int etaim_set_tuning(etaim_ctx* c, const etaim_tuning* t) {
+    g_err.clear();
+    CHK(check_ctx(c));
+    if (!t) return fail(ETAIM_EINVAL, "null tuning");
+    Shape s;
+    CHK(shape_from_c(c, t, s));
+    const bool ok = c->prec == ETAIM_FP32 ? shape_fits<float>(c, s) : shape_fits<double>(c, s);
+    if (!ok) return fail(ETAIM_EUNSUPPORTED, "the setting does not fit the kernels' LDS or register staging");
+    put_shape(c, s);
     return ETAIM_OK;
 }
 

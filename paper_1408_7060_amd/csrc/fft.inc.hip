@@ -262,11 +262,13 @@ struct LineArgs {
     // slow index s = s1 * ns0 + s0 -> offset s0 * in_s + s1 * in_s1 (same for out)
     int ns0;
     long long in_s1, out_s1;
+    const int* gate;  // optional GMRES gate
 };
 
 template <typename R>
 __global__ void __launch_bounds__(kPlaneThreads) k_lines(const cplx<R>* in, cplx<R>* out,
                                                          const cplx<R>* __restrict__ tw_g, LineArgs a) {
+    if (gated_off(a.gate)) return;
     extern __shared__ unsigned char smem_raw[];
     const int L = a.pl.L, ldl = L + 1, mt = a.mt;
     cplx<R>* buf = reinterpret_cast<cplx<R>*>(smem_raw);

@@ -21,7 +21,8 @@ __device__ __forceinline__ double block_sum256(double v, double* sh) {
 
 // h[i][b] = <V_i[b], w[b]> = sum_k conj(V_i[b][k]) w[b][k], i < nv.  grid (nv, B)
 __global__ void __launch_bounds__(256) k_dots(const zd* __restrict__ V, const zd* __restrict__ w, zd* __restrict__ h,
-                                              int ns, int B) {
+                                              int ns, int B, const int* __restrict__ gate) {
+    if (gated_off(gate)) return;
     __shared__ double sh[256];
     const int i = blockIdx.x, b = blockIdx.y;
     const zd* v = V + ((size_t)i * B + b) * ns;
@@ -39,7 +40,8 @@ __global__ void __launch_bounds__(256) k_dots(const zd* __restrict__ V, const zd
 
 // w[b] -= sum_{i<nv} h[i][b] V_i[b]  (one classical Gram-Schmidt pass)
 __global__ void __launch_bounds__(256) k_orth(const zd* __restrict__ V, zd* __restrict__ w, const zd* __restrict__ h,
-                                              int nv, int ns, int B) {
+                                              int nv, int ns, int B, const int* __restrict__ gate) {
+    if (gated_off(gate)) return;
     const int b = blockIdx.y;
     const int k = blockIdx.x * 256 + threadIdx.x;
     if (k >= ns) return;
@@ -49,7 +51,9 @@ __global__ void __launch_bounds__(256) k_orth(const zd* __restrict__ V, zd* __re
 }
 
 // nrm[b] = ||w[b]||
-__global__ void __launch_bounds__(256) k_norm(const zd* __restrict__ w, double* __restrict__ nrm, int ns) {
+__global__ void __launch_bounds__(256) k_norm(const zd* __restrict__ w, double* __restrict__ nrm, int ns,
+                                              const int* __restrict__ gate = nullptr) {
+    if (gated_off(gate)) return;
     __shared__ double sh[256];
     const int b = blockIdx.x;
     const zd* x = w + (size_t)b * ns;
@@ -61,7 +65,8 @@ __global__ void __launch_bounds__(256) k_norm(const zd* __restrict__ w, double* 
 
 // out[b] = w[b] / nrm[b] (0 if nrm == 0)
 __global__ void k_scale(const zd* __restrict__ w, const double* __restrict__ nrm, zd* __restrict__ out, int ns,
-                        int B) {
+                        int B, const int* __restrict__ gate = nullptr) {
+    if (gated_off(gate)) return;
     const size_t tot = (size_t)ns * B;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot; e += (size_t)gridDim.x * blockDim.x) {
         const int b = (int)(e / ns);
@@ -102,14 +107,17 @@ __global__ void __launch_bounds__(256) k_cycle_start(const double* __restrict__ 
 // Arnoldi column j for each active column b: Hessenberg entries
 // h1 + h2 (the two classical Gram-Schmidt passes) and h_{j+1,j} = nrm[b],
 // previous Givens rotations, a new rotation, residual estimate |g_{j+1}|.
-// One block, one thread per column (strided); flag must be zero on entry.
+// One block, one thread per column (strided); flag[0] must be zero on entry,
+// flag[1] (non-finite) is sticky until the next cycle start.
 __global__ void __launch_bounds__(256) k_arnoldi_update(const zd* __restrict__ h1, const zd* __restrict__ h2,
                                                         const double* __restrict__ nrm, zd* __restrict__ H,
                                                         double* __restrict__ cs, zd* __restrict__ sn,
                                                         zd* __restrict__ g, int* __restrict__ active,
                                                         int* __restrict__ jcnt, double* __restrict__ resid,
                                                         const double* __restrict__ bnorm, int* __restrict__ flag,
-                                                        int j, int B, int restart, double tol) {
+                                                        int j, int B, int restart, double tol,
+                                                        const int* __restrict__ gate) {
+    if (gated_off(gate)) return;
     const int ldh = restart + 1;
     for (int b = threadIdx.x; b < B; b += blockDim.x) {
         if (!active[b]) continue;
@@ -157,6 +165,19 @@ __global__ void __launch_bounds__(256) k_arnoldi_update(const zd* __restrict__ h
     }
 }
 
+// Gate of one Arnoldi step, flag = {active columns, non-finite, live,
+// steps taken this cycle, step budget}: the step is live while a column is
+// active, nothing went non-finite and the budget lasts.  One thread.
+__global__ void k_gate(int* __restrict__ flag) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int live = (flag[0] > 0 && flag[1] == 0 && flag[4] > 0) ? 1 : 0;
+    flag[2] = live;
+    if (live) {
+        flag[3] += 1;
+        flag[4] -= 1;
+    }
+}
+
 // Back-substitution R y = g per column (size jcnt[b]); y[b][i].
 __global__ void k_backsolve(const zd* __restrict__ H, const zd* __restrict__ g, const int* __restrict__ jcnt,
                             zd* __restrict__ y, int B, int restart) {
@@ -197,7 +218,8 @@ __global__ void k_copy_conj(const zd* __restrict__ in, zd* __restrict__ out, siz
     }
 }
 
-__global__ void k_fill_int(int* __restrict__ p, int n, int v) {
+__global__ void k_fill_int(int* __restrict__ p, int n, int v, const int* __restrict__ gate = nullptr) {
+    if (gated_off(gate)) return;
     for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = v;
 }
 

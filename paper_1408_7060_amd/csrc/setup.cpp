@@ -16,6 +16,7 @@
 //    degree-5 rule on triangle pairs; on pairs sharing a vertex the f(0)/R
 //    part is integrated in closed form over the source triangle (static
 //    potentials of a flat triangle, Wilton et al. 1984 / Graglia 1993).
+#include <cstdint>
 #include <omp.h>
 
 #include <algorithm>
@@ -223,8 +224,9 @@ static bool radix23(int n) {
 
 int derive_parameters(const Geometry& g, const etaim_params* p, Setup& s, std::string& err) {
     if (!(p->fc > 0) || p->nt_steps < 1 || p->batch < 1 || !(p->d_near >= 0) || !(p->tol > 0) ||
-        p->restart < 1 || p->restart > 200 || p->maxit < 1 || p->ng < 0 || p->dt < 0) {
-        err = "invalid parameter (fc, nt_steps, batch, d_near, tol, restart, maxit, ng, dt)";
+        p->restart < 1 || p->restart > 200 || p->maxit < 1 || p->ng < 0 || p->dt < 0 || p->sync_every < 0 ||
+        p->sync_every > p->restart) {
+        err = "invalid parameter (fc, nt_steps, batch, d_near, tol, restart, maxit, ng, dt, sync_every)";
         return ETAIM_EINVAL;
     }
     if (p->order != kQ) {
@@ -312,6 +314,20 @@ int derive_parameters(const Geometry& g, const etaim_params* p, Setup& s, std::s
             }
             s.i0[3 * k + a] = i0;
         }
+    // interpolation schedule: bases whose stencils overlap run close together
+    // in time, so that their shared grid lines are L2 hits
+    auto spread = [](uint64_t v) {
+        uint64_t r = 0;
+        for (int b = 0; b < 21; ++b) r |= ((v >> b) & 1u) << (3 * b);
+        return r;
+    };
+    std::vector<uint64_t> key(g.ns);
+    for (int k = 0; k < g.ns; ++k)
+        key[k] = spread((uint64_t)s.i0[3 * k]) | spread((uint64_t)s.i0[3 * k + 1]) << 1 |
+                 spread((uint64_t)s.i0[3 * k + 2]) << 2;
+    s.order.resize(g.ns);
+    for (int k = 0; k < g.ns; ++k) s.order[k] = k;
+    std::stable_sort(s.order.begin(), s.order.end(), [&](int a, int b) { return key[a] < key[b]; });
     s.d_near = p->d_near;
     return ETAIM_OK;
 }

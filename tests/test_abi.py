@@ -61,6 +61,10 @@ def test_rejects_null_arguments():
     assert lib.etaim_create(ctypes.byref(h), None, None, None, None) == _lib().EINVAL
     assert lib.etaim_describe(None, None) == _lib().EINVAL
     assert lib.etaim_march(None, None, None, 0, None) == _lib().EINVAL
+    t = _lib().Tuning()
+    assert lib.etaim_autotune(None, 100, None, ctypes.byref(t)) == _lib().EINVAL
+    assert lib.etaim_get_tuning(None, ctypes.byref(t)) == _lib().EINVAL
+    assert lib.etaim_set_tuning(None, ctypes.byref(t)) == _lib().EINVAL
     lib.etaim_destroy(None)
 
 
@@ -74,6 +78,8 @@ def test_rejects_null_arguments():
     (dict(tol=0.0), -1),
     (dict(restart=0), -1),
     (dict(beta=0.0), -1),                # dt and ng both derived needs beta
+    (dict(sync_every=-1), -1),
+    (dict(sync_every=61), -1),           # more Arnoldi steps per check than the restart length
 ])
 def test_rejects_bad_parameters(kw, code):
     rc, msg = _create(*_sphere(), **kw)
