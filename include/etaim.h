@@ -217,6 +217,12 @@ typedef struct {
     int32_t interp_waves;    /* bases (one wavefront each) per interpolation block, 1..4 */
     int32_t sync_every;      /* Arnoldi steps per host convergence check, 1..restart */
     int32_t graph;           /* 1: replay captured Arnoldi steps (ETAIM_F_GRAPH) */
+    int32_t yz_engine;       /* y/z plane stage: 0 LDS-staged radix passes over the whole padded
+                                plane, 1 register-resident parity quadrants (needs N_y = N_z in
+                                {16, 24, 48}) */
+    int32_t x_engine;        /* x stage: 0 LDS-staged lines with the anterpolation fused in,
+                                1 register-resident lines after a separate anterpolation
+                                (needs N_x in {16, 24, 48}) */
     double apply_ms;         /* out: measured matvec time [ms] (0 if not measured) */
     double solve_ms;         /* out: measured GMRES solve of the tuning right-hand side [ms] (0 if not
                                 measured) */
@@ -241,7 +247,7 @@ int etaim_get_tuning(const etaim_ctx *ctx, etaim_tuning *out);
 
 /* Apply a setting; EINVAL if a radix plan does not multiply to the padded
  * length or uses another radix, EUNSUPPORTED if a plan or shape does not fit
- * the kernels' LDS and register staging. */
+ * the kernels' LDS and register staging (or an engine 1 on another grid). */
 int etaim_set_tuning(etaim_ctx *ctx, const etaim_tuning *t);
 
 /* Copy a set-up array to host memory for inspection.  what: 0 projection

@@ -1,6 +1,11 @@
 // ET-AIM grid kernels (Sec. 4 stages (i)-(iv)):
 //  k_fwdx_gather  anterpolation (node-major gather of the projection) fused
-//                 with the forward x-FFT of the zero-padded grid
+//                 with the forward x-FFT of the zero-padded grid (LDS lines)
+//  k_prescale, k_anterp, k_xfwd, k_xinv
+//                 the same x stage with register-resident lines: the
+//                 anterpolated grid goes through the P buffer
+//  k_yzq_*        register-resident parity-quadrant variants of the plane
+//                 kernels below
 //  k_yz_green     per x-frequency plane: 2-D (y,z) FFT, Green-spectrum
 //                 multiply, inverse 2-D FFT, all in LDS
 //  k_yz_commit    per plane: forward 2-D FFT into a history-ring slot
@@ -9,7 +14,8 @@
 //  k_interp_near  interpolation (projection transposed) + near-zone SpMV
 // Grid layouts (per excitation b and component c = x,y,z,charge; bc = 4b+c):
 //  A: [bc][kx<Lx][z<Nz][y<Ny] (x-transformed, plane-major)
-//  ring slot: [bc][kx<Lx][kz<Lz][ky<Ly]   P: [bc][z][y][x] (N per bc)
+//  ring slot: [bc][kx<Lx][kz<Lz][ky<Ly] (LDS plane kernels) or quadrant-major
+//  [bc][kx][q][kz'][ky'] (register plane kernels)   P: [bc][z][x][y] (N per bc)
 #pragma once
 #include "fft.inc.hip"
 
@@ -75,6 +81,141 @@ __global__ void __launch_bounds__(kPlaneThreads) k_fwdx_gather(
 }
 
 __device__ __forceinline__ int fold(int k, int n2) { return k <= n2 / 2 ? k : n2 - k; }
+
+// w_{2N}^n (compile-time n after unrolling)
+template <typename R, int N>
+__device__ __forceinline__ cplx<R> w2n(int n, bool inverse) {
+    double c, s;
+    w96((96 / (2 * N)) * n, c, s);
+    return cplx<R>{(R)c, (R)(inverse ? -s : s)};
+}
+
+// ---------------------------------------------------------------------------
+// Register x stage (N_x = N with a register codelet, padded length 2N).  The
+// anterpolated grid and the potentials share one buffer laid out
+// [bc][z][x][y] (y fastest): lines along x of consecutive (z, y) are
+// consecutive addresses, so lanes that own consecutive lines coalesce.
+
+// xs[k][b] = conj?(x[b][k]) dinv[k] in the working precision, [ns][B]: the
+// anterpolation then reads the columns of one basis as one run.
+template <typename R>
+__global__ void k_prescale(const zd* __restrict__ x, const zd* __restrict__ dinv, cplx<R>* __restrict__ xs, int ns,
+                           int B, int conj_in, const int* __restrict__ gate) {
+    if (gated_off(gate)) return;
+    const size_t tot = (size_t)ns * B;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot; e += (size_t)gridDim.x * blockDim.x) {
+        const int k = (int)(e / B), b = (int)(e - (size_t)k * B);
+        zd v = x[(size_t)b * ns + k];
+        if (conj_in) v.y = -v.y;
+        if (dinv) v = v * dinv[k];
+        xs[e] = to_r<R>(v);
+    }
+}
+
+// Anterpolation (Sec. 4 stage (i)): q_c[n] = sum_k Lambda^c_{k,n} xs[k] for
+// kAntCols columns per thread, one thread per grid node (z, x, y) from the
+// node-major projection (nptr, nk, nw[4]); no atomics.  Output q[bc][z][x][y].
+constexpr int kAntCols = 8;
+template <typename R>
+__global__ void __launch_bounds__(256) k_anterp(const cplx<R>* __restrict__ xs, const int* __restrict__ nptr,
+                                                const int* __restrict__ nk, const R* __restrict__ nw,
+                                                cplx<R>* __restrict__ q, GridDims g, int B,
+                                                const int* __restrict__ gate) {
+    if (gated_off(gate)) return;
+    const int Nx = g.N[0], Ny = g.N[1], Nz = g.N[2];
+    const size_t N3 = (size_t)Nx * Ny * Nz;
+    const size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (t >= N3) return;
+    const int b0 = blockIdx.y * kAntCols, nb = min(kAntCols, B - b0);
+    const int y = (int)(t % Ny);
+    const size_t r = t / Ny;
+    const int x = (int)(r % Nx), z = (int)(r / Nx);
+    const size_t n = (size_t)x + (size_t)Nx * ((size_t)y + (size_t)Ny * z);
+    cplx<R> acc[kAntCols][4];
+#pragma unroll
+    for (int b = 0; b < kAntCols; ++b)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[b][c] = cplx<R>{0, 0};
+    const int e1 = nptr[n + 1];
+#pragma unroll 2
+    for (int e = nptr[n]; e < e1; ++e) {
+        const int k = nk[e];
+        R w[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) w[c] = nw[4 * (size_t)e + c];
+        const cplx<R>* xk = xs + (size_t)k * B + b0;
+#pragma unroll
+        for (int b = 0; b < kAntCols; ++b)
+            if (b < nb) {
+                const cplx<R> v = xk[b];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[b][c] += w[c] * v;
+            }
+    }
+#pragma unroll
+    for (int b = 0; b < kAntCols; ++b)
+        if (b < nb)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) q[((size_t)(b0 + b) * 4 + c) * N3 + t] = acc[b][c];
+}
+
+// Forward x transform of the zero-padded lines: A[bc][kx][z][y] =
+// sum_{x<N} q[bc][z][x][y] w_{2N}^{kx x}.  Lanes (2l, 2l+1) own line l =
+// (z, y) of one bc with parity p: kx = 2a + p is the N-point DFT of
+// q w_{2N}^{p x}.
+template <typename R, int N>
+__global__ void __launch_bounds__(256) k_xfwd(const cplx<R>* __restrict__ q, cplx<R>* __restrict__ A, GridDims g,
+                                              const int* __restrict__ gate) {
+    if (gated_off(gate)) return;
+    const int Ny = g.N[1], Nz = g.N[2], nl = Ny * Nz, bc = blockIdx.y;
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x, line = tid >> 1, p = tid & 1;
+    if (line >= nl) return;
+    const int z = line / Ny, y = line - z * Ny;
+    const cplx<R>* src = q + (size_t)bc * N * nl + (size_t)z * N * Ny + y;
+    cplx<R> u[N];
+#pragma unroll
+    for (int x = 0; x < N; ++x) u[x] = src[(size_t)x * Ny];
+    if (p) {
+#pragma unroll
+        for (int x = 1; x < N; ++x) u[x] = u[x] * w2n<R, N>(x, false);
+    }
+    dft_small<R, N>(u, false);
+    cplx<R>* dst = A + (size_t)bc * 2 * N * nl + (size_t)p * nl + line;
+#pragma unroll
+    for (int a = 0; a < N; ++a) dst[(size_t)2 * a * nl] = u[a];
+}
+
+// Inverse x transform kept to x < N: P[bc][z][x][y] = sum_{kx<2N}
+// A[bc][kx][z][y] w_{2N}^{-kx x}.  Lane (2l + p) takes the N-point inverse
+// DFT of A[2a + p] times w_{2N}^{-p x}; the lane pair adds its two halves,
+// each lane keeping and storing half of the x range.
+template <typename R, int N>
+__global__ void __launch_bounds__(256) k_xinv(const cplx<R>* __restrict__ A, cplx<R>* __restrict__ P, GridDims g,
+                                              const int* __restrict__ gate) {
+    if (gated_off(gate)) return;
+    const int Ny = g.N[1], Nz = g.N[2], nl = Ny * Nz, bc = blockIdx.y;
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x, line = tid >> 1, p = tid & 1;
+    if (line >= nl) return;  // both lanes of a pair leave together
+    const cplx<R>* src = A + (size_t)bc * 2 * N * nl + (size_t)p * nl + line;
+    cplx<R> u[N];
+#pragma unroll
+    for (int a = 0; a < N; ++a) u[a] = src[(size_t)2 * a * nl];
+    dft_small<R, N>(u, true);
+    if (p) {
+#pragma unroll
+        for (int x = 1; x < N; ++x) u[x] = u[x] * w2n<R, N>(x, true);
+    }
+    const int z = line / Ny, y = line - z * Ny;
+    cplx<R>* dst = P + (size_t)bc * N * nl + (size_t)z * N * Ny + y;
+    constexpr int H = N / 2;
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+        // lane p keeps x = p H + j and sends the partner its x = (1 - p) H + j
+        const cplx<R> keep = p ? u[H + j] : u[j], send = p ? u[j] : u[H + j];
+        const cplx<R> got{__shfl_xor(send.x, 1, 64), __shfl_xor(send.y, 1, 64)};
+        dst[(size_t)(p * H + j) * Ny] = keep + got;
+    }
+}
 
 // Shared shapes of the plane kernels: one block per (kx, bc) holds the
 // (y, z) plane of one x-frequency as buf[z * ldp + y], z in [0, Lz),
@@ -216,6 +357,268 @@ __global__ void __launch_bounds__(kPlaneThreads) k_yz_delayed(const cplx<R>* __r
     plane_store<R>(buf, A + ((size_t)bc * Lx + kx) * ((size_t)g.N[2] * g.N[1]), g);
 }
 
+// ---------------------------------------------------------------------------
+// Register plane kernels (N_y = N_z = N non-zero rows and columns, padded
+// length 2N, N | 48).  The zero-padded 2N x 2N transform of a plane X[z][y]
+// splits by the parities of the wavenumbers: Y[2b + pz][2a + py] is the
+// N x N DFT of X[z][y] w_{2N}^{pz z + py y}, and the kept outputs z, y < N
+// of the inverse transform are the sum over the four parity quadrants of
+// w_{2N}^{-(pz z + py y)} times their N x N inverse DFTs.  Wave q = 2 pz + py
+// of a block owns quadrant q: lane l < N holds one row (then one column) of
+// N points in registers, so each 1-D transform is an N-point FFT with
+// compile-time twiddles and no LDS traffic; only the row <-> column exchange
+// goes through the wave's LDS tile of N x (N+1) points.  The four quadrants
+// are summed through LDS at the end.  Ring slots of this path are stored
+// quadrant-major: [bc][kx][q][kz'][ky'] with kz = 2 kz' + pz, ky = 2 ky' + py.
+constexpr int kQuadThreads = 256;
+
+// two complex values as one vector load
+template <typename R>
+struct Pair;
+template <>
+struct Pair<float> {
+    using type = float4;
+};
+template <>
+struct Pair<double> {
+    using type = double4;
+};
+
+
+template <typename R, int N>
+__device__ __forceinline__ void tile_row(cplx<R>* t, int z, cplx<R> (&u)[N], bool store) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        if (store)
+            t[z * (N + 1) + j] = u[j];
+        else
+            u[j] = t[z * (N + 1) + j];
+    }
+}
+
+template <typename R, int N>
+__device__ __forceinline__ void tile_col(cplx<R>* t, int y, cplx<R> (&u)[N], bool store) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        if (store)
+            t[j * (N + 1) + y] = u[j];
+        else
+            u[j] = t[j * (N + 1) + y];
+    }
+}
+
+// stage the N x N plane src into this wave's tile (coalesced reads)
+template <typename R, int N>
+__device__ __forceinline__ void tile_stage(cplx<R>* t, const cplx<R>* __restrict__ src, int lane) {
+    for (int e = lane; e < N * N; e += 64) {
+        const int z = e / N, y = e - z * N;
+        t[z * (N + 1) + y] = src[e];
+    }
+}
+
+// forward row transforms of the quadrant: pre-twiddle w_{2N}^{py y}, N-point FFT
+template <typename R, int N>
+__device__ __forceinline__ void quad_rows_forward(cplx<R>* t, int lane, int py) {
+    if (lane < N) {
+        cplx<R> u[N];
+        tile_row<R, N>(t, lane, u, false);
+        if (py) {
+#pragma unroll
+            for (int j = 1; j < N; ++j) u[j] = u[j] * w2n<R, N>(j, false);
+        }
+        dft_small<R, N>(u, false);
+        tile_row<R, N>(t, lane, u, true);
+    }
+}
+
+// inverse row transforms, post-twiddle w_{2N}^{-py y}
+template <typename R, int N>
+__device__ __forceinline__ void quad_rows_inverse(cplx<R>* t, int lane, int py) {
+    if (lane < N) {
+        cplx<R> u[N];
+        tile_row<R, N>(t, lane, u, false);
+        dft_small<R, N>(u, true);
+        if (py) {
+#pragma unroll
+            for (int j = 1; j < N; ++j) u[j] = u[j] * w2n<R, N>(j, true);
+        }
+        tile_row<R, N>(t, lane, u, true);
+    }
+}
+
+// out[e] = sum of the four quadrant tiles at (z, y), e = z N + y
+template <typename R, int N>
+__device__ __forceinline__ void quad_sum_store(const cplx<R>* t0, cplx<R>* __restrict__ out) {
+    constexpr int TS = N * (N + 1);
+    for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
+        const int z = e / N, y = e - z * N, o = z * (N + 1) + y;
+        out[e] = (t0[o] + t0[TS + o]) + (t0[2 * TS + o] + t0[3 * TS + o]);
+    }
+}
+
+// Matvec y/z stage on the register path, in place on A (as k_yz_green).
+template <typename R, int N>
+__global__ void __launch_bounds__(kQuadThreads) k_yzq_green(cplx<R>* __restrict__ A, const cplx<R>* __restrict__ G,
+                                                            GridDims g, int conj_g, const int* __restrict__ gate) {
+    if (gated_off(gate)) return;
+    extern __shared__ unsigned char smem_raw[];
+    cplx<R>* t0 = reinterpret_cast<cplx<R>*>(smem_raw);
+    const int q = threadIdx.x >> 6, lane = threadIdx.x & 63, py = q & 1, pz = q >> 1;
+    cplx<R>* t = t0 + q * N * (N + 1);
+    const int kx = blockIdx.x, bc = blockIdx.y, Lx = g.L[0];
+    cplx<R>* pl = A + ((size_t)bc * Lx + kx) * (size_t)(N * N);
+    tile_stage<R, N>(t, pl, lane);
+    __syncthreads();
+    quad_rows_forward<R, N>(t, lane, py);
+    __syncthreads();
+    if (lane < N) {
+        cplx<R> u[N];
+        tile_col<R, N>(t, lane, u, false);
+        if (pz) {
+#pragma unroll
+            for (int j = 1; j < N; ++j) u[j] = u[j] * w2n<R, N>(j, false);
+        }
+        dft_small<R, N>(u, false);
+        const int gx = g.N[0] + 1, gg = N + 1;
+        const cplx<R>* Gk = G + ((size_t)((bc & 3) == 3 ? 1 : 0) * gx + fold(kx, Lx)) * (size_t)(gg * gg);
+        const int fy = fold(2 * lane + py, 2 * N);
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            cplx<R> gv = Gk[fold(2 * j + pz, 2 * N) * gg + fy];
+            if (conj_g) gv.y = -gv.y;
+            u[j] = u[j] * gv;
+        }
+        dft_small<R, N>(u, true);
+        if (pz) {
+#pragma unroll
+            for (int j = 1; j < N; ++j) u[j] = u[j] * w2n<R, N>(j, true);
+        }
+        tile_col<R, N>(t, lane, u, true);
+    }
+    __syncthreads();
+    quad_rows_inverse<R, N>(t, lane, py);
+    __syncthreads();
+    quad_sum_store<R, N>(t0, pl);
+}
+
+// Commit y/z stage on the register path: forward transforms of the plane
+// into a quadrant-major ring slot plane.
+template <typename R, int N>
+__global__ void __launch_bounds__(kQuadThreads) k_yzq_commit(const cplx<R>* __restrict__ A, cplx<R>* __restrict__ slot,
+                                                             GridDims g) {
+    extern __shared__ unsigned char smem_raw[];
+    cplx<R>* t0 = reinterpret_cast<cplx<R>*>(smem_raw);
+    const int q = threadIdx.x >> 6, lane = threadIdx.x & 63, py = q & 1, pz = q >> 1;
+    cplx<R>* t = t0 + q * N * (N + 1);
+    const int kx = blockIdx.x, bc = blockIdx.y, Lx = g.L[0];
+    tile_stage<R, N>(t, A + ((size_t)bc * Lx + kx) * (size_t)(N * N), lane);
+    __syncthreads();
+    quad_rows_forward<R, N>(t, lane, py);
+    __syncthreads();
+    if (lane < N) {
+        cplx<R> u[N];
+        tile_col<R, N>(t, lane, u, false);
+        if (pz) {
+#pragma unroll
+            for (int j = 1; j < N; ++j) u[j] = u[j] * w2n<R, N>(j, false);
+        }
+        dft_small<R, N>(u, false);
+        cplx<R>* o = slot + (((size_t)bc * Lx + kx) * 4 + q) * (size_t)(N * N) + lane;
+#pragma unroll
+        for (int j = 0; j < N; ++j) o[j * N] = u[j];
+    }
+}
+
+// Delayed-field y/z stage on the register path.  The k-space temporal sum
+// over the quadrant-major ring streams the history: the block's 256 threads
+// own consecutive pairs of spectrum points of the plane (16-byte loads of
+// the ring, coalesced), accumulate over m in registers and leave the sums
+// in the quadrant tiles; then the inverse column and row transforms and the
+// quadrant sum as in k_yzq_green.
+template <typename R, int N>
+__global__ void __launch_bounds__(kQuadThreads) k_yzq_delayed(const cplx<R>* __restrict__ ring,
+                                                              const cplx<R>* __restrict__ G, cplx<R>* __restrict__ A,
+                                                              GridDims g, int ng, int cur, int nm, int conj_g) {
+    extern __shared__ unsigned char smem_raw[];
+    cplx<R>* t0 = reinterpret_cast<cplx<R>*>(smem_raw);
+    // the plane's 4 N^2 points as pairs; the sum runs in chunks of PER pairs
+    // per thread so that the accumulators stay within half the VGPR file
+    constexpr int NN = N * N, PAIRS = 4 * NN / 2, PER = 9, CHUNK = PER * kQuadThreads;
+    const int q = threadIdx.x >> 6, lane = threadIdx.x & 63, py = q & 1, pz = q >> 1;
+    cplx<R>* t = t0 + q * N * (N + 1);
+    const int kx = blockIdx.x, bc = blockIdx.y, Lx = g.L[0];
+    const int gx = g.N[0] + 1, gg = N + 1;
+    const size_t gsz = (size_t)2 * gx * gg * gg;
+    const size_t slot_sz = (size_t)4 * g.B * Lx * 4 * NN;
+    const size_t roff = ((size_t)bc * Lx + kx) * (size_t)(4 * NN);
+    const size_t goff = ((size_t)((bc & 3) == 3 ? 1 : 0) * gx + fold(kx, Lx)) * (size_t)(gg * gg);
+    for (int c0 = 0; c0 < PAIRS; c0 += CHUNK) {
+        // point pair i: points 2 i, 2 i + 1 of the plane's quadrant-major
+        // spectrum (N is even, so a pair never straddles a quadrant row)
+        int gi[PER][2];
+        cplx<R> acc[PER][2];
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            const int i = c0 + threadIdx.x + r * kQuadThreads;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int e = 2 * i + h, qq = e / NN, rr = e - qq * NN;
+                const int kz = 2 * (rr / N) + (qq >> 1), ky = 2 * (rr % N) + (qq & 1);
+                gi[r][h] = fold(kz, 2 * N) * gg + fold(ky, 2 * N);
+                acc[r][h] = cplx<R>{0, 0};
+            }
+        }
+        for (int m = 1; m <= nm; ++m) {
+            int s = (cur - m) % ng;
+            if (s < 0) s += ng;
+            const cplx<R>* rs = ring + (size_t)s * slot_sz + roff;
+            const cplx<R>* Gm = G + (size_t)m * gsz + goff;
+#pragma unroll
+            for (int r = 0; r < PER; ++r) {
+                const int i = c0 + threadIdx.x + r * kQuadThreads;
+                if (i < PAIRS) {
+                    cplx<R> v[2];
+                    // one 16-byte (FP32) or 32-byte (FP64) load per pair
+                    *reinterpret_cast<typename Pair<R>::type*>(v) =
+                        *reinterpret_cast<const typename Pair<R>::type*>(rs + 2 * i);
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        cplx<R> gv = Gm[gi[r][h]];
+                        if (conj_g) gv.y = -gv.y;
+                        acc[r][h] += gv * v[h];
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            const int i = c0 + threadIdx.x + r * kQuadThreads;
+            if (i < PAIRS) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int e = 2 * i + h, qq = e / NN, rr = e - qq * NN;
+                    t0[qq * N * (N + 1) + (rr / N) * (N + 1) + rr % N] = acc[r][h];
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (lane < N) {
+        cplx<R> u[N];
+        tile_col<R, N>(t, lane, u, false);
+        dft_small<R, N>(u, true);
+        if (pz) {
+#pragma unroll
+            for (int j = 1; j < N; ++j) u[j] = u[j] * w2n<R, N>(j, true);
+        }
+        tile_col<R, N>(t, lane, u, true);
+    }
+    __syncthreads();
+    quad_rows_inverse<R, N>(t, lane, py);
+    __syncthreads();
+    quad_sum_store<R, N>(t0, A + ((size_t)bc * Lx + kx) * (size_t)(N * N));
+}
+
 template <typename R>
 __device__ __forceinline__ R wave_sum(R v) {
 #pragma unroll
@@ -248,11 +651,12 @@ __global__ void __launch_bounds__(256) k_interp_near(
     const int k = order[slot];
     const int Nx = g.N[0], Ny = g.N[1], Nz = g.N[2];
     const size_t N = (size_t)Nx * Ny * Nz;
-    const int jx = lane & 3, jy = (lane >> 2) & 3, jz = lane >> 4;
-    const size_t node = (size_t)(i0[3 * k] + jx) + (size_t)Nx * ((size_t)(i0[3 * k + 1] + jy) + (size_t)Ny * (i0[3 * k + 2] + jz));
+    // P is [bc][z][x][y]: lanes take the stencil with y fastest (32-byte runs)
+    const int jy = lane & 3, jx = (lane >> 2) & 3, jz = lane >> 4, j = jx + 4 * jy + 16 * jz;
+    const size_t node = (size_t)(i0[3 * k + 1] + jy) + (size_t)Ny * ((size_t)(i0[3 * k] + jx) + (size_t)Nx * (i0[3 * k + 2] + jz));
     R w[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) w[c] = lam[(size_t)k * 256 + 64 * c + lane];
+    for (int c = 0; c < 4; ++c) w[c] = lam[(size_t)k * 256 + 64 * c + j];
     const int e0 = rowptr[k], e1 = rowptr[k + 1];
     for (int b = 0; b < g.B; ++b) {
         cplx<R> acc{0, 0};

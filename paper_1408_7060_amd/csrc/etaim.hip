@@ -88,6 +88,9 @@ struct etaim_ctx {
     std::vector<hipGraphExec_t> graphs[2];  // [conj][j]
     // launch shapes (0 = automatic); the autotuner sets them
     int gather_rows_t = 0, lines_x_t = 0, interp_waves = 4;
+    int yz_engine = 0;  // 0: LDS plane kernels, 1: register quadrant kernels
+    int x_engine = 0;   // 0: LDS line kernels, 1: register line kernels
+    void* xs = nullptr; // [ns][B] scaled columns for the register anterpolation
     hipEvent_t ev[4] = {};
     // per-kernel-class tracing
     bool prof = false;
@@ -220,6 +223,21 @@ int launch_lines(etaim_ctx* c, const cplx<R>* in, cplx<R>* out, const cplx<R>* t
     return ETAIM_OK;
 }
 
+// N of the register x-line kernels (N_x = N, N | 48 with a register codelet), 0 if none
+int xline_n(const etaim_ctx* c) {
+    const int n = c->gd.N[0];
+    if (c->gd.L[0] != 2 * n) return 0;
+    return (n == 16 || n == 24 || n == 48) ? n : 0;
+}
+
+// N of the register quadrant kernels for this grid (N_y = N_z = N, N | 48
+// with a register codelet), 0 if they do not apply
+int quad_n(const etaim_ctx* c) {
+    const int n = c->gd.N[1];
+    if (c->gd.N[2] != n || c->gd.L[1] != 2 * n || c->gd.L[2] != 2 * n) return 0;
+    return (n == 16 || n == 24 || n == 48) ? n : 0;
+}
+
 template <typename R>
 struct Ops {
     static cplx<R>* A(etaim_ctx* c) { return (cplx<R>*)c->A; }
@@ -254,6 +272,22 @@ struct Ops {
         const double a_sz = 4.0 * c->B * g.L[0] * g.N[2] * g.N[1] * s;
         Trace t(c, ETAIM_K_ANTERP_X, nB * 16 + 64.0 * c->ns * (4 + 4 * sizeof(R)) + (c->N3 + 1) * 4.0 + a_sz +
                                          (dinv ? c->ns * 16.0 : 0.0));
+        if (c->x_engine == 1) {
+            cplx<R>* xs = (cplx<R>*)c->xs;
+            hipLaunchKernelGGL(k_prescale<R>, dim3(blocks_for(nB)), dim3(256), 0, c->stream, x, dinv, xs, c->ns, c->B,
+                               conj_in, gate);
+            hipLaunchKernelGGL(k_anterp<R>, dim3((unsigned)((c->N3 + 255) / 256), (c->B + kAntCols - 1) / kAntCols),
+                               dim3(256), 0, c->stream, xs, c->nptr, c->nk, (const R*)c->nw_r, P(c), g, c->B, gate);
+            const dim3 gx((2 * g.N[1] * g.N[2] + 255) / 256, 4 * c->B);
+            switch (xline_n(c)) {
+                case 16: hipLaunchKernelGGL((k_xfwd<R, 16>), gx, dim3(256), 0, c->stream, P(c), A(c), g, gate); break;
+                case 24: hipLaunchKernelGGL((k_xfwd<R, 24>), gx, dim3(256), 0, c->stream, P(c), A(c), g, gate); break;
+                case 48: hipLaunchKernelGGL((k_xfwd<R, 48>), gx, dim3(256), 0, c->stream, P(c), A(c), g, gate); break;
+                default: return fail(ETAIM_EUNSUPPORTED, "register x-line kernels need N_x in {16, 24, 48}");
+            }
+            HIPCHK(hipGetLastError());
+            return ETAIM_OK;
+        }
         hipLaunchKernelGGL(k_fwdx_gather<R>, grid, dim3(kPlaneThreads), gather_lds(c), c->stream, x, dinv, c->nptr,
                            c->nk, (const R*)c->nw_r, A(c), tw(c, 0), c->rx, g, mr, c->ns, conj_in, gate);
         HIPCHK(hipGetLastError());
@@ -265,18 +299,43 @@ struct Ops {
         const long long Lx = g.L[0], Nx = g.N[0], Ny = g.N[1], Nz = g.N[2];
         const double s = sizeof(cplx<R>), bc = 4.0 * c->B;
         Trace t(c, ETAIM_K_FFT_X_INV, bc * Lx * Nz * Ny * s + bc * c->N3 * s);
+        if (c->x_engine == 1) {
+            const dim3 gx((unsigned)((2 * Ny * Nz + 255) / 256), (unsigned)(4 * c->B));
+            switch (xline_n(c)) {
+                case 16: hipLaunchKernelGGL((k_xinv<R, 16>), gx, dim3(256), 0, c->stream, A(c), P(c), g, gate); break;
+                case 24: hipLaunchKernelGGL((k_xinv<R, 24>), gx, dim3(256), 0, c->stream, A(c), P(c), g, gate); break;
+                case 48: hipLaunchKernelGGL((k_xinv<R, 48>), gx, dim3(256), 0, c->stream, A(c), P(c), g, gate); break;
+                default: return fail(ETAIM_EUNSUPPORTED, "register x-line kernels need N_x in {16, 24, 48}");
+            }
+            HIPCHK(hipGetLastError());
+            return ETAIM_OK;
+        }
+        // lines (y fastest) of the LDS line kernel, written to P[bc][z][x][y]
         return launch_lines<R>(c, A(c), P(c), tw(c, 0), c->rx, (int)Ny, (int)(4 * c->B * Nz), (int)Lx, (int)Nx, 1,
-                               Ny, Nz * Ny, Nx, Ny * Nx, 1, true, (int)Nz, Lx * Nz * Ny, Nz * Ny * Nx, gate,
+                               Ny, Nz * Ny, 1, Nx * Ny, Ny, true, (int)Nz, Lx * Nz * Ny, Nz * Nx * Ny, gate,
                                c->lines_x_t);
     }
     static size_t plane_lds(etaim_ctx* c) {
         return ((size_t)c->gd.L[2] * (c->gd.L[1] + 1) + c->gd.L[1] + c->gd.L[2]) * sizeof(cplx<R>);
     }
+    static size_t quad_lds(etaim_ctx* c) { return (size_t)4 * quad_n(c) * (quad_n(c) + 1) * sizeof(cplx<R>); }
     static int yz_green(etaim_ctx* c, int m, int conj, const int* gate = nullptr) {
         const GridDims& g = c->gd;
         dim3 grid(g.L[0], 4 * c->B);
         const double s = sizeof(cplx<R>);
         Trace t(c, ETAIM_K_YZ_GREEN, 2.0 * 4 * c->B * g.L[0] * g.N[2] * g.N[1] * s + 2.0 * c->gfold * s);
+        if (c->yz_engine == 1) {
+            const cplx<R>* G = ghat(c) + (size_t)m * 2 * c->gfold;
+            const size_t lds = quad_lds(c);
+            switch (quad_n(c)) {
+                case 16: hipLaunchKernelGGL((k_yzq_green<R, 16>), grid, dim3(kQuadThreads), lds, c->stream, A(c), G, g, conj, gate); break;
+                case 24: hipLaunchKernelGGL((k_yzq_green<R, 24>), grid, dim3(kQuadThreads), lds, c->stream, A(c), G, g, conj, gate); break;
+                case 48: hipLaunchKernelGGL((k_yzq_green<R, 48>), grid, dim3(kQuadThreads), lds, c->stream, A(c), G, g, conj, gate); break;
+                default: return fail(ETAIM_EUNSUPPORTED, "register plane kernels need N_y = N_z in {16, 24, 48}");
+            }
+            HIPCHK(hipGetLastError());
+            return ETAIM_OK;
+        }
         hipLaunchKernelGGL(k_yz_green<R>, grid, dim3(kPlaneThreads), plane_lds(c), c->stream, A(c),
                            ghat(c) + (size_t)m * 2 * c->gfold, tw(c, 1), tw(c, 2), c->ry, c->rz, g, conj, gate);
         HIPCHK(hipGetLastError());
@@ -314,6 +373,18 @@ struct Ops {
             const double s = sizeof(cplx<R>);
             Trace t(c, ETAIM_K_YZ_DELAYED,
                     nm * (4.0 * c->B * c->Np * s + 2.0 * c->gfold * s) + 4.0 * c->B * g.L[0] * g.N[2] * g.N[1] * s);
+            if (c->yz_engine == 1) {
+                const dim3 grid(g.L[0], 4 * c->B);
+                const size_t lds = quad_lds(c);
+                const cplx<R>* rg = (const cplx<R>*)ring(c);
+                const int ng = c->st.ng;
+                switch (quad_n(c)) {
+                    case 16: hipLaunchKernelGGL((k_yzq_delayed<R, 16>), grid, dim3(kQuadThreads), lds, c->stream, rg, ghat(c), A(c), g, ng, cur, nm, conj); break;
+                    case 24: hipLaunchKernelGGL((k_yzq_delayed<R, 24>), grid, dim3(kQuadThreads), lds, c->stream, rg, ghat(c), A(c), g, ng, cur, nm, conj); break;
+                    case 48: hipLaunchKernelGGL((k_yzq_delayed<R, 48>), grid, dim3(kQuadThreads), lds, c->stream, rg, ghat(c), A(c), g, ng, cur, nm, conj); break;
+                    default: return fail(ETAIM_EUNSUPPORTED, "register plane kernels need N_y = N_z in {16, 24, 48}");
+                }
+            } else
             hipLaunchKernelGGL(k_yz_delayed<R>, dim3(g.L[0], 4 * c->B), dim3(kPlaneThreads), plane_lds(c), c->stream,
                                (const cplx<R>*)ring(c), ghat(c), A(c), tw(c, 1), tw(c, 2), c->ry, c->rz, g,
                                c->st.ng, cur, nm, conj);
@@ -332,6 +403,17 @@ struct Ops {
         {
             const double s = sizeof(cplx<R>);
             Trace t(c, ETAIM_K_YZ_COMMIT, 4.0 * c->B * g.L[0] * g.N[2] * g.N[1] * s + 4.0 * c->B * c->Np * s);
+            if (c->yz_engine == 1) {
+                const dim3 grid(g.L[0], 4 * c->B);
+                const size_t lds = quad_lds(c);
+                const cplx<R>* a = (const cplx<R>*)A(c);
+                switch (quad_n(c)) {
+                    case 16: hipLaunchKernelGGL((k_yzq_commit<R, 16>), grid, dim3(kQuadThreads), lds, c->stream, a, slot, g); break;
+                    case 24: hipLaunchKernelGGL((k_yzq_commit<R, 24>), grid, dim3(kQuadThreads), lds, c->stream, a, slot, g); break;
+                    case 48: hipLaunchKernelGGL((k_yzq_commit<R, 48>), grid, dim3(kQuadThreads), lds, c->stream, a, slot, g); break;
+                    default: return fail(ETAIM_EUNSUPPORTED, "register plane kernels need N_y = N_z in {16, 24, 48}");
+                }
+            } else
             hipLaunchKernelGGL(k_yz_commit<R>, dim3(g.L[0], 4 * c->B), dim3(kPlaneThreads), plane_lds(c), c->stream,
                                (const cplx<R>*)A(c), slot, tw(c, 1), tw(c, 2), c->ry, c->rz, g);
         }
@@ -348,6 +430,12 @@ struct Ops {
         const int bytes = (int)plane_lds(c);
         for (const void* f : {(const void*)k_yz_green<R>, (const void*)k_yz_commit<R>, (const void*)k_yz_delayed<R>})
             HIPCHK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+        for (const void* f : {(const void*)k_yzq_green<R, 16>, (const void*)k_yzq_green<R, 24>,
+                              (const void*)k_yzq_green<R, 48>, (const void*)k_yzq_commit<R, 16>,
+                              (const void*)k_yzq_commit<R, 24>, (const void*)k_yzq_commit<R, 48>,
+                              (const void*)k_yzq_delayed<R, 16>, (const void*)k_yzq_delayed<R, 24>,
+                              (const void*)k_yzq_delayed<R, 48>})
+            HIPCHK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
         // the gather's LDS grows with its tuned row count
         HIPCHK(hipFuncSetAttribute((const void*)k_fwdx_gather<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    160 * 1024));
@@ -684,6 +772,7 @@ int make_working(etaim_ctx* c) {
     }
     CHK(c->allocv(c->A, 4 * nB * (size_t)c->gd.N[2] * c->gd.N[1] * c->gd.L[0] * sizeof(cplx<R>)));
     CHK(c->allocv(c->P, 4 * nB * c->N3 * sizeof(cplx<R>)));
+    CHK(c->allocv(c->xs, nB * (size_t)c->ns * sizeof(cplx<R>)));
     CHK(c->allocv(c->ring, (size_t)c->st.ng * 4 * nB * c->Np * sizeof(cplx<R>)));
     // plane kernels: LDS and per-thread register staging limits
     const size_t lds = Ops<R>::plane_lds(c);
@@ -909,6 +998,8 @@ int etaim_create(etaim_ctx** out, const etaim_mesh* mesh, const etaim_rwg* rwg, 
     c->rx = make_radix(c->gd.L[0]);
     c->ry = make_radix(c->gd.L[1]);
     c->rz = make_radix(c->gd.L[2]);
+    c->yz_engine = quad_n(c.get()) ? 1 : 0;
+    c->x_engine = xline_n(c.get()) ? 1 : 0;
     c->N3 = (size_t)c->gd.N[0] * c->gd.N[1] * c->gd.N[2];
     c->Np = (size_t)c->gd.L[0] * c->gd.L[1] * c->gd.L[2];
     c->gfold = (size_t)(c->gd.N[0] + 1) * (c->gd.N[1] + 1) * (c->gd.N[2] + 1);

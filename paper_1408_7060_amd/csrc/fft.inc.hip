@@ -74,6 +74,47 @@ __device__ __forceinline__ void w48(int m, double& c, double& s) {
     s = -sr;  // exp(-i angle)
 }
 
+// exp(-2 pi i m / 96) for m = 0..95 (multiples of 3.75 degrees): the
+// parity pre-twiddles w_{2N}^n of the register plane kernels (2N | 96).
+__device__ __forceinline__ void w96(int m, double& c, double& s) {
+    // cos(k * pi / 48), k = 0..24 (quarter wave), exact decimal expansions
+    const double q[25] = {1.0,
+                          0.997858923238603506738,
+                          0.991444861373810411145,
+                          0.980785280403230449126,
+                          0.965925826289068286750,
+                          0.946930129495105664256,
+                          0.923879532511286756128,
+                          0.896872741532688303894,
+                          0.866025403784438646764,
+                          0.831469612302545237079,
+                          0.793353340291235164580,
+                          0.751839807478977396408,
+                          0.707106781186547524401,
+                          0.659345815100068868425,
+                          0.608761429008720639416,
+                          0.555570233019602224743,
+                          0.5,
+                          0.442288690219001281995,
+                          0.382683432365089771728,
+                          0.321439465303161580701,
+                          0.258819045102520762349,
+                          0.195090322016128267848,
+                          0.130526192220051591548,
+                          0.065403129230143066815,
+                          0.0};
+    m %= 96;
+    const int quad = m / 24, r = m % 24;
+    double cr = q[r], sr = q[24 - r];
+    for (int i = 0; i < quad; ++i) {
+        const double t = cr;
+        cr = -sr;
+        sr = t;
+    }
+    c = cr;
+    s = -sr;  // exp(-i angle)
+}
+
 template <typename R, int RAD>
 __device__ __forceinline__ void dft_small(cplx<R> (&u)[RAD], bool inverse);
 
@@ -140,6 +181,10 @@ __device__ __forceinline__ void dft_small(cplx<R> (&u)[RAD], bool inverse) {
         dft_composite<R, 2, 4>(u, inverse);
     } else if constexpr (RAD == 12) {
         dft_composite<R, 4, 3>(u, inverse);
+    } else if constexpr (RAD == 24) {
+        dft_composite<R, 8, 3>(u, inverse);
+    } else if constexpr (RAD == 48) {
+        dft_composite<R, 16, 3>(u, inverse);
     } else {
         static_assert(RAD == 16, "unsupported radix");
         dft_composite<R, 4, 4>(u, inverse);

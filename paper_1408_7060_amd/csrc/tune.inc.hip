@@ -39,7 +39,7 @@ bool radix_equal(const Radix& a, const Radix& b) {
 
 struct Shape {
     Radix rx, ry, rz;
-    int mr = 0, mt = 0, waves = 4, sync = 1, graph = 0;
+    int mr = 0, mt = 0, waves = 4, sync = 1, graph = 0, engine = 0, xeng = 0;
 };
 
 template <typename R>
@@ -68,7 +68,8 @@ bool shape_fits(const etaim_ctx* c, const Shape& s) {
     return plane_fits(g.N[2], s.ry) && plane_fits(g.L[1], s.rz) && plane_fits(4 * mr, s.rx) &&
            plane_fits(mt, s.rx) && (4 * (size_t)mr * (Lx + 1) + Lx) * e <= 160 * 1024 &&
            ((size_t)mt * (Lx + 1) + Lx) * e <= (size_t)kLdsBudget && s.waves >= 1 && s.waves <= 4 &&
-           s.sync >= 1 && s.sync <= c->prm.restart;
+           s.sync >= 1 && s.sync <= c->prm.restart && (s.engine == 0 || (s.engine == 1 && quad_n(c) > 0)) &&
+           (s.xeng == 0 || (s.xeng == 1 && xline_n(c) > 0));
 }
 
 void drop_graphs(etaim_ctx* c) {
@@ -88,6 +89,8 @@ void put_shape(etaim_ctx* c, const Shape& s) {
     c->interp_waves = s.waves;
     c->sync_every = s.sync;
     c->use_graph = s.graph != 0;
+    c->yz_engine = s.engine;
+    c->x_engine = s.xeng;
     drop_graphs(c);  // captured steps hold the old launch shapes
 }
 
@@ -101,6 +104,8 @@ Shape get_shape(const etaim_ctx* c) {
     s.waves = c->interp_waves;
     s.sync = c->sync_every;
     s.graph = c->use_graph ? 1 : 0;
+    s.engine = c->yz_engine;
+    s.xeng = c->x_engine;
     return s;
 }
 
@@ -115,6 +120,8 @@ void shape_to_c(const etaim_ctx* c, const Shape& s, etaim_tuning* t) {
     t->interp_waves = s.waves;
     t->sync_every = s.sync;
     t->graph = s.graph;
+    t->yz_engine = s.engine;
+    t->x_engine = s.xeng;
 }
 
 // EINVAL for malformed plans; shape_fits decides EUNSUPPORTED afterwards
@@ -141,6 +148,8 @@ int shape_from_c(const etaim_ctx* c, const etaim_tuning* t, Shape& s) {
     s.waves = t->interp_waves;
     s.sync = t->sync_every;
     s.graph = t->graph ? 1 : 0;
+    s.engine = t->yz_engine;
+    s.xeng = t->x_engine;
     return ETAIM_OK;
 }
 
@@ -152,7 +161,7 @@ std::string tune_key(const etaim_ctx* c) {
     return k;
 }
 
-// ---- JSON-lines cache (one flat object per line, written by tune_record)
+// ---- JSON-lines cache (one flat object per line, written by cache_append)
 bool json_int(const std::string& line, const char* name, long& v) {
     const std::string pat = std::string("\"") + name + "\":";
     size_t p = line.find(pat);
@@ -192,16 +201,19 @@ bool cache_lookup(const char* path, const std::string& key, etaim_tuning& t) {
         line = buf;
         if (line.find("\"key\": \"" + key + "\"") == std::string::npos) continue;
         std::memset(&t, 0, sizeof t);
-        long v[5];
+        long v[7];
         if (json_ints(line, "radix_x", t.radix[0], 8) && json_ints(line, "radix_y", t.radix[1], 8) &&
             json_ints(line, "radix_z", t.radix[2], 8) && json_int(line, "gather_rows", v[0]) &&
             json_int(line, "lines_per_block", v[1]) && json_int(line, "interp_waves", v[2]) &&
-            json_int(line, "sync_every", v[3]) && json_int(line, "graph", v[4])) {
+            json_int(line, "sync_every", v[3]) && json_int(line, "graph", v[4]) &&
+            json_int(line, "yz_engine", v[5]) && json_int(line, "x_engine", v[6])) {
             t.gather_rows = (int)v[0];
             t.lines_per_block = (int)v[1];
             t.interp_waves = (int)v[2];
             t.sync_every = (int)v[3];
             t.graph = (int)v[4];
+            t.yz_engine = (int)v[5];
+            t.x_engine = (int)v[6];
             found = true;  // the last matching record wins
         }
     }
@@ -220,9 +232,10 @@ int cache_append(const char* path, const std::string& key, const etaim_tuning& t
     std::fprintf(f,
                  "{\"key\": \"%s\", \"radix_x\": %s, \"radix_y\": %s, \"radix_z\": %s, \"gather_rows\": %d, "
                  "\"lines_per_block\": %d, \"interp_waves\": %d, \"sync_every\": %d, \"graph\": %d, "
-                 "\"apply_ms\": %.4f, \"solve_ms\": %.3f}\n",
+                 "\"yz_engine\": %d, \"x_engine\": %d, \"apply_ms\": %.4f, \"solve_ms\": %.3f}\n",
                  key.c_str(), arr(t.radix[0]).c_str(), arr(t.radix[1]).c_str(), arr(t.radix[2]).c_str(),
-                 t.gather_rows, t.lines_per_block, t.interp_waves, t.sync_every, t.graph, t.apply_ms, t.solve_ms);
+                 t.gather_rows, t.lines_per_block, t.interp_waves, t.sync_every, t.graph, t.yz_engine, t.x_engine, t.apply_ms,
+                 t.solve_ms);
     std::fclose(f);
     return ETAIM_OK;
 }
@@ -338,6 +351,18 @@ int autotune_impl(etaim_ctx* c, int budget_ms, etaim_tuning* out) {
         put_shape(c, best);
         return ETAIM_OK;
     };
+    for (int eng : {0, 1})
+        if (eng != best.engine) {
+            Shape s = best;
+            s.engine = eng;
+            CHK(trial(s));
+        }
+    for (int eng : {0, 1})
+        if (eng != best.xeng) {
+            Shape s = best;
+            s.xeng = eng;
+            CHK(trial(s));
+        }
     for (const Radix& p : candidate_plans(c->gd.L[0]))
         if (!radix_equal(p, best.rx)) {
             Shape s = best;

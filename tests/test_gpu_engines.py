@@ -1,0 +1,132 @@
+"""Both y/z plane engines (LDS-staged radix passes over the padded plane,
+and register-resident parity quadrants) against the FP64 oracle, through
+the C ABI.
+
+At the level-4 sphere (48^3 grid, the size the bench marches) the oracle's
+exact near-zone entries take minutes to assemble on the host, so the
+operator is checked where the near zone is empty: Z_m for m > M_n is the
+pure FFT (far) operator, and the delayed field of a history whose first M_n
+samples are zero only sees those Z_m."""
+import functools
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_cases import gpu_problem, oracle_aim, oracle_matvec, params_of, rel
+from oracle import aim, geometry, physics as ph
+
+pytestmark = pytest.mark.gpu
+
+L2 = W.SPHERE_L2.name
+L4 = W.SPHERE_L4.name
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128)).cuda()
+
+
+@functools.lru_cache(maxsize=None)
+def _oracle_far(name):
+    wl = W.WORKLOADS[name]
+    p = params_of(wl)
+    s = geometry.Surface(p["xyz"], p["tri"], p["rwg"])
+    return s, aim.AIM(s, wl.grid, p["d_near"], p["dt"], wl.f0, p["ng"]), p
+
+
+def _with_engine(P, engine):
+    """engine = (yz_engine, x_engine), or one value for both stages."""
+    yz, xe = engine if isinstance(engine, tuple) else (engine, engine)
+    d = P.tuning()
+    d["yz_engine"], d["x_engine"] = yz, xe
+    P.set_tuning(d)
+    t = P.tuning()
+    assert (t["yz_engine"], t["x_engine"]) == (yz, xe)
+
+
+ENGINES = [(0, 0), (1, 1), (1, 0), (0, 1)]
+
+
+@pytest.mark.parametrize("engine", ENGINES, ids=[f"yz{a}_x{b}" for a, b in ENGINES])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-5)], ids=["fp64", "fp32"])
+def test_far_operator_level4(torch, prec, tol, engine):
+    s, A, p = _oracle_far(L4)
+    assert A.mn < p["ng"]
+    P = gpu_problem(L4, precision=prec, batch=2, nt=8)
+    assert P.info["mn"] == A.mn
+    _with_engine(P, engine)
+    x = W.complex_normal(31, (2, s.ns))
+    for m in (A.mn + 1, (A.mn + p["ng"]) // 2, p["ng"]):
+        y = P.apply_z(m, _dev(torch, x)).cpu().numpy()
+        ref = np.array([A.far_matvec(m, xb) for xb in x])
+        e = rel(y, ref)
+        _say("L4 far", "fp32" if prec else "fp64", "engine", engine, "m", m, "rel", e)
+        assert e <= tol, (m, e)
+    P.close()
+
+
+@pytest.mark.parametrize("engine", [0, 1])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-5)], ids=["fp64", "fp32"])
+def test_delayed_field_level4(torch, prec, tol, engine):
+    s, A, p = _oracle_far(L4)
+    ng = p["ng"]
+    P = gpu_problem(L4, precision=prec, batch=1, nt=8)
+    _with_engine(P, engine)
+    hist = W.complex_normal(32, (ng, 1, s.ns))
+    hist[:A.mn] = 0.0
+    b = P.delayed_field(_dev(torch, hist)).cpu().numpy()
+    ref = sum(A.far_matvec(m, hist[m - 1, 0]) for m in range(A.mn + 1, ng + 1))[None]
+    e = rel(b, ref)
+    _say("L4 delayed", "fp32" if prec else "fp64", "engine", engine, "rel", e)
+    assert e <= tol
+    P.close()
+
+
+@pytest.mark.parametrize("engine", ENGINES, ids=[f"yz{a}_x{b}" for a, b in ENGINES])
+def test_engines_full_operator_level2(torch, engine):
+    """Every Z_m (near + far) and the delayed field at the 16^3 grid."""
+    s, A, vals, p = oracle_aim(L2)
+    P = gpu_problem(L2)
+    _with_engine(P, engine)
+    x = W.complex_normal(33, (2, s.ns))
+    for m in range(p["ng"] + 1):
+        y = P.apply_z(m, _dev(torch, x[:1])).cpu().numpy()
+        ref = oracle_matvec(L2, m, x[:1], direct=True)
+        assert rel(y, ref) <= 1e-12, (m, rel(y, ref))
+    hist = W.complex_normal(34, (p["ng"], 1, s.ns))
+    b = P.delayed_field(_dev(torch, hist)).cpu().numpy()
+    ref = sum(oracle_matvec(L2, m, hist[m - 1], direct=True) for m in range(1, p["ng"] + 1))
+    assert rel(b, ref) <= 1e-12
+    P.close()
+
+
+def test_engines_give_the_same_march(torch):
+    wl = W.SPHERE_L2
+    s, A, vals, p = oracle_aim(L2)
+    from oracle import excitation
+    kh = W.unit_vectors(35, 2, 3)
+    pp = W.polarisations(35, kh)
+    V = excitation.excitation(s, 16, p["dt"], kh, pp, wl.sigma, wl.td, wl.f0)
+    out = []
+    for engine in ENGINES:
+        P = gpu_problem(L2, nt=16, batch=2, tol=1e-13)
+        _with_engine(P, engine)
+        I, _ = P.march(_dev(torch, V))
+        out.append(I.cpu().numpy())
+        P.close()
+    for o in out[1:]:
+        assert rel(o, out[0]) <= 1e-11
