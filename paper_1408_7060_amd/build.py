@@ -14,6 +14,7 @@ ARCH = os.environ.get("ETAIM_OFFLOAD_ARCH", "gfx950")
 def command(out: str = LIB) -> list[str]:
     return [
         "hipcc", "-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-shared", "-fopenmp",
+        # separate roundings by default; kernels opt in to contraction where it measured faster
         "-ffp-contract=off",
         # no packed FP32 instructions in device code
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

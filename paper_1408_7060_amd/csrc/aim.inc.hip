@@ -121,6 +121,7 @@ __global__ void __launch_bounds__(256) k_anterp(const cplx<R>* __restrict__ xs, 
                                                 const int* __restrict__ nk, const R* __restrict__ nw,
                                                 cplx<R>* __restrict__ q, GridDims g, int B,
                                                 const int* __restrict__ gate) {
+#pragma clang fp contract(fast)  // fused multiply-adds: measured faster here
     if (gated_off(gate)) return;
     const int Nx = g.N[0], Ny = g.N[1], Nz = g.N[2];
     const size_t N3 = (size_t)Nx * Ny * Nz;
@@ -363,14 +364,18 @@ __global__ void __launch_bounds__(kPlaneThreads) k_yz_delayed(const cplx<R>* __r
 // splits by the parities of the wavenumbers: Y[2b + pz][2a + py] is the
 // N x N DFT of X[z][y] w_{2N}^{pz z + py y}, and the kept outputs z, y < N
 // of the inverse transform are the sum over the four parity quadrants of
-// w_{2N}^{-(pz z + py y)} times their N x N inverse DFTs.  Wave q = 2 pz + py
-// of a block owns quadrant q: lane l < N holds one row (then one column) of
-// N points in registers, so each 1-D transform is an N-point FFT with
-// compile-time twiddles and no LDS traffic; only the row <-> column exchange
-// goes through the wave's LDS tile of N x (N+1) points.  The four quadrants
-// are summed through LDS at the end.  Ring slots of this path are stored
-// quadrant-major: [bc][kx][q][kz'][ky'] with kz = 2 kz' + pz, ky = 2 ky' + py.
-constexpr int kQuadThreads = 256;
+// w_{2N}^{-(pz z + py y)} times their N x N inverse DFTs.  The row (y)
+// transforms do not depend on pz (w_{2N}^{pz z} scales a whole row), so
+// they run once per py and are then scaled into both pz tiles; on the way
+// back the two pz halves are added before the inverse row transforms.  A
+// task (thread) holds one row or column of N points in registers, so every
+// 1-D transform is an N-point FFT with compile-time twiddles and no LDS
+// traffic; the four quadrant tiles (N x (N+1) each, q = 2 pz + py) carry
+// the row <-> column exchanges.  Tasks per phase: 2N rows, 4N columns.
+// Ring slots of this path are quadrant-major: [bc][kx][q][kz'][ky'] with
+// kz = 2 kz' + pz, ky = 2 ky' + py.  Blocks run bc fastest (grid (4B, L_x)),
+// so the blocks of one XCD share the Green-spectrum plane of their kx in L2.
+constexpr int kQuadThreads = 192;
 
 // two complex values as one vector load
 template <typename R>
@@ -384,6 +389,10 @@ struct Pair<double> {
     using type = double4;
 };
 
+template <typename R, int N>
+__device__ __forceinline__ cplx<R>* qtile(cplx<R>* t0, int q) {
+    return t0 + q * N * (N + 1);
+}
 
 template <typename R, int N>
 __device__ __forceinline__ void tile_row(cplx<R>* t, int z, cplx<R> (&u)[N], bool store) {
@@ -407,146 +416,152 @@ __device__ __forceinline__ void tile_col(cplx<R>* t, int y, cplx<R> (&u)[N], boo
     }
 }
 
-// stage the N x N plane src into this wave's tile (coalesced reads)
+// tile 0 = X, tile 1 = X w_{2N}^{y} (the py = 1 pre-twiddle); twy[n] = w_{2N}^n
 template <typename R, int N>
-__device__ __forceinline__ void tile_stage(cplx<R>* t, const cplx<R>* __restrict__ src, int lane) {
-    for (int e = lane; e < N * N; e += 64) {
-        const int z = e / N, y = e - z * N;
-        t[z * (N + 1) + y] = src[e];
-    }
-}
-
-// forward row transforms of the quadrant: pre-twiddle w_{2N}^{py y}, N-point FFT
-template <typename R, int N>
-__device__ __forceinline__ void quad_rows_forward(cplx<R>* t, int lane, int py) {
-    if (lane < N) {
-        cplx<R> u[N];
-        tile_row<R, N>(t, lane, u, false);
-        if (py) {
-#pragma unroll
-            for (int j = 1; j < N; ++j) u[j] = u[j] * w2n<R, N>(j, false);
-        }
-        dft_small<R, N>(u, false);
-        tile_row<R, N>(t, lane, u, true);
-    }
-}
-
-// inverse row transforms, post-twiddle w_{2N}^{-py y}
-template <typename R, int N>
-__device__ __forceinline__ void quad_rows_inverse(cplx<R>* t, int lane, int py) {
-    if (lane < N) {
-        cplx<R> u[N];
-        tile_row<R, N>(t, lane, u, false);
-        dft_small<R, N>(u, true);
-        if (py) {
-#pragma unroll
-            for (int j = 1; j < N; ++j) u[j] = u[j] * w2n<R, N>(j, true);
-        }
-        tile_row<R, N>(t, lane, u, true);
-    }
-}
-
-// out[e] = sum of the four quadrant tiles at (z, y), e = z N + y
-template <typename R, int N>
-__device__ __forceinline__ void quad_sum_store(const cplx<R>* t0, cplx<R>* __restrict__ out) {
-    constexpr int TS = N * (N + 1);
+__device__ __forceinline__ void quad_stage(cplx<R>* t0, const cplx<R>* __restrict__ src,
+                                           const cplx<R>* __restrict__ twy) {
     for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
         const int z = e / N, y = e - z * N, o = z * (N + 1) + y;
-        out[e] = (t0[o] + t0[TS + o]) + (t0[2 * TS + o] + t0[3 * TS + o]);
+        const cplx<R> v = src[e];
+        t0[o] = v;
+        qtile<R, N>(t0, 1)[o] = v * twy[y];
     }
+}
+
+// forward rows: task (py, z): N-point DFT of row z of tile py, kept in tile
+// py (pz = 0) and, times w_{2N}^{z}, written to tile 2 + py (pz = 1)
+template <typename R, int N>
+__device__ __forceinline__ void quad_rows_forward(cplx<R>* t0, const cplx<R>* __restrict__ twz) {
+    const int i = threadIdx.x;
+    if (i < 2 * N) {
+        const int py = i / N, z = i - py * N;
+        cplx<R> u[N];
+        tile_row<R, N>(qtile<R, N>(t0, py), z, u, false);
+        dft_small<R, N>(u, false);
+        tile_row<R, N>(qtile<R, N>(t0, py), z, u, true);
+        const cplx<R> s = twz[z];
+#pragma unroll
+        for (int j = 0; j < N; ++j) u[j] = u[j] * s;
+        tile_row<R, N>(qtile<R, N>(t0, 2 + py), z, u, true);
+    }
+}
+
+// inverse rows: task (py, z): row z of tile py plus conj(w_{2N}^{z}) times
+// row z of tile 2 + py, N-point inverse DFT, back into tile py
+template <typename R, int N>
+__device__ __forceinline__ void quad_rows_inverse(cplx<R>* t0, const cplx<R>* __restrict__ twz) {
+    const int i = threadIdx.x;
+    if (i < 2 * N) {
+        const int py = i / N, z = i - py * N;
+        cplx<R> u[N];
+        tile_row<R, N>(qtile<R, N>(t0, py), z, u, false);
+        const cplx<R> s = conjz(twz[z]);
+        const cplx<R>* r1 = qtile<R, N>(t0, 2 + py) + z * (N + 1);
+#pragma unroll
+        for (int j = 0; j < N; ++j) u[j] += r1[j] * s;
+        dft_small<R, N>(u, true);
+        tile_row<R, N>(qtile<R, N>(t0, py), z, u, true);
+    }
+}
+
+// out[z N + y] = tile0 + conj(w_{2N}^{y}) tile1 (the py = 1 post-twiddle)
+template <typename R, int N>
+__device__ __forceinline__ void quad_sum_store(cplx<R>* t0, cplx<R>* __restrict__ out,
+                                               const cplx<R>* __restrict__ twy) {
+    for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
+        const int z = e / N, y = e - z * N, o = z * (N + 1) + y;
+        out[e] = t0[o] + qtile<R, N>(t0, 1)[o] * conjz(twy[y]);
+    }
+}
+
+// folded Green spectrum at ky = 2 c + py, kz = 2 j + pz for one plane
+template <typename R, int N>
+__device__ __forceinline__ cplx<R> quad_green(const cplx<R>* __restrict__ Gk, int j, int c, int py, int pz,
+                                              int conj_g) {
+    cplx<R> gv = Gk[fold(2 * j + pz, 2 * N) * (N + 1) + fold(2 * c + py, 2 * N)];
+    if (conj_g) gv.y = -gv.y;
+    return gv;
 }
 
 // Matvec y/z stage on the register path, in place on A (as k_yz_green).
 template <typename R, int N>
 __global__ void __launch_bounds__(kQuadThreads) k_yzq_green(cplx<R>* __restrict__ A, const cplx<R>* __restrict__ G,
-                                                            GridDims g, int conj_g, const int* __restrict__ gate) {
+                                                            const cplx<R>* __restrict__ twy,
+                                                            const cplx<R>* __restrict__ twz, GridDims g, int conj_g,
+                                                            const int* __restrict__ gate) {
     if (gated_off(gate)) return;
     extern __shared__ unsigned char smem_raw[];
     cplx<R>* t0 = reinterpret_cast<cplx<R>*>(smem_raw);
-    const int q = threadIdx.x >> 6, lane = threadIdx.x & 63, py = q & 1, pz = q >> 1;
-    cplx<R>* t = t0 + q * N * (N + 1);
-    const int kx = blockIdx.x, bc = blockIdx.y, Lx = g.L[0];
+    const int bc = blockIdx.x, kx = blockIdx.y, Lx = g.L[0];
     cplx<R>* pl = A + ((size_t)bc * Lx + kx) * (size_t)(N * N);
-    tile_stage<R, N>(t, pl, lane);
+    quad_stage<R, N>(t0, pl, twy);
     __syncthreads();
-    quad_rows_forward<R, N>(t, lane, py);
+    quad_rows_forward<R, N>(t0, twz);
     __syncthreads();
-    if (lane < N) {
-        cplx<R> u[N];
-        tile_col<R, N>(t, lane, u, false);
-        if (pz) {
-#pragma unroll
-            for (int j = 1; j < N; ++j) u[j] = u[j] * w2n<R, N>(j, false);
-        }
-        dft_small<R, N>(u, false);
+    const int i = threadIdx.x;
+    if (i < 4 * N) {
+        const int q = i / N, c = i - q * N, py = q & 1, pz = q >> 1;
         const int gx = g.N[0] + 1, gg = N + 1;
         const cplx<R>* Gk = G + ((size_t)((bc & 3) == 3 ? 1 : 0) * gx + fold(kx, Lx)) * (size_t)(gg * gg);
-        const int fy = fold(2 * lane + py, 2 * N);
+        cplx<R> u[N];
+        tile_col<R, N>(qtile<R, N>(t0, q), c, u, false);
+        dft_small<R, N>(u, false);
 #pragma unroll
-        for (int j = 0; j < N; ++j) {
-            cplx<R> gv = Gk[fold(2 * j + pz, 2 * N) * gg + fy];
-            if (conj_g) gv.y = -gv.y;
-            u[j] = u[j] * gv;
-        }
+        for (int j = 0; j < N; ++j) u[j] = u[j] * quad_green<R, N>(Gk, j, c, py, pz, conj_g);
         dft_small<R, N>(u, true);
-        if (pz) {
-#pragma unroll
-            for (int j = 1; j < N; ++j) u[j] = u[j] * w2n<R, N>(j, true);
-        }
-        tile_col<R, N>(t, lane, u, true);
+        tile_col<R, N>(qtile<R, N>(t0, q), c, u, true);
     }
     __syncthreads();
-    quad_rows_inverse<R, N>(t, lane, py);
+    quad_rows_inverse<R, N>(t0, twz);
     __syncthreads();
-    quad_sum_store<R, N>(t0, pl);
+    quad_sum_store<R, N>(t0, pl, twy);
 }
 
 // Commit y/z stage on the register path: forward transforms of the plane
 // into a quadrant-major ring slot plane.
 template <typename R, int N>
 __global__ void __launch_bounds__(kQuadThreads) k_yzq_commit(const cplx<R>* __restrict__ A, cplx<R>* __restrict__ slot,
-                                                             GridDims g) {
+                                                             const cplx<R>* __restrict__ twy,
+                                                             const cplx<R>* __restrict__ twz, GridDims g) {
     extern __shared__ unsigned char smem_raw[];
     cplx<R>* t0 = reinterpret_cast<cplx<R>*>(smem_raw);
-    const int q = threadIdx.x >> 6, lane = threadIdx.x & 63, py = q & 1, pz = q >> 1;
-    cplx<R>* t = t0 + q * N * (N + 1);
-    const int kx = blockIdx.x, bc = blockIdx.y, Lx = g.L[0];
-    tile_stage<R, N>(t, A + ((size_t)bc * Lx + kx) * (size_t)(N * N), lane);
+    const int bc = blockIdx.x, kx = blockIdx.y, Lx = g.L[0];
+    quad_stage<R, N>(t0, A + ((size_t)bc * Lx + kx) * (size_t)(N * N), twy);
     __syncthreads();
-    quad_rows_forward<R, N>(t, lane, py);
+    quad_rows_forward<R, N>(t0, twz);
     __syncthreads();
-    if (lane < N) {
+    const int i = threadIdx.x;
+    if (i < 4 * N) {
+        const int q = i / N, c = i - q * N;
         cplx<R> u[N];
-        tile_col<R, N>(t, lane, u, false);
-        if (pz) {
-#pragma unroll
-            for (int j = 1; j < N; ++j) u[j] = u[j] * w2n<R, N>(j, false);
-        }
+        tile_col<R, N>(qtile<R, N>(t0, q), c, u, false);
         dft_small<R, N>(u, false);
-        cplx<R>* o = slot + (((size_t)bc * Lx + kx) * 4 + q) * (size_t)(N * N) + lane;
+        cplx<R>* o = slot + (((size_t)bc * Lx + kx) * 4 + q) * (size_t)(N * N) + c;
 #pragma unroll
         for (int j = 0; j < N; ++j) o[j * N] = u[j];
     }
 }
 
 // Delayed-field y/z stage on the register path.  The k-space temporal sum
-// over the quadrant-major ring streams the history: the block's 256 threads
-// own consecutive pairs of spectrum points of the plane (16-byte loads of
-// the ring, coalesced), accumulate over m in registers and leave the sums
-// in the quadrant tiles; then the inverse column and row transforms and the
-// quadrant sum as in k_yzq_green.
+// over the quadrant-major ring streams the history: the block's threads
+// own consecutive pairs of spectrum points of the plane (one vector load of
+// the ring per pair, coalesced), accumulate over m in registers and leave
+// the sums in the quadrant tiles; then the inverse column and row
+// transforms and the quadrant sum as in k_yzq_green.
+constexpr int kDelayThreads = 256;  // the streaming sum wants more loads in flight than 4N tasks
+
 template <typename R, int N>
-__global__ void __launch_bounds__(kQuadThreads) k_yzq_delayed(const cplx<R>* __restrict__ ring,
+__global__ void __launch_bounds__(kDelayThreads) k_yzq_delayed(const cplx<R>* __restrict__ ring,
                                                               const cplx<R>* __restrict__ G, cplx<R>* __restrict__ A,
-                                                              GridDims g, int ng, int cur, int nm, int conj_g) {
+                                                              const cplx<R>* __restrict__ twy,
+                                                              const cplx<R>* __restrict__ twz, GridDims g, int ng,
+                                                              int cur, int nm, int conj_g) {
     extern __shared__ unsigned char smem_raw[];
     cplx<R>* t0 = reinterpret_cast<cplx<R>*>(smem_raw);
     // the plane's 4 N^2 points as pairs; the sum runs in chunks of PER pairs
     // per thread so that the accumulators stay within half the VGPR file
-    constexpr int NN = N * N, PAIRS = 4 * NN / 2, PER = 9, CHUNK = PER * kQuadThreads;
-    const int q = threadIdx.x >> 6, lane = threadIdx.x & 63, py = q & 1, pz = q >> 1;
-    cplx<R>* t = t0 + q * N * (N + 1);
-    const int kx = blockIdx.x, bc = blockIdx.y, Lx = g.L[0];
+    constexpr int NN = N * N, PAIRS = 4 * NN / 2, PER = 9, CHUNK = PER * kDelayThreads;
+    const int bc = blockIdx.x, kx = blockIdx.y, Lx = g.L[0];
     const int gx = g.N[0] + 1, gg = N + 1;
     const size_t gsz = (size_t)2 * gx * gg * gg;
     const size_t slot_sz = (size_t)4 * g.B * Lx * 4 * NN;
@@ -559,7 +574,7 @@ __global__ void __launch_bounds__(kQuadThreads) k_yzq_delayed(const cplx<R>* __r
         cplx<R> acc[PER][2];
 #pragma unroll
         for (int r = 0; r < PER; ++r) {
-            const int i = c0 + threadIdx.x + r * kQuadThreads;
+            const int i = c0 + threadIdx.x + r * kDelayThreads;
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const int e = 2 * i + h, qq = e / NN, rr = e - qq * NN;
@@ -575,10 +590,9 @@ __global__ void __launch_bounds__(kQuadThreads) k_yzq_delayed(const cplx<R>* __r
             const cplx<R>* Gm = G + (size_t)m * gsz + goff;
 #pragma unroll
             for (int r = 0; r < PER; ++r) {
-                const int i = c0 + threadIdx.x + r * kQuadThreads;
+                const int i = c0 + threadIdx.x + r * kDelayThreads;
                 if (i < PAIRS) {
                     cplx<R> v[2];
-                    // one 16-byte (FP32) or 32-byte (FP64) load per pair
                     *reinterpret_cast<typename Pair<R>::type*>(v) =
                         *reinterpret_cast<const typename Pair<R>::type*>(rs + 2 * i);
 #pragma unroll
@@ -592,7 +606,7 @@ __global__ void __launch_bounds__(kQuadThreads) k_yzq_delayed(const cplx<R>* __r
         }
 #pragma unroll
         for (int r = 0; r < PER; ++r) {
-            const int i = c0 + threadIdx.x + r * kQuadThreads;
+            const int i = c0 + threadIdx.x + r * kDelayThreads;
             if (i < PAIRS) {
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
@@ -603,20 +617,18 @@ __global__ void __launch_bounds__(kQuadThreads) k_yzq_delayed(const cplx<R>* __r
         }
     }
     __syncthreads();
-    if (lane < N) {
+    const int i = threadIdx.x;
+    if (i < 4 * N) {
+        const int q = i / N, c = i - q * N;
         cplx<R> u[N];
-        tile_col<R, N>(t, lane, u, false);
+        tile_col<R, N>(qtile<R, N>(t0, q), c, u, false);
         dft_small<R, N>(u, true);
-        if (pz) {
-#pragma unroll
-            for (int j = 1; j < N; ++j) u[j] = u[j] * w2n<R, N>(j, true);
-        }
-        tile_col<R, N>(t, lane, u, true);
+        tile_col<R, N>(qtile<R, N>(t0, q), c, u, true);
     }
     __syncthreads();
-    quad_rows_inverse<R, N>(t, lane, py);
+    quad_rows_inverse<R, N>(t0, twz);
     __syncthreads();
-    quad_sum_store<R, N>(t0, A + ((size_t)bc * Lx + kx) * (size_t)(N * N));
+    quad_sum_store<R, N>(t0, A + ((size_t)bc * Lx + kx) * (size_t)(N * N), twy);
 }
 
 template <typename R>

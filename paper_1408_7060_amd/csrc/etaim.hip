@@ -327,10 +327,11 @@ struct Ops {
         if (c->yz_engine == 1) {
             const cplx<R>* G = ghat(c) + (size_t)m * 2 * c->gfold;
             const size_t lds = quad_lds(c);
+            grid = dim3(4 * c->B, g.L[0]);
             switch (quad_n(c)) {
-                case 16: hipLaunchKernelGGL((k_yzq_green<R, 16>), grid, dim3(kQuadThreads), lds, c->stream, A(c), G, g, conj, gate); break;
-                case 24: hipLaunchKernelGGL((k_yzq_green<R, 24>), grid, dim3(kQuadThreads), lds, c->stream, A(c), G, g, conj, gate); break;
-                case 48: hipLaunchKernelGGL((k_yzq_green<R, 48>), grid, dim3(kQuadThreads), lds, c->stream, A(c), G, g, conj, gate); break;
+                case 16: hipLaunchKernelGGL((k_yzq_green<R, 16>), grid, dim3(kQuadThreads), lds, c->stream, A(c), G, tw(c, 1), tw(c, 2), g, conj, gate); break;
+                case 24: hipLaunchKernelGGL((k_yzq_green<R, 24>), grid, dim3(kQuadThreads), lds, c->stream, A(c), G, tw(c, 1), tw(c, 2), g, conj, gate); break;
+                case 48: hipLaunchKernelGGL((k_yzq_green<R, 48>), grid, dim3(kQuadThreads), lds, c->stream, A(c), G, tw(c, 1), tw(c, 2), g, conj, gate); break;
                 default: return fail(ETAIM_EUNSUPPORTED, "register plane kernels need N_y = N_z in {16, 24, 48}");
             }
             HIPCHK(hipGetLastError());
@@ -374,14 +375,14 @@ struct Ops {
             Trace t(c, ETAIM_K_YZ_DELAYED,
                     nm * (4.0 * c->B * c->Np * s + 2.0 * c->gfold * s) + 4.0 * c->B * g.L[0] * g.N[2] * g.N[1] * s);
             if (c->yz_engine == 1) {
-                const dim3 grid(g.L[0], 4 * c->B);
+                const dim3 grid(4 * c->B, g.L[0]);
                 const size_t lds = quad_lds(c);
                 const cplx<R>* rg = (const cplx<R>*)ring(c);
                 const int ng = c->st.ng;
                 switch (quad_n(c)) {
-                    case 16: hipLaunchKernelGGL((k_yzq_delayed<R, 16>), grid, dim3(kQuadThreads), lds, c->stream, rg, ghat(c), A(c), g, ng, cur, nm, conj); break;
-                    case 24: hipLaunchKernelGGL((k_yzq_delayed<R, 24>), grid, dim3(kQuadThreads), lds, c->stream, rg, ghat(c), A(c), g, ng, cur, nm, conj); break;
-                    case 48: hipLaunchKernelGGL((k_yzq_delayed<R, 48>), grid, dim3(kQuadThreads), lds, c->stream, rg, ghat(c), A(c), g, ng, cur, nm, conj); break;
+                    case 16: hipLaunchKernelGGL((k_yzq_delayed<R, 16>), grid, dim3(kDelayThreads), lds, c->stream, rg, ghat(c), A(c), tw(c, 1), tw(c, 2), g, ng, cur, nm, conj); break;
+                    case 24: hipLaunchKernelGGL((k_yzq_delayed<R, 24>), grid, dim3(kDelayThreads), lds, c->stream, rg, ghat(c), A(c), tw(c, 1), tw(c, 2), g, ng, cur, nm, conj); break;
+                    case 48: hipLaunchKernelGGL((k_yzq_delayed<R, 48>), grid, dim3(kDelayThreads), lds, c->stream, rg, ghat(c), A(c), tw(c, 1), tw(c, 2), g, ng, cur, nm, conj); break;
                     default: return fail(ETAIM_EUNSUPPORTED, "register plane kernels need N_y = N_z in {16, 24, 48}");
                 }
             } else
@@ -404,13 +405,13 @@ struct Ops {
             const double s = sizeof(cplx<R>);
             Trace t(c, ETAIM_K_YZ_COMMIT, 4.0 * c->B * g.L[0] * g.N[2] * g.N[1] * s + 4.0 * c->B * c->Np * s);
             if (c->yz_engine == 1) {
-                const dim3 grid(g.L[0], 4 * c->B);
+                const dim3 grid(4 * c->B, g.L[0]);
                 const size_t lds = quad_lds(c);
                 const cplx<R>* a = (const cplx<R>*)A(c);
                 switch (quad_n(c)) {
-                    case 16: hipLaunchKernelGGL((k_yzq_commit<R, 16>), grid, dim3(kQuadThreads), lds, c->stream, a, slot, g); break;
-                    case 24: hipLaunchKernelGGL((k_yzq_commit<R, 24>), grid, dim3(kQuadThreads), lds, c->stream, a, slot, g); break;
-                    case 48: hipLaunchKernelGGL((k_yzq_commit<R, 48>), grid, dim3(kQuadThreads), lds, c->stream, a, slot, g); break;
+                    case 16: hipLaunchKernelGGL((k_yzq_commit<R, 16>), grid, dim3(kQuadThreads), lds, c->stream, a, slot, tw(c, 1), tw(c, 2), g); break;
+                    case 24: hipLaunchKernelGGL((k_yzq_commit<R, 24>), grid, dim3(kQuadThreads), lds, c->stream, a, slot, tw(c, 1), tw(c, 2), g); break;
+                    case 48: hipLaunchKernelGGL((k_yzq_commit<R, 48>), grid, dim3(kQuadThreads), lds, c->stream, a, slot, tw(c, 1), tw(c, 2), g); break;
                     default: return fail(ETAIM_EUNSUPPORTED, "register plane kernels need N_y = N_z in {16, 24, 48}");
                 }
             } else

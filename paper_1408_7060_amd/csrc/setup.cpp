@@ -26,6 +26,9 @@
 
 #include "context.hpp"
 
+// host set-up keeps separate roundings (no contraction into fused multiply-adds)
+#pragma clang fp contract(off)
+
 namespace etaim {
 
 namespace {
