@@ -137,21 +137,32 @@ __global__ void __launch_bounds__(256) k_anterp(const cplx<R>* __restrict__ xs, 
     for (int b = 0; b < kAntCols; ++b)
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[b][c] = cplx<R>{0, 0};
+    // entries in groups of four with their loads issued together (the
+    // entry -> basis -> column chain is two dependent loads deep)
+    int e = nptr[n];
     const int e1 = nptr[n + 1];
-#pragma unroll 2
-    for (int e = nptr[n]; e < e1; ++e) {
-        const int k = nk[e];
-        R w[4];
+    for (; e < e1; e += 4) {
+        int k[4];
+        R w[4][4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) w[c] = nw[4 * (size_t)e + c];
-        const cplx<R>* xk = xs + (size_t)k * B + b0;
+        for (int u = 0; u < 4; ++u) {
+            const bool live = e + u < e1;
+            k[u] = live ? nk[e + u] : 0;
 #pragma unroll
-        for (int b = 0; b < kAntCols; ++b)
-            if (b < nb) {
-                const cplx<R> v = xk[b];
+            for (int c = 0; c < 4; ++c) w[u][c] = live ? nw[4 * (size_t)(e + u) + c] : (R)0;
+        }
+        cplx<R> v[4][kAntCols];
 #pragma unroll
-                for (int c = 0; c < 4; ++c) acc[b][c] += w[c] * v;
-            }
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int b = 0; b < kAntCols; ++b) v[u][b] = b < nb ? xs[(size_t)k[u] * B + b0 + b] : cplx<R>{0, 0};
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (e + u < e1)
+#pragma unroll
+                for (int b = 0; b < kAntCols; ++b)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) acc[b][c] += w[u][c] * v[u][b];
     }
 #pragma unroll
     for (int b = 0; b < kAntCols; ++b)
@@ -638,18 +649,26 @@ __device__ __forceinline__ R wave_sum(R v) {
     return v;
 }
 
-// Interpolation + near-zone SpMV, one wavefront per basis k.
+// Interpolation + near-zone SpMV, one wavefront per basis k, all columns b.
 // mode 0 (matvec):  y[b][k] = sum_c sum_j L[k][c][j] P[bc][node_j]
-//                              + sum_e val[e][m] (dinv x)[b][col_e]
+//                              + sum_e val[e][m] xr[col_e][b]
 // mode 1 (delayed): y[b][k] = V[b][k] - (interp(P) + sum_{m=1}^{nmh}
-//                              val[e][m] hist[(cur-m) mod mn][b][col_e])
+//                              val[e][m] hist[(cur-m) mod mn][col_e][b])
+// xr = the scaled columns dinv . x and hist the current history, both in
+// the working precision with the columns of one basis contiguous ([ns][B]).
+// Lane j of the wave owns stencil node j (and near-zone entries e0 + j,
+// e0 + j + 64, ...) for up to kInterpCols columns at once; the 64-lane sums
+// of all columns then take one transposing butterfly (each exchange halves
+// the columns a lane carries) instead of one full reduction per column.
+constexpr int kInterpCols = 32;
+
 template <typename R>
 __global__ void __launch_bounds__(256) k_interp_near(
     const cplx<R>* __restrict__ P, const R* __restrict__ lam, const int* __restrict__ i0,
     const int* __restrict__ order, GridDims g,
     const int* __restrict__ rowptr, const int* __restrict__ col, const cplx<R>* __restrict__ val, int mv,
-    const zd* __restrict__ x, const zd* __restrict__ dinv, int m, const zd* __restrict__ hist, int mn, int cur,
-    int nmh, const zd* __restrict__ V, zd* __restrict__ y, int ns, int mode, int conj_v, int conj_x,
+    const cplx<R>* __restrict__ xr, int m, const cplx<R>* __restrict__ hist, int mn, int cur,
+    int nmh, const zd* __restrict__ V, zd* __restrict__ y, int ns, int mode, int conj_v,
     const int* __restrict__ gate) {
     if (gated_off(gate)) return;
     const int lane = threadIdx.x & 63;
@@ -661,7 +680,7 @@ __global__ void __launch_bounds__(256) k_interp_near(
     const int slot = lb * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (slot >= ns) return;
     const int k = order[slot];
-    const int Nx = g.N[0], Ny = g.N[1], Nz = g.N[2];
+    const int Nx = g.N[0], Ny = g.N[1], Nz = g.N[2], B = g.B;
     const size_t N = (size_t)Nx * Ny * Nz;
     // P is [bc][z][x][y]: lanes take the stencil with y fastest (32-byte runs)
     const int jy = lane & 3, jx = (lane >> 2) & 3, jz = lane >> 4, j = jx + 4 * jy + 16 * jz;
@@ -670,20 +689,28 @@ __global__ void __launch_bounds__(256) k_interp_near(
 #pragma unroll
     for (int c = 0; c < 4; ++c) w[c] = lam[(size_t)k * 256 + 64 * c + j];
     const int e0 = rowptr[k], e1 = rowptr[k + 1];
-    for (int b = 0; b < g.B; ++b) {
-        cplx<R> acc{0, 0};
+    for (int b0 = 0; b0 < B; b0 += kInterpCols) {
+        const int nb = min(kInterpCols, B - b0);
+        cplx<R> acc[kInterpCols];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc += w[c] * P[((size_t)b * 4 + c) * N + node];
+        for (int bb = 0; bb < kInterpCols; ++bb) {
+            acc[bb] = cplx<R>{0, 0};
+            if (bb < nb) {
+                const cplx<R>* pb = P + (size_t)(b0 + bb) * 4 * N + node;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[bb] += w[c] * pb[(size_t)c * N];
+            }
+        }
         for (int e = e0 + lane; e < e1; e += 64) {
             const int cc = col[e];
             if (mode == 0) {
                 if (m <= mv - 1) {
                     cplx<R> v = val[(size_t)e * mv + m];
                     if (conj_v) v.y = -v.y;
-                    zd xv = x[(size_t)b * ns + cc];
-                    if (conj_x) xv.y = -xv.y;
-                    if (dinv) xv = xv * dinv[cc];
-                    acc += v * to_r<R>(xv);
+                    const cplx<R>* xc = xr + (size_t)cc * B + b0;
+#pragma unroll
+                    for (int bb = 0; bb < kInterpCols; ++bb)
+                        if (bb < nb) acc[bb] += v * xc[bb];
                 }
             } else {
                 for (int mm = 1; mm <= nmh; ++mm) {
@@ -691,17 +718,35 @@ __global__ void __launch_bounds__(256) k_interp_near(
                     if (s < 0) s += mn;
                     cplx<R> v = val[(size_t)e * mv + mm];
                     if (conj_v) v.y = -v.y;
-                    acc += v * to_r<R>(hist[((size_t)s * g.B + b) * ns + cc]);
+                    const cplx<R>* hc = hist + ((size_t)s * ns + cc) * B + b0;
+#pragma unroll
+                    for (int bb = 0; bb < kInterpCols; ++bb)
+                        if (bb < nb) acc[bb] += v * hc[bb];
                 }
             }
         }
-        const R re = wave_sum<R>(acc.x), im = wave_sum<R>(acc.y);
-        if (lane == 0) {
-            const size_t o = (size_t)b * ns + k;
+        // transposing butterfly over lane bits 5..1: after the exchange over
+        // bit 2h a lane keeps h partial sums, those of the half its bit
+        // selects; finally bit 0 pairs up, and lane 2 bb + {0, 1} holds the
+        // full sum of column bb
+#pragma unroll
+        for (int h = kInterpCols / 2, bit = 32; h >= 1; h >>= 1, bit >>= 1) {
+            const bool up = (lane & bit) != 0;
+#pragma unroll
+            for (int i = 0; i < h; ++i) {
+                const cplx<R> keep = up ? acc[i + h] : acc[i];
+                const cplx<R> send = up ? acc[i] : acc[i + h];
+                acc[i] = keep + cplx<R>{__shfl_xor(send.x, bit, 64), __shfl_xor(send.y, bit, 64)};
+            }
+        }
+        const cplx<R> tot = acc[0] + cplx<R>{__shfl_xor(acc[0].x, 1, 64), __shfl_xor(acc[0].y, 1, 64)};
+        const int bb = lane >> 1;
+        if ((lane & 1) == 0 && bb < nb) {
+            const size_t o = (size_t)(b0 + bb) * ns + k;
             if (mode == 0)
-                y[o] = zd{(double)re, (double)im};
+                y[o] = zd{(double)tot.x, (double)tot.y};
             else
-                y[o] = zd{V[o].x - (double)re, V[o].y - (double)im};
+                y[o] = zd{V[o].x - (double)tot.x, V[o].y - (double)tot.y};
         }
     }
 }

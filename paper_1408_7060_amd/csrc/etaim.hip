@@ -74,7 +74,7 @@ struct etaim_ctx {
     // working-precision arrays (float or double)
     void *lam_r = nullptr, *nw_r = nullptr, *near_r = nullptr, *nearT_r = nullptr, *ghat_r = nullptr, *tw_r[3] = {};
     void *A = nullptr, *P = nullptr, *ring = nullptr;
-    zd* hist = nullptr;
+    zd* hist = nullptr;  // [mn][ns][B] in the working precision (sized for complex128)
     // Krylov (FP64)
     zd *Vk = nullptr, *w = nullptr, *h1 = nullptr, *h2 = nullptr, *H = nullptr, *sn = nullptr, *g = nullptr,
        *yv = nullptr, *xk = nullptr, *rhs = nullptr, *zero = nullptr;
@@ -352,9 +352,16 @@ struct Ops {
         Trace t(c, ETAIM_K_INTERP_NEAR,
                 4.0 * c->B * c->N3 * s + c->ns * (256.0 * sizeof(R) + 12.0) + (c->ns + 1) * 4.0 + c->nnz * 4.0 +
                     c->nnz * nvals * s + (mode == 0 ? nB * 16 : (nmh + 1) * nB * 16) + nB * 16);
+        cplx<R>* xs = (cplx<R>*)c->xs;
+        // the near zone reads the scaled columns [ns][B]; the register x stage
+        // has already written them for this x
+        if (mode == 0 && (c->x_engine != 1 || conj_x))
+            hipLaunchKernelGGL(k_prescale<R>, dim3(blocks_for(nB)), dim3(256), 0, c->stream, x, dinv, xs, c->ns, c->B,
+                               conj_x, gate);
         hipLaunchKernelGGL(k_interp_near<R>, grid, dim3(64 * wpb), 0, c->stream, (const cplx<R>*)P(c),
-                           (const R*)c->lam_r, c->i0, c->korder, c->gd, c->rowptr, c->col, nearv(c, conj_v), c->mv, x, dinv, m,
-                           c->hist, std::max(c->st.mn, 1), cur, nmh, V, y, c->ns, mode, conj_v, conj_x, gate);
+                           (const R*)c->lam_r, c->i0, c->korder, c->gd, c->rowptr, c->col, nearv(c, conj_v), c->mv,
+                           (const cplx<R>*)xs, m, (const cplx<R>*)c->hist, std::max(c->st.mn, 1), cur, nmh, V, y,
+                           c->ns, mode, conj_v, gate);
         HIPCHK(hipGetLastError());
         return ETAIM_OK;
     }
@@ -421,8 +428,10 @@ struct Ops {
         HIPCHK(hipGetLastError());
         if (c->st.mn >= 1) {
             const size_t n = (size_t)c->B * c->ns;
-            HIPCHK(hipMemcpyAsync(c->hist + (size_t)(cur % c->st.mn) * n, x, n * sizeof(zd),
-                                  hipMemcpyDeviceToDevice, c->stream));
+            // current history slot in the working precision, columns of a basis contiguous
+            hipLaunchKernelGGL(k_prescale<R>, dim3(blocks_for(n)), dim3(256), 0, c->stream, x, nullptr,
+                               (cplx<R>*)c->hist + (size_t)(cur % c->st.mn) * n, c->ns, c->B, 0, nullptr);
+            HIPCHK(hipGetLastError());
         }
         return ETAIM_OK;
     }
