@@ -82,13 +82,6 @@ __global__ void __launch_bounds__(kPlaneThreads) k_fwdx_gather(
 
 __device__ __forceinline__ int fold(int k, int n2) { return k <= n2 / 2 ? k : n2 - k; }
 
-// w_{2N}^n (compile-time n after unrolling)
-template <typename R, int N>
-__device__ __forceinline__ cplx<R> w2n(int n, bool inverse) {
-    double c, s;
-    w96((96 / (2 * N)) * n, c, s);
-    return cplx<R>{(R)c, (R)(inverse ? -s : s)};
-}
 
 // ---------------------------------------------------------------------------
 // Register x stage (N_x = N with a register codelet, padded length 2N).  The
@@ -189,7 +182,7 @@ __global__ void __launch_bounds__(256) k_xfwd(const cplx<R>* __restrict__ q, cpl
     for (int x = 0; x < N; ++x) u[x] = src[(size_t)x * Ny];
     if (p) {
 #pragma unroll
-        for (int x = 1; x < N; ++x) u[x] = u[x] * w2n<R, N>(x, false);
+        for (int x = 1; x < N; ++x) u[x] = tw96_mul<R>(u[x], (96 / (2 * N)) * x, false);
     }
     dft_small<R, N>(u, false);
     cplx<R>* dst = A + (size_t)bc * 2 * N * nl + (size_t)p * nl + line;
@@ -215,7 +208,7 @@ __global__ void __launch_bounds__(256) k_xinv(const cplx<R>* __restrict__ A, cpl
     dft_small<R, N>(u, true);
     if (p) {
 #pragma unroll
-        for (int x = 1; x < N; ++x) u[x] = u[x] * w2n<R, N>(x, true);
+        for (int x = 1; x < N; ++x) u[x] = tw96_mul<R>(u[x], (96 / (2 * N)) * x, true);
     }
     const int z = line / Ny, y = line - z * Ny;
     cplx<R>* dst = P + (size_t)bc * N * nl + (size_t)z * N * Ny + y;
@@ -435,7 +428,7 @@ __device__ __forceinline__ void quad_stage(cplx<R>* t0, const cplx<R>* __restric
         const int z = e / N, y = e - z * N, o = z * (N + 1) + y;
         const cplx<R> v = src[e];
         t0[o] = v;
-        qtile<R, N>(t0, 1)[o] = v * twy[y];
+        qtile<R, N>(t0, 1)[o] = cmul_fma(v, twy[y]);
     }
 }
 
@@ -452,7 +445,7 @@ __device__ __forceinline__ void quad_rows_forward(cplx<R>* t0, const cplx<R>* __
         tile_row<R, N>(qtile<R, N>(t0, py), z, u, true);
         const cplx<R> s = twz[z];
 #pragma unroll
-        for (int j = 0; j < N; ++j) u[j] = u[j] * s;
+        for (int j = 0; j < N; ++j) u[j] = cmul_fma(u[j], s);
         tile_row<R, N>(qtile<R, N>(t0, 2 + py), z, u, true);
     }
 }
@@ -469,7 +462,7 @@ __device__ __forceinline__ void quad_rows_inverse(cplx<R>* t0, const cplx<R>* __
         const cplx<R> s = conjz(twz[z]);
         const cplx<R>* r1 = qtile<R, N>(t0, 2 + py) + z * (N + 1);
 #pragma unroll
-        for (int j = 0; j < N; ++j) u[j] += r1[j] * s;
+        for (int j = 0; j < N; ++j) u[j] += cmul_fma(r1[j], s);
         dft_small<R, N>(u, true);
         tile_row<R, N>(qtile<R, N>(t0, py), z, u, true);
     }
@@ -481,7 +474,7 @@ __device__ __forceinline__ void quad_sum_store(cplx<R>* t0, cplx<R>* __restrict_
                                                const cplx<R>* __restrict__ twy) {
     for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
         const int z = e / N, y = e - z * N, o = z * (N + 1) + y;
-        out[e] = t0[o] + qtile<R, N>(t0, 1)[o] * conjz(twy[y]);
+        out[e] = t0[o] + cmul_fma(qtile<R, N>(t0, 1)[o], conjz(twy[y]));
     }
 }
 
@@ -518,7 +511,7 @@ __global__ void __launch_bounds__(kQuadThreads) k_yzq_green(cplx<R>* __restrict_
         tile_col<R, N>(qtile<R, N>(t0, q), c, u, false);
         dft_small<R, N>(u, false);
 #pragma unroll
-        for (int j = 0; j < N; ++j) u[j] = u[j] * quad_green<R, N>(Gk, j, c, py, pz, conj_g);
+        for (int j = 0; j < N; ++j) u[j] = cmul_fma(u[j], quad_green<R, N>(Gk, j, c, py, pz, conj_g));
         dft_small<R, N>(u, true);
         tile_col<R, N>(qtile<R, N>(t0, q), c, u, true);
     }
@@ -610,7 +603,7 @@ __global__ void __launch_bounds__(kDelayThreads) k_yzq_delayed(const cplx<R>* __
                     for (int h = 0; h < 2; ++h) {
                         cplx<R> gv = Gm[gi[r][h]];
                         if (conj_g) gv.y = -gv.y;
-                        acc[r][h] += gv * v[h];
+                        acc[r][h] += cmul_fma(gv, v[h]);
                     }
                 }
             }

@@ -36,6 +36,12 @@ inline Radix make_radix(int L) {
     return p;
 }
 
+// a * b with two products and two fused multiply-adds
+template <typename R>
+__device__ __forceinline__ cplx<R> cmul_fma(cplx<R> a, cplx<R> b) {
+    return cplx<R>{fma(a.x, b.x, -(a.y * b.y)), fma(a.x, b.y, a.y * b.x)};
+}
+
 template <typename R>
 __device__ __forceinline__ cplx<R> mul_i(cplx<R> a, bool inverse) {
     // multiply by -i (forward) or +i (inverse)
@@ -118,6 +124,45 @@ __device__ __forceinline__ void w96(int m, double& c, double& s) {
 template <typename R, int RAD>
 __device__ __forceinline__ void dft_small(cplx<R> (&u)[RAD], bool inverse);
 
+// v * exp(-+2 pi i m / 48) for a compile-time m (after unrolling): exact
+// swaps and negations at multiples of 90 degrees, sqrt(1/2) (a +- b) at odd
+// multiples of 45 degrees, otherwise two products and two fused
+// multiply-adds
+template <typename R>
+__device__ __forceinline__ cplx<R> tw48_mul(cplx<R> v, int m, bool inverse) {
+    m %= 48;
+    if (inverse) m = (48 - m) % 48;  // conj(w^m) = w^(48 - m)
+    const R h = (R)0.70710678118654752440;
+    switch (m) {
+        case 0: return v;
+        case 12: return cplx<R>{v.y, -v.x};
+        case 24: return cplx<R>{-v.x, -v.y};
+        case 36: return cplx<R>{-v.y, v.x};
+        case 6: return cplx<R>{h * (v.x + v.y), h * (v.y - v.x)};
+        case 18: return cplx<R>{h * (v.y - v.x), -h * (v.x + v.y)};
+        case 30: return cplx<R>{-h * (v.x + v.y), h * (v.x - v.y)};
+        case 42: return cplx<R>{h * (v.x - v.y), h * (v.x + v.y)};
+        default: {
+            double c, s;
+            w48(m, c, s);
+            const R cr = (R)c, sr = (R)s;
+            return cplx<R>{fma(v.x, cr, -(v.y * sr)), fma(v.x, sr, v.y * cr)};
+        }
+    }
+}
+
+// v * exp(-+2 pi i m / 96) for a compile-time m, exact at multiples of 90
+// degrees and sqrt(1/2) (a +- b) at odd multiples of 45 degrees
+template <typename R>
+__device__ __forceinline__ cplx<R> tw96_mul(cplx<R> v, int m, bool inverse) {
+    m %= 96;
+    if (m % 2 == 0) return tw48_mul<R>(v, m / 2, inverse);
+    if (inverse) m = 96 - m;
+    double c, s;
+    w96(m, c, s);
+    return cmul_fma(v, cplx<R>{(R)c, (R)s});
+}
+
 // composite codelet of size N1*N2 in registers: X[k2 + N2 k1] =
 // sum_n1 W_N1^{n1 k1} W_N^{n1 k2} sum_n2 W_N2^{n2 k2} x[n1 + N1 n2]
 template <typename R, int N1, int N2>
@@ -132,14 +177,7 @@ __device__ __forceinline__ void dft_composite(cplx<R> (&u)[N1 * N2], bool invers
         dft_small<R, N2>(v, inverse);
 #pragma unroll
         for (int k2 = 0; k2 < N2; ++k2) {
-            if (n1 * k2 != 0) {
-                double c, s;
-                w48((48 / N) * n1 * k2, c, s);
-                const cplx<R> w{(R)c, (R)(inverse ? -s : s)};
-                y[n1][k2] = v[k2] * w;
-            } else {
-                y[n1][k2] = v[k2];
-            }
+            y[n1][k2] = tw48_mul<R>(v[k2], (48 / N) * n1 * k2, inverse);
         }
     }
 #pragma unroll
@@ -163,11 +201,11 @@ __device__ __forceinline__ void dft_small(cplx<R> (&u)[RAD], bool inverse) {
         const R s = inverse ? (R)0.86602540378443864676 : (R)-0.86602540378443864676;
         const cplx<R> t = u[1] + u[2];
         const cplx<R> d = u[1] - u[2];
-        const cplx<R> m = u[0] - (R)0.5 * t;
-        const cplx<R> id{-s * d.y, s * d.x};  // i s d
+        const cplx<R> m{fma((R)-0.5, t.x, u[0].x), fma((R)-0.5, t.y, u[0].y)};
         u[0] = u[0] + t;
-        u[1] = m + id;
-        u[2] = m - id;
+        // m +- i s d
+        u[1] = cplx<R>{fma(-s, d.y, m.x), fma(s, d.x, m.y)};
+        u[2] = cplx<R>{fma(s, d.y, m.x), fma(-s, d.x, m.y)};
     } else if constexpr (RAD == 4) {
         const cplx<R> a = u[0] + u[2], b = u[0] - u[2];
         const cplx<R> c = u[1] + u[3], d = mul_i(u[1] - u[3], inverse);
