@@ -223,6 +223,11 @@ typedef struct {
     int32_t x_engine;        /* x stage: 0 LDS-staged lines with the anterpolation fused in,
                                 1 register-resident lines after a separate anterpolation
                                 (needs N_x in {16, 24, 48}) */
+    int32_t guess_order;     /* GMRES initial guess of step l: the polynomial through the last
+                                p solutions evaluated at step l, p <= guess_order chosen as the
+                                order that best predicted step l-1 (0: zero guess, 1: the
+                                previous solution, up to 4: cubic); the converged solution does
+                                not depend on it beyond the tolerance (default 4) */
     double apply_ms;         /* out: measured matvec time [ms] (0 if not measured) */
     double solve_ms;         /* out: measured GMRES solve of the tuning right-hand side [ms] (0 if not
                                 measured) */

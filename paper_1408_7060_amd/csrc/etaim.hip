@@ -80,6 +80,7 @@ struct etaim_ctx {
        *yv = nullptr, *xk = nullptr, *rhs = nullptr, *zero = nullptr;
     double *cs = nullptr, *nrm = nullptr, *beta = nullptr, *bnorm = nullptr, *resid = nullptr;
     int *active = nullptr, *jcnt = nullptr, *flag = nullptr;
+    double* perr = nullptr;  // extrapolation errors of the step just solved (+ block partials)
     int* flag_h = nullptr;
     // batched-GMRES schedule: steps per host check, captured Arnoldi steps
     int sync_every = 1;
@@ -89,6 +90,7 @@ struct etaim_ctx {
     // launch shapes (0 = automatic); the autotuner sets them
     int gather_rows_t = 0, lines_x_t = 0, interp_waves = 4;
     int yz_engine = 0;  // 0: LDS plane kernels, 1: register quadrant kernels
+    int guess_order = 4;  // solutions extrapolated into a step's initial guess (0..4)
     int x_engine = 0;   // 0: LDS line kernels, 1: register line kernels
     void* xs = nullptr; // [ns][B] scaled columns for the register anterpolation
     hipEvent_t ev[4] = {};
@@ -643,6 +645,8 @@ int march_impl(etaim_ctx* c, const zd* V, zd* I, etaim_stats* st, bool adjoint, 
     double maxres = 0, ms_rhs = 0, ms_solve = 0, ms_commit = 0;
     bool nonfinite = false;
     std::vector<double> nrm_h(B);
+    double perr_h[4] = {0, 0, 0, 0};
+    int guess_p = c->guess_order == 0 ? 0 : 1;  // extrapolation order of the next initial guess
     for (int r = 0; r < nt; ++r) {
         const int l = adjoint ? nt - 1 - r : r;
         const zd* Vl = V + (size_t)l * nB;
@@ -654,12 +658,11 @@ int march_impl(etaim_ctx* c, const zd* V, zd* I, etaim_stats* st, bool adjoint, 
             HIPCHK(hipMemcpyAsync(c->rhs, Vl, nB * sizeof(zd), hipMemcpyDeviceToDevice, c->stream));
         }
         HIPCHK(hipEventRecord(c->ev[1], c->stream));
-        if (r >= 1) {
-            const zd* Ip = I + (size_t)(adjoint ? l + 1 : l - 1) * nB;
-            HIPCHK(hipMemcpyAsync(c->xk, Ip, nB * sizeof(zd), hipMemcpyDeviceToDevice, c->stream));
-        } else {
-            HIPCHK(hipMemsetAsync(c->xk, 0, nB * sizeof(zd), c->stream));
-        }
+        // initial guess: extrapolation of the last p solutions, p the order
+        // that best predicted the previous step (at most guess_order)
+        hipLaunchKernelGGL(k_extrap, dim3(blocks_for(nB)), dim3(256), 0, c->stream, (const zd*)I, c->xk, nB,
+                           (long long)l, adjoint ? -1 : 1, std::min(r, guess_p));
+        HIPCHK(hipGetLastError());
         StepResult sr;
         CHK(gmres<R>(c, c->rhs, c->xk, conj, sr));
         HIPCHK(hipEventRecord(c->ev[2], c->stream));
@@ -667,9 +670,24 @@ int march_impl(etaim_ctx* c, const zd* V, zd* I, etaim_stats* st, bool adjoint, 
         CHK(Ops<R>::commit(c, r, c->xk));
         hipLaunchKernelGGL(k_norm, dim3(B), dim3(256), 0, c->stream, c->xk, c->nrm, ns, nullptr);
         HIPCHK(hipMemcpyAsync(nrm_h.data(), c->nrm, B * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        const int pmax = std::min(r, c->guess_order);
+        if (pmax >= 2) {
+            hipLaunchKernelGGL(k_pred_err, dim3(kPredBlocks), dim3(256), 0, c->stream, (const zd*)I, nB,
+                               (long long)l, adjoint ? -1 : 1, pmax, c->perr + 4);
+            hipLaunchKernelGGL(k_pred_err_sum, dim3(1), dim3(256), 0, c->stream, (const double*)(c->perr + 4),
+                               kPredBlocks, c->perr);
+            HIPCHK(hipMemcpyAsync(perr_h, c->perr, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        }
         HIPCHK(hipEventRecord(c->ev[3], c->stream));
         HIPCHK(hipEventSynchronize(c->ev[3]));
         CHK(trace_flush(c));
+        if (pmax >= 2) {
+            guess_p = 1;
+            for (int p = 2; p <= pmax; ++p)
+                if (perr_h[p - 1] < perr_h[guess_p - 1]) guess_p = p;
+        } else {
+            guess_p = c->guess_order == 0 ? 0 : 1;
+        }
         float t01 = 0, t12 = 0, t23 = 0;
         HIPCHK(hipEventElapsedTime(&t01, c->ev[0], c->ev[1]));
         HIPCHK(hipEventElapsedTime(&t12, c->ev[1], c->ev[2]));
@@ -957,6 +975,7 @@ int device_setup(etaim_ctx* c) {
     CHK(c->alloc(c->active, c->B));
     CHK(c->alloc(c->jcnt, c->B));
     CHK(c->alloc(c->flag, 8));
+    CHK(c->alloc(c->perr, 4 + 4 * kPredBlocks));
     HIPCHK(hipHostMalloc((void**)&c->flag_h, 8 * sizeof(int), hipHostMallocDefault));
     for (auto& e : c->ev) HIPCHK(hipEventCreate(&e));
     HIPCHK(hipStreamSynchronize(c->stream));

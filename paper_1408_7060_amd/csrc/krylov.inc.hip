@@ -218,6 +218,63 @@ __global__ void k_copy_conj(const zd* __restrict__ in, zd* __restrict__ out, siz
     }
 }
 
+// Initial guess of a time step: x = sum_{i=1}^{p} a_i I_{l - dir i}, the
+// polynomial through the last p solutions evaluated one step ahead
+// (a_i = (-1)^(i+1) C(p, i)); p = 0 gives zero.  The march picks p as the
+// order whose prediction of the step just solved was closest.
+__global__ void k_extrap(const zd* __restrict__ I, zd* __restrict__ x, size_t nB, long long l, int dir, int p) {
+    const double a[4][4] = {{1, 0, 0, 0}, {2, -1, 0, 0}, {3, -3, 1, 0}, {4, -6, 4, -1}};
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < nB; e += (size_t)gridDim.x * blockDim.x) {
+        zd acc{0, 0};
+        for (int i = 1; i <= p; ++i) {
+            const zd v = I[(size_t)(l - (long long)dir * i) * nB + e];
+            acc.x += a[p - 1][i - 1] * v.x;
+            acc.y += a[p - 1][i - 1] * v.y;
+        }
+        x[e] = acc;
+    }
+}
+
+// Squared error of each extrapolation order p = 1..pmax at the step just
+// solved, ||I_l - sum_i a_i I_{l - dir i}||^2: per-block partial sums
+// part[blk][p-1] (grid-stride), then k_pred_err_sum adds the blocks in
+// order (deterministic).
+constexpr int kPredBlocks = 256;
+__global__ void __launch_bounds__(256) k_pred_err(const zd* __restrict__ I, size_t nB, long long l, int dir,
+                                                  int pmax, double* __restrict__ part) {
+    __shared__ double sh[256];
+    const double a[4][4] = {{1, 0, 0, 0}, {2, -1, 0, 0}, {3, -3, 1, 0}, {4, -6, 4, -1}};
+    double s[4] = {0, 0, 0, 0};
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < nB; e += (size_t)gridDim.x * blockDim.x) {
+        const zd x = I[(size_t)l * nB + e];
+        zd v[4];
+        for (int i = 1; i <= pmax; ++i) v[i - 1] = I[(size_t)(l - (long long)dir * i) * nB + e];
+        for (int p = 1; p <= pmax; ++p) {
+            double rx = x.x, ry = x.y;
+            for (int i = 1; i <= p; ++i) {
+                rx -= a[p - 1][i - 1] * v[i - 1].x;
+                ry -= a[p - 1][i - 1] * v[i - 1].y;
+            }
+            s[p - 1] += rx * rx + ry * ry;
+        }
+    }
+    for (int p = 0; p < 4; ++p) {
+        const double t = block_sum256(s[p], sh);
+        if (threadIdx.x == 0) part[(size_t)blockIdx.x * 4 + p] = t;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_pred_err_sum(const double* __restrict__ part, int nblk,
+                                                      double* __restrict__ err) {
+    __shared__ double sh[256];
+    for (int p = 0; p < 4; ++p) {
+        double s = 0;
+        for (int b = threadIdx.x; b < nblk; b += 256) s += part[(size_t)b * 4 + p];
+        const double t = block_sum256(s, sh);
+        if (threadIdx.x == 0) err[p] = t;
+    }
+}
+
 __global__ void k_fill_int(int* __restrict__ p, int n, int v, const int* __restrict__ gate = nullptr) {
     if (gated_off(gate)) return;
     for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = v;

@@ -176,3 +176,29 @@ def test_autotune_keeps_the_operator_and_caches(torch, tmp_path, name, prec, tol
     assert rel(P2.apply_z(0, xd).cpu().numpy(), ref) <= tol
     P2.close()
     assert rel(I1.cpu().numpy(), I0.cpu().numpy()) <= (1e-4 if prec else 1e-10)
+
+
+@pytest.mark.parametrize("name,prec,tol,bound", [(W.SPHERE_L2.name, 0, 1e-13, 1e-11),
+                                                 (W.SPHERE_L3.name, 1, 1e-6, 1e-5)])
+def test_initial_guess_order(torch, name, prec, tol, bound):
+    """The extrapolated initial guess changes the march only within the
+    GMRES tolerance; the adaptive order (the one that best predicted the
+    previous step) takes at most a few percent more iterations than the
+    previous solution as the guess, also where the envelope is coarsely
+    sampled and extrapolation does not pay."""
+    V = _excitation(name, 24, 2, 41)
+    out = {}
+    for order in (0, 1, 4):
+        P = gpu_problem(name, precision=prec, tol=tol, nt=24, batch=2, flags=F_CONTINUE_ON_NOCONV)
+        d = P.tuning()
+        d["guess_order"] = order
+        P.set_tuning(d)
+        I, st = P.march(torch.from_numpy(np.ascontiguousarray(V)).cuda())
+        out[order] = (I.cpu().numpy(), st["total_iters"])
+        P.close()
+        _say("guess order", order, "iterations", st["total_iters"])
+    ref = out[1][0]
+    for order in (0, 4):
+        e = float(np.linalg.norm(out[order][0] - ref) / np.linalg.norm(ref))
+        assert e <= bound, (order, e)
+    assert out[4][1] <= 1.05 * out[1][1]
