@@ -453,8 +453,8 @@ __device__ __forceinline__ void quad_rows_forward(cplx<R>* t0, const cplx<R>* __
 // inverse rows: task (py, z): row z of tile py plus conj(w_{2N}^{z}) times
 // row z of tile 2 + py, N-point inverse DFT, back into tile py
 template <typename R, int N>
-__device__ __forceinline__ void quad_rows_inverse(cplx<R>* t0, const cplx<R>* __restrict__ twz) {
-    const int i = threadIdx.x;
+__device__ __forceinline__ void quad_rows_inverse(cplx<R>* t0, const cplx<R>* __restrict__ twz,
+                                                  int i = threadIdx.x) {
     if (i < 2 * N) {
         const int py = i / N, z = i - py * N;
         cplx<R> u[N];
@@ -471,8 +471,9 @@ __device__ __forceinline__ void quad_rows_inverse(cplx<R>* t0, const cplx<R>* __
 // out[z N + y] = tile0 + conj(w_{2N}^{y}) tile1 (the py = 1 post-twiddle)
 template <typename R, int N>
 __device__ __forceinline__ void quad_sum_store(cplx<R>* t0, cplx<R>* __restrict__ out,
-                                               const cplx<R>* __restrict__ twy) {
-    for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
+                                               const cplx<R>* __restrict__ twy, int tid = threadIdx.x,
+                                               int nth = blockDim.x) {
+    for (int e = tid; e < N * N; e += nth) {
         const int z = e / N, y = e - z * N, o = z * (N + 1) + y;
         out[e] = t0[o] + cmul_fma(qtile<R, N>(t0, 1)[o], conjz(twy[y]));
     }
@@ -546,13 +547,42 @@ __global__ void __launch_bounds__(kQuadThreads) k_yzq_commit(const cplx<R>* __re
     }
 }
 
+// inverse column and row transforms of the quadrant tiles and the quadrant
+// sum into one plane of A, by threads tid < nth of the block (every thread
+// of the block must call it: it synchronises the block)
+template <typename R, int N>
+__device__ __forceinline__ void quad_inverse_store(cplx<R>* t0, cplx<R>* __restrict__ out,
+                                                   const cplx<R>* __restrict__ twy, const cplx<R>* __restrict__ twz,
+                                                   int tid, int nth) {
+    if (tid < 4 * N) {
+        const int q = tid / N, c = tid - q * N;
+        cplx<R> u[N];
+        tile_col<R, N>(qtile<R, N>(t0, q), c, u, false);
+        dft_small<R, N>(u, true);
+        tile_col<R, N>(qtile<R, N>(t0, q), c, u, true);
+    }
+    __syncthreads();
+    quad_rows_inverse<R, N>(t0, twz, tid);
+    __syncthreads();
+    quad_sum_store<R, N>(t0, out, twy, tid, nth);
+}
+
+// tile position of point e of a quadrant-major plane
+template <int N>
+__device__ __forceinline__ int quad_tile_pos(int e) {
+    const int qq = e / (N * N), rr = e - qq * N * N;
+    return qq * N * (N + 1) + (rr / N) * (N + 1) + rr % N;
+}
+
 // Delayed-field y/z stage on the register path.  The k-space temporal sum
-// over the quadrant-major ring streams the history: the block's threads
-// own consecutive pairs of spectrum points of the plane (one vector load of
-// the ring per pair, coalesced), accumulate over m in registers and leave
-// the sums in the quadrant tiles; then the inverse column and row
-// transforms and the quadrant sum as in k_yzq_green.
-constexpr int kDelayThreads = 256;  // the streaming sum wants more loads in flight than 4N tasks
+// over the quadrant-major ring streams the history.  A block owns the two
+// planes (bc, kx) and (bc + 4, kx) of one kx and component, which share
+// every Green value: each Green load serves two ring loads.  The block's
+// 512 threads own consecutive pairs of spectrum points (one vector load of
+// the ring per pair and plane, coalesced) and accumulate over m in
+// registers; the sums go to two sets of quadrant tiles (150 KB in FP32),
+// and each half of the block then transforms one plane.
+constexpr int kDelayThreads = 512;
 
 template <typename R, int N>
 __global__ void __launch_bounds__(kDelayThreads) k_yzq_delayed(const cplx<R>* __restrict__ ring,
@@ -562,9 +592,92 @@ __global__ void __launch_bounds__(kDelayThreads) k_yzq_delayed(const cplx<R>* __
                                                               int cur, int nm, int conj_g) {
     extern __shared__ unsigned char smem_raw[];
     cplx<R>* t0 = reinterpret_cast<cplx<R>*>(smem_raw);
+    constexpr int NN = N * N, PAIRS = 4 * NN / 2, PER = 6, CHUNK = PER * kDelayThreads, TS = 4 * N * (N + 1);
+    // plane pair p: bc0 = 8 (p / 4) + p % 4 and bc0 + 4 (the same component c)
+    const int p = blockIdx.x, bc0 = 8 * (p >> 2) + (p & 3);
+    const int kx = blockIdx.y, Lx = g.L[0];
+    const int gx = g.N[0] + 1, gg = N + 1;
+    const size_t gsz = (size_t)2 * gx * gg * gg;
+    const size_t slot_sz = (size_t)4 * g.B * Lx * 4 * NN;
+    const size_t roff0 = ((size_t)bc0 * Lx + kx) * (size_t)(4 * NN);
+    const size_t roff1 = roff0 + (size_t)4 * Lx * (4 * NN);
+    const size_t goff = ((size_t)((bc0 & 3) == 3 ? 1 : 0) * gx + fold(kx, Lx)) * (size_t)(gg * gg);
+    for (int c0 = 0; c0 < PAIRS; c0 += CHUNK) {
+        // point pair i: points 2 i, 2 i + 1 of the plane's quadrant-major
+        // spectrum (N is even, so a pair never straddles a quadrant row)
+        int gi[PER][2];
+        cplx<R> acc0[PER][2], acc1[PER][2];
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            const int i = c0 + threadIdx.x + r * kDelayThreads;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int e = 2 * i + h, qq = e / NN, rr = e - qq * NN;
+                const int kz = 2 * (rr / N) + (qq >> 1), ky = 2 * (rr % N) + (qq & 1);
+                gi[r][h] = fold(kz, 2 * N) * gg + fold(ky, 2 * N);
+                acc0[r][h] = cplx<R>{0, 0};
+                acc1[r][h] = cplx<R>{0, 0};
+            }
+        }
+        for (int m = 1; m <= nm; ++m) {
+            int s = (cur - m) % ng;
+            if (s < 0) s += ng;
+            const cplx<R>* rs0 = ring + (size_t)s * slot_sz + roff0;
+            const cplx<R>* rs1 = ring + (size_t)s * slot_sz + roff1;
+            const cplx<R>* Gm = G + (size_t)m * gsz + goff;
+#pragma unroll
+            for (int r = 0; r < PER; ++r) {
+                const int i = c0 + threadIdx.x + r * kDelayThreads;
+                if (i < PAIRS) {
+                    cplx<R> v0[2], v1[2];
+                    *reinterpret_cast<typename Pair<R>::type*>(v0) =
+                        *reinterpret_cast<const typename Pair<R>::type*>(rs0 + 2 * i);
+                    *reinterpret_cast<typename Pair<R>::type*>(v1) =
+                        *reinterpret_cast<const typename Pair<R>::type*>(rs1 + 2 * i);
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        cplx<R> gv = Gm[gi[r][h]];
+                        if (conj_g) gv.y = -gv.y;
+                        acc0[r][h] += cmul_fma(gv, v0[h]);
+                        acc1[r][h] += cmul_fma(gv, v1[h]);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            const int i = c0 + threadIdx.x + r * kDelayThreads;
+            if (i < PAIRS) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int o = quad_tile_pos<N>(2 * i + h);
+                    t0[o] = acc0[r][h];
+                    t0[TS + o] = acc1[r][h];
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const int half = threadIdx.x >= kDelayThreads / 2 ? 1 : 0;
+    quad_inverse_store<R, N>(t0 + half * TS, A + ((size_t)(bc0 + 4 * half) * Lx + kx) * (size_t)NN, twy, twz,
+                             threadIdx.x - half * (kDelayThreads / 2), kDelayThreads / 2);
+}
+
+constexpr int kDelay1Threads = 256;
+
+// One plane per block (any batch; used where two planes' tiles do not fit
+// the LDS, e.g. FP64 at N = 48).
+template <typename R, int N>
+__global__ void __launch_bounds__(kDelay1Threads) k_yzq_delayed1(const cplx<R>* __restrict__ ring,
+                                                              const cplx<R>* __restrict__ G, cplx<R>* __restrict__ A,
+                                                              const cplx<R>* __restrict__ twy,
+                                                              const cplx<R>* __restrict__ twz, GridDims g, int ng,
+                                                              int cur, int nm, int conj_g) {
+    extern __shared__ unsigned char smem_raw[];
+    cplx<R>* t0 = reinterpret_cast<cplx<R>*>(smem_raw);
     // the plane's 4 N^2 points as pairs; the sum runs in chunks of PER pairs
     // per thread so that the accumulators stay within half the VGPR file
-    constexpr int NN = N * N, PAIRS = 4 * NN / 2, PER = 9, CHUNK = PER * kDelayThreads;
+    constexpr int NN = N * N, PAIRS = 4 * NN / 2, PER = 9, CHUNK = PER * kDelay1Threads;
     const int bc = blockIdx.x, kx = blockIdx.y, Lx = g.L[0];
     const int gx = g.N[0] + 1, gg = N + 1;
     const size_t gsz = (size_t)2 * gx * gg * gg;
@@ -578,7 +691,7 @@ __global__ void __launch_bounds__(kDelayThreads) k_yzq_delayed(const cplx<R>* __
         cplx<R> acc[PER][2];
 #pragma unroll
         for (int r = 0; r < PER; ++r) {
-            const int i = c0 + threadIdx.x + r * kDelayThreads;
+            const int i = c0 + threadIdx.x + r * kDelay1Threads;
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const int e = 2 * i + h, qq = e / NN, rr = e - qq * NN;
@@ -594,7 +707,7 @@ __global__ void __launch_bounds__(kDelayThreads) k_yzq_delayed(const cplx<R>* __
             const cplx<R>* Gm = G + (size_t)m * gsz + goff;
 #pragma unroll
             for (int r = 0; r < PER; ++r) {
-                const int i = c0 + threadIdx.x + r * kDelayThreads;
+                const int i = c0 + threadIdx.x + r * kDelay1Threads;
                 if (i < PAIRS) {
                     cplx<R> v[2];
                     *reinterpret_cast<typename Pair<R>::type*>(v) =
@@ -610,7 +723,7 @@ __global__ void __launch_bounds__(kDelayThreads) k_yzq_delayed(const cplx<R>* __
         }
 #pragma unroll
         for (int r = 0; r < PER; ++r) {
-            const int i = c0 + threadIdx.x + r * kDelayThreads;
+            const int i = c0 + threadIdx.x + r * kDelay1Threads;
             if (i < PAIRS) {
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
@@ -621,18 +734,7 @@ __global__ void __launch_bounds__(kDelayThreads) k_yzq_delayed(const cplx<R>* __
         }
     }
     __syncthreads();
-    const int i = threadIdx.x;
-    if (i < 4 * N) {
-        const int q = i / N, c = i - q * N;
-        cplx<R> u[N];
-        tile_col<R, N>(qtile<R, N>(t0, q), c, u, false);
-        dft_small<R, N>(u, true);
-        tile_col<R, N>(qtile<R, N>(t0, q), c, u, true);
-    }
-    __syncthreads();
-    quad_rows_inverse<R, N>(t0, twz);
-    __syncthreads();
-    quad_sum_store<R, N>(t0, A + ((size_t)bc * Lx + kx) * (size_t)(N * N), twy);
+    quad_inverse_store<R, N>(t0, A + ((size_t)bc * Lx + kx) * (size_t)(N * N), twy, twz, threadIdx.x, blockDim.x);
 }
 
 template <typename R>

@@ -384,16 +384,28 @@ struct Ops {
             Trace t(c, ETAIM_K_YZ_DELAYED,
                     nm * (4.0 * c->B * c->Np * s + 2.0 * c->gfold * s) + 4.0 * c->B * g.L[0] * g.N[2] * g.N[1] * s);
             if (c->yz_engine == 1) {
-                const dim3 grid(4 * c->B, g.L[0]);
-                const size_t lds = quad_lds(c);
+                // plane pairs (bc, bc + 4) sharing the Green loads where the batch is even and two
+                // planes' tiles fit the LDS; one plane per block otherwise
+                const bool pair = c->B % 2 == 0 && 2 * quad_lds(c) <= (size_t)160 * 1024;
+                const dim3 grid(pair ? 2 * c->B : 4 * c->B, g.L[0]);
+                const dim3 blk(pair ? kDelayThreads : kDelay1Threads);
+                const size_t lds = (pair ? 2 : 1) * quad_lds(c);
                 const cplx<R>* rg = (const cplx<R>*)ring(c);
                 const int ng = c->st.ng;
+#define ETAIM_DELAYED(NN)                                                                                     \
+    if (pair)                                                                                                  \
+        hipLaunchKernelGGL((k_yzq_delayed<R, NN>), grid, blk, lds, c->stream, rg, ghat(c), A(c), tw(c, 1),     \
+                           tw(c, 2), g, ng, cur, nm, conj);                                                    \
+    else                                                                                                       \
+        hipLaunchKernelGGL((k_yzq_delayed1<R, NN>), grid, blk, lds, c->stream, rg, ghat(c), A(c), tw(c, 1),    \
+                           tw(c, 2), g, ng, cur, nm, conj);
                 switch (quad_n(c)) {
-                    case 16: hipLaunchKernelGGL((k_yzq_delayed<R, 16>), grid, dim3(kDelayThreads), lds, c->stream, rg, ghat(c), A(c), tw(c, 1), tw(c, 2), g, ng, cur, nm, conj); break;
-                    case 24: hipLaunchKernelGGL((k_yzq_delayed<R, 24>), grid, dim3(kDelayThreads), lds, c->stream, rg, ghat(c), A(c), tw(c, 1), tw(c, 2), g, ng, cur, nm, conj); break;
-                    case 48: hipLaunchKernelGGL((k_yzq_delayed<R, 48>), grid, dim3(kDelayThreads), lds, c->stream, rg, ghat(c), A(c), tw(c, 1), tw(c, 2), g, ng, cur, nm, conj); break;
+                    case 16: ETAIM_DELAYED(16) break;
+                    case 24: ETAIM_DELAYED(24) break;
+                    case 48: ETAIM_DELAYED(48) break;
                     default: return fail(ETAIM_EUNSUPPORTED, "register plane kernels need N_y = N_z in {16, 24, 48}");
                 }
+#undef ETAIM_DELAYED
             } else
             hipLaunchKernelGGL(k_yz_delayed<R>, dim3(g.L[0], 4 * c->B), dim3(kPlaneThreads), plane_lds(c), c->stream,
                                (const cplx<R>*)ring(c), ghat(c), A(c), tw(c, 1), tw(c, 2), c->ry, c->rz, g,
@@ -446,7 +458,8 @@ struct Ops {
                               (const void*)k_yzq_green<R, 48>, (const void*)k_yzq_commit<R, 16>,
                               (const void*)k_yzq_commit<R, 24>, (const void*)k_yzq_commit<R, 48>,
                               (const void*)k_yzq_delayed<R, 16>, (const void*)k_yzq_delayed<R, 24>,
-                              (const void*)k_yzq_delayed<R, 48>})
+                              (const void*)k_yzq_delayed<R, 48>, (const void*)k_yzq_delayed1<R, 16>,
+                              (const void*)k_yzq_delayed1<R, 24>, (const void*)k_yzq_delayed1<R, 48>})
             HIPCHK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
         // the gather's LDS grows with its tuned row count
         HIPCHK(hipFuncSetAttribute((const void*)k_fwdx_gather<R>, hipFuncAttributeMaxDynamicSharedMemorySize,

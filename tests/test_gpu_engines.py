@@ -79,17 +79,19 @@ def test_far_operator_level4(torch, prec, tol, engine):
     P.close()
 
 
-@pytest.mark.parametrize("engine", [0, 1])
+@pytest.mark.parametrize("engine,batch", [(0, 1), (1, 1), (1, 2)], ids=["lds", "reg", "reg_pairs"])
 @pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-5)], ids=["fp64", "fp32"])
-def test_delayed_field_level4(torch, prec, tol, engine):
+def test_delayed_field_level4(torch, prec, tol, engine, batch):
+    """batch 2 runs the plane-pair delayed kernel in FP32 (two planes share
+    each Green load); FP64 keeps one plane per block at this size."""
     s, A, p = _oracle_far(L4)
     ng = p["ng"]
-    P = gpu_problem(L4, precision=prec, batch=1, nt=8)
+    P = gpu_problem(L4, precision=prec, batch=batch, nt=8)
     _with_engine(P, engine)
-    hist = W.complex_normal(32, (ng, 1, s.ns))
+    hist = W.complex_normal(32, (ng, batch, s.ns))
     hist[:A.mn] = 0.0
     b = P.delayed_field(_dev(torch, hist)).cpu().numpy()
-    ref = sum(A.far_matvec(m, hist[m - 1, 0]) for m in range(A.mn + 1, ng + 1))[None]
+    ref = np.array([sum(A.far_matvec(m, hist[m - 1, j]) for m in range(A.mn + 1, ng + 1)) for j in range(batch)])
     e = rel(b, ref)
     _say("L4 delayed", "fp32" if prec else "fp64", "engine", engine, "rel", e)
     assert e <= tol
