@@ -93,6 +93,28 @@ def cpu_baseline(wl, iters_per_step, budget_s=20.0):
                       f"near-zone values zero (cost is value-independent)"}
 
 
+def step_err(a, b) -> float:
+    """Largest per-step error ||a_l - b_l|| relative to the peak step norm of b."""
+    nb = np.linalg.norm(b.reshape(len(b), -1), axis=1)
+    return float(np.max(np.linalg.norm((a - b).reshape(len(b), -1), axis=1)) / max(nb.max(), 1e-300))
+
+
+def stream_copy_gbps(torch, mib: int = 1024, reps: int = 5) -> float:
+    """Device-to-device copy rate (read + write bytes / time) of a plain copy."""
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    rate = 2.0 * n * 4 * reps / (time.perf_counter() - t) / 1e9
+    del src, dst
+    return rate
+
+
 def fft_flops(n: int) -> float:
     """Conventional flop count of an n-point complex FFT."""
     return 5.0 * n * math.log2(n)
@@ -223,11 +245,15 @@ def main():
         roof = {"bound": "hbm", "achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(hbm_gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
                 "bytes_per_launch": bytes_launch, "avg_launch_ms": avg_ms}
+    # one AIM matvec = the four matvec classes once each (launch averages)
+    per_matvec_ms = sum(ks[n]["ms"] / ks[n]["launches"] for n in ("anterp_x", "yz_green", "fft_x_inv", "interp_near"))
+    copy_gbps = stream_copy_gbps(torch)
+    roof["frac_of_stream_copy"] = round((hbm_gbs if roof["bound"] == "hbm" else roof["hbm_GBps"]) / copy_gbps, 4)
     # the HBM-bound class: the delayed field streams the whole history every step
     dl = ks["yz_delayed"]
-    hbm_stream = {"kernel": "yz_delayed", "GBps": round(dl["bytes"] / max(dl["ms"], 1e-9) / 1e6, 1),
-                  "frac": round(dl["bytes"] / max(dl["ms"], 1e-9) / 1e6 / HBM_PEAK_GBS, 4),
-                  "traffic": hbm_traffic(wl.name, "yz_delayed")}
+    dl_gbs = dl["bytes"] / max(dl["ms"], 1e-9) / 1e6
+    hbm_stream = {"kernel": "yz_delayed", "GBps": round(dl_gbs, 1), "frac": round(dl_gbs / HBM_PEAK_GBS, 4),
+                  "frac_of_stream_copy": round(dl_gbs / copy_gbps, 4), "traffic": hbm_traffic(wl.name, "yz_delayed")}
     out = {"metric": "ET-AIM time-steps/s & FFT-matvec HBM GB/s, FP32 batched vs FP64, 1 MI355X",
            "value": round(steps_s, 4), "unit": "time-steps/s", "n_gpus": 1, "steps": K, "warmup": args.warmup,
            "ms_per_step": round(1e3 * wall / K, 3), "higher_is_better": True, "scaling": "weak",
@@ -240,6 +266,9 @@ def main():
            "gmres_iters_per_step": round(iters, 2),
            "roofline": roof,
            "hbm_stream": hbm_stream,
+           "matvecs_per_s": round(1e3 / per_matvec_ms, 2),
+           "column_matvecs_per_s": round(1e3 * wl.batch / per_matvec_ms, 1),
+           "stream_copy_GBps": round(copy_gbps, 1),
            "tuning": tuning,
            "kernels": {n: {"ms": round(v["ms"], 2), "launches": v["launches"],
                            "GBps": round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1)} for n, v in ks.items()
@@ -280,8 +309,27 @@ def main():
                              "gmres_iters_per_step": round(st64["total_iters"] / K, 2)}
         out["fp32_batched_over_fp64_plain"] = round(steps_s * wl.batch / (K / w64), 2)
         out["fp32_rel_l2_vs_fp64_dir0"] = err
+        out["fp32_max_step_err_vs_fp64_dir0"] = step_err(I32_0[:K], I64_0[:K])
         log(f"[bench] fp64 plain: {K / w64:.2f} steps/s; fp32 batch vs fp64 rel L2 {err:.2e}")
         P64.close()
+        del I64
+        # precision error apart from the GMRES tolerance: FP32 at tol 1e-7
+        # against FP64 at tol 1e-12, direction 0, the first Kp steps
+        Kp = min(K, 100)
+        Pt = make_problem(wl, FP64, 1, nt, 1e-12)
+        It64, _ = Pt.march(V64, nsteps=Kp)
+        It64 = It64[:Kp, 0].cpu().numpy()
+        Pt.close()
+        Pt = make_problem(wl, FP32, 1, nt, 1e-7)
+        It32, _ = Pt.march(V64, nsteps=Kp)
+        It32 = It32[:Kp, 0].cpu().numpy()
+        Pt.close()
+        out["fp32_precision_error_dir0"] = {
+            "steps": Kp, "tol_fp32": 1e-7, "tol_fp64": 1e-12,
+            "rel_l2": float(np.linalg.norm(It32 - It64) / np.linalg.norm(It64)),
+            "max_step_err": step_err(It32, It64)}
+        log(f"[bench] precision error (tol 1e-7 vs 1e-12, {Kp} steps): "
+            f"{out['fp32_precision_error_dir0']['rel_l2']:.2e}")
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(wl, iters / 1.0)
