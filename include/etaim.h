@@ -228,6 +228,9 @@ typedef struct {
                                 order that best predicted step l-1 (0: zero guess, 1: the
                                 previous solution, up to 4: cubic); the converged solution does
                                 not depend on it beyond the tolerance (default 4) */
+    int32_t precond;         /* right preconditioner of the per-step GMRES: 0 Jacobi diag(Z0)^-1
+                                (the paper's choice), 1 sparse approximate inverse of Z0 on the
+                                near-zone pattern (default; M^H for the adjoint) */
     double apply_ms;         /* out: measured matvec time [ms] (0 if not measured) */
     double solve_ms;         /* out: measured GMRES solve of the tuning right-hand side [ms] (0 if not
                                 measured) */

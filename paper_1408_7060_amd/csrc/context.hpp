@@ -52,5 +52,7 @@ int derive_parameters(const Geometry& g, const etaim_params* p, Setup& s, std::s
 int build_projection(const Geometry& g, Setup& s, std::string& err);
 int build_near_zone(const Geometry& g, const etaim_params* p, Setup& s, std::string& err);
 void exact_near_entries(const Geometry& g, const etaim_params* p, Setup& s);
+// sparse approximate inverse of Z0 on the near pattern, in the near CSR layout
+void sparse_approximate_inverse(const Setup& s, int ns, std::vector<zd>& M);
 
 }  // namespace etaim

@@ -81,6 +81,9 @@ struct etaim_ctx {
     double *cs = nullptr, *nrm = nullptr, *beta = nullptr, *bnorm = nullptr, *resid = nullptr;
     int *active = nullptr, *jcnt = nullptr, *flag = nullptr;
     double* perr = nullptr;  // extrapolation errors of the step just solved (+ block partials)
+    // near-zone sparse approximate inverse (right preconditioner) and its transposed copy
+    zd *sai = nullptr, *saiT = nullptr, *zt = nullptr;
+    int precond = 1;  // 0: Jacobi diag(Z0)^-1, 1: near-zone sparse approximate inverse
     int* flag_h = nullptr;
     // batched-GMRES schedule: steps per host check, captured Arnoldi steps
     int sync_every = 1;
@@ -489,7 +492,17 @@ int arnoldi_step(etaim_ctx* c, int j, int conj, const int* gate) {
     zd* vj = c->Vk + (size_t)j * nB;
     zd* vn = c->Vk + (size_t)(j + 1) * nB;
     if (gate) hipLaunchKernelGGL(k_gate, dim3(1), dim3(64), 0, c->stream, c->flag);
-    CHK(Ops<R>::apply(c, 0, vj, dinv, c->w, conj, gate));
+    if (c->precond == 1) {
+        // w = Z (M v_j), M the near-zone sparse approximate inverse (M^H for the adjoint)
+        {
+            Trace tp(c, ETAIM_K_KRYLOV, (double)c->nnz * 20.0 + 2.0 * (double)nB * 16.0);
+            hipLaunchKernelGGL(k_spmv_cols, dim3(blocks_for(nB)), dim3(256), 0, c->stream, c->rowptr, c->col,
+                               conj ? c->saiT : c->sai, vj, c->zt, ns, B, conj, 0, gate);
+        }
+        CHK(Ops<R>::apply(c, 0, c->zt, nullptr, c->w, conj, gate));
+    } else {
+        CHK(Ops<R>::apply(c, 0, vj, dinv, c->w, conj, gate));
+    }
     dim3 gd(j + 1, B), go((ns + 255) / 256, B);
     Trace tk(c, ETAIM_K_KRYLOV, (4.0 * (j + 1) + 8.0) * (double)nB * 16.0);
     hipLaunchKernelGGL(k_dots, gd, dim3(256), 0, c->stream, c->Vk, c->w, c->h1, ns, B, gate);
@@ -618,8 +631,16 @@ int gmres(etaim_ctx* c, const zd* rhs, zd* x, int conj, StepResult& res) {
         }
         hipLaunchKernelGGL(k_backsolve, dim3((B + 63) / 64), dim3(64), 0, c->stream, c->H, c->g, c->jcnt, c->yv, B,
                            rs);
-        hipLaunchKernelGGL(k_update_x, dim3((ns + 255) / 256, B), dim3(256), 0, c->stream, x, c->Vk, c->yv, c->jcnt,
-                           dinv, ns, B, rs);
+        if (c->precond == 1) {
+            // x += M (V y)
+            hipLaunchKernelGGL(k_krylov_combine, dim3((ns + 255) / 256, B), dim3(256), 0, c->stream, c->zt, c->Vk,
+                               c->yv, c->jcnt, ns, B, rs);
+            hipLaunchKernelGGL(k_spmv_cols, dim3(blocks_for(nB)), dim3(256), 0, c->stream, c->rowptr, c->col,
+                               conj ? c->saiT : c->sai, c->zt, x, ns, B, conj, 1, nullptr);
+        } else {
+            hipLaunchKernelGGL(k_update_x, dim3((ns + 255) / 256, B), dim3(256), 0, c->stream, x, c->Vk, c->yv,
+                               c->jcnt, dinv, ns, B, rs);
+        }
         HIPCHK(hipGetLastError());
         if (res.nonfinite) break;
     }
@@ -918,6 +939,14 @@ int device_setup(etaim_ctx* c) {
         hipLaunchKernelGGL(k_permute_rows, dim3(blocks_for((size_t)c->nnz * c->mv)), dim3(256), 0, c->stream,
                            c->near64, c->nearT64, tp, c->nnz, c->mv);
         HIPCHK(hipGetLastError());
+        // sparse approximate inverse of Z0 on the near pattern, and M^T's values for M^H
+        std::vector<zd> Mv;
+        sparse_approximate_inverse(s, ns, Mv);
+        CHK(c->upload(c->sai, Mv));
+        CHK(c->alloc(c->saiT, (size_t)c->nnz));
+        hipLaunchKernelGGL(k_permute_rows, dim3(blocks_for((size_t)c->nnz)), dim3(256), 0, c->stream, c->sai,
+                           c->saiT, tp, c->nnz, 1);
+        HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(c->stream));
         auto it = std::find(c->allocs.begin(), c->allocs.end(), (void*)tp);
         c->allocs.erase(it);
@@ -971,6 +1000,7 @@ int device_setup(etaim_ctx* c) {
     CHK(c->alloc(c->Vk, (size_t)(rs + 1) * nB));
     CHK(c->alloc(c->w, nB));
     CHK(c->alloc(c->xk, nB));
+    CHK(c->alloc(c->zt, nB));
     CHK(c->alloc(c->rhs, nB));
     CHK(c->alloc(c->zero, nB));
     HIPCHK(hipMemsetAsync(c->zero, 0, nB * sizeof(zd), c->stream));

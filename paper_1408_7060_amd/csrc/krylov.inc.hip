@@ -210,6 +210,41 @@ __global__ void __launch_bounds__(256) k_update_x(zd* __restrict__ x, const zd* 
     x[(size_t)b * ns + k] += acc * d;
 }
 
+// y[b] = op(M) x[b] (or y[b] += op(M) x[b]) for every column b, M a complex
+// CSR matrix on the near-zone pattern; op(M) = M, or with conj = 1 the
+// conjugated values (the host passes the transposed copy for M^H).
+__global__ void k_spmv_cols(const int* __restrict__ rowptr, const int* __restrict__ col, const zd* __restrict__ M,
+                            const zd* __restrict__ x, zd* __restrict__ y, int ns, int B, int conj, int accumulate,
+                            const int* __restrict__ gate) {
+    if (gated_off(gate)) return;
+    const size_t tot = (size_t)ns * B;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot; e += (size_t)gridDim.x * blockDim.x) {
+        const int b = (int)(e / ns), i = (int)(e - (size_t)b * ns);
+        const zd* xb = x + (size_t)b * ns;
+        zd acc{0, 0};
+        for (int q = rowptr[i]; q < rowptr[i + 1]; ++q) {
+            zd v = M[q];
+            if (conj) v.y = -v.y;
+            acc += v * xb[col[q]];
+        }
+        y[e] = accumulate ? y[e] + acc : acc;
+    }
+}
+
+// u[b] = sum_{i < jcnt[b]} y[b][i] V_i[b]  (the Krylov combination before a
+// right preconditioner that is not diagonal)
+__global__ void __launch_bounds__(256) k_krylov_combine(zd* __restrict__ u, const zd* __restrict__ V,
+                                                        const zd* __restrict__ y, const int* __restrict__ jcnt, int ns,
+                                                        int B, int restart) {
+    const int b = blockIdx.y;
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= ns) return;
+    const int n = jcnt[b];
+    zd acc{0, 0};
+    for (int i = 0; i < n; ++i) acc += y[(size_t)b * restart + i] * V[((size_t)i * B + b) * ns + k];
+    u[(size_t)b * ns + k] = acc;
+}
+
 __global__ void k_copy_conj(const zd* __restrict__ in, zd* __restrict__ out, size_t n, int conj) {
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
         zd v = in[e];

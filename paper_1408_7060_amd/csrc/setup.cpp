@@ -21,6 +21,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstring>
 #include <numeric>
 
@@ -596,6 +597,110 @@ void exact_near_entries(const Geometry& g, const etaim_params* p, Setup& s) {
                         const double cP = sg * g.len[k] * g.len[kk] / (Aa * Ab);
                         for (int m = 0; m < M; ++m) out[m] += (sa * cA) * IA[m] + (sp * cP) * IF[m];
                     }
+            }
+        }
+    }
+}
+
+
+// ---------------------------------------------------------------------------
+// Sparse approximate inverse of the step matrix on the near-zone pattern
+// (right preconditioner of the per-step GMRES): column j of M minimises
+// || Z0[I, J] m - e_j ||_2 over the near neighbours J of basis j, with I the
+// rows that Z0[:, J] reaches (the neighbours of the neighbours).  Z0 on near
+// pairs is the exact step entry (the pre-corrected AIM operator reproduces
+// it there).  Each column is an independent small least-squares problem,
+// solved by Householder QR.  M is returned in the near CSR layout: M[e] for
+// e = (row i, column j) of the pattern, which is symmetric.
+namespace {
+
+using cz = std::complex<double>;
+
+// least-squares solution of the n_r x n_c system S m = r (n_r >= n_c,
+// column-major S, overwritten) by Householder QR
+void lsq_householder(std::vector<cz>& S, int nr, int nc, std::vector<cz>& r, std::vector<cz>& m) {
+    for (int k = 0; k < nc; ++k) {
+        cz* a = &S[(size_t)k * nr];
+        double sig = 0;
+        for (int i = k; i < nr; ++i) sig += std::norm(a[i]);
+        const double nrm = std::sqrt(sig);
+        if (nrm == 0) continue;
+        // v = a[k:] + e^{i arg a_k} |a| e_1; H = I - 2 v v^H / (v^H v)
+        const cz ph = std::abs(a[k]) > 0 ? a[k] / std::abs(a[k]) : cz(1, 0);
+        const cz alpha = -ph * nrm;
+        a[k] -= alpha;
+        double vv = 0;
+        for (int i = k; i < nr; ++i) vv += std::norm(a[i]);
+        for (int j = k + 1; j < nc; ++j) {
+            cz* b = &S[(size_t)j * nr];
+            cz d = 0;
+            for (int i = k; i < nr; ++i) d += std::conj(a[i]) * b[i];
+            d *= 2.0 / vv;
+            for (int i = k; i < nr; ++i) b[i] -= d * a[i];
+        }
+        cz d = 0;
+        for (int i = k; i < nr; ++i) d += std::conj(a[i]) * r[i];
+        d *= 2.0 / vv;
+        for (int i = k; i < nr; ++i) r[i] -= d * a[i];
+        a[k] = alpha;  // R's diagonal; the rest of the reflector is no longer needed
+    }
+    m.assign(nc, cz(0, 0));
+    for (int k = nc - 1; k >= 0; --k) {
+        cz acc = r[k];
+        for (int j = k + 1; j < nc; ++j) acc -= S[(size_t)j * nr + k] * m[j];
+        const cz dkk = S[(size_t)k * nr + k];
+        m[k] = std::abs(dkk) > 0 ? acc / dkk : cz(0, 0);
+    }
+}
+
+}  // namespace
+
+void sparse_approximate_inverse(const Setup& s, int ns, std::vector<zd>& M) {
+    const int mv = s.mn + 1;
+    const size_t nnz = s.col.size();
+    M.assign(nnz, zd{0, 0});
+    auto entry = [&](int i, int j, cz& v) {
+        const int* b = s.col.data() + s.rowptr[i];
+        const int* e = s.col.data() + s.rowptr[i + 1];
+        const int* p = std::lower_bound(b, e, j);
+        if (p == e || *p != j) return false;
+        const zd z = s.near_exact[(size_t)(p - s.col.data()) * mv];
+        v = cz(z.x, z.y);
+        return true;
+    };
+#pragma omp parallel
+    {
+        std::vector<int> I;
+        std::vector<cz> S, r, m;
+#pragma omp for schedule(dynamic, 16)
+        for (int j = 0; j < ns; ++j) {
+            const int j0 = s.rowptr[j], nc = s.rowptr[j + 1] - j0;
+            if (nc == 0) continue;
+            I.clear();
+            for (int a = 0; a < nc; ++a) {
+                const int k = s.col[j0 + a];
+                I.insert(I.end(), s.col.begin() + s.rowptr[k], s.col.begin() + s.rowptr[k + 1]);
+            }
+            std::sort(I.begin(), I.end());
+            I.erase(std::unique(I.begin(), I.end()), I.end());
+            const int nr = (int)I.size();
+            S.assign((size_t)nr * nc, cz(0, 0));
+            r.assign(nr, cz(0, 0));
+            for (int a = 0; a < nr; ++a) {
+                if (I[a] == j) r[a] = cz(1, 0);
+                for (int b = 0; b < nc; ++b) {
+                    cz v;
+                    if (entry(I[a], s.col[j0 + b], v)) S[(size_t)b * nr + a] = v;
+                }
+            }
+            lsq_householder(S, nr, nc, r, m);
+            // m[b] is M[col[j0 + b]][j]: stored at the pattern position (row col[j0 + b], column j)
+            for (int b = 0; b < nc; ++b) {
+                const int i = s.col[j0 + b];
+                const int* bb = s.col.data() + s.rowptr[i];
+                const int* ee = s.col.data() + s.rowptr[i + 1];
+                const int* p = std::lower_bound(bb, ee, j);
+                if (p != ee && *p == j) M[(size_t)(p - s.col.data())] = zd{m[b].real(), m[b].imag()};
             }
         }
     }

@@ -39,7 +39,7 @@ bool radix_equal(const Radix& a, const Radix& b) {
 
 struct Shape {
     Radix rx, ry, rz;
-    int mr = 0, mt = 0, waves = 4, sync = 1, graph = 0, engine = 0, xeng = 0, guess = 4;
+    int mr = 0, mt = 0, waves = 4, sync = 1, graph = 0, engine = 0, xeng = 0, guess = 4, precond = 1;
 };
 
 template <typename R>
@@ -69,7 +69,8 @@ bool shape_fits(const etaim_ctx* c, const Shape& s) {
            plane_fits(mt, s.rx) && (4 * (size_t)mr * (Lx + 1) + Lx) * e <= 160 * 1024 &&
            ((size_t)mt * (Lx + 1) + Lx) * e <= (size_t)kLdsBudget && s.waves >= 1 && s.waves <= 4 &&
            s.sync >= 1 && s.sync <= c->prm.restart && (s.engine == 0 || (s.engine == 1 && quad_n(c) > 0)) &&
-           (s.xeng == 0 || (s.xeng == 1 && xline_n(c) > 0)) && s.guess >= 0 && s.guess <= 4;
+           (s.xeng == 0 || (s.xeng == 1 && xline_n(c) > 0)) && s.guess >= 0 && s.guess <= 4 &&
+           (s.precond == 0 || s.precond == 1);
 }
 
 void drop_graphs(etaim_ctx* c) {
@@ -92,6 +93,7 @@ void put_shape(etaim_ctx* c, const Shape& s) {
     c->yz_engine = s.engine;
     c->x_engine = s.xeng;
     c->guess_order = s.guess;
+    c->precond = s.precond;
     drop_graphs(c);  // captured steps hold the old launch shapes
 }
 
@@ -108,6 +110,7 @@ Shape get_shape(const etaim_ctx* c) {
     s.engine = c->yz_engine;
     s.xeng = c->x_engine;
     s.guess = c->guess_order;
+    s.precond = c->precond;
     return s;
 }
 
@@ -125,6 +128,7 @@ void shape_to_c(const etaim_ctx* c, const Shape& s, etaim_tuning* t) {
     t->yz_engine = s.engine;
     t->x_engine = s.xeng;
     t->guess_order = s.guess;
+    t->precond = s.precond;
 }
 
 // EINVAL for malformed plans; shape_fits decides EUNSUPPORTED afterwards
@@ -154,6 +158,7 @@ int shape_from_c(const etaim_ctx* c, const etaim_tuning* t, Shape& s) {
     s.engine = t->yz_engine;
     s.xeng = t->x_engine;
     s.guess = t->guess_order;
+    s.precond = t->precond;
     return ETAIM_OK;
 }
 
@@ -205,13 +210,13 @@ bool cache_lookup(const char* path, const std::string& key, etaim_tuning& t) {
         line = buf;
         if (line.find("\"key\": \"" + key + "\"") == std::string::npos) continue;
         std::memset(&t, 0, sizeof t);
-        long v[8];
+        long v[9];
         if (json_ints(line, "radix_x", t.radix[0], 8) && json_ints(line, "radix_y", t.radix[1], 8) &&
             json_ints(line, "radix_z", t.radix[2], 8) && json_int(line, "gather_rows", v[0]) &&
             json_int(line, "lines_per_block", v[1]) && json_int(line, "interp_waves", v[2]) &&
             json_int(line, "sync_every", v[3]) && json_int(line, "graph", v[4]) &&
             json_int(line, "yz_engine", v[5]) && json_int(line, "x_engine", v[6]) &&
-            json_int(line, "guess_order", v[7])) {
+            json_int(line, "guess_order", v[7]) && json_int(line, "precond", v[8])) {
             t.gather_rows = (int)v[0];
             t.lines_per_block = (int)v[1];
             t.interp_waves = (int)v[2];
@@ -220,6 +225,7 @@ bool cache_lookup(const char* path, const std::string& key, etaim_tuning& t) {
             t.yz_engine = (int)v[5];
             t.x_engine = (int)v[6];
             t.guess_order = (int)v[7];
+            t.precond = (int)v[8];
             found = true;  // the last matching record wins
         }
     }
@@ -238,9 +244,9 @@ int cache_append(const char* path, const std::string& key, const etaim_tuning& t
     std::fprintf(f,
                  "{\"key\": \"%s\", \"radix_x\": %s, \"radix_y\": %s, \"radix_z\": %s, \"gather_rows\": %d, "
                  "\"lines_per_block\": %d, \"interp_waves\": %d, \"sync_every\": %d, \"graph\": %d, "
-                 "\"yz_engine\": %d, \"x_engine\": %d, \"guess_order\": %d, \"apply_ms\": %.4f, \"solve_ms\": %.3f}\n",
+                 "\"yz_engine\": %d, \"x_engine\": %d, \"guess_order\": %d, \"precond\": %d, \"apply_ms\": %.4f, \"solve_ms\": %.3f}\n",
                  key.c_str(), arr(t.radix[0]).c_str(), arr(t.radix[1]).c_str(), arr(t.radix[2]).c_str(),
-                 t.gather_rows, t.lines_per_block, t.interp_waves, t.sync_every, t.graph, t.yz_engine, t.x_engine, t.guess_order, t.apply_ms,
+                 t.gather_rows, t.lines_per_block, t.interp_waves, t.sync_every, t.graph, t.yz_engine, t.x_engine, t.guess_order, t.precond, t.apply_ms,
                  t.solve_ms);
     std::fclose(f);
     return ETAIM_OK;

@@ -202,3 +202,27 @@ def test_initial_guess_order(torch, name, prec, tol, bound):
         e = float(np.linalg.norm(out[order][0] - ref) / np.linalg.norm(ref))
         assert e <= bound, (order, e)
     assert out[4][1] <= 1.05 * out[1][1]
+
+
+@pytest.mark.parametrize("adjoint", [False, True], ids=["forward", "adjoint"])
+@pytest.mark.parametrize("name,prec,tol,bound", [(W.SPHERE_L2.name, 0, 1e-13, 1e-11),
+                                                 (W.SPHERE_L3.name, 1, 1e-6, 1e-4)])
+def test_preconditioners_agree(torch, name, prec, tol, bound, adjoint):
+    """The near-zone sparse approximate inverse and the Jacobi diagonal give
+    the same march within the GMRES tolerance; the approximate inverse needs
+    fewer iterations."""
+    V = _excitation(name, 16, 2, 43)
+    out = {}
+    for pc in (0, 1):
+        P = gpu_problem(name, precision=prec, tol=tol, nt=16, batch=2, flags=F_CONTINUE_ON_NOCONV)
+        d = P.tuning()
+        d["precond"] = pc
+        P.set_tuning(d)
+        Vd = torch.from_numpy(np.ascontiguousarray(V)).cuda()
+        I, st = P.adjoint_march(Vd) if adjoint else P.march(Vd)
+        out[pc] = (I.cpu().numpy(), st["total_iters"])
+        P.close()
+        _say("precond", pc, "iterations", st["total_iters"])
+    e = float(np.linalg.norm(out[1][0] - out[0][0]) / np.linalg.norm(out[0][0]))
+    assert e <= bound, e
+    assert out[1][1] < out[0][1]
