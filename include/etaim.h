@@ -231,6 +231,12 @@ typedef struct {
     int32_t precond;         /* right preconditioner of the per-step GMRES: 0 Jacobi diag(Z0)^-1
                                 (the paper's choice), 1 sparse approximate inverse of Z0 on the
                                 near-zone pattern (default; M^H for the adjoint) */
+    int32_t delay_block;     /* delayed field of the register engine in time blocks of this many
+                                steps (1..8; 1: the direct sum over all N_g history steps at every
+                                step): at step r0 + j of a block the terms that read history older
+                                than r0 are summed for the whole block in one pass at r0, the j
+                                terms of the block's own steps at the step; equal to the direct sum
+                                up to rounding (default 6; used when N_g <= 32) */
     double apply_ms;         /* out: measured matvec time [ms] (0 if not measured) */
     double solve_ms;         /* out: measured GMRES solve of the tuning right-hand side [ms] (0 if not
                                 measured) */

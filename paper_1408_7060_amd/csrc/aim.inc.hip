@@ -589,7 +589,8 @@ __global__ void __launch_bounds__(kDelayThreads) k_yzq_delayed(const cplx<R>* __
                                                               const cplx<R>* __restrict__ G, cplx<R>* __restrict__ A,
                                                               const cplx<R>* __restrict__ twy,
                                                               const cplx<R>* __restrict__ twz, GridDims g, int ng,
-                                                              int cur, int nm, int conj_g) {
+                                                              int cur, int nm, int conj_g,
+                                                              const cplx<R>* __restrict__ Fj) {
     extern __shared__ unsigned char smem_raw[];
     cplx<R>* t0 = reinterpret_cast<cplx<R>*>(smem_raw);
     constexpr int NN = N * N, PAIRS = 4 * NN / 2, PER = 6, CHUNK = PER * kDelayThreads, TS = 4 * N * (N + 1);
@@ -617,6 +618,14 @@ __global__ void __launch_bounds__(kDelayThreads) k_yzq_delayed(const cplx<R>* __
                 gi[r][h] = fold(kz, 2 * N) * gg + fold(ky, 2 * N);
                 acc0[r][h] = cplx<R>{0, 0};
                 acc1[r][h] = cplx<R>{0, 0};
+            }
+            // the older history's part of the sum, precomputed for this step's time block
+            if (Fj != nullptr && i < PAIRS) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    acc0[r][h] = Fj[roff0 + 2 * i + h];
+                    acc1[r][h] = Fj[roff1 + 2 * i + h];
+                }
             }
         }
         for (int m = 1; m <= nm; ++m) {
@@ -672,7 +681,8 @@ __global__ void __launch_bounds__(kDelay1Threads) k_yzq_delayed1(const cplx<R>* 
                                                               const cplx<R>* __restrict__ G, cplx<R>* __restrict__ A,
                                                               const cplx<R>* __restrict__ twy,
                                                               const cplx<R>* __restrict__ twz, GridDims g, int ng,
-                                                              int cur, int nm, int conj_g) {
+                                                              int cur, int nm, int conj_g,
+                                                              const cplx<R>* __restrict__ Fj) {
     extern __shared__ unsigned char smem_raw[];
     cplx<R>* t0 = reinterpret_cast<cplx<R>*>(smem_raw);
     // the plane's 4 N^2 points as pairs; the sum runs in chunks of PER pairs
@@ -697,7 +707,7 @@ __global__ void __launch_bounds__(kDelay1Threads) k_yzq_delayed1(const cplx<R>* 
                 const int e = 2 * i + h, qq = e / NN, rr = e - qq * NN;
                 const int kz = 2 * (rr / N) + (qq >> 1), ky = 2 * (rr % N) + (qq & 1);
                 gi[r][h] = fold(kz, 2 * N) * gg + fold(ky, 2 * N);
-                acc[r][h] = cplx<R>{0, 0};
+                acc[r][h] = (Fj != nullptr && i < PAIRS) ? Fj[roff + e] : cplx<R>{0, 0};
             }
         }
         for (int m = 1; m <= nm; ++m) {
@@ -735,6 +745,76 @@ __global__ void __launch_bounds__(kDelay1Threads) k_yzq_delayed1(const cplx<R>* 
     }
     __syncthreads();
     quad_inverse_store<R, N>(t0, A + ((size_t)bc * Lx + kx) * (size_t)(N * N), twy, twz, threadIdx.x, blockDim.x);
+}
+
+// History part of the delayed field for a block of pb steps starting at
+// march step r0.  At step r0 + j the sum over m splits at m = j: the terms
+// m > j read history older than r0, all known at the block's start, and are
+// summed for the whole block in one pass over the ring,
+//   F[j][p] = sum_{m = j+1}^{ng} G_m[p] ring[r0 + j - m][p],  j < pb,
+// for every spectrum point p (quadrant-major, all bc and kx; history steps
+// before 0 are zero); the j terms m <= j (the block's own, newer steps) are
+// added at the step itself.  Each history slot is read once per block and
+// feeds all pb outputs; the point's Green values stay in registers.  Points
+// are visited kx-major, so the blocks in flight share Green planes in L2.
+constexpr int kFarMaxNg = 32, kFarMaxBlock = 8;
+
+template <typename R, int N>
+__global__ void __launch_bounds__(256) k_ring_far(const cplx<R>* __restrict__ ring, const cplx<R>* __restrict__ G,
+                                                  cplx<R>* __restrict__ F, GridDims g, int ng, int r0, int pb,
+                                                  int conj_g) {
+    constexpr int NN = N * N, PP = 4 * NN;
+    const int Lx = g.L[0], BC = 4 * g.B;
+    const size_t gid = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (gid >= (size_t)BC * Lx * PP) return;
+    const int pl = (int)(gid / PP), e = (int)(gid - (size_t)pl * PP);
+    const int kx = pl / BC, bc = pl - kx * BC;
+    const size_t off = ((size_t)bc * Lx + kx) * PP + e;
+    const size_t slot = (size_t)BC * Lx * PP;
+    const int gx = g.N[0] + 1, gg = N + 1;
+    const size_t gsz = (size_t)2 * gx * gg * gg;
+    const int qq = e / NN, rr = e - qq * NN;
+    const size_t gp = ((size_t)((bc & 3) == 3 ? 1 : 0) * gx + fold(kx, Lx)) * (size_t)(gg * gg) +
+                      fold(2 * (rr / N) + (qq >> 1), 2 * N) * gg + fold(2 * (rr % N) + (qq & 1), 2 * N);
+    // all loads unconditional (dead terms read a live address and are
+    // zeroed), so that the compiler issues them back to back
+    const R sg = conj_g ? R(-1) : R(1);
+    cplx<R> gr[kFarMaxNg + 1];
+#pragma unroll
+    for (int m = 1; m <= kFarMaxNg; ++m) {
+        const R mk = m <= ng ? R(1) : R(0);
+        const cplx<R> v = G[(size_t)(m <= ng ? m : ng) * gsz + gp];
+        gr[m] = cplx<R>{v.x * mk, v.y * (sg * mk)};
+    }
+    cplx<R> acc[kFarMaxBlock];
+#pragma unroll
+    for (int j = 0; j < kFarMaxBlock; ++j) acc[j] = cplx<R>{0, 0};
+    // history step h = r0 - hp feeds output j through m = j + hp (the outputs
+    // j >= pb accumulate dead sums and are not stored); the slots are loaded
+    // a chunk at a time ahead of their products
+    constexpr int CH = sizeof(R) == 4 ? 8 : 4;
+#pragma unroll
+    for (int hp0 = 1; hp0 <= kFarMaxNg; hp0 += CH) {
+        if (hp0 > ng) break;
+        cplx<R> q[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const int hp = hp0 + u < ng ? hp0 + u : ng;
+            const int h = r0 - hp;
+            q[u] = ring[(size_t)((h > 0 ? h : 0) % ng) * slot + off];
+            if (h < 0 || hp0 + u > ng) q[u] = cplx<R>{0, 0};
+        }
+#pragma unroll
+        for (int u = 0; u < CH; ++u)
+#pragma unroll
+            for (int j = 0; j < kFarMaxBlock; ++j) {
+                const int m = j + hp0 + u;
+                if (m <= kFarMaxNg) acc[j] += cmul_fma(gr[m], q[u]);
+            }
+    }
+#pragma unroll
+    for (int j = 0; j < kFarMaxBlock; ++j)
+        if (j < pb) F[(size_t)j * slot + off] = acc[j];
 }
 
 template <typename R>

@@ -84,6 +84,10 @@ struct etaim_ctx {
     // near-zone sparse approximate inverse (right preconditioner) and its transposed copy
     zd *sai = nullptr, *saiT = nullptr, *zt = nullptr;
     int precond = 1;  // 0: Jacobi diag(Z0)^-1, 1: near-zone sparse approximate inverse
+    // delayed field in time blocks (register engine): far part of the history
+    // sum once per block of delay_block steps into far, near part per step
+    int delay_block = 6, far_slots = 0, far_r0 = -1;
+    void* far = nullptr;
     int* flag_h = nullptr;
     // batched-GMRES schedule: steps per host check, captured Arnoldi steps
     int sync_every = 1;
@@ -382,11 +386,52 @@ struct Ops {
     static int delayed(etaim_ctx* c, int cur, const zd* V, zd* rhs, int conj) {
         const GridDims& g = c->gd;
         const int nm = std::min(c->st.ng, cur);
+        const int ng = c->st.ng;
+        // time blocks (register engine): at step r0 + j the terms that read history
+        // older than r0 (m > j) are summed for the whole block at its first step, the
+        // j terms of the block's own steps at the step itself
+        const int pb = c->delay_block;
+        const bool blocked = c->yz_engine == 1 && cur >= 1 && pb > 1 && ng <= kFarMaxNg && pb <= kFarMaxBlock;
+        const int r0 = blocked ? cur - (cur - 1) % pb : 0;
+        const bool far_pass = blocked && c->far_r0 != r0;
+        const int nmx = blocked ? std::min(cur - r0, ng) : nm;
         {
-            const double s = sizeof(cplx<R>);
-            Trace t(c, ETAIM_K_YZ_DELAYED,
-                    nm * (4.0 * c->B * c->Np * s + 2.0 * c->gfold * s) + 4.0 * c->B * g.L[0] * g.N[2] * g.N[1] * s);
+            const double s = sizeof(cplx<R>), slot_b = 4.0 * c->B * c->Np * s, green_b = 2.0 * c->gfold * s;
+            double bytes = nmx * (slot_b + green_b) + 4.0 * c->B * g.L[0] * g.N[2] * g.N[1] * s;
+            if (blocked) bytes += slot_b;
+            if (far_pass) bytes += std::min(ng, r0) * slot_b + ng * green_b + pb * slot_b;
+            Trace t(c, ETAIM_K_YZ_DELAYED, bytes);
             if (c->yz_engine == 1) {
+                const size_t slot = (size_t)4 * c->B * c->Np;
+                const cplx<R>* Fj = nullptr;
+                if (blocked) {
+                    if (c->far_slots < pb) {
+                        if (c->far) {
+                            auto it = std::find(c->allocs.begin(), c->allocs.end(), c->far);
+                            if (it != c->allocs.end()) c->allocs.erase(it);
+                            HIPCHK(hipFree(c->far));
+                            c->dev_bytes -= (int64_t)((size_t)c->far_slots * slot * sizeof(cplx<R>));
+                            c->far = nullptr;
+                            c->far_slots = 0;
+                        }
+                        CHK(c->allocv(c->far, (size_t)pb * slot * sizeof(cplx<R>)));
+                        c->far_slots = pb;
+                    }
+                    if (far_pass) {
+                        const size_t pts = (size_t)4 * c->B * g.L[0] * 4 * (size_t)g.N[1] * g.N[2];
+                        const dim3 gf((unsigned)((pts + 255) / 256));
+                        cplx<R>* F = (cplx<R>*)c->far;
+                        switch (quad_n(c)) {
+                            case 16: hipLaunchKernelGGL((k_ring_far<R, 16>), gf, dim3(256), 0, c->stream, (const cplx<R>*)ring(c), ghat(c), F, g, ng, r0, pb, conj); break;
+                            case 24: hipLaunchKernelGGL((k_ring_far<R, 24>), gf, dim3(256), 0, c->stream, (const cplx<R>*)ring(c), ghat(c), F, g, ng, r0, pb, conj); break;
+                            case 48: hipLaunchKernelGGL((k_ring_far<R, 48>), gf, dim3(256), 0, c->stream, (const cplx<R>*)ring(c), ghat(c), F, g, ng, r0, pb, conj); break;
+                            default: return fail(ETAIM_EUNSUPPORTED, "register plane kernels need N_y = N_z in {16, 24, 48}");
+                        }
+                        HIPCHK(hipGetLastError());
+                        c->far_r0 = r0;
+                    }
+                    Fj = (const cplx<R>*)c->far + (size_t)(cur - r0) * slot;
+                }
                 // plane pairs (bc, bc + 4) sharing the Green loads where the batch is even and two
                 // planes' tiles fit the LDS; one plane per block otherwise
                 const bool pair = c->B % 2 == 0 && 2 * quad_lds(c) <= (size_t)160 * 1024;
@@ -394,14 +439,13 @@ struct Ops {
                 const dim3 blk(pair ? kDelayThreads : kDelay1Threads);
                 const size_t lds = (pair ? 2 : 1) * quad_lds(c);
                 const cplx<R>* rg = (const cplx<R>*)ring(c);
-                const int ng = c->st.ng;
 #define ETAIM_DELAYED(NN)                                                                                     \
     if (pair)                                                                                                  \
         hipLaunchKernelGGL((k_yzq_delayed<R, NN>), grid, blk, lds, c->stream, rg, ghat(c), A(c), tw(c, 1),     \
-                           tw(c, 2), g, ng, cur, nm, conj);                                                    \
+                           tw(c, 2), g, ng, cur, nmx, conj, Fj);                                               \
     else                                                                                                       \
         hipLaunchKernelGGL((k_yzq_delayed1<R, NN>), grid, blk, lds, c->stream, rg, ghat(c), A(c), tw(c, 1),    \
-                           tw(c, 2), g, ng, cur, nm, conj);
+                           tw(c, 2), g, ng, cur, nmx, conj, Fj);
                 switch (quad_n(c)) {
                     case 16: ETAIM_DELAYED(16) break;
                     case 24: ETAIM_DELAYED(24) break;
@@ -660,6 +704,7 @@ int march_impl(etaim_ctx* c, const zd* V, zd* I, etaim_stats* st, bool adjoint, 
     const size_t nB = (size_t)B * ns;
     const int conj = adjoint ? 1 : 0;
     HIPCHK(hipMemsetAsync(c->ring, 0, (size_t)c->st.ng * 4 * B * c->Np * sizeof(cplx<R>), c->stream));
+    c->far_r0 = -1;  // the far parts belong to the previous history
     if (c->st.mn >= 1) HIPCHK(hipMemsetAsync(c->hist, 0, (size_t)c->st.mn * nB * sizeof(zd), c->stream));
     // excitation norms per step (instability detector)
     std::vector<double> nV((size_t)nt * B), nI((size_t)nt, 0.0);
@@ -1147,6 +1192,7 @@ int etaim_delayed_field(etaim_ctx* c, const void* hist, void* b) {
     auto run = [&](auto tag) -> int {
         using R = decltype(tag);
         HIPCHK(hipMemsetAsync(c->ring, 0, (size_t)ng * 4 * c->B * c->Np * sizeof(cplx<R>), c->stream));
+        c->far_r0 = -1;
         if (c->st.mn >= 1) HIPCHK(hipMemsetAsync(c->hist, 0, (size_t)c->st.mn * nB * sizeof(zd), c->stream));
         for (int m = ng; m >= 1; --m) CHK(Ops<R>::commit(c, ng - m, (const zd*)hist + (size_t)(m - 1) * nB));
         CHK(Ops<R>::delayed(c, ng, c->zero, (zd*)b, 0));

@@ -39,7 +39,7 @@ bool radix_equal(const Radix& a, const Radix& b) {
 
 struct Shape {
     Radix rx, ry, rz;
-    int mr = 0, mt = 0, waves = 4, sync = 1, graph = 0, engine = 0, xeng = 0, guess = 4, precond = 1;
+    int mr = 0, mt = 0, waves = 4, sync = 1, graph = 0, engine = 0, xeng = 0, guess = 4, precond = 1, dblock = 6;
 };
 
 template <typename R>
@@ -70,7 +70,7 @@ bool shape_fits(const etaim_ctx* c, const Shape& s) {
            ((size_t)mt * (Lx + 1) + Lx) * e <= (size_t)kLdsBudget && s.waves >= 1 && s.waves <= 4 &&
            s.sync >= 1 && s.sync <= c->prm.restart && (s.engine == 0 || (s.engine == 1 && quad_n(c) > 0)) &&
            (s.xeng == 0 || (s.xeng == 1 && xline_n(c) > 0)) && s.guess >= 0 && s.guess <= 4 &&
-           (s.precond == 0 || s.precond == 1);
+           (s.precond == 0 || s.precond == 1) && s.dblock >= 1 && s.dblock <= kFarMaxBlock;
 }
 
 void drop_graphs(etaim_ctx* c) {
@@ -94,6 +94,8 @@ void put_shape(etaim_ctx* c, const Shape& s) {
     c->x_engine = s.xeng;
     c->guess_order = s.guess;
     c->precond = s.precond;
+    if (c->delay_block != s.dblock) c->far_r0 = -1;
+    c->delay_block = s.dblock;
     drop_graphs(c);  // captured steps hold the old launch shapes
 }
 
@@ -111,6 +113,7 @@ Shape get_shape(const etaim_ctx* c) {
     s.xeng = c->x_engine;
     s.guess = c->guess_order;
     s.precond = c->precond;
+    s.dblock = c->delay_block;
     return s;
 }
 
@@ -129,6 +132,7 @@ void shape_to_c(const etaim_ctx* c, const Shape& s, etaim_tuning* t) {
     t->x_engine = s.xeng;
     t->guess_order = s.guess;
     t->precond = s.precond;
+    t->delay_block = s.dblock;
 }
 
 // EINVAL for malformed plans; shape_fits decides EUNSUPPORTED afterwards
@@ -159,6 +163,7 @@ int shape_from_c(const etaim_ctx* c, const etaim_tuning* t, Shape& s) {
     s.xeng = t->x_engine;
     s.guess = t->guess_order;
     s.precond = t->precond;
+    s.dblock = t->delay_block;
     return ETAIM_OK;
 }
 
@@ -210,13 +215,14 @@ bool cache_lookup(const char* path, const std::string& key, etaim_tuning& t) {
         line = buf;
         if (line.find("\"key\": \"" + key + "\"") == std::string::npos) continue;
         std::memset(&t, 0, sizeof t);
-        long v[9];
+        long v[10];
         if (json_ints(line, "radix_x", t.radix[0], 8) && json_ints(line, "radix_y", t.radix[1], 8) &&
             json_ints(line, "radix_z", t.radix[2], 8) && json_int(line, "gather_rows", v[0]) &&
             json_int(line, "lines_per_block", v[1]) && json_int(line, "interp_waves", v[2]) &&
             json_int(line, "sync_every", v[3]) && json_int(line, "graph", v[4]) &&
             json_int(line, "yz_engine", v[5]) && json_int(line, "x_engine", v[6]) &&
-            json_int(line, "guess_order", v[7]) && json_int(line, "precond", v[8])) {
+            json_int(line, "guess_order", v[7]) && json_int(line, "precond", v[8]) &&
+            json_int(line, "delay_block", v[9])) {
             t.gather_rows = (int)v[0];
             t.lines_per_block = (int)v[1];
             t.interp_waves = (int)v[2];
@@ -226,6 +232,7 @@ bool cache_lookup(const char* path, const std::string& key, etaim_tuning& t) {
             t.x_engine = (int)v[6];
             t.guess_order = (int)v[7];
             t.precond = (int)v[8];
+            t.delay_block = (int)v[9];
             found = true;  // the last matching record wins
         }
     }
@@ -244,9 +251,9 @@ int cache_append(const char* path, const std::string& key, const etaim_tuning& t
     std::fprintf(f,
                  "{\"key\": \"%s\", \"radix_x\": %s, \"radix_y\": %s, \"radix_z\": %s, \"gather_rows\": %d, "
                  "\"lines_per_block\": %d, \"interp_waves\": %d, \"sync_every\": %d, \"graph\": %d, "
-                 "\"yz_engine\": %d, \"x_engine\": %d, \"guess_order\": %d, \"precond\": %d, \"apply_ms\": %.4f, \"solve_ms\": %.3f}\n",
+                 "\"yz_engine\": %d, \"x_engine\": %d, \"guess_order\": %d, \"precond\": %d, \"delay_block\": %d, \"apply_ms\": %.4f, \"solve_ms\": %.3f}\n",
                  key.c_str(), arr(t.radix[0]).c_str(), arr(t.radix[1]).c_str(), arr(t.radix[2]).c_str(),
-                 t.gather_rows, t.lines_per_block, t.interp_waves, t.sync_every, t.graph, t.yz_engine, t.x_engine, t.guess_order, t.precond, t.apply_ms,
+                 t.gather_rows, t.lines_per_block, t.interp_waves, t.sync_every, t.graph, t.yz_engine, t.x_engine, t.guess_order, t.precond, t.delay_block, t.apply_ms,
                  t.solve_ms);
     std::fclose(f);
     return ETAIM_OK;
@@ -290,6 +297,25 @@ int time_solve(etaim_ctx* c, TuneBufs& b, double& ms, int& iters) {
     HIPCHK(hipEventElapsedTime(&t, b.e0, b.e1));
     ms = t;
     iters = res.iters;
+    return ETAIM_OK;
+}
+
+// history sums at 24 consecutive steps past N_g (every block length up to 8
+// but 5 and 7 divides 24) over the ring as it stands; the block sums are
+// dropped before and after, so a march that follows starts its own
+template <typename R>
+int time_delayed(etaim_ctx* c, TuneBufs& b, double& ms) {
+    const int ng = c->st.ng, k = 24;
+    c->far_r0 = -1;
+    CHK(Ops<R>::delayed(c, ng + 1, c->zero, b.y, 0));
+    HIPCHK(hipEventRecord(b.e0, c->stream));
+    for (int i = 0; i < k; ++i) CHK(Ops<R>::delayed(c, ng + 2 + i, c->zero, b.y, 0));
+    HIPCHK(hipEventRecord(b.e1, c->stream));
+    HIPCHK(hipEventSynchronize(b.e1));
+    float t = 0;
+    HIPCHK(hipEventElapsedTime(&t, b.e0, b.e1));
+    ms = t / k;
+    c->far_r0 = -1;
     return ETAIM_OK;
 }
 
@@ -413,6 +439,24 @@ int autotune_impl(etaim_ctx* c, int budget_ms, etaim_tuning* out) {
     if (best.mr == 0) best.mr = auto_gather_rows<R>(c, best.rx);
     if (best.mt == 0) best.mt = lines_per_block<R>(best.rx);
     put_shape(c, best);
+    // time blocks of the delayed field (register engine only)
+    if (best.engine == 1 && c->st.ng > 2) {
+        double d_best = 0;
+        CHK(time_delayed<R>(c, b, d_best));
+        for (int pb : {1, 2, 3, 4, 5, 6, 7, 8}) {
+            Shape s = best;
+            s.dblock = pb;
+            if (pb == best.dblock || !shape_fits<R>(c, s) || spent() > budget_ms) continue;
+            put_shape(c, s);
+            double t = 0;
+            CHK(time_delayed<R>(c, b, t));
+            if (t < d_best) {
+                d_best = t;
+                best.dblock = pb;
+            }
+        }
+        put_shape(c, best);
+    }
     // GMRES schedule: solves of the seeded right-hand side (identical
     // iterates whatever the schedule; only the time differs)
     double s_best = 0;

@@ -98,6 +98,64 @@ def test_delayed_field_level4(torch, prec, tol, engine, batch):
     P.close()
 
 
+@functools.lru_cache(maxsize=None)
+def _delayed_ref_level4(batch):
+    s, A, p = _oracle_far(L4)
+    ng = p["ng"]
+    hist = W.complex_normal(36, (ng, batch, s.ns))
+    hist[:A.mn] = 0.0
+    ref = np.array([sum(A.far_matvec(m, hist[m - 1, j]) for m in range(A.mn + 1, ng + 1)) for j in range(batch)])
+    return hist, ref
+
+
+@pytest.mark.parametrize("block", [1, 3, 5, 8])
+@pytest.mark.parametrize("prec,tol,batch", [(0, 1e-12, 1), (1, 1e-5, 2)], ids=["fp64", "fp32_pairs"])
+def test_delayed_time_blocks_level4(torch, prec, tol, batch, block):
+    """The register engine sums, in time blocks of that many steps, the
+    history older than a block once at its first step and the block's own
+    steps at every step; the delayed field at step N_g then stands at block
+    position (N_g - 1) mod block (7 of 8 at block 8: seven own steps, the
+    rest from the block pass), which the oracle's direct sum checks."""
+    s, A, p = _oracle_far(L4)
+    hist, ref = _delayed_ref_level4(batch)
+    P = gpu_problem(L4, precision=prec, batch=batch, nt=8)
+    _with_engine(P, 1)
+    d = P.tuning()
+    d["delay_block"] = block
+    P.set_tuning(d)
+    assert P.tuning()["delay_block"] == block
+    b = P.delayed_field(_dev(torch, hist)).cpu().numpy()
+    e = rel(b, ref)
+    _say("L4 delayed blocks", block, "fp32" if prec else "fp64", "rel", e)
+    assert e <= tol
+    P.close()
+
+
+def test_time_blocks_give_the_same_march(torch):
+    """Marches with the history sum in time blocks of 2 and 3 steps (N_g = 4
+    at level 2) against the direct sum at every step."""
+    wl = W.SPHERE_L2
+    s, A, vals, p = oracle_aim(L2)
+    assert p["ng"] == 4
+    from oracle import excitation
+    kh = W.unit_vectors(37, 2, 3)
+    pp = W.polarisations(37, kh)
+    V = excitation.excitation(s, 24, p["dt"], kh, pp, wl.sigma, wl.td, wl.f0)
+    out = []
+    for block in (1, 2, 3):
+        P = gpu_problem(L2, nt=24, batch=2, tol=1e-13)
+        _with_engine(P, 1)
+        d = P.tuning()
+        d["delay_block"] = block
+        P.set_tuning(d)
+        I, _ = P.march(_dev(torch, V))
+        out.append(I.cpu().numpy())
+        P.close()
+    for o in out[1:]:
+        _say("L2 march blocks rel", rel(o, out[0]))
+        assert rel(o, out[0]) <= 1e-11
+
+
 @pytest.mark.parametrize("engine", ENGINES, ids=[f"yz{a}_x{b}" for a, b in ENGINES])
 def test_engines_full_operator_level2(torch, engine):
     """Every Z_m (near + far) and the delayed field at the 16^3 grid."""

@@ -137,7 +137,8 @@ def test_set_tuning_rejects_bad_settings(torch):
     P = gpu_problem(W.SPHERE_L2.name)
     base = P.tuning()
     for bad, code in ((dict(radix_x=[5, 6]), -1), (dict(radix_x=[16]), -1), (dict(interp_waves=5), -7),
-                      (dict(gather_rows=0), -1), (dict(sync_every=1000), -7)):
+                      (dict(gather_rows=0), -1), (dict(sync_every=1000), -7),
+                      (dict(delay_block=0), -7), (dict(delay_block=9), -7)):
         d = dict(base)
         d.update(bad)
         with pytest.raises(Exception) as ei:
