@@ -522,6 +522,112 @@ __global__ void __launch_bounds__(kQuadThreads) k_yzq_green(cplx<R>* __restrict_
     quad_sum_store<R, N>(t0, pl, twy);
 }
 
+// Matvec y/z stage with the z lines first: two N x (N+1) tiles (one per
+// z parity pz) instead of four quadrant tiles, so that four blocks share a
+// CU in FP32 at N = 48.  With kz = 2 kz' + pz and ky = 2 ky' + py:
+//  1. task (pz, y): column y of the plane (read from HBM), times
+//     w_{2N}^{pz z}, N-point DFT over z -> column y of tile pz (rows kz');
+//  2. task (pz, py, kz'): row kz' of tile pz times w_{2N}^{py y}, DFT over
+//     y, Green product, inverse DFT, times conj(w_{2N}^{py y}); the two py
+//     rows are summed back into row kz' of tile pz;
+//  3. task (pz, y): inverse DFT of column y of tile pz over kz', times
+//     conj(w_{2N}^{pz z}); the two pz columns are summed into the plane.
+// GT is the Green table with ky and kz exchanged ([ky fold][kz fold] per
+// plane), so that the lanes of phase 2 (consecutive kz') read neighbouring
+// entries.  Threads: 4N (2N busy in phases 1 and 3); in FP32 the registers
+// are capped for three waves per SIMD (four blocks per CU at N = 48).
+template <typename R, int N>
+__global__ void __launch_bounds__(4 * N) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 3 : 1))) k_yzc_green(cplx<R>* __restrict__ A, const cplx<R>* __restrict__ GT,
+                                                     const cplx<R>* __restrict__ twy,
+                                                     const cplx<R>* __restrict__ twz, GridDims g, int conj_g,
+                                                     const int* __restrict__ gate) {
+    if (gated_off(gate)) return;
+    extern __shared__ unsigned char smem_raw[];
+    cplx<R>* t0 = reinterpret_cast<cplx<R>*>(smem_raw);
+    const int bc = blockIdx.x, kx = blockIdx.y, Lx = g.L[0];
+    cplx<R>* pl = A + ((size_t)bc * Lx + kx) * (size_t)(N * N);
+    const int i = threadIdx.x;
+    cplx<R> u[N];
+    if (i < 2 * N) {
+        const int pz = i / N, y = i - pz * N;
+#pragma unroll
+        for (int z = 0; z < N; ++z) u[z] = pl[z * N + y];
+        if (pz) {
+#pragma unroll
+            for (int z = 0; z < N; ++z) u[z] = cmul_fma(u[z], twz[z]);
+        }
+        dft_small<R, N>(u, false);
+        tile_col<R, N>(qtile<R, N>(t0, pz), y, u, true);
+    }
+    __syncthreads();
+    const int pz2 = i / (2 * N), py = (i / N) & 1, kz = i % N;
+    {
+        const int gx = g.N[0] + 1, gg = N + 1;
+        const cplx<R>* Gk = GT + ((size_t)((bc & 3) == 3 ? 1 : 0) * gx + fold(kx, Lx)) * (size_t)(gg * gg);
+        const int zf = fold(2 * kz + pz2, 2 * N);
+        tile_row<R, N>(qtile<R, N>(t0, pz2), kz, u, false);
+        if (py) {
+#pragma unroll
+            for (int y = 0; y < N; ++y) u[y] = cmul_fma(u[y], twy[y]);
+        }
+        dft_small<R, N>(u, false);
+#pragma unroll
+        for (int c = 0; c < N; ++c) {
+            cplx<R> gv = Gk[fold(2 * c + py, 2 * N) * gg + zf];
+            if (conj_g) gv.y = -gv.y;
+            u[c] = cmul_fma(u[c], gv);
+        }
+        dft_small<R, N>(u, true);
+        if (py) {
+#pragma unroll
+            for (int y = 0; y < N; ++y) u[y] = cmul_fma(u[y], conjz(twy[y]));
+        }
+    }
+    __syncthreads();
+    cplx<R>* row = qtile<R, N>(t0, pz2) + kz * (N + 1);
+    if (py == 0) {
+#pragma unroll
+        for (int y = 0; y < N; ++y) row[y] = u[y];
+    }
+    __syncthreads();
+    if (py == 1) {
+#pragma unroll
+        for (int y = 0; y < N; ++y) row[y] += u[y];
+    }
+    __syncthreads();
+    if (i < 2 * N) {
+        const int pz = i / N, y = i - pz * N;
+        tile_col<R, N>(qtile<R, N>(t0, pz), y, u, false);
+        dft_small<R, N>(u, true);
+        if (pz) {
+#pragma unroll
+            for (int z = 0; z < N; ++z) u[z] = cmul_fma(u[z], conjz(twz[z]));
+        }
+        tile_col<R, N>(qtile<R, N>(t0, pz), y, u, true);
+    }
+    __syncthreads();
+    // quarter h of the z range of column y: the two parities summed
+    {
+        const int h = i / N, y = i - h * N;
+        const cplx<R>* c0 = qtile<R, N>(t0, 0);
+        const cplx<R>* c1 = qtile<R, N>(t0, 1);
+#pragma unroll
+        for (int z = h * (N / 4); z < (h + 1) * (N / 4); ++z)
+            pl[z * N + y] = c0[z * (N + 1) + y] + c1[z * (N + 1) + y];
+    }
+}
+
+// GT[p][a][b] = G[p][b][a] for the n x n planes p of a folded Green table
+template <typename R>
+__global__ void k_green_transpose(const cplx<R>* __restrict__ G, cplx<R>* __restrict__ GT, size_t planes, int n) {
+    const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    const size_t nn = (size_t)n * n;
+    if (i >= planes * nn) return;
+    const size_t p = i / nn;
+    const int r = (int)(i - p * nn), a = r / n, b = r - a * n;
+    GT[i] = G[p * nn + (size_t)b * n + a];
+}
+
 // Commit y/z stage on the register path: forward transforms of the plane
 // into a quadrant-major ring slot plane.
 template <typename R, int N>

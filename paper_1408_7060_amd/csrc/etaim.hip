@@ -73,6 +73,7 @@ struct etaim_ctx {
     double *Sq = nullptr, *rq = nullptr;
     // working-precision arrays (float or double)
     void *lam_r = nullptr, *nw_r = nullptr, *near_r = nullptr, *nearT_r = nullptr, *ghat_r = nullptr, *tw_r[3] = {};
+    void* ghatT_r = nullptr;  // ky/kz-exchanged copy for the z-lines-first plane kernel
     void *A = nullptr, *P = nullptr, *ring = nullptr;
     zd* hist = nullptr;  // [mn][ns][B] in the working precision (sized for complex128)
     // Krylov (FP64)
@@ -96,7 +97,7 @@ struct etaim_ctx {
     std::vector<hipGraphExec_t> graphs[2];  // [conj][j]
     // launch shapes (0 = automatic); the autotuner sets them
     int gather_rows_t = 0, lines_x_t = 0, interp_waves = 4;
-    int yz_engine = 0;  // 0: LDS plane kernels, 1: register quadrant kernels
+    int yz_engine = 0;  // 0: LDS plane kernels, 1: register quadrant kernels, 2: as 1 with the z-lines-first matvec plane kernel
     int guess_order = 4;  // solutions extrapolated into a step's initial guess (0..4)
     int x_engine = 0;   // 0: LDS line kernels, 1: register line kernels
     void* xs = nullptr; // [ns][B] scaled columns for the register anterpolation
@@ -253,6 +254,7 @@ struct Ops {
     static cplx<R>* P(etaim_ctx* c) { return (cplx<R>*)c->P; }
     static const cplx<R>* tw(etaim_ctx* c, int a) { return (const cplx<R>*)c->tw_r[a]; }
     static const cplx<R>* ghat(etaim_ctx* c) { return (const cplx<R>*)c->ghat_r; }
+    static const cplx<R>* ghatT(etaim_ctx* c) { return (const cplx<R>*)c->ghatT_r; }
     // near-zone values; the adjoint (conjugated) operators use the transposed
     // values: the exact entries are symmetric only up to quadrature
     static const cplx<R>* nearv(etaim_ctx* c, int conj) {
@@ -328,11 +330,25 @@ struct Ops {
         return ((size_t)c->gd.L[2] * (c->gd.L[1] + 1) + c->gd.L[1] + c->gd.L[2]) * sizeof(cplx<R>);
     }
     static size_t quad_lds(etaim_ctx* c) { return (size_t)4 * quad_n(c) * (quad_n(c) + 1) * sizeof(cplx<R>); }
+    static size_t zline_lds(etaim_ctx* c) { return (size_t)2 * quad_n(c) * (quad_n(c) + 1) * sizeof(cplx<R>); }
     static int yz_green(etaim_ctx* c, int m, int conj, const int* gate = nullptr) {
         const GridDims& g = c->gd;
         dim3 grid(g.L[0], 4 * c->B);
         const double s = sizeof(cplx<R>);
         Trace t(c, ETAIM_K_YZ_GREEN, 2.0 * 4 * c->B * g.L[0] * g.N[2] * g.N[1] * s + 2.0 * c->gfold * s);
+        if (c->yz_engine == 2) {
+            const cplx<R>* G = ghatT(c) + (size_t)m * 2 * c->gfold;
+            const size_t lds = zline_lds(c);
+            grid = dim3(4 * c->B, g.L[0]);
+            switch (quad_n(c)) {
+                case 16: hipLaunchKernelGGL((k_yzc_green<R, 16>), grid, dim3(4 * 16), lds, c->stream, A(c), G, tw(c, 1), tw(c, 2), g, conj, gate); break;
+                case 24: hipLaunchKernelGGL((k_yzc_green<R, 24>), grid, dim3(4 * 24), lds, c->stream, A(c), G, tw(c, 1), tw(c, 2), g, conj, gate); break;
+                case 48: hipLaunchKernelGGL((k_yzc_green<R, 48>), grid, dim3(4 * 48), lds, c->stream, A(c), G, tw(c, 1), tw(c, 2), g, conj, gate); break;
+                default: return fail(ETAIM_EUNSUPPORTED, "register plane kernels need N_y = N_z in {16, 24, 48}");
+            }
+            HIPCHK(hipGetLastError());
+            return ETAIM_OK;
+        }
         if (c->yz_engine == 1) {
             const cplx<R>* G = ghat(c) + (size_t)m * 2 * c->gfold;
             const size_t lds = quad_lds(c);
@@ -391,7 +407,7 @@ struct Ops {
         // older than r0 (m > j) are summed for the whole block at its first step, the
         // j terms of the block's own steps at the step itself
         const int pb = c->delay_block;
-        const bool blocked = c->yz_engine == 1 && cur >= 1 && pb > 1 && ng <= kFarMaxNg && pb <= kFarMaxBlock;
+        const bool blocked = c->yz_engine >= 1 && cur >= 1 && pb > 1 && ng <= kFarMaxNg && pb <= kFarMaxBlock;
         const int r0 = blocked ? cur - (cur - 1) % pb : 0;
         const bool far_pass = blocked && c->far_r0 != r0;
         const int nmx = blocked ? std::min(cur - r0, ng) : nm;
@@ -401,7 +417,7 @@ struct Ops {
             if (blocked) bytes += slot_b;
             if (far_pass) bytes += std::min(ng, r0) * slot_b + ng * green_b + pb * slot_b;
             Trace t(c, ETAIM_K_YZ_DELAYED, bytes);
-            if (c->yz_engine == 1) {
+            if (c->yz_engine >= 1) {
                 const size_t slot = (size_t)4 * c->B * c->Np;
                 const cplx<R>* Fj = nullptr;
                 if (blocked) {
@@ -472,7 +488,7 @@ struct Ops {
         {
             const double s = sizeof(cplx<R>);
             Trace t(c, ETAIM_K_YZ_COMMIT, 4.0 * c->B * g.L[0] * g.N[2] * g.N[1] * s + 4.0 * c->B * c->Np * s);
-            if (c->yz_engine == 1) {
+            if (c->yz_engine >= 1) {
                 const dim3 grid(4 * c->B, g.L[0]);
                 const size_t lds = quad_lds(c);
                 const cplx<R>* a = (const cplx<R>*)A(c);
@@ -866,6 +882,15 @@ int make_working(etaim_ctx* c) {
         c->near_r = nearv;
         c->ghat_r = gh;
     }
+    if (const int qn = quad_n(c)) {
+        const size_t planes = (size_t)(c->st.ng + 1) * 2 * (c->gd.N[0] + 1), n1 = (size_t)qn + 1;
+        cplx<R>* gt = nullptr;
+        CHK(c->alloc(gt, planes * n1 * n1));
+        hipLaunchKernelGGL(k_green_transpose<R>, dim3(blocks_for(planes * n1 * n1)), dim3(256), 0, c->stream,
+                           (const cplx<R>*)c->ghat_r, gt, planes, (int)n1);
+        HIPCHK(hipGetLastError());
+        c->ghatT_r = gt;
+    }
     for (int a = 0; a < 3; ++a) {
         const int L = c->gd.L[a];
         std::vector<cplx<R>> tw(L);
@@ -1115,7 +1140,7 @@ int etaim_create(etaim_ctx** out, const etaim_mesh* mesh, const etaim_rwg* rwg, 
     c->rx = make_radix(c->gd.L[0]);
     c->ry = make_radix(c->gd.L[1]);
     c->rz = make_radix(c->gd.L[2]);
-    c->yz_engine = quad_n(c.get()) ? 1 : 0;
+    c->yz_engine = quad_n(c.get()) ? 2 : 0;
     c->x_engine = xline_n(c.get()) ? 1 : 0;
     c->N3 = (size_t)c->gd.N[0] * c->gd.N[1] * c->gd.N[2];
     c->Np = (size_t)c->gd.L[0] * c->gd.L[1] * c->gd.L[2];

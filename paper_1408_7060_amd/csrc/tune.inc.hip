@@ -68,7 +68,7 @@ bool shape_fits(const etaim_ctx* c, const Shape& s) {
     return plane_fits(g.N[2], s.ry) && plane_fits(g.L[1], s.rz) && plane_fits(4 * mr, s.rx) &&
            plane_fits(mt, s.rx) && (4 * (size_t)mr * (Lx + 1) + Lx) * e <= 160 * 1024 &&
            ((size_t)mt * (Lx + 1) + Lx) * e <= (size_t)kLdsBudget && s.waves >= 1 && s.waves <= 4 &&
-           s.sync >= 1 && s.sync <= c->prm.restart && (s.engine == 0 || (s.engine == 1 && quad_n(c) > 0)) &&
+           s.sync >= 1 && s.sync <= c->prm.restart && (s.engine == 0 || ((s.engine == 1 || s.engine == 2) && quad_n(c) > 0)) &&
            (s.xeng == 0 || (s.xeng == 1 && xline_n(c) > 0)) && s.guess >= 0 && s.guess <= 4 &&
            (s.precond == 0 || s.precond == 1) && s.dblock >= 1 && s.dblock <= kFarMaxBlock;
 }
@@ -389,7 +389,7 @@ int autotune_impl(etaim_ctx* c, int budget_ms, etaim_tuning* out) {
         put_shape(c, best);
         return ETAIM_OK;
     };
-    for (int eng : {0, 1})
+    for (int eng : {0, 1, 2})
         if (eng != best.engine) {
             Shape s = best;
             s.engine = eng;
@@ -440,7 +440,7 @@ int autotune_impl(etaim_ctx* c, int budget_ms, etaim_tuning* out) {
     if (best.mt == 0) best.mt = lines_per_block<R>(best.rx);
     put_shape(c, best);
     // time blocks of the delayed field (register engine only)
-    if (best.engine == 1 && c->st.ng > 2) {
+    if (best.engine >= 1 && c->st.ng > 2) {
         double d_best = 0;
         CHK(time_delayed<R>(c, b, d_best));
         for (int pb : {1, 2, 3, 4, 5, 6, 7, 8}) {

@@ -1,6 +1,7 @@
-"""Both y/z plane engines (LDS-staged radix passes over the padded plane,
-and register-resident parity quadrants) against the FP64 oracle, through
-the C ABI.
+"""The y/z plane engines (LDS-staged radix passes over the padded plane,
+register-resident parity quadrants, and the same with the matvec plane
+transform taking the z lines first) against the FP64 oracle, through the
+C ABI.
 
 At the level-4 sphere (48^3 grid, the size the bench marches) the oracle's
 exact near-zone entries take minutes to assemble on the host, so the
@@ -58,7 +59,7 @@ def _with_engine(P, engine):
     assert (t["yz_engine"], t["x_engine"]) == (yz, xe)
 
 
-ENGINES = [(0, 0), (1, 1), (1, 0), (0, 1)]
+ENGINES = [(0, 0), (1, 1), (1, 0), (0, 1), (2, 1), (2, 0)]
 
 
 @pytest.mark.parametrize("engine", ENGINES, ids=[f"yz{a}_x{b}" for a, b in ENGINES])
