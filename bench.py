@@ -173,6 +173,9 @@ def main():
                     help="also time the march with Arnoldi steps replayed from HIP graphs (profiling off)")
     ap.add_argument("--tune-ms", type=int, default=4000,
                     help="autotuner budget before timing (0: keep the library's default shapes)")
+    ap.add_argument("--true-residual", action="store_true",
+                    help="confirm each step's convergence with a recomputed true residual (one operator "
+                         "application more per step) instead of stopping on the GMRES residual estimate")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="first copy this many MiB device-to-device (counter calibration)")
     args = ap.parse_args()
@@ -182,7 +185,8 @@ def main():
     import torch
     import workloads as W
     from paper_1408_7060_amd import FP32, FP64
-    from paper_1408_7060_amd._lib import F_GRAPH
+    from paper_1408_7060_amd._lib import F_CONTINUE_ON_NOCONV, F_GRAPH, F_IMPLICIT_STOP
+    fl = F_CONTINUE_ON_NOCONV | (0 if args.true_residual else F_IMPLICIT_STOP)
 
     wl = W.SPHERE_L4_BATCH if args.workload == "batch" else W.SPHERE_L4
     K = args.steps or wl.nt
@@ -198,7 +202,7 @@ def main():
         del src, dst
     log(f"[bench] set-up {wl.name}: B={wl.batch} nt={nt}")
     t = time.perf_counter()
-    P = make_problem(wl, FP32, wl.batch, nt, 1e-5, sync_every=args.sync_every)
+    P = make_problem(wl, FP32, wl.batch, nt, 1e-5, flags=fl, sync_every=args.sync_every)
     log(f"[bench] set-up {time.perf_counter() - t:.1f} s, info {P.info}")
     tuning = None
     if args.tune_ms:
@@ -260,6 +264,7 @@ def main():
            "vs_baseline": None, "dtype": "fp32 (grid/FFT/near) + fp64 (GMRES)", "data": "synthetic",
            "config": {"workload": wl.name, "ns": P.ns, "batch": wl.batch, "grid": wl.grid,
                       "sync_every": args.sync_every,
+                      "gmres_stop": "true_residual" if args.true_residual else "residual_estimate",
                       "padded": 2 * wl.grid, "ng": P.info["ng"], "mn": P.info["mn"], "nt": K, "tol": 1e-5,
                       "parallelism": "1 GPU"},
            "direction_steps_per_s": round(steps_s * wl.batch, 3),
@@ -276,7 +281,7 @@ def main():
     I32_0 = I32[:, 0].cpu().numpy()
     P.close()
     if args.graph or (tuning and tuning["graph"]):
-        Pg = make_problem(wl, FP32, wl.batch, nt, 1e-5, flags=1 | F_GRAPH, sync_every=args.sync_every)
+        Pg = make_problem(wl, FP32, wl.batch, nt, 1e-5, flags=fl | F_GRAPH, sync_every=args.sync_every)
         if tuning:
             Pg.set_tuning(dict(tuning, graph=1))
         if args.warmup:
@@ -294,7 +299,7 @@ def main():
     del V, I32
     torch.cuda.empty_cache()
     if not args.no_fp64:
-        P64 = make_problem(wl, FP64, 1, nt, 1e-5)
+        P64 = make_problem(wl, FP64, 1, nt, 1e-5, flags=fl)
         V64 = P64.excitation(kh[:1], pp[:1], wl.sigma, wl.td)
         if args.warmup:
             P64.march(V64, nsteps=args.warmup)
@@ -316,11 +321,11 @@ def main():
         # precision error apart from the GMRES tolerance: FP32 at tol 1e-7
         # against FP64 at tol 1e-12, direction 0, the first Kp steps
         Kp = min(K, 100)
-        Pt = make_problem(wl, FP64, 1, nt, 1e-12)
+        Pt = make_problem(wl, FP64, 1, nt, 1e-12, flags=fl)
         It64, _ = Pt.march(V64, nsteps=Kp)
         It64 = It64[:Kp, 0].cpu().numpy()
         Pt.close()
-        Pt = make_problem(wl, FP32, 1, nt, 1e-7)
+        Pt = make_problem(wl, FP32, 1, nt, 1e-7, flags=fl)
         It32, _ = Pt.march(V64, nsteps=Kp)
         It32 = It32[:Kp, 0].cpu().numpy()
         Pt.close()

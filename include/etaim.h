@@ -60,6 +60,11 @@ extern "C" {
 #define ETAIM_F_GRAPH 4              /* capture each Arnoldi step j of the batched GMRES once as a
                                         HIP graph and replay it (device-side gating, see sync_every);
                                         while profiling is on the same steps run as direct launches */
+#define ETAIM_F_IMPLICIT_STOP 8      /* end a step's GMRES as soon as every column's Givens residual
+                                        estimate meets the tolerance; without it the solver
+                                        recomputes the true residual b - Z x at a new cycle start
+                                        and stops only if that meets the tolerance too (one operator
+                                        application more per step) */
 
 typedef struct etaim_ctx etaim_ctx;
 

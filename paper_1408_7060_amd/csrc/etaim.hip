@@ -703,8 +703,12 @@ int gmres(etaim_ctx* c, const zd* rhs, zd* x, int conj, StepResult& res) {
         }
         HIPCHK(hipGetLastError());
         if (res.nonfinite) break;
+        // every column converged by its Arnoldi residual estimate: done, unless
+        // the true residual is to confirm it at a new cycle start
+        if ((c->prm.flags & ETAIM_F_IMPLICIT_STOP) && c->flag_h[0] == 0) break;
     }
-    // final residual estimate (true residual of the last cycle start)
+    // final residual: the true residual of the last cycle start, or the
+    // Arnoldi estimate of the last step under ETAIM_F_IMPLICIT_STOP
     std::vector<double> rr(B);
     HIPCHK(hipMemcpyAsync(rr.data(), c->resid, B * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));

@@ -227,3 +227,26 @@ def test_preconditioners_agree(torch, name, prec, tol, bound, adjoint):
     e = float(np.linalg.norm(out[1][0] - out[0][0]) / np.linalg.norm(out[0][0]))
     assert e <= bound, e
     assert out[1][1] < out[0][1]
+
+
+@pytest.mark.parametrize("name,prec,tol,bound", [(W.SPHERE_L2.name, 0, 1e-12, 1e-11),
+                                                 (W.SPHERE_L3.name, 1, 1e-6, 1e-5)])
+@pytest.mark.parametrize("adjoint", [False, True], ids=["forward", "adjoint"])
+def test_implicit_stop(torch, name, prec, tol, bound, adjoint):
+    """Stopping on the GMRES residual estimate (no confirming true residual)
+    keeps the Arnoldi iterations of every step and the march within the
+    tolerance of the confirmed one; every step's reported residual is the
+    estimate, below the tolerance."""
+    F_IMPLICIT_STOP = 8
+    V = _excitation(name, 16, 3, 43)
+    common = dict(precision=prec, tol=tol, adjoint=adjoint)
+    (I0, it0, per0), = _march(torch, name, V, flags=F_CONTINUE_ON_NOCONV, **common)
+    P = gpu_problem(name, nt=V.shape[0], batch=V.shape[1], flags=F_CONTINUE_ON_NOCONV | F_IMPLICIT_STOP,
+                    precision=prec, tol=tol)
+    Vd = torch.from_numpy(np.ascontiguousarray(V)).cuda()
+    I1, st = (P.adjoint_march(Vd) if adjoint else P.march(Vd))
+    P.close()
+    _say("implicit stop", name, "iters", st["total_iters"], "vs", it0, "max resid", st["max_rel_residual"])
+    assert st["total_iters"] <= it0
+    assert st["max_rel_residual"] <= tol
+    assert rel(I1.cpu().numpy(), I0) <= bound
