@@ -617,6 +617,54 @@ __global__ void __launch_bounds__(4 * N) __attribute__((amdgpu_waves_per_eu(size
     }
 }
 
+// Commit y/z stage with the z lines first (two tiles, as k_yzc_green):
+// z columns per parity into the tiles, then the row tasks (pz, py, kz')
+// transform their rows; the py = 0 rows, then the py = 1 rows go back into
+// the tiles and out to the ring slot's quadrants q = 2 pz + py (coalesced).
+template <typename R, int N>
+__global__ void __launch_bounds__(4 * N) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 3 : 1)))
+k_yzc_commit(const cplx<R>* __restrict__ A, cplx<R>* __restrict__ slot, const cplx<R>* __restrict__ twy,
+             const cplx<R>* __restrict__ twz, GridDims g) {
+    extern __shared__ unsigned char smem_raw[];
+    cplx<R>* t0 = reinterpret_cast<cplx<R>*>(smem_raw);
+    constexpr int NN = N * N;
+    const int bc = blockIdx.x, kx = blockIdx.y, Lx = g.L[0];
+    const cplx<R>* pl = A + ((size_t)bc * Lx + kx) * (size_t)NN;
+    cplx<R>* out = slot + ((size_t)bc * Lx + kx) * (size_t)(4 * NN);
+    const int i = threadIdx.x;
+    cplx<R> u[N];
+    if (i < 2 * N) {
+        const int pz = i / N, y = i - pz * N;
+#pragma unroll
+        for (int z = 0; z < N; ++z) u[z] = pl[z * N + y];
+        if (pz) {
+#pragma unroll
+            for (int z = 0; z < N; ++z) u[z] = cmul_fma(u[z], twz[z]);
+        }
+        dft_small<R, N>(u, false);
+        tile_col<R, N>(qtile<R, N>(t0, pz), y, u, true);
+    }
+    __syncthreads();
+    const int pz2 = i / (2 * N), py = (i / N) & 1, kz = i % N;
+    tile_row<R, N>(qtile<R, N>(t0, pz2), kz, u, false);
+    __syncthreads();
+    if (py) {
+#pragma unroll
+        for (int y = 0; y < N; ++y) u[y] = cmul_fma(u[y], twy[y]);
+    }
+    dft_small<R, N>(u, false);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        if (py == h) tile_row<R, N>(qtile<R, N>(t0, pz2), kz, u, true);
+        __syncthreads();
+        for (int e = i; e < 2 * NN; e += 4 * N) {
+            const int pz = e / NN, r = e - pz * NN;
+            out[(size_t)(2 * pz + h) * NN + r] = qtile<R, N>(t0, pz)[(r / N) * (N + 1) + r % N];
+        }
+        __syncthreads();
+    }
+}
+
 // GT[p][a][b] = G[p][b][a] for the n x n planes p of a folded Green table
 template <typename R>
 __global__ void k_green_transpose(const cplx<R>* __restrict__ G, cplx<R>* __restrict__ GT, size_t planes, int n) {

@@ -97,7 +97,7 @@ struct etaim_ctx {
     std::vector<hipGraphExec_t> graphs[2];  // [conj][j]
     // launch shapes (0 = automatic); the autotuner sets them
     int gather_rows_t = 0, lines_x_t = 0, interp_waves = 4;
-    int yz_engine = 0;  // 0: LDS plane kernels, 1: register quadrant kernels, 2: as 1 with the z-lines-first matvec plane kernel
+    int yz_engine = 0;  // 0: LDS plane kernels, 1: register quadrant kernels, 2: as 1 with z-lines-first matvec and commit
     int guess_order = 4;  // solutions extrapolated into a step's initial guess (0..4)
     int x_engine = 0;   // 0: LDS line kernels, 1: register line kernels
     void* xs = nullptr; // [ns][B] scaled columns for the register anterpolation
@@ -488,7 +488,17 @@ struct Ops {
         {
             const double s = sizeof(cplx<R>);
             Trace t(c, ETAIM_K_YZ_COMMIT, 4.0 * c->B * g.L[0] * g.N[2] * g.N[1] * s + 4.0 * c->B * c->Np * s);
-            if (c->yz_engine >= 1) {
+            if (c->yz_engine == 2) {
+                const dim3 grid(4 * c->B, g.L[0]);
+                const size_t lds = zline_lds(c);
+                const cplx<R>* a = (const cplx<R>*)A(c);
+                switch (quad_n(c)) {
+                    case 16: hipLaunchKernelGGL((k_yzc_commit<R, 16>), grid, dim3(4 * 16), lds, c->stream, a, slot, tw(c, 1), tw(c, 2), g); break;
+                    case 24: hipLaunchKernelGGL((k_yzc_commit<R, 24>), grid, dim3(4 * 24), lds, c->stream, a, slot, tw(c, 1), tw(c, 2), g); break;
+                    case 48: hipLaunchKernelGGL((k_yzc_commit<R, 48>), grid, dim3(4 * 48), lds, c->stream, a, slot, tw(c, 1), tw(c, 2), g); break;
+                    default: return fail(ETAIM_EUNSUPPORTED, "register plane kernels need N_y = N_z in {16, 24, 48}");
+                }
+            } else if (c->yz_engine == 1) {
                 const dim3 grid(4 * c->B, g.L[0]);
                 const size_t lds = quad_lds(c);
                 const cplx<R>* a = (const cplx<R>*)A(c);
@@ -522,7 +532,10 @@ struct Ops {
                               (const void*)k_yzq_commit<R, 24>, (const void*)k_yzq_commit<R, 48>,
                               (const void*)k_yzq_delayed<R, 16>, (const void*)k_yzq_delayed<R, 24>,
                               (const void*)k_yzq_delayed<R, 48>, (const void*)k_yzq_delayed1<R, 16>,
-                              (const void*)k_yzq_delayed1<R, 24>, (const void*)k_yzq_delayed1<R, 48>})
+                              (const void*)k_yzq_delayed1<R, 24>, (const void*)k_yzq_delayed1<R, 48>,
+                              (const void*)k_yzc_green<R, 16>, (const void*)k_yzc_green<R, 24>,
+                              (const void*)k_yzc_green<R, 48>, (const void*)k_yzc_commit<R, 16>,
+                              (const void*)k_yzc_commit<R, 24>, (const void*)k_yzc_commit<R, 48>})
             HIPCHK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
         // the gather's LDS grows with its tuned row count
         HIPCHK(hipFuncSetAttribute((const void*)k_fwdx_gather<R>, hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -80,7 +80,8 @@ def test_far_operator_level4(torch, prec, tol, engine):
     P.close()
 
 
-@pytest.mark.parametrize("engine,batch", [(0, 1), (1, 1), (1, 2)], ids=["lds", "reg", "reg_pairs"])
+@pytest.mark.parametrize("engine,batch", [(0, 1), (1, 1), (1, 2), ((2, 1), 1), ((2, 1), 2)],
+                         ids=["lds", "reg", "reg_pairs", "zlines", "zlines_b2"])
 @pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-5)], ids=["fp64", "fp32"])
 def test_delayed_field_level4(torch, prec, tol, engine, batch):
     """batch 2 runs the plane-pair delayed kernel in FP32 (two planes share
@@ -110,8 +111,9 @@ def _delayed_ref_level4(batch):
 
 
 @pytest.mark.parametrize("block", [1, 3, 5, 8])
-@pytest.mark.parametrize("prec,tol,batch", [(0, 1e-12, 1), (1, 1e-5, 2)], ids=["fp64", "fp32_pairs"])
-def test_delayed_time_blocks_level4(torch, prec, tol, batch, block):
+@pytest.mark.parametrize("engine", [1, (2, 1)], ids=["reg", "zlines"])
+@pytest.mark.parametrize("prec,tol,batch", [(0, 1e-12, 1), (1, 1e-5, 2)], ids=["fp64", "fp32_b2"])
+def test_delayed_time_blocks_level4(torch, prec, tol, batch, engine, block):
     """The register engine sums, in time blocks of that many steps, the
     history older than a block once at its first step and the block's own
     steps at every step; the delayed field at step N_g then stands at block
@@ -120,14 +122,14 @@ def test_delayed_time_blocks_level4(torch, prec, tol, batch, block):
     s, A, p = _oracle_far(L4)
     hist, ref = _delayed_ref_level4(batch)
     P = gpu_problem(L4, precision=prec, batch=batch, nt=8)
-    _with_engine(P, 1)
+    _with_engine(P, engine)
     d = P.tuning()
     d["delay_block"] = block
     P.set_tuning(d)
     assert P.tuning()["delay_block"] == block
     b = P.delayed_field(_dev(torch, hist)).cpu().numpy()
     e = rel(b, ref)
-    _say("L4 delayed blocks", block, "fp32" if prec else "fp64", "rel", e)
+    _say("L4 delayed blocks", block, "engine", engine, "fp32" if prec else "fp64", "rel", e)
     assert e <= tol
     P.close()
 
@@ -145,7 +147,7 @@ def test_time_blocks_give_the_same_march(torch):
     out = []
     for block in (1, 2, 3):
         P = gpu_problem(L2, nt=24, batch=2, tol=1e-13)
-        _with_engine(P, 1)
+        _with_engine(P, (2, 1))
         d = P.tuning()
         d["delay_block"] = block
         P.set_tuning(d)
