@@ -275,7 +275,9 @@ struct Ops {
     static size_t gather_lds(etaim_ctx* c) {
         return ((size_t)4 * gather_rows(c) * (c->gd.L[0] + 1) + c->gd.L[0]) * sizeof(cplx<R>);
     }
-    static int forward_x(etaim_ctx* c, const zd* x, const zd* dinv, int conj_in, const int* gate = nullptr) {
+    // xs_ready: the scaled columns are already in c->xs ([ns][B], register x stage only)
+    static int forward_x(etaim_ctx* c, const zd* x, const zd* dinv, int conj_in, const int* gate = nullptr,
+                         bool xs_ready = false) {
         const GridDims& g = c->gd;
         const int mr = gather_rows(c);
         dim3 grid((g.N[1] + mr - 1) / mr, g.N[2], c->B);
@@ -285,8 +287,9 @@ struct Ops {
                                          (dinv ? c->ns * 16.0 : 0.0));
         if (c->x_engine == 1) {
             cplx<R>* xs = (cplx<R>*)c->xs;
-            hipLaunchKernelGGL(k_prescale<R>, dim3(blocks_for(nB)), dim3(256), 0, c->stream, x, dinv, xs, c->ns, c->B,
-                               conj_in, gate);
+            if (!xs_ready)
+                hipLaunchKernelGGL(k_prescale<R>, dim3(blocks_for(nB)), dim3(256), 0, c->stream, x, dinv, xs, c->ns,
+                                   c->B, conj_in, gate);
             hipLaunchKernelGGL(k_anterp<R>, dim3((unsigned)((c->N3 + 255) / 256), (c->B + kAntCols - 1) / kAntCols),
                                dim3(256), 0, c->stream, xs, c->nptr, c->nk, (const R*)c->nw_r, P(c), g, c->B, gate);
             const dim3 gx((2 * g.N[1] * g.N[2] + 255) / 256, 4 * c->B);
@@ -391,9 +394,10 @@ struct Ops {
         return ETAIM_OK;
     }
     // y = conj?(Z_m) (dinv . x)
+    // (xs_ready: x is given as the scaled columns in c->xs, register x stage only)
     static int apply(etaim_ctx* c, int m, const zd* x, const zd* dinv, zd* y, int conj,
-                     const int* gate = nullptr) {
-        CHK(forward_x(c, x, dinv, 0, gate));
+                     const int* gate = nullptr, bool xs_ready = false) {
+        CHK(forward_x(c, x, dinv, 0, gate, xs_ready));
         CHK(yz_green(c, m, conj, gate));
         CHK(inverse_x(c, gate));
         return interp_near(c, 0, x, dinv, m, 0, 0, nullptr, y, conj, 0, gate);
@@ -565,7 +569,19 @@ int arnoldi_step(etaim_ctx* c, int j, int conj, const int* gate) {
     zd* vj = c->Vk + (size_t)j * nB;
     zd* vn = c->Vk + (size_t)(j + 1) * nB;
     if (gate) hipLaunchKernelGGL(k_gate, dim3(1), dim3(64), 0, c->stream, c->flag);
-    if (c->precond == 1) {
+    if (c->precond == 1 && c->x_engine == 1) {
+        // w = Z (M v_j), M the near-zone sparse approximate inverse (M^H for the
+        // adjoint): v_j transposed to [ns][B], then M v_j straight into the
+        // operator's scaled-column buffer
+        {
+            Trace tp(c, ETAIM_K_KRYLOV, (double)c->nnz * 20.0 + 2.0 * (double)nB * 16.0 + (double)nB * sizeof(cplx<R>));
+            hipLaunchKernelGGL(k_prescale<double>, dim3(blocks_for(nB)), dim3(256), 0, c->stream, vj, nullptr,
+                               (cplx<double>*)c->zt, ns, B, 0, gate);
+            hipLaunchKernelGGL(k_spmv_rows<R>, dim3(blocks_for(nB)), dim3(256), 0, c->stream, c->rowptr, c->col,
+                               conj ? c->saiT : c->sai, c->zt, (cplx<R>*)c->xs, ns, B, conj, gate);
+        }
+        CHK(Ops<R>::apply(c, 0, nullptr, nullptr, c->w, conj, gate, true));
+    } else if (c->precond == 1) {
         // w = Z (M v_j), M the near-zone sparse approximate inverse (M^H for the adjoint)
         {
             Trace tp(c, ETAIM_K_KRYLOV, (double)c->nnz * 20.0 + 2.0 * (double)nB * 16.0);

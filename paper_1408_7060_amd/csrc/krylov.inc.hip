@@ -231,6 +231,38 @@ __global__ void k_spmv_cols(const int* __restrict__ rowptr, const int* __restric
     }
 }
 
+// out[i][b] = (op(M) x)[b][i] in the working precision, the layout the
+// operator's anterpolation and near zone read, from the columns of x
+// transposed to xt[k][b] (FP64).  Lanes take consecutive columns b of a row:
+// each matrix entry is one broadcast load and each x row one coalesced run;
+// entries go in groups of four with their loads issued together.
+template <typename R>
+__global__ void __launch_bounds__(256) k_spmv_rows(const int* __restrict__ rowptr, const int* __restrict__ col,
+                                                   const zd* __restrict__ M, const zd* __restrict__ xt,
+                                                   cplx<R>* __restrict__ out, int ns, int B, int conj,
+                                                   const int* __restrict__ gate) {
+    if (gated_off(gate)) return;
+    const size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (e >= (size_t)ns * B) return;
+    const int i = (int)(e / B), b = (int)(e - (size_t)i * B);
+    const double sg = conj ? -1.0 : 1.0;
+    zd acc{0, 0};
+    const int q1 = rowptr[i + 1];
+    for (int q = rowptr[i]; q < q1; q += 4) {
+        zd v[4], xv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const bool live = q + u < q1;
+            const int cu = live ? col[q + u] : 0;
+            v[u] = live ? M[q + u] : zd{0, 0};
+            xv[u] = xt[(size_t)cu * B + b];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc += zd{v[u].x, sg * v[u].y} * xv[u];
+    }
+    out[e] = to_r<R>(acc);
+}
+
 // u[b] = sum_{i < jcnt[b]} y[b][i] V_i[b]  (the Krylov combination before a
 // right preconditioner that is not diagonal)
 __global__ void __launch_bounds__(256) k_krylov_combine(zd* __restrict__ u, const zd* __restrict__ V,
