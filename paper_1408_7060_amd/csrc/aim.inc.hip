@@ -1,7 +1,7 @@
 // ET-AIM grid kernels (Sec. 4 stages (i)-(iv)):
 //  k_fwdx_gather  anterpolation (node-major gather of the projection) fused
 //                 with the forward x-FFT of the zero-padded grid (LDS lines)
-//  k_prescale, k_anterp, k_xfwd, k_xinv
+//  k_prescale, k_anterp_nz, k_xfwd, k_xinv
 //                 the same x stage with register-resident lines: the
 //                 anterpolated grid goes through the P buffer
 //  k_yzq_*        register-resident parity-quadrant variants of the plane
@@ -105,81 +105,72 @@ __global__ void k_prescale(const zd* __restrict__ x, const zd* __restrict__ dinv
     }
 }
 
-// Anterpolation (Sec. 4 stage (i)): q_c[n] = sum_k Lambda^c_{k,n} xs[k] for
-// kAntCols columns per thread, one thread per grid node (z, x, y) from the
-// node-major projection (nptr, nk, nw[4]); no atomics.  Output q[bc][z][x][y].
-constexpr int kAntCols = 8;
+// Anterpolation (Sec. 4 stage (i)): q_c[n] = sum_k Lambda^c_{k,n} xs[k] from
+// the node-major projection (nptr, nk, nw[4]), no atomics, over the grid
+// nodes that some basis reaches (nodes[j], as the index t of q[bc][z][x][y]
+// within a component plane; the other nodes of q stay zero).  Thread (j, b),
+// columns b fastest, so that a wave shares the entry loads of a node and
+// reads each basis's columns as one run.
 template <typename R>
-__global__ void __launch_bounds__(256) k_anterp(const cplx<R>* __restrict__ xs, const int* __restrict__ nptr,
-                                                const int* __restrict__ nk, const R* __restrict__ nw,
-                                                cplx<R>* __restrict__ q, GridDims g, int B,
-                                                const int* __restrict__ gate) {
-#pragma clang fp contract(fast)  // fused multiply-adds: measured faster here
+__global__ void __launch_bounds__(256) k_anterp_nz(const cplx<R>* __restrict__ xs, const int* __restrict__ nodes,
+                                                   int nnodes, const int* __restrict__ nptr,
+                                                   const int* __restrict__ nk, const R* __restrict__ nw,
+                                                   cplx<R>* __restrict__ q, GridDims g, int B,
+                                                   const int* __restrict__ gate) {
+#pragma clang fp contract(fast)  // fused multiply-adds
     if (gated_off(gate)) return;
-    const int Nx = g.N[0], Ny = g.N[1], Nz = g.N[2];
-    const size_t N3 = (size_t)Nx * Ny * Nz;
-    const size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-    if (t >= N3) return;
-    const int b0 = blockIdx.y * kAntCols, nb = min(kAntCols, B - b0);
-    const int y = (int)(t % Ny);
-    const size_t r = t / Ny;
-    const int x = (int)(r % Nx), z = (int)(r / Nx);
+    const size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (e >= (size_t)nnodes * B) return;
+    const int j = (int)(e / B), b = (int)(e - (size_t)j * B);
+    const int Nx = g.N[0], Ny = g.N[1];
+    const size_t N3 = (size_t)Nx * Ny * g.N[2];
+    const int t = nodes[j], y = t % Ny, r = t / Ny, x = r % Nx, z = r / Nx;
     const size_t n = (size_t)x + (size_t)Nx * ((size_t)y + (size_t)Ny * z);
-    cplx<R> acc[kAntCols][4];
+    cplx<R> acc[4];
 #pragma unroll
-    for (int b = 0; b < kAntCols; ++b)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[b][c] = cplx<R>{0, 0};
-    // entries in groups of four with their loads issued together (the
-    // entry -> basis -> column chain is two dependent loads deep)
-    int e = nptr[n];
-    const int e1 = nptr[n + 1];
-    for (; e < e1; e += 4) {
+    for (int c = 0; c < 4; ++c) acc[c] = cplx<R>{0, 0};
+    const int p1 = nptr[n + 1];
+    for (int p = nptr[n]; p < p1; p += 4) {
         int k[4];
         R w[4][4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const bool live = e + u < e1;
-            k[u] = live ? nk[e + u] : 0;
+            const bool live = p + u < p1;
+            k[u] = live ? nk[p + u] : 0;
 #pragma unroll
-            for (int c = 0; c < 4; ++c) w[u][c] = live ? nw[4 * (size_t)(e + u) + c] : (R)0;
+            for (int c = 0; c < 4; ++c) w[u][c] = live ? nw[4 * (size_t)(p + u) + c] : (R)0;
         }
-        cplx<R> v[4][kAntCols];
+        cplx<R> v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = xs[(size_t)k[u] * B + b];
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
-            for (int b = 0; b < kAntCols; ++b) v[u][b] = b < nb ? xs[(size_t)k[u] * B + b0 + b] : cplx<R>{0, 0};
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-            if (e + u < e1)
-#pragma unroll
-                for (int b = 0; b < kAntCols; ++b)
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) acc[b][c] += w[u][c] * v[u][b];
+            for (int c = 0; c < 4; ++c) acc[c] += w[u][c] * v[u];
     }
 #pragma unroll
-    for (int b = 0; b < kAntCols; ++b)
-        if (b < nb)
-#pragma unroll
-            for (int c = 0; c < 4; ++c) q[((size_t)(b0 + b) * 4 + c) * N3 + t] = acc[b][c];
+    for (int c = 0; c < 4; ++c) q[((size_t)b * 4 + c) * N3 + t] = acc[c];
 }
 
 // Forward x transform of the zero-padded lines: A[bc][kx][z][y] =
 // sum_{x<N} q[bc][z][x][y] w_{2N}^{kx x}.  Lanes (2l, 2l+1) own line l =
 // (z, y) of one bc with parity p: kx = 2a + p is the N-point DFT of
-// q w_{2N}^{p x}.
+// q w_{2N}^{p x}.  Bit x of xmask[l] marks the nodes some basis reaches;
+// the others read the zero block zsrc instead (cached, no HBM traffic).
 template <typename R, int N>
 __global__ void __launch_bounds__(256) k_xfwd(const cplx<R>* __restrict__ q, cplx<R>* __restrict__ A, GridDims g,
-                                              const int* __restrict__ gate) {
+                                              const unsigned long long* __restrict__ xmask,
+                                              const cplx<R>* __restrict__ zsrc, const int* __restrict__ gate) {
     if (gated_off(gate)) return;
     const int Ny = g.N[1], Nz = g.N[2], nl = Ny * Nz, bc = blockIdx.y;
     const int tid = blockIdx.x * blockDim.x + threadIdx.x, line = tid >> 1, p = tid & 1;
     if (line >= nl) return;
     const int z = line / Ny, y = line - z * Ny;
     const cplx<R>* src = q + (size_t)bc * N * nl + (size_t)z * N * Ny + y;
+    const unsigned long long mk = xmask[line];
     cplx<R> u[N];
 #pragma unroll
-    for (int x = 0; x < N; ++x) u[x] = src[(size_t)x * Ny];
+    for (int x = 0; x < N; ++x) u[x] = *(((mk >> x) & 1ull) ? src + (size_t)x * Ny : zsrc);
     if (p) {
 #pragma unroll
         for (int x = 1; x < N; ++x) u[x] = tw96_mul<R>(u[x], (96 / (2 * N)) * x, false);

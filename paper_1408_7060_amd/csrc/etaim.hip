@@ -75,6 +75,12 @@ struct etaim_ctx {
     void *lam_r = nullptr, *nw_r = nullptr, *near_r = nullptr, *nearT_r = nullptr, *ghat_r = nullptr, *tw_r[3] = {};
     void* ghatT_r = nullptr;  // ky/kz-exchanged copy for the z-lines-first plane kernel
     void *A = nullptr, *P = nullptr, *ring = nullptr;
+    // register x stage: anterpolated grid q[bc][z][x][y], zero outside the
+    // nodes some basis reaches (anodes, as plane indices)
+    void* Q = nullptr;
+    int* anodes = nullptr;
+    unsigned long long* xmask = nullptr;  // [z][y]: bit x set where node (x, y, z) is reached
+    int n_anodes = 0;
     zd* hist = nullptr;  // [mn][ns][B] in the working precision (sized for complex128)
     // Krylov (FP64)
     zd *Vk = nullptr, *w = nullptr, *h1 = nullptr, *h2 = nullptr, *H = nullptr, *sn = nullptr, *g = nullptr,
@@ -252,6 +258,7 @@ template <typename R>
 struct Ops {
     static cplx<R>* A(etaim_ctx* c) { return (cplx<R>*)c->A; }
     static cplx<R>* P(etaim_ctx* c) { return (cplx<R>*)c->P; }
+    static cplx<R>* Q(etaim_ctx* c) { return (cplx<R>*)c->Q; }
     static const cplx<R>* tw(etaim_ctx* c, int a) { return (const cplx<R>*)c->tw_r[a]; }
     static const cplx<R>* ghat(etaim_ctx* c) { return (const cplx<R>*)c->ghat_r; }
     static const cplx<R>* ghatT(etaim_ctx* c) { return (const cplx<R>*)c->ghatT_r; }
@@ -290,13 +297,16 @@ struct Ops {
             if (!xs_ready)
                 hipLaunchKernelGGL(k_prescale<R>, dim3(blocks_for(nB)), dim3(256), 0, c->stream, x, dinv, xs, c->ns,
                                    c->B, conj_in, gate);
-            hipLaunchKernelGGL(k_anterp<R>, dim3((unsigned)((c->N3 + 255) / 256), (c->B + kAntCols - 1) / kAntCols),
-                               dim3(256), 0, c->stream, xs, c->nptr, c->nk, (const R*)c->nw_r, P(c), g, c->B, gate);
+            if (c->n_anodes > 0)
+                hipLaunchKernelGGL(k_anterp_nz<R>, dim3(blocks_for((size_t)c->n_anodes * c->B)), dim3(256), 0,
+                                   c->stream, xs, c->anodes, c->n_anodes, c->nptr, c->nk, (const R*)c->nw_r, Q(c), g,
+                                   c->B, gate);
             const dim3 gx((2 * g.N[1] * g.N[2] + 255) / 256, 4 * c->B);
+            const cplx<R>* zsrc = (const cplx<R>*)c->zero;
             switch (xline_n(c)) {
-                case 16: hipLaunchKernelGGL((k_xfwd<R, 16>), gx, dim3(256), 0, c->stream, P(c), A(c), g, gate); break;
-                case 24: hipLaunchKernelGGL((k_xfwd<R, 24>), gx, dim3(256), 0, c->stream, P(c), A(c), g, gate); break;
-                case 48: hipLaunchKernelGGL((k_xfwd<R, 48>), gx, dim3(256), 0, c->stream, P(c), A(c), g, gate); break;
+                case 16: hipLaunchKernelGGL((k_xfwd<R, 16>), gx, dim3(256), 0, c->stream, Q(c), A(c), g, c->xmask, zsrc, gate); break;
+                case 24: hipLaunchKernelGGL((k_xfwd<R, 24>), gx, dim3(256), 0, c->stream, Q(c), A(c), g, c->xmask, zsrc, gate); break;
+                case 48: hipLaunchKernelGGL((k_xfwd<R, 48>), gx, dim3(256), 0, c->stream, Q(c), A(c), g, c->xmask, zsrc, gate); break;
                 default: return fail(ETAIM_EUNSUPPORTED, "register x-line kernels need N_x in {16, 24, 48}");
             }
             HIPCHK(hipGetLastError());
@@ -937,6 +947,10 @@ int make_working(etaim_ctx* c) {
     }
     CHK(c->allocv(c->A, 4 * nB * (size_t)c->gd.N[2] * c->gd.N[1] * c->gd.L[0] * sizeof(cplx<R>)));
     CHK(c->allocv(c->P, 4 * nB * c->N3 * sizeof(cplx<R>)));
+    if (xline_n(c)) {
+        CHK(c->allocv(c->Q, 4 * nB * c->N3 * sizeof(cplx<R>)));
+        HIPCHK(hipMemsetAsync(c->Q, 0, 4 * nB * c->N3 * sizeof(cplx<R>), c->stream));
+    }
     CHK(c->allocv(c->xs, nB * (size_t)c->ns * sizeof(cplx<R>)));
     CHK(c->allocv(c->ring, (size_t)c->st.ng * 4 * nB * c->Np * sizeof(cplx<R>)));
     // plane kernels: LDS and per-thread register staging limits
@@ -962,6 +976,25 @@ int device_setup(etaim_ctx* c) {
         for (int e = s.rowptr[k]; e < s.rowptr[k + 1]; ++e) rowof[e] = k;
     CHK(c->upload(c->rowof, rowof));
     CHK(c->upload(c->nptr, s.nptr));
+    {
+        // grid nodes that some basis reaches, as plane indices t = y + Ny (x + Nx z)
+        const int Nx = s.N[0], Ny = s.N[1], Nz = s.N[2];
+        std::vector<int> an;
+        for (int z = 0; z < Nz; ++z)
+            for (int x = 0; x < Nx; ++x)
+                for (int y = 0; y < Ny; ++y) {
+                    const size_t n = (size_t)x + (size_t)Nx * ((size_t)y + (size_t)Ny * z);
+                    if (s.nptr[n + 1] > s.nptr[n]) an.push_back(y + Ny * (x + Nx * z));
+                }
+        c->n_anodes = (int)an.size();
+        if (!an.empty()) CHK(c->upload(c->anodes, an));
+        std::vector<unsigned long long> xm((size_t)Ny * Nz, 0ull);
+        for (int t : an) {
+            const int y = t % Ny, r = t / Ny, x = r % Nx, z = r / Nx;
+            if (x < 64) xm[(size_t)z * Ny + y] |= 1ull << x;
+        }
+        CHK(c->upload(c->xmask, xm));
+    }
     CHK(c->upload(c->nk, s.nk));
     CHK(c->upload(c->near64, s.near_exact));
     // diagonal of Z0 = exact self entry (pre-correction restores it)
