@@ -3,9 +3,11 @@
 //                 with the forward x-FFT of the zero-padded grid (LDS lines)
 //  k_prescale, k_anterp_nz, k_xfwd, k_xinv
 //                 the same x stage with register-resident lines: the
-//                 anterpolated grid goes through the P buffer
+//                 anterpolated grid goes through its own buffer Q, zero
+//                 outside the nodes some basis reaches
 //  k_yzq_*        register-resident parity-quadrant variants of the plane
-//                 kernels below
+//                 kernels below; k_yzc_* the same with the z lines first
+//                 (two tiles); k_ring_far the time-block history pass
 //  k_yz_green     per x-frequency plane: 2-D (y,z) FFT, Green-spectrum
 //                 multiply, inverse 2-D FFT, all in LDS
 //  k_yz_commit    per plane: forward 2-D FFT into a history-ring slot
@@ -15,7 +17,7 @@
 // Grid layouts (per excitation b and component c = x,y,z,charge; bc = 4b+c):
 //  A: [bc][kx<Lx][z<Nz][y<Ny] (x-transformed, plane-major)
 //  ring slot: [bc][kx<Lx][kz<Lz][ky<Ly] (LDS plane kernels) or quadrant-major
-//  [bc][kx][q][kz'][ky'] (register plane kernels)   P: [bc][z][x][y] (N per bc)
+//  [bc][kx][q][kz'][ky'] (register plane kernels)   P, Q: [bc][z][x][y] (N per bc)
 #pragma once
 #include "fft.inc.hip"
 
@@ -900,66 +902,106 @@ __global__ void __launch_bounds__(kDelay1Threads) k_yzq_delayed1(const cplx<R>* 
 // for every spectrum point p (quadrant-major, all bc and kx; history steps
 // before 0 are zero); the j terms m <= j (the block's own, newer steps) are
 // added at the step itself.  Each history slot is read once per block and
-// feeds all pb outputs; the point's Green values stay in registers.  Points
-// are visited kx-major, so the blocks in flight share Green planes in L2.
+// feeds all pb outputs.  A thread owns one 16-byte vector of points (two in
+// FP32) of one component c and kx and loops over the batch columns b: the
+// points' Green values, the same for every b, are loaded once and stay in
+// registers (NGX >= ng of them, a compile-time bound).  Ring reads and F
+// writes are streaming (non-temporal).
 constexpr int kFarMaxNg = 32, kFarMaxBlock = 8;
 
-template <typename R, int N>
+template <typename R>
+struct Vec16;
+template <>
+struct Vec16<float> {
+    typedef float type __attribute__((ext_vector_type(4)));
+    static constexpr int P = 2;
+};
+template <>
+struct Vec16<double> {
+    typedef double type __attribute__((ext_vector_type(2)));
+    static constexpr int P = 1;
+};
+
+template <typename R, int N, int NGX>
 __global__ void __launch_bounds__(256) k_ring_far(const cplx<R>* __restrict__ ring, const cplx<R>* __restrict__ G,
                                                   cplx<R>* __restrict__ F, GridDims g, int ng, int r0, int pb,
                                                   int conj_g) {
-    constexpr int NN = N * N, PP = 4 * NN;
-    const int Lx = g.L[0], BC = 4 * g.B;
-    const size_t gid = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-    if (gid >= (size_t)BC * Lx * PP) return;
+    using V = typename Vec16<R>::type;
+    constexpr int P = Vec16<R>::P, NN = N * N, PP = 4 * NN;
+    const int Lx = g.L[0];
+    const size_t slot = (size_t)4 * g.B * Lx * PP;
+    const size_t gid = (blockIdx.x * (size_t)blockDim.x + threadIdx.x) * P;
+    if (gid >= (size_t)4 * Lx * PP) return;
+    // PP is even, so the P points share (c, kx) and one quadrant row
     const int pl = (int)(gid / PP), e = (int)(gid - (size_t)pl * PP);
-    const int kx = pl / BC, bc = pl - kx * BC;
-    const size_t off = ((size_t)bc * Lx + kx) * PP + e;
-    const size_t slot = (size_t)BC * Lx * PP;
+    const int kx = pl >> 2, c = pl & 3;
     const int gx = g.N[0] + 1, gg = N + 1;
     const size_t gsz = (size_t)2 * gx * gg * gg;
-    const int qq = e / NN, rr = e - qq * NN;
-    const size_t gp = ((size_t)((bc & 3) == 3 ? 1 : 0) * gx + fold(kx, Lx)) * (size_t)(gg * gg) +
-                      fold(2 * (rr / N) + (qq >> 1), 2 * N) * gg + fold(2 * (rr % N) + (qq & 1), 2 * N);
     // all loads unconditional (dead terms read a live address and are
     // zeroed), so that the compiler issues them back to back
     const R sg = conj_g ? R(-1) : R(1);
-    cplx<R> gr[kFarMaxNg + 1];
+    cplx<R> gr[NGX + 1][P];
 #pragma unroll
-    for (int m = 1; m <= kFarMaxNg; ++m) {
-        const R mk = m <= ng ? R(1) : R(0);
-        const cplx<R> v = G[(size_t)(m <= ng ? m : ng) * gsz + gp];
-        gr[m] = cplx<R>{v.x * mk, v.y * (sg * mk)};
+    for (int p = 0; p < P; ++p) {
+        const int ee = e + p, qq = ee / NN, rr = ee - qq * NN;
+        const size_t gp = ((size_t)(c == 3 ? 1 : 0) * gx + fold(kx, Lx)) * (size_t)(gg * gg) +
+                          fold(2 * (rr / N) + (qq >> 1), 2 * N) * gg + fold(2 * (rr % N) + (qq & 1), 2 * N);
+#pragma unroll
+        for (int m = 1; m <= NGX; ++m) {
+            const R mk = m <= ng ? R(1) : R(0);
+            const cplx<R> v = G[(size_t)(m <= ng ? m : ng) * gsz + gp];
+            gr[m][p] = cplx<R>{v.x * mk, v.y * (sg * mk)};
+        }
     }
-    cplx<R> acc[kFarMaxBlock];
+    for (int b = 0; b < g.B; ++b) {
+        const size_t off = ((size_t)(4 * b + c) * Lx + kx) * PP + e;
+        cplx<R> acc[kFarMaxBlock][P];
 #pragma unroll
-    for (int j = 0; j < kFarMaxBlock; ++j) acc[j] = cplx<R>{0, 0};
-    // history step h = r0 - hp feeds output j through m = j + hp (the outputs
-    // j >= pb accumulate dead sums and are not stored); the slots are loaded
-    // a chunk at a time ahead of their products
-    constexpr int CH = sizeof(R) == 4 ? 8 : 4;
+        for (int j = 0; j < kFarMaxBlock; ++j)
 #pragma unroll
-    for (int hp0 = 1; hp0 <= kFarMaxNg; hp0 += CH) {
-        if (hp0 > ng) break;
-        cplx<R> q[CH];
+            for (int p = 0; p < P; ++p) acc[j][p] = cplx<R>{0, 0};
+        // history step h = r0 - hp feeds output j through m = j + hp (the
+        // outputs j >= pb accumulate dead sums and are not stored); the slots
+        // are loaded eight at a time ahead of their products
+        constexpr int CH = 8;
 #pragma unroll
-        for (int u = 0; u < CH; ++u) {
-            const int hp = hp0 + u < ng ? hp0 + u : ng;
-            const int h = r0 - hp;
-            q[u] = ring[(size_t)((h > 0 ? h : 0) % ng) * slot + off];
-            if (h < 0 || hp0 + u > ng) q[u] = cplx<R>{0, 0};
+        for (int hp0 = 1; hp0 <= NGX; hp0 += CH) {
+            if (hp0 > ng) break;
+            cplx<R> q[CH][P];
+#pragma unroll
+            for (int u = 0; u < CH; ++u) {
+                const int hp = hp0 + u < ng ? hp0 + u : ng;
+                const int h = r0 - hp;
+                const V t = __builtin_nontemporal_load(
+                    reinterpret_cast<const V*>(ring + (size_t)((h > 0 ? h : 0) % ng) * slot + off));
+#pragma unroll
+                for (int p = 0; p < P; ++p) q[u][p] = cplx<R>{t[2 * p], t[2 * p + 1]};
+                if (h < 0 || hp0 + u > ng)
+#pragma unroll
+                    for (int p = 0; p < P; ++p) q[u][p] = cplx<R>{0, 0};
+            }
+#pragma unroll
+            for (int u = 0; u < CH; ++u)
+#pragma unroll
+                for (int j = 0; j < kFarMaxBlock; ++j) {
+                    const int m = j + hp0 + u;
+                    if (m <= NGX)
+#pragma unroll
+                        for (int p = 0; p < P; ++p) acc[j][p] += cmul_fma(gr[m][p], q[u][p]);
+                }
         }
 #pragma unroll
-        for (int u = 0; u < CH; ++u)
+        for (int j = 0; j < kFarMaxBlock; ++j)
+            if (j < pb) {
+                V t;
 #pragma unroll
-            for (int j = 0; j < kFarMaxBlock; ++j) {
-                const int m = j + hp0 + u;
-                if (m <= kFarMaxNg) acc[j] += cmul_fma(gr[m], q[u]);
+                for (int p = 0; p < P; ++p) {
+                    t[2 * p] = acc[j][p].x;
+                    t[2 * p + 1] = acc[j][p].y;
+                }
+                __builtin_nontemporal_store(t, reinterpret_cast<V*>(F + (size_t)j * slot + off));
             }
     }
-#pragma unroll
-    for (int j = 0; j < kFarMaxBlock; ++j)
-        if (j < pb) F[(size_t)j * slot + off] = acc[j];
 }
 
 template <typename R>

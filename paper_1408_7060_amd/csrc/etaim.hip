@@ -448,15 +448,22 @@ struct Ops {
                         c->far_slots = pb;
                     }
                     if (far_pass) {
-                        const size_t pts = (size_t)4 * c->B * g.L[0] * 4 * (size_t)g.N[1] * g.N[2];
+                        // one thread per 16-byte vector of points of one component and kx
+                        const size_t pts = (size_t)4 * g.L[0] * 4 * (size_t)g.N[1] * g.N[2] * sizeof(cplx<R>) / 16;
                         const dim3 gf((unsigned)((pts + 255) / 256));
                         cplx<R>* F = (cplx<R>*)c->far;
+                        const cplx<R>* rg = (const cplx<R>*)ring(c);
+#define ETAIM_FAR(NN, NG) hipLaunchKernelGGL((k_ring_far<R, NN, NG>), gf, dim3(256), 0, c->stream, rg, ghat(c), F, g, ng, r0, pb, conj)
+#define ETAIM_FAR_NG(NN) \
+    if (ng <= 16) ETAIM_FAR(NN, 16); else if (ng <= 24) ETAIM_FAR(NN, 24); else ETAIM_FAR(NN, 32);
                         switch (quad_n(c)) {
-                            case 16: hipLaunchKernelGGL((k_ring_far<R, 16>), gf, dim3(256), 0, c->stream, (const cplx<R>*)ring(c), ghat(c), F, g, ng, r0, pb, conj); break;
-                            case 24: hipLaunchKernelGGL((k_ring_far<R, 24>), gf, dim3(256), 0, c->stream, (const cplx<R>*)ring(c), ghat(c), F, g, ng, r0, pb, conj); break;
-                            case 48: hipLaunchKernelGGL((k_ring_far<R, 48>), gf, dim3(256), 0, c->stream, (const cplx<R>*)ring(c), ghat(c), F, g, ng, r0, pb, conj); break;
+                            case 16: ETAIM_FAR_NG(16) break;
+                            case 24: ETAIM_FAR_NG(24) break;
+                            case 48: ETAIM_FAR_NG(48) break;
                             default: return fail(ETAIM_EUNSUPPORTED, "register plane kernels need N_y = N_z in {16, 24, 48}");
                         }
+#undef ETAIM_FAR_NG
+#undef ETAIM_FAR
                         HIPCHK(hipGetLastError());
                         c->far_r0 = r0;
                     }
