@@ -41,7 +41,7 @@ HBM_PEAK_GBS = 8000.0
 # disables them): 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz
 ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 CSRC = os.path.join(ROOT, "paper_1408_7060_amd", "csrc")
-FFT_CLASSES = ("anterp_x", "yz_green", "fft_x_inv", "interp_near", "yz_delayed", "yz_commit")
+FFT_CLASSES = ("anterp_x", "yz_green", "fft_x_inv", "interp_near", "yz_delayed", "yz_commit", "ring_far")
 
 
 def log(*a):
@@ -121,12 +121,14 @@ def fft_flops(n: int) -> float:
 
 
 def class_flops(cls: str, info: dict, batch: int):
-    """Algorithmic flops of one launch of the y/z matvec stage on the register
-    path (N_y = N_z = N, padded 2N): per (bc, kx) plane, 2N forward row
-    transforms, 4N column transforms each way, 2N inverse row transforms of N
-    points, the Green multiply (6 flops per point of the 4 N^2-point
-    spectrum) and the parity twiddles (N^2 + 2 N^2 + 2 N^2 complex products,
-    N^2 + 2 N^2 additions).  None for the other classes."""
+    """Algorithmic flops of one launch of the y/z matvec stage split into
+    parity halves (N_y = N_z = N, padded 2N): per (bc, kx) plane, 12 N
+    transforms of N points (2N + 4N forward, 4N + 2N inverse: the zero half
+    of the input and the discarded half of the output are pruned), the Green
+    multiply (6 flops per point of the 4 N^2-point spectrum) and the parity
+    twiddles (5 N^2 complex products, 3 N^2 additions).  Both register
+    engines do this work (in the z-lines-first order the twiddles are N^2
+    products more).  None for the other classes."""
     if cls != "yz_green":
         return None
     n = info["grid"][1]
@@ -253,11 +255,15 @@ def main():
     per_matvec_ms = sum(ks[n]["ms"] / ks[n]["launches"] for n in ("anterp_x", "yz_green", "fft_x_inv", "interp_near"))
     copy_gbps = stream_copy_gbps(torch)
     roof["frac_of_stream_copy"] = round((hbm_gbs if roof["bound"] == "hbm" else roof["hbm_GBps"]) / copy_gbps, 4)
-    # the HBM-bound class: the delayed field streams the whole history every step
-    dl = ks["yz_delayed"]
-    dl_gbs = dl["bytes"] / max(dl["ms"], 1e-9) / 1e6
-    hbm_stream = {"kernel": "yz_delayed", "GBps": round(dl_gbs, 1), "frac": round(dl_gbs / HBM_PEAK_GBS, 4),
-                  "frac_of_stream_copy": round(dl_gbs / copy_gbps, 4), "traffic": hbm_traffic(wl.name, "yz_delayed")}
+    # the HBM-bound stage: the delayed field streams the history (the time-block
+    # pass over the ring plus the per-step sum of the block's own steps)
+    dl_b = ks["yz_delayed"]["bytes"] + ks["ring_far"]["bytes"]
+    dl_ms = ks["yz_delayed"]["ms"] + ks["ring_far"]["ms"]
+    dl_gbs = dl_b / max(dl_ms, 1e-9) / 1e6
+    hbm_stream = {"kernels": ["ring_far", "yz_delayed"], "GBps": round(dl_gbs, 1),
+                  "frac": round(dl_gbs / HBM_PEAK_GBS, 4), "frac_of_stream_copy": round(dl_gbs / copy_gbps, 4),
+                  "ms_per_step": round(dl_ms / max(K, 1), 3),
+                  "traffic": {n: hbm_traffic(wl.name, n) for n in ("ring_far", "yz_delayed")}}
     out = {"metric": "ET-AIM time-steps/s & FFT-matvec HBM GB/s, FP32 batched vs FP64, 1 MI355X",
            "value": round(steps_s, 4), "unit": "time-steps/s", "n_gpus": 1, "steps": K, "warmup": args.warmup,
            "ms_per_step": round(1e3 * wall / K, 3), "higher_is_better": True, "scaling": "weak",

@@ -200,7 +200,9 @@ int etaim_adjoint_march(etaim_ctx *ctx, const void *S, void *Lambda, etaim_stats
 #define ETAIM_K_YZ_DELAYED 4  /* k-space temporal sum over the history + inverse 2-D FFT */
 #define ETAIM_K_YZ_COMMIT 5   /* forward 2-D FFT into the history ring */
 #define ETAIM_K_KRYLOV 6      /* GMRES vector kernels */
-#define ETAIM_K_COUNT 7
+#define ETAIM_K_RING_FAR 7    /* time-block pass over the history ring (the terms a block's steps
+                                 take from history older than the block, once per block) */
+#define ETAIM_K_COUNT 8
 
 /* Turn per-class kernel tracing on (1) or off (0); turning it on clears the
  * counters.  Tracing adds two event records per launch. */

@@ -11,7 +11,8 @@ LIB_PATH = os.path.join(HERE, "libetaim.so")
 OK, EINVAL, ENOMEM, EHIP, ENOCONV, ENONFINITE, EUNSTABLE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
 FP64, FP32 = 0, 1
 F_CONTINUE_ON_NOCONV, F_FAIL_ON_UNSTABLE, F_GRAPH, F_IMPLICIT_STOP = 1, 2, 4, 8
-KERNEL_CLASSES = ["anterp_x", "yz_green", "fft_x_inv", "interp_near", "yz_delayed", "yz_commit", "krylov"]
+KERNEL_CLASSES = ["anterp_x", "yz_green", "fft_x_inv", "interp_near", "yz_delayed", "yz_commit", "krylov",
+                  "ring_far"]
 
 
 class Mesh(ctypes.Structure):

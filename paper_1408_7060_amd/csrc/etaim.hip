@@ -96,6 +96,8 @@ struct etaim_ctx {
     int delay_block = 6, far_slots = 0, far_r0 = -1;
     void* far = nullptr;
     int* flag_h = nullptr;
+    double* res_h = nullptr;  // pinned: per-column residuals [B], then per-column norms [B]
+    int* pnext = nullptr;     // device: extrapolation order chosen for the next step
     // batched-GMRES schedule: steps per host check, captured Arnoldi steps
     int sync_every = 1;
     bool use_graph = false, capturing = false;
@@ -107,7 +109,7 @@ struct etaim_ctx {
     int guess_order = 4;  // solutions extrapolated into a step's initial guess (0..4)
     int x_engine = 0;   // 0: LDS line kernels, 1: register line kernels
     void* xs = nullptr; // [ns][B] scaled columns for the register anterpolation
-    hipEvent_t ev[4] = {};
+    hipEvent_t ev[8] = {};  // march phase events, two sets (steps alternate)
     // per-kernel-class tracing
     bool prof = false;
     double k_ms[ETAIM_K_COUNT] = {}, k_bytes[ETAIM_K_COUNT] = {};
@@ -148,6 +150,7 @@ struct etaim_ctx {
             if (e) (void)hipEventDestroy(e);
         for (auto& e : pool) (void)hipEventDestroy(e);
         if (flag_h) (void)hipHostFree(flag_h);
+        if (res_h) (void)hipHostFree(res_h);
         for (auto& v : graphs)
             for (auto& x : v)
                 if (x) (void)hipGraphExecDestroy(x);
@@ -183,7 +186,10 @@ struct Trace {
     }
 };
 
-// resolve pending event pairs (call after the stream has drained them)
+// traced launches held before the march resolves them
+constexpr size_t kTraceBatch = 2048;
+
+// resolve pending event pairs (waits on the stream)
 int trace_flush(etaim_ctx* c) {
     if (c->pending.empty()) return ETAIM_OK;
     HIPCHK(hipStreamSynchronize(c->stream));
@@ -429,8 +435,6 @@ struct Ops {
             const double s = sizeof(cplx<R>), slot_b = 4.0 * c->B * c->Np * s, green_b = 2.0 * c->gfold * s;
             double bytes = nmx * (slot_b + green_b) + 4.0 * c->B * g.L[0] * g.N[2] * g.N[1] * s;
             if (blocked) bytes += slot_b;
-            if (far_pass) bytes += std::min(ng, r0) * slot_b + ng * green_b + pb * slot_b;
-            Trace t(c, ETAIM_K_YZ_DELAYED, bytes);
             if (c->yz_engine >= 1) {
                 const size_t slot = (size_t)4 * c->B * c->Np;
                 const cplx<R>* Fj = nullptr;
@@ -448,6 +452,7 @@ struct Ops {
                         c->far_slots = pb;
                     }
                     if (far_pass) {
+                        Trace tf(c, ETAIM_K_RING_FAR, std::min(ng, r0) * slot_b + ng * green_b + pb * slot_b);
                         // one thread per 16-byte vector of points of one component and kx
                         const size_t pts = (size_t)4 * g.L[0] * 4 * (size_t)g.N[1] * g.N[2] * sizeof(cplx<R>) / 16;
                         const dim3 gf((unsigned)((pts + 255) / 256));
@@ -469,6 +474,7 @@ struct Ops {
                     }
                     Fj = (const cplx<R>*)c->far + (size_t)(cur - r0) * slot;
                 }
+                Trace t(c, ETAIM_K_YZ_DELAYED, bytes);
                 // plane pairs (bc, bc + 4) sharing the Green loads where the batch is even and two
                 // planes' tiles fit the LDS; one plane per block otherwise
                 const bool pair = c->B % 2 == 0 && 2 * quad_lds(c) <= (size_t)160 * 1024;
@@ -490,10 +496,12 @@ struct Ops {
                     default: return fail(ETAIM_EUNSUPPORTED, "register plane kernels need N_y = N_z in {16, 24, 48}");
                 }
 #undef ETAIM_DELAYED
-            } else
-            hipLaunchKernelGGL(k_yz_delayed<R>, dim3(g.L[0], 4 * c->B), dim3(kPlaneThreads), plane_lds(c), c->stream,
-                               (const cplx<R>*)ring(c), ghat(c), A(c), tw(c, 1), tw(c, 2), c->ry, c->rz, g,
-                               c->st.ng, cur, nm, conj);
+            } else {
+                Trace t(c, ETAIM_K_YZ_DELAYED, bytes);
+                hipLaunchKernelGGL(k_yz_delayed<R>, dim3(g.L[0], 4 * c->B), dim3(kPlaneThreads), plane_lds(c),
+                                   c->stream, (const cplx<R>*)ring(c), ghat(c), A(c), tw(c, 1), tw(c, 2), c->ry, c->rz,
+                                   g, c->st.ng, cur, nm, conj);
+            }
         }
         HIPCHK(hipGetLastError());
         CHK(inverse_x(c));
@@ -684,7 +692,9 @@ int gmres(etaim_ctx* c, const zd* rhs, zd* x, int conj, StepResult& res) {
                            std::max(c->prm.maxit - total, 0), nullptr);
         hipLaunchKernelGGL(k_cycle_start, dim3(1), dim3(256), 0, c->stream, c->beta, c->bnorm, c->active, c->jcnt,
                            c->g, c->resid, c->flag, B, c->ldg, tol);
+        // flags and the true residuals of the cycle start in one readback
         HIPCHK(hipMemcpyAsync(c->flag_h, c->flag, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipMemcpyAsync(c->res_h, c->resid, B * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
         if (c->flag_h[1]) {
             res.nonfinite = true;
@@ -698,10 +708,8 @@ int gmres(etaim_ctx* c, const zd* rhs, zd* x, int conj, StepResult& res) {
         // stagnation: the true residual at a restart did not drop below half of
         // the previous restart's (e.g. a tolerance below the working precision)
         {
-            std::vector<double> bh(B);
-            HIPCHK(hipMemcpy(bh.data(), c->resid, B * sizeof(double), hipMemcpyDeviceToHost));
             double worst = 0;
-            for (double v : bh) worst = std::max(worst, v);
+            for (int b = 0; b < B; ++b) worst = std::max(worst, c->res_h[b]);
             if (cycle > 0 && worst > 0.5 * prev_worst) {
                 res.noconv = true;
                 break;
@@ -722,6 +730,7 @@ int gmres(etaim_ctx* c, const zd* rhs, zd* x, int conj, StepResult& res) {
                     CHK(arnoldi_step<R>(c, j, conj, gated ? c->flag + 2 : nullptr));
             }
             HIPCHK(hipMemcpyAsync(c->flag_h, c->flag, 5 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(hipMemcpyAsync(c->res_h, c->resid, B * sizeof(double), hipMemcpyDeviceToHost, c->stream));
             HIPCHK(hipStreamSynchronize(c->stream));
             HIPCHK(hipGetLastError());
             if (gated) {
@@ -753,13 +762,10 @@ int gmres(etaim_ctx* c, const zd* rhs, zd* x, int conj, StepResult& res) {
         // the true residual is to confirm it at a new cycle start
         if ((c->prm.flags & ETAIM_F_IMPLICIT_STOP) && c->flag_h[0] == 0) break;
     }
-    // final residual: the true residual of the last cycle start, or the
-    // Arnoldi estimate of the last step under ETAIM_F_IMPLICIT_STOP
-    std::vector<double> rr(B);
-    HIPCHK(hipMemcpyAsync(rr.data(), c->resid, B * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
+    // final residual (the last readback): the true residual of the last cycle
+    // start, or the Arnoldi estimate of the last step under ETAIM_F_IMPLICIT_STOP
     res.resid = 0;
-    for (double v : rr) res.resid = std::max(res.resid, v);
+    for (int b = 0; b < B; ++b) res.resid = std::max(res.resid, c->res_h[b]);
     return ETAIM_OK;
 }
 
@@ -789,63 +795,94 @@ int march_impl(etaim_ctx* c, const zd* V, zd* I, etaim_stats* st, bool adjoint, 
     int steps = 0, tot_iters = 0, max_iters = 0, first_noconv = -1, unstable = -1;
     double maxres = 0, ms_rhs = 0, ms_solve = 0, ms_commit = 0;
     bool nonfinite = false;
-    std::vector<double> nrm_h(B);
-    double perr_h[4] = {0, 0, 0, 0};
-    int guess_p = c->guess_order == 0 ? 0 : 1;  // extrapolation order of the next initial guess
+    // per-step current norms on the device [nt][B] (instability detector); with
+    // ETAIM_F_FAIL_ON_UNSTABLE the host reads them every step, otherwise once
+    // at the end, so that steps are enqueued without waiting for the last one
+    const bool eager_detect = (c->prm.flags & ETAIM_F_FAIL_ON_UNSTABLE) != 0;
+    double* nrm_all = nullptr;
+    CHK(c->alloc(nrm_all, (size_t)nt * B));
+    const int W = 32;
+    auto detect = [&](int r) {
+        // late-time growth: monotone growth by > 10x over W steps while the
+        // excitation is negligible
+        if (unstable >= 0 || r < W) return;
+        bool mono = nI[r] > 10.0 * nI[r - W];
+        double vw = 0;
+        for (int q = r - W + 1; q <= r && mono; ++q) {
+            mono = nI[q] > nI[q - 1];
+            const int lq = adjoint ? nt - 1 - q : q;
+            for (int b = 0; b < B; ++b) vw = std::max(vw, nV[(size_t)lq * B + b]);
+        }
+        if (mono && vw < 1e-6 * vmax) unstable = r;
+    };
+    // phase times of a step, read once its events are complete
+    auto phase_ms = [&](int r) -> int {
+        hipEvent_t* ev = c->ev + 4 * (r & 1);
+        float t01 = 0, t12 = 0, t23 = 0;
+        HIPCHK(hipEventElapsedTime(&t01, ev[0], ev[1]));
+        HIPCHK(hipEventElapsedTime(&t12, ev[1], ev[2]));
+        HIPCHK(hipEventElapsedTime(&t23, ev[2], ev[3]));
+        ms_rhs += t01;
+        ms_solve += t12;
+        ms_commit += t23;
+        return ETAIM_OK;
+    };
+    // extrapolation order of the next initial guess: known on the host while
+    // fewer than two orders can be compared, else chosen on the device
+    int guess_p = c->guess_order == 0 ? 0 : 1;
+    bool guess_dev = false;
     for (int r = 0; r < nt; ++r) {
         const int l = adjoint ? nt - 1 - r : r;
         const zd* Vl = V + (size_t)l * nB;
         zd* Il = I + (size_t)l * nB;
-        HIPCHK(hipEventRecord(c->ev[0], c->stream));
+        hipEvent_t* ev = c->ev + 4 * (r & 1);
+        HIPCHK(hipEventRecord(ev[0], c->stream));
         if (r >= 1) {
             CHK(Ops<R>::delayed(c, r, Vl, c->rhs, conj));
         } else {
             HIPCHK(hipMemcpyAsync(c->rhs, Vl, nB * sizeof(zd), hipMemcpyDeviceToDevice, c->stream));
         }
-        HIPCHK(hipEventRecord(c->ev[1], c->stream));
+        HIPCHK(hipEventRecord(ev[1], c->stream));
         // initial guess: extrapolation of the last p solutions, p the order
         // that best predicted the previous step (at most guess_order)
         hipLaunchKernelGGL(k_extrap, dim3(blocks_for(nB)), dim3(256), 0, c->stream, (const zd*)I, c->xk, nB,
-                           (long long)l, adjoint ? -1 : 1, std::min(r, guess_p));
+                           (long long)l, adjoint ? -1 : 1, guess_dev ? r : std::min(r, guess_p),
+                           guess_dev ? (const int*)c->pnext : nullptr);
         HIPCHK(hipGetLastError());
         StepResult sr;
         CHK(gmres<R>(c, c->rhs, c->xk, conj, sr));
-        HIPCHK(hipEventRecord(c->ev[2], c->stream));
+        // gmres has waited on the stream: the previous step's events are complete
+        if (r >= 1) CHK(phase_ms(r - 1));
+        HIPCHK(hipEventRecord(ev[2], c->stream));
         HIPCHK(hipMemcpyAsync(Il, c->xk, nB * sizeof(zd), hipMemcpyDeviceToDevice, c->stream));
         CHK(Ops<R>::commit(c, r, c->xk));
-        hipLaunchKernelGGL(k_norm, dim3(B), dim3(256), 0, c->stream, c->xk, c->nrm, ns, nullptr);
-        HIPCHK(hipMemcpyAsync(nrm_h.data(), c->nrm, B * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        hipLaunchKernelGGL(k_norm, dim3(B), dim3(256), 0, c->stream, c->xk, nrm_all + (size_t)r * B, ns, nullptr);
         const int pmax = std::min(r, c->guess_order);
         if (pmax >= 2) {
             hipLaunchKernelGGL(k_pred_err, dim3(kPredBlocks), dim3(256), 0, c->stream, (const zd*)I, nB,
                                (long long)l, adjoint ? -1 : 1, pmax, c->perr + 4);
             hipLaunchKernelGGL(k_pred_err_sum, dim3(1), dim3(256), 0, c->stream, (const double*)(c->perr + 4),
-                               kPredBlocks, c->perr);
-            HIPCHK(hipMemcpyAsync(perr_h, c->perr, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-        }
-        HIPCHK(hipEventRecord(c->ev[3], c->stream));
-        HIPCHK(hipEventSynchronize(c->ev[3]));
-        CHK(trace_flush(c));
-        if (pmax >= 2) {
-            guess_p = 1;
-            for (int p = 2; p <= pmax; ++p)
-                if (perr_h[p - 1] < perr_h[guess_p - 1]) guess_p = p;
+                               kPredBlocks, c->perr, pmax, c->pnext);
+            guess_dev = true;
         } else {
             guess_p = c->guess_order == 0 ? 0 : 1;
+            guess_dev = false;
         }
-        float t01 = 0, t12 = 0, t23 = 0;
-        HIPCHK(hipEventElapsedTime(&t01, c->ev[0], c->ev[1]));
-        HIPCHK(hipEventElapsedTime(&t12, c->ev[1], c->ev[2]));
-        HIPCHK(hipEventElapsedTime(&t23, c->ev[2], c->ev[3]));
-        ms_rhs += t01;
-        ms_solve += t12;
-        ms_commit += t23;
+        HIPCHK(hipEventRecord(ev[3], c->stream));
+        HIPCHK(hipGetLastError());
+        // kernel traces are resolved in batches (each flush waits on the stream)
+        if (c->pending.size() >= kTraceBatch) CHK(trace_flush(c));
+        if (eager_detect) {
+            HIPCHK(hipMemcpyAsync(c->res_h + B, nrm_all + (size_t)r * B, B * sizeof(double), hipMemcpyDeviceToHost,
+                                  c->stream));
+            HIPCHK(hipStreamSynchronize(c->stream));
+            for (int b = 0; b < B; ++b) nI[r] = std::max(nI[r], c->res_h[B + b]);
+        }
         steps = r + 1;
         tot_iters += sr.iters;
         max_iters = std::max(max_iters, sr.iters);
         maxres = std::max(maxres, sr.resid);
         if (st && st->iters_per_step) st->iters_per_step[r] = sr.iters;
-        for (double v : nrm_h) nI[r] = std::max(nI[r], v);
         if (sr.nonfinite) {
             nonfinite = true;
             break;
@@ -854,23 +891,27 @@ int march_impl(etaim_ctx* c, const zd* V, zd* I, etaim_stats* st, bool adjoint, 
             first_noconv = r;
             if (!(c->prm.flags & ETAIM_F_CONTINUE_ON_NOCONV)) break;
         }
-        // late-time growth: monotone growth by > 10x over 32 steps while the
-        // excitation is negligible
-        const int W = 32;
-        if (unstable < 0 && r >= W) {
-            bool mono = nI[r] > 10.0 * nI[r - W];
-            double vw = 0;
-            for (int q = r - W + 1; q <= r && mono; ++q) {
-                mono = nI[q] > nI[q - 1];
-                const int lq = adjoint ? nt - 1 - q : q;
-                for (int b = 0; b < B; ++b) vw = std::max(vw, nV[(size_t)lq * B + b]);
-            }
-            if (mono && vw < 1e-6 * vmax) {
-                unstable = r;
-                if (c->prm.flags & ETAIM_F_FAIL_ON_UNSTABLE) break;
-            }
+        if (eager_detect) {
+            detect(r);
+            if (unstable >= 0) break;
         }
     }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    CHK(trace_flush(c));
+    if (steps >= 1) CHK(phase_ms(steps - 1));
+    if (!eager_detect && steps >= 1) {
+        std::vector<double> na((size_t)steps * B);
+        HIPCHK(hipMemcpy(na.data(), nrm_all, na.size() * sizeof(double), hipMemcpyDeviceToHost));
+        for (int r = 0; r < steps; ++r) {
+            for (int b = 0; b < B; ++b) nI[r] = std::max(nI[r], na[(size_t)r * B + b]);
+            detect(r);
+        }
+    }
+    // (the delayed field may have allocated after nrm_all: remove it by value)
+    auto it = std::find(c->allocs.begin(), c->allocs.end(), (void*)nrm_all);
+    if (it != c->allocs.end()) c->allocs.erase(it);
+    c->dev_bytes -= (int64_t)((size_t)nt * B * sizeof(double));
+    HIPCHK(hipFree(nrm_all));
     if (st) {
         st->steps_done = steps;
         st->total_iters = tot_iters;
@@ -1163,6 +1204,8 @@ int device_setup(etaim_ctx* c) {
     CHK(c->alloc(c->flag, 8));
     CHK(c->alloc(c->perr, 4 + 4 * kPredBlocks));
     HIPCHK(hipHostMalloc((void**)&c->flag_h, 8 * sizeof(int), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&c->res_h, 2 * (size_t)c->B * sizeof(double), hipHostMallocDefault));
+    CHK(c->alloc(c->pnext, 1));
     for (auto& e : c->ev) HIPCHK(hipEventCreate(&e));
     HIPCHK(hipStreamSynchronize(c->stream));
     return ETAIM_OK;

@@ -289,7 +289,10 @@ __global__ void k_copy_conj(const zd* __restrict__ in, zd* __restrict__ out, siz
 // polynomial through the last p solutions evaluated one step ahead
 // (a_i = (-1)^(i+1) C(p, i)); p = 0 gives zero.  The march picks p as the
 // order whose prediction of the step just solved was closest.
-__global__ void k_extrap(const zd* __restrict__ I, zd* __restrict__ x, size_t nB, long long l, int dir, int p) {
+__global__ void k_extrap(const zd* __restrict__ I, zd* __restrict__ x, size_t nB, long long l, int dir, int p,
+                         const int* __restrict__ pdev) {
+    // p caps the order (history available); pdev, when given, holds the order chosen on the device
+    if (pdev) p = min(p, *pdev);
     const double a[4][4] = {{1, 0, 0, 0}, {2, -1, 0, 0}, {3, -3, 1, 0}, {4, -6, 4, -1}};
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < nB; e += (size_t)gridDim.x * blockDim.x) {
         zd acc{0, 0};
@@ -332,13 +335,21 @@ __global__ void __launch_bounds__(256) k_pred_err(const zd* __restrict__ I, size
 }
 
 __global__ void __launch_bounds__(256) k_pred_err_sum(const double* __restrict__ part, int nblk,
-                                                      double* __restrict__ err) {
+                                                      double* __restrict__ err, int pmax, int* __restrict__ pbest) {
     __shared__ double sh[256];
+    double e[4];
     for (int p = 0; p < 4; ++p) {
         double s = 0;
         for (int b = threadIdx.x; b < nblk; b += 256) s += part[(size_t)b * 4 + p];
-        const double t = block_sum256(s, sh);
-        if (threadIdx.x == 0) err[p] = t;
+        e[p] = block_sum256(s, sh);
+        if (threadIdx.x == 0) err[p] = e[p];
+    }
+    // the order that predicted best (the lowest on ties)
+    if (threadIdx.x == 0) {
+        int best = 1;
+        for (int p = 2; p <= pmax; ++p)
+            if (e[p - 1] < e[best - 1]) best = p;
+        *pbest = best;
     }
 }
 
