@@ -11,6 +11,8 @@
 #include <string>
 #include <vector>
 
+#include <hip/hip_ext.h>
+
 #include "aim.inc.hip"
 #include "context.hpp"
 #include "krylov.inc.hip"
@@ -161,12 +163,15 @@ struct etaim_ctx {
 
 namespace {
 
-// Tracing: an event pair around each launch of a class (when enabled).
+// Tracing: an event pair around each launch of a class (when enabled).  A
+// class of one kernel passes the pair to the launch itself (launch_timed):
+// the events then take the dispatch's own start and end, with no queue gap.
 struct Trace {
     etaim_ctx* c;
     int cls, idx = -1;
     double bytes;
-    Trace(etaim_ctx* c_, int cls_, double bytes_) : c(c_), cls(cls_), bytes(bytes_) {
+    bool ext;
+    Trace(etaim_ctx* c_, int cls_, double bytes_, bool ext_ = false) : c(c_), cls(cls_), bytes(bytes_), ext(ext_) {
         if (!c->prof || c->capturing) return;
         if ((size_t)(c->pool_next + 2) > c->pool.size()) {
             for (int i = 0; i < 64; ++i) {
@@ -177,14 +182,25 @@ struct Trace {
         }
         idx = c->pool_next;
         c->pool_next += 2;
-        (void)hipEventRecord(c->pool[idx], c->stream);
+        if (!ext) (void)hipEventRecord(c->pool[idx], c->stream);
     }
+    hipEvent_t ev0() const { return idx >= 0 ? c->pool[idx] : nullptr; }
+    hipEvent_t ev1() const { return idx >= 0 ? c->pool[idx + 1] : nullptr; }
     ~Trace() {
         if (idx < 0) return;
-        (void)hipEventRecord(c->pool[idx + 1], c->stream);
+        if (!ext) (void)hipEventRecord(c->pool[idx + 1], c->stream);
         c->pending.push_back({cls, idx, bytes});
     }
 };
+
+// the one launch of an ext-mode trace (a plain launch when tracing is off)
+template <typename F, typename... Args>
+void launch_timed(const Trace& t, F kernel, dim3 grid, dim3 block, size_t lds, hipStream_t st, Args... args) {
+    if (t.ev0())
+        hipExtLaunchKernelGGL(kernel, grid, block, (std::uint32_t)lds, st, t.ev0(), t.ev1(), 0, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, lds, st, args...);
+}
 
 // traced launches held before the march resolves them
 constexpr size_t kTraceBatch = 2048;
@@ -328,13 +344,13 @@ struct Ops {
         const GridDims& g = c->gd;
         const long long Lx = g.L[0], Nx = g.N[0], Ny = g.N[1], Nz = g.N[2];
         const double s = sizeof(cplx<R>), bc = 4.0 * c->B;
-        Trace t(c, ETAIM_K_FFT_X_INV, bc * Lx * Nz * Ny * s + bc * c->N3 * s);
+        Trace t(c, ETAIM_K_FFT_X_INV, bc * Lx * Nz * Ny * s + bc * c->N3 * s, c->x_engine == 1);
         if (c->x_engine == 1) {
             const dim3 gx((unsigned)((2 * Ny * Nz + 255) / 256), (unsigned)(4 * c->B));
             switch (xline_n(c)) {
-                case 16: hipLaunchKernelGGL((k_xinv<R, 16>), gx, dim3(256), 0, c->stream, A(c), P(c), g, gate); break;
-                case 24: hipLaunchKernelGGL((k_xinv<R, 24>), gx, dim3(256), 0, c->stream, A(c), P(c), g, gate); break;
-                case 48: hipLaunchKernelGGL((k_xinv<R, 48>), gx, dim3(256), 0, c->stream, A(c), P(c), g, gate); break;
+                case 16: launch_timed(t, k_xinv<R, 16>, gx, dim3(256), 0, c->stream, A(c), P(c), g, gate); break;
+                case 24: launch_timed(t, k_xinv<R, 24>, gx, dim3(256), 0, c->stream, A(c), P(c), g, gate); break;
+                case 48: launch_timed(t, k_xinv<R, 48>, gx, dim3(256), 0, c->stream, A(c), P(c), g, gate); break;
                 default: return fail(ETAIM_EUNSUPPORTED, "register x-line kernels need N_x in {16, 24, 48}");
             }
             HIPCHK(hipGetLastError());
@@ -354,15 +370,15 @@ struct Ops {
         const GridDims& g = c->gd;
         dim3 grid(g.L[0], 4 * c->B);
         const double s = sizeof(cplx<R>);
-        Trace t(c, ETAIM_K_YZ_GREEN, 2.0 * 4 * c->B * g.L[0] * g.N[2] * g.N[1] * s + 2.0 * c->gfold * s);
+        Trace t(c, ETAIM_K_YZ_GREEN, 2.0 * 4 * c->B * g.L[0] * g.N[2] * g.N[1] * s + 2.0 * c->gfold * s, true);
         if (c->yz_engine == 2) {
             const cplx<R>* G = ghatT(c) + (size_t)m * 2 * c->gfold;
             const size_t lds = zline_lds(c);
             grid = dim3(4 * c->B, g.L[0]);
             switch (quad_n(c)) {
-                case 16: hipLaunchKernelGGL((k_yzc_green<R, 16>), grid, dim3(4 * 16), lds, c->stream, A(c), G, tw(c, 1), tw(c, 2), g, conj, gate); break;
-                case 24: hipLaunchKernelGGL((k_yzc_green<R, 24>), grid, dim3(4 * 24), lds, c->stream, A(c), G, tw(c, 1), tw(c, 2), g, conj, gate); break;
-                case 48: hipLaunchKernelGGL((k_yzc_green<R, 48>), grid, dim3(4 * 48), lds, c->stream, A(c), G, tw(c, 1), tw(c, 2), g, conj, gate); break;
+                case 16: launch_timed(t, k_yzc_green<R, 16>, grid, dim3(4 * 16), lds, c->stream, A(c), G, tw(c, 1), tw(c, 2), g, conj, gate); break;
+                case 24: launch_timed(t, k_yzc_green<R, 24>, grid, dim3(4 * 24), lds, c->stream, A(c), G, tw(c, 1), tw(c, 2), g, conj, gate); break;
+                case 48: launch_timed(t, k_yzc_green<R, 48>, grid, dim3(4 * 48), lds, c->stream, A(c), G, tw(c, 1), tw(c, 2), g, conj, gate); break;
                 default: return fail(ETAIM_EUNSUPPORTED, "register plane kernels need N_y = N_z in {16, 24, 48}");
             }
             HIPCHK(hipGetLastError());
@@ -373,16 +389,16 @@ struct Ops {
             const size_t lds = quad_lds(c);
             grid = dim3(4 * c->B, g.L[0]);
             switch (quad_n(c)) {
-                case 16: hipLaunchKernelGGL((k_yzq_green<R, 16>), grid, dim3(kQuadThreads), lds, c->stream, A(c), G, tw(c, 1), tw(c, 2), g, conj, gate); break;
-                case 24: hipLaunchKernelGGL((k_yzq_green<R, 24>), grid, dim3(kQuadThreads), lds, c->stream, A(c), G, tw(c, 1), tw(c, 2), g, conj, gate); break;
-                case 48: hipLaunchKernelGGL((k_yzq_green<R, 48>), grid, dim3(kQuadThreads), lds, c->stream, A(c), G, tw(c, 1), tw(c, 2), g, conj, gate); break;
+                case 16: launch_timed(t, k_yzq_green<R, 16>, grid, dim3(kQuadThreads), lds, c->stream, A(c), G, tw(c, 1), tw(c, 2), g, conj, gate); break;
+                case 24: launch_timed(t, k_yzq_green<R, 24>, grid, dim3(kQuadThreads), lds, c->stream, A(c), G, tw(c, 1), tw(c, 2), g, conj, gate); break;
+                case 48: launch_timed(t, k_yzq_green<R, 48>, grid, dim3(kQuadThreads), lds, c->stream, A(c), G, tw(c, 1), tw(c, 2), g, conj, gate); break;
                 default: return fail(ETAIM_EUNSUPPORTED, "register plane kernels need N_y = N_z in {16, 24, 48}");
             }
             HIPCHK(hipGetLastError());
             return ETAIM_OK;
         }
-        hipLaunchKernelGGL(k_yz_green<R>, grid, dim3(kPlaneThreads), plane_lds(c), c->stream, A(c),
-                           ghat(c) + (size_t)m * 2 * c->gfold, tw(c, 1), tw(c, 2), c->ry, c->rz, g, conj, gate);
+        launch_timed(t, k_yz_green<R>, grid, dim3(kPlaneThreads), plane_lds(c), c->stream, A(c),
+                     ghat(c) + (size_t)m * 2 * c->gfold, tw(c, 1), tw(c, 2), c->ry, c->rz, g, conj, gate);
         HIPCHK(hipGetLastError());
         return ETAIM_OK;
     }
@@ -452,13 +468,13 @@ struct Ops {
                         c->far_slots = pb;
                     }
                     if (far_pass) {
-                        Trace tf(c, ETAIM_K_RING_FAR, std::min(ng, r0) * slot_b + ng * green_b + pb * slot_b);
+                        Trace tf(c, ETAIM_K_RING_FAR, std::min(ng, r0) * slot_b + ng * green_b + pb * slot_b, true);
                         // one thread per 16-byte vector of points of one component and kx
                         const size_t pts = (size_t)4 * g.L[0] * 4 * (size_t)g.N[1] * g.N[2] * sizeof(cplx<R>) / 16;
                         const dim3 gf((unsigned)((pts + 255) / 256));
                         cplx<R>* F = (cplx<R>*)c->far;
                         const cplx<R>* rg = (const cplx<R>*)ring(c);
-#define ETAIM_FAR(NN, NG) hipLaunchKernelGGL((k_ring_far<R, NN, NG>), gf, dim3(256), 0, c->stream, rg, ghat(c), F, g, ng, r0, pb, conj)
+#define ETAIM_FAR(NN, NG) launch_timed(tf, k_ring_far<R, NN, NG>, gf, dim3(256), 0, c->stream, rg, ghat(c), F, g, ng, r0, pb, conj)
 #define ETAIM_FAR_NG(NN) \
     if (ng <= 16) ETAIM_FAR(NN, 16); else if (ng <= 24) ETAIM_FAR(NN, 24); else ETAIM_FAR(NN, 32);
                         switch (quad_n(c)) {
@@ -474,7 +490,7 @@ struct Ops {
                     }
                     Fj = (const cplx<R>*)c->far + (size_t)(cur - r0) * slot;
                 }
-                Trace t(c, ETAIM_K_YZ_DELAYED, bytes);
+                Trace t(c, ETAIM_K_YZ_DELAYED, bytes, true);
                 // plane pairs (bc, bc + 4) sharing the Green loads where the batch is even and two
                 // planes' tiles fit the LDS; one plane per block otherwise
                 const bool pair = c->B % 2 == 0 && 2 * quad_lds(c) <= (size_t)160 * 1024;
@@ -484,11 +500,11 @@ struct Ops {
                 const cplx<R>* rg = (const cplx<R>*)ring(c);
 #define ETAIM_DELAYED(NN)                                                                                     \
     if (pair)                                                                                                  \
-        hipLaunchKernelGGL((k_yzq_delayed<R, NN>), grid, blk, lds, c->stream, rg, ghat(c), A(c), tw(c, 1),     \
-                           tw(c, 2), g, ng, cur, nmx, conj, Fj);                                               \
+        launch_timed(t, k_yzq_delayed<R, NN>, grid, blk, lds, c->stream, rg, ghat(c), A(c), tw(c, 1), tw(c, 2), \
+                     g, ng, cur, nmx, conj, Fj);                                                               \
     else                                                                                                       \
-        hipLaunchKernelGGL((k_yzq_delayed1<R, NN>), grid, blk, lds, c->stream, rg, ghat(c), A(c), tw(c, 1),    \
-                           tw(c, 2), g, ng, cur, nmx, conj, Fj);
+        launch_timed(t, k_yzq_delayed1<R, NN>, grid, blk, lds, c->stream, rg, ghat(c), A(c), tw(c, 1),         \
+                     tw(c, 2), g, ng, cur, nmx, conj, Fj);
                 switch (quad_n(c)) {
                     case 16: ETAIM_DELAYED(16) break;
                     case 24: ETAIM_DELAYED(24) break;
@@ -497,10 +513,10 @@ struct Ops {
                 }
 #undef ETAIM_DELAYED
             } else {
-                Trace t(c, ETAIM_K_YZ_DELAYED, bytes);
-                hipLaunchKernelGGL(k_yz_delayed<R>, dim3(g.L[0], 4 * c->B), dim3(kPlaneThreads), plane_lds(c),
-                                   c->stream, (const cplx<R>*)ring(c), ghat(c), A(c), tw(c, 1), tw(c, 2), c->ry, c->rz,
-                                   g, c->st.ng, cur, nm, conj);
+                Trace t(c, ETAIM_K_YZ_DELAYED, bytes, true);
+                launch_timed(t, k_yz_delayed<R>, dim3(g.L[0], 4 * c->B), dim3(kPlaneThreads), plane_lds(c), c->stream,
+                             (const cplx<R>*)ring(c), ghat(c), A(c), tw(c, 1), tw(c, 2), c->ry, c->rz, g, c->st.ng,
+                             cur, nm, conj);
             }
         }
         HIPCHK(hipGetLastError());
@@ -516,15 +532,15 @@ struct Ops {
         cplx<R>* slot = ring(c) + (size_t)(cur % c->st.ng) * slot_sz;
         {
             const double s = sizeof(cplx<R>);
-            Trace t(c, ETAIM_K_YZ_COMMIT, 4.0 * c->B * g.L[0] * g.N[2] * g.N[1] * s + 4.0 * c->B * c->Np * s);
+            Trace t(c, ETAIM_K_YZ_COMMIT, 4.0 * c->B * g.L[0] * g.N[2] * g.N[1] * s + 4.0 * c->B * c->Np * s, true);
             if (c->yz_engine == 2) {
                 const dim3 grid(4 * c->B, g.L[0]);
                 const size_t lds = zline_lds(c);
                 const cplx<R>* a = (const cplx<R>*)A(c);
                 switch (quad_n(c)) {
-                    case 16: hipLaunchKernelGGL((k_yzc_commit<R, 16>), grid, dim3(4 * 16), lds, c->stream, a, slot, tw(c, 1), tw(c, 2), g); break;
-                    case 24: hipLaunchKernelGGL((k_yzc_commit<R, 24>), grid, dim3(4 * 24), lds, c->stream, a, slot, tw(c, 1), tw(c, 2), g); break;
-                    case 48: hipLaunchKernelGGL((k_yzc_commit<R, 48>), grid, dim3(4 * 48), lds, c->stream, a, slot, tw(c, 1), tw(c, 2), g); break;
+                    case 16: launch_timed(t, k_yzc_commit<R, 16>, grid, dim3(4 * 16), lds, c->stream, a, slot, tw(c, 1), tw(c, 2), g); break;
+                    case 24: launch_timed(t, k_yzc_commit<R, 24>, grid, dim3(4 * 24), lds, c->stream, a, slot, tw(c, 1), tw(c, 2), g); break;
+                    case 48: launch_timed(t, k_yzc_commit<R, 48>, grid, dim3(4 * 48), lds, c->stream, a, slot, tw(c, 1), tw(c, 2), g); break;
                     default: return fail(ETAIM_EUNSUPPORTED, "register plane kernels need N_y = N_z in {16, 24, 48}");
                 }
             } else if (c->yz_engine == 1) {
@@ -532,14 +548,14 @@ struct Ops {
                 const size_t lds = quad_lds(c);
                 const cplx<R>* a = (const cplx<R>*)A(c);
                 switch (quad_n(c)) {
-                    case 16: hipLaunchKernelGGL((k_yzq_commit<R, 16>), grid, dim3(kQuadThreads), lds, c->stream, a, slot, tw(c, 1), tw(c, 2), g); break;
-                    case 24: hipLaunchKernelGGL((k_yzq_commit<R, 24>), grid, dim3(kQuadThreads), lds, c->stream, a, slot, tw(c, 1), tw(c, 2), g); break;
-                    case 48: hipLaunchKernelGGL((k_yzq_commit<R, 48>), grid, dim3(kQuadThreads), lds, c->stream, a, slot, tw(c, 1), tw(c, 2), g); break;
+                    case 16: launch_timed(t, k_yzq_commit<R, 16>, grid, dim3(kQuadThreads), lds, c->stream, a, slot, tw(c, 1), tw(c, 2), g); break;
+                    case 24: launch_timed(t, k_yzq_commit<R, 24>, grid, dim3(kQuadThreads), lds, c->stream, a, slot, tw(c, 1), tw(c, 2), g); break;
+                    case 48: launch_timed(t, k_yzq_commit<R, 48>, grid, dim3(kQuadThreads), lds, c->stream, a, slot, tw(c, 1), tw(c, 2), g); break;
                     default: return fail(ETAIM_EUNSUPPORTED, "register plane kernels need N_y = N_z in {16, 24, 48}");
                 }
             } else
-            hipLaunchKernelGGL(k_yz_commit<R>, dim3(g.L[0], 4 * c->B), dim3(kPlaneThreads), plane_lds(c), c->stream,
-                               (const cplx<R>*)A(c), slot, tw(c, 1), tw(c, 2), c->ry, c->rz, g);
+            launch_timed(t, k_yz_commit<R>, dim3(g.L[0], 4 * c->B), dim3(kPlaneThreads), plane_lds(c), c->stream,
+                         (const cplx<R>*)A(c), slot, tw(c, 1), tw(c, 2), c->ry, c->rz, g);
         }
         HIPCHK(hipGetLastError());
         if (c->st.mn >= 1) {
@@ -747,11 +763,14 @@ int gmres(etaim_ctx* c, const zd* rhs, zd* x, int conj, StepResult& res) {
         hipLaunchKernelGGL(k_backsolve, dim3((B + 63) / 64), dim3(64), 0, c->stream, c->H, c->g, c->jcnt, c->yv, B,
                            rs);
         if (c->precond == 1) {
-            // x += M (V y)
+            // x += M (V y): the combination, transposed to [ns][B] (in w, free
+            // until the next cycle start), then the rows of M on the lanes' columns
             hipLaunchKernelGGL(k_krylov_combine, dim3((ns + 255) / 256, B), dim3(256), 0, c->stream, c->zt, c->Vk,
                                c->yv, c->jcnt, ns, B, rs);
-            hipLaunchKernelGGL(k_spmv_cols, dim3(blocks_for(nB)), dim3(256), 0, c->stream, c->rowptr, c->col,
-                               conj ? c->saiT : c->sai, c->zt, x, ns, B, conj, 1, nullptr);
+            hipLaunchKernelGGL(k_prescale<double>, dim3(blocks_for(nB)), dim3(256), 0, c->stream, c->zt, nullptr,
+                               (cplx<double>*)c->w, ns, B, 0, nullptr);
+            hipLaunchKernelGGL(k_spmv_rows_add, dim3(blocks_for(nB)), dim3(256), 0, c->stream, c->rowptr, c->col,
+                               conj ? c->saiT : c->sai, c->w, x, ns, B, conj);
         } else {
             hipLaunchKernelGGL(k_update_x, dim3((ns + 255) / 256, B), dim3(256), 0, c->stream, x, c->Vk, c->yv,
                                c->jcnt, dinv, ns, B, rs);

@@ -231,20 +231,13 @@ __global__ void k_spmv_cols(const int* __restrict__ rowptr, const int* __restric
     }
 }
 
-// out[i][b] = (op(M) x)[b][i] in the working precision, the layout the
-// operator's anterpolation and near zone read, from the columns of x
-// transposed to xt[k][b] (FP64).  Lanes take consecutive columns b of a row:
-// each matrix entry is one broadcast load and each x row one coalesced run;
-// entries go in groups of four with their loads issued together.
-template <typename R>
-__global__ void __launch_bounds__(256) k_spmv_rows(const int* __restrict__ rowptr, const int* __restrict__ col,
-                                                   const zd* __restrict__ M, const zd* __restrict__ xt,
-                                                   cplx<R>* __restrict__ out, int ns, int B, int conj,
-                                                   const int* __restrict__ gate) {
-    if (gated_off(gate)) return;
-    const size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-    if (e >= (size_t)ns * B) return;
-    const int i = (int)(e / B), b = (int)(e - (size_t)i * B);
+// (op(M) x)[b][i] from the columns of x transposed to xt[k][b] (FP64), for
+// lanes on consecutive columns b of row i: each matrix entry is one broadcast
+// load and each x row one coalesced run; entries go in groups of four with
+// their loads issued together.
+__device__ __forceinline__ zd spmv_row_col(const int* __restrict__ rowptr, const int* __restrict__ col,
+                                           const zd* __restrict__ M, const zd* __restrict__ xt, int i, int b, int B,
+                                           int conj) {
     const double sg = conj ? -1.0 : 1.0;
     zd acc{0, 0};
     const int q1 = rowptr[i + 1];
@@ -260,7 +253,31 @@ __global__ void __launch_bounds__(256) k_spmv_rows(const int* __restrict__ rowpt
 #pragma unroll
         for (int u = 0; u < 4; ++u) acc += zd{v[u].x, sg * v[u].y} * xv[u];
     }
-    out[e] = to_r<R>(acc);
+    return acc;
+}
+
+// out[i][b] = (op(M) x)[b][i] in the working precision, the layout the
+// operator's anterpolation and near zone read
+template <typename R>
+__global__ void __launch_bounds__(256) k_spmv_rows(const int* __restrict__ rowptr, const int* __restrict__ col,
+                                                   const zd* __restrict__ M, const zd* __restrict__ xt,
+                                                   cplx<R>* __restrict__ out, int ns, int B, int conj,
+                                                   const int* __restrict__ gate) {
+    if (gated_off(gate)) return;
+    const size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (e >= (size_t)ns * B) return;
+    const int i = (int)(e / B), b = (int)(e - (size_t)i * B);
+    out[e] = to_r<R>(spmv_row_col(rowptr, col, M, xt, i, b, B, conj));
+}
+
+// y[b][i] += (op(M) x)[b][i] (FP64, columns of y contiguous)
+__global__ void __launch_bounds__(256) k_spmv_rows_add(const int* __restrict__ rowptr, const int* __restrict__ col,
+                                                       const zd* __restrict__ M, const zd* __restrict__ xt,
+                                                       zd* __restrict__ y, int ns, int B, int conj) {
+    const size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (e >= (size_t)ns * B) return;
+    const int i = (int)(e / B), b = (int)(e - (size_t)i * B);
+    y[(size_t)b * ns + i] += spmv_row_col(rowptr, col, M, xt, i, b, B, conj);
 }
 
 // u[b] = sum_{i < jcnt[b]} y[b][i] V_i[b]  (the Krylov combination before a

@@ -463,7 +463,7 @@ int autotune_impl(etaim_ctx* c, int budget_ms, etaim_tuning* out) {
     int it_ref = 0;
     CHK(time_solve<R>(c, b, s_best, it_ref));
     for (int graph : {0, 1})
-        for (int sync : {1, 2, 4, 8}) {
+        for (int sync : {1, 2, 3, 4, 6, 8}) {
             Shape s = best;
             s.graph = graph;
             s.sync = sync;
