@@ -102,6 +102,7 @@ struct etaim_ctx {
     int* pnext = nullptr;     // device: extrapolation order chosen for the next step
     // batched-GMRES schedule: steps per host check, captured Arnoldi steps
     int sync_every = 1;
+    int iter_hint = 0;  // Arnoldi steps of the last solve of the march (first chunk size)
     bool use_graph = false, capturing = false;
     hipStream_t cap_stream = nullptr;
     std::vector<hipGraphExec_t> graphs[2];  // [conj][j]
@@ -735,8 +736,13 @@ int gmres(etaim_ctx* c, const zd* rhs, zd* x, int conj, StepResult& res) {
         hipLaunchKernelGGL(k_scale, dim3(blocks_for(nB)), dim3(256), 0, c->stream, c->w, c->beta, c->Vk, ns, B,
                            nullptr);
         const int base = total;
-        for (int j0 = 0; j0 < rs; j0 += chunk) {
-            const int j1 = std::min(j0 + chunk, rs);
+        // first chunk of a solve: as many steps as the previous solve took (the
+        // count is steady along a march), so that no step is enqueued past
+        // convergence; sync_every steps per chunk after that
+        int j1 = 0;
+        for (int j0 = 0; j0 < rs; j0 = j1) {
+            const int len = (cycle == 0 && j0 == 0 && gated && c->iter_hint > 0) ? c->iter_hint : chunk;
+            j1 = std::min(j0 + len, rs);
             std::vector<size_t> mark(j1 - j0);
             for (int j = j0; j < j1; ++j) {
                 mark[j - j0] = c->pending.size();
@@ -796,6 +802,7 @@ int march_impl(etaim_ctx* c, const zd* V, zd* I, etaim_stats* st, bool adjoint, 
     const int conj = adjoint ? 1 : 0;
     HIPCHK(hipMemsetAsync(c->ring, 0, (size_t)c->st.ng * 4 * B * c->Np * sizeof(cplx<R>), c->stream));
     c->far_r0 = -1;  // the far parts belong to the previous history
+    c->iter_hint = 0;
     if (c->st.mn >= 1) HIPCHK(hipMemsetAsync(c->hist, 0, (size_t)c->st.mn * nB * sizeof(zd), c->stream));
     // excitation norms per step (instability detector)
     std::vector<double> nV((size_t)nt * B), nI((size_t)nt, 0.0);
@@ -870,6 +877,7 @@ int march_impl(etaim_ctx* c, const zd* V, zd* I, etaim_stats* st, bool adjoint, 
         HIPCHK(hipGetLastError());
         StepResult sr;
         CHK(gmres<R>(c, c->rhs, c->xk, conj, sr));
+        c->iter_hint = std::min(sr.iters, c->prm.restart);
         // gmres has waited on the stream: the previous step's events are complete
         if (r >= 1) CHK(phase_ms(r - 1));
         HIPCHK(hipEventRecord(ev[2], c->stream));

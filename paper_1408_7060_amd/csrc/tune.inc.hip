@@ -343,6 +343,7 @@ int autotune_impl(etaim_ctx* c, int budget_ms, etaim_tuning* out) {
     const double tol = sizeof(R) == 4 ? 1e-4 : 1e-10;
     const bool prof = c->prof;
     c->prof = false;
+    c->iter_hint = 0;
     TuneBufs b;
     HIPCHK(hipMalloc(&b.x, nB * sizeof(zd)));
     HIPCHK(hipMalloc(&b.y, nB * sizeof(zd)));
