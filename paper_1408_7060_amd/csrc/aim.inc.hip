@@ -1063,29 +1063,55 @@ __global__ void __launch_bounds__(256) k_interp_near(
                 for (int c = 0; c < 4; ++c) acc[bb] += w[c] * pb[(size_t)c * N];
             }
         }
-        for (int e = e0 + lane; e < e1; e += 64) {
-            const int cc = col[e];
+        // near zone: lane = (entry slot, column) with the columns innermost, so
+        // that the lanes of one entry read one coalesced run of its basis's
+        // columns and share the entry's loads
+        int C = 1;
+        while (C < nb) C <<= 1;
+        const int E = 64 / C, bcol = lane & (C - 1), eslot = lane / C;
+        cplx<R> nacc{0, 0};
+        // four entries per slot at a time, their loads issued together
+        constexpr int U = 4;
+        for (int e = e0 + eslot; e < e1; e += U * E) {
+            int cc[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) cc[u] = e + u * E < e1 ? col[e + u * E] : -1;
             if (mode == 0) {
                 if (m <= mv - 1) {
-                    cplx<R> v = val[(size_t)e * mv + m];
-                    if (conj_v) v.y = -v.y;
-                    const cplx<R>* xc = xr + (size_t)cc * B + b0;
+                    cplx<R> v[U], xv[U];
 #pragma unroll
-                    for (int bb = 0; bb < kInterpCols; ++bb)
-                        if (bb < nb) acc[bb] += v * xc[bb];
+                    for (int u = 0; u < U; ++u) {
+                        v[u] = cplx<R>{0, 0};
+                        xv[u] = cplx<R>{0, 0};
+                        if (cc[u] >= 0) {
+                            v[u] = val[(size_t)(e + u * E) * mv + m];
+                            if (bcol < nb) xv[u] = xr[(size_t)cc[u] * B + b0 + bcol];
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        if (conj_v) v[u].y = -v[u].y;
+                        nacc += v[u] * xv[u];
+                    }
                 }
             } else {
                 for (int mm = 1; mm <= nmh; ++mm) {
                     int s = (cur - mm) % mn;
                     if (s < 0) s += mn;
-                    cplx<R> v = val[(size_t)e * mv + mm];
-                    if (conj_v) v.y = -v.y;
-                    const cplx<R>* hc = hist + ((size_t)s * ns + cc) * B + b0;
 #pragma unroll
-                    for (int bb = 0; bb < kInterpCols; ++bb)
-                        if (bb < nb) acc[bb] += v * hc[bb];
+                    for (int u = 0; u < U; ++u) {
+                        if (cc[u] < 0) continue;
+                        cplx<R> v = val[(size_t)(e + u * E) * mv + mm];
+                        if (conj_v) v.y = -v.y;
+                        if (bcol < nb) nacc += v * hist[((size_t)s * ns + cc[u]) * B + b0 + bcol];
+                    }
                 }
             }
+        }
+        // sum over the entry slots: every lane then holds its column's total
+        for (int o = C; o < 64; o <<= 1) {
+            nacc.x += __shfl_xor(nacc.x, o, 64);
+            nacc.y += __shfl_xor(nacc.y, o, 64);
         }
         // transposing butterfly over lane bits 5..1: after the exchange over
         // bit 2h a lane keeps h partial sums, those of the half its bit
@@ -1101,8 +1127,11 @@ __global__ void __launch_bounds__(256) k_interp_near(
                 acc[i] = keep + cplx<R>{__shfl_xor(send.x, bit, 64), __shfl_xor(send.y, bit, 64)};
             }
         }
-        const cplx<R> tot = acc[0] + cplx<R>{__shfl_xor(acc[0].x, 1, 64), __shfl_xor(acc[0].y, 1, 64)};
+        cplx<R> tot = acc[0] + cplx<R>{__shfl_xor(acc[0].x, 1, 64), __shfl_xor(acc[0].y, 1, 64)};
         const int bb = lane >> 1;
+        // the near-zone total of column bb sits in lane bb (entry slot 0)
+        const cplx<R> near{__shfl(nacc.x, bb, 64), __shfl(nacc.y, bb, 64)};
+        tot += near;
         if ((lane & 1) == 0 && bb < nb) {
             const size_t o = (size_t)(b0 + bb) * ns + k;
             if (mode == 0)
