@@ -709,22 +709,28 @@ int gmres(etaim_ctx* c, const zd* rhs, zd* x, int conj, StepResult& res) {
                            std::max(c->prm.maxit - total, 0), nullptr);
         hipLaunchKernelGGL(k_cycle_start, dim3(1), dim3(256), 0, c->stream, c->beta, c->bnorm, c->active, c->jcnt,
                            c->g, c->resid, c->flag, B, c->ldg, tol);
-        // flags and the true residuals of the cycle start in one readback
-        HIPCHK(hipMemcpyAsync(c->flag_h, c->flag, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(hipMemcpyAsync(c->res_h, c->resid, B * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(hipStreamSynchronize(c->stream));
-        if (c->flag_h[1]) {
-            res.nonfinite = true;
-            break;
-        }
-        if (c->flag_h[0] == 0) break;
-        if (total >= c->prm.maxit) {
-            res.noconv = true;
-            break;
-        }
-        // stagnation: the true residual at a restart did not drop below half of
-        // the previous restart's (e.g. a tolerance below the working precision)
-        {
+        // the first cycle of a gated solve goes straight on to its Arnoldi steps:
+        // the gate holds them back if no column is active, and the host reads the
+        // cycle start's flags and residuals with the first chunk's
+        const bool defer = gated && cycle == 0;
+        if (defer) {
+            HIPCHK(hipMemcpyAsync(c->res_h + B, c->resid, B * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        } else {
+            // flags and the true residuals of the cycle start in one readback
+            HIPCHK(hipMemcpyAsync(c->flag_h, c->flag, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(hipMemcpyAsync(c->res_h, c->resid, B * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(hipStreamSynchronize(c->stream));
+            if (c->flag_h[1]) {
+                res.nonfinite = true;
+                break;
+            }
+            if (c->flag_h[0] == 0) break;
+            if (total >= c->prm.maxit) {
+                res.noconv = true;
+                break;
+            }
+            // stagnation: the true residual at a restart did not drop below half of
+            // the previous restart's (e.g. a tolerance below the working precision)
             double worst = 0;
             for (int b = 0; b < B; ++b) worst = std::max(worst, c->res_h[b]);
             if (cycle > 0 && worst > 0.5 * prev_worst) {
@@ -755,6 +761,11 @@ int gmres(etaim_ctx* c, const zd* rhs, zd* x, int conj, StepResult& res) {
             HIPCHK(hipMemcpyAsync(c->res_h, c->resid, B * sizeof(double), hipMemcpyDeviceToHost, c->stream));
             HIPCHK(hipStreamSynchronize(c->stream));
             HIPCHK(hipGetLastError());
+            if (defer && j0 == 0) {
+                // the deferred cycle start: its residuals for the next restart's stagnation test
+                prev_worst = 0;
+                for (int b = 0; b < B; ++b) prev_worst = std::max(prev_worst, c->res_h[B + b]);
+            }
             if (gated) {
                 // steps enqueued past convergence did no work (the gate is
                 // monotone, so they are the chunk's last): drop their traces
