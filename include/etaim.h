@@ -162,6 +162,30 @@ int etaim_excitation_planewave(etaim_ctx *ctx, int32_t nb, const double *khat,
  * ENONFINITE, EUNSTABLE (with FAIL_ON_UNSTABLE). */
 int etaim_march(etaim_ctx *ctx, const void *V, void *I_out, int32_t nsteps, etaim_stats *stats);
 
+/* Continue a forward march (checkpoint/resume of the time marching, eq. (5)):
+ * steps first .. first + nsteps - 1, with the history rings as the last
+ * etaim_march / etaim_march_continue on this context left them, or as
+ * etaim_state_load set them, at step `first` (ETAIM_EINVAL otherwise).
+ * V and I_out are the full device arrays [N_t][B][ns]; I_out must hold the
+ * solutions of the steps before `first` (the initial guess extrapolates the
+ * last four).  The result equals that of one uninterrupted march; stats
+ * cover this call's steps (iters_per_step[0] is step `first`). */
+int etaim_march_continue(etaim_ctx *ctx, const void *V, void *I_out, int32_t first, int32_t nsteps,
+                         etaim_stats *stats);
+
+/* March state for checkpoint/resume: the spectrum ring (N_g slots), the
+ * current ring (M_n steps), the next step and the carried initial-guess
+ * order.  etaim_state_size gives the bytes; save copies the state of the
+ * last completed forward march to caller-owned host memory (ETAIM_EINVAL if
+ * there is none, or after etaim_delayed_field / an adjoint march / a change
+ * between the LDS and register y/z engines replaced the rings); load
+ * restores it into a context of the same problem (precision, batch, mesh,
+ * grid, N_g, M_n; ETAIM_EINVAL otherwise).  At the bench workload the state
+ * is 21.7 GB. */
+int etaim_state_size(const etaim_ctx *ctx, size_t *bytes);
+int etaim_state_save(const etaim_ctx *ctx, void *host, size_t bytes);
+int etaim_state_load(etaim_ctx *ctx, const void *host, size_t bytes);
+
 /* y = (Zmnear + Zmfft) x for 0 <= m <= N_g (Sec. 4 stages (i)-(iv)).
  * x, y: device complex128 [B][ns]. */
 int etaim_apply_z(etaim_ctx *ctx, int32_t m, const void *x, void *y);

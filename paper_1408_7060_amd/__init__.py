@@ -8,7 +8,7 @@ paper_1408_7060_amd.build``); there is no CPU fallback.
 from __future__ import annotations
 
 import ctypes
-from ctypes import POINTER, byref, c_double, c_int32, c_void_p
+from ctypes import POINTER, byref, c_double, c_int32, c_size_t, c_void_p
 
 import numpy as np
 
@@ -98,6 +98,29 @@ class Problem:
         st.iters_per_step = it.ctypes.data_as(POINTER(c_int32))
         _lib.check(_lib.load().etaim_march(self._h, c_void_p(_dptr(V)), c_void_p(_dptr(I)), nsteps, byref(st)))
         return I, _stats_dict(st, it)
+
+    def march_continue(self, V, I, first: int, nsteps: int):
+        """Steps first .. first + nsteps - 1 of the forward march, continuing
+        the history of the last march on this problem (or a loaded state);
+        I holds the earlier steps and receives these."""
+        it = np.zeros(nsteps, dtype=np.int32)
+        st = Stats()
+        st.iters_per_step = it.ctypes.data_as(POINTER(c_int32))
+        _lib.check(_lib.load().etaim_march_continue(self._h, c_void_p(_dptr(V)), c_void_p(_dptr(I)), first, nsteps,
+                                                    byref(st)))
+        return I, _stats_dict(st, it)
+
+    def save_state(self) -> np.ndarray:
+        """The march state (history rings, next step) as host bytes."""
+        n = c_size_t(0)
+        _lib.check(_lib.load().etaim_state_size(self._h, byref(n)))
+        buf = np.empty(n.value, dtype=np.uint8)
+        _lib.check(_lib.load().etaim_state_save(self._h, buf.ctypes.data_as(c_void_p), buf.nbytes))
+        return buf
+
+    def load_state(self, buf: np.ndarray):
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        _lib.check(_lib.load().etaim_state_load(self._h, buf.ctypes.data_as(c_void_p), buf.nbytes))
 
     def adjoint_march(self, S):
         L = self.empty(self.nt, self.batch, self.ns)

@@ -65,6 +65,10 @@ SIGNATURES = {
     "etaim_farfield": (c_int32, [c_void_p, c_int32, POINTER(c_double), c_void_p, c_void_p]),
     "etaim_farfield_adjoint": (c_int32, [c_void_p, c_int32, POINTER(c_double), c_void_p, c_void_p]),
     "etaim_adjoint_march": (c_int32, [c_void_p, c_void_p, c_void_p, POINTER(Stats)]),
+    "etaim_march_continue": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_int32, POINTER(Stats)]),
+    "etaim_state_size": (c_int32, [c_void_p, POINTER(c_size_t)]),
+    "etaim_state_save": (c_int32, [c_void_p, c_void_p, c_size_t]),
+    "etaim_state_load": (c_int32, [c_void_p, c_void_p, c_size_t]),
     "etaim_export": (c_int32, [c_void_p, c_int32, c_void_p, c_size_t]),
     "etaim_set_profiling": (c_int32, [c_void_p, c_int32]),
     "etaim_kernel_stats": (c_int32, [c_void_p, c_int32, POINTER(c_double), POINTER(c_double), POINTER(c_int64)]),

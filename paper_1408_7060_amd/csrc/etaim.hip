@@ -103,6 +103,10 @@ struct etaim_ctx {
     // batched-GMRES schedule: steps per host check, captured Arnoldi steps
     int sync_every = 1;
     int iter_hint = 0;  // Arnoldi steps of the last solve of the march (first chunk size)
+    // forward march state: the next step the history rings are ready for (-1:
+    // none), and the initial-guess order carried into it
+    int next_step = -1, guess_p_next = 1;
+    bool guess_dev_next = false;
     bool use_graph = false, capturing = false;
     hipStream_t cap_stream = nullptr;
     std::vector<hipGraphExec_t> graphs[2];  // [conj][j]
@@ -806,21 +810,28 @@ int gmres(etaim_ctx* c, const zd* rhs, zd* x, int conj, StepResult& res) {
 }
 
 // ---------------------------------------------------------------------------
+// Steps first .. first + count - 1 of a march (the adjoint march: first = 0).
+// With first > 0 the history rings continue from the last forward march on
+// this context (or a loaded state) that ended at step first; otherwise they
+// start empty.  Per-call arrays (norms, stats) are indexed by r - first.
 template <typename R>
-int march_impl(etaim_ctx* c, const zd* V, zd* I, etaim_stats* st, bool adjoint, int nsteps) {
-    const int nt = nsteps > 0 ? nsteps : c->prm.nt_steps, B = c->B, ns = c->ns;
+int march_impl(etaim_ctx* c, const zd* V, zd* I, etaim_stats* st, bool adjoint, int first, int count) {
+    const int nt = count, B = c->B, ns = c->ns;
     const size_t nB = (size_t)B * ns;
     const int conj = adjoint ? 1 : 0;
-    HIPCHK(hipMemsetAsync(c->ring, 0, (size_t)c->st.ng * 4 * B * c->Np * sizeof(cplx<R>), c->stream));
-    c->far_r0 = -1;  // the far parts belong to the previous history
-    c->iter_hint = 0;
-    if (c->st.mn >= 1) HIPCHK(hipMemsetAsync(c->hist, 0, (size_t)c->st.mn * nB * sizeof(zd), c->stream));
-    // excitation norms per step (instability detector)
+    if (first == 0) {
+        HIPCHK(hipMemsetAsync(c->ring, 0, (size_t)c->st.ng * 4 * B * c->Np * sizeof(cplx<R>), c->stream));
+        c->far_r0 = -1;  // the block sums belong to the previous history
+        c->iter_hint = 0;
+        if (c->st.mn >= 1) HIPCHK(hipMemsetAsync(c->hist, 0, (size_t)c->st.mn * nB * sizeof(zd), c->stream));
+    }
+    c->next_step = -1;  // valid again once this call completes its steps
+    // excitation norms per step of this call (instability detector)
     std::vector<double> nV((size_t)nt * B), nI((size_t)nt, 0.0);
     {
         double* d = nullptr;
         CHK(c->alloc(d, (size_t)nt * B));
-        hipLaunchKernelGGL(k_norm, dim3(nt * B), dim3(256), 0, c->stream, V, d, ns, nullptr);
+        hipLaunchKernelGGL(k_norm, dim3(nt * B), dim3(256), 0, c->stream, V + (size_t)first * nB, d, ns, nullptr);
         HIPCHK(hipMemcpyAsync(nV.data(), d, nV.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
         c->allocs.pop_back();
@@ -868,7 +879,12 @@ int march_impl(etaim_ctx* c, const zd* V, zd* I, etaim_stats* st, bool adjoint, 
     // fewer than two orders can be compared, else chosen on the device
     int guess_p = c->guess_order == 0 ? 0 : 1;
     bool guess_dev = false;
-    for (int r = 0; r < nt; ++r) {
+    if (first > 0) {
+        guess_p = c->guess_p_next;
+        guess_dev = c->guess_dev_next;
+    }
+    for (int r = first; r < first + nt; ++r) {
+        const int i = r - first;  // index within this call
         const int l = adjoint ? nt - 1 - r : r;
         const zd* Vl = V + (size_t)l * nB;
         zd* Il = I + (size_t)l * nB;
@@ -890,11 +906,11 @@ int march_impl(etaim_ctx* c, const zd* V, zd* I, etaim_stats* st, bool adjoint, 
         CHK(gmres<R>(c, c->rhs, c->xk, conj, sr));
         c->iter_hint = std::min(sr.iters, c->prm.restart);
         // gmres has waited on the stream: the previous step's events are complete
-        if (r >= 1) CHK(phase_ms(r - 1));
+        if (r > first) CHK(phase_ms(r - 1));
         HIPCHK(hipEventRecord(ev[2], c->stream));
         HIPCHK(hipMemcpyAsync(Il, c->xk, nB * sizeof(zd), hipMemcpyDeviceToDevice, c->stream));
         CHK(Ops<R>::commit(c, r, c->xk));
-        hipLaunchKernelGGL(k_norm, dim3(B), dim3(256), 0, c->stream, c->xk, nrm_all + (size_t)r * B, ns, nullptr);
+        hipLaunchKernelGGL(k_norm, dim3(B), dim3(256), 0, c->stream, c->xk, nrm_all + (size_t)i * B, ns, nullptr);
         const int pmax = std::min(r, c->guess_order);
         if (pmax >= 2) {
             hipLaunchKernelGGL(k_pred_err, dim3(kPredBlocks), dim3(256), 0, c->stream, (const zd*)I, nB,
@@ -911,16 +927,16 @@ int march_impl(etaim_ctx* c, const zd* V, zd* I, etaim_stats* st, bool adjoint, 
         // kernel traces are resolved in batches (each flush waits on the stream)
         if (c->pending.size() >= kTraceBatch) CHK(trace_flush(c));
         if (eager_detect) {
-            HIPCHK(hipMemcpyAsync(c->res_h + B, nrm_all + (size_t)r * B, B * sizeof(double), hipMemcpyDeviceToHost,
+            HIPCHK(hipMemcpyAsync(c->res_h + B, nrm_all + (size_t)i * B, B * sizeof(double), hipMemcpyDeviceToHost,
                                   c->stream));
             HIPCHK(hipStreamSynchronize(c->stream));
-            for (int b = 0; b < B; ++b) nI[r] = std::max(nI[r], c->res_h[B + b]);
+            for (int b = 0; b < B; ++b) nI[i] = std::max(nI[i], c->res_h[B + b]);
         }
-        steps = r + 1;
+        steps = i + 1;
         tot_iters += sr.iters;
         max_iters = std::max(max_iters, sr.iters);
         maxres = std::max(maxres, sr.resid);
-        if (st && st->iters_per_step) st->iters_per_step[r] = sr.iters;
+        if (st && st->iters_per_step) st->iters_per_step[i] = sr.iters;
         if (sr.nonfinite) {
             nonfinite = true;
             break;
@@ -930,13 +946,13 @@ int march_impl(etaim_ctx* c, const zd* V, zd* I, etaim_stats* st, bool adjoint, 
             if (!(c->prm.flags & ETAIM_F_CONTINUE_ON_NOCONV)) break;
         }
         if (eager_detect) {
-            detect(r);
+            detect(i);
             if (unstable >= 0) break;
         }
     }
     HIPCHK(hipStreamSynchronize(c->stream));
     CHK(trace_flush(c));
-    if (steps >= 1) CHK(phase_ms(steps - 1));
+    if (steps >= 1) CHK(phase_ms(first + steps - 1));
     if (!eager_detect && steps >= 1) {
         std::vector<double> na((size_t)steps * B);
         HIPCHK(hipMemcpy(na.data(), nrm_all, na.size() * sizeof(double), hipMemcpyDeviceToHost));
@@ -955,18 +971,23 @@ int march_impl(etaim_ctx* c, const zd* V, zd* I, etaim_stats* st, bool adjoint, 
         st->total_iters = tot_iters;
         st->max_iters = max_iters;
         st->first_noconv_step = first_noconv;
-        st->unstable_step = unstable;
+        st->unstable_step = unstable >= 0 ? first + unstable : -1;
         st->ms_rhs = ms_rhs;
         st->ms_solve = ms_solve;
         st->ms_commit = ms_commit;
         st->ms_total = ms_rhs + ms_solve + ms_commit;
         st->max_rel_residual = maxres;
     }
-    if (nonfinite) return fail(ETAIM_ENONFINITE, "non-finite GMRES residual at step " + std::to_string(steps));
+    if (!adjoint && steps == nt && !nonfinite) {
+        c->next_step = first + steps;
+        c->guess_p_next = guess_p;
+        c->guess_dev_next = guess_dev;
+    }
+    if (nonfinite) return fail(ETAIM_ENONFINITE, "non-finite GMRES residual at step " + std::to_string(first + steps - 1));
     if (first_noconv >= 0 && !(c->prm.flags & ETAIM_F_CONTINUE_ON_NOCONV))
         return fail(ETAIM_ENOCONV, "GMRES reached maxit at step " + std::to_string(first_noconv));
     if (unstable >= 0 && (c->prm.flags & ETAIM_F_FAIL_ON_UNSTABLE))
-        return fail(ETAIM_EUNSTABLE, "late-time growth detected at step " + std::to_string(unstable));
+        return fail(ETAIM_EUNSTABLE, "late-time growth detected at step " + std::to_string(first + unstable));
     return ETAIM_OK;
 }
 
@@ -1372,6 +1393,7 @@ int etaim_delayed_field(etaim_ctx* c, const void* hist, void* b) {
         using R = decltype(tag);
         HIPCHK(hipMemsetAsync(c->ring, 0, (size_t)ng * 4 * c->B * c->Np * sizeof(cplx<R>), c->stream));
         c->far_r0 = -1;
+        c->next_step = -1;  // the rings now hold the injected history
         if (c->st.mn >= 1) HIPCHK(hipMemsetAsync(c->hist, 0, (size_t)c->st.mn * nB * sizeof(zd), c->stream));
         for (int m = ng; m >= 1; --m) CHK(Ops<R>::commit(c, ng - m, (const zd*)hist + (size_t)(m - 1) * nB));
         CHK(Ops<R>::delayed(c, ng, c->zero, (zd*)b, 0));
@@ -1386,8 +1408,99 @@ int etaim_march(etaim_ctx* c, const void* V, void* I_out, int32_t nsteps, etaim_
     CHK(check_ctx(c));
     if (!V || !I_out) return fail(ETAIM_EINVAL, "null V or I_out");
     if (nsteps < 0 || nsteps > c->prm.nt_steps) return fail(ETAIM_EINVAL, "nsteps out of range");
-    return c->prec == ETAIM_FP32 ? march_impl<float>(c, (const zd*)V, (zd*)I_out, st, false, nsteps)
-                                 : march_impl<double>(c, (const zd*)V, (zd*)I_out, st, false, nsteps);
+    const int n = nsteps > 0 ? nsteps : c->prm.nt_steps;
+    return c->prec == ETAIM_FP32 ? march_impl<float>(c, (const zd*)V, (zd*)I_out, st, false, 0, n)
+                                 : march_impl<double>(c, (const zd*)V, (zd*)I_out, st, false, 0, n);
+}
+
+int etaim_march_continue(etaim_ctx* c, const void* V, void* I_out, int32_t first, int32_t nsteps,
+                         etaim_stats* st) {
+    CHK(check_ctx(c));
+    if (!V || !I_out) return fail(ETAIM_EINVAL, "null V or I_out");
+    if (first < 1 || nsteps < 1 || first + nsteps > c->prm.nt_steps)
+        return fail(ETAIM_EINVAL, "steps out of range: need 1 <= first, first + nsteps <= nt_steps");
+    if (c->next_step != first)
+        return fail(ETAIM_EINVAL, "the history is not at step " + std::to_string(first) + " (it is at " +
+                                      std::to_string(c->next_step) + ")");
+    return c->prec == ETAIM_FP32 ? march_impl<float>(c, (const zd*)V, (zd*)I_out, st, false, first, nsteps)
+                                 : march_impl<double>(c, (const zd*)V, (zd*)I_out, st, false, first, nsteps);
+}
+
+// ---- march state (history rings and the carried initial-guess order)
+namespace {
+struct StateHeader {
+    char magic[8];
+    int32_t version, prec, B, ns, ng, mn, next_step, guess_p, guess_dev, pnext;
+    int64_t Np, ring_bytes, hist_bytes;
+};
+constexpr char kStateMagic[8] = {'E', 'T', 'A', 'I', 'M', 'S', 'T', '1'};
+
+size_t ring_bytes(const etaim_ctx* c) {
+    return (size_t)c->st.ng * 4 * c->B * c->Np * (c->prec == ETAIM_FP32 ? sizeof(zf) : sizeof(zd));
+}
+size_t hist_bytes(const etaim_ctx* c) { return (size_t)std::max(c->st.mn, 1) * c->B * c->ns * sizeof(zd); }
+}  // namespace
+
+int etaim_state_size(const etaim_ctx* c, size_t* bytes) {
+    CHK(check_ctx(c));
+    if (!bytes) return fail(ETAIM_EINVAL, "null bytes");
+    *bytes = sizeof(StateHeader) + ring_bytes(c) + hist_bytes(c);
+    return ETAIM_OK;
+}
+
+int etaim_state_save(const etaim_ctx* c, void* host, size_t bytes) {
+    CHK(check_ctx(c));
+    if (!host) return fail(ETAIM_EINVAL, "null host pointer");
+    const size_t rb = ring_bytes(c), hb = hist_bytes(c);
+    if (bytes != sizeof(StateHeader) + rb + hb) return fail(ETAIM_EINVAL, "state size mismatch");
+    if (c->next_step < 1) return fail(ETAIM_EINVAL, "no forward march state to save");
+    StateHeader h{};
+    std::memcpy(h.magic, kStateMagic, 8);
+    h.version = 1;
+    h.prec = c->prec;
+    h.B = c->B;
+    h.ns = c->ns;
+    h.ng = c->st.ng;
+    h.mn = c->st.mn;
+    h.next_step = c->next_step;
+    h.guess_p = c->guess_p_next;
+    h.guess_dev = c->guess_dev_next ? 1 : 0;
+    h.Np = (int64_t)c->Np;
+    h.ring_bytes = (int64_t)rb;
+    h.hist_bytes = (int64_t)hb;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipMemcpy(&h.pnext, c->pnext, sizeof(int), hipMemcpyDeviceToHost));
+    unsigned char* p = (unsigned char*)host;
+    std::memcpy(p, &h, sizeof h);
+    HIPCHK(hipMemcpy(p + sizeof h, c->ring, rb, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(p + sizeof h + rb, c->hist, hb, hipMemcpyDeviceToHost));
+    return ETAIM_OK;
+}
+
+int etaim_state_load(etaim_ctx* c, const void* host, size_t bytes) {
+    CHK(check_ctx(c));
+    if (!host) return fail(ETAIM_EINVAL, "null host pointer");
+    const size_t rb = ring_bytes(c), hb = hist_bytes(c);
+    if (bytes != sizeof(StateHeader) + rb + hb) return fail(ETAIM_EINVAL, "state size mismatch");
+    StateHeader h;
+    std::memcpy(&h, host, sizeof h);
+    if (std::memcmp(h.magic, kStateMagic, 8) != 0 || h.version != 1)
+        return fail(ETAIM_EINVAL, "not a march state of this library");
+    if (h.prec != c->prec || h.B != c->B || h.ns != c->ns || h.ng != c->st.ng || h.mn != c->st.mn ||
+        h.Np != (int64_t)c->Np || h.ring_bytes != (int64_t)rb || h.hist_bytes != (int64_t)hb)
+        return fail(ETAIM_EINVAL, "the state belongs to a different problem (precision, batch, mesh or grid)");
+    if (h.next_step < 1 || h.next_step > c->prm.nt_steps) return fail(ETAIM_EINVAL, "corrupt state: step");
+    const unsigned char* p = (const unsigned char*)host;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipMemcpy(c->ring, p + sizeof h, rb, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->hist, p + sizeof h + rb, hb, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->pnext, &h.pnext, sizeof(int), hipMemcpyHostToDevice));
+    c->next_step = h.next_step;
+    c->guess_p_next = h.guess_p;
+    c->guess_dev_next = h.guess_dev != 0;
+    c->far_r0 = -1;  // block sums are recomputed from the loaded ring
+    c->iter_hint = 0;
+    return ETAIM_OK;
 }
 
 int etaim_adjoint_march(etaim_ctx* c, const void* S, void* Lambda, etaim_stats* st) {
@@ -1396,8 +1509,8 @@ int etaim_adjoint_march(etaim_ctx* c, const void* S, void* Lambda, etaim_stats* 
     // Z^H = conj(Z): every operator is complex-symmetric, so the adjoint
     // march runs the same kernels with conjugated Green spectra, near-zone
     // values and preconditioner, backward in time
-    return c->prec == ETAIM_FP32 ? march_impl<float>(c, (const zd*)S, (zd*)Lambda, st, true, 0)
-                                 : march_impl<double>(c, (const zd*)S, (zd*)Lambda, st, true, 0);
+    return c->prec == ETAIM_FP32 ? march_impl<float>(c, (const zd*)S, (zd*)Lambda, st, true, 0, c->prm.nt_steps)
+                                 : march_impl<double>(c, (const zd*)S, (zd*)Lambda, st, true, 0, c->prm.nt_steps);
 }
 
 int etaim_export(const etaim_ctx* c, int32_t what, void* host, size_t bytes) {

@@ -94,6 +94,8 @@ void put_shape(etaim_ctx* c, const Shape& s) {
     c->x_engine = s.xeng;
     c->guess_order = s.guess;
     c->precond = s.precond;
+    // the LDS and register engines lay the spectrum ring out differently
+    if ((c->yz_engine == 0) != (s.engine == 0)) c->next_step = -1;
     if (c->delay_block != s.dblock) c->far_r0 = -1;
     c->delay_block = s.dblock;
     drop_graphs(c);  // captured steps hold the old launch shapes

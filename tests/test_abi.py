@@ -65,6 +65,11 @@ def test_rejects_null_arguments():
     assert lib.etaim_autotune(None, 100, None, ctypes.byref(t)) == _lib().EINVAL
     assert lib.etaim_get_tuning(None, ctypes.byref(t)) == _lib().EINVAL
     assert lib.etaim_set_tuning(None, ctypes.byref(t)) == _lib().EINVAL
+    assert lib.etaim_march_continue(None, None, None, 1, 1, None) == _lib().EINVAL
+    n = ctypes.c_size_t(0)
+    assert lib.etaim_state_size(None, ctypes.byref(n)) == _lib().EINVAL
+    assert lib.etaim_state_save(None, None, 0) == _lib().EINVAL
+    assert lib.etaim_state_load(None, None, 0) == _lib().EINVAL
     lib.etaim_destroy(None)
 
 
