@@ -207,6 +207,28 @@ int etaim_farfield(etaim_ctx *ctx, int32_t nd, const double *dirs, const void *I
 int etaim_farfield_adjoint(etaim_ctx *ctx, int32_t nd, const double *dirs, const void *Ubar,
                            void *S);
 
+/* Co-polarised radar cross section from far-field envelopes (Sec. 2.4):
+ * for frequency f_c + df[i], incidence b and direction d,
+ *   sigma_out[i][b][d] = 4 pi |pol_d . U_bd(df_i)|^2 / G(df_i)^2,
+ *   U_bd(df) = dt sum_l U[l][b][d] exp(-j 2 pi df (l+1) dt),
+ *   G(df) = pulse_sigma sqrt(2 pi) exp(-2 pi^2 pulse_sigma^2 df^2),
+ * i.e. the far field per unit incident field at that frequency: the
+ * envelope's Fourier transform over that of the Gaussian pulse of eq. (1)
+ * of width pulse_sigma (its delay and carrier phase drop out of |.|).
+ * U: device complex128 [N_t][B][nd][3] as etaim_farfield writes it; pol:
+ * host [nd][3] unit vectors (theta-hat for sigma_theta-theta); df: host
+ * [nf] in Hz; sigma_out: device double [nf][B][nd], in m^2. */
+int etaim_rcs(etaim_ctx *ctx, int32_t nd, const double *pol, int32_t nf, const double *df,
+              double pulse_sigma, const void *U, double *sigma_out);
+
+/* Thresholded dB-error norm of eq. (2) (Sec. 2.4) between two RCS patterns
+ * sampled on n directions with quadrature weights w (sin(theta) on a
+ * (theta, phi) grid): values are mapped to max(10 log10 sigma, TH) - TH with
+ * TH = 10 log10(max sigma_ref) - floor_db (the paper uses 80 dB), then
+ * err = sum w (a - b)^2 / sum w b^2.  Host arrays; needs no context. */
+int etaim_db_error(int32_t n, const double *sigma, const double *sigma_ref, const double *w, double floor_db,
+                   double *err);
+
 /* Adjoint march, backward in time with the conjugate Green spectra and
  * conjugate near-zone values (the operators are complex-symmetric):
  *   Z0^H lambda_l = S_l - sum_{m=1}^{N_g} Zm^H lambda_{l+m}, l = N_t..1.

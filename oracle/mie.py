@@ -123,6 +123,24 @@ def rcs_theta_current(surf, I: np.ndarray, f: float, d, th_hat):
     return (4 * math.pi * np.abs(Eth) ** 2).reshape(d.shape[:-1])
 
 
+def rcs_envelope(u: np.ndarray, dt: float, df: float, sigma: float, pol: np.ndarray) -> np.ndarray:
+    """sigma_pol(f_c + df) [D] from the far-field envelope samples u [nt, D, 3]
+    of one incidence (u[l] at t = (l+1) dt, the march's sample times) driven
+    by the Gaussian pulse of eq. (1) with width sigma.  The time-harmonic
+    far field at f = f_c + df is the envelope's Fourier transform at df
+    divided by the incident envelope's at the origin,
+        U(df) = dt sum_l u_l exp(-j 2 pi df (l+1) dt),
+        G(df) = sigma sqrt(2 pi) exp(-2 pi^2 sigma^2 df^2)
+    (the transform of g = exp(-t^2/2 sigma^2); its delay and carrier phase
+    drop out of |.|), so sigma_pol = 4 pi |pol . U(df)|^2 / G(df)^2 as for a
+    unit incident field (Sec. 2.4)."""
+    nt = u.shape[0]
+    ph = np.exp(-2j * math.pi * df * (np.arange(nt) + 1.0) * dt)
+    U = dt * np.einsum("l,ldx->dx", ph, u)
+    G = sigma * math.sqrt(2.0 * math.pi) * math.exp(-2.0 * math.pi ** 2 * sigma ** 2 * df ** 2)
+    return 4.0 * math.pi * np.abs(np.einsum("dx,dx->d", U, pol)) ** 2 / G ** 2
+
+
 def db_error(sig: np.ndarray, sig_ref: np.ndarray, theta: np.ndarray, floor_db: float = 80.0) -> float:
     """Eq. (2): thresholded dB-error norm over the (theta, phi) grid."""
     TH = 10 * np.log10(np.max(sig_ref)) - floor_db

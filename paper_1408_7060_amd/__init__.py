@@ -154,6 +154,20 @@ class Problem:
                                                       c_void_p(_dptr(U)), c_void_p(_dptr(S))))
         return S
 
+    def rcs(self, U, pol, df, pulse_sigma: float):
+        """Co-polarised RCS [len(df), B, nd] (m^2, device float64) at f_c + df
+        from far-field envelopes U [N_t][B][nd][3] (farfield), for the
+        Gaussian pulse of width pulse_sigma; pol [nd][3] (theta-hat for
+        sigma_theta-theta)."""
+        torch = _torch()
+        p = np.ascontiguousarray(np.atleast_2d(pol), dtype=np.float64)
+        f = np.ascontiguousarray(np.atleast_1d(df), dtype=np.float64)
+        out = torch.empty((len(f), self.batch, len(p)), dtype=torch.float64, device=U.device)
+        _lib.check(_lib.load().etaim_rcs(self._h, len(p), p.ctypes.data_as(POINTER(c_double)), len(f),
+                                         f.ctypes.data_as(POINTER(c_double)), float(pulse_sigma),
+                                         c_void_p(_dptr(U)), c_void_p(out.data_ptr())))
+        return out
+
     _EXPORT = {"lambda": (0, np.float64, lambda i: (i["ns"], 4, 64)),
                "corners": (1, np.int32, lambda i: (i["ns"], 3)),
                "rowptr": (2, np.int32, lambda i: (i["ns"] + 1,)),
@@ -221,6 +235,21 @@ class Problem:
             self.close()
         except Exception:
             pass
+
+
+def db_error(sigma, sigma_ref, weight, floor_db: float = 80.0) -> float:
+    """Thresholded dB-error norm of eq. (2) between two RCS patterns on the
+    same directions (host arrays; weight = sin(theta) on a (theta, phi) grid)."""
+    a = np.ascontiguousarray(np.ravel(sigma), dtype=np.float64)
+    b = np.ascontiguousarray(np.ravel(sigma_ref), dtype=np.float64)
+    w = np.ascontiguousarray(np.ravel(weight), dtype=np.float64)
+    if not (a.size == b.size == w.size):
+        raise ValueError("sigma, sigma_ref and weight need the same size")
+    err = c_double(0)
+    _lib.check(_lib.load().etaim_db_error(a.size, a.ctypes.data_as(POINTER(c_double)),
+                                          b.ctypes.data_as(POINTER(c_double)), w.ctypes.data_as(POINTER(c_double)),
+                                          floor_db, byref(err)))
+    return err.value
 
 
 class EtaimMarch:

@@ -70,6 +70,10 @@ SIGNATURES = {
     "etaim_state_save": (c_int32, [c_void_p, c_void_p, c_size_t]),
     "etaim_state_load": (c_int32, [c_void_p, c_void_p, c_size_t]),
     "etaim_export": (c_int32, [c_void_p, c_int32, c_void_p, c_size_t]),
+    "etaim_rcs": (c_int32, [c_void_p, c_int32, POINTER(c_double), c_int32, POINTER(c_double), c_double, c_void_p,
+                            c_void_p]),
+    "etaim_db_error": (c_int32, [c_int32, POINTER(c_double), POINTER(c_double), POINTER(c_double), c_double,
+                                 POINTER(c_double)]),
     "etaim_set_profiling": (c_int32, [c_void_p, c_int32]),
     "etaim_kernel_stats": (c_int32, [c_void_p, c_int32, POINTER(c_double), POINTER(c_double), POINTER(c_int64)]),
     "etaim_autotune": (c_int32, [c_void_p, c_int32, c_char_p, POINTER(Tuning)]),

@@ -1356,6 +1356,33 @@ __global__ void __launch_bounds__(256) k_farfield_apply(zd* __restrict__ U, cons
 }
 
 // S[j][b][k] = sum_tap sum_{d,x} conj(F[tap][d][x][k]) U[j + m_lo + tap][b][d][x]
+// Co-polarised RCS from far-field envelopes (Sec. 2.4), one thread per
+// (frequency i, incidence b, direction d): the envelope's Fourier transform
+// at df[i] (samples at t = (l+1) dt), projected on pol[d], over the incident
+// Gaussian envelope's transform G[i]: sigma = 4 pi |pol . U(df)|^2 / G^2.
+__global__ void k_rcs(double* __restrict__ out, const zd* __restrict__ U, const double* __restrict__ pol,
+                      const double* __restrict__ df, const double* __restrict__ G, int nt, int B, int nd, int nf,
+                      double dt) {
+    const size_t tot = (size_t)nf * B * nd;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot; e += (size_t)gridDim.x * blockDim.x) {
+        const int d = (int)(e % nd);
+        const size_t r = e / nd;
+        const int b = (int)(r % B), i = (int)(r / B);
+        const double px = pol[3 * d], py = pol[3 * d + 1], pz = pol[3 * d + 2];
+        const double w = -2.0 * kPi * df[i] * dt;
+        zd acc{0, 0};
+        for (int l = 0; l < nt; ++l) {
+            const zd* u = U + (((size_t)l * B + b) * nd + d) * 3;
+            const zd v = zd{px * u[0].x + py * u[1].x + pz * u[2].x, px * u[0].y + py * u[1].y + pz * u[2].y};
+            double sn, cs;
+            sincos(w * (l + 1.0), &sn, &cs);
+            acc += v * zd{cs, sn};
+        }
+        const double a2 = (acc.x * acc.x + acc.y * acc.y) * dt * dt;
+        out[e] = 4.0 * kPi * a2 / (G[i] * G[i]);
+    }
+}
+
 __global__ void k_farfield_adjoint(zd* __restrict__ S, const zd* __restrict__ F, const zd* __restrict__ U, int nt,
                                    int B, int nd, int ns, int ntap, int m_lo) {
     const size_t tot = (size_t)nt * B * ns;

@@ -1711,4 +1711,50 @@ int etaim_farfield_adjoint(etaim_ctx* c, int32_t nd, const double* dirs, const v
     c->dev_bytes = before;
     return ETAIM_OK;
 }
+
+int etaim_rcs(etaim_ctx* c, int32_t nd, const double* pol, int32_t nf, const double* df, double pulse_sigma,
+              const void* U, double* sigma_out) {
+    CHK(check_ctx(c));
+    if (nd < 1 || nf < 1 || !pol || !df || !U || !sigma_out || !(pulse_sigma > 0))
+        return fail(ETAIM_EINVAL, "rcs needs nd >= 1, nf >= 1, pol, df, pulse_sigma > 0, U, sigma_out");
+    // the incident envelope's transform: g = exp(-t^2 / 2 sigma^2) -> sigma sqrt(2 pi) exp(-2 pi^2 sigma^2 df^2)
+    std::vector<double> host((size_t)3 * nd + 2 * (size_t)nf);
+    std::memcpy(host.data(), pol, sizeof(double) * 3 * nd);
+    for (int i = 0; i < nf; ++i) {
+        host[3 * (size_t)nd + i] = df[i];
+        host[3 * (size_t)nd + nf + i] =
+            pulse_sigma * std::sqrt(2.0 * kPi) * std::exp(-2.0 * kPi * kPi * pulse_sigma * pulse_sigma * df[i] * df[i]);
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const int64_t before = c->dev_bytes;
+    double* d = nullptr;
+    CHK(c->upload(d, host));
+    const size_t tot = (size_t)nf * c->B * nd;
+    hipLaunchKernelGGL(k_rcs, dim3(blocks_for(tot)), dim3(256), 0, c->stream, sigma_out, (const zd*)U, d,
+                       d + 3 * (size_t)nd, d + 3 * (size_t)nd + nf, c->prm.nt_steps, c->B, nd, nf, c->st.dt);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    CHK(release_last(c, 1));
+    c->dev_bytes = before;
+    return ETAIM_OK;
+}
+
+int etaim_db_error(int32_t n, const double* sigma, const double* sigma_ref, const double* w, double floor_db,
+                   double* err) {
+    if (n < 1 || !sigma || !sigma_ref || !w || !err || !(floor_db > 0))
+        return fail(ETAIM_EINVAL, "db_error needs n >= 1, sigma, sigma_ref, w, floor_db > 0, err");
+    double peak = 0;
+    for (int i = 0; i < n; ++i) peak = std::max(peak, sigma_ref[i]);
+    if (!(peak > 0)) return fail(ETAIM_EINVAL, "the reference pattern has no positive value");
+    const double th = 10.0 * std::log10(peak) - floor_db;
+    auto thr = [&](double v) { return std::max(10.0 * std::log10(std::max(v, 1e-300)), th) - th; };
+    double num = 0, den = 0;
+    for (int i = 0; i < n; ++i) {
+        const double a = thr(sigma[i]), b = thr(sigma_ref[i]);
+        num += (a - b) * (a - b) * w[i];
+        den += b * b * w[i];
+    }
+    *err = num / den;
+    return ETAIM_OK;
+}
 }  // extern "C"

@@ -119,3 +119,23 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(L, "_LIB", None)
     with pytest.raises(ImportError):
         L.load()
+
+
+def test_db_error_matches_the_oracle():
+    """eq. (2) in the library (host code) against the oracle's, on random
+    patterns spanning 100 dB, with values below the threshold on both sides."""
+    from oracle import mie
+    from paper_1408_7060_amd import db_error
+    rng = np.random.default_rng(7)
+    TH, PH, d, th = mie.sphere_grid(19, 36)
+    ref = 10.0 ** rng.uniform(-10, 0, TH.shape)
+    sig = ref * 10.0 ** rng.normal(0, 0.05, TH.shape)
+    sig[3, 5] = 0.0
+    for floor in (80.0, 30.0):
+        e = db_error(sig, ref, np.sin(TH), floor)
+        assert e == pytest.approx(mie.db_error(sig, ref, TH, floor), rel=1e-12)
+    assert db_error(ref, ref, np.sin(TH)) == 0.0
+    lib = _lib().load()
+    assert lib.etaim_db_error(0, None, None, None, 80.0, None) == _lib().EINVAL
+    assert lib.etaim_rcs(None, 1, None, 1, None, 1.0, None, None) == _lib().EINVAL
+
