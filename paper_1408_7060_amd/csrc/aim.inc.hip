@@ -527,7 +527,8 @@ __global__ void __launch_bounds__(kQuadThreads) k_yzq_green(cplx<R>* __restrict_
 //     conj(w_{2N}^{pz z}); the two pz columns are summed into the plane.
 // GT is the Green table with ky and kz exchanged ([ky fold][kz fold] per
 // plane), so that the lanes of phase 2 (consecutive kz') read neighbouring
-// entries.  Threads: 4N (2N busy in phases 1 and 3); in FP32 the registers
+// entries.  Threads: 4N (2N busy in phases 1 and 3, parity-grouped by wave);
+// in FP32 the registers
 // are capped for three waves per SIMD (four blocks per CU at N = 48).
 template <typename R, int N>
 __global__ void __launch_bounds__(4 * N) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 3 : 1))) k_yzc_green(cplx<R>* __restrict__ A, const cplx<R>* __restrict__ GT,
@@ -540,9 +541,15 @@ __global__ void __launch_bounds__(4 * N) __attribute__((amdgpu_waves_per_eu(size
     const int bc = blockIdx.x, kx = blockIdx.y, Lx = g.L[0];
     cplx<R>* pl = A + ((size_t)bc * Lx + kx) * (size_t)(N * N);
     const int i = threadIdx.x;
+    // phases 1 and 3: the pz = 1 tasks start at lane 64 where the block has
+    // room, so that the first wave holds only pz = 0 tasks and skips the
+    // twiddles; phase 2: py-major, so that the first wave skips them there
+    constexpr int OFF1 = 4 * N >= 64 + N ? 64 : N;
+    const bool zt = i < N || (i >= OFF1 && i < OFF1 + N);
+    const int zpz = i < N ? 0 : 1, zy = i < N ? i : i - OFF1;
     cplx<R> u[N];
-    if (i < 2 * N) {
-        const int pz = i / N, y = i - pz * N;
+    if (zt) {
+        const int pz = zpz, y = zy;
 #pragma unroll
         for (int z = 0; z < N; ++z) u[z] = pl[z * N + y];
         if (pz) {
@@ -553,7 +560,7 @@ __global__ void __launch_bounds__(4 * N) __attribute__((amdgpu_waves_per_eu(size
         tile_col<R, N>(qtile<R, N>(t0, pz), y, u, true);
     }
     __syncthreads();
-    const int pz2 = i / (2 * N), py = (i / N) & 1, kz = i % N;
+    const int py = i / (2 * N), pz2 = (i / N) & 1, kz = i % N;
     {
         const int gx = g.N[0] + 1, gg = N + 1;
         const cplx<R>* Gk = GT + ((size_t)((bc & 3) == 3 ? 1 : 0) * gx + fold(kx, Lx)) * (size_t)(gg * gg);
@@ -588,8 +595,8 @@ __global__ void __launch_bounds__(4 * N) __attribute__((amdgpu_waves_per_eu(size
         for (int y = 0; y < N; ++y) row[y] += u[y];
     }
     __syncthreads();
-    if (i < 2 * N) {
-        const int pz = i / N, y = i - pz * N;
+    if (zt) {
+        const int pz = zpz, y = zy;
         tile_col<R, N>(qtile<R, N>(t0, pz), y, u, false);
         dft_small<R, N>(u, true);
         if (pz) {
@@ -625,9 +632,14 @@ k_yzc_commit(const cplx<R>* __restrict__ A, cplx<R>* __restrict__ slot, const cp
     const cplx<R>* pl = A + ((size_t)bc * Lx + kx) * (size_t)NN;
     cplx<R>* out = slot + ((size_t)bc * Lx + kx) * (size_t)(4 * NN);
     const int i = threadIdx.x;
+    // as in k_yzc_green: pz = 1 column tasks from lane 64 where the block has
+    // room, row tasks py-major, so that the first wave skips the twiddles
+    constexpr int OFF1 = 4 * N >= 64 + N ? 64 : N;
+    const bool zt = i < N || (i >= OFF1 && i < OFF1 + N);
+    const int zpz = i < N ? 0 : 1, zy = i < N ? i : i - OFF1;
     cplx<R> u[N];
-    if (i < 2 * N) {
-        const int pz = i / N, y = i - pz * N;
+    if (zt) {
+        const int pz = zpz, y = zy;
 #pragma unroll
         for (int z = 0; z < N; ++z) u[z] = pl[z * N + y];
         if (pz) {
@@ -638,7 +650,7 @@ k_yzc_commit(const cplx<R>* __restrict__ A, cplx<R>* __restrict__ slot, const cp
         tile_col<R, N>(qtile<R, N>(t0, pz), y, u, true);
     }
     __syncthreads();
-    const int pz2 = i / (2 * N), py = (i / N) & 1, kz = i % N;
+    const int py = i / (2 * N), pz2 = (i / N) & 1, kz = i % N;
     tile_row<R, N>(qtile<R, N>(t0, pz2), kz, u, false);
     __syncthreads();
     if (py) {
