@@ -780,11 +780,10 @@ __global__ void __launch_bounds__(kDelayThreads) k_yzq_delayed(const cplx<R>* __
             }
             // the older history's part of the sum, precomputed for this step's time block
             if (Fj != nullptr && i < PAIRS) {
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    acc0[r][h] = Fj[roff0 + 2 * i + h];
-                    acc1[r][h] = Fj[roff1 + 2 * i + h];
-                }
+                *reinterpret_cast<typename Pair<R>::type*>(acc0[r]) =
+                    *reinterpret_cast<const typename Pair<R>::type*>(Fj + roff0 + 2 * i);
+                *reinterpret_cast<typename Pair<R>::type*>(acc1[r]) =
+                    *reinterpret_cast<const typename Pair<R>::type*>(Fj + roff1 + 2 * i);
             }
         }
         for (int m = 1; m <= nm; ++m) {
@@ -866,8 +865,11 @@ __global__ void __launch_bounds__(kDelay1Threads) k_yzq_delayed1(const cplx<R>* 
                 const int e = 2 * i + h, qq = e / NN, rr = e - qq * NN;
                 const int kz = 2 * (rr / N) + (qq >> 1), ky = 2 * (rr % N) + (qq & 1);
                 gi[r][h] = fold(kz, 2 * N) * gg + fold(ky, 2 * N);
-                acc[r][h] = (Fj != nullptr && i < PAIRS) ? Fj[roff + e] : cplx<R>{0, 0};
+                acc[r][h] = cplx<R>{0, 0};
             }
+            if (Fj != nullptr && i < PAIRS)
+                *reinterpret_cast<typename Pair<R>::type*>(acc[r]) =
+                    *reinterpret_cast<const typename Pair<R>::type*>(Fj + roff + 2 * i);
         }
         for (int m = 1; m <= nm; ++m) {
             int s = (cur - m) % ng;
@@ -1125,10 +1127,11 @@ __global__ void __launch_bounds__(256) k_interp_near(
             nacc.x += __shfl_xor(nacc.x, o, 64);
             nacc.y += __shfl_xor(nacc.y, o, 64);
         }
-        // transposing butterfly over lane bits 5..1: after the exchange over
-        // bit 2h a lane keeps h partial sums, those of the half its bit
-        // selects; finally bit 0 pairs up, and lane 2 bb + {0, 1} holds the
-        // full sum of column bb
+        // transposing butterfly over the top log2(kInterpCols) lane bits: after
+        // the exchange over a bit a lane keeps half its partial sums, those of
+        // the half its bit selects; the lower bits then pair up, and the GL
+        // lanes GL bb + {0 .. GL - 1} hold the full sum of column bb
+        constexpr int GL = 64 / kInterpCols;
 #pragma unroll
         for (int h = kInterpCols / 2, bit = 32; h >= 1; h >>= 1, bit >>= 1) {
             const bool up = (lane & bit) != 0;
@@ -1139,12 +1142,15 @@ __global__ void __launch_bounds__(256) k_interp_near(
                 acc[i] = keep + cplx<R>{__shfl_xor(send.x, bit, 64), __shfl_xor(send.y, bit, 64)};
             }
         }
-        cplx<R> tot = acc[0] + cplx<R>{__shfl_xor(acc[0].x, 1, 64), __shfl_xor(acc[0].y, 1, 64)};
-        const int bb = lane >> 1;
+        cplx<R> tot = acc[0];
+#pragma unroll
+        for (int bit = GL / 2; bit >= 1; bit >>= 1)
+            tot += cplx<R>{__shfl_xor(tot.x, bit, 64), __shfl_xor(tot.y, bit, 64)};
+        const int bb = lane / GL;
         // the near-zone total of column bb sits in lane bb (entry slot 0)
         const cplx<R> near{__shfl(nacc.x, bb, 64), __shfl(nacc.y, bb, 64)};
         tot += near;
-        if ((lane & 1) == 0 && bb < nb) {
+        if (lane % GL == 0 && bb < nb) {
             const size_t o = (size_t)(b0 + bb) * ns + k;
             if (mode == 0)
                 y[o] = zd{(double)tot.x, (double)tot.y};
