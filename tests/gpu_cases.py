@@ -56,11 +56,12 @@ def oracle_dense_aim(name):
     return Z
 
 
-def gpu_problem(name, precision=0, tol=1e-13, batch=None, nt=None, restart=60, maxit=2000, flags=0, sync_every=1):
+def gpu_problem(name, precision=0, tol=1e-13, batch=None, nt=None, restart=60, maxit=2000, flags=0, sync_every=1,
+                grid=None):
     from paper_1408_7060_amd import Problem
     wl = W.WORKLOADS[name]
     p = params_of(wl)
-    kw = dict(fc=wl.f0, nt=nt or wl.nt, grid=wl.grid, d_near=p["d_near"], precision=precision,
+    kw = dict(fc=wl.f0, nt=nt or wl.nt, grid=grid or wl.grid, d_near=p["d_near"], precision=precision,
               batch=batch or wl.batch, tol=tol, restart=restart, maxit=maxit, flags=flags,
               sync_every=sync_every)
     if wl.ng:

@@ -21,6 +21,7 @@ from oracle import aim, geometry, physics as ph
 pytestmark = pytest.mark.gpu
 
 L2 = W.SPHERE_L2.name
+L3 = W.SPHERE_L3.name
 L4 = W.SPHERE_L4.name
 
 
@@ -96,6 +97,45 @@ def test_delayed_field_level4(torch, prec, tol, engine, batch):
     ref = np.array([sum(A.far_matvec(m, hist[m - 1, j]) for m in range(A.mn + 1, ng + 1)) for j in range(batch)])
     e = rel(b, ref)
     _say("L4 delayed", "fp32" if prec else "fp64", "engine", engine, "rel", e)
+    assert e <= tol
+    P.close()
+
+
+@functools.lru_cache(maxsize=None)
+def _oracle_far_grid(name, grid):
+    wl = W.WORKLOADS[name]
+    p = params_of(wl)
+    s = geometry.Surface(p["xyz"], p["tri"], p["rwg"])
+    return s, aim.AIM(s, grid, p["d_near"], p["dt"], wl.f0, p["ng"]), p
+
+
+@pytest.mark.parametrize("engine", [(2, 1), (2, 0), (1, 1)], ids=["zlines", "zlines_xlds", "reg"])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-5)], ids=["fp64", "fp32"])
+def test_register_planes_grid24(torch, prec, tol, engine):
+    """The register plane kernels at N = 24 (96-thread blocks: the matvec
+    and commit kernels' second wave holds only odd-parity tasks): the level-3
+    sphere on a 24^3 grid, far operator Z_m for m > M_n and the delayed field
+    of a history whose first M_n samples are zero (commit + delayed sum),
+    against the oracle."""
+    s, A, p = _oracle_far_grid(L3, 24)
+    ng = p["ng"]
+    assert A.mn < ng
+    P = gpu_problem(L3, precision=prec, batch=2, nt=8, grid=24)
+    assert P.info["mn"] == A.mn
+    _with_engine(P, engine)
+    x = W.complex_normal(33, (2, s.ns))
+    for m in range(A.mn + 1, ng + 1):
+        y = P.apply_z(m, _dev(torch, x)).cpu().numpy()
+        ref = np.array([A.far_matvec(m, xb) for xb in x])
+        e = rel(y, ref)
+        _say("grid24 far", "fp32" if prec else "fp64", "engine", engine, "m", m, "rel", e)
+        assert e <= tol, (m, e)
+    hist = W.complex_normal(34, (ng, 2, s.ns))
+    hist[:A.mn] = 0.0
+    b = P.delayed_field(_dev(torch, hist)).cpu().numpy()
+    ref = np.array([sum(A.far_matvec(m, hist[m - 1, j]) for m in range(A.mn + 1, ng + 1)) for j in range(2)])
+    e = rel(b, ref)
+    _say("grid24 delayed", "fp32" if prec else "fp64", "engine", engine, "rel", e)
     assert e <= tol
     P.close()
 
