@@ -254,6 +254,14 @@ int etaim_adjoint_march(etaim_ctx *ctx, const void *S, void *Lambda, etaim_stats
  * counters.  Tracing adds two event records per launch. */
 int etaim_set_profiling(etaim_ctx *ctx, int32_t on);
 
+/* Trace only the kernel classes whose bit (1 << ETAIM_K_*) is set in
+ * classes (0: off); clears the counters when any bit is set.  Single-kernel
+ * classes (ETAIM_K_YZ_GREEN, _FFT_X_INV with the register x lines,
+ * _YZ_DELAYED, _YZ_COMMIT, _RING_FAR) carry their events on the dispatch
+ * itself; the others record event markers between launches, which cost
+ * stream time.  ETAIM_EINVAL for a bit at or above ETAIM_K_COUNT. */
+int etaim_set_profiling_mask(etaim_ctx *ctx, uint32_t classes);
+
 /* Accumulated device time [ms], algorithmic bytes and launch count of one
  * kernel class since tracing was turned on (host outputs). */
 int etaim_kernel_stats(const etaim_ctx *ctx, int32_t cls, double *ms, double *bytes, int64_t *launches);

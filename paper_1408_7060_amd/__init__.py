@@ -183,8 +183,16 @@ class Problem:
         _lib.check(_lib.load().etaim_export(self._h, wid, a.ctypes.data_as(c_void_p), a.nbytes))
         return a
 
-    def set_profiling(self, on: bool = True):
-        _lib.check(_lib.load().etaim_set_profiling(self._h, 1 if on else 0))
+    def set_profiling(self, on: bool = True, classes=None):
+        """Per-class kernel tracing: all classes, or only the named ones
+        (names from KERNEL_CLASSES)."""
+        if classes is None:
+            _lib.check(_lib.load().etaim_set_profiling(self._h, 1 if on else 0))
+            return
+        mask = 0
+        for name in classes:
+            mask |= 1 << _lib.KERNEL_CLASSES.index(name)
+        _lib.check(_lib.load().etaim_set_profiling_mask(self._h, mask if on else 0))
 
     def kernel_stats(self) -> dict:
         out = {}

@@ -3,7 +3,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from ctypes import POINTER, c_char_p, c_double, c_int32, c_int64, c_size_t, c_void_p
+from ctypes import POINTER, c_char_p, c_double, c_int32, c_int64, c_size_t, c_uint32, c_void_p
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libetaim.so")
@@ -75,6 +75,7 @@ SIGNATURES = {
     "etaim_db_error": (c_int32, [c_int32, POINTER(c_double), POINTER(c_double), POINTER(c_double), c_double,
                                  POINTER(c_double)]),
     "etaim_set_profiling": (c_int32, [c_void_p, c_int32]),
+    "etaim_set_profiling_mask": (c_int32, [c_void_p, c_uint32]),
     "etaim_kernel_stats": (c_int32, [c_void_p, c_int32, POINTER(c_double), POINTER(c_double), POINTER(c_int64)]),
     "etaim_autotune": (c_int32, [c_void_p, c_int32, c_char_p, POINTER(Tuning)]),
     "etaim_get_tuning": (c_int32, [c_void_p, POINTER(Tuning)]),

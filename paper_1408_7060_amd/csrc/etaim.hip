@@ -119,6 +119,7 @@ struct etaim_ctx {
     hipEvent_t ev[8] = {};  // march phase events, two sets (steps alternate)
     // per-kernel-class tracing
     bool prof = false;
+    uint32_t prof_mask = 0;  // traced kernel classes, bit ETAIM_K_*
     double k_ms[ETAIM_K_COUNT] = {}, k_bytes[ETAIM_K_COUNT] = {};
     int64_t k_n[ETAIM_K_COUNT] = {};
     std::vector<hipEvent_t> pool;
@@ -177,7 +178,7 @@ struct Trace {
     double bytes;
     bool ext;
     Trace(etaim_ctx* c_, int cls_, double bytes_, bool ext_ = false) : c(c_), cls(cls_), bytes(bytes_), ext(ext_) {
-        if (!c->prof || c->capturing) return;
+        if (!c->prof || c->capturing || !((c->prof_mask >> cls) & 1u)) return;
         if ((size_t)(c->pool_next + 2) > c->pool.size()) {
             for (int i = 0; i < 64; ++i) {
                 hipEvent_t e;
@@ -1565,13 +1566,19 @@ int etaim_export(const etaim_ctx* c, int32_t what, void* host, size_t bytes) {
     }
 }
 
-int etaim_set_profiling(etaim_ctx* c, int32_t on) {
+int etaim_set_profiling_mask(etaim_ctx* c, uint32_t classes) {
     CHK(check_ctx(c));
+    if (classes >> ETAIM_K_COUNT) return fail(ETAIM_EINVAL, "profiling mask names an unknown kernel class");
     CHK(trace_flush(c));
-    c->prof = on != 0;
+    c->prof_mask = classes;
+    c->prof = classes != 0;
     if (c->prof)
         for (int i = 0; i < ETAIM_K_COUNT; ++i) c->k_ms[i] = c->k_bytes[i] = 0, c->k_n[i] = 0;
     return ETAIM_OK;
+}
+
+int etaim_set_profiling(etaim_ctx* c, int32_t on) {
+    return etaim_set_profiling_mask(c, on ? (1u << ETAIM_K_COUNT) - 1u : 0u);
 }
 
 int etaim_kernel_stats(const etaim_ctx* c, int32_t cls, double* ms, double* bytes, int64_t* launches) {

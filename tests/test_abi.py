@@ -70,6 +70,8 @@ def test_rejects_null_arguments():
     assert lib.etaim_state_size(None, ctypes.byref(n)) == _lib().EINVAL
     assert lib.etaim_state_save(None, None, 0) == _lib().EINVAL
     assert lib.etaim_state_load(None, None, 0) == _lib().EINVAL
+    assert lib.etaim_set_profiling(None, 1) == _lib().EINVAL
+    assert lib.etaim_set_profiling_mask(None, 1) == _lib().EINVAL
     lib.etaim_destroy(None)
 
 

@@ -250,3 +250,29 @@ def test_implicit_stop(torch, name, prec, tol, bound, adjoint):
     assert st["total_iters"] <= it0
     assert st["max_rel_residual"] <= tol
     assert rel(I1.cpu().numpy(), I0) <= bound
+
+
+def test_profiling_mask(torch):
+    """Tracing a subset of the kernel classes counts launches of those only
+    and leaves the march bit for bit as untraced; tracing every class then
+    counts the marker-timed classes too."""
+    name = W.SPHERE_L2.name
+    V = _excitation(name, 12, 2, 47)
+    P = gpu_problem(name, nt=V.shape[0], batch=V.shape[1], flags=F_CONTINUE_ON_NOCONV)
+    Vd = torch.from_numpy(np.ascontiguousarray(V)).cuda()
+    I0 = P.march(Vd)[0].cpu().numpy()
+    some = ("yz_green", "yz_delayed")
+    P.set_profiling(classes=some)
+    I1 = P.march(Vd)[0].cpu().numpy()
+    ks = P.kernel_stats()
+    P.set_profiling(True)
+    I2 = P.march(Vd)[0].cpu().numpy()
+    ks2 = P.kernel_stats()
+    P.set_profiling(False)
+    P.close()
+    _say("profiling mask", {n: v["launches"] for n, v in ks.items()}, {n: v["launches"] for n, v in ks2.items()})
+    assert all(ks[n]["launches"] > 0 and ks[n]["ms"] > 0 for n in some)
+    assert all(v["launches"] == 0 for n, v in ks.items() if n not in some)
+    assert ks2["krylov"]["launches"] > 0 and ks2["anterp_x"]["launches"] > 0
+    assert ks2["yz_green"]["launches"] == ks["yz_green"]["launches"]
+    assert np.array_equal(I1, I0) and np.array_equal(I2, I0)
