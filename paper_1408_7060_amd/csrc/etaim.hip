@@ -641,11 +641,11 @@ int arnoldi_step(etaim_ctx* c, int j, int conj, const int* gate) {
     }
     dim3 gd(j + 1, B), go((ns + 255) / 256, B);
     Trace tk(c, ETAIM_K_KRYLOV, (4.0 * (j + 1) + 8.0) * (double)nB * 16.0);
-    hipLaunchKernelGGL(k_dots, gd, dim3(256), 0, c->stream, c->Vk, c->w, c->h1, ns, B, gate);
+    hipLaunchKernelGGL(k_dots, gd, dim3(kRedThreads), 0, c->stream, c->Vk, c->w, c->h1, ns, B, gate);
     hipLaunchKernelGGL(k_orth, go, dim3(256), 0, c->stream, c->Vk, c->w, c->h1, j + 1, ns, B, gate);
-    hipLaunchKernelGGL(k_dots, gd, dim3(256), 0, c->stream, c->Vk, c->w, c->h2, ns, B, gate);
+    hipLaunchKernelGGL(k_dots, gd, dim3(kRedThreads), 0, c->stream, c->Vk, c->w, c->h2, ns, B, gate);
     hipLaunchKernelGGL(k_orth, go, dim3(256), 0, c->stream, c->Vk, c->w, c->h2, j + 1, ns, B, gate);
-    hipLaunchKernelGGL(k_norm, dim3(B), dim3(256), 0, c->stream, c->w, c->nrm, ns, gate);
+    hipLaunchKernelGGL(k_norm, dim3(B), dim3(kRedThreads), 0, c->stream, c->w, c->nrm, ns, gate);
     hipLaunchKernelGGL(k_scale, dim3(blocks_for(nB)), dim3(256), 0, c->stream, c->w, c->nrm, vn, ns, B, gate);
     hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, c->stream, c->flag, 1, 0, gate);
     hipLaunchKernelGGL(k_arnoldi_update, dim3(1), dim3(256), 0, c->stream, c->h1, c->h2, c->nrm, c->H, c->cs, c->sn,
@@ -701,14 +701,14 @@ int gmres(etaim_ctx* c, const zd* rhs, zd* x, int conj, StepResult& res) {
     const bool graph = c->use_graph && !c->prof;
     const bool gated = graph || c->sync_every > 1;
     const int chunk = gated ? std::max(c->sync_every, 1) : 1;
-    hipLaunchKernelGGL(k_norm, dim3(B), dim3(256), 0, c->stream, rhs, c->bnorm, ns, nullptr);
+    hipLaunchKernelGGL(k_norm, dim3(B), dim3(kRedThreads), 0, c->stream, rhs, c->bnorm, ns, nullptr);
     int total = 0;
     double prev_worst = 0;
     for (int cycle = 0;; ++cycle) {
         // r = rhs - A x
         CHK(Ops<R>::apply(c, 0, x, nullptr, c->w, conj));
         hipLaunchKernelGGL(k_residual, dim3(blocks_for(nB)), dim3(256), 0, c->stream, rhs, c->w, nB);
-        hipLaunchKernelGGL(k_norm, dim3(B), dim3(256), 0, c->stream, c->w, c->beta, ns, nullptr);
+        hipLaunchKernelGGL(k_norm, dim3(B), dim3(kRedThreads), 0, c->stream, c->w, c->beta, ns, nullptr);
         hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, c->stream, c->flag, 4, 0, nullptr);
         hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, c->stream, c->flag + 4, 1,
                            std::max(c->prm.maxit - total, 0), nullptr);
@@ -832,7 +832,7 @@ int march_impl(etaim_ctx* c, const zd* V, zd* I, etaim_stats* st, bool adjoint, 
     {
         double* d = nullptr;
         CHK(c->alloc(d, (size_t)nt * B));
-        hipLaunchKernelGGL(k_norm, dim3(nt * B), dim3(256), 0, c->stream, V + (size_t)first * nB, d, ns, nullptr);
+        hipLaunchKernelGGL(k_norm, dim3(nt * B), dim3(kRedThreads), 0, c->stream, V + (size_t)first * nB, d, ns, nullptr);
         HIPCHK(hipMemcpyAsync(nV.data(), d, nV.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
         c->allocs.pop_back();
@@ -911,7 +911,7 @@ int march_impl(etaim_ctx* c, const zd* V, zd* I, etaim_stats* st, bool adjoint, 
         HIPCHK(hipEventRecord(ev[2], c->stream));
         HIPCHK(hipMemcpyAsync(Il, c->xk, nB * sizeof(zd), hipMemcpyDeviceToDevice, c->stream));
         CHK(Ops<R>::commit(c, r, c->xk));
-        hipLaunchKernelGGL(k_norm, dim3(B), dim3(256), 0, c->stream, c->xk, nrm_all + (size_t)i * B, ns, nullptr);
+        hipLaunchKernelGGL(k_norm, dim3(B), dim3(kRedThreads), 0, c->stream, c->xk, nrm_all + (size_t)i * B, ns, nullptr);
         const int pmax = std::min(r, c->guess_order);
         if (pmax >= 2) {
             hipLaunchKernelGGL(k_pred_err, dim3(kPredBlocks), dim3(256), 0, c->stream, (const zd*)I, nB,

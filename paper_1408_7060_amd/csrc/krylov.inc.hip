@@ -19,22 +19,39 @@ __device__ __forceinline__ double block_sum256(double v, double* sh) {
     return r;
 }
 
+// Block of the column reductions: 1024 threads, so that the few blocks of
+// a reduction (one per column) keep enough loads in flight
+constexpr int kRedThreads = 1024;
+
+// deterministic sum over a kRedThreads block, valid in thread 0: a fixed
+// butterfly within each wave, then the wave sums in order
+__device__ __forceinline__ double block_sum_t0(double v, double* sh) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = 0;
+    if (threadIdx.x == 0)
+        for (int q = 0; q < kRedThreads / 64; ++q) r += sh[q];
+    return r;
+}
+
 // h[i][b] = <V_i[b], w[b]> = sum_k conj(V_i[b][k]) w[b][k], i < nv.  grid (nv, B)
-__global__ void __launch_bounds__(256) k_dots(const zd* __restrict__ V, const zd* __restrict__ w, zd* __restrict__ h,
-                                              int ns, int B, const int* __restrict__ gate) {
+__global__ void __launch_bounds__(kRedThreads) k_dots(const zd* __restrict__ V, const zd* __restrict__ w,
+                                                      zd* __restrict__ h, int ns, int B,
+                                                      const int* __restrict__ gate) {
     if (gated_off(gate)) return;
-    __shared__ double sh[256];
+    __shared__ double sh[2][kRedThreads / 64];
     const int i = blockIdx.x, b = blockIdx.y;
     const zd* v = V + ((size_t)i * B + b) * ns;
     const zd* x = w + (size_t)b * ns;
     double re = 0, im = 0;
-    for (int k = threadIdx.x; k < ns; k += 256) {
+    for (int k = threadIdx.x; k < ns; k += kRedThreads) {
         const zd a = v[k], c = x[k];
         re += a.x * c.x + a.y * c.y;
         im += a.x * c.y - a.y * c.x;
     }
-    re = block_sum256(re, sh);
-    im = block_sum256(im, sh);
+    re = block_sum_t0(re, sh[0]);
+    im = block_sum_t0(im, sh[1]);
     if (threadIdx.x == 0) h[(size_t)i * B + b] = zd{re, im};
 }
 
@@ -50,16 +67,16 @@ __global__ void __launch_bounds__(256) k_orth(const zd* __restrict__ V, zd* __re
     w[(size_t)b * ns + k] = acc;
 }
 
-// nrm[b] = ||w[b]||
-__global__ void __launch_bounds__(256) k_norm(const zd* __restrict__ w, double* __restrict__ nrm, int ns,
-                                              const int* __restrict__ gate = nullptr) {
+// nrm[b] = ||w[b]||  (kRedThreads per block)
+__global__ void __launch_bounds__(kRedThreads) k_norm(const zd* __restrict__ w, double* __restrict__ nrm, int ns,
+                                                      const int* __restrict__ gate = nullptr) {
     if (gated_off(gate)) return;
-    __shared__ double sh[256];
+    __shared__ double sh[kRedThreads / 64];
     const int b = blockIdx.x;
     const zd* x = w + (size_t)b * ns;
     double s = 0;
-    for (int k = threadIdx.x; k < ns; k += 256) s += x[k].x * x[k].x + x[k].y * x[k].y;
-    s = block_sum256(s, sh);
+    for (int k = threadIdx.x; k < ns; k += kRedThreads) s += x[k].x * x[k].x + x[k].y * x[k].y;
+    s = block_sum_t0(s, sh);
     if (threadIdx.x == 0) nrm[b] = sqrt(s);
 }
 
