@@ -253,3 +253,45 @@ def test_batched_march_equals_single(torch):
         I1, _ = P1.march(_dev(torch, V[:, b:b + 1]))
         assert rel(Ib[:, b], I1.cpu().numpy()[:, 0]) <= 1e-12
     P1.close()
+
+
+@pytest.mark.parametrize("prec,tol,bound", [(0, 1e-12, 1e-9), (1, 1e-5, 3e-4)], ids=["fp64", "fp32"])
+def test_adjoint_gradient_full_size(torch, prec, tol, bound):
+    """The adjoint workload's mesh and objective (level-4 sphere, one
+    incidence, 64 far-field directions).  J(V) = sum |F march(V)|^2 is
+    quadratic in V, so along a direction d the central difference
+    J(V + d) - J(V - d) equals 2 Re <grad, d> exactly (torch's gradient
+    convention, 2 dJ/d conj V); the backward march's gradient must match it.
+
+    The march runs 80 of the workload's 300 steps (the pulse peaks near step
+    66): at N_g = 24 the CPPIF march has a growing mode (about x300 per 25
+    steps, the instability of Sec. 3.1.1), which rounding seeds; past ~100
+    steps it swamps the FP32 march, and a rough d (random per unknown)
+    excites it directly.  d is therefore a second incidence's excitation,
+    as smooth as V.  Measured: 1.4e-11 (FP64, tol 1e-12) and 1.0e-4 (FP32,
+    tol 1e-5, the growing mode amplifying its rounding)."""
+    from paper_1408_7060_amd import EtaimMarch
+    wl = W.SPHERE_L4_ADJ
+    nt = 80
+    _say("adjoint gradient", wl.name, "fp32" if prec else "fp64", "steps", nt)
+    P = gpu_problem(wl.name, precision=prec, tol=tol, nt=nt, batch=1)
+    kh, pp = wl.incidence()
+    V = P.excitation(kh, pp, wl.sigma, wl.td)
+    k2 = W.unit_vectors(9, 2, 1)
+    d = P.excitation(k2, W.polarisations(9, k2), wl.sigma, wl.td)
+    dirs = W.unit_vectors(7, 3, 64)
+    Vt = V.clone().requires_grad_(True)
+    U = EtaimMarch.apply(Vt, P, dirs)
+    (U.abs() ** 2).sum().backward()
+    g = Vt.grad
+
+    def J(v):
+        I, _ = P.march(v.contiguous())
+        return float((P.farfield(dirs, I).abs() ** 2).sum())
+
+    fd = J(V + d) - J(V - d)
+    an = 2.0 * float(torch.real(torch.sum(torch.conj(g) * d)))
+    e = abs(fd - an) / abs(fd)
+    _say("  central difference", fd, "gradient", an, "rel", e)
+    P.close()
+    assert e <= bound
