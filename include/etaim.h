@@ -288,8 +288,8 @@ typedef struct {
     int32_t guess_order;     /* GMRES initial guess of step l: the polynomial through the last
                                 p solutions evaluated at step l, p <= guess_order chosen as the
                                 order that best predicted step l-1 (0: zero guess, 1: the
-                                previous solution, up to 4: cubic); the converged solution does
-                                not depend on it beyond the tolerance (default 4) */
+                                previous solution, up to 6: quintic); the converged solution
+                                does not depend on it beyond the tolerance (default 6) */
     int32_t precond;         /* right preconditioner of the per-step GMRES: 0 Jacobi diag(Z0)^-1
                                 (the paper's choice), 1 sparse approximate inverse of Z0 on the
                                 near-zone pattern (default; M^H for the adjoint) */

@@ -113,7 +113,7 @@ struct etaim_ctx {
     // launch shapes (0 = automatic); the autotuner sets them
     int gather_rows_t = 0, lines_x_t = 0, interp_waves = 4;
     int yz_engine = 0;  // 0: LDS plane kernels, 1: register quadrant kernels, 2: as 1 with z-lines-first matvec and commit
-    int guess_order = 4;  // solutions extrapolated into a step's initial guess (0..4)
+    int guess_order = kMaxGuess;  // solutions extrapolated into a step's initial guess (0..kMaxGuess)
     int x_engine = 0;   // 0: LDS line kernels, 1: register line kernels
     void* xs = nullptr; // [ns][B] scaled columns for the register anterpolation
     hipEvent_t ev[8] = {};  // march phase events, two sets (steps alternate)
@@ -915,8 +915,8 @@ int march_impl(etaim_ctx* c, const zd* V, zd* I, etaim_stats* st, bool adjoint, 
         const int pmax = std::min(r, c->guess_order);
         if (pmax >= 2) {
             hipLaunchKernelGGL(k_pred_err, dim3(kPredBlocks), dim3(256), 0, c->stream, (const zd*)I, nB,
-                               (long long)l, adjoint ? -1 : 1, pmax, c->perr + 4);
-            hipLaunchKernelGGL(k_pred_err_sum, dim3(1), dim3(256), 0, c->stream, (const double*)(c->perr + 4),
+                               (long long)l, adjoint ? -1 : 1, pmax, c->perr + kMaxGuess);
+            hipLaunchKernelGGL(k_pred_err_sum, dim3(1), dim3(256), 0, c->stream, (const double*)(c->perr + kMaxGuess),
                                kPredBlocks, c->perr, pmax, c->pnext);
             guess_dev = true;
         } else {
@@ -1262,7 +1262,7 @@ int device_setup(etaim_ctx* c) {
     CHK(c->alloc(c->active, c->B));
     CHK(c->alloc(c->jcnt, c->B));
     CHK(c->alloc(c->flag, 8));
-    CHK(c->alloc(c->perr, 4 + 4 * kPredBlocks));
+    CHK(c->alloc(c->perr, kMaxGuess + kMaxGuess * kPredBlocks));
     HIPCHK(hipHostMalloc((void**)&c->flag_h, 8 * sizeof(int), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&c->res_h, 2 * (size_t)c->B * sizeof(double), hipHostMallocDefault));
     CHK(c->alloc(c->pnext, 1));

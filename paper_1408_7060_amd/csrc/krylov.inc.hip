@@ -319,6 +319,13 @@ __global__ void k_copy_conj(const zd* __restrict__ in, zd* __restrict__ out, siz
     }
 }
 
+// Extrapolation orders: the polynomial through the last p solutions at the
+// next step, x = sum_i (-1)^(i+1) C(p, i) x_{-i}, p = 1 .. kMaxGuess
+constexpr int kMaxGuess = 6;
+__constant__ double kExtrap[kMaxGuess][kMaxGuess] = {{1, 0, 0, 0, 0, 0},       {2, -1, 0, 0, 0, 0},
+                                                      {3, -3, 1, 0, 0, 0},      {4, -6, 4, -1, 0, 0},
+                                                      {5, -10, 10, -5, 1, 0},   {6, -15, 20, -15, 6, -1}};
+
 // Initial guess of a time step: x = sum_{i=1}^{p} a_i I_{l - dir i}, the
 // polynomial through the last p solutions evaluated one step ahead
 // (a_i = (-1)^(i+1) C(p, i)); p = 0 gives zero.  The march picks p as the
@@ -327,7 +334,7 @@ __global__ void k_extrap(const zd* __restrict__ I, zd* __restrict__ x, size_t nB
                          const int* __restrict__ pdev) {
     // p caps the order (history available); pdev, when given, holds the order chosen on the device
     if (pdev) p = min(p, *pdev);
-    const double a[4][4] = {{1, 0, 0, 0}, {2, -1, 0, 0}, {3, -3, 1, 0}, {4, -6, 4, -1}};
+    const auto& a = kExtrap;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < nB; e += (size_t)gridDim.x * blockDim.x) {
         zd acc{0, 0};
         for (int i = 1; i <= p; ++i) {
@@ -347,11 +354,11 @@ constexpr int kPredBlocks = 256;
 __global__ void __launch_bounds__(256) k_pred_err(const zd* __restrict__ I, size_t nB, long long l, int dir,
                                                   int pmax, double* __restrict__ part) {
     __shared__ double sh[256];
-    const double a[4][4] = {{1, 0, 0, 0}, {2, -1, 0, 0}, {3, -3, 1, 0}, {4, -6, 4, -1}};
-    double s[4] = {0, 0, 0, 0};
+    const auto& a = kExtrap;
+    double s[kMaxGuess] = {0, 0, 0, 0, 0, 0};
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < nB; e += (size_t)gridDim.x * blockDim.x) {
         const zd x = I[(size_t)l * nB + e];
-        zd v[4];
+        zd v[kMaxGuess];
         for (int i = 1; i <= pmax; ++i) v[i - 1] = I[(size_t)(l - (long long)dir * i) * nB + e];
         for (int p = 1; p <= pmax; ++p) {
             double rx = x.x, ry = x.y;
@@ -362,19 +369,19 @@ __global__ void __launch_bounds__(256) k_pred_err(const zd* __restrict__ I, size
             s[p - 1] += rx * rx + ry * ry;
         }
     }
-    for (int p = 0; p < 4; ++p) {
+    for (int p = 0; p < kMaxGuess; ++p) {
         const double t = block_sum256(s[p], sh);
-        if (threadIdx.x == 0) part[(size_t)blockIdx.x * 4 + p] = t;
+        if (threadIdx.x == 0) part[(size_t)blockIdx.x * kMaxGuess + p] = t;
     }
 }
 
 __global__ void __launch_bounds__(256) k_pred_err_sum(const double* __restrict__ part, int nblk,
                                                       double* __restrict__ err, int pmax, int* __restrict__ pbest) {
     __shared__ double sh[256];
-    double e[4];
-    for (int p = 0; p < 4; ++p) {
+    double e[kMaxGuess];
+    for (int p = 0; p < kMaxGuess; ++p) {
         double s = 0;
-        for (int b = threadIdx.x; b < nblk; b += 256) s += part[(size_t)b * 4 + p];
+        for (int b = threadIdx.x; b < nblk; b += 256) s += part[(size_t)b * kMaxGuess + p];
         e[p] = block_sum256(s, sh);
         if (threadIdx.x == 0) err[p] = e[p];
     }

@@ -39,7 +39,7 @@ bool radix_equal(const Radix& a, const Radix& b) {
 
 struct Shape {
     Radix rx, ry, rz;
-    int mr = 0, mt = 0, waves = 4, sync = 1, graph = 0, engine = 0, xeng = 0, guess = 4, precond = 1, dblock = 6;
+    int mr = 0, mt = 0, waves = 4, sync = 1, graph = 0, engine = 0, xeng = 0, guess = kMaxGuess, precond = 1, dblock = 6;
 };
 
 template <typename R>
@@ -69,7 +69,7 @@ bool shape_fits(const etaim_ctx* c, const Shape& s) {
            plane_fits(mt, s.rx) && (4 * (size_t)mr * (Lx + 1) + Lx) * e <= 160 * 1024 &&
            ((size_t)mt * (Lx + 1) + Lx) * e <= (size_t)kLdsBudget && s.waves >= 1 && s.waves <= 4 &&
            s.sync >= 1 && s.sync <= c->prm.restart && (s.engine == 0 || ((s.engine == 1 || s.engine == 2) && quad_n(c) > 0)) &&
-           (s.xeng == 0 || (s.xeng == 1 && xline_n(c) > 0)) && s.guess >= 0 && s.guess <= 4 &&
+           (s.xeng == 0 || (s.xeng == 1 && xline_n(c) > 0)) && s.guess >= 0 && s.guess <= kMaxGuess &&
            (s.precond == 0 || s.precond == 1) && s.dblock >= 1 && s.dblock <= kFarMaxBlock;
 }
 
