@@ -914,7 +914,7 @@ int march_impl(etaim_ctx* c, const zd* V, zd* I, etaim_stats* st, bool adjoint, 
         hipLaunchKernelGGL(k_norm, dim3(B), dim3(kRedThreads), 0, c->stream, c->xk, nrm_all + (size_t)i * B, ns, nullptr);
         const int pmax = std::min(r, c->guess_order);
         if (pmax >= 2) {
-            hipLaunchKernelGGL(k_pred_err, dim3(kPredBlocks), dim3(256), 0, c->stream, (const zd*)I, nB,
+            hipLaunchKernelGGL(k_pred_err, dim3(kPredBlocks), dim3(kRedThreads), 0, c->stream, (const zd*)I, nB,
                                (long long)l, adjoint ? -1 : 1, pmax, c->perr + kMaxGuess);
             hipLaunchKernelGGL(k_pred_err_sum, dim3(1), dim3(256), 0, c->stream, (const double*)(c->perr + kMaxGuess),
                                kPredBlocks, c->perr, pmax, c->pnext);

@@ -351,9 +351,9 @@ __global__ void k_extrap(const zd* __restrict__ I, zd* __restrict__ x, size_t nB
 // part[blk][p-1] (grid-stride), then k_pred_err_sum adds the blocks in
 // order (deterministic).
 constexpr int kPredBlocks = 256;
-__global__ void __launch_bounds__(256) k_pred_err(const zd* __restrict__ I, size_t nB, long long l, int dir,
-                                                  int pmax, double* __restrict__ part) {
-    __shared__ double sh[256];
+__global__ void __launch_bounds__(kRedThreads) k_pred_err(const zd* __restrict__ I, size_t nB, long long l, int dir,
+                                                          int pmax, double* __restrict__ part) {
+    __shared__ double sh[kMaxGuess][kRedThreads / 64];
     const auto& a = kExtrap;
     double s[kMaxGuess] = {0, 0, 0, 0, 0, 0};
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < nB; e += (size_t)gridDim.x * blockDim.x) {
@@ -370,7 +370,7 @@ __global__ void __launch_bounds__(256) k_pred_err(const zd* __restrict__ I, size
         }
     }
     for (int p = 0; p < kMaxGuess; ++p) {
-        const double t = block_sum256(s[p], sh);
+        const double t = block_sum_t0(s[p], sh[p]);
         if (threadIdx.x == 0) part[(size_t)blockIdx.x * kMaxGuess + p] = t;
     }
 }
