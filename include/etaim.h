@@ -153,8 +153,10 @@ int etaim_describe(const etaim_ctx *ctx, etaim_derived *out);
 int etaim_excitation_planewave(etaim_ctx *ctx, int32_t nb, const double *khat,
                                const double *phat, double sigma, double td, void *V);
 
-/* Forward march of eq. (5) (Sec. 4 stage (v), GMRES with diagonal
- * preconditioning, Sec. 5.1): for l = 1..n solve
+/* Forward march of eq. (5) (Sec. 4 stage (v); GMRES as in Sec. 5.1, right-
+ * preconditioned by default with a sparse approximate inverse of Z0 on the
+ * near-zone pattern, or with the paper's diagonal (Jacobi) preconditioner
+ * when etaim_tuning.precond = 0): for l = 1..n solve
  *   (Z0near + Z0fft) I_l = V_l - sum_{m=1}^{N_g} (Zmnear + Zmfft) I_{l-m},
  * starting from a zero history, n = nsteps (1..N_t; 0 means N_t).
  * V, I_out: device complex128 [N_t][B][ns] (the first n steps are used).
@@ -168,7 +170,8 @@ int etaim_march(etaim_ctx *ctx, const void *V, void *I_out, int32_t nsteps, etai
  * etaim_state_load set them, at step `first` (ETAIM_EINVAL otherwise).
  * V and I_out are the full device arrays [N_t][B][ns]; I_out must hold the
  * solutions of the steps before `first` (the initial guess extrapolates the
- * last four).  The result equals that of one uninterrupted march; stats
+ * last guess_order solutions, at most 6: etaim_tuning.guess_order).  The
+ * result equals that of one uninterrupted march; stats
  * cover this call's steps (iters_per_step[0] is step `first`). */
 int etaim_march_continue(etaim_ctx *ctx, const void *V, void *I_out, int32_t first, int32_t nsteps,
                          etaim_stats *stats);
@@ -233,7 +236,10 @@ int etaim_db_error(int32_t n, const double *sigma, const double *sigma_ref, cons
  * conjugate near-zone values (the operators are complex-symmetric):
  *   Z0^H lambda_l = S_l - sum_{m=1}^{N_g} Zm^H lambda_{l+m}, l = N_t..1.
  * S, Lambda: device complex128 [N_t][B][ns].  For J = |F I|^2 and
- * S = F^H F I, dJ/d conj(V) = Lambda. */
+ * S = F^H F I, dJ/d conj(V) = Lambda.  The call takes no checkpoint
+ * interval: eq. (5) is linear in I, so the adjoint needs only S (which the
+ * caller forms from the forward currents it holds), never the forward
+ * history rings, and there is no forward state to recompute. */
 int etaim_adjoint_march(etaim_ctx *ctx, const void *S, void *Lambda, etaim_stats *stats);
 
 /* Kernel classes traced by etaim_set_profiling (HIP events recorded on the

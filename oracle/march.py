@@ -5,21 +5,11 @@
   solved with one LU factorisation of Z_0 (used both for the direct ET-MOT
   matrices and for the assembled ET-AIM matrices Z^near_m + Z^FFT_m of
   eq. (5)).
-* ``delayed_dense``: the right-hand-side sum of eq. (4)/(5) for an injected
-  history.
 """
 from __future__ import annotations
 
 import numpy as np
 import scipy.linalg as sla
-
-
-def delayed_dense(Z: np.ndarray, hist: np.ndarray) -> np.ndarray:
-    """b = sum_{m=1}^{N_g} Z_m hist[m-1]; hist[m-1] = I_{l-m}, [N_g, B, ns]."""
-    b = np.zeros(hist.shape[1:], dtype=np.complex128)
-    for m in range(1, min(len(Z), len(hist) + 1)):
-        b += hist[m - 1] @ Z[m].T
-    return b
 
 
 def march_dense(Z: np.ndarray, V: np.ndarray) -> np.ndarray:

@@ -1491,14 +1491,21 @@ int etaim_state_load(etaim_ctx* c, const void* host, size_t bytes) {
         h.Np != (int64_t)c->Np || h.ring_bytes != (int64_t)rb || h.hist_bytes != (int64_t)hb)
         return fail(ETAIM_EINVAL, "the state belongs to a different problem (precision, batch, mesh or grid)");
     if (h.next_step < 1 || h.next_step > c->prm.nt_steps) return fail(ETAIM_EINVAL, "corrupt state: step");
+    // extrapolation orders index the 6 x 6 coefficient table of the initial guess
+    if (h.guess_p < 0 || h.guess_p > kMaxGuess || h.pnext < 1 || h.pnext > kMaxGuess || h.guess_dev < 0 ||
+        h.guess_dev > 1)
+        return fail(ETAIM_EINVAL, "corrupt state: initial-guess order");
     const unsigned char* p = (const unsigned char*)host;
     HIPCHK(hipStreamSynchronize(c->stream));
     HIPCHK(hipMemcpy(c->ring, p + sizeof h, rb, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->hist, p + sizeof h + rb, hb, hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(c->pnext, &h.pnext, sizeof(int), hipMemcpyHostToDevice));
+    // the loading context's cap on the extrapolation order applies from the first step on
+    const int pcap = std::max(c->guess_order, 1);
+    const int pnext = std::min(h.pnext, pcap);
+    HIPCHK(hipMemcpy(c->pnext, &pnext, sizeof(int), hipMemcpyHostToDevice));
     c->next_step = h.next_step;
-    c->guess_p_next = h.guess_p;
-    c->guess_dev_next = h.guess_dev != 0;
+    c->guess_p_next = std::min(h.guess_p, c->guess_order);
+    c->guess_dev_next = h.guess_dev != 0 && c->guess_order >= 2;
     c->far_r0 = -1;  // block sums are recomputed from the loaded ring
     c->iter_hint = 0;
     return ETAIM_OK;

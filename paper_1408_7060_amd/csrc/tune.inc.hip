@@ -90,12 +90,16 @@ void put_shape(etaim_ctx* c, const Shape& s) {
     c->interp_waves = s.waves;
     c->sync_every = s.sync;
     c->use_graph = s.graph != 0;
+    // the LDS and register engines lay the spectrum ring out differently: a
+    // change between them invalidates the history (and its block sums)
+    if ((c->yz_engine == 0) != (s.engine == 0)) {
+        c->next_step = -1;
+        c->far_r0 = -1;
+    }
     c->yz_engine = s.engine;
     c->x_engine = s.xeng;
     c->guess_order = s.guess;
     c->precond = s.precond;
-    // the LDS and register engines lay the spectrum ring out differently
-    if ((c->yz_engine == 0) != (s.engine == 0)) c->next_step = -1;
     if (c->delay_block != s.dblock) c->far_r0 = -1;
     c->delay_block = s.dblock;
     drop_graphs(c);  // captured steps hold the old launch shapes

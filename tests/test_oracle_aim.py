@@ -138,3 +138,23 @@ def test_aim_far_accuracy_on_separated_pairs():
     Zf = A.far_dense(0)
     err = np.linalg.norm((Zf - Z[0])[sep]) / np.linalg.norm(Z[0][sep])
     assert err < 0.05
+
+
+@pytest.mark.parametrize("level,radius,lam_frac,fc", [(2, 0.5, 0.3, 300e6), (3, 1.0, 0.3, 300e6)])
+def test_near_pairs_equal_brute_force_distance_scan(level, radius, lam_frac, fc):
+    """The near-zone pattern (stage (iv)): every ordered pair (k, k') with
+    |c_k - c_k'| <= d_near, the basis itself included, by the full O(N_s^2)
+    distance matrix of the basis centres (no spatial tree), row-major."""
+    xyz, tri = W.icosphere(level, radius)
+    s = sphere(level, radius)
+    d_near = lam_frac * ph.C0 / fc
+    rows, cols = aim.near_pairs(s, d_near)
+    c = s.c
+    D = np.sqrt(((c[:, None, :] - c[None, :, :]) ** 2).sum(axis=-1))
+    br, bc = np.nonzero(D <= d_near)          # row-major order, columns ascending
+    assert np.array_equal(rows, br) and np.array_equal(cols, bc)
+    assert np.all(D[rows, rows] == 0) and len(rows) == int((D <= d_near).sum())
+    # the test is inclusive: a radius equal to one pair's distance keeps that pair
+    k, k2 = 0, int(np.argsort(D[0])[5])
+    r2, c2 = aim.near_pairs(s, float(np.linalg.norm(c[k] - c[k2])))
+    assert np.any((r2 == k) & (c2 == k2)) and np.any((r2 == k2) & (c2 == k))

@@ -73,3 +73,23 @@ def test_envelope_rcs_matches_fd_rcs_in_band():
         sf = mie.rcs_theta_current(s, np.linalg.solve(Z[ng + 1 + i], Vf), f, d, th)
         assert np.abs(se - sf).max() / sf.max() < tol, df
         assert mie.db_error(se, sf, TH) < 1e-5
+
+
+def test_db_error_hand_computed():
+    """Eq. (2) on four directions whose RCS values are whole decibels, worked
+    by hand: the reference peaks at 20 dB, so TH = 20 - 80 = -60 dB; both
+    patterns are clipped at TH and shifted by -TH (reference 80, 70, 0, 30;
+    test 77, 70, 20, 0), and the (theta, phi) quadrature weight is sin(theta)."""
+    theta = np.array([math.pi / 6, math.pi / 2, math.pi / 3, math.pi / 4])
+    ref_db = np.array([20.0, 10.0, -70.0, -30.0])
+    sig_db = np.array([17.0, 10.0, -40.0, -65.0])
+    w = [0.5, 1.0, math.sqrt(3) / 2, math.sqrt(2) / 2]
+    num = w[0] * 3 ** 2 + w[1] * 0 + w[2] * 20 ** 2 + w[3] * 30 ** 2
+    den = w[0] * 80 ** 2 + w[1] * 70 ** 2 + w[2] * 0 ** 2 + w[3] * 30 ** 2
+    e = mie.db_error(10.0 ** (sig_db / 10), 10.0 ** (ref_db / 10), theta)
+    assert e == pytest.approx(num / den, rel=1e-12)
+    # the floor is relative to the reference's peak, not to 0 dB: with a
+    # 50 dB floor TH = -30 dB, so the last two directions of both patterns
+    # clip to 0 (reference 50, 40, 0, 0; test 47, 40, 0, 0)
+    e50 = mie.db_error(10.0 ** (sig_db / 10), 10.0 ** (ref_db / 10), theta, floor_db=50.0)
+    assert e50 == pytest.approx(w[0] * 3 ** 2 / (w[0] * 50 ** 2 + w[1] * 40 ** 2), rel=1e-12)

@@ -5,7 +5,8 @@ import math
 import numpy as np
 import pytest
 
-from oracle import excitation, march, physics as ph
+import workloads as W
+from oracle import excitation, geometry, kernels, march, physics as ph, zfill
 from oracle_cases import dense_z, l2_band_params, sphere
 
 FC = 300e6
@@ -79,3 +80,40 @@ def test_broadband_cppif_march_is_unstable_narrowband_stable():
         out[frac] = nrm[-1] / nrm.max()
     assert out[0.01] < 1e-6
     assert out[0.2] > 0.5
+
+
+def test_refined_touching_rule_is_the_7x7_rule_at_n1():
+    """The refined reference rule for touching pairs (both triangles split
+    into n^2 sub-triangles, extraction per sub-pair) is the 7 x 7 rule with
+    extraction itself at n = 1: on a self pair, where all four half pairs
+    touch, it reproduces the impedance entries to rounding."""
+    from oracle import touching
+    s = sphere()
+    dt, ng = l2_band_params()
+    ks = [kernels.EnvelopeKernel(m, dt, 300e6) for m in range(ng + 1)]
+    for k in (0, 211):
+        z = zfill.assemble_pairs(s, [k], [k], ks)[:, 0]
+        assert np.abs(touching.refined_pair_entries(s, k, k, ks, 1) - z).max() <= 1e-13 * np.abs(z).max()
+
+
+def test_touching_pair_spans_against_c_dt():
+    """Reading of the touching-pair quadrature: the extraction assumes f(R)
+    smooth over the pair, i.e. tau = m - R/(c dt) on one CPPIF piece, which
+    holds when the pair spans less than c dt.  On the level-2 sphere (dt from
+    beta = 1/5, c dt = 1 m) every touching pair does; on the level-4 sphere
+    with N_g = 24 (c dt = 9.3 cm) every touching pair spans more, so the
+    library and the oracle apply the same 7 x 7 remainder rule across a
+    CPPIF breakpoint there rather than reject the configuration."""
+    from oracle import aim, touching
+    from gpu_cases import params_of
+    for wl, inside in ((W.SPHERE_L2, True), (W.SPHERE_L4, False)):
+        p = params_of(wl)
+        s = geometry.Surface(p["xyz"], p["tri"], p["rwg"])
+        rows, cols = aim.near_pairs(s, p["d_near"])
+        span = touching.touching_spans(s, rows, cols)
+        t = span > 0
+        assert t.sum() > len(rows) // 2
+        if inside:
+            assert span[t].max() < touching.cdt(p["dt"])
+        else:
+            assert span[t].min() > touching.cdt(p["dt"])
