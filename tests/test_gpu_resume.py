@@ -99,3 +99,47 @@ def test_state_of_another_problem_is_refused(torch):
     assert ei.value.code == -1
     Q.close()
     R.close()
+
+
+def test_engine_switch_invalidates_the_history(torch):
+    """The LDS and register y/z engines lay the spectrum ring out
+    differently: after a switch between them the history of the last march
+    is not resumable (continue and save are refused), while a switch of the
+    x stage only (same ring layout) keeps it."""
+    nt = 10
+    V = _excitation(nt, 1, 53)
+    Vd = torch.from_numpy(np.ascontiguousarray(V)).cuda()
+    P = gpu_problem(L2, precision=0, nt=nt, batch=1, flags=F_CONTINUE_ON_NOCONV)
+    t0 = P.tuning()
+    assert t0["yz_engine"] != 0
+    I, _ = P.march(Vd, nsteps=4)
+    P.set_tuning(dict(t0, x_engine=1 - t0["x_engine"]))      # same ring layout
+    I, _ = P.march_continue(Vd, I, 4, 2)
+    P.set_tuning(dict(t0, yz_engine=0))
+    for call in (lambda: P.march_continue(Vd, I, 6, 2), P.save_state):
+        with pytest.raises(Exception) as ei:
+            call()
+        assert ei.value.code == -1
+    P.close()
+
+
+def test_state_with_a_corrupt_guess_order_is_refused(torch):
+    """The carried initial-guess orders index a 6 x 6 coefficient table; a
+    state whose orders lie outside 1..6 is refused before it is loaded."""
+    V = _excitation(8, 1, 54)
+    Vd = torch.from_numpy(np.ascontiguousarray(V)).cuda()
+    P = gpu_problem(L2, precision=0, nt=8, batch=1, flags=F_CONTINUE_ON_NOCONV)
+    P.march(Vd, nsteps=5)
+    state = P.save_state()
+    # magic (8 bytes = int32 slots 0, 1), then version, prec, B, ns, ng, mn,
+    # next_step, guess_p (slot 9), guess_dev, pnext (slot 11)
+    hdr = state[:48].view(np.int32)
+    for field, value in ((9, 7), (9, -1), (11, 0), (11, 7)):
+        bad = state.copy()
+        bad[:48].view(np.int32)[field] = value
+        assert hdr[field] != value
+        with pytest.raises(Exception) as ei:
+            P.load_state(bad)
+        assert ei.value.code == -1
+    P.load_state(state)
+    P.close()
