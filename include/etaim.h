@@ -153,6 +153,19 @@ int etaim_describe(const etaim_ctx *ctx, etaim_derived *out);
 int etaim_excitation_planewave(etaim_ctx *ctx, int32_t nb, const double *khat,
                                const double *phat, double sigma, double td, void *V);
 
+/* etaim_excitation_planewave for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same vectors, computed by the same kernel, with the
+ * directions and polarisations staged in a fixed per-device array instead
+ * of a per-call allocation.  The call allocates and frees nothing.  Limit:
+ * nb <= 4096 (ETAIM_EINVAL beyond, with a message naming the limit).  The
+ * array (48 KiB per device, held until the process ends) is shared by every
+ * call on a device and keeps the last call's contents: calls that overlap
+ * on one device, from different host threads or streams, race.  The call
+ * synchronises the context's stream before it returns. */
+int etaim_excitation_planewave_noalloc(etaim_ctx *ctx, int32_t nb, const double *khat,
+                                       const double *phat, double sigma, double td, void *V);
+
 /* Forward march of eq. (5) (Sec. 4 stage (v); GMRES as in Sec. 5.1, right-
  * preconditioned by default with a sparse approximate inverse of Z0 on the
  * near-zone pattern, or with the paper's diagonal (Jacobi) preconditioner

@@ -82,13 +82,16 @@ class Problem:
             out[f] = list(v) if hasattr(v, "__len__") else v
         return out
 
-    def excitation(self, khat, phat, sigma: float, td: float):
+    def excitation(self, khat, phat, sigma: float, td: float, out=None, noalloc: bool = False):
+        """Excitation vectors V [N_t][B][ns] of the plane wave of eq. (1);
+        noalloc selects etaim_excitation_planewave_noalloc (no device
+        allocation inside the library; out may then be a preallocated V)."""
         kh = np.ascontiguousarray(np.atleast_2d(khat), dtype=np.float64)
         ph = np.ascontiguousarray(np.atleast_2d(phat), dtype=np.float64)
-        V = self.empty(self.nt, len(kh), self.ns)
-        _lib.check(_lib.load().etaim_excitation_planewave(
-            self._h, len(kh), kh.ctypes.data_as(POINTER(c_double)), ph.ctypes.data_as(POINTER(c_double)),
-            sigma, td, c_void_p(_dptr(V))))
+        V = out if out is not None else self.empty(self.nt, len(kh), self.ns)
+        fn = _lib.load().etaim_excitation_planewave_noalloc if noalloc else _lib.load().etaim_excitation_planewave
+        _lib.check(fn(self._h, len(kh), kh.ctypes.data_as(POINTER(c_double)), ph.ctypes.data_as(POINTER(c_double)),
+                      sigma, td, c_void_p(_dptr(V))))
         return V
 
     def march(self, V, out=None, nsteps: int = 0):

@@ -59,6 +59,8 @@ SIGNATURES = {
     "etaim_describe": (c_int32, [c_void_p, POINTER(Derived)]),
     "etaim_excitation_planewave": (c_int32, [c_void_p, c_int32, POINTER(c_double), POINTER(c_double), c_double,
                                              c_double, c_void_p]),
+    "etaim_excitation_planewave_noalloc": (c_int32, [c_void_p, c_int32, POINTER(c_double), POINTER(c_double),
+                                                     c_double, c_double, c_void_p]),
     "etaim_march": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, POINTER(Stats)]),
     "etaim_apply_z": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
     "etaim_delayed_field": (c_int32, [c_void_p, c_void_p, c_void_p]),

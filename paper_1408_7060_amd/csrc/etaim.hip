@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1280,6 +1281,39 @@ int check_ctx(const etaim_ctx* c) {
 
 }  // namespace
 
+// Staging of the no-allocation excitation entry point: the incidence
+// directions and polarisations [2][nb][3] of one call.  Each device holds
+// its own copy for the life of the process; every call on a device shares
+// it.  Host code never uses the array's name as an address (on the host it
+// is a stand-in symbol): the device address comes from hipGetSymbolAddress,
+// once per device, at context creation.
+constexpr int kNoallocMaxDirs = 4096;
+static __device__ __align__(256) double scratch[6 * kNoallocMaxDirs];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// device address of `scratch` on device dev, which must be current
+int scratch_init(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(ETAIM_EUNSUPPORTED, "device ordinal beyond 63");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return ETAIM_OK;
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(ETAIM_EHIP, "hipGetSymbolAddress returned no address for the staging array");
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+    return ETAIM_OK;
+}
+
+double* scratch_of(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[dev];
+}
+}  // namespace
+
 // ===========================================================================
 extern "C" {
 
@@ -1323,6 +1357,8 @@ int etaim_create(etaim_ctx** out, const etaim_mesh* mesh, const etaim_rwg* rwg, 
     c->gfold = (size_t)(c->gd.N[0] + 1) * (c->gd.N[1] + 1) * (c->gd.N[2] + 1);
     exact_near_entries(c->geo, params, c->st);
     if (hipGetDevice(&c->device) != hipSuccess) return fail(ETAIM_EHIP, "no HIP device");
+    rc = scratch_init(c->device);
+    if (rc) return rc;
     if (hipDeviceGetAttribute(&c->ncu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess || c->ncu < 1)
         c->ncu = 256;
     c->stream = (hipStream_t)hip_stream;
@@ -1372,6 +1408,28 @@ int etaim_excitation_planewave(etaim_ctx* c, int32_t nb, const double* khat, con
     c->allocs.pop_back();
     c->dev_bytes -= (int64_t)(kp.size() * sizeof(double));
     HIPCHK(hipFree(d));
+    return ETAIM_OK;
+}
+
+int etaim_excitation_planewave_noalloc(etaim_ctx* c, int32_t nb, const double* khat, const double* phat,
+                                       double sigma, double td, void* V) {
+    CHK(check_ctx(c));
+    if (nb > kNoallocMaxDirs)
+        return fail(ETAIM_EINVAL, "no-allocation excitation: nb = " + std::to_string(nb) + " exceeds its limit of " +
+                                      std::to_string(kNoallocMaxDirs) + " directions");
+    if (nb != c->B || !khat || !phat || !V || !(sigma > 0))
+        return fail(ETAIM_EINVAL, "excitation needs nb == batch, khat, phat, V and sigma > 0");
+    double* d = scratch_of(c->device);
+    if (!d) return fail(ETAIM_EHIP, "the staging array of this device has no address");
+    HIPCHK(hipMemcpyAsync(d, khat, 3 * (size_t)nb * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(d + 3 * (size_t)nb, phat, 3 * (size_t)nb * sizeof(double), hipMemcpyHostToDevice,
+                          c->stream));
+    const size_t tot = (size_t)c->prm.nt_steps * nb * c->ns;
+    hipLaunchKernelGGL(k_excitation, dim3(blocks_for(tot)), dim3(256), 0, c->stream, (zd*)V, c->Sq, c->rq, d,
+                       d + 3 * (size_t)nb, c->prm.nt_steps, nb, c->ns, c->st.dt, sigma, td, 2.0 * kPi * c->prm.fc);
+    HIPCHK(hipGetLastError());
+    // the staging is free for the next call (and the caller's host arrays) once this returns
+    HIPCHK(hipStreamSynchronize(c->stream));
     return ETAIM_OK;
 }
 
