@@ -11,19 +11,24 @@ shapes and GMRES schedule for this problem (--tune-ms budget, untimed).
 A "step" is one time step of the batched march: delayed field (k-space
 temporal sum over the history + inverse FFT + interpolation + near history),
 the GMRES solve (one AIM matvec per iteration) and the commit (anterpolation
-+ forward FFT into the history ring).  --warmup W marches W untimed steps
-first; the timed region is one march of --steps K steps from a zero history,
-bracketed by torch.cuda.synchronize().  Inputs (excitation) are resident in
-HBM before timing.
++ forward FFT into the history ring).  The timed window is K = --steps steps
+of the march, steps first .. first + K - 1, reached by marching the steps
+before it untimed (at least --warmup of them): by default the window is
+centred on the peak of the pulse (t_d / dt) and starts no earlier than
+N_g + 8, so that every timed step sums all N_g history terms.  The timed
+region is one etaim_march_continue call bracketed by
+torch.cuda.synchronize(); it holds no ring reset.  Inputs (excitation) are
+resident in HBM before timing.  The 40 (or K) steps just before the window
+are marched with every kernel class traced, untimed, for the per-class
+table; inside the timed region only the roofline kernel and the
+delayed-field kernels are traced (their events ride on the dispatch).
 
 Printed: one JSON line with the metric, the roofline record of the dominant
-kernel class (algorithmic bytes / device time, HIP events on the library's
-stream over the timed region), the plain FP64 GPU path on the first
-direction for comparison, the FP32-vs-FP64 error on that direction, and the
-CPU oracle baseline on a bounded sample.  Inside the timed region only the
-roofline kernel and the delayed-field kernels are traced (their events ride
-on the dispatch); the per-class table ("kernels") comes from a second,
-untimed march of K steps with every class traced.
+kernel class (algorithmic bytes or flops / device time, HIP events on the
+library's stream over the timed region), the plain FP64 GPU path on the
+first direction over the same window, the FP32-vs-FP64 error there, and the
+CPU oracle baseline (the oracle's FFT march on the host cores, run as a
+child process).
 """
 from __future__ import annotations
 
@@ -40,9 +45,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# FP32 vector FMA issue rate without packed FP32 instructions (the build
-# disables them): 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz
-ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# published FP32 vector peak of the MI355X: 256 CUs x 4 SIMDs x 16 lanes x
+# 2 flops (FMA) x 2 (packed FP32) x 2.4 GHz = 157.3 TFLOP/s
+ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2 * 2.4e9 / 1e12
+# the rate without packed FP32 instructions, which the build disables: the
+# issue ceiling of this code, reported beside the fraction of the peak
+ALU_ISSUE_TFLOPS = ALU_PEAK_TFLOPS / 2
 CSRC = os.path.join(ROOT, "paper_1408_7060_amd", "csrc")
 FFT_CLASSES = ("anterp_x", "yz_green", "fft_x_inv", "interp_near", "yz_delayed", "yz_commit", "ring_far")
 # traced inside the timed region: the roofline kernel and the delayed-field
@@ -68,35 +76,17 @@ def make_problem(wl, precision, batch, nt, tol, flags=1, sync_every=1):
     return Problem(xyz, tri, rwg, **kw)
 
 
-def cpu_baseline(wl, iters_per_step, budget_s=20.0):
-    """Oracle (numpy FP64, as it stands) on a bounded sample: time the
-    oracle's AIM operator application (FFT convolution + near SpMV) at the
-    workload's size for one direction, then price one oracle time step as
-    (N_g delayed-field applications + average GMRES iterations + 1)."""
-    from oracle import aim, geometry, physics as ph
-    xyz, tri, rwg = wl.mesh()
-    s = geometry.Surface(xyz, tri, rwg)
-    rmax = ph.rmax_of(xyz)
-    dt = ph.dt_from_ng(rmax, wl.ng) if wl.ng else ph.dt_from_beta(wl.beta, wl.f_bw)
-    ng = wl.ng or ph.ng_from(rmax, dt)
-    A = aim.AIM(s, wl.grid, wl.near_lambda * ph.C0 / wl.f0, dt, wl.f0, ng)
-    vals = np.zeros(len(A.rows), dtype=np.complex128)    # timing only: cost is value-independent
-    import workloads as W
-    x = W.complex_normal(3, s.ns)
-    n, t0 = 0, time.perf_counter()
-    while True:
-        A.far_matvec(n % (ng + 1), x)
-        A.near_matvec(vals, x)
-        n += 1
-        if time.perf_counter() - t0 > budget_s or n >= 50:
-            break
-    t_mv = (time.perf_counter() - t0) / n
-    step_s = (ng + iters_per_step + 1) * t_mv * wl.batch
-    return {"value": 1.0 / step_s, "unit": "time-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n} oracle AIM operator applications (numpy FP64, {s.ns} RWG, {2 * wl.grid}^3 FFT) "
-                      f"at {t_mv:.3f} s each; one step of the {wl.batch}-direction job priced as "
-                      f"{wl.batch} x ({ng} delayed + {iters_per_step:.1f} GMRES + 1) applications; "
-                      f"near-zone values zero (cost is value-independent)"}
+def cpu_baseline(wl, budget_s=25.0):
+    """The oracle's FFT march of eq. (5) (numpy/scipy FP64, exact near-zone
+    entries, right-Jacobi GMRES) on the host cores for one direction, run as
+    a child process that never touches the GPU (its set-up forks a worker
+    pool); returns its JSON record."""
+    import subprocess
+    cmd = [sys.executable, "-m", "oracle.baseline", "--workload", wl.name, "--budget", str(budget_s)]
+    r = subprocess.run(cmd, cwd=ROOT, capture_output=True, text=True, timeout=900)
+    if r.returncode != 0:
+        raise RuntimeError(f"cpu baseline failed ({r.returncode}): {r.stderr[-2000:]}")
+    return json.loads(r.stdout.strip().splitlines()[-1])
 
 
 def step_err(a, b) -> float:
@@ -167,18 +157,62 @@ def hbm_traffic(workload: str, kernel: str):
     return k["bytes_per_launch"]
 
 
+def derived_dt(wl, xyz) -> float:
+    """The time step the library derives for the workload: with N_g given,
+    dt = R_max / (c (N_g - Q + 1/2)), R_max the largest vertex distance;
+    otherwise dt = beta / f_bw."""
+    if not wl.ng:
+        return wl.beta / wl.f_bw
+    d = np.sqrt(((xyz[:, None, :] - xyz[None, :, :]) ** 2).sum(-1))
+    return float(d.max()) / (299_792_458.0 * (wl.ng - 3 + 0.5))
+
+
+def window(wl, dt: float, ng: int, K: int, warmup: int, first: int):
+    """(first timed step, traced steps before it, pulse-peak step).  Default:
+    centred on the pulse peak t_d / dt, no earlier than N_g + 8 plus the
+    traced pass (every timed and traced step has N_g live history terms),
+    and after at least `warmup` untimed steps."""
+    peak = int(round(wl.td / dt))
+    kt = min(K, 40)
+    if first < 0:
+        first = max(warmup, ng + 8 + kt, peak - K // 2)
+    if first < kt + 1:
+        raise SystemExit(f"--first must be at least {kt + 1}")
+    return first, kt, peak
+
+
+def roofline_record(dom, d, info, batch, traffic):
+    avg_ms = d["ms"] / d["launches"]
+    bytes_launch = d["bytes"] / d["launches"]
+    hbm_gbs = bytes_launch / (avg_ms / 1e3) / 1e9
+    flops = class_flops(dom, info, batch)
+    if flops is not None and flops / (avg_ms / 1e3) / 1e12 / ALU_PEAK_TFLOPS > hbm_gbs / HBM_PEAK_GBS:
+        # the FFT work, not the bytes, bounds this kernel: roofline against the FP32 vector issue rate
+        achieved = flops / (avg_ms / 1e3) / 1e12
+        return {"bound": "alu", "achieved": round(achieved, 2), "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / ALU_PEAK_TFLOPS, 4), "traffic": traffic, "kernel": dom,
+                "frac_of_unpacked_issue_rate": round(achieved / ALU_ISSUE_TFLOPS, 4), "flops_per_launch": flops, "bytes_per_launch": bytes_launch, "avg_launch_ms": avg_ms,
+                "launches": d["launches"], "hbm_GBps": round(hbm_gbs, 1),
+                "hbm_frac": round(hbm_gbs / HBM_PEAK_GBS, 4)}
+    return {"bound": "hbm", "achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(hbm_gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
+            "bytes_per_launch": bytes_launch, "avg_launch_ms": avg_ms, "launches": d["launches"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=0, help="timed steps (default: the workload's N_t)")
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=5, help="at least this many untimed steps before the window")
+    ap.add_argument("--first", type=int, default=-1,
+                    help="first timed step (default: the window is centred on the pulse peak)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--workload", default="batch", choices=["batch", "single"])
     ap.add_argument("--sync-every", type=int, default=4,
                     help="Arnoldi steps enqueued per host convergence check")
     ap.add_argument("--graph", action="store_true",
-                    help="also time the march with Arnoldi steps replayed from HIP graphs (profiling off)")
+                    help="also time the window with Arnoldi steps replayed from HIP graphs (profiling off)")
     ap.add_argument("--tune-ms", type=int, default=4000,
                     help="autotuner budget before timing (0: keep the library's default shapes)")
     ap.add_argument("--true-residual", action="store_true",
@@ -198,7 +232,11 @@ def main():
 
     wl = W.SPHERE_L4_BATCH if args.workload == "batch" else W.SPHERE_L4
     K = args.steps or wl.nt
-    nt = max(K, args.warmup, 1)
+    xyz, _, _ = wl.mesh()
+    dt = derived_dt(wl, xyz)
+    ng = wl.ng   # both bench workloads state N_g
+    first, kt, peak = window(wl, dt, ng, K, args.warmup, args.first)
+    nt = first + K
     torch.cuda.set_device(0)
     if args.calib_copy:
         n = args.calib_copy * (1 << 20) // 4
@@ -208,10 +246,12 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] calibration copy of {args.calib_copy} MiB done")
         del src, dst
-    log(f"[bench] set-up {wl.name}: B={wl.batch} nt={nt}")
+    log(f"[bench] set-up {wl.name}: B={wl.batch}, timed steps {first}..{nt - 1} (pulse peak at step {peak})")
     t = time.perf_counter()
     P = make_problem(wl, FP32, wl.batch, nt, 1e-5, flags=fl, sync_every=args.sync_every)
     log(f"[bench] set-up {time.perf_counter() - t:.1f} s, info {P.info}")
+    if abs(P.info["dt"] - dt) > 1e-9 * dt or P.info["ng"] != ng:
+        raise SystemExit(f"window derived for dt {dt}, N_g {ng}; the library derived {P.info['dt']}, {P.info['ng']}")
     tuning = None
     if args.tune_ms:
         t = time.perf_counter()
@@ -219,63 +259,53 @@ def main():
         log(f"[bench] autotune {time.perf_counter() - t:.1f} s: {tuning}")
     kh, pp = wl.incidence()
     V = P.excitation(kh, pp, wl.sigma, wl.td)
-    if args.warmup:
-        P.march(V, nsteps=args.warmup)
-        log(f"[bench] warm-up {args.warmup} steps done")
-    # inside the timed region only the roofline kernel and the delayed-field
-    # stream are traced (single-kernel classes: their events ride on the dispatch);
-    # the per-class table comes from a second, untimed pass that traces every
-    # class (event markers between launches cost stream time)
+    I32 = P.empty(nt, wl.batch, P.ns)
+    # untimed: steps 0 .. first - kt - 1, then steps first - kt .. first - 1 with
+    # every kernel class traced (event markers between launches cost stream time)
+    _, st_w = P.march(V, out=I32, nsteps=first - kt)
+    P.set_profiling(True)
+    _, st_t = P.march_continue(V, I32, first - kt, kt)
+    ks = P.kernel_stats()
+    log(f"[bench] untimed steps 0..{first - 1} done ({(st_w['total_iters'] + st_t['total_iters']) / first:.2f} "
+        f"GMRES it/step)")
+    # timed: steps first .. first + K - 1; only the single-kernel classes of the
+    # roofline record are traced (their events ride on the dispatch)
     P.set_profiling(classes=TIMED_CLASSES)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    I32, st = P.march(V, nsteps=K)
+    _, st = P.march_continue(V, I32, first, K)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    kt = P.kernel_stats()
-    P.set_profiling(True)
-    P.march(V, nsteps=K)
-    ks = P.kernel_stats()
+    kt_stats = P.kernel_stats()
     P.set_profiling(False)
     wall = t1 - t0
     steps_s = K / wall
     iters = st["total_iters"] / max(K, 1)
-    log(f"[bench] timed {K} steps in {wall:.2f} s: {steps_s:.2f} steps/s, {iters:.1f} GMRES it/step, "
+    unstable = [x["unstable_step"] for x in (st_w, st_t, st) if x["unstable_step"] >= 0]
+    log(f"[bench] timed {K} steps in {wall:.3f} s: {steps_s:.2f} steps/s, {iters:.2f} GMRES it/step, "
         f"phase ms rhs {st['ms_rhs']:.0f} solve {st['ms_solve']:.0f} commit {st['ms_commit']:.0f}")
     for name, v in ks.items():
         if v["launches"]:
             log(f"[bench]   {name:12s} {v['ms']:9.1f} ms {v['launches']:7d} launches "
                 f"{v['bytes'] / max(v['ms'], 1e-9) / 1e6:8.1f} GB/s")
     dom = max(FFT_CLASSES, key=lambda n: ks[n]["ms"])
-    d = kt[dom] if dom in TIMED_CLASSES else ks[dom]
-    avg_ms = d["ms"] / d["launches"]
-    bytes_launch = d["bytes"] / d["launches"]
-    hbm_gbs = bytes_launch / (avg_ms / 1e3) / 1e9
-    traffic = hbm_traffic(wl.name, dom)
-    flops = class_flops(dom, P.info, wl.batch)
-    if flops is not None and flops / (avg_ms / 1e3) / 1e12 / ALU_PEAK_TFLOPS > hbm_gbs / HBM_PEAK_GBS:
-        # the FFT work, not the bytes, bounds this kernel: roofline against the FP32 vector issue rate
-        achieved = flops / (avg_ms / 1e3) / 1e12
-        roof = {"bound": "alu", "achieved": round(achieved, 2), "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / ALU_PEAK_TFLOPS, 4), "traffic": traffic, "kernel": dom,
-                "flops_per_launch": flops, "bytes_per_launch": bytes_launch, "avg_launch_ms": avg_ms,
-                "hbm_GBps": round(hbm_gbs, 1), "hbm_frac": round(hbm_gbs / HBM_PEAK_GBS, 4)}
-    else:
-        roof = {"bound": "hbm", "achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(hbm_gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
-                "bytes_per_launch": bytes_launch, "avg_launch_ms": avg_ms}
+    d = kt_stats[dom] if dom in TIMED_CLASSES else ks[dom]
+    roof = roofline_record(dom, d, P.info, wl.batch, hbm_traffic(wl.name, dom))
+    roof["timed_in"] = "timed window" if dom in TIMED_CLASSES else "traced pass before the window"
     # one AIM matvec = the four matvec classes once each (launch averages)
     per_matvec_ms = sum(ks[n]["ms"] / ks[n]["launches"] for n in ("anterp_x", "yz_green", "fft_x_inv", "interp_near"))
     copy_gbps = stream_copy_gbps(torch)
-    roof["frac_of_stream_copy"] = round((hbm_gbs if roof["bound"] == "hbm" else roof["hbm_GBps"]) / copy_gbps, 4)
+    roof["frac_of_stream_copy"] = round((roof["achieved"] if roof["bound"] == "hbm" else roof["hbm_GBps"])
+                                        / copy_gbps, 4)
     # the HBM-bound stage: the delayed field streams the history (the time-block
     # pass over the ring plus the per-step sum of the block's own steps)
-    dl_b = kt["yz_delayed"]["bytes"] + kt["ring_far"]["bytes"]
-    dl_ms = kt["yz_delayed"]["ms"] + kt["ring_far"]["ms"]
+    dl_b = kt_stats["yz_delayed"]["bytes"] + kt_stats["ring_far"]["bytes"]
+    dl_ms = kt_stats["yz_delayed"]["ms"] + kt_stats["ring_far"]["ms"]
     dl_gbs = dl_b / max(dl_ms, 1e-9) / 1e6
     hbm_stream = {"kernels": ["ring_far", "yz_delayed"], "GBps": round(dl_gbs, 1),
                   "frac": round(dl_gbs / HBM_PEAK_GBS, 4), "frac_of_stream_copy": round(dl_gbs / copy_gbps, 4),
                   "ms_per_step": round(dl_ms / max(K, 1), 3),
+                  "launches": {n: kt_stats[n]["launches"] for n in ("ring_far", "yz_delayed")},
                   "traffic": {n: hbm_traffic(wl.name, n) for n in ("ring_far", "yz_delayed")}}
     out = {"metric": "ET-AIM time-steps/s & FFT-matvec HBM GB/s, FP32 batched vs FP64, 1 MI355X",
            "value": round(steps_s, 4), "unit": "time-steps/s", "n_gpus": 1, "steps": K, "warmup": args.warmup,
@@ -284,8 +314,11 @@ def main():
            "config": {"workload": wl.name, "ns": P.ns, "batch": wl.batch, "grid": wl.grid,
                       "sync_every": args.sync_every,
                       "gmres_stop": "true_residual" if args.true_residual else "residual_estimate",
-                      "padded": 2 * wl.grid, "ng": P.info["ng"], "mn": P.info["mn"], "nt": K, "tol": 1e-5,
+                      "padded": 2 * wl.grid, "ng": P.info["ng"], "mn": P.info["mn"], "nt": nt, "tol": 1e-5,
                       "parallelism": "1 GPU"},
+           "window": {"first_step": first, "last_step": nt - 1, "untimed_steps_before": first,
+                      "pulse_peak_step": peak, "history_terms_per_step": ng},
+           "unstable_step": min(unstable) if unstable else None,
            "direction_steps_per_s": round(steps_s * wl.batch, 3),
            "gmres_iters_per_step": round(iters, 2),
            "roofline": roof,
@@ -296,67 +329,72 @@ def main():
            "tuning": tuning,
            "kernels": {n: {"ms": round(v["ms"], 2), "launches": v["launches"],
                            "GBps": round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1)} for n, v in ks.items()
-                       if v["launches"]}}
+                       if v["launches"]},
+           "kernels_from": f"steps {first - kt}..{first - 1}, every class traced"}
     I32_0 = I32[:, 0].cpu().numpy()
     P.close()
+    del I32
     if args.graph or (tuning and tuning["graph"]):
         Pg = make_problem(wl, FP32, wl.batch, nt, 1e-5, flags=fl | F_GRAPH, sync_every=args.sync_every)
         if tuning:
             Pg.set_tuning(dict(tuning, graph=1))
-        if args.warmup:
-            Pg.march(V, nsteps=args.warmup)
+        Ig = Pg.empty(nt, wl.batch, Pg.ns)
+        Pg.march(V, out=Ig, nsteps=first)
         torch.cuda.synchronize()
         g0 = time.perf_counter()
-        Ig, stg = Pg.march(V, nsteps=K)
+        _, stg = Pg.march_continue(V, Ig, first, K)
         torch.cuda.synchronize()
         wg = time.perf_counter() - g0
         out["graph"] = {"time_steps_per_s": round(K / wg, 4), "gmres_iters_per_step": round(stg["total_iters"] / K, 2),
-                        "max_abs_diff_vs_eager": float((Ig[:, 0].cpu().numpy() - I32_0).__abs__().max())}
+                        "max_abs_diff_vs_eager": float(np.abs(Ig[:, 0].cpu().numpy() - I32_0).max())}
         log(f"[bench] graph replay: {K / wg:.2f} steps/s")
         Pg.close()
         del Ig
-    del V, I32
+    del V
     torch.cuda.empty_cache()
+    win = slice(first, nt)
     if not args.no_fp64:
         P64 = make_problem(wl, FP64, 1, nt, 1e-5, flags=fl)
+        if tuning:
+            P64.autotune(budget_ms=max(args.tune_ms // 2, 1))
         V64 = P64.excitation(kh[:1], pp[:1], wl.sigma, wl.td)
-        if args.warmup:
-            P64.march(V64, nsteps=args.warmup)
+        I64 = P64.empty(nt, 1, P64.ns)
+        P64.march(V64, out=I64, nsteps=first)
         torch.cuda.synchronize()
         s0 = time.perf_counter()
-        I64, st64 = P64.march(V64, nsteps=K)
+        _, st64 = P64.march_continue(V64, I64, first, K)
         torch.cuda.synchronize()
         w64 = time.perf_counter() - s0
         I64_0 = I64[:, 0].cpu().numpy()
-        err = float(np.linalg.norm(I32_0[:K] - I64_0[:K]) / np.linalg.norm(I64_0[:K]))
+        err = float(np.linalg.norm(I32_0[win] - I64_0[win]) / np.linalg.norm(I64_0[win]))
         out["fp64_plain"] = {"direction_steps_per_s": round(K / w64, 3), "time_steps_per_s": round(K / w64, 3),
                              "gmres_iters_per_step": round(st64["total_iters"] / K, 2)}
         out["fp32_batched_over_fp64_plain"] = round(steps_s * wl.batch / (K / w64), 2)
         out["fp32_rel_l2_vs_fp64_dir0"] = err
-        out["fp32_max_step_err_vs_fp64_dir0"] = step_err(I32_0[:K], I64_0[:K])
-        log(f"[bench] fp64 plain: {K / w64:.2f} steps/s; fp32 batch vs fp64 rel L2 {err:.2e}")
+        out["fp32_max_step_err_vs_fp64_dir0"] = step_err(I32_0[win], I64_0[win])
+        out["fp32_rel_l2_vs_fp64_dir0_steps_0_to_last"] = float(np.linalg.norm(I32_0 - I64_0) / np.linalg.norm(I64_0))
+        log(f"[bench] fp64 plain: {K / w64:.2f} steps/s; fp32 batch vs fp64 rel L2 over the window {err:.2e}")
         P64.close()
         del I64
-        # precision error apart from the GMRES tolerance: FP32 at tol 1e-7
-        # against FP64 at tol 1e-12, direction 0, the first Kp steps
-        Kp = min(K, 100)
-        Pt = make_problem(wl, FP64, 1, nt, 1e-12, flags=fl)
-        It64, _ = Pt.march(V64, nsteps=Kp)
-        It64 = It64[:Kp, 0].cpu().numpy()
-        Pt.close()
-        Pt = make_problem(wl, FP32, 1, nt, 1e-7, flags=fl)
-        It32, _ = Pt.march(V64, nsteps=Kp)
-        It32 = It32[:Kp, 0].cpu().numpy()
-        Pt.close()
+        # precision error apart from the GMRES tolerance: FP32 at tol 1e-7 against
+        # FP64 at tol 1e-12, direction 0, over the same window
+        res = {}
+        for prec, tol in ((FP64, 1e-12), (FP32, 1e-7)):
+            Pt = make_problem(wl, prec, 1, nt, tol, flags=fl)
+            It, _ = Pt.march(V64, nsteps=nt)
+            res[prec] = It[:, 0].cpu().numpy()
+            Pt.close()
+            del It
         out["fp32_precision_error_dir0"] = {
-            "steps": Kp, "tol_fp32": 1e-7, "tol_fp64": 1e-12,
-            "rel_l2": float(np.linalg.norm(It32 - It64) / np.linalg.norm(It64)),
-            "max_step_err": step_err(It32, It64)}
-        log(f"[bench] precision error (tol 1e-7 vs 1e-12, {Kp} steps): "
+            "steps": [first, nt - 1], "tol_fp32": 1e-7, "tol_fp64": 1e-12,
+            "rel_l2": float(np.linalg.norm(res[FP32][win] - res[FP64][win]) / np.linalg.norm(res[FP64][win])),
+            "max_step_err": step_err(res[FP32][win], res[FP64][win])}
+        log(f"[bench] precision error (tol 1e-7 vs 1e-12, steps {first}..{nt - 1}): "
             f"{out['fp32_precision_error_dir0']['rel_l2']:.2e}")
+        del V64
     if not args.no_cpu:
-        log("[bench] cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(wl, iters / 1.0)
+        log("[bench] cpu baseline (oracle march on the host cores, child process) ...")
+        out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)
 
 

@@ -39,6 +39,25 @@ from .kernels import EnvelopeKernel
 from .physics import C0
 from .quadrature import collapsed_gauss, points
 
+# threads of the 3-D transforms: 1 = numpy's FFT; more = scipy.fft with that
+# many workers (the same transform, run on several cores; the timed CPU
+# baseline sets it to the machine's core count)
+FFT_WORKERS = 1
+
+
+def _fftn(a):
+    if FFT_WORKERS == 1:
+        return np.fft.fftn(a)
+    import scipy.fft
+    return scipy.fft.fftn(a, workers=FFT_WORKERS)
+
+
+def _ifftn(a):
+    if FFT_WORKERS == 1:
+        return np.fft.ifftn(a)
+    import scipy.fft
+    return scipy.fft.ifftn(a, workers=FFT_WORKERS)
+
 
 class Grid:
     def __init__(self, xyz: np.ndarray, n):
@@ -202,23 +221,71 @@ class AIM:
         out[3] = dense_node_matrix(self.grid, self.GP[m]) @ q[3]
         return out
 
+    def green_hat(self, m: int, c: int) -> np.ndarray:
+        """FFT of the circulant embedding of G^A_m (c < 3) or G^phi_m (c = 3),
+        [2Nz, 2Ny, 2Nx]; computed once per (m, part) and kept."""
+        key = (m, c < 3)
+        cache = self.__dict__.setdefault("_ghat", {})
+        if key not in cache:
+            cache[key] = _fftn(circulant(self.GA[m] if c < 3 else self.GP[m]))
+        return cache[key]
+
+    def spectra(self, x: np.ndarray) -> np.ndarray:
+        """Forward FFT of the zero-padded anterpolated grid, [4, 2Nz, 2Ny, 2Nx]."""
+        nx, ny, nz = self.grid.n
+        q = self.anterpolate(x)
+        out = np.zeros((4, 2 * nz, 2 * ny, 2 * nx), dtype=np.complex128)
+        for c in range(4):
+            out[c, :nz, :ny, :nx] = q[c].reshape(nz, ny, nx)
+            out[c] = _fftn(out[c])
+        return out
+
     def propagate_fft(self, m: int, q: np.ndarray) -> np.ndarray:
         """p = G_m q by zero-padded circulant FFT convolution (2N per axis)."""
         nx, ny, nz = self.grid.n
         out = np.empty_like(q)
         for c in range(4):
-            tab = self.GA[m] if c < 3 else self.GP[m]
-            circ = circulant(tab)
             qq = np.zeros((2 * nz, 2 * ny, 2 * nx), dtype=np.complex128)
             qq[:nz, :ny, :nx] = q[c].reshape(nz, ny, nx)
-            p = np.fft.ifftn(np.fft.fftn(circ) * np.fft.fftn(qq))
+            p = _ifftn(self.green_hat(m, c) * _fftn(qq))
             out[c] = p[:nz, :ny, :nx].ravel()
         return out
 
     def far_matvec(self, m: int, x: np.ndarray, direct: bool = False) -> np.ndarray:
         q = self.anterpolate(x)
-        p = self.propagate_direct(m, q) if direct else self.propagate_fft(m, q)
+        p = self.propagate_fft(m, q) if not direct else self.propagate_direct(m, q)
         return self.interpolate(p)
+
+    def far_sum_rows(self, terms, rows) -> np.ndarray:
+        """sum_i Z^FFT_{m_i} x_i on the given rows only, for terms = [(m_i,
+        spectra(x_i))]: the products with the Green spectra are summed before
+        one inverse transform (the transform is linear), then interpolated at
+        the stencils of ``rows``."""
+        nx, ny, nz = self.grid.n
+        rows = np.asarray(rows)
+        p = np.empty((4, self.grid.nnodes), dtype=np.complex128)
+        for c in range(4):
+            acc = np.zeros((2 * nz, 2 * ny, 2 * nx), dtype=np.complex128)
+            for m, qh in terms:
+                acc += self.green_hat(m, c) * qh[c]
+            p[c] = _ifftn(acc)[:nz, :ny, :nx].ravel()
+        return sum(np.einsum("kn,kn->k", self.L[rows, c, :], p[c][self.nodes[rows]]) for c in range(4))
+
+    def near_values_rows(self, zfill_pairs, rows):
+        """Pre-corrected values [M_n+1, P] of the near pairs whose row is in
+        ``rows`` (the pairs in CSR order: (self.rows[sel], self.cols[sel])).
+        Returns (sel, values)."""
+        sel = np.isin(self.rows, np.asarray(rows))
+        rr, cc = self.rows[sel], self.cols[sel]
+        ms = list(range(self.mn + 1))
+        return sel, zfill_pairs(rr, cc, ms) - self.far_pairs(ms, rr, cc)
+
+    def near_rows(self, sel, vals_m: np.ndarray, x: np.ndarray, rows) -> np.ndarray:
+        """(Z^near_m x) on ``rows`` from the values of ``near_values_rows``."""
+        rr, cc = self.rows[sel], self.cols[sel]
+        y = np.zeros(self.surf.ns, dtype=np.complex128)
+        np.add.at(y, rr, vals_m * x[cc])
+        return y[np.asarray(rows)]
 
     def far_dense(self, m: int) -> np.ndarray:
         """Z^FFT_m as a dense [ns, ns] matrix (tiny problems)."""

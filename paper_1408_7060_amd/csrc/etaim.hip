@@ -840,8 +840,18 @@ int march_impl(etaim_ctx* c, const zd* V, zd* I, etaim_stats* st, bool adjoint, 
         c->dev_bytes -= (int64_t)((size_t)nt * B * sizeof(double));
         HIPCHK(hipFree(d));
     }
+    // the excitation's largest norm and the step of the call (in marching
+    // order) where it peaks: growth counts as late-time only after it
     double vmax = 0;
-    for (double v : nV) vmax = std::max(vmax, v);
+    int vpeak = 0;
+    for (int q = 0; q < nt; ++q) {
+        const int lq = adjoint ? nt - 1 - q : q;
+        for (int b = 0; b < B; ++b)
+            if (nV[(size_t)lq * B + b] > vmax) {
+                vmax = nV[(size_t)lq * B + b];
+                vpeak = q;
+            }
+    }
     int steps = 0, tot_iters = 0, max_iters = 0, first_noconv = -1, unstable = -1;
     double maxres = 0, ms_rhs = 0, ms_solve = 0, ms_commit = 0;
     bool nonfinite = false;
@@ -853,9 +863,10 @@ int march_impl(etaim_ctx* c, const zd* V, zd* I, etaim_stats* st, bool adjoint, 
     CHK(c->alloc(nrm_all, (size_t)nt * B));
     const int W = 32;
     auto detect = [&](int r) {
-        // late-time growth: monotone growth by > 10x over W steps while the
-        // excitation is negligible
-        if (unstable >= 0 || r < W) return;
+        // late-time growth: monotone growth by > 10x over W steps that follow
+        // the excitation's peak, while the excitation is negligible (a current
+        // that grows with a rising pulse is not flagged)
+        if (unstable >= 0 || r < W || r - W + 1 <= vpeak) return;
         bool mono = nI[r] > 10.0 * nI[r - W];
         double vw = 0;
         for (int q = r - W + 1; q <= r && mono; ++q) {

@@ -1,0 +1,172 @@
+"""Oracle parity at the full shape of the batched level-4 workload, in the
+launch configuration the bench times (Sec. 4 stages (i)-(v), eq. (5)).
+
+Problem: level-4 icosphere of radius 1 m (7680 RWG), 48^3 grid padded to
+96^3, N_g = 24, M_n = 7, 343 440 near-zone entries, B = 32 columns, with the
+y/z plane engine that takes the z lines first, register x lines and time
+blocks of 7 steps (the setting the autotuner picks for this problem), in FP64
+and FP32.  The near zone is live: the oracle computes the exact near-zone
+entries of 256 sampled rows (seeded) and the FFT far part on the whole grid,
+and the library's outputs are compared on those rows for 4 columns (0, 1,
+16, 31: both entry slots and both halves of the interpolation's
+32-column lane map).
+
+* every Z_m with a near part (m = 0..M_n) and two far-only m;
+* the delayed field of a full N_g-step history, near history live;
+* the residual of eq. (5) of a march, at steps that take every position of
+  a 7-step time block, on the same rows.
+
+Tolerances: relative L2 over the sampled block 1e-12 (FP64) and 1e-5 (FP32)
+for the operators, as at the smaller sizes; for the march, the residual of
+eq. (5) relative to the right-hand side, 1e-10 (FP64 at GMRES tolerance
+1e-12) and 1e-4 (FP32 at 1e-5), the bounds stated for each precision."""
+import functools
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_cases import gpu_problem, params_of, rel
+from oracle import aim, geometry, kernels, zfill
+
+pytestmark = pytest.mark.gpu
+
+WL = W.SPHERE_L4_BATCH
+COLS = (0, 1, 16, 31)
+NROWS = 256
+F_CONTINUE_ON_NOCONV = 1
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128)).cuda()
+
+
+@functools.lru_cache(maxsize=None)
+def _oracle():
+    """(surface, AIM, params, sampled rows, near selection, near values)."""
+    p = params_of(WL)
+    s = geometry.Surface(p["xyz"], p["tri"], p["rwg"])
+    A = aim.AIM(s, WL.grid, p["d_near"], p["dt"], WL.f0, p["ng"])
+    rows = np.sort(W.rng(0, 6).choice(s.ns, NROWS, replace=False))
+
+    def exact(r, c, ms):
+        return zfill.assemble_pairs(s, r, c, [kernels.EnvelopeKernel(m, p["dt"], WL.f0) for m in ms])
+
+    sel, vals = A.near_values_rows(exact, rows)
+    _say(f"oracle: level-4 rows {NROWS}, near pairs of those rows {int(sel.sum())}, M_n {A.mn}")
+    return s, A, p, rows, sel, vals
+
+
+def _bench_setting(P):
+    d = P.tuning()
+    d.update(yz_engine=2, x_engine=1, delay_block=7)
+    P.set_tuning(d)
+    t = P.tuning()
+    assert (t["yz_engine"], t["x_engine"], t["delay_block"]) == (2, 1, 7)
+
+
+def _zx_rows(A, sel, vals, terms, rows):
+    """sum over (m, x) of (Z^near_m + Z^FFT_m) x on the sampled rows."""
+    far = A.far_sum_rows([(m, A.spectra(x)) for m, x in terms], rows)
+    near = sum(A.near_rows(sel, vals[m], x, rows) for m, x in terms if m <= A.mn)
+    return far + near
+
+
+@functools.lru_cache(maxsize=None)
+def _operator_ref():
+    s, A, p, rows, sel, vals = _oracle()
+    x = W.complex_normal(43, (WL.batch, s.ns))
+    ms = list(range(A.mn + 1)) + [A.mn + 1, p["ng"]]
+    ref = {m: np.array([_zx_rows(A, sel, vals, [(m, x[c])], rows) for c in COLS]) for m in ms}
+    return x, ref
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-5)], ids=["fp64", "fp32"])
+def test_operator_at_bench_shape(torch, prec, tol):
+    s, A, p, rows, sel, vals = _oracle()
+    x, ref = _operator_ref()
+    P = gpu_problem(WL.name, precision=prec, nt=8)
+    assert (P.info["mn"], P.info["nnz"], P.batch) == (A.mn, len(A.rows), 32)
+    _bench_setting(P)
+    xd = _dev(torch, x)
+    for m, r in ref.items():
+        y = P.apply_z(m, xd).cpu().numpy()[list(COLS)][:, rows]
+        e = rel(y, r)
+        _say("bench shape Z_m", "fp32" if prec else "fp64", "m", m, "rel", e)
+        assert e <= tol, (m, e)
+    P.close()
+
+
+@functools.lru_cache(maxsize=None)
+def _delayed_ref():
+    s, A, p, rows, sel, vals = _oracle()
+    ng = p["ng"]
+    hist = W.complex_normal(44, (ng, WL.batch, s.ns))
+    ref = np.array([_zx_rows(A, sel, vals, [(m, hist[m - 1, c]) for m in range(1, ng + 1)], rows) for c in COLS])
+    return hist, ref
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-5)], ids=["fp64", "fp32"])
+def test_delayed_field_at_bench_shape(torch, prec, tol):
+    """b = sum_{m=1}^{N_g} (Z^near_m + Z^FFT_m) I_{l-m} over a full history,
+    near history live (m <= M_n), time blocks of 7."""
+    s, A, p, rows, sel, vals = _oracle()
+    hist, ref = _delayed_ref()
+    P = gpu_problem(WL.name, precision=prec, nt=8)
+    _bench_setting(P)
+    b = P.delayed_field(_dev(torch, hist)).cpu().numpy()[list(COLS)][:, rows]
+    e = rel(b, ref)
+    _say("bench shape delayed field", "fp32" if prec else "fp64", "rel", e)
+    assert e <= tol
+    P.close()
+
+
+@pytest.mark.parametrize("prec,gtol,bound", [(0, 1e-12, 1e-10), (1, 1e-5, 1e-4)], ids=["fp64", "fp32"])
+def test_march_residual_at_bench_shape(torch, prec, gtol, bound):
+    """A 36-step march of the 32 directions (the pulse of the workload,
+    delayed so that it peaks inside the window), then the oracle's residual
+    of eq. (5), V_l - sum_{m=0}^{min(l, N_g)} (Z^near_m + Z^FFT_m) I_{l-m},
+    relative to the right-hand side V_l - sum_{m>=1} ..., on the sampled rows
+    for columns 0 and 31 at steps 28..34 (every position of a 7-step block;
+    every step then has all N_g history terms live)."""
+    s, A, p, rows, sel, vals = _oracle()
+    nt, ng = 36, p["ng"]
+    P = gpu_problem(WL.name, precision=prec, nt=nt, tol=gtol, restart=50, flags=F_CONTINUE_ON_NOCONV,
+                    sync_every=4)
+    _bench_setting(P)
+    kh, pp = WL.incidence()
+    V = P.excitation(kh, pp, WL.sigma, 24 * p["dt"])
+    I, st = P.march(V)
+    assert st["first_noconv_step"] == -1
+    V, I = V.cpu().numpy(), I.cpu().numpy()
+    _say("bench shape march", "fp32" if prec else "fp64", "iterations", st["total_iters"])
+    worst = 0.0
+    for c in (0, 31):
+        spec = {j: A.spectra(I[j, c]) for j in range(28 - ng, 35)}
+
+        def zx(terms):
+            far = A.far_sum_rows([(m, spec[j]) for m, j in terms], rows)
+            return far + sum(A.near_rows(sel, vals[m], I[j, c], rows) for m, j in terms if m <= A.mn)
+
+        for l in range(28, 35):
+            rhs = V[l, c][rows] - zx([(m, l - m) for m in range(1, min(l, ng) + 1)])
+            r = rhs - zx([(0, l)])
+            e = float(np.linalg.norm(r) / np.linalg.norm(rhs))
+            worst = max(worst, e)
+            _say(f"  column {c} step {l} (block position {(l - 1) % 7}) residual {e:.2e}")
+    assert worst <= bound, worst
+    P.close()

@@ -158,3 +158,29 @@ def test_near_pairs_equal_brute_force_distance_scan(level, radius, lam_frac, fc)
     k, k2 = 0, int(np.argsort(D[0])[5])
     r2, c2 = aim.near_pairs(s, float(np.linalg.norm(c[k] - c[k2])))
     assert np.any((r2 == k) & (c2 == k2)) and np.any((r2 == k2) & (c2 == k))
+
+
+def test_sampled_row_helpers_equal_the_full_operator():
+    """The sampled-row forms used at full size (a k-space sum of several
+    terms before one inverse transform, interpolated at chosen rows; the
+    pre-corrected near values of the chosen rows' pairs) equal the full
+    operator's rows: the sum of far_matvec over the terms, and near_values
+    restricted to those rows."""
+    A, dt, ng = get_aim()
+    s = A.surf
+    rows = np.array([0, 5, 77, 200, 479])
+    xs = [W.complex_normal(60 + i, s.ns) for i in range(3)]
+    ms = [0, 2, ng]
+    ref = sum(A.far_matvec(m, x) for m, x in zip(ms, xs))[rows]
+    got = A.far_sum_rows([(m, A.spectra(x)) for m, x in zip(ms, xs)], rows)
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+
+    def exact(r, c, mm):
+        return zfill.assemble_pairs(s, r, c, [kernels.EnvelopeKernel(m, dt, FC) for m in mm])
+
+    full = A.near_values(exact)
+    sel, vals = A.near_values_rows(exact, rows)
+    np.testing.assert_allclose(vals, full[:, sel], rtol=0, atol=1e-13 * np.abs(full).max())
+    for m in range(A.mn + 1):
+        y = A.near_matvec(full[m], xs[0])[rows]
+        assert np.abs(A.near_rows(sel, vals[m], xs[0], rows) - y).max() <= 1e-13 * np.abs(y).max()
