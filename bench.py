@@ -227,8 +227,9 @@ def main():
     import torch
     import workloads as W
     from paper_1408_7060_amd import FP32, FP64
-    from paper_1408_7060_amd._lib import F_CONTINUE_ON_NOCONV, F_GRAPH, F_IMPLICIT_STOP
-    fl = F_CONTINUE_ON_NOCONV | (0 if args.true_residual else F_IMPLICIT_STOP)
+    from paper_1408_7060_amd._lib import F_CONTINUE_ON_NOCONV, F_GRAPH, F_IMPLICIT_STOP, F_RESIDUAL_CHECK
+    # the FP64 residual check of eq. (5) every 16 steps is part of the precision form
+    fl = F_CONTINUE_ON_NOCONV | F_RESIDUAL_CHECK | (0 if args.true_residual else F_IMPLICIT_STOP)
 
     wl = W.SPHERE_L4_BATCH if args.workload == "batch" else W.SPHERE_L4
     K = args.steps or wl.nt
@@ -319,6 +320,10 @@ def main():
            "window": {"first_step": first, "last_step": nt - 1, "untimed_steps_before": first,
                       "pulse_peak_step": peak, "history_terms_per_step": ng},
            "unstable_step": min(unstable) if unstable else None,
+           "fp64_residual_check": {"column": 0, "every_steps": 16, "checks_in_window": st["residual_checks"],
+                                   "max_rel_residual": st["max_residual64"], "worst_step": st["residual_worst_step"],
+                                   "max_rel_residual_before_window": max(st_w["max_residual64"],
+                                                                         st_t["max_residual64"])},
            "direction_steps_per_s": round(steps_s * wl.batch, 3),
            "gmres_iters_per_step": round(iters, 2),
            "roofline": roof,

@@ -65,6 +65,13 @@ extern "C" {
                                         recomputes the true residual b - Z x at a new cycle start
                                         and stops only if that meets the tolerance too (one operator
                                         application more per step) */
+#define ETAIM_F_RESIDUAL_CHECK 16    /* forward marches check eq. (5) in FP64 every 16 steps (step l
+                                        with (l + 1) % 16 == 0) and at the last step of the call:
+                                        ||V_l - sum_{m>=0} Z_m I_{l-m}|| / ||V_l - sum_{m>=1} Z_m I_{l-m}||
+                                        with the FP64 operators, for every column of an FP64 march and
+                                        for column 0 of an FP32 one (its FP64 history is kept by an
+                                        internal FP64 context of the same problem, about 1.4 GB at the
+                                        level-4 size); results in etaim_stats */
 
 typedef struct etaim_ctx etaim_ctx;
 
@@ -129,6 +136,9 @@ typedef struct {
     double ms_rhs, ms_solve, ms_commit, ms_total;  /* device time per phase */
     double max_rel_residual;   /* largest final relative residual (estimate) */
     int32_t *iters_per_step;   /* optional caller host buffer [N_t] (or NULL) */
+    int32_t residual_checks;     /* FP64 checks of eq. (5) made (ETAIM_F_RESIDUAL_CHECK), else 0 */
+    int32_t residual_worst_step; /* step of the largest checked residual (-1: none) */
+    double max_residual64;       /* largest FP64 relative residual of eq. (5) over the checks */
 } etaim_stats;
 
 /* Context set-up (the paper's "matrix fill", Sec. 4 stages (i)-(iv), not

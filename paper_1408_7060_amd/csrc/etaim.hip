@@ -109,6 +109,10 @@ struct etaim_ctx {
     int next_step = -1, guess_p_next = 1;
     bool guess_dev_next = false;
     bool use_graph = false, capturing = false;
+    bool no_solver = false;  // an operator-only context (the FP64 check companion): no preconditioner set-up
+    int ring_cols = 0;       // columns of a spectrum-ring slot (0: B)
+    int check_next = 0;      // companion: the first step its history does not hold yet
+    int check_synced = -1;   // the step at which the companion's history continues this context's march
     hipStream_t cap_stream = nullptr;
     std::vector<hipGraphExec_t> graphs[2];  // [conj][j]
     // launch shapes (0 = automatic); the autotuner sets them
@@ -118,6 +122,9 @@ struct etaim_ctx {
     int x_engine = 0;   // 0: LDS line kernels, 1: register line kernels
     void* xs = nullptr; // [ns][B] scaled columns for the register anterpolation
     hipEvent_t ev[8] = {};  // march phase events, two sets (steps alternate)
+    // FP64 residual check of an FP32 march (ETAIM_F_RESIDUAL_CHECK): an FP64
+    // context of the same problem for the monitored column 0, on this stream
+    etaim_ctx* check = nullptr;
     // per-kernel-class tracing
     bool prof = false;
     uint32_t prof_mask = 0;  // traced kernel classes, bit ETAIM_K_*
@@ -155,6 +162,7 @@ struct etaim_ctx {
         return ETAIM_OK;
     }
     ~etaim_ctx() {
+        delete check;
         for (auto& e : ev)
             if (e) (void)hipEventDestroy(e);
         for (auto& e : pool) (void)hipEventDestroy(e);
@@ -533,10 +541,21 @@ struct Ops {
     }
     // push the converged I_cur into the spectrum ring and the current ring
     static int commit(etaim_ctx* c, int cur, const zd* x) {
+        const size_t slot_sz = (size_t)4 * c->B * c->Np;
+        CHK(commit_slot(c, ring(c) + (size_t)(cur % c->st.ng) * slot_sz, x));
+        if (c->st.mn >= 1) {
+            const size_t n = (size_t)c->B * c->ns;
+            // current history slot in the working precision, columns of a basis contiguous
+            hipLaunchKernelGGL(k_prescale<R>, dim3(blocks_for(n)), dim3(256), 0, c->stream, x, nullptr,
+                               (cplx<R>*)c->hist + (size_t)(cur % c->st.mn) * n, c->ns, c->B, 0, nullptr);
+            HIPCHK(hipGetLastError());
+        }
+        return ETAIM_OK;
+    }
+    // anterpolate + forward FFT of the B columns of x into the spectrum slot `slot`
+    static int commit_slot(etaim_ctx* c, cplx<R>* slot, const zd* x) {
         CHK(forward_x(c, x, nullptr, 0));
         const GridDims& g = c->gd;
-        const size_t slot_sz = (size_t)4 * c->B * c->Np;
-        cplx<R>* slot = ring(c) + (size_t)(cur % c->st.ng) * slot_sz;
         {
             const double s = sizeof(cplx<R>);
             Trace t(c, ETAIM_K_YZ_COMMIT, 4.0 * c->B * g.L[0] * g.N[2] * g.N[1] * s + 4.0 * c->B * c->Np * s, true);
@@ -565,13 +584,6 @@ struct Ops {
                          (const cplx<R>*)A(c), slot, tw(c, 1), tw(c, 2), c->ry, c->rz, g);
         }
         HIPCHK(hipGetLastError());
-        if (c->st.mn >= 1) {
-            const size_t n = (size_t)c->B * c->ns;
-            // current history slot in the working precision, columns of a basis contiguous
-            hipLaunchKernelGGL(k_prescale<R>, dim3(blocks_for(n)), dim3(256), 0, c->stream, x, nullptr,
-                               (cplx<R>*)c->hist + (size_t)(cur % c->st.mn) * n, c->ns, c->B, 0, nullptr);
-            HIPCHK(hipGetLastError());
-        }
         return ETAIM_OK;
     }
     // allow the plane kernels and the gather their dynamic LDS
@@ -812,6 +824,126 @@ int gmres(etaim_ctx* c, const zd* rhs, zd* x, int conj, StepResult& res) {
 }
 
 // ---------------------------------------------------------------------------
+// FP64 residual check of eq. (5) (the late-time check of the precision form).
+// Every kCheckEvery steps (step r with (r + 1) % kCheckEvery == 0) and at the
+// last step of a call, the march forms in FP64
+//   res_l = ||V_l - sum_{m=0}^{min(N_g, l)} Z_m I_{l-m}|| / ||V_l - sum_{m>=1} Z_m I_{l-m}||
+// with the FP64 operators.  An FP64 march checks every column on the context
+// itself (rhs of the step, one FP64 matvec); an FP32 march checks column 0
+// on an FP64 companion context, which commits that column of every solution
+// into its own FP64 history and forms the delayed field from it.
+constexpr int kCheckEvery = 16;
+constexpr int kCheckBatch = 16;  // history steps transformed together by the FP64 companion
+
+int device_setup(etaim_ctx* c);
+
+int checker_create(etaim_ctx* c) {
+    if (c->check) return ETAIM_OK;
+    std::unique_ptr<etaim_ctx> k(new etaim_ctx());
+    k->prm = c->prm;
+    k->prm.precision = ETAIM_FP64;
+    k->prm.batch = kCheckBatch;
+    k->prm.flags = 0;
+    k->geo = c->geo;
+    k->st = c->st;
+    k->ns = c->ns;
+    k->B = kCheckBatch;  // grid buffers for the batched history transforms
+    k->ring_cols = 1;    // the history of one column
+    k->prec = ETAIM_FP64;
+    k->mv = c->mv;
+    k->nnz = c->nnz;
+    k->gd = c->gd;
+    k->gd.B = kCheckBatch;
+    k->rx = make_radix(k->gd.L[0]);
+    k->ry = make_radix(k->gd.L[1]);
+    k->rz = make_radix(k->gd.L[2]);
+    k->N3 = c->N3;
+    k->Np = c->Np;
+    k->gfold = c->gfold;
+    k->device = c->device;
+    k->ncu = c->ncu;
+    k->stream = c->stream;
+    k->no_solver = true;
+    k->yz_engine = quad_n(k.get()) ? 2 : 0;
+    k->x_engine = xline_n(k.get()) ? 1 : 0;
+    k->delay_block = 1;  // the delayed field is formed only at check steps: direct sum
+    CHK(device_setup(k.get()));
+    k->B = 1;  // its operators act on the one monitored column
+    k->gd.B = 1;
+    c->check = k.release();
+    return ETAIM_OK;
+}
+
+// an empty companion history that starts at step `from` (read from I_out later)
+int checker_reset(etaim_ctx* c, int from) {
+    etaim_ctx* k = c->check;
+    HIPCHK(hipMemsetAsync(k->ring, 0, (size_t)k->st.ng * 4 * k->Np * sizeof(zd), k->stream));
+    if (k->st.mn >= 1) HIPCHK(hipMemsetAsync(k->hist, 0, (size_t)k->st.mn * k->ns * sizeof(zd), k->stream));
+    k->far_r0 = -1;
+    k->check_next = std::max(from, 0);
+    return ETAIM_OK;
+}
+
+// the companion's history up to step hi - 1: column 0 of steps check_next..hi-1
+// of I_out (only the last N_g of them matter), in runs of consecutive ring
+// slots transformed together as the columns of one batch, and the last M_n
+// of them into its current ring
+int checker_fill(etaim_ctx* c, const zd* I, int hi) {
+    etaim_ctx* k = c->check;
+    const int ng = k->st.ng, mn = k->st.mn, ns = k->ns;
+    const int lo = std::max(k->check_next, hi - ng);
+    const size_t step = (size_t)c->B * ns;  // stride of I_out's steps
+    for (int s = lo; s < hi;) {
+        const int run = std::min({kCheckBatch, hi - s, ng - s % ng});
+        HIPCHK(hipMemcpy2DAsync(k->xk, (size_t)ns * sizeof(zd), I + (size_t)s * step, step * sizeof(zd),
+                                (size_t)ns * sizeof(zd), run, hipMemcpyDeviceToDevice, k->stream));
+        k->B = run;
+        k->gd.B = run;
+        const int rc = Ops<double>::commit_slot(k, (cplx<double>*)k->ring + (size_t)(s % ng) * 4 * k->Np, k->xk);
+        k->B = 1;
+        k->gd.B = 1;
+        CHK(rc);
+        s += run;
+    }
+    for (int s = std::max(lo, hi - mn); s < hi && mn >= 1; ++s)
+        hipLaunchKernelGGL(k_prescale<double>, dim3(blocks_for((size_t)ns)), dim3(256), 0, k->stream,
+                           I + (size_t)s * step, nullptr, (cplx<double>*)k->hist + (size_t)(s % mn) * ns, ns, 1, 0,
+                           nullptr);
+    HIPCHK(hipGetLastError());
+    k->check_next = std::max(k->check_next, hi);
+    return ETAIM_OK;
+}
+
+// residual and right-hand-side norms of step r into out[0..cols) and out[cols..2 cols)
+template <typename R>
+int check_step(etaim_ctx* c, int r, const zd* Vl, const zd* I, const zd* Il, double* out) {
+    if (c->prec == ETAIM_FP64) {
+        // the rhs of this step is still in c->rhs: r = rhs - Z0 I_l, all columns
+        const size_t nB = (size_t)c->B * c->ns;
+        CHK(Ops<double>::apply(c, 0, Il, nullptr, c->w, 0));
+        hipLaunchKernelGGL(k_residual, dim3(blocks_for(nB)), dim3(256), 0, c->stream, c->rhs, c->w, nB);
+        hipLaunchKernelGGL(k_norm, dim3(c->B), dim3(kRedThreads), 0, c->stream, c->w, out, c->ns, nullptr);
+        hipLaunchKernelGGL(k_norm, dim3(c->B), dim3(kRedThreads), 0, c->stream, c->rhs, out + c->B, c->ns,
+                           nullptr);
+        HIPCHK(hipGetLastError());
+        return ETAIM_OK;
+    }
+    etaim_ctx* k = c->check;
+    const size_t n = (size_t)k->ns;
+    CHK(checker_fill(c, I, r));
+    if (r >= 1)
+        CHK(Ops<double>::delayed(k, r, Vl, k->rhs, 0));
+    else
+        HIPCHK(hipMemcpyAsync(k->rhs, Vl, n * sizeof(zd), hipMemcpyDeviceToDevice, k->stream));
+    CHK(Ops<double>::apply(k, 0, Il, nullptr, k->w, 0));
+    hipLaunchKernelGGL(k_residual, dim3(blocks_for(n)), dim3(256), 0, k->stream, k->rhs, k->w, n);
+    hipLaunchKernelGGL(k_norm, dim3(1), dim3(kRedThreads), 0, k->stream, k->w, out, k->ns, nullptr);
+    hipLaunchKernelGGL(k_norm, dim3(1), dim3(kRedThreads), 0, k->stream, k->rhs, out + 1, k->ns, nullptr);
+    HIPCHK(hipGetLastError());
+    return ETAIM_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Steps first .. first + count - 1 of a march (the adjoint march: first = 0).
 // With first > 0 the history rings continue from the last forward march on
 // this context (or a loaded state) that ended at step first; otherwise they
@@ -828,6 +960,8 @@ int march_impl(etaim_ctx* c, const zd* V, zd* I, etaim_stats* st, bool adjoint, 
         if (c->st.mn >= 1) HIPCHK(hipMemsetAsync(c->hist, 0, (size_t)c->st.mn * nB * sizeof(zd), c->stream));
     }
     c->next_step = -1;  // valid again once this call completes its steps
+    const int check_synced = c->check_synced;
+    c->check_synced = -1;
     // excitation norms per step of this call (instability detector)
     std::vector<double> nV((size_t)nt * B), nI((size_t)nt, 0.0);
     {
@@ -861,6 +995,24 @@ int march_impl(etaim_ctx* c, const zd* V, zd* I, etaim_stats* st, bool adjoint, 
     const bool eager_detect = (c->prm.flags & ETAIM_F_FAIL_ON_UNSTABLE) != 0;
     double* nrm_all = nullptr;
     CHK(c->alloc(nrm_all, (size_t)nt * B));
+    // FP64 residual check of eq. (5) (forward marches with ETAIM_F_RESIDUAL_CHECK)
+    const bool checking = !adjoint && (c->prm.flags & ETAIM_F_RESIDUAL_CHECK) != 0;
+    const int ccols = c->prec == ETAIM_FP64 ? B : 1;
+    std::vector<int> chk_steps;
+    double* chk = nullptr;
+    if (checking) {
+        for (int r = first; r < first + nt; ++r)
+            if ((r + 1) % kCheckEvery == 0 || r == first + nt - 1) chk_steps.push_back(r);
+        CHK(c->alloc(chk, 2 * (size_t)ccols * chk_steps.size()));
+        if (c->prec != ETAIM_FP64) {
+            CHK(checker_create(c));
+            // the companion's history: kept when this call continues the march
+            // it follows, else the monitored column of the steps before `first`,
+            // read from I_out at the first check
+            if (first == 0 || check_synced != first) CHK(checker_reset(c, first - c->st.ng));
+        }
+    }
+    size_t nchk = 0;
     const int W = 32;
     auto detect = [&](int r) {
         // late-time growth: monotone growth by > 10x over W steps that follow
@@ -922,6 +1074,10 @@ int march_impl(etaim_ctx* c, const zd* V, zd* I, etaim_stats* st, bool adjoint, 
         if (r > first) CHK(phase_ms(r - 1));
         HIPCHK(hipEventRecord(ev[2], c->stream));
         HIPCHK(hipMemcpyAsync(Il, c->xk, nB * sizeof(zd), hipMemcpyDeviceToDevice, c->stream));
+        if (checking && nchk < chk_steps.size() && chk_steps[nchk] == r) {
+            CHK(check_step<R>(c, r, Vl, I, Il, chk + 2 * (size_t)ccols * nchk));
+            ++nchk;
+        }
         CHK(Ops<R>::commit(c, r, c->xk));
         hipLaunchKernelGGL(k_norm, dim3(B), dim3(kRedThreads), 0, c->stream, c->xk, nrm_all + (size_t)i * B, ns, nullptr);
         const int pmax = std::min(r, c->guess_order);
@@ -979,6 +1135,26 @@ int march_impl(etaim_ctx* c, const zd* V, zd* I, etaim_stats* st, bool adjoint, 
     if (it != c->allocs.end()) c->allocs.erase(it);
     c->dev_bytes -= (int64_t)((size_t)nt * B * sizeof(double));
     HIPCHK(hipFree(nrm_all));
+    int n_checks = 0, worst_step = -1;
+    double worst = 0;
+    if (chk) {
+        std::vector<double> cn(2 * (size_t)ccols * nchk);
+        if (nchk > 0) HIPCHK(hipMemcpy(cn.data(), chk, cn.size() * sizeof(double), hipMemcpyDeviceToHost));
+        for (size_t q = 0; q < nchk; ++q)
+            for (int b = 0; b < ccols; ++b) {
+                const double rn = cn[2 * ccols * q + b], bn = cn[2 * ccols * q + ccols + b];
+                const double e = bn > 0 ? rn / bn : (rn > 0 ? INFINITY : 0.0);  // k_norm gives 2-norms
+                if (worst_step < 0 || !(e <= worst)) {  // a NaN residual counts as the worst
+                    worst = e;
+                    worst_step = chk_steps[q];
+                }
+            }
+        n_checks = (int)nchk;
+        it = std::find(c->allocs.begin(), c->allocs.end(), (void*)chk);
+        if (it != c->allocs.end()) c->allocs.erase(it);
+        c->dev_bytes -= (int64_t)(2 * (size_t)ccols * chk_steps.size() * sizeof(double));
+        HIPCHK(hipFree(chk));
+    }
     if (st) {
         st->steps_done = steps;
         st->total_iters = tot_iters;
@@ -990,8 +1166,12 @@ int march_impl(etaim_ctx* c, const zd* V, zd* I, etaim_stats* st, bool adjoint, 
         st->ms_commit = ms_commit;
         st->ms_total = ms_rhs + ms_solve + ms_commit;
         st->max_rel_residual = maxres;
+        st->residual_checks = n_checks;
+        st->residual_worst_step = worst_step;
+        st->max_residual64 = worst;
     }
     if (!adjoint && steps == nt && !nonfinite) {
+        if (checking && c->check) c->check_synced = first + steps;
         c->next_step = first + steps;
         c->guess_p_next = guess_p;
         c->guess_dev_next = guess_dev;
@@ -1072,7 +1252,8 @@ int make_working(etaim_ctx* c) {
         HIPCHK(hipMemsetAsync(c->Q, 0, 4 * nB * c->N3 * sizeof(cplx<R>), c->stream));
     }
     CHK(c->allocv(c->xs, nB * (size_t)c->ns * sizeof(cplx<R>)));
-    CHK(c->allocv(c->ring, (size_t)c->st.ng * 4 * nB * c->Np * sizeof(cplx<R>)));
+    const size_t ring_cols = c->ring_cols > 0 ? (size_t)c->ring_cols : nB;
+    CHK(c->allocv(c->ring, (size_t)c->st.ng * 4 * ring_cols * c->Np * sizeof(cplx<R>)));
     // plane kernels: LDS and per-thread register staging limits
     const size_t lds = Ops<R>::plane_lds(c);
     if (lds > 160 * 1024 || Ops<R>::gather_lds(c) > 160 * 1024 || !plane_fits(c->gd.N[2], c->ry) ||
@@ -1196,13 +1377,15 @@ int device_setup(etaim_ctx* c) {
                            c->near64, c->nearT64, tp, c->nnz, c->mv);
         HIPCHK(hipGetLastError());
         // sparse approximate inverse of Z0 on the near pattern, and M^T's values for M^H
-        std::vector<zd> Mv;
-        sparse_approximate_inverse(s, ns, Mv);
-        CHK(c->upload(c->sai, Mv));
-        CHK(c->alloc(c->saiT, (size_t)c->nnz));
-        hipLaunchKernelGGL(k_permute_rows, dim3(blocks_for((size_t)c->nnz)), dim3(256), 0, c->stream, c->sai,
-                           c->saiT, tp, c->nnz, 1);
-        HIPCHK(hipGetLastError());
+        if (!c->no_solver) {
+            std::vector<zd> Mv;
+            sparse_approximate_inverse(s, ns, Mv);
+            CHK(c->upload(c->sai, Mv));
+            CHK(c->alloc(c->saiT, (size_t)c->nnz));
+            hipLaunchKernelGGL(k_permute_rows, dim3(blocks_for((size_t)c->nnz)), dim3(256), 0, c->stream, c->sai,
+                               c->saiT, tp, c->nnz, 1);
+            HIPCHK(hipGetLastError());
+        }
         HIPCHK(hipStreamSynchronize(c->stream));
         auto it = std::find(c->allocs.begin(), c->allocs.end(), (void*)tp);
         c->allocs.erase(it);
@@ -1464,6 +1647,7 @@ int etaim_delayed_field(etaim_ctx* c, const void* hist, void* b) {
         HIPCHK(hipMemsetAsync(c->ring, 0, (size_t)ng * 4 * c->B * c->Np * sizeof(cplx<R>), c->stream));
         c->far_r0 = -1;
         c->next_step = -1;  // the rings now hold the injected history
+        c->check_synced = -1;
         if (c->st.mn >= 1) HIPCHK(hipMemsetAsync(c->hist, 0, (size_t)c->st.mn * nB * sizeof(zd), c->stream));
         for (int m = ng; m >= 1; --m) CHK(Ops<R>::commit(c, ng - m, (const zd*)hist + (size_t)(m - 1) * nB));
         CHK(Ops<R>::delayed(c, ng, c->zero, (zd*)b, 0));
@@ -1577,6 +1761,7 @@ int etaim_state_load(etaim_ctx* c, const void* host, size_t bytes) {
     c->guess_dev_next = h.guess_dev != 0 && c->guess_order >= 2;
     c->far_r0 = -1;  // block sums are recomputed from the loaded ring
     c->iter_hint = 0;
+    c->check_synced = -1;  // the residual check's FP64 history is rebuilt from I_out
     return ETAIM_OK;
 }
 

@@ -1,0 +1,101 @@
+"""The FP64 residual check of eq. (5) (ETAIM_F_RESIDUAL_CHECK): every 16
+steps and at the last step of a call the march reports
+||V_l - sum_{m>=0} Z_m I_{l-m}|| / ||V_l - sum_{m>=1} Z_m I_{l-m}|| in FP64,
+for every column of an FP64 march and for column 0 of an FP32 one (whose
+FP64 history an internal FP64 context keeps).  The worst value and its step
+must equal the oracle's FP64 residual of the march's own currents, computed
+with the assembled AIM matrices (level-2 sphere), also when the march is
+split and continued (the FP64 history is rebuilt from the earlier steps)."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_cases import gpu_problem, oracle_aim, oracle_dense_aim
+
+pytestmark = pytest.mark.gpu
+
+L2 = W.SPHERE_L2.name
+F_CONTINUE_ON_NOCONV, F_RESIDUAL_CHECK = 1, 16
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+def _oracle_residuals(V, I, steps, cols):
+    """{(l, b): FP64 relative residual of eq. (5)} from the dense Z_m."""
+    Z = oracle_dense_aim(L2)
+    ng = len(Z) - 1
+    out = {}
+    for l in steps:
+        for b in cols:
+            rhs = V[l, b] - sum(Z[m] @ I[l - m, b] for m in range(1, min(ng, l) + 1))
+            r = rhs - Z[0] @ I[l, b]
+            out[(l, b)] = float(np.linalg.norm(r) / np.linalg.norm(rhs))
+    return out
+
+
+def _excitation(nt, nb):
+    from oracle import excitation
+    wl = W.SPHERE_L2
+    s, A, vals, p = oracle_aim(L2)
+    kh = W.unit_vectors(71, 2, nb)
+    pp = W.polarisations(71, kh)
+    return excitation.excitation(s, nt, p["dt"], kh, pp, wl.sigma, 10 * p["dt"], wl.f0)
+
+
+@pytest.mark.parametrize("prec,tol", [(1, 1e-6), (0, 1e-9)], ids=["fp32", "fp64"])
+def test_residual_check_equals_the_oracle(torch, prec, tol):
+    nt, nb = 40, 2
+    V = _excitation(nt, nb)
+    Vd = torch.from_numpy(np.ascontiguousarray(V)).cuda()
+    P = gpu_problem(L2, precision=prec, nt=nt, batch=nb, tol=tol, flags=F_CONTINUE_ON_NOCONV | F_RESIDUAL_CHECK)
+    I, st = P.march(Vd)
+    I = I.cpu().numpy()
+    cols = [0] if prec == 1 else list(range(nb))
+    ref = _oracle_residuals(V, I, (15, 31, 39), cols)
+    (l, b), worst = max(ref.items(), key=lambda kv: kv[1])
+    _say("residual check", "fp32" if prec else "fp64", "library", st["max_residual64"], "step",
+         st["residual_worst_step"], "oracle", worst, "step", l, "all", ref)
+    assert st["residual_checks"] == 3
+    assert st["residual_worst_step"] == l
+    assert st["max_residual64"] == pytest.approx(worst, rel=1e-6)
+    assert worst <= (1e-4 if prec else 1e-8)
+    # split at step 20: the continued call checks steps 31 and 39 (the FP64
+    # history continues), and so does a fresh context that loads the state
+    # (its FP64 history is rebuilt from the earlier steps of I)
+    I1, st1 = P.march(Vd, nsteps=20)
+    state = P.save_state()
+    I2 = I1.clone()
+    I1, st2 = P.march_continue(Vd, I1, 20, nt - 20)
+    assert (st1["residual_checks"], st2["residual_checks"]) == (2, 2)
+    ref2 = _oracle_residuals(V, I1.cpu().numpy(), (31, 39), cols)
+    (l2, _), worst2 = max(ref2.items(), key=lambda kv: kv[1])
+    assert st2["residual_worst_step"] == l2
+    assert st2["max_residual64"] == pytest.approx(worst2, rel=1e-6)
+    P.close()
+    Q = gpu_problem(L2, precision=prec, nt=nt, batch=nb, tol=tol, flags=F_CONTINUE_ON_NOCONV | F_RESIDUAL_CHECK)
+    Q.load_state(state)
+    I2, st3 = Q.march_continue(Vd, I2, 20, nt - 20)
+    np.testing.assert_array_equal(I2.cpu().numpy(), I1.cpu().numpy())
+    assert (st3["residual_worst_step"], st3["max_residual64"]) == (st2["residual_worst_step"], st2["max_residual64"])
+    Q.close()
+
+
+def test_no_check_without_the_flag(torch):
+    V = _excitation(20, 1)
+    P = gpu_problem(L2, precision=1, nt=20, batch=1, tol=1e-6, flags=F_CONTINUE_ON_NOCONV)
+    _, st = P.march(torch.from_numpy(np.ascontiguousarray(V)).cuda())
+    assert (st["residual_checks"], st["residual_worst_step"], st["max_residual64"]) == (0, -1, 0.0)
+    P.close()
