@@ -213,6 +213,8 @@ def main():
                     help="Arnoldi steps enqueued per host convergence check")
     ap.add_argument("--graph", action="store_true",
                     help="also time the window with Arnoldi steps replayed from HIP graphs (profiling off)")
+    ap.add_argument("--no-step-graph", action="store_true",
+                    help="skip timing the window with whole time steps replayed from HIP graphs")
     ap.add_argument("--tune-ms", type=int, default=4000,
                     help="autotuner budget before timing (0: keep the library's default shapes)")
     ap.add_argument("--true-residual", action="store_true",
@@ -355,6 +357,29 @@ def main():
         log(f"[bench] graph replay: {K / wg:.2f} steps/s")
         Pg.close()
         del Ig
+    if not args.no_step_graph:
+        # the same window with every step replayed from a captured whole-step graph
+        # (delayed field, device-gated GMRES cycle, commit; several steps per host check)
+        Ps = make_problem(wl, FP32, wl.batch, nt, 1e-5, flags=fl, sync_every=args.sync_every)
+        if tuning:
+            Ps.set_tuning(dict(tuning, graph=2))
+        else:
+            Ps.set_tuning(dict(Ps.tuning(), graph=2))
+        Is = Ps.empty(nt, wl.batch, Ps.ns)
+        Ps.march(V, out=Is, nsteps=first)
+        torch.cuda.synchronize()
+        g0 = time.perf_counter()
+        _, sts = Ps.march_continue(V, Is, first, K)
+        torch.cuda.synchronize()
+        wsg = time.perf_counter() - g0
+        out["step_graph"] = {"time_steps_per_s": round(K / wsg, 4), "ms_per_step": round(1e3 * wsg / K, 3),
+                             "gmres_iters_per_step": round(sts["total_iters"] / K, 2),
+                             "replayed_steps": sts["graph_steps"], "halts": sts["graph_halts"],
+                             "bit_identical_to_eager": bool(np.array_equal(Is[:, 0].cpu().numpy(), I32_0))}
+        log(f"[bench] whole-step graphs: {K / wsg:.2f} steps/s ({sts['graph_steps']} replayed, "
+            f"{sts['graph_halts']} halts)")
+        Ps.close()
+        del Is
     del V
     torch.cuda.empty_cache()
     win = slice(first, nt)

@@ -65,6 +65,17 @@ extern "C" {
                                         recomputes the true residual b - Z x at a new cycle start
                                         and stops only if that meets the tolerance too (one operator
                                         application more per step) */
+#define ETAIM_F_STEP_GRAPH 32        /* replay every time step of a forward march (from its fourth step
+                                        and from the second step of a call on) from captured HIP graphs:
+                                        delayed field, one GMRES cycle of device-gated Arnoldi steps,
+                                        commit and bookkeeping in one graph, its per-step values read
+                                        from device descriptors; several steps are enqueued per host
+                                        check.  A step that has not converged within the captured
+                                        Arnoldi steps stops the replays on the device and is completed
+                                        eagerly.  Needs ETAIM_F_IMPLICIT_STOP and the register engines;
+                                        otherwise, while profiling, for the adjoint march and with
+                                        ETAIM_F_FAIL_ON_UNSTABLE the steps run eagerly.  Results equal
+                                        the eager march bit for bit. */
 #define ETAIM_F_RESIDUAL_CHECK 16    /* forward marches check eq. (5) in FP64 every 16 steps (step l
                                         with (l + 1) % 16 == 0) and at the last step of the call:
                                         ||V_l - sum_{m>=0} Z_m I_{l-m}|| / ||V_l - sum_{m>=1} Z_m I_{l-m}||
@@ -139,6 +150,9 @@ typedef struct {
     int32_t residual_checks;     /* FP64 checks of eq. (5) made (ETAIM_F_RESIDUAL_CHECK), else 0 */
     int32_t residual_worst_step; /* step of the largest checked residual (-1: none) */
     double max_residual64;       /* largest FP64 relative residual of eq. (5) over the checks */
+    int32_t graph_steps;         /* steps replayed from whole-step graphs (ETAIM_F_STEP_GRAPH) */
+    int32_t graph_halts;         /* replayed steps that did not converge within their graph's
+                                    Arnoldi steps and were completed eagerly */
 } etaim_stats;
 
 /* Context set-up (the paper's "matrix fill", Sec. 4 stages (i)-(iv), not
@@ -309,7 +323,8 @@ typedef struct {
     int32_t lines_per_block; /* lines per block of the inverse x pass (>= 1) */
     int32_t interp_waves;    /* bases (one wavefront each) per interpolation block, 1..4 */
     int32_t sync_every;      /* Arnoldi steps per host convergence check, 1..restart */
-    int32_t graph;           /* 1: replay captured Arnoldi steps (ETAIM_F_GRAPH) */
+    int32_t graph;           /* 1: replay captured Arnoldi steps (ETAIM_F_GRAPH); 2: replay whole
+                                time steps of forward marches (ETAIM_F_STEP_GRAPH) */
     int32_t yz_engine;       /* y/z plane stage: 0 LDS-staged radix passes over the whole padded
                                 plane, 1 register-resident parity quadrants (needs N_y = N_z in
                                 {16, 24, 48}), 2 as 1 but the matvec and commit plane transforms take

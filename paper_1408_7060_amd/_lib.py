@@ -10,7 +10,7 @@ LIB_PATH = os.path.join(HERE, "libetaim.so")
 
 OK, EINVAL, ENOMEM, EHIP, ENOCONV, ENONFINITE, EUNSTABLE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
 FP64, FP32 = 0, 1
-F_CONTINUE_ON_NOCONV, F_FAIL_ON_UNSTABLE, F_GRAPH, F_IMPLICIT_STOP, F_RESIDUAL_CHECK = 1, 2, 4, 8, 16
+F_CONTINUE_ON_NOCONV, F_FAIL_ON_UNSTABLE, F_GRAPH, F_IMPLICIT_STOP, F_RESIDUAL_CHECK, F_STEP_GRAPH = 1, 2, 4, 8, 16, 32
 KERNEL_CLASSES = ["anterp_x", "yz_green", "fft_x_inv", "interp_near", "yz_delayed", "yz_commit", "krylov",
                   "ring_far"]
 
@@ -42,7 +42,8 @@ class Stats(ctypes.Structure):
                 ("first_noconv_step", c_int32), ("unstable_step", c_int32), ("ms_rhs", c_double),
                 ("ms_solve", c_double), ("ms_commit", c_double), ("ms_total", c_double),
                 ("max_rel_residual", c_double), ("iters_per_step", POINTER(c_int32)),
-                ("residual_checks", c_int32), ("residual_worst_step", c_int32), ("max_residual64", c_double)]
+                ("residual_checks", c_int32), ("residual_worst_step", c_int32), ("max_residual64", c_double),
+                ("graph_steps", c_int32), ("graph_halts", c_int32)]
 
 
 class Tuning(ctypes.Structure):

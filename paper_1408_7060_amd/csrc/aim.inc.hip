@@ -624,7 +624,11 @@ __global__ void __launch_bounds__(4 * N) __attribute__((amdgpu_waves_per_eu(size
 template <typename R, int N>
 __global__ void __launch_bounds__(4 * N) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 3 : 1)))
 k_yzc_commit(const cplx<R>* __restrict__ A, cplx<R>* __restrict__ slot, const cplx<R>* __restrict__ twy,
-             const cplx<R>* __restrict__ twz, GridDims g) {
+             const cplx<R>* __restrict__ twz, GridDims g, StepRef sr, int ng) {
+    if (step_off(sr)) return;
+    // replayed: slot is the ring's base and the step picks its slot
+    if (const StepDesc* d = step_of(sr))
+        slot += (size_t)(d->cur % ng) * (4 * (size_t)g.B * g.L[0] * 4 * N * N);
     extern __shared__ unsigned char smem_raw[];
     cplx<R>* t0 = reinterpret_cast<cplx<R>*>(smem_raw);
     constexpr int NN = N * N;
@@ -749,10 +753,17 @@ __global__ void __launch_bounds__(kDelayThreads) k_yzq_delayed(const cplx<R>* __
                                                               const cplx<R>* __restrict__ twy,
                                                               const cplx<R>* __restrict__ twz, GridDims g, int ng,
                                                               int cur, int nm, int conj_g,
-                                                              const cplx<R>* __restrict__ Fj) {
+                                                              const cplx<R>* __restrict__ Fj, StepRef sr) {
+    if (step_off(sr)) return;
     extern __shared__ unsigned char smem_raw[];
     cplx<R>* t0 = reinterpret_cast<cplx<R>*>(smem_raw);
     constexpr int NN = N * N, PAIRS = 4 * NN / 2, PER = 6, CHUNK = PER * kDelayThreads, TS = 4 * N * (N + 1);
+    if (const StepDesc* d = step_of(sr)) {
+        // Fj is the base of the block sums here: slot fj of this step, if any
+        cur = d->cur;
+        nm = d->nm;
+        Fj = d->fj >= 0 ? Fj + (size_t)d->fj * (4 * (size_t)g.B * g.L[0] * 4 * NN) : nullptr;
+    }
     // plane pair p: bc0 = 8 (p / 4) + p % 4 and bc0 + 4 (the same component c)
     const int p = blockIdx.x, bc0 = 8 * (p >> 2) + (p & 3);
     const int kx = blockIdx.y, Lx = g.L[0];
@@ -840,12 +851,18 @@ __global__ void __launch_bounds__(kDelay1Threads) k_yzq_delayed1(const cplx<R>* 
                                                               const cplx<R>* __restrict__ twy,
                                                               const cplx<R>* __restrict__ twz, GridDims g, int ng,
                                                               int cur, int nm, int conj_g,
-                                                              const cplx<R>* __restrict__ Fj) {
+                                                              const cplx<R>* __restrict__ Fj, StepRef sr) {
+    if (step_off(sr)) return;
     extern __shared__ unsigned char smem_raw[];
     cplx<R>* t0 = reinterpret_cast<cplx<R>*>(smem_raw);
     // the plane's 4 N^2 points as pairs; the sum runs in chunks of PER pairs
     // per thread so that the accumulators stay within half the VGPR file
     constexpr int NN = N * N, PAIRS = 4 * NN / 2, PER = 9, CHUNK = PER * kDelay1Threads;
+    if (const StepDesc* d = step_of(sr)) {
+        cur = d->cur;
+        nm = d->nm;
+        Fj = d->fj >= 0 ? Fj + (size_t)d->fj * (4 * (size_t)g.B * g.L[0] * 4 * NN) : nullptr;
+    }
     const int bc = blockIdx.x, kx = blockIdx.y, Lx = g.L[0];
     const int gx = g.N[0] + 1, gg = N + 1;
     const size_t gsz = (size_t)2 * gx * gg * gg;
@@ -939,7 +956,9 @@ struct Vec16<double> {
 template <typename R, int N, int NGX>
 __global__ void __launch_bounds__(256) k_ring_far(const cplx<R>* __restrict__ ring, const cplx<R>* __restrict__ G,
                                                   cplx<R>* __restrict__ F, GridDims g, int ng, int r0, int pb,
-                                                  int conj_g) {
+                                                  int conj_g, StepRef sr) {
+    if (step_off(sr)) return;
+    if (const StepDesc* d = step_of(sr)) r0 = d->r0;
     using V = typename Vec16<R>::type;
     constexpr int P = Vec16<R>::P, NN = N * N, PP = 4 * NN;
     const int Lx = g.L[0];
@@ -1045,8 +1064,14 @@ __global__ void __launch_bounds__(256) k_interp_near(
     const int* __restrict__ rowptr, const int* __restrict__ col, const cplx<R>* __restrict__ val, int mv,
     const cplx<R>* __restrict__ xr, int m, const cplx<R>* __restrict__ hist, int mn, int cur,
     int nmh, const zd* __restrict__ V, zd* __restrict__ y, int ns, int mode, int conj_v,
-    const int* __restrict__ gate) {
-    if (gated_off(gate)) return;
+    const int* __restrict__ gate, StepRef sr = {}) {
+    if (gated_off(gate) || step_off(sr)) return;
+    if (const StepDesc* d = step_of(sr)) {
+        // replayed delayed field: this step's excitation from the call's array
+        cur = d->cur;
+        nmh = d->nmh;
+        V = d->V + (size_t)d->cur * g.B * ns;
+    }
     const int lane = threadIdx.x & 63;
     // consecutive blocks land on different XCDs (round-robin dispatch), so
     // give each XCD one contiguous run of the Morton-ordered bases: its L2

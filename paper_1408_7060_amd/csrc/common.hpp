@@ -18,6 +18,7 @@ constexpr int kXcds = 8;
 // step that are launched ahead of the host's convergence check (or replayed
 // from a captured graph) return at once when the step is not live.
 __device__ __forceinline__ bool gated_off(const int* gate) { return gate != nullptr && *gate == 0; }
+
 constexpr double kMu0 = 4.0e-7 * kPi;
 // eps0 = 1/(mu0 c^2), evaluated at run time to keep one definition
 __host__ __device__ inline double eps0() { return 1.0 / (kMu0 * kC0 * kC0); }
@@ -29,6 +30,36 @@ struct cplx {
 };
 using zd = cplx<double>;
 using zf = cplx<float>;
+
+// Per-step values of a forward march replayed from a captured whole-step
+// graph.  The host writes one descriptor per step before the replays; the
+// graph's kernels read sd[*ctr], and its last kernel advances *ctr.  *live
+// drops to 0 when a step does not converge within the graph's Arnoldi
+// steps: every later node of the graph (and of the steps enqueued after
+// it) then returns at once, and the host completes that step eagerly.
+struct StepDesc {
+    int cur;   // the step (index of V and I)
+    int i;     // the step's index within the march call
+    int r0;    // first step of its time block
+    int nm;    // history terms of the per-step delayed sum
+    int fj;    // block-sum slot of the step (-1: none)
+    int nmh;   // near-history terms, min(M_n, cur)
+    int p;     // extrapolation order cap of the initial guess
+    int pdev;  // 1: the order is the one chosen on the device (pnext)
+    int pmax;  // extrapolation orders compared after the step
+    int pad;
+    // the call's arrays: excitation and solutions [N_t][B][ns], current norms [steps][B]
+    const cplx<double>* V;
+    cplx<double>* I;
+    double* nrm;
+};
+struct StepRef {
+    const StepDesc* sd = nullptr;  // nullptr: an eager launch (values from the arguments)
+    const int* ctr = nullptr;
+    const int* live = nullptr;
+};
+__device__ __forceinline__ const StepDesc* step_of(StepRef s) { return s.sd ? s.sd + *s.ctr : nullptr; }
+__device__ __forceinline__ bool step_off(StepRef s) { return s.live != nullptr && *s.live == 0; }
 
 template <typename R>
 __host__ __device__ inline cplx<R> mk(R a, R b) { return cplx<R>{a, b}; }

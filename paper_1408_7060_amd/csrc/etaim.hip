@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -115,6 +116,16 @@ struct etaim_ctx {
     int check_synced = -1;   // the step at which the companion's history continues this context's march
     hipStream_t cap_stream = nullptr;
     std::vector<hipGraphExec_t> graphs[2];  // [conj][j]
+    // whole-step graphs of the forward march (ETAIM_F_STEP_GRAPH): device step
+    // descriptors of the current call, {descriptor index, live}, per-step
+    // Arnoldi steps and residual estimates, pinned readback; graphs by variant
+    bool step_graph = false;
+    StepDesc* sdesc = nullptr;
+    int* sctl = nullptr;
+    int* siters = nullptr;
+    double* sres = nullptr;
+    int* sctl_h = nullptr;
+    std::map<int, hipGraphExec_t> step_graphs;
     // launch shapes (0 = automatic); the autotuner sets them
     int gather_rows_t = 0, lines_x_t = 0, interp_waves = 4;
     int yz_engine = 0;  // 0: LDS plane kernels, 1: register quadrant kernels, 2: as 1 with z-lines-first matvec and commit
@@ -122,6 +133,7 @@ struct etaim_ctx {
     int x_engine = 0;   // 0: LDS line kernels, 1: register line kernels
     void* xs = nullptr; // [ns][B] scaled columns for the register anterpolation
     hipEvent_t ev[8] = {};  // march phase events, two sets (steps alternate)
+    hipEvent_t evg[2] = {}; // around a run of replayed whole-step graphs
     // FP64 residual check of an FP32 march (ETAIM_F_RESIDUAL_CHECK): an FP64
     // context of the same problem for the monitored column 0, on this stream
     etaim_ctx* check = nullptr;
@@ -165,12 +177,16 @@ struct etaim_ctx {
         delete check;
         for (auto& e : ev)
             if (e) (void)hipEventDestroy(e);
+        for (auto& e : evg)
+            if (e) (void)hipEventDestroy(e);
         for (auto& e : pool) (void)hipEventDestroy(e);
         if (flag_h) (void)hipHostFree(flag_h);
         if (res_h) (void)hipHostFree(res_h);
         for (auto& v : graphs)
             for (auto& x : v)
                 if (x) (void)hipGraphExecDestroy(x);
+        for (auto& kv : step_graphs) (void)hipGraphExecDestroy(kv.second);
+        if (sctl_h) (void)hipHostFree(sctl_h);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         for (void* p : allocs) (void)hipFree(p);
     }
@@ -418,7 +434,8 @@ struct Ops {
         return ETAIM_OK;
     }
     static int interp_near(etaim_ctx* c, int mode, const zd* x, const zd* dinv, int m, int cur, int nmh,
-                           const zd* V, zd* y, int conj_v, int conj_x, const int* gate = nullptr) {
+                           const zd* V, zd* y, int conj_v, int conj_x, const int* gate = nullptr,
+                           StepRef sr = {}) {
         // whole multiple of the XCD count: the kernel's block -> basis map is a bijection
         const int wpb = c->interp_waves;
         dim3 grid(((c->ns + wpb - 1) / wpb + kXcds - 1) / kXcds * kXcds);
@@ -436,7 +453,7 @@ struct Ops {
         hipLaunchKernelGGL(k_interp_near<R>, grid, dim3(64 * wpb), 0, c->stream, (const cplx<R>*)P(c),
                            (const R*)c->lam_r, c->i0, c->korder, c->gd, c->rowptr, c->col, nearv(c, conj_v), c->mv,
                            (const cplx<R>*)xs, m, (const cplx<R>*)c->hist, std::max(c->st.mn, 1), cur, nmh, V, y,
-                           c->ns, mode, conj_v, gate);
+                           c->ns, mode, conj_v, gate, sr);
         HIPCHK(hipGetLastError());
         return ETAIM_OK;
     }
@@ -449,18 +466,26 @@ struct Ops {
         CHK(inverse_x(c, gate));
         return interp_near(c, 0, x, dinv, m, 0, 0, nullptr, y, conj, 0, gate);
     }
-    // rhs = V - sum_{m>=1} conj?(Z_m) I_{cur-m} from the rings (cur >= 1)
-    static int delayed(etaim_ctx* c, int cur, const zd* V, zd* rhs, int conj) {
+    // rhs = V - sum_{m>=1} conj?(Z_m) I_{cur-m} from the rings (cur >= 1).
+    // Captured into a whole-step graph (sr.sd set) the step's values come from
+    // its descriptor; graph_far then says whether the time-block pass runs.
+    static bool blocks_on(const etaim_ctx* c) {
+        return c->yz_engine >= 1 && c->delay_block > 1 && c->st.ng <= kFarMaxNg && c->delay_block <= kFarMaxBlock;
+    }
+    static int delayed(etaim_ctx* c, int cur, const zd* V, zd* rhs, int conj, StepRef sr = {}, int graph_far = 0) {
         const GridDims& g = c->gd;
         const int nm = std::min(c->st.ng, cur);
         const int ng = c->st.ng;
+        const bool graph = sr.sd != nullptr;
         // time blocks (register engine): at step r0 + j the terms that read history
         // older than r0 (m > j) are summed for the whole block at its first step, the
         // j terms of the block's own steps at the step itself
         const int pb = c->delay_block;
-        const bool blocked = c->yz_engine >= 1 && cur >= 1 && pb > 1 && ng <= kFarMaxNg && pb <= kFarMaxBlock;
+        const bool blocked = blocks_on(c) && cur >= 1;
         const int r0 = blocked ? cur - (cur - 1) % pb : 0;
-        const bool far_pass = blocked && c->far_r0 != r0;
+        const bool far_pass = graph ? (blocked && graph_far != 0) : (blocked && c->far_r0 != r0);
+        if (graph && blocked && (!c->far || c->far_slots < pb))
+            return fail(ETAIM_EUNSUPPORTED, "whole-step graph: the time-block sums are not allocated");
         const int nmx = blocked ? std::min(cur - r0, ng) : nm;
         {
             const double s = sizeof(cplx<R>), slot_b = 4.0 * c->B * c->Np * s, green_b = 2.0 * c->gfold * s;
@@ -470,7 +495,7 @@ struct Ops {
                 const size_t slot = (size_t)4 * c->B * c->Np;
                 const cplx<R>* Fj = nullptr;
                 if (blocked) {
-                    if (c->far_slots < pb) {
+                    if (c->far_slots < pb && !graph) {
                         if (c->far) {
                             auto it = std::find(c->allocs.begin(), c->allocs.end(), c->far);
                             if (it != c->allocs.end()) c->allocs.erase(it);
@@ -489,7 +514,7 @@ struct Ops {
                         const dim3 gf((unsigned)((pts + 255) / 256));
                         cplx<R>* F = (cplx<R>*)c->far;
                         const cplx<R>* rg = (const cplx<R>*)ring(c);
-#define ETAIM_FAR(NN, NG) launch_timed(tf, k_ring_far<R, NN, NG>, gf, dim3(256), 0, c->stream, rg, ghat(c), F, g, ng, r0, pb, conj)
+#define ETAIM_FAR(NN, NG) launch_timed(tf, k_ring_far<R, NN, NG>, gf, dim3(256), 0, c->stream, rg, ghat(c), F, g, ng, r0, pb, conj, sr)
 #define ETAIM_FAR_NG(NN) \
     if (ng <= 16) ETAIM_FAR(NN, 16); else if (ng <= 24) ETAIM_FAR(NN, 24); else ETAIM_FAR(NN, 32);
                         switch (quad_n(c)) {
@@ -501,9 +526,10 @@ struct Ops {
 #undef ETAIM_FAR_NG
 #undef ETAIM_FAR
                         HIPCHK(hipGetLastError());
-                        c->far_r0 = r0;
+                        if (!graph) c->far_r0 = r0;
                     }
-                    Fj = (const cplx<R>*)c->far + (size_t)(cur - r0) * slot;
+                    // replayed: the kernel takes the block sums' base and the step's slot
+                    Fj = (const cplx<R>*)c->far + (graph ? 0 : (size_t)(cur - r0) * slot);
                 }
                 Trace t(c, ETAIM_K_YZ_DELAYED, bytes, true);
                 // plane pairs (bc, bc + 4) sharing the Green loads where the batch is even and two
@@ -516,10 +542,10 @@ struct Ops {
 #define ETAIM_DELAYED(NN)                                                                                     \
     if (pair)                                                                                                  \
         launch_timed(t, k_yzq_delayed<R, NN>, grid, blk, lds, c->stream, rg, ghat(c), A(c), tw(c, 1), tw(c, 2), \
-                     g, ng, cur, nmx, conj, Fj);                                                               \
+                     g, ng, cur, nmx, conj, Fj, sr);                                                           \
     else                                                                                                       \
         launch_timed(t, k_yzq_delayed1<R, NN>, grid, blk, lds, c->stream, rg, ghat(c), A(c), tw(c, 1),         \
-                     tw(c, 2), g, ng, cur, nmx, conj, Fj);
+                     tw(c, 2), g, ng, cur, nmx, conj, Fj, sr);
                 switch (quad_n(c)) {
                     case 16: ETAIM_DELAYED(16) break;
                     case 24: ETAIM_DELAYED(24) break;
@@ -528,6 +554,7 @@ struct Ops {
                 }
 #undef ETAIM_DELAYED
             } else {
+                if (graph) return fail(ETAIM_EUNSUPPORTED, "whole-step graph: needs the register plane kernels");
                 Trace t(c, ETAIM_K_YZ_DELAYED, bytes, true);
                 launch_timed(t, k_yz_delayed<R>, dim3(g.L[0], 4 * c->B), dim3(kPlaneThreads), plane_lds(c), c->stream,
                              (const cplx<R>*)ring(c), ghat(c), A(c), tw(c, 1), tw(c, 2), c->ry, c->rz, g, c->st.ng,
@@ -535,13 +562,24 @@ struct Ops {
             }
         }
         HIPCHK(hipGetLastError());
-        CHK(inverse_x(c));
+        CHK(inverse_x(c, sr.live));
         const int nmh = std::min(c->st.mn, cur);
-        return interp_near(c, 1, nullptr, nullptr, 0, cur, nmh, V, rhs, conj, 0);
+        return interp_near(c, 1, nullptr, nullptr, 0, cur, nmh, V, rhs, conj, 0, sr.live, sr);
     }
     // push the converged I_cur into the spectrum ring and the current ring
-    static int commit(etaim_ctx* c, int cur, const zd* x) {
+    static int commit(etaim_ctx* c, int cur, const zd* x, StepRef sr = {}) {
         const size_t slot_sz = (size_t)4 * c->B * c->Np;
+        if (sr.sd) {
+            // replayed: the commit kernel and the history store take the step from its descriptor
+            CHK(commit_slot(c, ring(c), x, sr));
+            if (c->st.mn >= 1) {
+                const size_t n = (size_t)c->B * c->ns;
+                hipLaunchKernelGGL(k_store_hist<R>, dim3(blocks_for(n)), dim3(256), 0, c->stream, x, (cplx<R>*)c->hist,
+                                   c->ns, c->B, c->st.mn, sr);
+                HIPCHK(hipGetLastError());
+            }
+            return ETAIM_OK;
+        }
         CHK(commit_slot(c, ring(c) + (size_t)(cur % c->st.ng) * slot_sz, x));
         if (c->st.mn >= 1) {
             const size_t n = (size_t)c->B * c->ns;
@@ -552,9 +590,12 @@ struct Ops {
         }
         return ETAIM_OK;
     }
-    // anterpolate + forward FFT of the B columns of x into the spectrum slot `slot`
-    static int commit_slot(etaim_ctx* c, cplx<R>* slot, const zd* x) {
-        CHK(forward_x(c, x, nullptr, 0));
+    // anterpolate + forward FFT of the B columns of x into the spectrum slot
+    // `slot` (replayed: the ring's base, the kernel picks the step's slot)
+    static int commit_slot(etaim_ctx* c, cplx<R>* slot, const zd* x, StepRef sr = {}) {
+        CHK(forward_x(c, x, nullptr, 0, sr.live));
+        if (sr.sd && c->yz_engine != 2)
+            return fail(ETAIM_EUNSUPPORTED, "whole-step graph: needs the z-lines-first plane kernels");
         const GridDims& g = c->gd;
         {
             const double s = sizeof(cplx<R>);
@@ -564,9 +605,9 @@ struct Ops {
                 const size_t lds = zline_lds(c);
                 const cplx<R>* a = (const cplx<R>*)A(c);
                 switch (quad_n(c)) {
-                    case 16: launch_timed(t, k_yzc_commit<R, 16>, grid, dim3(4 * 16), lds, c->stream, a, slot, tw(c, 1), tw(c, 2), g); break;
-                    case 24: launch_timed(t, k_yzc_commit<R, 24>, grid, dim3(4 * 24), lds, c->stream, a, slot, tw(c, 1), tw(c, 2), g); break;
-                    case 48: launch_timed(t, k_yzc_commit<R, 48>, grid, dim3(4 * 48), lds, c->stream, a, slot, tw(c, 1), tw(c, 2), g); break;
+                    case 16: launch_timed(t, k_yzc_commit<R, 16>, grid, dim3(4 * 16), lds, c->stream, a, slot, tw(c, 1), tw(c, 2), g, sr, c->st.ng); break;
+                    case 24: launch_timed(t, k_yzc_commit<R, 24>, grid, dim3(4 * 24), lds, c->stream, a, slot, tw(c, 1), tw(c, 2), g, sr, c->st.ng); break;
+                    case 48: launch_timed(t, k_yzc_commit<R, 48>, grid, dim3(4 * 48), lds, c->stream, a, slot, tw(c, 1), tw(c, 2), g, sr, c->st.ng); break;
                     default: return fail(ETAIM_EUNSUPPORTED, "register plane kernels need N_y = N_z in {16, 24, 48}");
                 }
             } else if (c->yz_engine == 1) {
@@ -622,13 +663,13 @@ struct StepResult {
 // live flag (k_gate), so steps can be enqueued ahead of the host's
 // convergence check or replayed from a captured graph.
 template <typename R>
-int arnoldi_step(etaim_ctx* c, int j, int conj, const int* gate) {
+int arnoldi_step(etaim_ctx* c, int j, int conj, const int* gate, const int* step_live = nullptr) {
     const int B = c->B, ns = c->ns, rs = c->prm.restart;
     const size_t nB = (size_t)B * ns;
     const zd* dinv = conj ? c->dinv_c : c->dinv;
     zd* vj = c->Vk + (size_t)j * nB;
     zd* vn = c->Vk + (size_t)(j + 1) * nB;
-    if (gate) hipLaunchKernelGGL(k_gate, dim3(1), dim3(64), 0, c->stream, c->flag);
+    if (gate) hipLaunchKernelGGL(k_gate, dim3(1), dim3(64), 0, c->stream, c->flag, step_live);
     if (c->precond == 1 && c->x_engine == 1) {
         // w = Z (M v_j), M the near-zone sparse approximate inverse (M^H for the
         // adjoint): v_j transposed to [ns][B], then M v_j straight into the
@@ -820,6 +861,112 @@ int gmres(etaim_ctx* c, const zd* rhs, zd* x, int conj, StepResult& res) {
     // start, or the Arnoldi estimate of the last step under ETAIM_F_IMPLICIT_STOP
     res.resid = 0;
     for (int b = 0; b < B; ++b) res.resid = std::max(res.resid, c->res_h[b]);
+    return ETAIM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Whole-step graphs (ETAIM_F_STEP_GRAPH).  One forward time step as a captured
+// graph: the delayed field (with or without the time-block pass: two
+// variants), the extrapolated initial guess, one GMRES cycle of J
+// device-gated Arnoldi steps ending on the residual estimate, the step
+// check, the store of the solution, the commit, the growth-detector norms,
+// the extrapolation-order selection (with or without: two variants) and the
+// step end.  Every per-step value comes from the descriptor sdesc[ctl[0]];
+// the step end advances ctl[0]; ctl[1] = 0 (set by the step check) makes
+// every later node return.
+constexpr int kStepChunk = 8;  // replayed steps enqueued per host check
+
+int step_graph_setup(etaim_ctx* c) {
+    if (c->sdesc) return ETAIM_OK;
+    const size_t n = (size_t)std::max(c->prm.nt_steps, 1);
+    CHK(c->alloc(c->sdesc, n));
+    CHK(c->alloc(c->sctl, 2));
+    CHK(c->alloc(c->siters, n));
+    CHK(c->alloc(c->sres, n));
+    HIPCHK(hipHostMalloc((void**)&c->sctl_h, 4 * sizeof(int), hipHostMallocDefault));
+    return ETAIM_OK;
+}
+
+template <typename R>
+int step_body(etaim_ctx* c, int J, int far, int pred) {
+    const StepRef sr{c->sdesc, c->sctl, c->sctl + 1};
+    const int* live = c->sctl + 1;
+    const int B = c->B, ns = c->ns, rs = c->prm.restart;
+    const size_t nB = (size_t)B * ns;
+    // rhs = V_l - sum_{m>=1} Z_m I_{l-m} (cur = 1 only selects the blocked kernels)
+    CHK(Ops<R>::delayed(c, 1, nullptr, c->rhs, 0, sr, far));
+    hipLaunchKernelGGL(k_extrap, dim3(blocks_for(nB)), dim3(256), 0, c->stream, (const zd*)nullptr, c->xk, nB, 0LL, 1,
+                       0, (const int*)c->pnext, sr);
+    // GMRES, one cycle (the first cycle of the gated eager solve)
+    hipLaunchKernelGGL(k_norm, dim3(B), dim3(kRedThreads), 0, c->stream, c->rhs, c->bnorm, ns, live, StepRef{});
+    CHK(Ops<R>::apply(c, 0, c->xk, nullptr, c->w, 0, live));
+    hipLaunchKernelGGL(k_residual, dim3(blocks_for(nB)), dim3(256), 0, c->stream, c->rhs, c->w, nB, live);
+    hipLaunchKernelGGL(k_norm, dim3(B), dim3(kRedThreads), 0, c->stream, c->w, c->beta, ns, live, StepRef{});
+    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, c->stream, c->flag, 4, 0, live);
+    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, c->stream, c->flag + 4, 1, c->prm.maxit, live);
+    hipLaunchKernelGGL(k_cycle_start, dim3(1), dim3(256), 0, c->stream, c->beta, c->bnorm, c->active, c->jcnt, c->g,
+                       c->resid, c->flag, B, c->ldg, c->prm.tol, live);
+    hipLaunchKernelGGL(k_scale, dim3(blocks_for(nB)), dim3(256), 0, c->stream, c->w, c->beta, c->Vk, ns, B, live);
+    for (int j = 0; j < J; ++j) CHK(arnoldi_step<R>(c, j, 0, c->flag + 2, live));
+    hipLaunchKernelGGL(k_backsolve, dim3((B + 63) / 64), dim3(64), 0, c->stream, c->H, c->g, c->jcnt, c->yv, B, rs,
+                       live);
+    if (c->precond == 1) {
+        hipLaunchKernelGGL(k_krylov_combine, dim3((ns + 255) / 256, B), dim3(256), 0, c->stream, c->zt, c->Vk, c->yv,
+                           c->jcnt, ns, B, rs, live);
+        hipLaunchKernelGGL(k_prescale<double>, dim3(blocks_for(nB)), dim3(256), 0, c->stream, c->zt, nullptr,
+                           (cplx<double>*)c->w, ns, B, 0, live);
+        hipLaunchKernelGGL(k_spmv_rows_add, dim3(blocks_for(nB)), dim3(256), 0, c->stream, c->rowptr, c->col, c->sai,
+                           c->w, c->xk, ns, B, 0, live);
+    } else {
+        hipLaunchKernelGGL(k_update_x, dim3((ns + 255) / 256, B), dim3(256), 0, c->stream, c->xk, c->Vk, c->yv,
+                           c->jcnt, c->dinv, ns, B, rs, live);
+    }
+    hipLaunchKernelGGL(k_step_check, dim3(1), dim3(64), 0, c->stream, c->flag, c->sctl + 1);
+    // the solution, the rings, the detector's norms, the next extrapolation order
+    hipLaunchKernelGGL(k_store_step, dim3(blocks_for(nB)), dim3(256), 0, c->stream, c->xk, nB, sr);
+    CHK(Ops<R>::commit(c, 0, c->xk, sr));
+    hipLaunchKernelGGL(k_norm, dim3(B), dim3(kRedThreads), 0, c->stream, c->xk, nullptr, ns, live, sr);
+    if (pred) {
+        hipLaunchKernelGGL(k_pred_err, dim3(kPredBlocks), dim3(kRedThreads), 0, c->stream, (const zd*)nullptr, nB, 0LL,
+                           1, 0, c->perr + kMaxGuess, sr);
+        hipLaunchKernelGGL(k_pred_err_sum, dim3(1), dim3(256), 0, c->stream, (const double*)(c->perr + kMaxGuess),
+                           kPredBlocks, c->perr, 0, c->pnext, sr);
+    }
+    hipLaunchKernelGGL(k_step_end, dim3(1), dim3(64), 0, c->stream, c->flag, c->resid, B, c->siters, c->sres, c->sctl,
+                       (const int*)(c->sctl + 1));
+    HIPCHK(hipGetLastError());
+    return ETAIM_OK;
+}
+
+// the executable graph of a step variant, captured on first use
+template <typename R>
+int step_graph_get(etaim_ctx* c, int J, int far, int pred, hipGraphExec_t& out) {
+    const int key = (J * 2 + far) * 2 + pred;
+    auto it = c->step_graphs.find(key);
+    if (it != c->step_graphs.end()) {
+        out = it->second;
+        return ETAIM_OK;
+    }
+    if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    hipStream_t user = c->stream;
+    c->stream = c->cap_stream;
+    c->capturing = true;
+    const hipError_t e0 = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+    const int rc = e0 == hipSuccess ? step_body<R>(c, J, far, pred) : (int)ETAIM_EHIP;
+    hipGraph_t g = nullptr;
+    const hipError_t e1 = e0 == hipSuccess ? hipStreamEndCapture(c->stream, &g) : e0;
+    c->stream = user;
+    c->capturing = false;
+    if (rc != ETAIM_OK || e1 != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc != ETAIM_OK ? rc : fail(ETAIM_EHIP, std::string("step graph capture failed: ") + hipGetErrorString(e1));
+    }
+    hipGraphExec_t x = nullptr;
+    const hipError_t e2 = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e2 != hipSuccess) return fail(ETAIM_EHIP, std::string("step graph instantiation failed: ") + hipGetErrorString(e2));
+    c->step_graphs[key] = x;
+    out = x;
     return ETAIM_OK;
 }
 
@@ -1048,7 +1195,12 @@ int march_impl(etaim_ctx* c, const zd* V, zd* I, etaim_stats* st, bool adjoint, 
         guess_p = c->guess_p_next;
         guess_dev = c->guess_dev_next;
     }
-    for (int r = first; r < first + nt; ++r) {
+    // the eager step whose phase events have not been read yet (-1: none)
+    int ev_step = -1;
+    double ms_graph = 0;
+    int graph_steps = 0, graph_halts = 0;
+    // one step launched kernel by kernel; 1: the march stops after it
+    auto eager_step = [&](int r) -> int {
         const int i = r - first;  // index within this call
         const int l = adjoint ? nt - 1 - r : r;
         const zd* Vl = V + (size_t)l * nB;
@@ -1065,13 +1217,16 @@ int march_impl(etaim_ctx* c, const zd* V, zd* I, etaim_stats* st, bool adjoint, 
         // that best predicted the previous step (at most guess_order)
         hipLaunchKernelGGL(k_extrap, dim3(blocks_for(nB)), dim3(256), 0, c->stream, (const zd*)I, c->xk, nB,
                            (long long)l, adjoint ? -1 : 1, guess_dev ? r : std::min(r, guess_p),
-                           guess_dev ? (const int*)c->pnext : nullptr);
+                           guess_dev ? (const int*)c->pnext : nullptr, StepRef{});
         HIPCHK(hipGetLastError());
         StepResult sr;
         CHK(gmres<R>(c, c->rhs, c->xk, conj, sr));
         c->iter_hint = std::min(sr.iters, c->prm.restart);
         // gmres has waited on the stream: the previous step's events are complete
-        if (r > first) CHK(phase_ms(r - 1));
+        if (ev_step >= 0) {
+            CHK(phase_ms(ev_step));
+            ev_step = -1;
+        }
         HIPCHK(hipEventRecord(ev[2], c->stream));
         HIPCHK(hipMemcpyAsync(Il, c->xk, nB * sizeof(zd), hipMemcpyDeviceToDevice, c->stream));
         if (checking && nchk < chk_steps.size() && chk_steps[nchk] == r) {
@@ -1079,19 +1234,21 @@ int march_impl(etaim_ctx* c, const zd* V, zd* I, etaim_stats* st, bool adjoint, 
             ++nchk;
         }
         CHK(Ops<R>::commit(c, r, c->xk));
-        hipLaunchKernelGGL(k_norm, dim3(B), dim3(kRedThreads), 0, c->stream, c->xk, nrm_all + (size_t)i * B, ns, nullptr);
+        hipLaunchKernelGGL(k_norm, dim3(B), dim3(kRedThreads), 0, c->stream, c->xk, nrm_all + (size_t)i * B, ns,
+                           nullptr, StepRef{});
         const int pmax = std::min(r, c->guess_order);
         if (pmax >= 2) {
             hipLaunchKernelGGL(k_pred_err, dim3(kPredBlocks), dim3(kRedThreads), 0, c->stream, (const zd*)I, nB,
-                               (long long)l, adjoint ? -1 : 1, pmax, c->perr + kMaxGuess);
+                               (long long)l, adjoint ? -1 : 1, pmax, c->perr + kMaxGuess, StepRef{});
             hipLaunchKernelGGL(k_pred_err_sum, dim3(1), dim3(256), 0, c->stream, (const double*)(c->perr + kMaxGuess),
-                               kPredBlocks, c->perr, pmax, c->pnext);
+                               kPredBlocks, c->perr, pmax, c->pnext, StepRef{});
             guess_dev = true;
         } else {
             guess_p = c->guess_order == 0 ? 0 : 1;
             guess_dev = false;
         }
         HIPCHK(hipEventRecord(ev[3], c->stream));
+        ev_step = r;
         HIPCHK(hipGetLastError());
         // kernel traces are resolved in batches (each flush waits on the stream)
         if (c->pending.size() >= kTraceBatch) CHK(trace_flush(c));
@@ -1108,20 +1265,134 @@ int march_impl(etaim_ctx* c, const zd* V, zd* I, etaim_stats* st, bool adjoint, 
         if (st && st->iters_per_step) st->iters_per_step[i] = sr.iters;
         if (sr.nonfinite) {
             nonfinite = true;
-            break;
+            return 1;
         }
         if (sr.noconv && first_noconv < 0) {
             first_noconv = r;
-            if (!(c->prm.flags & ETAIM_F_CONTINUE_ON_NOCONV)) break;
+            if (!(c->prm.flags & ETAIM_F_CONTINUE_ON_NOCONV)) return 1;
         }
         if (eager_detect) {
             detect(i);
-            if (unstable >= 0) break;
+            if (unstable >= 0) return 1;
         }
+        return 0;
+    };
+    // whole-step graph replays: forward marches with the estimate stop, the
+    // register engines, no tracing and no per-step growth check
+    const bool graph_mode = !adjoint && c->step_graph && !c->prof && !eager_detect &&
+                            (c->prm.flags & ETAIM_F_IMPLICIT_STOP) && c->yz_engine == 2 && c->x_engine == 1 &&
+                            xline_n(c) > 0 && quad_n(c) > 0;
+    const bool blocked = Ops<R>::blocks_on(c);
+    const int pb = c->delay_block, ng = c->st.ng;
+    auto block_start = [&](int r) { return r - (r - 1) % pb; };
+    if (graph_mode) {
+        CHK(step_graph_setup(c));
+        std::vector<StepDesc> d((size_t)nt);
+        for (int r = first; r < first + nt; ++r) {
+            StepDesc& e = d[(size_t)(r - first)];
+            e.cur = r;
+            e.i = r - first;
+            e.r0 = blocked ? block_start(r) : 0;
+            e.nm = blocked ? std::min(r - e.r0, ng) : std::min(ng, r);
+            e.fj = blocked ? r - e.r0 : -1;
+            e.nmh = std::min(c->st.mn, r);
+            // replayed steps follow a step that compared >= 2 orders when guess_order >= 2
+            e.pdev = c->guess_order >= 2 ? 1 : 0;
+            e.p = e.pdev ? r : std::min(r, c->guess_order == 0 ? 0 : 1);
+            e.pmax = std::min(r, c->guess_order);
+            e.pad = 0;
+            e.V = V;
+            e.I = I;
+            e.nrm = nrm_all;
+        }
+        HIPCHK(hipMemcpy(c->sdesc, d.data(), d.size() * sizeof(StepDesc), hipMemcpyHostToDevice));
+    }
+    std::vector<int> it_h(kStepChunk);
+    std::vector<double> res_hv(kStepChunk);
+    for (int r = first; r < first + nt;) {
+        if (!graph_mode || r < 3 || r == first) {
+            const int rc = eager_step(r);
+            if (rc < 0) return rc;
+            if (rc == 1) break;
+            ++r;
+            continue;
+        }
+        // a run a..b of replayed steps, ending at the next residual check
+        const int a = r;
+        int b = std::min(first + nt - 1, a + kStepChunk - 1);
+        int chk_at = -1;
+        if (checking && nchk < chk_steps.size() && chk_steps[nchk] <= b) b = chk_at = chk_steps[nchk];
+        const int J = std::max(2, std::min(c->iter_hint + 1, c->prm.restart));
+        hipLaunchKernelGGL(k_step_ctl, dim3(1), dim3(64), 0, c->stream, c->sctl, a - first);
+        HIPCHK(hipEventRecord(c->evg[0], c->stream));
+        for (int q = a; q <= b; ++q) {
+            const int far = blocked && c->far_r0 != block_start(q) ? 1 : 0;
+            if (far) c->far_r0 = block_start(q);
+            const int pred = std::min(q, c->guess_order) >= 2 ? 1 : 0;
+            hipGraphExec_t gx = nullptr;
+            CHK(step_graph_get<R>(c, J, far, pred, gx));
+            HIPCHK(hipGraphLaunch(gx, c->stream));
+        }
+        if (chk_at >= 0)
+            CHK(check_step<R>(c, chk_at, V + (size_t)chk_at * nB, I, I + (size_t)chk_at * nB,
+                              chk + 2 * (size_t)ccols * nchk));
+        HIPCHK(hipEventRecord(c->evg[1], c->stream));
+        HIPCHK(hipMemcpyAsync(c->sctl_h, c->sctl, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        if (ev_step >= 0) {
+            CHK(phase_ms(ev_step));
+            ev_step = -1;
+        }
+        {
+            float t = 0;
+            HIPCHK(hipEventElapsedTime(&t, c->evg[0], c->evg[1]));
+            ms_graph += t;
+        }
+        const int done = c->sctl_h[0] - (a - first);
+        if (done < 0 || done > b - a + 1) return fail(ETAIM_EHIP, "whole-step graph: inconsistent step counter");
+        if (done > 0) {
+            HIPCHK(hipMemcpy(it_h.data(), c->siters + (a - first), done * sizeof(int), hipMemcpyDeviceToHost));
+            HIPCHK(hipMemcpy(res_hv.data(), c->sres + (a - first), done * sizeof(double), hipMemcpyDeviceToHost));
+        }
+        int hint = 0;
+        graph_steps += done;
+        for (int q = 0; q < done; ++q) {
+            const int i = a - first + q;
+            steps = i + 1;
+            tot_iters += it_h[q];
+            max_iters = std::max(max_iters, it_h[q]);
+            maxres = std::max(maxres, res_hv[q]);
+            hint = std::max(hint, it_h[q]);
+            if (st && st->iters_per_step) st->iters_per_step[i] = it_h[q];
+        }
+        if (done > 0) {
+            c->iter_hint = std::min(hint, c->prm.restart);
+            const int qlast = a + done - 1;
+            guess_dev = std::min(qlast, c->guess_order) >= 2;
+            if (!guess_dev) guess_p = c->guess_order == 0 ? 0 : 1;
+        }
+        if (c->sctl_h[1] != 0) {
+            if (chk_at >= 0) ++nchk;
+            r = b + 1;
+            continue;
+        }
+        // step h did not converge within J Arnoldi steps (or went non-finite):
+        // nothing after its GMRES ran, for it or the steps enqueued after it.
+        // Its time block's sums are in place (their pass ran at or before h).
+        const int h = a + done;
+        ++graph_halts;
+        if (blocked) c->far_r0 = block_start(h);
+        // a residual check enqueued after the halt read solutions that were not
+        // computed: it is not counted, and the FP64 history refills from h on
+        if (c->check) c->check->check_next = std::min(c->check->check_next, h);
+        const int rc = eager_step(h);
+        if (rc < 0) return rc;
+        if (rc == 1) break;
+        r = h + 1;
     }
     HIPCHK(hipStreamSynchronize(c->stream));
     CHK(trace_flush(c));
-    if (steps >= 1) CHK(phase_ms(first + steps - 1));
+    if (ev_step >= 0) CHK(phase_ms(ev_step));
     if (!eager_detect && steps >= 1) {
         std::vector<double> na((size_t)steps * B);
         HIPCHK(hipMemcpy(na.data(), nrm_all, na.size() * sizeof(double), hipMemcpyDeviceToHost));
@@ -1164,11 +1435,13 @@ int march_impl(etaim_ctx* c, const zd* V, zd* I, etaim_stats* st, bool adjoint, 
         st->ms_rhs = ms_rhs;
         st->ms_solve = ms_solve;
         st->ms_commit = ms_commit;
-        st->ms_total = ms_rhs + ms_solve + ms_commit;
+        st->ms_total = ms_rhs + ms_solve + ms_commit + ms_graph;
         st->max_rel_residual = maxres;
         st->residual_checks = n_checks;
         st->residual_worst_step = worst_step;
         st->max_residual64 = worst;
+        st->graph_steps = graph_steps;
+        st->graph_halts = graph_halts;
     }
     if (!adjoint && steps == nt && !nonfinite) {
         if (checking && c->check) c->check_synced = first + steps;
@@ -1462,6 +1735,7 @@ int device_setup(etaim_ctx* c) {
     HIPCHK(hipHostMalloc((void**)&c->res_h, 2 * (size_t)c->B * sizeof(double), hipHostMallocDefault));
     CHK(c->alloc(c->pnext, 1));
     for (auto& e : c->ev) HIPCHK(hipEventCreate(&e));
+    for (auto& e : c->evg) HIPCHK(hipEventCreate(&e));
     HIPCHK(hipStreamSynchronize(c->stream));
     return ETAIM_OK;
 }
@@ -1533,6 +1807,7 @@ int etaim_create(etaim_ctx** out, const etaim_mesh* mesh, const etaim_rwg* rwg, 
     c->B = params->batch;
     c->sync_every = std::max(params->sync_every, 1);
     c->use_graph = (params->flags & ETAIM_F_GRAPH) != 0;
+    c->step_graph = (params->flags & ETAIM_F_STEP_GRAPH) != 0;
     c->prec = params->precision;
     c->mv = c->st.mn + 1;
     c->nnz = (int)c->st.col.size();

@@ -69,8 +69,10 @@ __global__ void __launch_bounds__(256) k_orth(const zd* __restrict__ V, zd* __re
 
 // nrm[b] = ||w[b]||  (kRedThreads per block)
 __global__ void __launch_bounds__(kRedThreads) k_norm(const zd* __restrict__ w, double* __restrict__ nrm, int ns,
-                                                      const int* __restrict__ gate = nullptr) {
-    if (gated_off(gate)) return;
+                                                      const int* __restrict__ gate = nullptr, StepRef sr = {}) {
+    if (gated_off(gate) || step_off(sr)) return;
+    // replayed step: its row of the call's per-step norms [steps][B]
+    if (const StepDesc* d = step_of(sr)) nrm = d->nrm + (size_t)d->i * gridDim.x;
     __shared__ double sh[kRedThreads / 64];
     const int b = blockIdx.x;
     const zd* x = w + (size_t)b * ns;
@@ -94,7 +96,9 @@ __global__ void k_scale(const zd* __restrict__ w, const double* __restrict__ nrm
 }
 
 // r = rhs - r  (r holds A x on entry)
-__global__ void k_residual(const zd* __restrict__ rhs, zd* __restrict__ r, size_t n) {
+__global__ void k_residual(const zd* __restrict__ rhs, zd* __restrict__ r, size_t n,
+                           const int* __restrict__ gate = nullptr) {
+    if (gated_off(gate)) return;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
         r[e] = rhs[e] - r[e];
 }
@@ -106,7 +110,9 @@ __global__ void k_residual(const zd* __restrict__ rhs, zd* __restrict__ r, size_
 __global__ void __launch_bounds__(256) k_cycle_start(const double* __restrict__ beta, const double* __restrict__ bnorm,
                                                      int* __restrict__ active, int* __restrict__ jcnt,
                                                      zd* __restrict__ g, double* __restrict__ resid,
-                                                     int* __restrict__ flag, int B, int ldg, double tol) {
+                                                     int* __restrict__ flag, int B, int ldg, double tol,
+                                                     const int* __restrict__ gate = nullptr) {
+    if (gated_off(gate)) return;
     for (int b = threadIdx.x; b < B; b += blockDim.x) {
         const double be = beta[b];
         const bool fin = isfinite(be);
@@ -185,9 +191,10 @@ __global__ void __launch_bounds__(256) k_arnoldi_update(const zd* __restrict__ h
 // Gate of one Arnoldi step, flag = {active columns, non-finite, live,
 // steps taken this cycle, step budget}: the step is live while a column is
 // active, nothing went non-finite and the budget lasts.  One thread.
-__global__ void k_gate(int* __restrict__ flag) {
+__global__ void k_gate(int* __restrict__ flag, const int* __restrict__ step_live = nullptr) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const int live = (flag[0] > 0 && flag[1] == 0 && flag[4] > 0) ? 1 : 0;
+    const int live =
+        (flag[0] > 0 && flag[1] == 0 && flag[4] > 0 && (step_live == nullptr || *step_live != 0)) ? 1 : 0;
     flag[2] = live;
     if (live) {
         flag[3] += 1;
@@ -197,7 +204,8 @@ __global__ void k_gate(int* __restrict__ flag) {
 
 // Back-substitution R y = g per column (size jcnt[b]); y[b][i].
 __global__ void k_backsolve(const zd* __restrict__ H, const zd* __restrict__ g, const int* __restrict__ jcnt,
-                            zd* __restrict__ y, int B, int restart) {
+                            zd* __restrict__ y, int B, int restart, const int* __restrict__ gate = nullptr) {
+    if (gated_off(gate)) return;
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= B) return;
     const int ldh = restart + 1;
@@ -215,7 +223,9 @@ __global__ void k_backsolve(const zd* __restrict__ H, const zd* __restrict__ g, 
 // x[b] += dinv . sum_{i<jcnt[b]} y[b][i] V_i[b]
 __global__ void __launch_bounds__(256) k_update_x(zd* __restrict__ x, const zd* __restrict__ V,
                                                   const zd* __restrict__ y, const int* __restrict__ jcnt,
-                                                  const zd* __restrict__ dinv, int ns, int B, int restart) {
+                                                  const zd* __restrict__ dinv, int ns, int B, int restart,
+                                                  const int* __restrict__ gate = nullptr) {
+    if (gated_off(gate)) return;
     const int b = blockIdx.y;
     const int k = blockIdx.x * 256 + threadIdx.x;
     if (k >= ns) return;
@@ -290,7 +300,9 @@ __global__ void __launch_bounds__(256) k_spmv_rows(const int* __restrict__ rowpt
 // y[b][i] += (op(M) x)[b][i] (FP64, columns of y contiguous)
 __global__ void __launch_bounds__(256) k_spmv_rows_add(const int* __restrict__ rowptr, const int* __restrict__ col,
                                                        const zd* __restrict__ M, const zd* __restrict__ xt,
-                                                       zd* __restrict__ y, int ns, int B, int conj) {
+                                                       zd* __restrict__ y, int ns, int B, int conj,
+                                                       const int* __restrict__ gate = nullptr) {
+    if (gated_off(gate)) return;
     const size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
     if (e >= (size_t)ns * B) return;
     const int i = (int)(e / B), b = (int)(e - (size_t)i * B);
@@ -301,7 +313,8 @@ __global__ void __launch_bounds__(256) k_spmv_rows_add(const int* __restrict__ r
 // right preconditioner that is not diagonal)
 __global__ void __launch_bounds__(256) k_krylov_combine(zd* __restrict__ u, const zd* __restrict__ V,
                                                         const zd* __restrict__ y, const int* __restrict__ jcnt, int ns,
-                                                        int B, int restart) {
+                                                        int B, int restart, const int* __restrict__ gate = nullptr) {
+    if (gated_off(gate)) return;
     const int b = blockIdx.y;
     const int k = blockIdx.x * 256 + threadIdx.x;
     if (k >= ns) return;
@@ -331,7 +344,14 @@ __constant__ double kExtrap[kMaxGuess][kMaxGuess] = {{1, 0, 0, 0, 0, 0},       {
 // (a_i = (-1)^(i+1) C(p, i)); p = 0 gives zero.  The march picks p as the
 // order whose prediction of the step just solved was closest.
 __global__ void k_extrap(const zd* __restrict__ I, zd* __restrict__ x, size_t nB, long long l, int dir, int p,
-                         const int* __restrict__ pdev) {
+                         const int* __restrict__ pdev, StepRef sr = {}) {
+    if (step_off(sr)) return;
+    if (const StepDesc* d = step_of(sr)) {
+        I = d->I;
+        l = d->cur;
+        p = d->p;
+        if (!d->pdev) pdev = nullptr;
+    }
     // p caps the order (history available); pdev, when given, holds the order chosen on the device
     if (pdev) p = min(p, *pdev);
     const auto& a = kExtrap;
@@ -352,7 +372,13 @@ __global__ void k_extrap(const zd* __restrict__ I, zd* __restrict__ x, size_t nB
 // order (deterministic).
 constexpr int kPredBlocks = 256;
 __global__ void __launch_bounds__(kRedThreads) k_pred_err(const zd* __restrict__ I, size_t nB, long long l, int dir,
-                                                          int pmax, double* __restrict__ part) {
+                                                          int pmax, double* __restrict__ part, StepRef sr = {}) {
+    if (step_off(sr)) return;
+    if (const StepDesc* d = step_of(sr)) {
+        I = d->I;
+        l = d->cur;
+        pmax = d->pmax;
+    }
     __shared__ double sh[kMaxGuess][kRedThreads / 64];
     const auto& a = kExtrap;
     double s[kMaxGuess] = {0, 0, 0, 0, 0, 0};
@@ -376,7 +402,10 @@ __global__ void __launch_bounds__(kRedThreads) k_pred_err(const zd* __restrict__
 }
 
 __global__ void __launch_bounds__(256) k_pred_err_sum(const double* __restrict__ part, int nblk,
-                                                      double* __restrict__ err, int pmax, int* __restrict__ pbest) {
+                                                      double* __restrict__ err, int pmax, int* __restrict__ pbest,
+                                                      StepRef sr = {}) {
+    if (step_off(sr)) return;
+    if (const StepDesc* d = step_of(sr)) pmax = d->pmax;
     __shared__ double sh[256];
     double e[kMaxGuess];
     for (int p = 0; p < kMaxGuess; ++p) {
@@ -413,6 +442,61 @@ template <typename R>
 __global__ void k_to_r(const zd* __restrict__ in, cplx<R>* __restrict__ out, size_t n) {
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
         out[e] = cplx<R>{(R)in[e].x, (R)in[e].y};
+}
+
+// The replayed step's solution x into the call's I_out[cur] ([N_t][B][ns]).
+__global__ void k_store_step(const zd* __restrict__ x, size_t nB, StepRef sr) {
+    if (step_off(sr)) return;
+    const StepDesc* d = step_of(sr);
+    zd* out = d->I + (size_t)d->cur * nB;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < nB; e += (size_t)gridDim.x * blockDim.x)
+        out[e] = x[e];
+}
+
+// The replayed step's solution into its slot of the current history
+// [M_n][ns][B] in the working precision (columns of a basis contiguous).
+template <typename R>
+__global__ void k_store_hist(const zd* __restrict__ x, cplx<R>* __restrict__ hist, int ns, int B, int mn,
+                             StepRef sr) {
+    if (step_off(sr)) return;
+    const StepDesc* d = step_of(sr);
+    cplx<R>* out = hist + (size_t)(d->cur % mn) * ns * B;
+    const size_t tot = (size_t)ns * B;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot; e += (size_t)gridDim.x * blockDim.x) {
+        const int k = (int)(e / B), b = (int)(e - (size_t)k * B);
+        const zd v = x[(size_t)b * ns + k];
+        out[e] = cplx<R>{(R)v.x, (R)v.y};
+    }
+}
+
+// Start of a run of replayed steps (one thread): ctl = {descriptor index, live}.
+__global__ void k_step_ctl(int* __restrict__ ctl, int idx) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    ctl[0] = idx;
+    ctl[1] = 1;
+}
+
+// After a replayed step's GMRES cycle (one thread): a column still active
+// (not converged within the captured Arnoldi steps) or a non-finite residual
+// stops the replays (live = 0) before the step commits anything.
+// flag = the Arnoldi flags {active columns, non-finite, ...}.
+__global__ void k_step_check(const int* __restrict__ flag, int* __restrict__ live) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (*live != 0 && (flag[0] > 0 || flag[1] != 0)) *live = 0;
+}
+
+// End of a replayed step (one thread): its Arnoldi step count and largest
+// residual estimate into the per-step records, and the descriptor counter
+// moves on.
+__global__ void k_step_end(const int* __restrict__ flag, const double* __restrict__ resid, int B,
+                           int* __restrict__ iters, double* __restrict__ res, int* __restrict__ ctr,
+                           const int* __restrict__ live) {
+    if (threadIdx.x != 0 || blockIdx.x != 0 || *live == 0) return;
+    double w = 0;
+    for (int b = 0; b < B; ++b) w = fmax(w, resid[b]);
+    iters[*ctr] = flag[3];
+    res[*ctr] = w;
+    *ctr += 1;
 }
 
 template <typename R>

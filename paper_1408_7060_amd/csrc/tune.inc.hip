@@ -79,6 +79,8 @@ void drop_graphs(etaim_ctx* c) {
             if (x) (void)hipGraphExecDestroy(x);
         v.clear();
     }
+    for (auto& kv : c->step_graphs) (void)hipGraphExecDestroy(kv.second);
+    c->step_graphs.clear();
 }
 
 void put_shape(etaim_ctx* c, const Shape& s) {
@@ -89,7 +91,8 @@ void put_shape(etaim_ctx* c, const Shape& s) {
     c->lines_x_t = s.mt;
     c->interp_waves = s.waves;
     c->sync_every = s.sync;
-    c->use_graph = s.graph != 0;
+    c->use_graph = s.graph == 1;
+    c->step_graph = s.graph == 2;
     // the LDS and register engines lay the spectrum ring out differently: a
     // change between them invalidates the history (and its block sums)
     if ((c->yz_engine == 0) != (s.engine == 0)) {
@@ -114,7 +117,7 @@ Shape get_shape(const etaim_ctx* c) {
     s.mt = c->lines_x_t;
     s.waves = c->interp_waves;
     s.sync = c->sync_every;
-    s.graph = c->use_graph ? 1 : 0;
+    s.graph = c->step_graph ? 2 : (c->use_graph ? 1 : 0);
     s.engine = c->yz_engine;
     s.xeng = c->x_engine;
     s.guess = c->guess_order;
@@ -160,11 +163,12 @@ int shape_from_c(const etaim_ctx* c, const etaim_tuning* t, Shape& s) {
     }
     if (t->gather_rows < 1 || t->lines_per_block < 1 || t->interp_waves < 1 || t->sync_every < 1)
         return fail(ETAIM_EINVAL, "gather_rows, lines_per_block, interp_waves and sync_every must be >= 1");
+    if (t->graph < 0 || t->graph > 2) return fail(ETAIM_EINVAL, "graph must be 0, 1 or 2");
     s.mr = t->gather_rows;
     s.mt = t->lines_per_block;
     s.waves = t->interp_waves;
     s.sync = t->sync_every;
-    s.graph = t->graph ? 1 : 0;
+    s.graph = t->graph;
     s.engine = t->yz_engine;
     s.xeng = t->x_engine;
     s.guess = t->guess_order;
