@@ -346,6 +346,10 @@ typedef struct {
                                 than r0 are summed for the whole block in one pass at r0, the j
                                 terms of the block's own steps at the step; equal to the direct sum
                                 up to rounding (default 6; used when N_g <= 32) */
+    int32_t interp_engine;   /* interpolation + near zone: 0 one wavefront per basis gathering its
+                                stencil from HBM/L2 (interp_waves bases per block), 1 by grid tiles:
+                                a block loads a tile's node box of a group of columns into LDS and
+                                its wavefronts take the tile's bases from there */
     double apply_ms;         /* out: measured matvec time [ms] (0 if not measured) */
     double solve_ms;         /* out: measured GMRES solve of the tuning right-hand side [ms] (0 if not
                                 measured) */

@@ -210,7 +210,7 @@ class Problem:
     def _tuning_dict(t) -> dict:
         d = {ax: [v for v in t.radix[a] if v] for a, ax in enumerate(("radix_x", "radix_y", "radix_z"))}
         for f in ("gather_rows", "lines_per_block", "interp_waves", "sync_every", "graph", "yz_engine", "x_engine",
-                  "guess_order", "precond", "delay_block", "apply_ms", "solve_ms"):
+                  "guess_order", "precond", "delay_block", "interp_engine", "apply_ms", "solve_ms"):
             d[f] = getattr(t, f)
         return d
 
@@ -232,8 +232,8 @@ class Problem:
             for i, v in enumerate(d[ax]):
                 t.radix[a][i] = int(v)
         for f in ("gather_rows", "lines_per_block", "interp_waves", "sync_every", "graph", "yz_engine", "x_engine",
-                  "guess_order", "precond", "delay_block"):
-            setattr(t, f, int(d[f]))
+                  "guess_order", "precond", "delay_block", "interp_engine"):
+            setattr(t, f, int(d.get(f, 0)))
         _lib.check(_lib.load().etaim_set_tuning(self._h, byref(t)))
 
     def close(self):

@@ -50,7 +50,7 @@ class Tuning(ctypes.Structure):
     _fields_ = [("radix", (c_int32 * 8) * 3), ("gather_rows", c_int32), ("lines_per_block", c_int32),
                 ("interp_waves", c_int32), ("sync_every", c_int32), ("graph", c_int32), ("yz_engine", c_int32),
                 ("x_engine", c_int32), ("guess_order", c_int32), ("precond", c_int32),
-                ("delay_block", c_int32),
+                ("delay_block", c_int32), ("interp_engine", c_int32),
                 ("apply_ms", c_double),
                 ("solve_ms", c_double)]
 

@@ -1185,6 +1185,152 @@ __global__ void __launch_bounds__(256) k_interp_near(
     }
 }
 
+// Interpolation + near-zone SpMV by grid tiles (the same sums as
+// k_interp_near).  The bases are grouped by the tile of their stencil
+// corner (kTileX x kTileY x kTileZ corners); a block takes one tile and a
+// group of GC columns: it loads the tile's node box (the corners plus the
+// stencil's 3-node reach, y fastest, so that the loads are runs of kBoxY
+// nodes) of the 4 GC potential planes into LDS, then its waves take the
+// tile's bases one by one as k_interp_near does, lane j on stencil node j,
+// reading the potentials from LDS.  Blocks run tile-fastest within a column
+// group, each XCD a contiguous run of the Morton-ordered tiles.
+constexpr int kTileX = 4, kTileY = 8, kTileZ = 4;
+constexpr int kBoxX = kTileX + 3, kBoxY = kTileY + 3, kBoxZ = kTileZ + 3, kBoxN = kBoxX * kBoxY * kBoxZ;
+
+constexpr int kTileThreads = 1024;
+
+template <typename R, int GC>
+__global__ void __launch_bounds__(kTileThreads) k_interp_tile(
+    const cplx<R>* __restrict__ P, const R* __restrict__ lam, const int* __restrict__ i0,
+    const int* __restrict__ tptr, const int* __restrict__ tbase, const int* __restrict__ torg, int ntiles,
+    GridDims g, const int* __restrict__ rowptr, const int* __restrict__ col, const cplx<R>* __restrict__ val,
+    int mv, const cplx<R>* __restrict__ xr, int m, const cplx<R>* __restrict__ hist, int mn, int cur, int nmh,
+    const zd* __restrict__ V, zd* __restrict__ y, int ns, int mode, int conj_v, const int* __restrict__ gate,
+    StepRef sr) {
+    if (gated_off(gate) || step_off(sr)) return;
+    if (const StepDesc* d = step_of(sr)) {
+        cur = d->cur;
+        nmh = d->nmh;
+        V = d->V + (size_t)d->cur * g.B * ns;
+    }
+    extern __shared__ unsigned char smem_raw[];
+    cplx<R>* box = reinterpret_cast<cplx<R>*>(smem_raw);
+    // block -> (column group, tile): each XCD (round-robin dispatch) gets one
+    // contiguous run of the logical blocks
+    const int per = gridDim.x / kXcds;
+    const int lb = (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+    const int ngroups = (g.B + GC - 1) / GC;
+    if (lb >= ntiles * ngroups) return;
+    const int t = lb % ntiles, b0 = (lb / ntiles) * GC;
+    const int nb = min(GC, g.B - b0);
+    const int Nx = g.N[0], Ny = g.N[1], Nz = g.N[2], B = g.B;
+    const size_t N = (size_t)Nx * Ny * Nz;
+    const int ox = torg[3 * t], oy = torg[3 * t + 1], oz = torg[3 * t + 2];
+    // the box as rows of kBoxY y-nodes, one row per 16 lanes (y = lane % 16):
+    // each load instruction takes four coalesced runs
+    constexpr int ROWS = 4 * GC * kBoxZ * kBoxX;
+    for (int e = threadIdx.x; e < ROWS * 16; e += blockDim.x) {
+        const int ly = e & 15, row = e >> 4;
+        if (ly >= kBoxY) continue;
+        const int lx = row % kBoxX, r2 = row / kBoxX, lz = r2 % kBoxZ, bcl = r2 / kBoxZ;
+        const int gx = ox + lx, gy = oy + ly, gz = oz + lz;
+        cplx<R> v{0, 0};
+        if (bcl < 4 * nb && gx < Nx && gy < Ny && gz < Nz)
+            v = P[(size_t)(4 * b0 + bcl) * N + (size_t)gy + (size_t)Ny * ((size_t)gx + (size_t)Nx * gz)];
+        box[row * kBoxY + ly] = v;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int jy = lane & 3, jx = (lane >> 2) & 3, jz = lane >> 4, j = jx + 4 * jy + 16 * jz;
+    // near zone: lane = (entry slot, column), columns innermost
+    constexpr int C = GC, E = 64 / GC, GL = 64 / GC;
+    const int bcol = lane & (C - 1), eslot = lane / C;
+    for (int q = tptr[t] + wave; q < tptr[t + 1]; q += nw) {
+        const int k = tbase[q];
+        const int lx = i0[3 * k] - ox + jx, ly = i0[3 * k + 1] - oy + jy, lz = i0[3 * k + 2] - oz + jz;
+        const int o = (lz * kBoxX + lx) * kBoxY + ly;
+        R w[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) w[c] = lam[(size_t)k * 256 + 64 * c + j];
+        cplx<R> acc[GC];
+#pragma unroll
+        for (int bb = 0; bb < GC; ++bb) {
+            acc[bb] = cplx<R>{0, 0};
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[bb] += w[c] * box[(size_t)(4 * bb + c) * kBoxN + o];
+        }
+        cplx<R> nacc{0, 0};
+        const int e0 = rowptr[k], e1 = rowptr[k + 1];
+        constexpr int U = 4;
+        for (int e = e0 + eslot; e < e1; e += U * E) {
+            int cc[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) cc[u] = e + u * E < e1 ? col[e + u * E] : -1;
+            if (mode == 0) {
+                if (m <= mv - 1) {
+                    cplx<R> v[U], xv[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        v[u] = cplx<R>{0, 0};
+                        xv[u] = cplx<R>{0, 0};
+                        if (cc[u] >= 0) {
+                            v[u] = val[(size_t)(e + u * E) * mv + m];
+                            if (bcol < nb) xv[u] = xr[(size_t)cc[u] * B + b0 + bcol];
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        if (conj_v) v[u].y = -v[u].y;
+                        nacc += v[u] * xv[u];
+                    }
+                }
+            } else {
+                for (int mm = 1; mm <= nmh; ++mm) {
+                    int sl = (cur - mm) % mn;
+                    if (sl < 0) sl += mn;
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        if (cc[u] < 0) continue;
+                        cplx<R> v = val[(size_t)(e + u * E) * mv + mm];
+                        if (conj_v) v.y = -v.y;
+                        if (bcol < nb) nacc += v * hist[((size_t)sl * ns + cc[u]) * B + b0 + bcol];
+                    }
+                }
+            }
+        }
+        for (int sft = C; sft < 64; sft <<= 1) {
+            nacc.x += __shfl_xor(nacc.x, sft, 64);
+            nacc.y += __shfl_xor(nacc.y, sft, 64);
+        }
+        // transposing butterfly over the top log2(GC) lane bits, then the GL
+        // lanes of each column group summed: lane GL bb + i holds column bb
+#pragma unroll
+        for (int h = GC / 2, bit = 32; h >= 1; h >>= 1, bit >>= 1) {
+            const bool up = (lane & bit) != 0;
+#pragma unroll
+            for (int i = 0; i < h; ++i) {
+                const cplx<R> keep = up ? acc[i + h] : acc[i];
+                const cplx<R> send = up ? acc[i] : acc[i + h];
+                acc[i] = keep + cplx<R>{__shfl_xor(send.x, bit, 64), __shfl_xor(send.y, bit, 64)};
+            }
+        }
+        cplx<R> tot = acc[0];
+#pragma unroll
+        for (int bit = GL / 2; bit >= 1; bit >>= 1)
+            tot += cplx<R>{__shfl_xor(tot.x, bit, 64), __shfl_xor(tot.y, bit, 64)};
+        const int bb = lane / GL;
+        const cplx<R> near{__shfl(nacc.x, bb, 64), __shfl(nacc.y, bb, 64)};
+        tot += near;
+        if (lane % GL == 0 && bb < nb) {
+            const size_t oo = (size_t)(b0 + bb) * ns + k;
+            if (mode == 0)
+                y[oo] = zd{(double)tot.x, (double)tot.y};
+            else
+                y[oo] = zd{V[oo].x - (double)tot.x, V[oo].y - (double)tot.y};
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Set-up kernels (FP64): Green tables, circulant embedding, folding,
 // pre-correction, excitation.

@@ -95,6 +95,9 @@ struct etaim_ctx {
     // near-zone sparse approximate inverse (right preconditioner) and its transposed copy
     zd *sai = nullptr, *saiT = nullptr, *zt = nullptr;
     int precond = 1;  // 0: Jacobi diag(Z0)^-1, 1: near-zone sparse approximate inverse
+    // interpolation by grid tiles: tile -> bases (CSR), tile origins [ntiles][3]
+    int interp_engine = 0, ntiles = 0;
+    int *tptr = nullptr, *tbase = nullptr, *torg = nullptr;
     // delayed field in time blocks (register engine): far part of the history
     // sum once per block of delay_block steps into far, near part per step
     int delay_block = 6, far_slots = 0, far_r0 = -1;
@@ -307,6 +310,20 @@ int quad_n(const etaim_ctx* c) {
     return (n == 16 || n == 24 || n == 48) ? n : 0;
 }
 
+// columns per block of the grid-tile interpolation (a power of two, its LDS
+// box of 4 GC potential planes within 69 KB)
+template <typename R>
+int interp_tile_gc(const etaim_ctx* c) {
+    const int cap = sizeof(R) == 4 ? 4 : 2;
+    int gc = 1;
+    while (gc < cap && gc < c->B) gc *= 2;
+    return gc;
+}
+template <typename R>
+size_t interp_tile_lds(const etaim_ctx* c) {
+    return (size_t)4 * interp_tile_gc<R>(c) * kBoxN * sizeof(cplx<R>);
+}
+
 template <typename R>
 struct Ops {
     static cplx<R>* A(etaim_ctx* c) { return (cplx<R>*)c->A; }
@@ -450,6 +467,25 @@ struct Ops {
         if (mode == 0 && (c->x_engine != 1 || conj_x))
             hipLaunchKernelGGL(k_prescale<R>, dim3(blocks_for(nB)), dim3(256), 0, c->stream, x, dinv, xs, c->ns, c->B,
                                conj_x, gate);
+        if (c->interp_engine == 1 && c->ntiles > 0) {
+            const int gc = interp_tile_gc<R>(c);
+            const int nblk = c->ntiles * ((c->B + gc - 1) / gc);
+            const dim3 tg((nblk + kXcds - 1) / kXcds * kXcds);
+            const size_t lds = interp_tile_lds<R>(c);
+#define ETAIM_TILE(GC)                                                                                               \
+    hipLaunchKernelGGL((k_interp_tile<R, GC>), tg, dim3(kTileThreads), lds, c->stream, (const cplx<R>*)P(c), (const R*)c->lam_r, \
+                       c->i0, c->tptr, c->tbase, c->torg, c->ntiles, c->gd, c->rowptr, c->col, nearv(c, conj_v), c->mv, \
+                       (const cplx<R>*)xs, m, (const cplx<R>*)c->hist, std::max(c->st.mn, 1), cur, nmh, V, y, c->ns,   \
+                       mode, conj_v, gate, sr)
+            switch (gc) {
+                case 1: ETAIM_TILE(1); break;
+                case 2: ETAIM_TILE(2); break;
+                default: ETAIM_TILE(4); break;
+            }
+#undef ETAIM_TILE
+            HIPCHK(hipGetLastError());
+            return ETAIM_OK;
+        }
         hipLaunchKernelGGL(k_interp_near<R>, grid, dim3(64 * wpb), 0, c->stream, (const cplx<R>*)P(c),
                            (const R*)c->lam_r, c->i0, c->korder, c->gd, c->rowptr, c->col, nearv(c, conj_v), c->mv,
                            (const cplx<R>*)xs, m, (const cplx<R>*)c->hist, std::max(c->st.mn, 1), cur, nmh, V, y,
@@ -641,6 +677,9 @@ struct Ops {
                               (const void*)k_yzc_green<R, 16>, (const void*)k_yzc_green<R, 24>,
                               (const void*)k_yzc_green<R, 48>, (const void*)k_yzc_commit<R, 16>,
                               (const void*)k_yzc_commit<R, 24>, (const void*)k_yzc_commit<R, 48>})
+            HIPCHK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+        for (const void* f : {(const void*)k_interp_tile<R, 1>, (const void*)k_interp_tile<R, 2>,
+                              (const void*)k_interp_tile<R, 4>})
             HIPCHK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
         // the gather's LDS grows with its tuned row count
         HIPCHK(hipFuncSetAttribute((const void*)k_fwdx_gather<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1570,6 +1609,35 @@ int device_setup(etaim_ctx* c) {
         CHK(c->upload(c->xmask, xm));
     }
     CHK(c->upload(c->nk, s.nk));
+    {
+        // interpolation tiles: the bases (in their Morton order) grouped by the
+        // tile of their stencil corner, the tiles in the Morton order of their index
+        std::map<long long, std::vector<int>> by_tile;
+        auto spread = [](uint64_t v) {
+            uint64_t r = 0;
+            for (int b = 0; b < 21; ++b) r |= ((v >> b) & 1u) << (3 * b);
+            return r;
+        };
+        for (int q = 0; q < ns; ++q) {
+            const int k = s.order[q];
+            const uint64_t tx = (uint64_t)(s.i0[3 * k] / kTileX), ty = (uint64_t)(s.i0[3 * k + 1] / kTileY),
+                           tz = (uint64_t)(s.i0[3 * k + 2] / kTileZ);
+            by_tile[(long long)(spread(tx) | spread(ty) << 1 | spread(tz) << 2)].push_back(k);
+        }
+        std::vector<int> tptr(1, 0), tbase, torg;
+        for (const auto& kv : by_tile) {
+            const int k = kv.second.front();
+            torg.push_back(s.i0[3 * k] / kTileX * kTileX);
+            torg.push_back(s.i0[3 * k + 1] / kTileY * kTileY);
+            torg.push_back(s.i0[3 * k + 2] / kTileZ * kTileZ);
+            tbase.insert(tbase.end(), kv.second.begin(), kv.second.end());
+            tptr.push_back((int)tbase.size());
+        }
+        c->ntiles = (int)by_tile.size();
+        CHK(c->upload(c->tptr, tptr));
+        CHK(c->upload(c->tbase, tbase));
+        CHK(c->upload(c->torg, torg));
+    }
     CHK(c->upload(c->near64, s.near_exact));
     // diagonal of Z0 = exact self entry (pre-correction restores it)
     std::vector<zd> diag(ns), dinv(ns), dinv_c(ns);

@@ -39,7 +39,8 @@ bool radix_equal(const Radix& a, const Radix& b) {
 
 struct Shape {
     Radix rx, ry, rz;
-    int mr = 0, mt = 0, waves = 4, sync = 1, graph = 0, engine = 0, xeng = 0, guess = kMaxGuess, precond = 1, dblock = 6;
+    int mr = 0, mt = 0, waves = 4, sync = 1, graph = 0, engine = 0, xeng = 0, guess = kMaxGuess, precond = 1, dblock = 6,
+        ieng = 0;
 };
 
 template <typename R>
@@ -70,7 +71,8 @@ bool shape_fits(const etaim_ctx* c, const Shape& s) {
            ((size_t)mt * (Lx + 1) + Lx) * e <= (size_t)kLdsBudget && s.waves >= 1 && s.waves <= 4 &&
            s.sync >= 1 && s.sync <= c->prm.restart && (s.engine == 0 || ((s.engine == 1 || s.engine == 2) && quad_n(c) > 0)) &&
            (s.xeng == 0 || (s.xeng == 1 && xline_n(c) > 0)) && s.guess >= 0 && s.guess <= kMaxGuess &&
-           (s.precond == 0 || s.precond == 1) && s.dblock >= 1 && s.dblock <= kFarMaxBlock;
+           (s.precond == 0 || s.precond == 1) && s.dblock >= 1 && s.dblock <= kFarMaxBlock &&
+           (s.ieng == 0 || (s.ieng == 1 && c->ntiles > 0 && interp_tile_lds<R>(c) <= 160 * 1024));
 }
 
 void drop_graphs(etaim_ctx* c) {
@@ -103,6 +105,7 @@ void put_shape(etaim_ctx* c, const Shape& s) {
     c->x_engine = s.xeng;
     c->guess_order = s.guess;
     c->precond = s.precond;
+    c->interp_engine = s.ieng;
     if (c->delay_block != s.dblock) c->far_r0 = -1;
     c->delay_block = s.dblock;
     drop_graphs(c);  // captured steps hold the old launch shapes
@@ -123,6 +126,7 @@ Shape get_shape(const etaim_ctx* c) {
     s.guess = c->guess_order;
     s.precond = c->precond;
     s.dblock = c->delay_block;
+    s.ieng = c->interp_engine;
     return s;
 }
 
@@ -142,6 +146,7 @@ void shape_to_c(const etaim_ctx* c, const Shape& s, etaim_tuning* t) {
     t->guess_order = s.guess;
     t->precond = s.precond;
     t->delay_block = s.dblock;
+    t->interp_engine = s.ieng;
 }
 
 // EINVAL for malformed plans; shape_fits decides EUNSUPPORTED afterwards
@@ -174,6 +179,7 @@ int shape_from_c(const etaim_ctx* c, const etaim_tuning* t, Shape& s) {
     s.guess = t->guess_order;
     s.precond = t->precond;
     s.dblock = t->delay_block;
+    s.ieng = t->interp_engine;
     return ETAIM_OK;
 }
 
@@ -225,14 +231,14 @@ bool cache_lookup(const char* path, const std::string& key, etaim_tuning& t) {
         line = buf;
         if (line.find("\"key\": \"" + key + "\"") == std::string::npos) continue;
         std::memset(&t, 0, sizeof t);
-        long v[10];
+        long v[11];
         if (json_ints(line, "radix_x", t.radix[0], 8) && json_ints(line, "radix_y", t.radix[1], 8) &&
             json_ints(line, "radix_z", t.radix[2], 8) && json_int(line, "gather_rows", v[0]) &&
             json_int(line, "lines_per_block", v[1]) && json_int(line, "interp_waves", v[2]) &&
             json_int(line, "sync_every", v[3]) && json_int(line, "graph", v[4]) &&
             json_int(line, "yz_engine", v[5]) && json_int(line, "x_engine", v[6]) &&
             json_int(line, "guess_order", v[7]) && json_int(line, "precond", v[8]) &&
-            json_int(line, "delay_block", v[9])) {
+            json_int(line, "delay_block", v[9]) && json_int(line, "interp_engine", v[10])) {
             t.gather_rows = (int)v[0];
             t.lines_per_block = (int)v[1];
             t.interp_waves = (int)v[2];
@@ -243,6 +249,7 @@ bool cache_lookup(const char* path, const std::string& key, etaim_tuning& t) {
             t.guess_order = (int)v[7];
             t.precond = (int)v[8];
             t.delay_block = (int)v[9];
+            t.interp_engine = (int)v[10];
             found = true;  // the last matching record wins
         }
     }
@@ -261,9 +268,10 @@ int cache_append(const char* path, const std::string& key, const etaim_tuning& t
     std::fprintf(f,
                  "{\"key\": \"%s\", \"radix_x\": %s, \"radix_y\": %s, \"radix_z\": %s, \"gather_rows\": %d, "
                  "\"lines_per_block\": %d, \"interp_waves\": %d, \"sync_every\": %d, \"graph\": %d, "
-                 "\"yz_engine\": %d, \"x_engine\": %d, \"guess_order\": %d, \"precond\": %d, \"delay_block\": %d, \"apply_ms\": %.4f, \"solve_ms\": %.3f}\n",
+                 "\"yz_engine\": %d, \"x_engine\": %d, \"guess_order\": %d, \"precond\": %d, \"delay_block\": %d, "
+                 "\"interp_engine\": %d, \"apply_ms\": %.4f, \"solve_ms\": %.3f}\n",
                  key.c_str(), arr(t.radix[0]).c_str(), arr(t.radix[1]).c_str(), arr(t.radix[2]).c_str(),
-                 t.gather_rows, t.lines_per_block, t.interp_waves, t.sync_every, t.graph, t.yz_engine, t.x_engine, t.guess_order, t.precond, t.delay_block, t.apply_ms,
+                 t.gather_rows, t.lines_per_block, t.interp_waves, t.sync_every, t.graph, t.yz_engine, t.x_engine, t.guess_order, t.precond, t.delay_block, t.interp_engine, t.apply_ms,
                  t.solve_ms);
     std::fclose(f);
     return ETAIM_OK;
@@ -444,6 +452,11 @@ int autotune_impl(etaim_ctx* c, int budget_ms, etaim_tuning* out) {
     for (int w : {1, 2, 4}) {
         Shape s = best;
         s.waves = w;
+        CHK(trial(s));
+    }
+    {
+        Shape s = best;
+        s.ieng = 1 - best.ieng;
         CHK(trial(s));
     }
     // freeze the automatic choices so that the record is explicit

@@ -71,12 +71,12 @@ def _oracle():
     return s, A, p, rows, sel, vals
 
 
-def _bench_setting(P):
+def _bench_setting(P, interp_engine=0):
     d = P.tuning()
-    d.update(yz_engine=2, x_engine=1, delay_block=7)
+    d.update(yz_engine=2, x_engine=1, delay_block=7, interp_engine=interp_engine)
     P.set_tuning(d)
     t = P.tuning()
-    assert (t["yz_engine"], t["x_engine"], t["delay_block"]) == (2, 1, 7)
+    assert (t["yz_engine"], t["x_engine"], t["delay_block"], t["interp_engine"]) == (2, 1, 7, interp_engine)
 
 
 def _zx_rows(A, sel, vals, terms, rows):
@@ -95,13 +95,14 @@ def _operator_ref():
     return x, ref
 
 
+@pytest.mark.parametrize("ieng", [0, 1], ids=["per_basis", "tiles"])
 @pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-5)], ids=["fp64", "fp32"])
-def test_operator_at_bench_shape(torch, prec, tol):
+def test_operator_at_bench_shape(torch, prec, tol, ieng):
     s, A, p, rows, sel, vals = _oracle()
     x, ref = _operator_ref()
     P = gpu_problem(WL.name, precision=prec, nt=8)
     assert (P.info["mn"], P.info["nnz"], P.batch) == (A.mn, len(A.rows), 32)
-    _bench_setting(P)
+    _bench_setting(P, ieng)
     xd = _dev(torch, x)
     for m, r in ref.items():
         y = P.apply_z(m, xd).cpu().numpy()[list(COLS)][:, rows]
@@ -120,14 +121,15 @@ def _delayed_ref():
     return hist, ref
 
 
+@pytest.mark.parametrize("ieng", [0, 1], ids=["per_basis", "tiles"])
 @pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-5)], ids=["fp64", "fp32"])
-def test_delayed_field_at_bench_shape(torch, prec, tol):
+def test_delayed_field_at_bench_shape(torch, prec, tol, ieng):
     """b = sum_{m=1}^{N_g} (Z^near_m + Z^FFT_m) I_{l-m} over a full history,
     near history live (m <= M_n), time blocks of 7."""
     s, A, p, rows, sel, vals = _oracle()
     hist, ref = _delayed_ref()
     P = gpu_problem(WL.name, precision=prec, nt=8)
-    _bench_setting(P)
+    _bench_setting(P, ieng)
     b = P.delayed_field(_dev(torch, hist)).cpu().numpy()[list(COLS)][:, rows]
     e = rel(b, ref)
     _say("bench shape delayed field", "fp32" if prec else "fp64", "rel", e)

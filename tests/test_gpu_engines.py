@@ -233,3 +233,30 @@ def test_engines_give_the_same_march(torch):
         P.close()
     for o in out[1:]:
         assert rel(o, out[0]) <= 1e-11
+
+
+@pytest.mark.parametrize("batch", [1, 3])
+def test_interp_tiles_full_operator_level2(torch, batch):
+    """The grid-tile interpolation engine (a block per tile and column group,
+    the tile's potentials staged in LDS): every Z_m (near + far) and the
+    delayed field at the 16^3 grid against the oracle, FP64; batch 3 leaves
+    the last column group partial."""
+    s, A, vals, p = oracle_aim(L2)
+    P = gpu_problem(L2, batch=batch)
+    d = P.tuning()
+    d["interp_engine"] = 1
+    P.set_tuning(d)
+    assert P.tuning()["interp_engine"] == 1
+    x = W.complex_normal(38, (batch, s.ns))
+    for m in range(p["ng"] + 1):
+        y = P.apply_z(m, _dev(torch, x)).cpu().numpy()
+        ref = oracle_matvec(L2, m, x, direct=True)
+        assert rel(y, ref) <= 1e-12, (m, rel(y, ref))
+    hist = W.complex_normal(39, (p["ng"], batch, s.ns))
+    b = P.delayed_field(_dev(torch, hist)).cpu().numpy()
+    ref = np.array([sum(oracle_matvec(L2, m, hist[m - 1, j:j + 1], direct=True)[0] for m in range(1, p["ng"] + 1))
+                    for j in range(batch)])
+    e = rel(b, ref)
+    _say("L2 tiles batch", batch, "delayed rel", e)
+    assert e <= 1e-12
+    P.close()
