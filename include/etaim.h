@@ -328,7 +328,10 @@ typedef struct {
     int32_t yz_engine;       /* y/z plane stage: 0 LDS-staged radix passes over the whole padded
                                 plane, 1 register-resident parity quadrants (needs N_y = N_z in
                                 {16, 24, 48}), 2 as 1 but the matvec and commit plane transforms take
-                                the z lines first and hold two tiles instead of four */
+                                the z lines first and hold two tiles instead of four, 3 separate
+                                y- and z-line passes over a full-spectrum work array (any grid whose
+                                lines fit the LDS line kernel; chosen by itself where the padded
+                                plane does not fit the LDS) */
     int32_t x_engine;        /* x stage: 0 LDS-staged lines with the anterpolation fused in,
                                 1 register-resident lines after a separate anterpolation
                                 (needs N_x in {16, 24, 48}) */

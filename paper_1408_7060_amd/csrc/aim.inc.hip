@@ -953,6 +953,102 @@ struct Vec16<double> {
     static constexpr int P = 1;
 };
 
+// ---------------------------------------------------------------------------
+// Line-pass y/z engine (any grid whose lines fit the LDS line kernel, also
+// where a padded (y, z) plane does not fit the LDS): the y and z transforms
+// as separate passes over a full-spectrum work array S[bc][kx][kz][ky]
+// (the ring-slot layout of this engine), k_lines for the y passes and the
+// forward z pass, and these two kernels.
+
+// Matvec z stage, in place on S: lines along z of one (bc, kx) plane, mt
+// consecutive ky per block; the zero-padded forward transform of rows
+// z < Nz, the product with the folded Green spectrum, the inverse
+// transform, rows z < Nz stored back.
+template <typename R>
+__global__ void __launch_bounds__(kPlaneThreads) k_zlines_green(cplx<R>* __restrict__ S, const cplx<R>* __restrict__ G,
+                                                               const cplx<R>* __restrict__ twz_g, Radix rz, GridDims g,
+                                                               int mt, int conj_g, const int* __restrict__ gate) {
+    if (gated_off(gate)) return;
+    extern __shared__ unsigned char smem_raw[];
+    const int Lz = g.L[2], Ly = g.L[1], Lx = g.L[0], Nz = g.N[2], ldl = Lz + 1;
+    cplx<R>* buf = reinterpret_cast<cplx<R>*>(smem_raw);
+    cplx<R>* tw = buf + mt * ldl;
+    for (int i = threadIdx.x; i < Lz; i += blockDim.x) tw[i] = twz_g[i];
+    const int ky0 = blockIdx.x * mt, pl = blockIdx.y, kx = pl % Lx, bc = pl / Lx;
+    cplx<R>* base = S + (size_t)pl * Lz * Ly;
+    // rows z (the line points) outer, consecutive ky (the lines) inner: coalesced
+    for (int e = threadIdx.x; e < mt * Lz; e += blockDim.x) {
+        const int p = e / mt, l = e - p * mt, ky = ky0 + l;
+        cplx<R> v{0, 0};
+        if (ky < Ly && p < Nz) v = base[(size_t)p * Ly + ky];
+        buf[l * ldl + p] = v;
+    }
+    __syncthreads();
+    plane_fft<R>(buf, mt, ldl, 1, rz, tw, false);
+    const int gx = g.N[0] + 1, gy = g.N[1] + 1, gz = g.N[2] + 1;
+    const int t = (bc & 3) == 3 ? 1 : 0;
+    const cplx<R>* Gk = G + ((size_t)t * gx + fold(kx, Lx)) * ((size_t)gz * gy);
+    for (int e = threadIdx.x; e < mt * Lz; e += blockDim.x) {
+        const int p = e / mt, l = e - p * mt, ky = ky0 + l;
+        if (ky < Ly) {
+            cplx<R> gv = Gk[(size_t)fold(p, Lz) * gy + fold(ky, Ly)];
+            if (conj_g) gv.y = -gv.y;
+            buf[l * ldl + p] = buf[l * ldl + p] * gv;
+        }
+    }
+    __syncthreads();
+    plane_fft<R>(buf, mt, ldl, 1, rz, tw, true);
+    for (int e = threadIdx.x; e < mt * Nz; e += blockDim.x) {
+        const int p = e / mt, l = e - p * mt, ky = ky0 + l;
+        if (ky < Ly) base[(size_t)p * Ly + ky] = buf[l * ldl + p];
+    }
+}
+
+// Delayed-field sum of the line-pass engine: S = sum_{m=1}^{nm} G_m . ring
+// slot (cur - m) mod ng over every spectrum point [bc][kx][kz][ky]; a thread
+// owns one 16-byte vector of points (two in FP32) of one plane row and
+// loops over m.
+template <typename R>
+__global__ void __launch_bounds__(256) k_delay_sum(const cplx<R>* __restrict__ ring, const cplx<R>* __restrict__ G,
+                                                   cplx<R>* __restrict__ S, GridDims g, int ng, int cur, int nm,
+                                                   int conj_g) {
+    using V = typename Vec16<R>::type;
+    constexpr int P = Vec16<R>::P;
+    const int Lx = g.L[0], Ly = g.L[1], Lz = g.L[2];
+    const size_t plane = (size_t)Ly * Lz, slot = (size_t)4 * g.B * Lx * plane;
+    const size_t gid = (blockIdx.x * (size_t)blockDim.x + threadIdx.x) * P;
+    if (gid >= slot) return;
+    // Ly is even, so the P points share one (bc, kx, kz) row
+    const size_t pl = gid / plane;
+    const int r = (int)(gid - pl * plane), kz = r / Ly, ky = r - kz * Ly;
+    const int kx = (int)(pl % Lx), bc = (int)(pl / Lx);
+    const int gx = g.N[0] + 1, gy = g.N[1] + 1, gz = g.N[2] + 1;
+    const size_t gsz = (size_t)2 * gx * gy * gz;
+    const size_t goff = (((size_t)((bc & 3) == 3 ? 1 : 0) * gx + fold(kx, Lx)) * gz + fold(kz, Lz)) * gy;
+    const R sg = conj_g ? R(-1) : R(1);
+    cplx<R> acc[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) acc[q] = cplx<R>{0, 0};
+    for (int m = 1; m <= nm; ++m) {
+        int s = (cur - m) % ng;
+        if (s < 0) s += ng;
+        const V t = __builtin_nontemporal_load(reinterpret_cast<const V*>(ring + (size_t)s * slot + gid));
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            cplx<R> gv = G[(size_t)m * gsz + goff + fold(ky + q, Ly)];
+            gv.y *= sg;
+            acc[q] += cmul_fma(gv, cplx<R>{t[2 * q], t[2 * q + 1]});
+        }
+    }
+    V o;
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        o[2 * q] = acc[q].x;
+        o[2 * q + 1] = acc[q].y;
+    }
+    *reinterpret_cast<V*>(S + gid) = o;
+}
+
 template <typename R, int N, int NGX>
 __global__ void __launch_bounds__(256) k_ring_far(const cplx<R>* __restrict__ ring, const cplx<R>* __restrict__ G,
                                                   cplx<R>* __restrict__ F, GridDims g, int ng, int r0, int pb,

@@ -79,6 +79,7 @@ struct etaim_ctx {
     void *lam_r = nullptr, *nw_r = nullptr, *near_r = nullptr, *nearT_r = nullptr, *ghat_r = nullptr, *tw_r[3] = {};
     void* ghatT_r = nullptr;  // ky/kz-exchanged copy for the z-lines-first plane kernel
     void *A = nullptr, *P = nullptr, *ring = nullptr;
+    void* S = nullptr;  // line-pass engine: full-spectrum work array [bc][kx][kz][ky] (allocated on first use)
     // register x stage: anterpolated grid q[bc][z][x][y], zero outside the
     // nodes some basis reaches (anodes, as plane indices)
     void* Q = nullptr;
@@ -266,6 +267,14 @@ int lines_per_block(const Radix& pl) {
     return mt;
 }
 
+// a radix plan whose lines the LDS line kernel can take (at least one line
+// per block within the LDS budget)
+template <typename R>
+bool line_fits(const Radix& pl) {
+    const int mt = lines_per_block<R>(pl);
+    return plane_fits(mt, pl) && ((size_t)mt * (pl.L + 1) + pl.L) * sizeof(cplx<R>) <= (size_t)kLdsBudget;
+}
+
 template <typename R>
 int launch_lines(etaim_ctx* c, const cplx<R>* in, cplx<R>* out, const cplx<R>* tw, const Radix& pl, int nf,
                  int nslow, int in_len, int out_len, long long in_f, long long in_s, long long in_p,
@@ -338,6 +347,42 @@ struct Ops {
         return (const cplx<R>*)(conj ? c->nearT_r : c->near_r);
     }
     static cplx<R>* ring(etaim_ctx* c) { return (cplx<R>*)c->ring; }
+    static cplx<R>* S(etaim_ctx* c) { return (cplx<R>*)c->S; }
+
+    // ---- line-pass y/z engine (yz_engine 3): S = the y/z spectrum of the A planes
+    static int ensure_S(etaim_ctx* c) {
+        if (c->S) return ETAIM_OK;
+        if (c->capturing) return fail(ETAIM_EUNSUPPORTED, "the line-pass work array is not allocated");
+        return c->allocv(c->S, (size_t)4 * c->B * c->Np * sizeof(cplx<R>));
+    }
+    // A[bc][kx][z][y] -> S rows z < Nz: zero-padded forward y transforms
+    static int ylines_fwd(etaim_ctx* c, const int* gate) {
+        const GridDims& g = c->gd;
+        const long long Ny = g.N[1], Nz = g.N[2], Ly = g.L[1], Lz = g.L[2];
+        return launch_lines<R>(c, A(c), S(c), tw(c, 1), c->ry, (int)Nz, 4 * c->B * g.L[0], (int)Ny, (int)Ly, Ny,
+                               Ny * Nz, 1, Ly, Ly * Lz, 1, false, 0, 0, 0, gate);
+    }
+    // S rows z < Nz -> A[bc][kx][z][y]: inverse y transforms kept to y < Ny
+    static int ylines_inv(etaim_ctx* c, const int* gate) {
+        const GridDims& g = c->gd;
+        const long long Ny = g.N[1], Nz = g.N[2], Ly = g.L[1], Lz = g.L[2];
+        return launch_lines<R>(c, S(c), A(c), tw(c, 1), c->ry, (int)Nz, 4 * c->B * g.L[0], (int)Ly, (int)Ny, Ly,
+                               Ly * Lz, 1, Ny, Ny * Nz, 1, true, 0, 0, 0, gate);
+    }
+    // S rows z < Nz -> out (every kz): zero-padded forward z transforms
+    static int zlines_fwd(etaim_ctx* c, cplx<R>* out) {
+        const GridDims& g = c->gd;
+        const long long Nz = g.N[2], Ly = g.L[1], Lz = g.L[2];
+        return launch_lines<R>(c, S(c), out, tw(c, 2), c->rz, (int)Ly, 4 * c->B * g.L[0], (int)Nz, (int)Lz, 1,
+                               Ly * Lz, Ly, 1, Ly * Lz, Ly, false);
+    }
+    // S (every kz) -> S rows z < Nz: inverse z transforms, in place
+    static int zlines_inv(etaim_ctx* c) {
+        const GridDims& g = c->gd;
+        const long long Nz = g.N[2], Ly = g.L[1], Lz = g.L[2];
+        return launch_lines<R>(c, S(c), S(c), tw(c, 2), c->rz, (int)Ly, 4 * c->B * g.L[0], (int)Lz, (int)Nz, 1,
+                               Ly * Lz, Ly, 1, Ly * Lz, Ly, true);
+    }
 
     // anterpolate x (optionally scaled by dinv) and forward x pass -> A
     static int gather_rows(etaim_ctx* c) {
@@ -418,6 +463,18 @@ struct Ops {
         const GridDims& g = c->gd;
         dim3 grid(g.L[0], 4 * c->B);
         const double s = sizeof(cplx<R>);
+        if (c->yz_engine == 3) {
+            CHK(ensure_S(c));
+            Trace t(c, ETAIM_K_YZ_GREEN, 2.0 * 4 * c->B * g.L[0] * g.N[2] * g.N[1] * s + 2.0 * c->gfold * s);
+            CHK(ylines_fwd(c, gate));
+            const int mt = lines_per_block<R>(c->rz);
+            const size_t lds = ((size_t)mt * (g.L[2] + 1) + g.L[2]) * sizeof(cplx<R>);
+            hipLaunchKernelGGL(k_zlines_green<R>, dim3((g.L[1] + mt - 1) / mt, 4 * c->B * g.L[0]), dim3(kPlaneThreads),
+                               lds, c->stream, S(c), ghat(c) + (size_t)m * 2 * c->gfold, tw(c, 2), c->rz, g, mt, conj,
+                               gate);
+            HIPCHK(hipGetLastError());
+            return ylines_inv(c, gate);
+        }
         Trace t(c, ETAIM_K_YZ_GREEN, 2.0 * 4 * c->B * g.L[0] * g.N[2] * g.N[1] * s + 2.0 * c->gfold * s, true);
         if (c->yz_engine == 2) {
             const cplx<R>* G = ghatT(c) + (size_t)m * 2 * c->gfold;
@@ -506,7 +563,8 @@ struct Ops {
     // Captured into a whole-step graph (sr.sd set) the step's values come from
     // its descriptor; graph_far then says whether the time-block pass runs.
     static bool blocks_on(const etaim_ctx* c) {
-        return c->yz_engine >= 1 && c->delay_block > 1 && c->st.ng <= kFarMaxNg && c->delay_block <= kFarMaxBlock;
+        return (c->yz_engine == 1 || c->yz_engine == 2) && c->delay_block > 1 && c->st.ng <= kFarMaxNg &&
+               c->delay_block <= kFarMaxBlock;
     }
     static int delayed(etaim_ctx* c, int cur, const zd* V, zd* rhs, int conj, StepRef sr = {}, int graph_far = 0) {
         const GridDims& g = c->gd;
@@ -527,7 +585,18 @@ struct Ops {
             const double s = sizeof(cplx<R>), slot_b = 4.0 * c->B * c->Np * s, green_b = 2.0 * c->gfold * s;
             double bytes = nmx * (slot_b + green_b) + 4.0 * c->B * g.L[0] * g.N[2] * g.N[1] * s;
             if (blocked) bytes += slot_b;
-            if (c->yz_engine >= 1) {
+            if (c->yz_engine == 3) {
+                // the direct sum over the history into S, then the inverse z and y passes
+                if (graph) return fail(ETAIM_EUNSUPPORTED, "whole-step graph: needs the register plane kernels");
+                CHK(ensure_S(c));
+                Trace t(c, ETAIM_K_YZ_DELAYED, bytes);
+                const size_t vecs = (size_t)4 * c->B * c->Np * sizeof(cplx<R>) / 16;
+                hipLaunchKernelGGL(k_delay_sum<R>, dim3((unsigned)((vecs + 255) / 256)), dim3(256), 0, c->stream,
+                                   (const cplx<R>*)ring(c), ghat(c), S(c), g, ng, cur, nm, conj);
+                HIPCHK(hipGetLastError());
+                CHK(zlines_inv(c));
+                CHK(ylines_inv(c, nullptr));
+            } else if (c->yz_engine >= 1) {
                 const size_t slot = (size_t)4 * c->B * c->Np;
                 const cplx<R>* Fj = nullptr;
                 if (blocked) {
@@ -633,6 +702,13 @@ struct Ops {
         if (sr.sd && c->yz_engine != 2)
             return fail(ETAIM_EUNSUPPORTED, "whole-step graph: needs the z-lines-first plane kernels");
         const GridDims& g = c->gd;
+        if (c->yz_engine == 3) {
+            CHK(ensure_S(c));
+            const double s = sizeof(cplx<R>);
+            Trace t(c, ETAIM_K_YZ_COMMIT, 4.0 * c->B * g.L[0] * g.N[2] * g.N[1] * s + 4.0 * c->B * c->Np * s);
+            CHK(ylines_fwd(c, nullptr));
+            return zlines_fwd(c, slot);
+        }
         {
             const double s = sizeof(cplx<R>);
             Trace t(c, ETAIM_K_YZ_COMMIT, 4.0 * c->B * g.L[0] * g.N[2] * g.N[1] * s + 4.0 * c->B * c->Np * s, true);
@@ -665,7 +741,8 @@ struct Ops {
     }
     // allow the plane kernels and the gather their dynamic LDS
     static int set_lds(etaim_ctx* c) {
-        const int bytes = (int)plane_lds(c);
+        // (a plane larger than the LDS runs on the line-pass engine instead)
+        const int bytes = (int)std::min(plane_lds(c), (size_t)160 * 1024);
         for (const void* f : {(const void*)k_yz_green<R>, (const void*)k_yz_commit<R>, (const void*)k_yz_delayed<R>})
             HIPCHK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
         for (const void* f : {(const void*)k_yzq_green<R, 16>, (const void*)k_yzq_green<R, 24>,
@@ -678,6 +755,8 @@ struct Ops {
                               (const void*)k_yzc_green<R, 48>, (const void*)k_yzc_commit<R, 16>,
                               (const void*)k_yzc_commit<R, 24>, (const void*)k_yzc_commit<R, 48>})
             HIPCHK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+        HIPCHK(hipFuncSetAttribute((const void*)k_zlines_green<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   160 * 1024));
         for (const void* f : {(const void*)k_interp_tile<R, 1>, (const void*)k_interp_tile<R, 2>,
                               (const void*)k_interp_tile<R, 4>})
             HIPCHK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
@@ -1566,11 +1645,14 @@ int make_working(etaim_ctx* c) {
     CHK(c->allocv(c->xs, nB * (size_t)c->ns * sizeof(cplx<R>)));
     const size_t ring_cols = c->ring_cols > 0 ? (size_t)c->ring_cols : nB;
     CHK(c->allocv(c->ring, (size_t)c->st.ng * 4 * ring_cols * c->Np * sizeof(cplx<R>)));
-    // plane kernels: LDS and per-thread register staging limits
-    const size_t lds = Ops<R>::plane_lds(c);
-    if (lds > 160 * 1024 || Ops<R>::gather_lds(c) > 160 * 1024 || !plane_fits(c->gd.N[2], c->ry) ||
-        !plane_fits(c->gd.L[1], c->rz) || !plane_fits(4, c->rx))
-        return fail(ETAIM_EUNSUPPORTED, "the padded (y, z) plane does not fit the LDS plane kernels");
+    // plane kernels: LDS and per-thread register staging limits; where the
+    // padded (y, z) plane does not fit, the line-pass engine takes the y/z stage
+    const bool plane_ok = Ops<R>::plane_lds(c) <= 160 * 1024 && plane_fits(c->gd.N[2], c->ry) &&
+                          plane_fits(c->gd.L[1], c->rz);
+    if (c->yz_engine == 0 && !plane_ok) c->yz_engine = 3;
+    if (Ops<R>::gather_lds(c) > 160 * 1024 || !plane_fits(4, c->rx) ||
+        (c->yz_engine == 3 && !(line_fits<R>(c->ry) && line_fits<R>(c->rz))))
+        return fail(ETAIM_EUNSUPPORTED, "the padded grid's lines do not fit the LDS line kernels");
     CHK(Ops<R>::set_lds(c));
     return ETAIM_OK;
 }

@@ -66,10 +66,15 @@ bool shape_fits(const etaim_ctx* c, const Shape& s) {
     const int mr = s.mr > 0 ? s.mr : auto_gather_rows<R>(c, s.rx);
     const int mt = s.mt > 0 ? s.mt : lines_per_block<R>(s.rx);
     const size_t e = sizeof(cplx<R>), Lx = (size_t)g.L[0];
-    return plane_fits(g.N[2], s.ry) && plane_fits(g.L[1], s.rz) && plane_fits(4 * mr, s.rx) &&
+    const bool yz_fits =
+        s.engine == 3 ? (line_fits<R>(s.ry) && line_fits<R>(s.rz))
+                      : (plane_fits(g.N[2], s.ry) && plane_fits(g.L[1], s.rz) &&
+                         (s.engine != 0 || ((size_t)g.L[2] * (g.L[1] + 1) + g.L[1] + g.L[2]) * sizeof(cplx<R>) <=
+                                               (size_t)160 * 1024));
+    return yz_fits && plane_fits(4 * mr, s.rx) &&
            plane_fits(mt, s.rx) && (4 * (size_t)mr * (Lx + 1) + Lx) * e <= 160 * 1024 &&
            ((size_t)mt * (Lx + 1) + Lx) * e <= (size_t)kLdsBudget && s.waves >= 1 && s.waves <= 4 &&
-           s.sync >= 1 && s.sync <= c->prm.restart && (s.engine == 0 || ((s.engine == 1 || s.engine == 2) && quad_n(c) > 0)) &&
+           s.sync >= 1 && s.sync <= c->prm.restart && (s.engine == 0 || s.engine == 3 || ((s.engine == 1 || s.engine == 2) && quad_n(c) > 0)) &&
            (s.xeng == 0 || (s.xeng == 1 && xline_n(c) > 0)) && s.guess >= 0 && s.guess <= kMaxGuess &&
            (s.precond == 0 || s.precond == 1) && s.dblock >= 1 && s.dblock <= kFarMaxBlock &&
            (s.ieng == 0 || (s.ieng == 1 && c->ntiles > 0 && interp_tile_lds<R>(c) <= 160 * 1024));
@@ -95,9 +100,11 @@ void put_shape(etaim_ctx* c, const Shape& s) {
     c->sync_every = s.sync;
     c->use_graph = s.graph == 1;
     c->step_graph = s.graph == 2;
-    // the LDS and register engines lay the spectrum ring out differently: a
-    // change between them invalidates the history (and its block sums)
-    if ((c->yz_engine == 0) != (s.engine == 0)) {
+    // the register engines lay the spectrum ring out by parity quadrants, the
+    // LDS and line-pass engines plainly: a change between the two layouts
+    // invalidates the history (and its block sums)
+    auto quad = [](int e) { return e == 1 || e == 2; };
+    if (quad(c->yz_engine) != quad(s.engine)) {
         c->next_step = -1;
         c->far_r0 = -1;
     }
@@ -408,7 +415,7 @@ int autotune_impl(etaim_ctx* c, int budget_ms, etaim_tuning* out) {
         put_shape(c, best);
         return ETAIM_OK;
     };
-    for (int eng : {0, 1, 2})
+    for (int eng : {0, 1, 2, 3})
         if (eng != best.engine) {
             Shape s = best;
             s.engine = eng;
@@ -464,7 +471,7 @@ int autotune_impl(etaim_ctx* c, int budget_ms, etaim_tuning* out) {
     if (best.mt == 0) best.mt = lines_per_block<R>(best.rx);
     put_shape(c, best);
     // time blocks of the delayed field (register engine only)
-    if (best.engine >= 1 && c->st.ng > 2) {
+    if ((best.engine == 1 || best.engine == 2) && c->st.ng > 2) {
         double d_best = 0;
         CHK(time_delayed<R>(c, b, d_best));
         for (int pb : {1, 2, 3, 4, 5, 6, 7, 8}) {

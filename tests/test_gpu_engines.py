@@ -1,7 +1,7 @@
 """The y/z plane engines (LDS-staged radix passes over the padded plane,
-register-resident parity quadrants, and the same with the matvec plane
-transform taking the z lines first) against the FP64 oracle, through the
-C ABI.
+register-resident parity quadrants, the same with the matvec plane
+transform taking the z lines first, and separate y- and z-line passes over
+a full-spectrum work array) against the FP64 oracle, through the C ABI.
 
 At the level-4 sphere (48^3 grid, the size the bench marches) the oracle's
 exact near-zone entries take minutes to assemble on the host, so the
@@ -60,7 +60,7 @@ def _with_engine(P, engine):
     assert (t["yz_engine"], t["x_engine"]) == (yz, xe)
 
 
-ENGINES = [(0, 0), (1, 1), (1, 0), (0, 1), (2, 1), (2, 0)]
+ENGINES = [(0, 0), (1, 1), (1, 0), (0, 1), (2, 1), (2, 0), (3, 0), (3, 1)]
 
 
 @pytest.mark.parametrize("engine", ENGINES, ids=[f"yz{a}_x{b}" for a, b in ENGINES])
@@ -259,4 +259,33 @@ def test_interp_tiles_full_operator_level2(torch, batch):
     e = rel(b, ref)
     _say("L2 tiles batch", batch, "delayed rel", e)
     assert e <= 1e-12
+    P.close()
+
+
+@pytest.mark.parametrize("prec,grid,tol", [(0, 54, 1e-12), (1, 72, 1e-5)], ids=["fp64_54", "fp32_72"])
+def test_line_engine_where_planes_do_not_fit(torch, prec, grid, tol):
+    """A padded (y, z) plane larger than the LDS (108^2 FP64 = 186 KB, 144^2
+    FP32 = 166 KB) puts the y/z stage on the line-pass engine by itself: the
+    level-3 sphere on that grid, far operator Z_m for m > M_n and the
+    delayed field of a history whose first M_n samples are zero, against
+    the oracle."""
+    s, A, p = _oracle_far_grid(L3, grid)
+    ng = p["ng"]
+    assert A.mn < ng
+    P = gpu_problem(L3, precision=prec, batch=2, nt=8, grid=grid)
+    assert P.tuning()["yz_engine"] == 3 and P.info["mn"] == A.mn
+    x = W.complex_normal(40, (2, s.ns))
+    for m in range(A.mn + 1, ng + 1):
+        y = P.apply_z(m, _dev(torch, x)).cpu().numpy()
+        ref = np.array([A.far_matvec(m, xb) for xb in x])
+        e = rel(y, ref)
+        _say("line engine", grid, "fp32" if prec else "fp64", "m", m, "rel", e)
+        assert e <= tol, (m, e)
+    hist = W.complex_normal(41, (ng, 2, s.ns))
+    hist[:A.mn] = 0.0
+    b = P.delayed_field(_dev(torch, hist)).cpu().numpy()
+    ref = np.array([sum(A.far_matvec(m, hist[m - 1, j]) for m in range(A.mn + 1, ng + 1)) for j in range(2)])
+    e = rel(b, ref)
+    _say("line engine", grid, "delayed rel", e)
+    assert e <= tol
     P.close()
