@@ -58,8 +58,17 @@ def dt_from_ng(rmax: float, ng: int, lmax: int = Q_CPPIF) -> float:
 
 
 def rmax_of(xyz: np.ndarray) -> float:
-    """Largest vertex-to-vertex distance of the mesh (brute force)."""
+    """Largest vertex-to-vertex distance of the mesh: brute force over the
+    vertices of the point set's convex hull (a farthest pair of points is a
+    pair of hull vertices); over all vertices where the hull is degenerate
+    or the set is small."""
     xyz = np.asarray(xyz, dtype=np.float64)
+    if len(xyz) > 2048:
+        try:
+            from scipy.spatial import ConvexHull
+            xyz = xyz[ConvexHull(xyz).vertices]
+        except Exception:       # flat or degenerate point sets: all vertices
+            pass
     best = 0.0
     for s in range(0, len(xyz), 512):
         d = xyz[s:s + 512, None, :] - xyz[None, :, :]

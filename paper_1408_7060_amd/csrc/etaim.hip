@@ -45,6 +45,8 @@ int fail(int code, const std::string& msg) {
     } while (0)
 
 constexpr int kLdsBudget = 64 * 1024;
+// largest grid y dimension of a launch
+constexpr size_t kMaxGridY = 65535;
 
 int pick_lines(int L, size_t elem, int cap) {
     int mt = (int)(kLdsBudget / (2 * (size_t)(L + 1) * elem));
@@ -390,8 +392,9 @@ struct Ops {
         const int Lx = c->gd.L[0];
         if (c->gather_rows_t > 0) return c->gather_rows_t;
         int mr = sizeof(R) == 4 ? 16 : 8;
-        while (mr > 1 && !plane_fits(4 * mr, c->rx)) mr /= 2;
-        (void)Lx;
+        while (mr > 1 && (!plane_fits(4 * mr, c->rx) ||
+                          (4 * (size_t)mr * (Lx + 1) + Lx) * sizeof(cplx<R>) > (size_t)160 * 1024))
+            mr /= 2;
         return mr;
     }
     static size_t gather_lds(etaim_ctx* c) {
@@ -1653,6 +1656,9 @@ int make_working(etaim_ctx* c) {
     if (Ops<R>::gather_lds(c) > 160 * 1024 || !plane_fits(4, c->rx) ||
         (c->yz_engine == 3 && !(line_fits<R>(c->ry) && line_fits<R>(c->rz))))
         return fail(ETAIM_EUNSUPPORTED, "the padded grid's lines do not fit the LDS line kernels");
+    // the line launches index (bc, kx) or (bc, z) planes by the grid's y dimension
+    if ((c->yz_engine == 3 && 4 * nB * c->gd.L[0] > kMaxGridY) || ((c->x_engine == 0 || !xline_n(c)) && 4 * nB * c->gd.N[2] > kMaxGridY))
+        return fail(ETAIM_EUNSUPPORTED, "batch too large for the line kernels at this grid (4 B L_x planes)");
     CHK(Ops<R>::set_lds(c));
     return ETAIM_OK;
 }

@@ -46,7 +46,9 @@ struct Shape {
 template <typename R>
 int auto_gather_rows(const etaim_ctx* c, const Radix& rx) {
     int mr = sizeof(R) == 4 ? 16 : 8;
-    while (mr > 1 && !plane_fits(4 * mr, rx)) mr /= 2;
+    const size_t lx = (size_t)rx.L;
+    while (mr > 1 && (!plane_fits(4 * mr, rx) || (4 * (size_t)mr * (lx + 1) + lx) * sizeof(cplx<R>) > 160 * 1024))
+        mr /= 2;
     return mr;
 }
 
@@ -71,6 +73,8 @@ bool shape_fits(const etaim_ctx* c, const Shape& s) {
                       : (plane_fits(g.N[2], s.ry) && plane_fits(g.L[1], s.rz) &&
                          (s.engine != 0 || ((size_t)g.L[2] * (g.L[1] + 1) + g.L[1] + g.L[2]) * sizeof(cplx<R>) <=
                                                (size_t)160 * 1024));
+    const size_t nb = (size_t)c->B;
+    if ((s.engine == 3 && 4 * nb * g.L[0] > kMaxGridY) || (s.xeng == 0 && 4 * nb * g.N[2] > kMaxGridY)) return false;
     return yz_fits && plane_fits(4 * mr, s.rx) &&
            plane_fits(mt, s.rx) && (4 * (size_t)mr * (Lx + 1) + Lx) * e <= 160 * 1024 &&
            ((size_t)mt * (Lx + 1) + Lx) * e <= (size_t)kLdsBudget && s.waves >= 1 && s.waves <= 4 &&

@@ -97,6 +97,176 @@ def rwg_table(tri: np.ndarray) -> np.ndarray:
     return np.array(rows, dtype=np.int32).reshape(-1, 4)
 
 
+def _merge(parts):
+    """Concatenate meshes (xyz, tri) into one."""
+    xyz, tri, off = [], [], 0
+    for v, t in parts:
+        xyz.append(v)
+        tri.append(t + off)
+        off += len(v)
+    return np.concatenate(xyz), np.concatenate(tri).astype(np.int32)
+
+
+def _orient_outward(xyz, tri, centre):
+    """Flip triangles whose normal points towards the centre of their
+    (convex) object."""
+    p0, p1, p2 = xyz[tri[:, 0]], xyz[tri[:, 1]], xyz[tri[:, 2]]
+    nrm = np.cross(p1 - p0, p2 - p0)
+    flip = np.einsum("ij,ij->i", nrm, (p0 + p1 + p2) / 3.0 - centre) < 0
+    tri = tri.copy()
+    tri[flip] = tri[flip][:, [0, 2, 1]]
+    return tri
+
+
+def box_mesh(centre, size, edge):
+    """Closed surface of an axis-aligned box: each face a structured grid of
+    rectangles no longer than `edge` per side, each split into two
+    triangles; vertices shared along the box edges."""
+    centre, size = np.asarray(centre, float), np.asarray(size, float)
+    n = np.maximum(1, np.ceil(size / edge).astype(int))
+    index, xyz, tri = {}, [], []
+
+    def vid(i, j, k):
+        key = (i, j, k)
+        if key not in index:
+            index[key] = len(xyz)
+            xyz.append(centre - size / 2 + size * np.array([i, j, k]) / n)
+        return index[key]
+
+    for a in range(3):
+        b, c = (a + 1) % 3, (a + 2) % 3
+        for side in (0, n[a]):
+            for u in range(n[b]):
+                for v in range(n[c]):
+                    q = []
+                    for du, dv in ((0, 0), (1, 0), (1, 1), (0, 1)):
+                        ijk = [0, 0, 0]
+                        ijk[a], ijk[b], ijk[c] = side, u + du, v + dv
+                        q.append(vid(*ijk))
+                    tri += [(q[0], q[1], q[2]), (q[0], q[2], q[3])]
+    xyz = np.array(xyz)
+    return xyz, _orient_outward(xyz, np.array(tri, dtype=np.int32), centre)
+
+
+def _zip_rings(ia, ta, ib, tb):
+    """Triangles between two closed rings of vertices (indices ia, ib at
+    angles ta, tb, increasing), advancing along the ring whose next vertex
+    comes first in angle."""
+    na, nb = len(ia), len(ib)
+    i = j = 0
+    tri = []
+    while i < na or j < nb:
+        a0, b0 = ia[i % na], ib[j % nb]
+        na_ang = ta[(i + 1) % na] + (2 * math.pi if i + 1 >= na else 0.0)
+        nb_ang = tb[(j + 1) % nb] + (2 * math.pi if j + 1 >= nb else 0.0)
+        if j >= nb or (i < na and na_ang <= nb_ang):
+            tri.append((a0, ia[(i + 1) % na], b0))
+            i += 1
+        else:
+            tri.append((a0, ib[(j + 1) % nb], b0))
+            j += 1
+    return tri
+
+
+def cylinder_mesh(centre, radius, height, axis, edge):
+    """Closed surface of a circular cylinder along coordinate `axis`: the
+    side a structured grid (n_theta around, n_h along), each cap concentric
+    rings zipped together down to a centre vertex; the caps' outer rings
+    are the side's end rings."""
+    centre = np.asarray(centre, float)
+    nt = max(8, int(math.ceil(2 * math.pi * radius / edge)))
+    nh = max(1, int(math.ceil(height / edge)))
+    nr = max(1, int(math.ceil(radius / edge)))
+    b, c = (axis + 1) % 3, (axis + 2) % 3
+    xyz, tri = [], []
+
+    def point(r, th, z):
+        p = centre.copy()
+        p[b] += r * math.cos(th)
+        p[c] += r * math.sin(th)
+        p[axis] += z
+        return p
+
+    ang = 2 * math.pi * np.arange(nt) / nt
+    side = []
+    for h in range(nh + 1):
+        row = []
+        for t in range(nt):
+            row.append(len(xyz))
+            xyz.append(point(radius, ang[t], -height / 2 + height * h / nh))
+        side.append(row)
+    for h in range(nh):
+        for t in range(nt):
+            q = (side[h][t], side[h][(t + 1) % nt], side[h + 1][(t + 1) % nt], side[h + 1][t])
+            tri += [(q[0], q[1], q[2]), (q[0], q[2], q[3])]
+    for h, z in ((0, -height / 2), (nh, height / 2)):
+        outer, oang = side[h], ang
+        for k in range(nr - 1, 0, -1):
+            rk = radius * k / nr
+            n_k = max(3, int(math.ceil(2 * math.pi * rk / edge)))
+            kang = 2 * math.pi * (np.arange(n_k) + 0.5 * (k % 2)) / n_k
+            ring = []
+            for t in range(n_k):
+                ring.append(len(xyz))
+                xyz.append(point(rk, kang[t], z))
+            tri += _zip_rings(outer, oang, ring, kang)
+            outer, oang = ring, kang
+        ctr = len(xyz)
+        xyz.append(point(0.0, 0.0, z))
+        m = len(outer)
+        tri += [(outer[t], outer[(t + 1) % m], ctr) for t in range(m)]
+    xyz = np.array(xyz)
+    tri = np.array(tri, dtype=np.int32)
+    # orient each triangle outward: side triangles radially, cap triangles along the axis
+    p0, p1, p2 = xyz[tri[:, 0]], xyz[tri[:, 1]], xyz[tri[:, 2]]
+    nrm = np.cross(p1 - p0, p2 - p0)
+    cen = (p0 + p1 + p2) / 3.0 - centre
+    out = cen.copy()
+    cap = np.abs(np.abs(cen[:, axis]) - height / 2) < 1e-9
+    out[~cap, axis] = 0.0
+    out[cap] = 0.0
+    out[cap, axis] = np.sign(cen[cap, axis])
+    flip = np.einsum("ij,ij->i", nrm, out) < 0
+    tri[flip] = tri[flip][:, [0, 2, 1]]
+    return xyz, tri
+
+
+def composite(seed: int, n: int = 6, cube: float = 5.4, smin: float = 0.5, smax: float = 3.0,
+              edge: float = 0.02855, gap_edges: float = 2.0):
+    """Union of n seeded, disjoint, axis-aligned boxes and cylinders (stream
+    5) inside a cube of side `cube` centred at the origin: kind (box or
+    cylinder, even odds), sizes log-uniform in [smin, smax] (box sides;
+    cylinder diameter and height), a random axis for a cylinder, the
+    position uniform where the object fits; placements whose bounding boxes
+    come closer than gap_edges edge lengths to an earlier object are drawn
+    again.  Returns (xyz, tri) meshed at edge length `edge`."""
+    g = rng(seed, 5)
+    placed, parts = [], []
+    while len(placed) < n:
+        kind = "box" if g.uniform() < 0.5 else "cylinder"
+        if kind == "box":
+            size = np.exp(g.uniform(math.log(smin), math.log(smax), 3))
+            axis = -1
+        else:
+            d, hgt = np.exp(g.uniform(math.log(smin), math.log(smax), 2))
+            axis = int(g.integers(0, 3))
+            size = np.full(3, d)
+            size[axis] = hgt
+        if np.any(size > cube):
+            continue
+        centre = g.uniform(-cube / 2 + size / 2, cube / 2 - size / 2)
+        lo, hi = centre - size / 2, centre + size / 2
+        gap = gap_edges * edge
+        if any(np.all(lo < h2 + gap) and np.all(l2 < hi + gap) for l2, h2 in placed):
+            continue
+        placed.append((lo, hi))
+        if kind == "box":
+            parts.append(box_mesh(centre, size, edge))
+        else:
+            parts.append(cylinder_mesh(centre, size[(axis + 1) % 3] / 2, size[axis], axis, edge))
+    return _merge(parts)
+
+
 # ---------------------------------------------------------------- seeds
 
 def rng(seed: int, stream: int) -> np.random.Generator:
@@ -148,7 +318,10 @@ def complex_normal(seed: int, shape, stream: int = 6) -> np.ndarray:
 
 @dataclass
 class Workload:
-    """One synthetic benchmark problem (a sphere meshed as an icosphere)."""
+    """One synthetic benchmark problem: a sphere meshed as an icosphere
+    (level, radius), or, with composite_seed set, the composite object of
+    ``composite`` meshed at edge length lambda_min / 10, lambda_min the
+    wavelength at the top of the pulse band f0 (1 + frac_bw)."""
     name: str
     level: int
     radius: float
@@ -164,6 +337,7 @@ class Workload:
     dir_seed: int | None = None
     khat: tuple = (0.0, 0.0, -1.0)
     phat: tuple = (1.0, 0.0, 0.0)
+    composite_seed: int | None = None
     extra: dict = field(default_factory=dict)
 
     @property
@@ -179,7 +353,14 @@ class Workload:
     def td(self) -> float:
         return 8.0 * self.sigma
 
+    @property
+    def edge(self) -> float:
+        return C0 / (self.f0 * (1.0 + self.frac_bw)) / 10.0
+
     def mesh(self):
+        if self.composite_seed is not None:
+            xyz, tri = composite(self.composite_seed, edge=self.edge)
+            return xyz, tri, rwg_table(tri)
         rot = random_rotation(self.rotate_seed) if self.rotate_seed is not None else None
         xyz, tri = icosphere(self.level, self.radius, rot)
         return xyz, tri, rwg_table(tri)
@@ -211,5 +392,14 @@ SPHERE_L3 = Workload("sphere_L3_r1_300MHz", level=3, radius=1.0, f0=300e6, frac_
 SPHERE_L2_NARROW = Workload("sphere_L2_r0.5_300MHz_narrow", level=2, radius=0.5, f0=300e6, frac_bw=0.01,
                             nt=60, grid=16, near_lambda=0.3, beta=0.2)
 
+# composite object: six seeded boxes and cylinders of 0.5-3 m, edge
+# lambda_min/10 = 2.86 cm, 200 634 RWG; 192^3 grid (h = 2.45 cm), N_g = 32
+COMPOSITE = Workload("composite6_1GHz", level=0, radius=0.0, f0=1e9, frac_bw=0.05, nt=1000, grid=192,
+                     near_lambda=0.25, ng=32, composite_seed=0)
+# the same recipe at 250 MHz (edge 11.4 cm, 12 321 RWG, 48^3 grid): the
+# composite parity case at a size the oracle finishes in seconds
+COMPOSITE_SMALL = Workload("composite6_250MHz", level=0, radius=0.0, f0=250e6, frac_bw=0.05, nt=200, grid=48,
+                           near_lambda=0.25, ng=32, composite_seed=0)
+
 WORKLOADS = {w.name: w for w in (SPHERE_L2, SPHERE_L4, SPHERE_L4_BATCH, SPHERE_L4_ADJ, SPHERE_L3,
-                                 SPHERE_L2_NARROW)}
+                                 SPHERE_L2_NARROW, COMPOSITE, COMPOSITE_SMALL)}
