@@ -1004,6 +1004,72 @@ __global__ void __launch_bounds__(kPlaneThreads) k_zlines_green(cplx<R>* __restr
     }
 }
 
+// The same z stage with four-step z lines (L_z = A B, both factors register
+// codelets): the forward transform's first step loads rows z < N_z of MT
+// consecutive ky (lanes over the lines, so each row's loads are one run),
+// the second step, the Green product and the inverse's first step run in
+// the registers of the (ky, k1) tasks, and the inverse's second step stores
+// rows z < N_z back.
+template <typename R, int A, int B>
+__global__ void __launch_bounds__((lines4_threads<R, A, B>())) k_zg4(cplx<R>* __restrict__ S,
+                                                                  const cplx<R>* __restrict__ G,
+                                                                  const cplx<R>* __restrict__ twz_g, GridDims g,
+                                                                  int conj_g, const int* __restrict__ gate) {
+    if (gated_off(gate)) return;
+    constexpr int MT = lines4_mt<R>(), L = A * B;
+    extern __shared__ unsigned char smem_raw[];
+    cplx<R>* tw = reinterpret_cast<cplx<R>*>(smem_raw);
+    cplx<R>* Y = tw + L;
+    for (int i = threadIdx.x; i < L; i += blockDim.x) tw[i] = twz_g[i];
+    const int Ly = g.L[1], Lx = g.L[0], Nz = g.N[2];
+    const int ky0 = blockIdx.x * MT, pl = blockIdx.y, kx = pl % Lx, bc = pl / Lx;
+    cplx<R>* base = S + (size_t)pl * L * Ly;
+    __syncthreads();
+    for (int t = threadIdx.x; t < MT * B; t += blockDim.x) {
+        const int l = t % MT, n2 = t / MT, ky = ky0 + l;
+        cplx<R> u[A];
+#pragma unroll
+        for (int n1 = 0; n1 < A; ++n1) {
+            const int z = n2 + B * n1;
+            u[n1] = (ky < Ly && z < Nz) ? base[(size_t)z * Ly + ky] : cplx<R>{0, 0};
+        }
+        l4_fwd_first<R, A, B, MT, true>(u, Y, tw, l, n2);
+    }
+    __syncthreads();
+    const int gx = g.N[0] + 1, gy = g.N[1] + 1, gz = g.N[2] + 1;
+    const cplx<R>* Gk = G + ((size_t)((bc & 3) == 3 ? 1 : 0) * gx + fold(kx, Lx)) * ((size_t)gz * gy);
+    for (int t = threadIdx.x; t < MT * A; t += blockDim.x) {
+        const int l = t % MT, k1 = t / MT, ky = ky0 + l;
+        const int fy = fold(ky < Ly ? ky : 0, Ly);
+        cplx<R> u[B];
+#pragma unroll
+        for (int n2 = 0; n2 < B; ++n2) u[n2] = Y[l4_y<A, B, MT, true>(l, k1, n2)];
+        dft_small<R, B>(u, false);
+#pragma unroll
+        for (int k2 = 0; k2 < B; ++k2) {
+            cplx<R> gv = Gk[(size_t)fold(k1 + A * k2, L) * gy + fy];
+            if (conj_g) gv.y = -gv.y;
+            u[k2] = u[k2] * gv;
+        }
+        // the task rewrites only the Y entries it has just read
+        l4_inv_first<R, A, B, MT, true>(u, Y, tw, l, k1);
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < MT * B; t += blockDim.x) {
+        const int l = t % MT, n2 = t / MT, ky = ky0 + l;
+        cplx<R> u[A];
+#pragma unroll
+        for (int k1 = 0; k1 < A; ++k1) u[k1] = Y[l4_y<A, B, MT, true>(l, k1, n2)];
+        dft_small<R, A>(u, true);
+        if (ky < Ly)
+#pragma unroll
+            for (int n1 = 0; n1 < A; ++n1) {
+                const int z = n2 + B * n1;
+                if (z < Nz) base[(size_t)z * Ly + ky] = u[n1];
+            }
+    }
+}
+
 // Delayed-field sum of the line-pass engine: S = sum_{m=1}^{nm} G_m . ring
 // slot (cur - m) mod ng over every spectrum point [bc][kx][kz][ky]; a thread
 // owns one 16-byte vector of points (two in FP32) of one plane row and

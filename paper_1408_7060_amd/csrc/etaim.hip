@@ -277,6 +277,29 @@ bool line_fits(const Radix& pl) {
     return plane_fits(mt, pl) && ((size_t)mt * (pl.L + 1) + pl.L) * sizeof(cplx<R>) <= (size_t)kLdsBudget;
 }
 
+// one four-step line launch; the LDS attribute is raised once per instance
+// where the block's buffers pass 64 KB
+template <typename R, int A, int B, bool LF>
+int launch_l4(etaim_ctx* c, dim3 grid, const cplx<R>* in, cplx<R>* out, const cplx<R>* tw, const LineArgs& a) {
+    constexpr size_t lds = lines4_lds<R, A, B, LF>();
+    static bool attr = false;
+    if (lds > 64 * 1024 && !attr) {
+        HIPCHK(hipFuncSetAttribute((const void*)k_lines4<R, A, B, LF>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)lds));
+        attr = true;
+    }
+    hipLaunchKernelGGL((k_lines4<R, A, B, LF>), grid, dim3(lines4_threads<R, A, B>()), lds, c->stream, in, out, tw, a);
+    HIPCHK(hipGetLastError());
+    return ETAIM_OK;
+}
+template <typename R, int A, int B>
+int launch_l4(etaim_ctx* c, bool lf, dim3 grid, const cplx<R>* in, cplx<R>* out, const cplx<R>* tw,
+              const LineArgs& a) {
+    return lf ? launch_l4<R, A, B, true>(c, grid, in, out, tw, a) : launch_l4<R, A, B, false>(c, grid, in, out, tw, a);
+}
+// the four-step instances of lines4_split
+#define ETAIM_L4_SPLITS(X) X(8, 12) X(12, 12) X(8, 24) X(12, 24) X(16, 24) X(24, 24)
+
 template <typename R>
 int launch_lines(etaim_ctx* c, const cplx<R>* in, cplx<R>* out, const cplx<R>* tw, const Radix& pl, int nf,
                  int nslow, int in_len, int out_len, long long in_f, long long in_s, long long in_p,
@@ -298,6 +321,16 @@ int launch_lines(etaim_ctx* c, const cplx<R>* in, cplx<R>* out, const cplx<R>* t
     a.out_s = out_s;
     a.out_p = out_p;
     a.inverse = inverse ? 1 : 0;
+    int A4 = 0, B4 = 0;
+    if (lines4_split(pl.L, A4, B4)) {
+        // register four-step lines; lanes over the lines where the lines are adjacent
+        const bool lf = in_f == 1 || out_f == 1;
+        const dim3 grid4((nf + lines4_mt<R>() - 1) / lines4_mt<R>(), nslow);
+#define ETAIM_L4_CASE(AA, BB) \
+    if (A4 == AA && B4 == BB) return launch_l4<R, AA, BB>(c, lf, grid4, in, out, tw, a);
+        ETAIM_L4_SPLITS(ETAIM_L4_CASE)
+#undef ETAIM_L4_CASE
+    }
     a.mt = mt > 0 ? mt : lines_per_block<R>(pl);
     const size_t lds = ((size_t)a.mt * (pl.L + 1) + pl.L) * sizeof(cplx<R>);
     dim3 grid((nf + a.mt - 1) / a.mt, nslow);
@@ -370,6 +403,41 @@ struct Ops {
         const long long Ny = g.N[1], Nz = g.N[2], Ly = g.L[1], Lz = g.L[2];
         return launch_lines<R>(c, S(c), A(c), tw(c, 1), c->ry, (int)Nz, 4 * c->B * g.L[0], (int)Ly, (int)Ny, Ly,
                                Ly * Lz, 1, Ny, Ny * Nz, 1, true, 0, 0, 0, gate);
+    }
+    // S rows z < Nz: forward z transforms, product with the Green spectrum G,
+    // inverse, rows z < Nz stored back (four-step register lines where L_z
+    // splits, else the LDS passes)
+    template <int A, int B>
+    static int zg4(etaim_ctx* c, const cplx<R>* G, int conj, const int* gate) {
+        constexpr size_t lds = lines4_lds<R, A, B, true>();
+        static bool attr = false;
+        if (lds > 64 * 1024 && !attr) {
+            HIPCHK(hipFuncSetAttribute((const void*)k_zg4<R, A, B>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds));
+            attr = true;
+        }
+        const GridDims& g = c->gd;
+        const int mt = lines4_mt<R>();
+        hipLaunchKernelGGL((k_zg4<R, A, B>), dim3((g.L[1] + mt - 1) / mt, 4 * c->B * g.L[0]),
+                           dim3(lines4_threads<R, A, B>()), lds, c->stream, S(c), G, tw(c, 2), g, conj, gate);
+        HIPCHK(hipGetLastError());
+        return ETAIM_OK;
+    }
+    static int zlines_green(etaim_ctx* c, const cplx<R>* G, int conj, const int* gate) {
+        const GridDims& g = c->gd;
+        int A4 = 0, B4 = 0;
+        if (lines4_split(g.L[2], A4, B4)) {
+#define ETAIM_ZG4_CASE(AA, BB) \
+    if (A4 == AA && B4 == BB) return zg4<AA, BB>(c, G, conj, gate);
+            ETAIM_L4_SPLITS(ETAIM_ZG4_CASE)
+#undef ETAIM_ZG4_CASE
+        }
+        const int mt = lines_per_block<R>(c->rz);
+        const size_t lds = ((size_t)mt * (g.L[2] + 1) + g.L[2]) * sizeof(cplx<R>);
+        hipLaunchKernelGGL(k_zlines_green<R>, dim3((g.L[1] + mt - 1) / mt, 4 * c->B * g.L[0]), dim3(kPlaneThreads),
+                           lds, c->stream, S(c), G, tw(c, 2), c->rz, g, mt, conj, gate);
+        HIPCHK(hipGetLastError());
+        return ETAIM_OK;
     }
     // S rows z < Nz -> out (every kz): zero-padded forward z transforms
     static int zlines_fwd(etaim_ctx* c, cplx<R>* out) {
@@ -470,12 +538,7 @@ struct Ops {
             CHK(ensure_S(c));
             Trace t(c, ETAIM_K_YZ_GREEN, 2.0 * 4 * c->B * g.L[0] * g.N[2] * g.N[1] * s + 2.0 * c->gfold * s);
             CHK(ylines_fwd(c, gate));
-            const int mt = lines_per_block<R>(c->rz);
-            const size_t lds = ((size_t)mt * (g.L[2] + 1) + g.L[2]) * sizeof(cplx<R>);
-            hipLaunchKernelGGL(k_zlines_green<R>, dim3((g.L[1] + mt - 1) / mt, 4 * c->B * g.L[0]), dim3(kPlaneThreads),
-                               lds, c->stream, S(c), ghat(c) + (size_t)m * 2 * c->gfold, tw(c, 2), c->rz, g, mt, conj,
-                               gate);
-            HIPCHK(hipGetLastError());
+            CHK(zlines_green(c, ghat(c) + (size_t)m * 2 * c->gfold, conj, gate));
             return ylines_inv(c, gate);
         }
         Trace t(c, ETAIM_K_YZ_GREEN, 2.0 * 4 * c->B * g.L[0] * g.N[2] * g.N[1] * s + 2.0 * c->gfold * s, true);

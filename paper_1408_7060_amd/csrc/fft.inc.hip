@@ -397,4 +397,168 @@ __global__ void __launch_bounds__(kPlaneThreads) k_lines(const cplx<R>* in, cplx
     }
 }
 
+// ---------------------------------------------------------------------------
+// Four-step line FFT for L = A B points with both factors register codelets
+// (A, B dividing 48).  Index maps n = n2 + B n1, k = k1 + A k2 give
+//   X[k1 + A k2] = sum_n2 W_B^{n2 k2} W_L^{n2 k1} sum_n1 W_A^{n1 k1} x[n2 + B n1]
+// (W_L^{nk} = W_L^{n2 k1} W_B^{n2 k2} W_A^{n1 k1}).  A block takes MT lines:
+// tasks (line, n2) do the A-point DFTs in registers, scale by W_L^{n2 k1}
+// and write Y[line][k1][n2] to LDS; after one barrier, tasks (line, k1) read
+// their B values and do the B-point DFTs in registers.  The inverse runs
+// the same steps mirrored with conjugate twiddles (unnormalised).  Loads of
+// points >= in_len read as zero; outputs >= out_len are not stored.
+//
+// LF (lines fastest): lanes run over consecutive lines, for layouts whose
+// lines are adjacent in memory (a line's points strided); otherwise lanes
+// run over a line's points, for layouts whose points are adjacent.  Y is
+// laid out to match: [k1][n2][line] (LF) or [line][k1][n2 + pad] (points
+// fastest, rows of B + 1), so that the lanes of a wave touch consecutive
+// LDS words in both phases.
+template <typename R>
+__host__ __device__ constexpr int lines4_mt() {
+    return sizeof(R) == 4 ? 16 : 8;
+}
+template <typename R, int A, int B>
+__host__ __device__ constexpr int lines4_threads() {
+    return lines4_mt<R>() * (A > B ? A : B);
+}
+template <typename R, int A, int B, bool LF>
+__host__ __device__ constexpr int lines4_ysize() {
+    return LF ? A * B * lines4_mt<R>() : lines4_mt<R>() * A * (B + 1);
+}
+template <typename R, int A, int B, bool LF>
+__host__ __device__ constexpr size_t lines4_lds() {
+    return (size_t)(A * B + lines4_ysize<R, A, B, LF>()) * sizeof(cplx<R>);
+}
+
+template <int A, int B, int MT, bool LF>
+__device__ __forceinline__ int l4_y(int l, int k1, int n2) {
+    return LF ? (k1 * B + n2) * MT + l : (l * A + k1) * (B + 1) + n2;
+}
+
+// tasks over (line, j), j < J: t -> (l, j)
+template <int J, int MT, bool LF>
+__device__ __forceinline__ void l4_task(int t, int& l, int& j) {
+    if (LF) {
+        l = t % MT;
+        j = t / MT;
+    } else {
+        j = t % J;
+        l = t / J;
+    }
+}
+
+// forward: x (stride B per n1, loaded by the caller into u) -> Y
+template <typename R, int A, int B, int MT, bool LF>
+__device__ __forceinline__ void l4_fwd_first(cplx<R> (&u)[A], cplx<R>* Y, const cplx<R>* tw, int l, int n2) {
+    dft_small<R, A>(u, false);
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) Y[l4_y<A, B, MT, LF>(l, k1, n2)] = k1 ? u[k1] * tw[n2 * k1] : u[k1];
+}
+
+// inverse: X (stride A per k2, in u) -> Y
+template <typename R, int A, int B, int MT, bool LF>
+__device__ __forceinline__ void l4_inv_first(cplx<R> (&u)[B], cplx<R>* Y, const cplx<R>* tw, int l, int k1) {
+    dft_small<R, B>(u, true);
+#pragma unroll
+    for (int n2 = 0; n2 < B; ++n2) {
+        cplx<R> v = u[n2];
+        if (n2 && k1) {
+            cplx<R> w = tw[n2 * k1];
+            w.y = -w.y;
+            v = v * w;
+        }
+        Y[l4_y<A, B, MT, LF>(l, k1, n2)] = v;
+    }
+}
+
+template <typename R, int A, int B, bool LF>
+__global__ void __launch_bounds__((lines4_threads<R, A, B>())) k_lines4(const cplx<R>* in, cplx<R>* out,
+                                                                     const cplx<R>* __restrict__ tw_g,
+                                                                     LineArgs a) {
+    if (gated_off(a.gate)) return;
+    constexpr int MT = lines4_mt<R>(), L = A * B;
+    extern __shared__ unsigned char smem_raw[];
+    cplx<R>* tw = reinterpret_cast<cplx<R>*>(smem_raw);
+    cplx<R>* Y = tw + L;
+    for (int i = threadIdx.x; i < L; i += blockDim.x) tw[i] = tw_g[i];
+    const int f0 = blockIdx.x * MT;
+    const long long s0 = blockIdx.y % a.ns0, s1 = blockIdx.y / a.ns0;
+    const cplx<R>* ibase = in + s0 * a.in_s + s1 * a.in_s1;
+    cplx<R>* obase = out + s0 * a.out_s + s1 * a.out_s1;
+    __syncthreads();
+    if (!a.inverse) {
+        for (int t = threadIdx.x; t < MT * B; t += blockDim.x) {
+            int l, n2;
+            l4_task<B, MT, LF>(t, l, n2);
+            const int f = f0 + l;
+            cplx<R> u[A];
+#pragma unroll
+            for (int n1 = 0; n1 < A; ++n1) {
+                const int n = n2 + B * n1;
+                u[n1] = (f < a.nf && n < a.in_len) ? ibase[f * a.in_f + n * a.in_p] : cplx<R>{0, 0};
+            }
+            l4_fwd_first<R, A, B, MT, LF>(u, Y, tw, l, n2);
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < MT * A; t += blockDim.x) {
+            int l, k1;
+            l4_task<A, MT, LF>(t, l, k1);
+            const int f = f0 + l;
+            cplx<R> u[B];
+#pragma unroll
+            for (int n2 = 0; n2 < B; ++n2) u[n2] = Y[l4_y<A, B, MT, LF>(l, k1, n2)];
+            dft_small<R, B>(u, false);
+            if (f < a.nf)
+#pragma unroll
+                for (int k2 = 0; k2 < B; ++k2) {
+                    const int k = k1 + A * k2;
+                    if (k < a.out_len) obase[f * a.out_f + k * a.out_p] = u[k2];
+                }
+        }
+    } else {
+        for (int t = threadIdx.x; t < MT * A; t += blockDim.x) {
+            int l, k1;
+            l4_task<A, MT, LF>(t, l, k1);
+            const int f = f0 + l;
+            cplx<R> u[B];
+#pragma unroll
+            for (int k2 = 0; k2 < B; ++k2) {
+                const int k = k1 + A * k2;
+                u[k2] = (f < a.nf && k < a.in_len) ? ibase[f * a.in_f + k * a.in_p] : cplx<R>{0, 0};
+            }
+            l4_inv_first<R, A, B, MT, LF>(u, Y, tw, l, k1);
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < MT * B; t += blockDim.x) {
+            int l, n2;
+            l4_task<B, MT, LF>(t, l, n2);
+            const int f = f0 + l;
+            cplx<R> u[A];
+#pragma unroll
+            for (int k1 = 0; k1 < A; ++k1) u[k1] = Y[l4_y<A, B, MT, LF>(l, k1, n2)];
+            dft_small<R, A>(u, true);
+            if (f < a.nf)
+#pragma unroll
+                for (int n1 = 0; n1 < A; ++n1) {
+                    const int n = n2 + B * n1;
+                    if (n < a.out_len) obase[f * a.out_f + n * a.out_p] = u[n1];
+                }
+        }
+    }
+}
+
+// the (A, B) split of a line length with a four-step kernel, A <= B; false if none
+inline bool lines4_split(int L, int& A, int& B) {
+    switch (L) {
+        case 96: A = 8; B = 12; return true;
+        case 144: A = 12; B = 12; return true;
+        case 192: A = 8; B = 24; return true;
+        case 288: A = 12; B = 24; return true;
+        case 384: A = 16; B = 24; return true;
+        case 576: A = 24; B = 24; return true;
+        default: return false;
+    }
+}
+
 }  // namespace etaim
