@@ -47,6 +47,10 @@ int fail(int code, const std::string& msg) {
 constexpr int kLdsBudget = 64 * 1024;
 // largest grid y dimension of a launch
 constexpr size_t kMaxGridY = 65535;
+// batches up to this many columns apply the preconditioner with lane groups per row
+constexpr int kSpmvGroupMaxB = 4;
+// most blocks one dot product or norm is split over
+constexpr int kRedMaxChunks = 64;
 
 int pick_lines(int L, size_t elem, int cap) {
     int mt = (int)(kLdsBudget / (2 * (size_t)(L + 1) * elem));
@@ -97,6 +101,8 @@ struct etaim_ctx {
     double* perr = nullptr;  // extrapolation errors of the step just solved (+ block partials)
     // near-zone sparse approximate inverse (right preconditioner) and its transposed copy
     zd *sai = nullptr, *saiT = nullptr, *zt = nullptr;
+    // partial sums of the dot products and norms split over several blocks
+    void* redpart = nullptr;
     int precond = 1;  // 0: Jacobi diag(Z0)^-1, 1: near-zone sparse approximate inverse
     // interpolation by grid tiles: tile -> bases (CSR), tile origins [ntiles][3]
     int interp_engine = 0, ntiles = 0;
@@ -346,6 +352,13 @@ int xline_n(const etaim_ctx* c) {
     return (n == 16 || n == 24 || n == 48) ? n : 0;
 }
 
+// the register x stage applies: a register x-line codelet, or four-step
+// lines of length L_x (the anterpolated grid is then transformed by them)
+bool xreg_ok(const etaim_ctx* c) {
+    int A = 0, B = 0;
+    return xline_n(c) > 0 || (c->gd.L[0] == 2 * c->gd.N[0] && lines4_split(c->gd.L[0], A, B));
+}
+
 // N of the register quadrant kernels for this grid (N_y = N_z = N, N | 48
 // with a register codelet), 0 if they do not apply
 int quad_n(const etaim_ctx* c) {
@@ -487,6 +500,13 @@ struct Ops {
                 hipLaunchKernelGGL(k_anterp_nz<R>, dim3(blocks_for((size_t)c->n_anodes * c->B)), dim3(256), 0,
                                    c->stream, xs, c->anodes, c->n_anodes, c->nptr, c->nk, (const R*)c->nw_r, Q(c), g,
                                    c->B, gate);
+            if (!xline_n(c)) {
+                // four-step lines along x, q[bc][z][x][y] -> A[bc][kx][z][y], zero-padded
+                const long long Lx = g.L[0], Nx = g.N[0], Ny = g.N[1], Nz = g.N[2];
+                return launch_lines<R>(c, Q(c), A(c), tw(c, 0), c->rx, (int)Ny, (int)(4 * c->B * Nz), (int)Nx,
+                                       (int)Lx, 1, Nx * Ny, Ny, 1, Ny, Nz * Ny, false, (int)Nz, Nz * Nx * Ny,
+                                       Lx * Nz * Ny, gate);
+            }
             const dim3 gx((2 * g.N[1] * g.N[2] + 255) / 256, 4 * c->B);
             const cplx<R>* zsrc = (const cplx<R>*)c->zero;
             switch (xline_n(c)) {
@@ -508,8 +528,9 @@ struct Ops {
         const GridDims& g = c->gd;
         const long long Lx = g.L[0], Nx = g.N[0], Ny = g.N[1], Nz = g.N[2];
         const double s = sizeof(cplx<R>), bc = 4.0 * c->B;
-        Trace t(c, ETAIM_K_FFT_X_INV, bc * Lx * Nz * Ny * s + bc * c->N3 * s, c->x_engine == 1);
-        if (c->x_engine == 1) {
+        // one register kernel (events on its dispatch) or the line launches
+        Trace t(c, ETAIM_K_FFT_X_INV, bc * Lx * Nz * Ny * s + bc * c->N3 * s, c->x_engine == 1 && xline_n(c) > 0);
+        if (c->x_engine == 1 && xline_n(c)) {
             const dim3 gx((unsigned)((2 * Ny * Nz + 255) / 256), (unsigned)(4 * c->B));
             switch (xline_n(c)) {
                 case 16: launch_timed(t, k_xinv<R, 16>, gx, dim3(256), 0, c->stream, A(c), P(c), g, gate); break;
@@ -846,6 +867,9 @@ struct StepResult {
 // active afterwards).  With a gate every kernel first checks the step's
 // live flag (k_gate), so steps can be enqueued ahead of the host's
 // convergence check or replayed from a captured graph.
+// blocks per dot product or norm: one per 16 K entries, at most 64
+inline int red_chunks(int ns) { return std::max(1, std::min(kRedMaxChunks, ns / 16384)); }
+
 template <typename R>
 int arnoldi_step(etaim_ctx* c, int j, int conj, const int* gate, const int* step_live = nullptr) {
     const int B = c->B, ns = c->ns, rs = c->prm.restart;
@@ -854,24 +878,39 @@ int arnoldi_step(etaim_ctx* c, int j, int conj, const int* gate, const int* step
     zd* vj = c->Vk + (size_t)j * nB;
     zd* vn = c->Vk + (size_t)(j + 1) * nB;
     if (gate) hipLaunchKernelGGL(k_gate, dim3(1), dim3(64), 0, c->stream, c->flag, step_live);
+    // few columns: lane groups per row (the column-lane kernels would leave
+    // most lanes idle)
+    const bool grp = B <= kSpmvGroupMaxB;
+    const unsigned gblocks = (unsigned)((nB * kSpmvLanes + 255) / 256);
     if (c->precond == 1 && c->x_engine == 1) {
         // w = Z (M v_j), M the near-zone sparse approximate inverse (M^H for the
         // adjoint): v_j transposed to [ns][B], then M v_j straight into the
         // operator's scaled-column buffer
         {
             Trace tp(c, ETAIM_K_KRYLOV, (double)c->nnz * 20.0 + 2.0 * (double)nB * 16.0 + (double)nB * sizeof(cplx<R>));
-            hipLaunchKernelGGL(k_prescale<double>, dim3(blocks_for(nB)), dim3(256), 0, c->stream, vj, nullptr,
-                               (cplx<double>*)c->zt, ns, B, 0, gate);
-            hipLaunchKernelGGL(k_spmv_rows<R>, dim3(blocks_for(nB)), dim3(256), 0, c->stream, c->rowptr, c->col,
-                               conj ? c->saiT : c->sai, c->zt, (cplx<R>*)c->xs, ns, B, conj, gate);
+            if (grp) {
+                hipLaunchKernelGGL(k_spmv_grp<R>, dim3(gblocks), dim3(256), 0, c->stream, c->rowptr, c->col,
+                                   conj ? c->saiT : c->sai, vj, 1LL, (long long)ns, (cplx<R>*)c->xs, (zd*)nullptr, ns,
+                                   B, conj, 0, gate);
+            } else {
+                hipLaunchKernelGGL(k_prescale<double>, dim3(blocks_for(nB)), dim3(256), 0, c->stream, vj, nullptr,
+                                   (cplx<double>*)c->zt, ns, B, 0, gate);
+                hipLaunchKernelGGL(k_spmv_rows<R>, dim3(blocks_for(nB)), dim3(256), 0, c->stream, c->rowptr, c->col,
+                                   conj ? c->saiT : c->sai, c->zt, (cplx<R>*)c->xs, ns, B, conj, gate);
+            }
         }
         CHK(Ops<R>::apply(c, 0, nullptr, nullptr, c->w, conj, gate, true));
     } else if (c->precond == 1) {
         // w = Z (M v_j), M the near-zone sparse approximate inverse (M^H for the adjoint)
         {
             Trace tp(c, ETAIM_K_KRYLOV, (double)c->nnz * 20.0 + 2.0 * (double)nB * 16.0);
-            hipLaunchKernelGGL(k_spmv_cols, dim3(blocks_for(nB)), dim3(256), 0, c->stream, c->rowptr, c->col,
-                               conj ? c->saiT : c->sai, vj, c->zt, ns, B, conj, 0, gate);
+            if (grp)
+                hipLaunchKernelGGL(k_spmv_grp<R>, dim3(gblocks), dim3(256), 0, c->stream, c->rowptr, c->col,
+                                   conj ? c->saiT : c->sai, vj, 1LL, (long long)ns, (cplx<R>*)nullptr, c->zt, ns, B,
+                                   conj, 0, gate);
+            else
+                hipLaunchKernelGGL(k_spmv_cols, dim3(blocks_for(nB)), dim3(256), 0, c->stream, c->rowptr, c->col,
+                                   conj ? c->saiT : c->sai, vj, c->zt, ns, B, conj, 0, gate);
         }
         CHK(Ops<R>::apply(c, 0, c->zt, nullptr, c->w, conj, gate));
     } else {
@@ -879,11 +918,30 @@ int arnoldi_step(etaim_ctx* c, int j, int conj, const int* gate, const int* step
     }
     dim3 gd(j + 1, B), go((ns + 255) / 256, B);
     Trace tk(c, ETAIM_K_KRYLOV, (4.0 * (j + 1) + 8.0) * (double)nB * 16.0);
-    hipLaunchKernelGGL(k_dots, gd, dim3(kRedThreads), 0, c->stream, c->Vk, c->w, c->h1, ns, B, gate);
+    // long columns: each dot product and norm over several blocks, finished in order
+    const int nch = red_chunks(ns);
+    auto dots = [&](zd* h) {
+        if (nch == 1) {
+            hipLaunchKernelGGL(k_dots, gd, dim3(kRedThreads), 0, c->stream, c->Vk, c->w, h, ns, B, gate);
+            return;
+        }
+        hipLaunchKernelGGL(k_dots_part, dim3(j + 1, B, nch), dim3(kRedThreads), 0, c->stream, c->Vk, c->w,
+                           (zd*)c->redpart, ns, B, nch, gate);
+        hipLaunchKernelGGL(k_dots_fin, dim3(((j + 1) * B + 63) / 64), dim3(64), 0, c->stream, (const zd*)c->redpart,
+                           h, (j + 1) * B, nch, gate);
+    };
+    dots(c->h1);
     hipLaunchKernelGGL(k_orth, go, dim3(256), 0, c->stream, c->Vk, c->w, c->h1, j + 1, ns, B, gate);
-    hipLaunchKernelGGL(k_dots, gd, dim3(kRedThreads), 0, c->stream, c->Vk, c->w, c->h2, ns, B, gate);
+    dots(c->h2);
     hipLaunchKernelGGL(k_orth, go, dim3(256), 0, c->stream, c->Vk, c->w, c->h2, j + 1, ns, B, gate);
-    hipLaunchKernelGGL(k_norm, dim3(B), dim3(kRedThreads), 0, c->stream, c->w, c->nrm, ns, gate);
+    if (nch == 1) {
+        hipLaunchKernelGGL(k_norm, dim3(B), dim3(kRedThreads), 0, c->stream, c->w, c->nrm, ns, gate);
+    } else {
+        hipLaunchKernelGGL(k_norm_part, dim3(B, nch), dim3(kRedThreads), 0, c->stream, c->w, (double*)c->redpart, ns,
+                           nch, gate);
+        hipLaunchKernelGGL(k_norm_fin, dim3((B + 63) / 64), dim3(64), 0, c->stream, (const double*)c->redpart, c->nrm,
+                           B, nch, gate);
+    }
     hipLaunchKernelGGL(k_scale, dim3(blocks_for(nB)), dim3(256), 0, c->stream, c->w, c->nrm, vn, ns, B, gate);
     hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(64), 0, c->stream, c->flag, 1, 0, gate);
     hipLaunchKernelGGL(k_arnoldi_update, dim3(1), dim3(256), 0, c->stream, c->h1, c->h2, c->nrm, c->H, c->cs, c->sn,
@@ -1027,10 +1085,16 @@ int gmres(etaim_ctx* c, const zd* rhs, zd* x, int conj, StepResult& res) {
             // until the next cycle start), then the rows of M on the lanes' columns
             hipLaunchKernelGGL(k_krylov_combine, dim3((ns + 255) / 256, B), dim3(256), 0, c->stream, c->zt, c->Vk,
                                c->yv, c->jcnt, ns, B, rs);
-            hipLaunchKernelGGL(k_prescale<double>, dim3(blocks_for(nB)), dim3(256), 0, c->stream, c->zt, nullptr,
-                               (cplx<double>*)c->w, ns, B, 0, nullptr);
-            hipLaunchKernelGGL(k_spmv_rows_add, dim3(blocks_for(nB)), dim3(256), 0, c->stream, c->rowptr, c->col,
-                               conj ? c->saiT : c->sai, c->w, x, ns, B, conj);
+            if (B <= kSpmvGroupMaxB) {
+                hipLaunchKernelGGL(k_spmv_grp<double>, dim3((unsigned)((nB * kSpmvLanes + 255) / 256)), dim3(256), 0,
+                                   c->stream, c->rowptr, c->col, conj ? c->saiT : c->sai, c->zt, 1LL, (long long)ns,
+                                   (cplx<double>*)nullptr, x, ns, B, conj, 1, nullptr);
+            } else {
+                hipLaunchKernelGGL(k_prescale<double>, dim3(blocks_for(nB)), dim3(256), 0, c->stream, c->zt, nullptr,
+                                   (cplx<double>*)c->w, ns, B, 0, nullptr);
+                hipLaunchKernelGGL(k_spmv_rows_add, dim3(blocks_for(nB)), dim3(256), 0, c->stream, c->rowptr, c->col,
+                                   conj ? c->saiT : c->sai, c->w, x, ns, B, conj);
+            }
         } else {
             hipLaunchKernelGGL(k_update_x, dim3((ns + 255) / 256, B), dim3(256), 0, c->stream, x, c->Vk, c->yv,
                                c->jcnt, dinv, ns, B, rs);
@@ -1097,10 +1161,17 @@ int step_body(etaim_ctx* c, int J, int far, int pred) {
     if (c->precond == 1) {
         hipLaunchKernelGGL(k_krylov_combine, dim3((ns + 255) / 256, B), dim3(256), 0, c->stream, c->zt, c->Vk, c->yv,
                            c->jcnt, ns, B, rs, live);
-        hipLaunchKernelGGL(k_prescale<double>, dim3(blocks_for(nB)), dim3(256), 0, c->stream, c->zt, nullptr,
-                           (cplx<double>*)c->w, ns, B, 0, live);
-        hipLaunchKernelGGL(k_spmv_rows_add, dim3(blocks_for(nB)), dim3(256), 0, c->stream, c->rowptr, c->col, c->sai,
-                           c->w, c->xk, ns, B, 0, live);
+        // the same product as the eager solve's end (bit-identical replays)
+        if (B <= kSpmvGroupMaxB) {
+            hipLaunchKernelGGL(k_spmv_grp<double>, dim3((unsigned)((nB * kSpmvLanes + 255) / 256)), dim3(256), 0,
+                               c->stream, c->rowptr, c->col, c->sai, c->zt, 1LL, (long long)ns, (cplx<double>*)nullptr,
+                               c->xk, ns, B, 0, 1, live);
+        } else {
+            hipLaunchKernelGGL(k_prescale<double>, dim3(blocks_for(nB)), dim3(256), 0, c->stream, c->zt, nullptr,
+                               (cplx<double>*)c->w, ns, B, 0, live);
+            hipLaunchKernelGGL(k_spmv_rows_add, dim3(blocks_for(nB)), dim3(256), 0, c->stream, c->rowptr, c->col,
+                               c->sai, c->w, c->xk, ns, B, 0, live);
+        }
     } else {
         hipLaunchKernelGGL(k_update_x, dim3((ns + 255) / 256, B), dim3(256), 0, c->stream, c->xk, c->Vk, c->yv,
                            c->jcnt, c->dinv, ns, B, rs, live);
@@ -1196,7 +1267,7 @@ int checker_create(etaim_ctx* c) {
     k->stream = c->stream;
     k->no_solver = true;
     k->yz_engine = quad_n(k.get()) ? 2 : 0;
-    k->x_engine = xline_n(k.get()) ? 1 : 0;
+    k->x_engine = xreg_ok(k.get()) ? 1 : 0;
     k->delay_block = 1;  // the delayed field is formed only at check steps: direct sum
     CHK(device_setup(k.get()));
     k->B = 1;  // its operators act on the one monitored column
@@ -1704,7 +1775,7 @@ int make_working(etaim_ctx* c) {
     }
     CHK(c->allocv(c->A, 4 * nB * (size_t)c->gd.N[2] * c->gd.N[1] * c->gd.L[0] * sizeof(cplx<R>)));
     CHK(c->allocv(c->P, 4 * nB * c->N3 * sizeof(cplx<R>)));
-    if (xline_n(c)) {
+    if (xreg_ok(c)) {
         CHK(c->allocv(c->Q, 4 * nB * c->N3 * sizeof(cplx<R>)));
         HIPCHK(hipMemsetAsync(c->Q, 0, 4 * nB * c->N3 * sizeof(cplx<R>), c->stream));
     }
@@ -1935,6 +2006,7 @@ int device_setup(etaim_ctx* c) {
     CHK(c->alloc(c->rhs, nB));
     CHK(c->alloc(c->zero, nB));
     HIPCHK(hipMemsetAsync(c->zero, 0, nB * sizeof(zd), c->stream));
+    CHK(c->allocv(c->redpart, (size_t)(rs + 1) * c->B * kRedMaxChunks * sizeof(zd)));
     CHK(c->alloc(c->h1, (size_t)(rs + 1) * c->B));
     CHK(c->alloc(c->h2, (size_t)(rs + 1) * c->B));
     CHK(c->alloc(c->H, (size_t)c->B * rs * (rs + 1)));
@@ -2039,7 +2111,7 @@ int etaim_create(etaim_ctx** out, const etaim_mesh* mesh, const etaim_rwg* rwg, 
     c->ry = make_radix(c->gd.L[1]);
     c->rz = make_radix(c->gd.L[2]);
     c->yz_engine = quad_n(c.get()) ? 2 : 0;
-    c->x_engine = xline_n(c.get()) ? 1 : 0;
+    c->x_engine = xreg_ok(c.get()) ? 1 : 0;
     c->N3 = (size_t)c->gd.N[0] * c->gd.N[1] * c->gd.N[2];
     c->Np = (size_t)c->gd.L[0] * c->gd.L[1] * c->gd.L[2];
     c->gfold = (size_t)(c->gd.N[0] + 1) * (c->gd.N[1] + 1) * (c->gd.N[2] + 1);

@@ -55,6 +55,62 @@ __global__ void __launch_bounds__(kRedThreads) k_dots(const zd* __restrict__ V, 
     if (threadIdx.x == 0) h[(size_t)i * B + b] = zd{re, im};
 }
 
+// The same dot products over long columns, split over nchunk blocks per
+// (i, b): each block sums one contiguous chunk (part[(i B + b) nchunk + c]),
+// then k_dots_fin adds the chunks in order (deterministic, no atomics).
+__global__ void __launch_bounds__(kRedThreads) k_dots_part(const zd* __restrict__ V, const zd* __restrict__ w,
+                                                           zd* __restrict__ part, int ns, int B, int nchunk,
+                                                           const int* __restrict__ gate) {
+    if (gated_off(gate)) return;
+    __shared__ double sh[2][kRedThreads / 64];
+    const int i = blockIdx.x, b = blockIdx.y, ch = blockIdx.z;
+    const int len = (ns + nchunk - 1) / nchunk, k0 = ch * len, k1 = min(ns, k0 + len);
+    const zd* v = V + ((size_t)i * B + b) * ns;
+    const zd* x = w + (size_t)b * ns;
+    double re = 0, im = 0;
+    for (int k = k0 + threadIdx.x; k < k1; k += kRedThreads) {
+        const zd a = v[k], c = x[k];
+        re += a.x * c.x + a.y * c.y;
+        im += a.x * c.y - a.y * c.x;
+    }
+    re = block_sum_t0(re, sh[0]);
+    im = block_sum_t0(im, sh[1]);
+    if (threadIdx.x == 0) part[((size_t)i * B + b) * nchunk + ch] = zd{re, im};
+}
+// h[e] = sum_c part[e nchunk + c], e < n
+__global__ void k_dots_fin(const zd* __restrict__ part, zd* __restrict__ h, int n, int nchunk,
+                           const int* __restrict__ gate) {
+    if (gated_off(gate)) return;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    zd acc{0, 0};
+    for (int ch = 0; ch < nchunk; ++ch) acc += part[(size_t)e * nchunk + ch];
+    h[e] = acc;
+}
+// nrm[b] = ||w[b]|| over nchunk chunks per column (sum of squares in part,
+// finished by k_norm_fin)
+__global__ void __launch_bounds__(kRedThreads) k_norm_part(const zd* __restrict__ w, double* __restrict__ part,
+                                                           int ns, int nchunk, const int* __restrict__ gate) {
+    if (gated_off(gate)) return;
+    __shared__ double sh[kRedThreads / 64];
+    const int b = blockIdx.x, ch = blockIdx.y;
+    const int len = (ns + nchunk - 1) / nchunk, k0 = ch * len, k1 = min(ns, k0 + len);
+    const zd* x = w + (size_t)b * ns;
+    double s = 0;
+    for (int k = k0 + threadIdx.x; k < k1; k += kRedThreads) s += x[k].x * x[k].x + x[k].y * x[k].y;
+    s = block_sum_t0(s, sh);
+    if (threadIdx.x == 0) part[(size_t)b * nchunk + ch] = s;
+}
+__global__ void k_norm_fin(const double* __restrict__ part, double* __restrict__ nrm, int B, int nchunk,
+                           const int* __restrict__ gate) {
+    if (gated_off(gate)) return;
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    double s = 0;
+    for (int ch = 0; ch < nchunk; ++ch) s += part[(size_t)b * nchunk + ch];
+    nrm[b] = sqrt(s);
+}
+
 // w[b] -= sum_{i<nv} h[i][b] V_i[b]  (one classical Gram-Schmidt pass)
 __global__ void __launch_bounds__(256) k_orth(const zd* __restrict__ V, zd* __restrict__ w, const zd* __restrict__ h,
                                               int nv, int ns, int B, const int* __restrict__ gate) {
@@ -281,6 +337,47 @@ __device__ __forceinline__ zd spmv_row_col(const int* __restrict__ rowptr, const
         for (int u = 0; u < 4; ++u) acc += zd{v[u].x, sg * v[u].y} * xv[u];
     }
     return acc;
+}
+
+// (op(M) x)[b][i] for few columns: a group of kSpmvLanes lanes per (row i,
+// column b) runs over the row's entries (coalesced entry loads), then sums
+// across the group.  x[b][k] is read at x + k xs_k + b xs_b.  rows_out:
+// out[i B + b] in the working precision (the operator's scaled-column
+// layout); otherwise y[b][i] (FP64), added to y when accumulate.
+constexpr int kSpmvLanes = 16;
+template <typename R>
+__global__ void __launch_bounds__(256) k_spmv_grp(const int* __restrict__ rowptr, const int* __restrict__ col,
+                                                  const zd* __restrict__ M, const zd* __restrict__ x, long long xs_k,
+                                                  long long xs_b, cplx<R>* __restrict__ out, zd* __restrict__ y,
+                                                  int ns, int B, int conj, int accumulate,
+                                                  const int* __restrict__ gate) {
+    if (gated_off(gate)) return;
+    const size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    const size_t pr = t / kSpmvLanes;
+    const int g = (int)(t % kSpmvLanes);
+    const bool live = pr < (size_t)ns * B;
+    const int i = live ? (int)(pr / B) : 0, b = live ? (int)(pr % B) : 0;
+    const double sg = conj ? -1.0 : 1.0;
+    zd acc{0, 0};
+    if (live) {
+        const int q1 = rowptr[i + 1];
+        for (int q = rowptr[i] + g; q < q1; q += kSpmvLanes) {
+            const zd v = M[q];
+            acc += zd{v.x, sg * v.y} * x[(size_t)col[q] * xs_k + (size_t)b * xs_b];
+        }
+    }
+#pragma unroll
+    for (int o = kSpmvLanes / 2; o > 0; o >>= 1) {
+        acc.x += __shfl_xor(acc.x, o, 64);
+        acc.y += __shfl_xor(acc.y, o, 64);
+    }
+    if (!live || g != 0) return;
+    if (out)
+        out[(size_t)i * B + b] = to_r<R>(acc);
+    else {
+        zd& d = y[(size_t)b * ns + i];
+        d = accumulate ? d + acc : acc;
+    }
 }
 
 // out[i][b] = (op(M) x)[b][i] in the working precision, the layout the

@@ -74,12 +74,13 @@ bool shape_fits(const etaim_ctx* c, const Shape& s) {
                          (s.engine != 0 || ((size_t)g.L[2] * (g.L[1] + 1) + g.L[1] + g.L[2]) * sizeof(cplx<R>) <=
                                                (size_t)160 * 1024));
     const size_t nb = (size_t)c->B;
-    if ((s.engine == 3 && 4 * nb * g.L[0] > kMaxGridY) || (s.xeng == 0 && 4 * nb * g.N[2] > kMaxGridY)) return false;
+    if ((s.engine == 3 && 4 * nb * g.L[0] > kMaxGridY) || ((s.xeng == 0 || !xline_n(c)) && 4 * nb * g.N[2] > kMaxGridY))
+        return false;
     return yz_fits && plane_fits(4 * mr, s.rx) &&
            plane_fits(mt, s.rx) && (4 * (size_t)mr * (Lx + 1) + Lx) * e <= 160 * 1024 &&
            ((size_t)mt * (Lx + 1) + Lx) * e <= (size_t)kLdsBudget && s.waves >= 1 && s.waves <= 4 &&
            s.sync >= 1 && s.sync <= c->prm.restart && (s.engine == 0 || s.engine == 3 || ((s.engine == 1 || s.engine == 2) && quad_n(c) > 0)) &&
-           (s.xeng == 0 || (s.xeng == 1 && xline_n(c) > 0)) && s.guess >= 0 && s.guess <= kMaxGuess &&
+           (s.xeng == 0 || (s.xeng == 1 && xreg_ok(c))) && s.guess >= 0 && s.guess <= kMaxGuess &&
            (s.precond == 0 || s.precond == 1) && s.dblock >= 1 && s.dblock <= kFarMaxBlock &&
            (s.ieng == 0 || (s.ieng == 1 && c->ntiles > 0 && interp_tile_lds<R>(c) <= 160 * 1024));
 }

@@ -262,18 +262,26 @@ def test_interp_tiles_full_operator_level2(torch, batch):
     P.close()
 
 
-@pytest.mark.parametrize("prec,grid,tol", [(0, 54, 1e-12), (1, 72, 1e-5)], ids=["fp64_54", "fp32_72"])
-def test_line_engine_where_planes_do_not_fit(torch, prec, grid, tol):
+@pytest.mark.parametrize("prec,grid,tol,xe", [(0, 54, 1e-12, None), (1, 72, 1e-5, None), (0, 72, 1e-12, None),
+                                              (1, 72, 1e-5, 0)],
+                         ids=["fp64_54", "fp32_72", "fp64_72", "fp32_72_xlds"])
+def test_line_engine_where_planes_do_not_fit(torch, prec, grid, tol, xe):
     """A padded (y, z) plane larger than the LDS (108^2 FP64 = 186 KB, 144^2
     FP32 = 166 KB) puts the y/z stage on the line-pass engine by itself: the
     level-3 sphere on that grid, far operator Z_m for m > M_n and the
     delayed field of a history whose first M_n samples are zero, against
-    the oracle."""
+    the oracle.  Line length 108 runs the LDS passes; 144 = 12 x 12 the
+    four-step register lines, with the anterpolated grid transformed by
+    them (the default x stage there) or the LDS gather (xlds)."""
     s, A, p = _oracle_far_grid(L3, grid)
     ng = p["ng"]
     assert A.mn < ng
     P = gpu_problem(L3, precision=prec, batch=2, nt=8, grid=grid)
     assert P.tuning()["yz_engine"] == 3 and P.info["mn"] == A.mn
+    assert P.tuning()["x_engine"] == (0 if grid == 54 else 1)
+    if xe is not None:
+        P.set_tuning(dict(P.tuning(), x_engine=xe))
+        assert P.tuning()["x_engine"] == xe
     x = W.complex_normal(40, (2, s.ns))
     for m in range(A.mn + 1, ng + 1):
         y = P.apply_z(m, _dev(torch, x)).cpu().numpy()

@@ -276,3 +276,28 @@ def test_profiling_mask(torch):
     assert ks2["krylov"]["launches"] > 0 and ks2["anterp_x"]["launches"] > 0
     assert ks2["yz_green"]["launches"] == ks["yz_green"]["launches"]
     assert np.array_equal(I1, I0) and np.array_equal(I2, I0)
+
+
+@pytest.mark.parametrize("xe", [1, 0], ids=["x_register", "x_lds"])
+def test_profiling_on_the_line_engine(torch, xe):
+    """Every class traced on a grid whose planes take the line-pass engine
+    (level-3 sphere on a 72^3 grid: four-step lines of 144 points, the x
+    stage from the anterpolated grid or the LDS gather): all event pairs
+    resolve, every matvec class is counted, and the march is bit for bit
+    the untraced one."""
+    name = W.SPHERE_L3.name
+    V = _excitation(name, 8, 1, 48)
+    P = gpu_problem(name, nt=V.shape[0], batch=V.shape[1], flags=F_CONTINUE_ON_NOCONV, grid=72)
+    P.set_tuning(dict(P.tuning(), x_engine=xe))
+    assert (P.tuning()["yz_engine"], P.tuning()["x_engine"]) == (3, xe)
+    Vd = torch.from_numpy(np.ascontiguousarray(V)).cuda()
+    I0 = P.march(Vd)[0].cpu().numpy()
+    P.set_profiling(True)
+    I1 = P.march(Vd)[0].cpu().numpy()
+    ks = P.kernel_stats()
+    P.set_profiling(False)
+    P.close()
+    _say("line engine profiling", {n: v["launches"] for n, v in ks.items()})
+    for n in ("anterp_x", "yz_green", "fft_x_inv", "interp_near", "yz_delayed", "yz_commit", "krylov"):
+        assert ks[n]["launches"] > 0 and ks[n]["ms"] > 0, n
+    assert np.array_equal(I1, I0)
