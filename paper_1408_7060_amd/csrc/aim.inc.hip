@@ -1077,7 +1077,7 @@ __global__ void __launch_bounds__((lines4_threads<R, A, B>())) k_zg4(cplx<R>* __
 template <typename R>
 __global__ void __launch_bounds__(256) k_delay_sum(const cplx<R>* __restrict__ ring, const cplx<R>* __restrict__ G,
                                                    cplx<R>* __restrict__ S, GridDims g, int ng, int cur, int nm,
-                                                   int conj_g) {
+                                                   int conj_g, const cplx<R>* __restrict__ Fj) {
     using V = typename Vec16<R>::type;
     constexpr int P = Vec16<R>::P;
     const int Lx = g.L[0], Ly = g.L[1], Lz = g.L[2];
@@ -1093,8 +1093,16 @@ __global__ void __launch_bounds__(256) k_delay_sum(const cplx<R>* __restrict__ r
     const size_t goff = (((size_t)((bc & 3) == 3 ? 1 : 0) * gx + fold(kx, Lx)) * gz + fold(kz, Lz)) * gy;
     const R sg = conj_g ? R(-1) : R(1);
     cplx<R> acc[P];
+    if (Fj) {
+        // time blocks: the step's block sum of the older history, then its nm
+        // newest terms
+        const V f = __builtin_nontemporal_load(reinterpret_cast<const V*>(Fj + gid));
 #pragma unroll
-    for (int q = 0; q < P; ++q) acc[q] = cplx<R>{0, 0};
+        for (int q = 0; q < P; ++q) acc[q] = cplx<R>{f[2 * q], f[2 * q + 1]};
+    } else {
+#pragma unroll
+        for (int q = 0; q < P; ++q) acc[q] = cplx<R>{0, 0};
+    }
     for (int m = 1; m <= nm; ++m) {
         int s = (cur - m) % ng;
         if (s < 0) s += ng;
@@ -1195,6 +1203,89 @@ __global__ void __launch_bounds__(256) k_ring_far(const cplx<R>* __restrict__ ri
                     t[2 * p + 1] = acc[j][p].y;
                 }
                 __builtin_nontemporal_store(t, reinterpret_cast<V*>(F + (size_t)j * slot + off));
+            }
+    }
+}
+
+// Time-block pass of the line-pass engine (spectrum slots [bc][kx][kz][ky]):
+// F[j] = sum_{hp=1}^{min(ng, r0)} G_{j+hp} . ring slot (r0 - hp) mod ng for
+// the pb steps r0 + j of a block (terms with j + hp > ng dropped).  A thread
+// owns one 16-byte vector of points of one component, kx and kz and loops
+// over the batch, so that its Green values are loaded once for all columns;
+// history slots are loaded eight at a time ahead of their products.
+template <typename R, int NGX>
+__global__ void __launch_bounds__(256) k_ring_far3(const cplx<R>* __restrict__ ring, const cplx<R>* __restrict__ G,
+                                                   cplx<R>* __restrict__ F, GridDims g, int ng, int r0, int pb,
+                                                   int conj_g) {
+    using V = typename Vec16<R>::type;
+    constexpr int P = Vec16<R>::P;
+    const int Lx = g.L[0], Ly = g.L[1], Lz = g.L[2];
+    const size_t plane = (size_t)Ly * Lz, col = 4 * (size_t)Lx * plane, slot = (size_t)g.B * col;
+    const size_t gid = (blockIdx.x * (size_t)blockDim.x + threadIdx.x) * P;
+    if (gid >= col) return;
+    // Ly is even, so the P points share one (c, kx, kz) row
+    const size_t pl = gid / plane;
+    const int r = (int)(gid - pl * plane), kz = r / Ly, ky = r - kz * Ly;
+    const int kx = (int)(pl % Lx), c = (int)(pl / Lx);
+    const int gx = g.N[0] + 1, gy = g.N[1] + 1, gz = g.N[2] + 1;
+    const size_t gsz = (size_t)2 * gx * gy * gz;
+    const size_t goff = (((size_t)(c == 3 ? 1 : 0) * gx + fold(kx, Lx)) * gz + fold(kz, Lz)) * gy;
+    const R sg = conj_g ? R(-1) : R(1);
+    cplx<R> gr[NGX + 1][P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        const int fy = fold(ky + q, Ly);
+#pragma unroll
+        for (int m = 1; m <= NGX; ++m) {
+            const R mk = m <= ng ? R(1) : R(0);
+            const cplx<R> v = G[(size_t)(m <= ng ? m : ng) * gsz + goff + fy];
+            gr[m][q] = cplx<R>{v.x * mk, v.y * (sg * mk)};
+        }
+    }
+    for (int b = 0; b < g.B; ++b) {
+        const size_t off = (size_t)b * col + gid;
+        cplx<R> acc[kFarMaxBlock][P];
+#pragma unroll
+        for (int j = 0; j < kFarMaxBlock; ++j)
+#pragma unroll
+            for (int q = 0; q < P; ++q) acc[j][q] = cplx<R>{0, 0};
+        constexpr int CH = 8;
+#pragma unroll
+        for (int hp0 = 1; hp0 <= NGX; hp0 += CH) {
+            if (hp0 > ng) break;
+            cplx<R> t[CH][P];
+#pragma unroll
+            for (int u = 0; u < CH; ++u) {
+                const int hp = hp0 + u < ng ? hp0 + u : ng;
+                const int h = r0 - hp;
+                const V v = __builtin_nontemporal_load(
+                    reinterpret_cast<const V*>(ring + (size_t)((h > 0 ? h : 0) % ng) * slot + off));
+#pragma unroll
+                for (int q = 0; q < P; ++q) t[u][q] = cplx<R>{v[2 * q], v[2 * q + 1]};
+                if (h < 0 || hp0 + u > ng)
+#pragma unroll
+                    for (int q = 0; q < P; ++q) t[u][q] = cplx<R>{0, 0};
+            }
+#pragma unroll
+            for (int u = 0; u < CH; ++u)
+#pragma unroll
+                for (int j = 0; j < kFarMaxBlock; ++j) {
+                    const int m = j + hp0 + u;
+                    if (m <= NGX)
+#pragma unroll
+                        for (int q = 0; q < P; ++q) acc[j][q] += cmul_fma(gr[m][q], t[u][q]);
+                }
+        }
+#pragma unroll
+        for (int j = 0; j < kFarMaxBlock; ++j)
+            if (j < pb) {
+                V v;
+#pragma unroll
+                for (int q = 0; q < P; ++q) {
+                    v[2 * q] = acc[j][q].x;
+                    v[2 * q + 1] = acc[j][q].y;
+                }
+                __builtin_nontemporal_store(v, reinterpret_cast<V*>(F + (size_t)j * slot + off));
             }
     }
 }

@@ -650,8 +650,24 @@ struct Ops {
     // Captured into a whole-step graph (sr.sd set) the step's values come from
     // its descriptor; graph_far then says whether the time-block pass runs.
     static bool blocks_on(const etaim_ctx* c) {
-        return (c->yz_engine == 1 || c->yz_engine == 2) && c->delay_block > 1 && c->st.ng <= kFarMaxNg &&
-               c->delay_block <= kFarMaxBlock;
+        return (c->yz_engine >= 1) && c->delay_block > 1 && c->st.ng <= kFarMaxNg && c->delay_block <= kFarMaxBlock;
+    }
+    // the block sums' pb spectrum slots (reallocated when a longer block is set)
+    static int ensure_far(etaim_ctx* c, int pb) {
+        if (c->far_slots >= pb) return ETAIM_OK;
+        if (c->capturing) return fail(ETAIM_EUNSUPPORTED, "the time-block sums are not allocated");
+        const size_t slot = (size_t)4 * c->B * c->Np;
+        if (c->far) {
+            auto it = std::find(c->allocs.begin(), c->allocs.end(), c->far);
+            if (it != c->allocs.end()) c->allocs.erase(it);
+            HIPCHK(hipFree(c->far));
+            c->dev_bytes -= (int64_t)((size_t)c->far_slots * slot * sizeof(cplx<R>));
+            c->far = nullptr;
+            c->far_slots = 0;
+        }
+        CHK(c->allocv(c->far, (size_t)pb * slot * sizeof(cplx<R>)));
+        c->far_slots = pb;
+        return ETAIM_OK;
     }
     static int delayed(etaim_ctx* c, int cur, const zd* V, zd* rhs, int conj, StepRef sr = {}, int graph_far = 0) {
         const GridDims& g = c->gd;
@@ -673,13 +689,39 @@ struct Ops {
             double bytes = nmx * (slot_b + green_b) + 4.0 * c->B * g.L[0] * g.N[2] * g.N[1] * s;
             if (blocked) bytes += slot_b;
             if (c->yz_engine == 3) {
-                // the direct sum over the history into S, then the inverse z and y passes
+                // the sum over the history into S (from the step's block sum with
+                // time blocks), then the inverse z and y passes
                 if (graph) return fail(ETAIM_EUNSUPPORTED, "whole-step graph: needs the register plane kernels");
                 CHK(ensure_S(c));
+                const size_t slot = (size_t)4 * c->B * c->Np;
+                const cplx<R>* Fj = nullptr;
+                if (blocked) {
+                    CHK(ensure_far(c, pb));
+                    if (far_pass) {
+                        Trace tf(c, ETAIM_K_RING_FAR, std::min(ng, r0) * slot_b + ng * green_b + pb * slot_b);
+                        // one thread per 16-byte vector of one column's points
+                        const size_t pts = (size_t)4 * c->Np * sizeof(cplx<R>) / 16;
+                        const dim3 gf((unsigned)((pts + 255) / 256));
+                        cplx<R>* F = (cplx<R>*)c->far;
+                        const cplx<R>* rg = (const cplx<R>*)ring(c);
+                        if (ng <= 16)
+                            hipLaunchKernelGGL((k_ring_far3<R, 16>), gf, dim3(256), 0, c->stream, rg, ghat(c), F, g, ng,
+                                               r0, pb, conj);
+                        else if (ng <= 24)
+                            hipLaunchKernelGGL((k_ring_far3<R, 24>), gf, dim3(256), 0, c->stream, rg, ghat(c), F, g, ng,
+                                               r0, pb, conj);
+                        else
+                            hipLaunchKernelGGL((k_ring_far3<R, 32>), gf, dim3(256), 0, c->stream, rg, ghat(c), F, g, ng,
+                                               r0, pb, conj);
+                        HIPCHK(hipGetLastError());
+                        c->far_r0 = r0;
+                    }
+                    Fj = (const cplx<R>*)c->far + (size_t)(cur - r0) * slot;
+                }
                 Trace t(c, ETAIM_K_YZ_DELAYED, bytes);
                 const size_t vecs = (size_t)4 * c->B * c->Np * sizeof(cplx<R>) / 16;
                 hipLaunchKernelGGL(k_delay_sum<R>, dim3((unsigned)((vecs + 255) / 256)), dim3(256), 0, c->stream,
-                                   (const cplx<R>*)ring(c), ghat(c), S(c), g, ng, cur, nm, conj);
+                                   (const cplx<R>*)ring(c), ghat(c), S(c), g, ng, cur, nmx, conj, Fj);
                 HIPCHK(hipGetLastError());
                 CHK(zlines_inv(c));
                 CHK(ylines_inv(c, nullptr));
@@ -687,18 +729,7 @@ struct Ops {
                 const size_t slot = (size_t)4 * c->B * c->Np;
                 const cplx<R>* Fj = nullptr;
                 if (blocked) {
-                    if (c->far_slots < pb && !graph) {
-                        if (c->far) {
-                            auto it = std::find(c->allocs.begin(), c->allocs.end(), c->far);
-                            if (it != c->allocs.end()) c->allocs.erase(it);
-                            HIPCHK(hipFree(c->far));
-                            c->dev_bytes -= (int64_t)((size_t)c->far_slots * slot * sizeof(cplx<R>));
-                            c->far = nullptr;
-                            c->far_slots = 0;
-                        }
-                        CHK(c->allocv(c->far, (size_t)pb * slot * sizeof(cplx<R>)));
-                        c->far_slots = pb;
-                    }
+                    if (!graph) CHK(ensure_far(c, pb));
                     if (far_pass) {
                         Trace tf(c, ETAIM_K_RING_FAR, std::min(ng, r0) * slot_b + ng * green_b + pb * slot_b, true);
                         // one thread per 16-byte vector of points of one component and kx

@@ -475,8 +475,8 @@ int autotune_impl(etaim_ctx* c, int budget_ms, etaim_tuning* out) {
     if (best.mr == 0) best.mr = auto_gather_rows<R>(c, best.rx);
     if (best.mt == 0) best.mt = lines_per_block<R>(best.rx);
     put_shape(c, best);
-    // time blocks of the delayed field (register engine only)
-    if ((best.engine == 1 || best.engine == 2) && c->st.ng > 2) {
+    // time blocks of the delayed field (register and line-pass engines)
+    if ((best.engine == 1 || best.engine == 2 || best.engine == 3) && c->st.ng > 2) {
         double d_best = 0;
         CHK(time_delayed<R>(c, b, d_best));
         for (int pb : {1, 2, 3, 4, 5, 6, 7, 8}) {

@@ -151,10 +151,10 @@ def _delayed_ref_level4(batch):
 
 
 @pytest.mark.parametrize("block", [1, 3, 5, 8])
-@pytest.mark.parametrize("engine", [1, (2, 1)], ids=["reg", "zlines"])
+@pytest.mark.parametrize("engine", [1, (2, 1), (3, 1)], ids=["reg", "zlines", "lines"])
 @pytest.mark.parametrize("prec,tol,batch", [(0, 1e-12, 1), (1, 1e-5, 2)], ids=["fp64", "fp32_b2"])
 def test_delayed_time_blocks_level4(torch, prec, tol, batch, engine, block):
-    """The register engine sums, in time blocks of that many steps, the
+    """The register and line-pass engines sum, in time blocks of that many steps, the
     history older than a block once at its first step and the block's own
     steps at every step; the delayed field at step N_g then stands at block
     position (N_g - 1) mod block (7 of 8 at block 8: seven own steps, the
@@ -174,7 +174,8 @@ def test_delayed_time_blocks_level4(torch, prec, tol, batch, engine, block):
     P.close()
 
 
-def test_time_blocks_give_the_same_march(torch):
+@pytest.mark.parametrize("engine", [(2, 1), (3, 1)], ids=["zlines", "lines"])
+def test_time_blocks_give_the_same_march(torch, engine):
     """Marches with the history sum in time blocks of 2 and 3 steps (N_g = 4
     at level 2) against the direct sum at every step."""
     wl = W.SPHERE_L2
@@ -187,7 +188,7 @@ def test_time_blocks_give_the_same_march(torch):
     out = []
     for block in (1, 2, 3):
         P = gpu_problem(L2, nt=24, batch=2, tol=1e-13)
-        _with_engine(P, (2, 1))
+        _with_engine(P, engine)
         d = P.tuning()
         d["delay_block"] = block
         P.set_tuning(d)
