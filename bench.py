@@ -214,7 +214,7 @@ def main():
     ap.add_argument("--workload", default="batch", choices=["batch", "single", "composite"],
                     help="batch: level-4 sphere, 32 directions; single: one direction; composite: six boxes "
                          "and cylinders, 200 634 RWG, 384^3 padded grid (default 100 timed steps; no CPU "
-                         "baseline, whole-step graphs or FP64 residual check at that size)")
+                         "baseline or whole-step graphs at that size)")
     ap.add_argument("--sync-every", type=int, default=4,
                     help="Arnoldi steps enqueued per host convergence check")
     ap.add_argument("--graph", action="store_true",
@@ -242,10 +242,8 @@ def main():
     wl = {"batch": W.SPHERE_L4_BATCH, "single": W.SPHERE_L4, "composite": W.COMPOSITE}[args.workload]
     large = wl is W.COMPOSITE
     if large:
-        # the FP64 companion of the residual check would hold a 116 GB FP64
-        # history beside the 58 GB FP32 one; the oracle's set-up (13.7 M exact
-        # near-zone entries) does not fit a CPU leg of minutes
-        fl &= ~F_RESIDUAL_CHECK
+        # the oracle's set-up (13.7 M exact near-zone entries) does not fit a
+        # CPU leg of minutes; whole-step graphs need the register plane kernels
         args.no_cpu = True
         args.no_step_graph = True
     K = args.steps or (100 if large else wl.nt)
@@ -336,7 +334,7 @@ def main():
            "window": {"first_step": first, "last_step": nt - 1, "untimed_steps_before": first,
                       "pulse_peak_step": peak, "history_terms_per_step": ng},
            "unstable_step": min(unstable) if unstable else None,
-           "fp64_residual_check": None if large else {
+           "fp64_residual_check": {
                "column": 0, "every_steps": 16, "checks_in_window": st["residual_checks"],
                "max_rel_residual": st["max_residual64"], "worst_step": st["residual_worst_step"],
                "max_rel_residual_before_window": max(st_w["max_residual64"], st_t["max_residual64"])},

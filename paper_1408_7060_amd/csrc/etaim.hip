@@ -110,6 +110,7 @@ struct etaim_ctx {
     // delayed field in time blocks (register engine): far part of the history
     // sum once per block of delay_block steps into far, near part per step
     int delay_block = 6, far_slots = 0, far_r0 = -1;
+    int check_cols = 0;  // FP64 companion: history steps transformed together
     void* far = nullptr;
     int* flag_h = nullptr;
     double* res_h = nullptr;  // pinned: per-column residuals [B], then per-column norms [B]
@@ -1267,26 +1268,37 @@ int step_graph_get(etaim_ctx* c, int J, int far, int pred, hipGraphExec_t& out) 
 // into its own FP64 history and forms the delayed field from it.
 constexpr int kCheckEvery = 16;
 constexpr int kCheckBatch = 16;  // history steps transformed together by the FP64 companion
+constexpr double kCheckGridBytes = 8e9;
 
 int device_setup(etaim_ctx* c);
 
+// history steps the FP64 companion transforms together: kCheckBatch, fewer
+// where the per-column FP64 grid buffers (work spectrum, planes, grids) of a
+// large grid would pass kCheckGridBytes
+int check_batch(const etaim_ctx* c) {
+    const double per = 16.0 * (4.0 * (double)c->Np + 4.0 * c->gd.L[0] * (double)c->gd.N[1] * c->gd.N[2] +
+                               8.0 * (double)c->N3);
+    return (int)std::max(1.0, std::min((double)kCheckBatch, std::floor(kCheckGridBytes / per)));
+}
+
 int checker_create(etaim_ctx* c) {
     if (c->check) return ETAIM_OK;
+    const int cb = check_batch(c);
     std::unique_ptr<etaim_ctx> k(new etaim_ctx());
     k->prm = c->prm;
     k->prm.precision = ETAIM_FP64;
-    k->prm.batch = kCheckBatch;
+    k->prm.batch = cb;
     k->prm.flags = 0;
     k->geo = c->geo;
     k->st = c->st;
     k->ns = c->ns;
-    k->B = kCheckBatch;  // grid buffers for the batched history transforms
+    k->B = cb;  // grid buffers for the batched history transforms
     k->ring_cols = 1;    // the history of one column
     k->prec = ETAIM_FP64;
     k->mv = c->mv;
     k->nnz = c->nnz;
     k->gd = c->gd;
-    k->gd.B = kCheckBatch;
+    k->gd.B = cb;
     k->rx = make_radix(k->gd.L[0]);
     k->ry = make_radix(k->gd.L[1]);
     k->rz = make_radix(k->gd.L[2]);
@@ -1300,7 +1312,10 @@ int checker_create(etaim_ctx* c) {
     k->yz_engine = quad_n(k.get()) ? 2 : 0;
     k->x_engine = xreg_ok(k.get()) ? 1 : 0;
     k->delay_block = 1;  // the delayed field is formed only at check steps: direct sum
+    k->check_cols = cb;
     CHK(device_setup(k.get()));
+    // the line-pass work spectrum sized for the widest batch of history transforms
+    if (k->yz_engine == 3) CHK(Ops<double>::ensure_S(k.get()));
     k->B = 1;  // its operators act on the one monitored column
     k->gd.B = 1;
     c->check = k.release();
@@ -1327,7 +1342,7 @@ int checker_fill(etaim_ctx* c, const zd* I, int hi) {
     const int lo = std::max(k->check_next, hi - ng);
     const size_t step = (size_t)c->B * ns;  // stride of I_out's steps
     for (int s = lo; s < hi;) {
-        const int run = std::min({kCheckBatch, hi - s, ng - s % ng});
+        const int run = std::min({k->check_cols, hi - s, ng - s % ng});
         HIPCHK(hipMemcpy2DAsync(k->xk, (size_t)ns * sizeof(zd), I + (size_t)s * step, step * sizeof(zd),
                                 (size_t)ns * sizeof(zd), run, hipMemcpyDeviceToDevice, k->stream));
         k->B = run;

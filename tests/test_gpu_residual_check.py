@@ -99,3 +99,66 @@ def test_no_check_without_the_flag(torch):
     _, st = P.march(torch.from_numpy(np.ascontiguousarray(V)).cuda())
     assert (st["residual_checks"], st["residual_worst_step"], st["max_residual64"]) == (0, -1, 0.0)
     P.close()
+
+
+L3 = W.SPHERE_L3.name
+
+
+def test_residual_check_on_the_line_engine(torch):
+    """The check where the planes take the line-pass engine (level-3 sphere
+    on a 72^3 grid, FP32, the FP64 companion on the line engine too): the
+    worst residual and its step equal the oracle's FP64 residual of eq. (5)
+    of the march's own currents, for the uninterrupted march and for a
+    fresh context continued from a saved state at step 20 (its FP64
+    history rebuilt in runs of several steps)."""
+    from oracle import aim, excitation, geometry, kernels, zfill
+    from gpu_cases import params_of
+    wl = W.SPHERE_L3
+    p = params_of(wl)
+    s = geometry.Surface(p["xyz"], p["tri"], p["rwg"])
+    A = aim.AIM(s, 72, p["d_near"], p["dt"], wl.f0, p["ng"])
+    vals = A.near_values(lambda r, c, ms: zfill.assemble_pairs(
+        s, r, c, [kernels.EnvelopeKernel(m, p["dt"], wl.f0) for m in ms]))
+    nt, nb, ng = 48, 2, p["ng"]
+    kh = W.unit_vectors(72, 2, nb)
+    pp = W.polarisations(72, kh)
+    V = excitation.excitation(s, nt, p["dt"], kh, pp, wl.sigma, 12 * p["dt"], wl.f0)
+    Vd = torch.from_numpy(np.ascontiguousarray(V)).cuda()
+    kw = dict(precision=1, nt=nt, batch=nb, tol=1e-6, flags=F_CONTINUE_ON_NOCONV | F_RESIDUAL_CHECK, grid=72)
+    P = gpu_problem(L3, **kw)
+    assert P.tuning()["yz_engine"] == 3
+    I, st = P.march(Vd)
+    I = I.cpu().numpy()
+    spec = {}
+
+    def zx(terms):
+        """sum over (m, j) of (Z^near_m + Z^FFT_m) I_j (column 0)."""
+        for _, j in terms:
+            if j not in spec:
+                spec[j] = A.spectra(I[j, 0])
+        y = A.far_sum_rows([(m, spec[j]) for m, j in terms], np.arange(s.ns))
+        return y + sum(A.near_matvec(vals[m], I[j, 0]) for m, j in terms if m <= A.mn)
+
+    ref = {}
+    for l in (15, 31, 47):
+        rhs = V[l, 0] - zx([(m, l - m) for m in range(1, min(ng, l) + 1)])
+        ref[l] = float(np.linalg.norm(rhs - zx([(0, l)])) / np.linalg.norm(rhs))
+    l, worst = max(ref.items(), key=lambda kv: kv[1])
+    _say("line-engine residual check", st["max_residual64"], st["residual_worst_step"], "oracle", ref)
+    assert st["residual_checks"] == 3
+    assert st["residual_worst_step"] == l
+    assert st["max_residual64"] == pytest.approx(worst, rel=1e-6)
+    # (FP32 grid arithmetic on this fine grid leaves about 1e-3 of the
+    # right-hand side: the check reports it, it does not bound it)
+    assert worst <= 1e-2
+    I1, _ = P.march(Vd, nsteps=20)
+    state = P.save_state()
+    P.close()
+    Q = gpu_problem(L3, **kw)
+    Q.load_state(state)
+    I2, st2 = Q.march_continue(Vd, I1, 20, nt - 20)
+    np.testing.assert_array_equal(I2.cpu().numpy(), I)
+    assert st2["residual_checks"] == 2
+    assert st2["residual_worst_step"] == max((31, 47), key=lambda q: ref[q])
+    assert st2["max_residual64"] == pytest.approx(max(ref[31], ref[47]), rel=1e-6)
+    Q.close()
