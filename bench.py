@@ -205,7 +205,8 @@ def roofline_record(dom, d, info, batch, traffic):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=0, help="timed steps (default: the workload's N_t)")
+    ap.add_argument("--steps", type=int, default=100,
+                    help="timed steps (default 100, centred on the pulse peak inside the configured march)")
     ap.add_argument("--warmup", type=int, default=5, help="at least this many untimed steps before the window")
     ap.add_argument("--first", type=int, default=-1,
                     help="first timed step (default: the window is centred on the pulse peak)")
@@ -246,12 +247,15 @@ def main():
         # CPU leg of minutes; whole-step graphs need the register plane kernels
         args.no_cpu = True
         args.no_step_graph = True
-    K = args.steps or (100 if large else wl.nt)
+    K = args.steps
     xyz, _, _ = wl.mesh()
     dt = derived_dt(wl, xyz)
     ng = wl.ng   # every bench workload states N_g
     first, kt, peak = window(wl, dt, ng, K, args.warmup, args.first)
     nt = first + K
+    if nt > wl.nt:
+        # past the configured length the growing mode of the CPPIF envelope march can overflow FP32
+        log(f"[bench] note: the window ends at step {nt - 1}, past the workload's {wl.nt} steps")
     torch.cuda.set_device(0)
     if args.calib_copy:
         n = args.calib_copy * (1 << 20) // 4
