@@ -1028,10 +1028,11 @@ __global__ void __launch_bounds__((lines4_threads<R, A, B>())) k_zg4(cplx<R>* __
     for (int t = threadIdx.x; t < MT * B; t += blockDim.x) {
         const int l = t % MT, n2 = t / MT, ky = ky0 + l;
         cplx<R> u[A];
+        // the padded half (z >= N_z = L/2, i.e. n1 >= A/2) is zero
 #pragma unroll
         for (int n1 = 0; n1 < A; ++n1) {
             const int z = n2 + B * n1;
-            u[n1] = (ky < Ly && z < Nz) ? base[(size_t)z * Ly + ky] : cplx<R>{0, 0};
+            u[n1] = (n1 < A / 2 && ky < Ly) ? base[(size_t)z * Ly + ky] : cplx<R>{0, 0};
         }
         l4_fwd_first<R, A, B, MT, true>(u, Y, tw, l, n2);
     }
@@ -1043,7 +1044,7 @@ __global__ void __launch_bounds__((lines4_threads<R, A, B>())) k_zg4(cplx<R>* __
         const int fy = fold(ky < Ly ? ky : 0, Ly);
         cplx<R> u[B];
 #pragma unroll
-        for (int n2 = 0; n2 < B; ++n2) u[n2] = Y[l4_y<A, B, MT, true>(l, k1, n2)];
+        for (int n2 = 0; n2 < B; ++n2) u[n2] = Y[l4_y<R, A, B, true>(l, k1, n2)];
         dft_small<R, B>(u, false);
 #pragma unroll
         for (int k2 = 0; k2 < B; ++k2) {
@@ -1059,14 +1060,11 @@ __global__ void __launch_bounds__((lines4_threads<R, A, B>())) k_zg4(cplx<R>* __
         const int l = t % MT, n2 = t / MT, ky = ky0 + l;
         cplx<R> u[A];
 #pragma unroll
-        for (int k1 = 0; k1 < A; ++k1) u[k1] = Y[l4_y<A, B, MT, true>(l, k1, n2)];
+        for (int k1 = 0; k1 < A; ++k1) u[k1] = Y[l4_y<R, A, B, true>(l, k1, n2)];
         dft_small<R, A>(u, true);
         if (ky < Ly)
 #pragma unroll
-            for (int n1 = 0; n1 < A; ++n1) {
-                const int z = n2 + B * n1;
-                if (z < Nz) base[(size_t)z * Ly + ky] = u[n1];
-            }
+            for (int n1 = 0; n1 < A / 2; ++n1) base[(size_t)(n2 + B * n1) * Ly + ky] = u[n1];
     }
 }
 

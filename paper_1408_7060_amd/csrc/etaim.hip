@@ -286,23 +286,31 @@ bool line_fits(const Radix& pl) {
 
 // one four-step line launch; the LDS attribute is raised once per instance
 // where the block's buffers pass 64 KB
-template <typename R, int A, int B, bool LF>
+template <typename R, int A, int B, bool LF, bool HALF>
 int launch_l4(etaim_ctx* c, dim3 grid, const cplx<R>* in, cplx<R>* out, const cplx<R>* tw, const LineArgs& a) {
     constexpr size_t lds = lines4_lds<R, A, B, LF>();
     static bool attr = false;
     if (lds > 64 * 1024 && !attr) {
-        HIPCHK(hipFuncSetAttribute((const void*)k_lines4<R, A, B, LF>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)lds));
+        HIPCHK(hipFuncSetAttribute((const void*)k_lines4<R, A, B, LF, HALF>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         attr = true;
     }
-    hipLaunchKernelGGL((k_lines4<R, A, B, LF>), grid, dim3(lines4_threads<R, A, B>()), lds, c->stream, in, out, tw, a);
+    hipLaunchKernelGGL((k_lines4<R, A, B, LF, HALF>), grid, dim3(lines4_threads<R, A, B>()), lds, c->stream, in, out,
+                       tw, a);
     HIPCHK(hipGetLastError());
     return ETAIM_OK;
 }
 template <typename R, int A, int B>
 int launch_l4(etaim_ctx* c, bool lf, dim3 grid, const cplx<R>* in, cplx<R>* out, const cplx<R>* tw,
               const LineArgs& a) {
-    return lf ? launch_l4<R, A, B, true>(c, grid, in, out, tw, a) : launch_l4<R, A, B, false>(c, grid, in, out, tw, a);
+    // the zero-padded forward input or the pruned inverse output, fixed at compile time
+    const int L = A * B;
+    const bool half = a.inverse ? (a.out_len == L / 2 && a.in_len == L) : (a.in_len == L / 2 && a.out_len == L);
+    if (half)
+        return lf ? launch_l4<R, A, B, true, true>(c, grid, in, out, tw, a)
+                  : launch_l4<R, A, B, false, true>(c, grid, in, out, tw, a);
+    return lf ? launch_l4<R, A, B, true, false>(c, grid, in, out, tw, a)
+              : launch_l4<R, A, B, false, false>(c, grid, in, out, tw, a);
 }
 // the four-step instances of lines4_split
 #define ETAIM_L4_SPLITS(X) X(8, 12) X(12, 12) X(8, 24) X(12, 24) X(16, 24) X(24, 24)

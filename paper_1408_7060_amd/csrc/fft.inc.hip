@@ -422,18 +422,26 @@ template <typename R, int A, int B>
 __host__ __device__ constexpr int lines4_threads() {
     return lines4_mt<R>() * (A > B ? A : B);
 }
+// lanes over the lines: the k1 rows of Y are padded by 128 bytes, so that
+// the four (FP32) or eight (FP64) k1 rows one wave reads in the second
+// step fall on alternate halves of the LDS banks
+template <typename R>
+__host__ __device__ constexpr int lines4_pad() {
+    return 128 / (int)sizeof(cplx<R>);
+}
 template <typename R, int A, int B, bool LF>
 __host__ __device__ constexpr int lines4_ysize() {
-    return LF ? A * B * lines4_mt<R>() : lines4_mt<R>() * A * (B + 1);
+    return LF ? A * (B * lines4_mt<R>() + lines4_pad<R>()) : lines4_mt<R>() * A * (B + 1);
 }
 template <typename R, int A, int B, bool LF>
 __host__ __device__ constexpr size_t lines4_lds() {
     return (size_t)(A * B + lines4_ysize<R, A, B, LF>()) * sizeof(cplx<R>);
 }
 
-template <int A, int B, int MT, bool LF>
+template <typename R, int A, int B, bool LF>
 __device__ __forceinline__ int l4_y(int l, int k1, int n2) {
-    return LF ? (k1 * B + n2) * MT + l : (l * A + k1) * (B + 1) + n2;
+    constexpr int MT = lines4_mt<R>();
+    return LF ? k1 * (B * MT + lines4_pad<R>()) + n2 * MT + l : (l * A + k1) * (B + 1) + n2;
 }
 
 // tasks over (line, j), j < J: t -> (l, j)
@@ -453,7 +461,7 @@ template <typename R, int A, int B, int MT, bool LF>
 __device__ __forceinline__ void l4_fwd_first(cplx<R> (&u)[A], cplx<R>* Y, const cplx<R>* tw, int l, int n2) {
     dft_small<R, A>(u, false);
 #pragma unroll
-    for (int k1 = 0; k1 < A; ++k1) Y[l4_y<A, B, MT, LF>(l, k1, n2)] = k1 ? u[k1] * tw[n2 * k1] : u[k1];
+    for (int k1 = 0; k1 < A; ++k1) Y[l4_y<R, A, B, LF>(l, k1, n2)] = k1 ? u[k1] * tw[n2 * k1] : u[k1];
 }
 
 // inverse: X (stride A per k2, in u) -> Y
@@ -468,11 +476,15 @@ __device__ __forceinline__ void l4_inv_first(cplx<R> (&u)[B], cplx<R>* Y, const 
             w.y = -w.y;
             v = v * w;
         }
-        Y[l4_y<A, B, MT, LF>(l, k1, n2)] = v;
+        Y[l4_y<R, A, B, LF>(l, k1, n2)] = v;
     }
 }
 
-template <typename R, int A, int B, bool LF>
+// HALF: the zero-padded half is known at compile time (forward: in_len =
+// L/2, so n1 >= A/2 load as zero; inverse: out_len = L/2, so only n1 < A/2
+// are stored), and the codelets drop the work on those constant zeros and
+// unused outputs.
+template <typename R, int A, int B, bool LF, bool HALF>
 __global__ void __launch_bounds__((lines4_threads<R, A, B>())) k_lines4(const cplx<R>* in, cplx<R>* out,
                                                                      const cplx<R>* __restrict__ tw_g,
                                                                      LineArgs a) {
@@ -496,7 +508,10 @@ __global__ void __launch_bounds__((lines4_threads<R, A, B>())) k_lines4(const cp
 #pragma unroll
             for (int n1 = 0; n1 < A; ++n1) {
                 const int n = n2 + B * n1;
-                u[n1] = (f < a.nf && n < a.in_len) ? ibase[f * a.in_f + n * a.in_p] : cplx<R>{0, 0};
+                if (HALF && n1 >= A / 2)
+                    u[n1] = cplx<R>{0, 0};
+                else
+                    u[n1] = (f < a.nf && (HALF || n < a.in_len)) ? ibase[f * a.in_f + n * a.in_p] : cplx<R>{0, 0};
             }
             l4_fwd_first<R, A, B, MT, LF>(u, Y, tw, l, n2);
         }
@@ -507,7 +522,7 @@ __global__ void __launch_bounds__((lines4_threads<R, A, B>())) k_lines4(const cp
             const int f = f0 + l;
             cplx<R> u[B];
 #pragma unroll
-            for (int n2 = 0; n2 < B; ++n2) u[n2] = Y[l4_y<A, B, MT, LF>(l, k1, n2)];
+            for (int n2 = 0; n2 < B; ++n2) u[n2] = Y[l4_y<R, A, B, LF>(l, k1, n2)];
             dft_small<R, B>(u, false);
             if (f < a.nf)
 #pragma unroll
@@ -536,13 +551,13 @@ __global__ void __launch_bounds__((lines4_threads<R, A, B>())) k_lines4(const cp
             const int f = f0 + l;
             cplx<R> u[A];
 #pragma unroll
-            for (int k1 = 0; k1 < A; ++k1) u[k1] = Y[l4_y<A, B, MT, LF>(l, k1, n2)];
+            for (int k1 = 0; k1 < A; ++k1) u[k1] = Y[l4_y<R, A, B, LF>(l, k1, n2)];
             dft_small<R, A>(u, true);
             if (f < a.nf)
 #pragma unroll
-                for (int n1 = 0; n1 < A; ++n1) {
+                for (int n1 = 0; n1 < (HALF ? A / 2 : A); ++n1) {
                     const int n = n2 + B * n1;
-                    if (n < a.out_len) obase[f * a.out_f + n * a.out_p] = u[n1];
+                    if (HALF || n < a.out_len) obase[f * a.out_f + n * a.out_p] = u[n1];
                 }
         }
     }
