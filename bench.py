@@ -202,6 +202,45 @@ def roofline_record(dom, d, info, batch, traffic):
             "bytes_per_launch": bytes_launch, "avg_launch_ms": avg_ms, "launches": d["launches"]}
 
 
+def sweep(torch, W, FP64):
+    """The ET-AIM size and bandwidth sweep of spheres (the trends of the
+    paper's Figs. 2-3 without the comparison methods): every size at
+    chi = 3 and 100, every chi at the smallest and the level-4 size; per
+    point the whole march of one incidence along -z in FP64 (GMRES tol 1e-6,
+    near-zone approximate inverse), its right-hand-side, solve and commit
+    time per step, iterations per step, N_t, N_g and M_n."""
+    from paper_1408_7060_amd._lib import F_CONTINUE_ON_NOCONV
+    pts = [(L, a, g, chi) for (L, a, g) in W.SWEEP_SIZES for chi in (3, 100)]
+    pts += [(L, a, g, chi) for (L, a, g) in (W.SWEEP_SIZES[0], W.SWEEP_SIZES[2]) for chi in (10, 30)]
+    torch.cuda.set_device(0)
+    for (L, a, g, chi) in pts:
+        wl = W.sweep_workload(L, a, g, chi)
+        t = time.perf_counter()
+        P = make_problem(wl, FP64, 1, wl.nt, 1e-6, flags=F_CONTINUE_ON_NOCONV)
+        setup_s = time.perf_counter() - t
+        kh, pp = wl.incidence()
+        V = P.excitation(kh, pp, wl.sigma, wl.td)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, st = P.march(V)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t
+        nt = st["steps_done"]
+        rec = {"point": wl.name, "ns": P.ns, "chi": chi, "f_c_MHz": round(wl.f0 / 1e6, 1),
+               "f_bw_MHz": round(wl.f_bw / 1e6, 2), "grid": g, "ng": P.info["ng"], "mn": P.info["mn"],
+               "nnz": P.info["nnz"], "nt": nt, "gmres_iters_per_step": round(st["total_iters"] / max(nt, 1), 2),
+               "ms_rhs_per_step": round(st["ms_rhs"] / max(nt, 1), 3),
+               "ms_solve_per_step": round(st["ms_solve"] / max(nt, 1), 3),
+               "ms_commit_per_step": round(st["ms_commit"] / max(nt, 1), 3),
+               "march_s": round(wall, 3), "setup_s": round(setup_s, 2),
+               "unstable_step": st["unstable_step"] if st["unstable_step"] >= 0 else None,
+               "first_noconv_step": st["first_noconv_step"] if st["first_noconv_step"] >= 0 else None}
+        P.close()
+        del V
+        torch.cuda.empty_cache()
+        print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -227,6 +266,9 @@ def main():
     ap.add_argument("--true-residual", action="store_true",
                     help="confirm each step's convergence with a recomputed true residual (one operator "
                          "application more per step) instead of stopping on the GMRES residual estimate")
+    ap.add_argument("--sweep", action="store_true",
+                    help="instead of the bench: the sphere size and bandwidth sweep (ET-AIM only, FP64), one JSON "
+                         "line per point")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="first copy this many MiB device-to-device (counter calibration)")
     args = ap.parse_args()
@@ -236,6 +278,8 @@ def main():
     import torch
     import workloads as W
     from paper_1408_7060_amd import FP32, FP64
+    if args.sweep:
+        return sweep(torch, W, FP64)
     from paper_1408_7060_amd._lib import F_CONTINUE_ON_NOCONV, F_GRAPH, F_IMPLICIT_STOP, F_RESIDUAL_CHECK
     # the FP64 residual check of eq. (5) every 16 steps is part of the precision form
     fl = F_CONTINUE_ON_NOCONV | F_RESIDUAL_CHECK | (0 if args.true_residual else F_IMPLICIT_STOP)

@@ -403,3 +403,24 @@ COMPOSITE_SMALL = Workload("composite6_250MHz", level=0, radius=0.0, f0=250e6, f
 
 WORKLOADS = {w.name: w for w in (SPHERE_L2, SPHERE_L4, SPHERE_L4_BATCH, SPHERE_L4_ADJ, SPHERE_L3,
                                  SPHERE_L2_NARROW, COMPOSITE, COMPOSITE_SMALL)}
+
+# size and bandwidth sweep of spheres (ET-AIM only): the band's top fixed at
+# f_max = 300 MHz while chi = f_max / f_bw varies (f_c = f_max - f_bw), and
+# the radius doubling with each icosphere level, so that the mesh keeps an
+# edge of about 15 cm (lambda_min / 6.7); grids of about 8.5 cm spacing
+SWEEP_F_MAX = 300e6
+SWEEP_SIZES = ((2, 0.5, 16), (3, 1.0, 24), (4, 2.0, 48), (5, 4.0, 96), (6, 8.0, 192))   # level, radius, grid
+SWEEP_CHI = (3, 10, 30, 100)
+
+
+def sweep_workload(level: int, radius: float, grid: int, chi: float) -> Workload:
+    """Sphere of the sweep at one size and bandwidth: beta = 1/5, near zone
+    0.3 lambda_c, one incidence along -z; the march long enough for the
+    pulse (t_d + 8 sigma) and one crossing of the sphere."""
+    f_bw = SWEEP_F_MAX / chi
+    f0 = SWEEP_F_MAX - f_bw
+    sigma = 3.0 / (2.0 * math.pi * f_bw)
+    dt = 0.2 / f_bw
+    nt = int(math.ceil((16.0 * sigma + 2.0 * radius / C0) / dt)) + 4
+    return Workload(f"sweep_L{level}_r{radius:g}_chi{chi:g}", level=level, radius=radius, f0=f0,
+                    frac_bw=f_bw / f0, nt=nt, grid=grid, near_lambda=0.3, beta=0.2)
