@@ -148,3 +148,19 @@ def test_rmax_from_hull_equals_brute_force():
         d = xyz[s:s + 256, None, :] - xyz[None, :, :]
         best = max(best, float(np.sqrt((d * d).sum(-1)).max()))
     assert ph.rmax_of(xyz) == best
+
+
+def test_sweep_recipes():
+    """The sweep keeps the band's top at 300 MHz (f_c + f_bw) while chi =
+    f_max / f_bw varies, marches past the pulse and one crossing, and keeps
+    the sphere's mesh edge at about 15 cm as the radius doubles per level."""
+    for level, radius, grid in W.SWEEP_SIZES:
+        xyz, tri = W.icosphere(level, radius)
+        e = np.linalg.norm(xyz[tri[:, 0]] - xyz[tri[:, 1]], axis=1)
+        assert 0.10 < np.median(e) < 0.20, (level, radius, np.median(e))
+        for chi in W.SWEEP_CHI:
+            wl = W.sweep_workload(level, radius, grid, chi)
+            assert wl.f0 + wl.f_bw == pytest.approx(300e6, rel=1e-12)
+            assert 300e6 / wl.f_bw == pytest.approx(chi, rel=1e-12)
+            dt = wl.beta / wl.f_bw
+            assert wl.nt * dt >= 16 * wl.sigma + 2 * radius / 299_792_458.0
