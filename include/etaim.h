@@ -221,10 +221,12 @@ int etaim_march_continue(etaim_ctx *ctx, const void *V, void *I_out, int32_t fir
  * order.  etaim_state_size gives the bytes; save copies the state of the
  * last completed forward march to caller-owned host memory (ETAIM_EINVAL if
  * there is none, or after etaim_delayed_field / an adjoint march / a change
- * between the LDS and register y/z engines replaced the rings); load
- * restores it into a context of the same problem (precision, batch, mesh,
- * grid, N_g, M_n; ETAIM_EINVAL otherwise).  At the bench workload the state
- * is 21.7 GB. */
+ * between the register plane engines (yz_engine 1, 2: ring slots by parity
+ * quadrants) and the LDS or line-pass engines (0, 3: plain slots) replaced
+ * the rings); load restores it into a context of the same problem
+ * (precision, batch, mesh, grid, N_g, M_n) whose y/z engine lays the ring
+ * out the same way (ETAIM_EINVAL otherwise).  At the bench workload the
+ * state is 21.7 GB. */
 int etaim_state_size(const etaim_ctx *ctx, size_t *bytes);
 int etaim_state_save(const etaim_ctx *ctx, void *host, size_t bytes);
 int etaim_state_load(etaim_ctx *ctx, const void *host, size_t bytes);

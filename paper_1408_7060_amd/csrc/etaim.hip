@@ -2305,8 +2305,10 @@ namespace {
 struct StateHeader {
     char magic[8];
     int32_t version, prec, B, ns, ng, mn, next_step, guess_p, guess_dev, pnext;
+    int32_t quad, pad;  // ring slots by parity quadrants (register plane engines) or plain
     int64_t Np, ring_bytes, hist_bytes;
 };
+constexpr int32_t kStateVersion = 2;
 constexpr char kStateMagic[8] = {'E', 'T', 'A', 'I', 'M', 'S', 'T', '1'};
 
 size_t ring_bytes(const etaim_ctx* c) {
@@ -2330,7 +2332,8 @@ int etaim_state_save(const etaim_ctx* c, void* host, size_t bytes) {
     if (c->next_step < 1) return fail(ETAIM_EINVAL, "no forward march state to save");
     StateHeader h{};
     std::memcpy(h.magic, kStateMagic, 8);
-    h.version = 1;
+    h.version = kStateVersion;
+    h.quad = (c->yz_engine == 1 || c->yz_engine == 2) ? 1 : 0;
     h.prec = c->prec;
     h.B = c->B;
     h.ns = c->ns;
@@ -2358,8 +2361,11 @@ int etaim_state_load(etaim_ctx* c, const void* host, size_t bytes) {
     if (bytes != sizeof(StateHeader) + rb + hb) return fail(ETAIM_EINVAL, "state size mismatch");
     StateHeader h;
     std::memcpy(&h, host, sizeof h);
-    if (std::memcmp(h.magic, kStateMagic, 8) != 0 || h.version != 1)
+    if (std::memcmp(h.magic, kStateMagic, 8) != 0 || h.version != kStateVersion)
         return fail(ETAIM_EINVAL, "not a march state of this library");
+    if (h.quad != ((c->yz_engine == 1 || c->yz_engine == 2) ? 1 : 0))
+        return fail(ETAIM_EINVAL, "the state's spectrum ring is laid out for the other class of y/z engines "
+                                  "(parity quadrants or plain): set the y/z engine it was saved with");
     if (h.prec != c->prec || h.B != c->B || h.ns != c->ns || h.ng != c->st.ng || h.mn != c->st.mn ||
         h.Np != (int64_t)c->Np || h.ring_bytes != (int64_t)rb || h.hist_bytes != (int64_t)hb)
         return fail(ETAIM_EINVAL, "the state belongs to a different problem (precision, batch, mesh or grid)");

@@ -143,3 +143,42 @@ def test_state_with_a_corrupt_guess_order_is_refused(torch):
         assert ei.value.code == -1
     P.load_state(state)
     P.close()
+
+
+def test_state_of_another_ring_layout_is_refused(torch):
+    """A state saved with the register plane engine (ring slots by parity
+    quadrants) loads into a context with the other register engine, not
+    into one with the line-pass engine (plain slots); saved with the
+    line-pass engine, it loads there and continues the march bit for bit."""
+    nt = 10
+    V = _excitation(nt, 1, 55)
+    Vd = torch.from_numpy(np.ascontiguousarray(V)).cuda()
+    kw = dict(precision=0, nt=nt, batch=1, flags=F_CONTINUE_ON_NOCONV)
+    P = gpu_problem(L2, **kw)
+    t0 = P.tuning()
+    assert t0["yz_engine"] == 2
+    I, _ = P.march(Vd, nsteps=4)
+    state = P.save_state()
+    P.close()
+    for yz, ok in ((1, True), (3, False), (0, False)):
+        Q = gpu_problem(L2, **kw)
+        Q.set_tuning(dict(Q.tuning(), yz_engine=yz))
+        if ok:
+            Q.load_state(state)
+        else:
+            with pytest.raises(Exception) as ei:
+                Q.load_state(state)
+            assert ei.value.code == -1
+        Q.close()
+    R = gpu_problem(L2, **kw)
+    R.set_tuning(dict(R.tuning(), yz_engine=3))
+    I_full, _ = R.march(Vd)
+    I3, _ = R.march(Vd, nsteps=4)
+    s3 = R.save_state()
+    R.close()
+    S = gpu_problem(L2, **kw)
+    S.set_tuning(dict(S.tuning(), yz_engine=3))
+    S.load_state(s3)
+    I3, _ = S.march_continue(Vd, I3, 4, nt - 4)
+    np.testing.assert_array_equal(I3.cpu().numpy(), I_full.cpu().numpy())
+    S.close()
