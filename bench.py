@@ -399,6 +399,10 @@ def main():
                        if v["launches"]},
            "kernels_from": f"steps {first - kt}..{first - 1}, every class traced"}
     I32_0 = I32[:, 0].cpu().numpy()
+    # the current's growth over the window (direction 0): a stable march
+    # follows the pulse; the CPPIF growing mode multiplies it every step
+    n0, n1 = (float(np.linalg.norm(I32_0[q])) for q in (first, nt - 1))
+    out["current_growth_per_step_dir0"] = round((n1 / n0) ** (1.0 / max(K - 1, 1)), 4) if n0 > 0 else None
     P.close()
     del I32
     if args.graph or (tuning and tuning["graph"]):

@@ -142,8 +142,9 @@ typedef struct {
     int32_t first_noconv_step; /* -1 if every step converged */
     int32_t unstable_step;     /* -1, or the step where late-time growth was flagged: the
                                   current norm grew monotonically by more than 10x over 32 steps
-                                  of this call that follow the step where the excitation's norm
-                                  peaked, with the excitation below 1e-6 of that peak */
+                                  of this call that begin more than N_g steps after the step
+                                  where the excitation's norm peaked (the pulse has crossed the
+                                  object) */
     double ms_rhs, ms_solve, ms_commit, ms_total;  /* device time per phase */
     double max_rel_residual;   /* largest final relative residual (estimate) */
     int32_t *iters_per_step;   /* optional caller host buffer [N_t] (or NULL) */

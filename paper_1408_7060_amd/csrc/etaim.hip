@@ -1471,18 +1471,14 @@ int march_impl(etaim_ctx* c, const zd* V, zd* I, etaim_stats* st, bool adjoint, 
     size_t nchk = 0;
     const int W = 32;
     auto detect = [&](int r) {
-        // late-time growth: monotone growth by > 10x over W steps that follow
-        // the excitation's peak, while the excitation is negligible (a current
-        // that grows with a rising pulse is not flagged)
-        if (unstable >= 0 || r < W || r - W + 1 <= vpeak) return;
+        // late-time growth: monotone growth by > 10x over W steps that begin
+        // after the excitation's peak plus N_g steps (the pulse has crossed the
+        // object, so the current of a stable march decays with the excitation;
+        // a current that grows with a rising pulse is not flagged)
+        if (unstable >= 0 || r < W || r - W + 1 <= vpeak + c->st.ng) return;
         bool mono = nI[r] > 10.0 * nI[r - W];
-        double vw = 0;
-        for (int q = r - W + 1; q <= r && mono; ++q) {
-            mono = nI[q] > nI[q - 1];
-            const int lq = adjoint ? nt - 1 - q : q;
-            for (int b = 0; b < B; ++b) vw = std::max(vw, nV[(size_t)lq * B + b]);
-        }
-        if (mono && vw < 1e-6 * vmax) unstable = r;
+        for (int q = r - W + 1; q <= r && mono; ++q) mono = nI[q] > nI[q - 1];
+        if (mono) unstable = r;
     };
     // phase times of a step, read once its events are complete
     auto phase_ms = [&](int r) -> int {
