@@ -24,6 +24,12 @@ rule to ref. [13] and the matrix entries to ref. [7]):
 * System (eq. (5), parentheses restored):
   (Z^near_0 + Z^FFT_0) I_l = V_l - sum_{m>=1} (Z^near_m + Z^FFT_m) I_{l-m}.
 
+* CFIE (alpha < 1, ``oracle.mfie``): the far part is alpha times the EFIE
+  far part above plus (1 - alpha) eta times the MFIE far part
+  - sum_c H_c G^H_m L_c^T, on the same anterpolated components.  Each
+  product is a channel (test projection, source component, Green table,
+  coefficient); the EFIE has four, the CFIE seven.
+
 Pins: projection moments vs the simplex monomial formula, FFT convolution
 vs the literal double sum, symmetry, AIM accuracy on separated pairs.
 """
@@ -36,7 +42,7 @@ import numpy as np
 from . import cppif
 from .geometry import Surface
 from .kernels import EnvelopeKernel
-from .physics import C0
+from .physics import C0, ETA0
 from .quadrature import collapsed_gauss, points
 
 # threads of the 3-D transforms: 1 = numpy's FFT; more = scipy.fft with that
@@ -187,14 +193,27 @@ def near_depth(d_near: float, r_max: float, dt: float, ng: int, q: int = cppif.Q
 
 
 class AIM:
-    """All L-B pieces for one problem."""
+    """All L-B pieces for one problem (alpha = 1: EFIE; alpha < 1: CFIE)."""
 
-    def __init__(self, surf: Surface, grid_n, d_near: float, dt: float, fc: float, ng: int):
+    def __init__(self, surf: Surface, grid_n, d_near: float, dt: float, fc: float, ng: int,
+                 alpha: float = 1.0):
         self.surf, self.dt, self.fc, self.ng, self.d_near = surf, dt, fc, ng, d_near
+        self.alpha = float(alpha)
         self.grid = Grid(surf.xyz, grid_n)
         self.L, self.i0 = projection(surf, self.grid)
         self.nodes = stencil_nodes(self.grid, self.i0)
         self.GA, self.GP = green_tables(self.grid, range(ng + 1), dt, fc)
+        self.tables = {"A": self.GA, "P": self.GP}
+        a = self.alpha
+        # channels: (test projection [ns,64], source component, table, coefficient)
+        self.channels = [(self.L[:, c, :], c, "A", a) for c in range(3)] + [(self.L[:, 3, :], 3, "P", a)]
+        if a != 1.0:
+            from . import mfie
+            self.H = mfie.projection_curl(surf, self.grid, self.i0)
+            self.GH = mfie.green_table_h(self.grid, range(ng + 1), dt, fc)
+            self.tables["H"] = self.GH
+            b = -(1.0 - a) * ETA0
+            self.channels += [(self.H[:, c, :], c, "H", b) for c in range(3)]
         self.rows, self.cols = near_pairs(surf, d_near)
         self.r_max = stencil_radius(surf, self.grid, self.i0)
         self.mn = near_depth(d_near, self.r_max, dt, ng)
@@ -207,28 +226,29 @@ class AIM:
             np.add.at(q[c], self.nodes.ravel(), (self.L[:, c, :] * x[:, None]).ravel())
         return q
 
-    def interpolate(self, p: np.ndarray) -> np.ndarray:
-        """y [ns] = sum_c L_c p_c (stage (iii))."""
-        return sum(np.einsum("kn,kn->k", self.L[:, c, :], p[c][self.nodes]) for c in range(4))
+    def interpolate(self, p) -> np.ndarray:
+        """y [ns] = sum over channels of coef * T_ch p_ch (stage (iii)); p holds
+        one potential grid per channel."""
+        return sum(coef * np.einsum("kn,kn->k", T, p[i][self.nodes])
+                   for i, (T, _, _, coef) in enumerate(self.channels))
 
-    def propagate_direct(self, m: int, q: np.ndarray) -> np.ndarray:
-        """p = G_m q by the literal double sum over grid nodes (stage (ii))."""
-        out = np.empty_like(q)
-        GA = dense_node_matrix(self.grid, self.GA[m])
-        for c in range(3):
-            out[c] = GA @ q[c]
-        del GA
-        out[3] = dense_node_matrix(self.grid, self.GP[m]) @ q[3]
-        return out
+    def propagate_direct(self, m: int, q: np.ndarray) -> list:
+        """p_ch = G_m q_src per channel by the literal double sum over grid nodes
+        (stage (ii))."""
+        dense = {key: dense_node_matrix(self.grid, tab[m]) for key, tab in self.tables.items()}
+        return [dense[key] @ q[src] for _, src, key, _ in self.channels]
+
+    def ghat(self, m: int, key: str) -> np.ndarray:
+        """FFT of the circulant embedding of table `key` at m, [2Nz, 2Ny, 2Nx];
+        computed once per (m, key) and kept."""
+        cache = self.__dict__.setdefault("_ghat", {})
+        if (m, key) not in cache:
+            cache[(m, key)] = _fftn(circulant(self.tables[key][m]))
+        return cache[(m, key)]
 
     def green_hat(self, m: int, c: int) -> np.ndarray:
-        """FFT of the circulant embedding of G^A_m (c < 3) or G^phi_m (c = 3),
-        [2Nz, 2Ny, 2Nx]; computed once per (m, part) and kept."""
-        key = (m, c < 3)
-        cache = self.__dict__.setdefault("_ghat", {})
-        if key not in cache:
-            cache[key] = _fftn(circulant(self.GA[m] if c < 3 else self.GP[m]))
-        return cache[key]
+        """The EFIE's spectrum of component c: G^A_m (c < 3) or G^phi_m (c = 3)."""
+        return self.ghat(m, "A" if c < 3 else "P")
 
     def spectra(self, x: np.ndarray) -> np.ndarray:
         """Forward FFT of the zero-padded anterpolated grid, [4, 2Nz, 2Ny, 2Nx]."""
@@ -240,16 +260,15 @@ class AIM:
             out[c] = _fftn(out[c])
         return out
 
-    def propagate_fft(self, m: int, q: np.ndarray) -> np.ndarray:
-        """p = G_m q by zero-padded circulant FFT convolution (2N per axis)."""
+    def propagate_fft(self, m: int, q: np.ndarray) -> list:
+        """p_ch = G_m q_src by zero-padded circulant FFT convolution (2N per axis)."""
         nx, ny, nz = self.grid.n
-        out = np.empty_like(q)
+        qh = []
         for c in range(4):
             qq = np.zeros((2 * nz, 2 * ny, 2 * nx), dtype=np.complex128)
             qq[:nz, :ny, :nx] = q[c].reshape(nz, ny, nx)
-            p = _ifftn(self.green_hat(m, c) * _fftn(qq))
-            out[c] = p[:nz, :ny, :nx].ravel()
-        return out
+            qh.append(_fftn(qq))
+        return [_ifftn(self.ghat(m, key) * qh[src])[:nz, :ny, :nx].ravel() for _, src, key, _ in self.channels]
 
     def far_matvec(self, m: int, x: np.ndarray, direct: bool = False) -> np.ndarray:
         q = self.anterpolate(x)
@@ -259,17 +278,18 @@ class AIM:
     def far_sum_rows(self, terms, rows) -> np.ndarray:
         """sum_i Z^FFT_{m_i} x_i on the given rows only, for terms = [(m_i,
         spectra(x_i))]: the products with the Green spectra are summed before
-        one inverse transform (the transform is linear), then interpolated at
-        the stencils of ``rows``."""
+        one inverse transform per channel (the transform is linear), then
+        interpolated at the stencils of ``rows``."""
         nx, ny, nz = self.grid.n
         rows = np.asarray(rows)
-        p = np.empty((4, self.grid.nnodes), dtype=np.complex128)
-        for c in range(4):
+        y = 0
+        for T, src, key, coef in self.channels:
             acc = np.zeros((2 * nz, 2 * ny, 2 * nx), dtype=np.complex128)
             for m, qh in terms:
-                acc += self.green_hat(m, c) * qh[c]
-            p[c] = _ifftn(acc)[:nz, :ny, :nx].ravel()
-        return sum(np.einsum("kn,kn->k", self.L[rows, c, :], p[c][self.nodes[rows]]) for c in range(4))
+                acc += self.ghat(m, key) * qh[src]
+            p = _ifftn(acc)[:nz, :ny, :nx].ravel()
+            y = y + coef * np.einsum("kn,kn->k", T[rows], p[self.nodes[rows]])
+        return y
 
     def near_values_rows(self, zfill_pairs, rows):
         """Pre-corrected values [M_n+1, P] of the near pairs whose row is in
@@ -287,19 +307,19 @@ class AIM:
         np.add.at(y, rr, vals_m * x[cc])
         return y[np.asarray(rows)]
 
+    def _full(self, T: np.ndarray) -> np.ndarray:
+        ns = self.surf.ns
+        out = np.zeros((ns, self.grid.nnodes))
+        np.add.at(out, (np.repeat(np.arange(ns), 64), self.nodes.ravel()), T.ravel())
+        return out
+
     def far_dense(self, m: int) -> np.ndarray:
         """Z^FFT_m as a dense [ns, ns] matrix (tiny problems)."""
         ns = self.surf.ns
-        Lfull = np.zeros((4, ns, self.grid.nnodes))
-        for c in range(4):
-            np.add.at(Lfull[c], (np.repeat(np.arange(ns), 64), self.nodes.ravel()),
-                      self.L[:, c, :].ravel())
         Z = np.zeros((ns, ns), dtype=np.complex128)
-        GA = dense_node_matrix(self.grid, self.GA[m])
-        for c in range(3):
-            Z += Lfull[c] @ (GA @ Lfull[c].T)
-        del GA
-        Z += Lfull[3] @ (dense_node_matrix(self.grid, self.GP[m]) @ Lfull[3].T)
+        dense = {key: dense_node_matrix(self.grid, tab[m]) for key, tab in self.tables.items()}
+        for T, src, key, coef in self.channels:
+            Z += coef * (self._full(T) @ (dense[key] @ self._full(self.L[:, src, :]).T))
         return Z
 
     def far_pairs(self, m, rows, cols) -> np.ndarray:
@@ -315,12 +335,14 @@ class AIM:
             ib = np.stack([nb % nx, (nb // nx) % ny, nb // (nx * ny)], -1)
             d = np.abs(ia[:, :, None, :] - ib[:, None, :, :])       # [p,64,64,3]
             flat = (d[..., 2] * ny + d[..., 1]) * nx + d[..., 0]
-            sA = sum(np.einsum("pn,pq->pnq", self.L[r, cc], self.L[c, cc]) for cc in range(3))
-            sP = np.einsum("pn,pq->pnq", self.L[r, 3], self.L[c, 3])
+            # stencil weight products per table: sum over its channels of coef T_r L_c
+            prod = {}
+            for T, src, key, coef in self.channels:
+                w = coef * np.einsum("pn,pq->pnq", T[r], self.L[c, src])
+                prod[key] = prod[key] + w if key in prod else w
             for i, mm in enumerate(ms):
-                GA = self.GA[mm].ravel()[flat]
-                GP = self.GP[mm].ravel()[flat]
-                out[i, s:s + 512] = np.einsum("pnq,pnq->p", sA, GA) + np.einsum("pnq,pnq->p", sP, GP)
+                out[i, s:s + 512] = sum(np.einsum("pnq,pnq->p", w, self.tables[key][mm].ravel()[flat])
+                                        for key, w in prod.items())
         return out[0] if np.isscalar(m) else out
 
     # ---- near part

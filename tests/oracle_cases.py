@@ -29,3 +29,13 @@ def l2_band_params(frac=0.2, beta=0.2, fc=300e6):
     dt = beta / fbw
     ng = ph.ng_from(ph.rmax_of(s.xyz), dt)
     return dt, ng
+
+
+@functools.lru_cache(maxsize=None)
+def dense_h(dt, fc, ng, fd_freqs=()):
+    """Dense envelope MFIE Z^H_0..Z^H_ng followed by FD MFIE matrices at fd_freqs."""
+    from oracle import mfie
+    s = sphere()
+    ks = [mfie.MFIEKernel(m, dt, fc) for m in range(ng + 1)]
+    ks += [mfie.FDMFIEKernel(f) for f in fd_freqs]
+    return mfie.assemble_dense(s, ks)
