@@ -84,6 +84,24 @@ extern "C" {
                                         internal FP64 context of the same problem, about 1.4 GB at the
                                         level-4 size); results in etaim_stats */
 
+/* Integral equation (Sec. 2.1).  ETAIM_EFIE: the time-differentiated EFIE
+ * on the envelopes.  ETAIM_CFIE: alpha EFIE + (1 - alpha) eta MFIE, the
+ * MFIE taken on the exterior of the closed surface (outward normals, the
+ * mesh's counter-clockwise order), differentiated in time like the EFIE:
+ *   Z^H_m = D_m / 2 <S_k, S_k'> - int int g'_m(R) S_k . (n x (Rhat x S_k')),
+ *   g'_m = -(exp(-j k_c R)/4 pi) [P_A(tau)/(c R) + (T'/dt + j w_c T)(tau)/R^2],
+ * D_m = (T'/dt + j w_c T)(m) (piece m), the same 7 x 7 rule (zero on a
+ * triangle with itself).  Its far part is the curl of the interpolated
+ * potential: test projection H[k,:,n] = int (S_k x n) x grad l_n over the
+ * stencil's Lagrange functions, Green table exp(-j k_c R)(T'/dt + j w_c
+ * T)(tau)/(4 pi R) on the EFIE's anterpolated currents and forward
+ * spectra.  The excitation adds (1 - alpha) <S_k, n x (khat x D E~_inc)>.
+ * With ETAIM_CFIE the forward operators and the forward march are
+ * supported; the adjoint (transposed) operators and march return
+ * ETAIM_EUNSUPPORTED. */
+#define ETAIM_EFIE 0
+#define ETAIM_CFIE 1
+
 typedef struct etaim_ctx etaim_ctx;
 
 /* Triangle mesh of the closed PEC surface (Sec. 3, RWG on a triangular
@@ -126,6 +144,9 @@ typedef struct {
     int32_t sync_every; /* Arnoldi steps enqueued per host convergence check; 0 or 1 => check after
                            every step.  Steps enqueued past convergence return at once on the
                            device (a gate flag), so results do not depend on it. */
+    int32_t formulation; /* ETAIM_EFIE (0) or ETAIM_CFIE (1), Sec. 2.1 */
+    double alpha;        /* ETAIM_CFIE: weight of the EFIE, 0 <= alpha < 1 (the paper's spheres:
+                            0.5, Sec. 5.1); ignored for ETAIM_EFIE */
 } etaim_params;
 
 typedef struct {
@@ -369,7 +390,7 @@ typedef struct {
  * budget_ms bounds the timing work (>= 1; candidates are tried in order of
  * expected benefit).  cache_path (host string or NULL): a JSON-lines file; a
  * record whose key matches this problem's shape (precision, batch, ns,
- * grid, near-zone size, restart) is applied without timing, otherwise the
+ * grid, near-zone size, restart, formulation) is applied without timing, otherwise the
  * result is appended.  out (host, may be NULL) receives the setting.  Must
  * not run while a march is in flight on the context's stream.  Errors:
  * EINVAL (budget < 1), EHIP, or the cache file cannot be written (EINVAL). */
@@ -388,8 +409,9 @@ int etaim_set_tuning(etaim_ctx *ctx, const etaim_tuning *t);
  * row pointers int32 [ns+1], 3 column indices int32 [nnz], 4 pre-corrected
  * near values complex128 [mn+1][nnz] (m-major), 5 diagonal of Z0 complex128
  * [ns], 6 folded Green spectra complex128 [ng+1][2][gz+1][gy+1][gx+1]
- * (g = grid size, already divided by the padded size).  bytes must equal the
- * array size. */
+ * (g = grid size, already divided by the padded size; with ETAIM_CFIE the
+ * EFIE's, weighted by alpha), 7 (ETAIM_CFIE) the MFIE's curl test projection
+ * float64 [ns][4][64] (component 3 zero).  bytes must equal the array size. */
 int etaim_export(const etaim_ctx *ctx, int32_t what, void *host, size_t bytes);
 
 /* Message of the last failing call on this thread ("" if none). */

@@ -13,9 +13,9 @@ from ctypes import POINTER, byref, c_double, c_int32, c_size_t, c_void_p
 import numpy as np
 
 from . import _lib
-from ._lib import FP32, FP64, EtaimError, Stats
+from ._lib import CFIE, EFIE, FP32, FP64, EtaimError, Stats
 
-__all__ = ["Problem", "EtaimMarch", "EtaimError", "FP32", "FP64"]
+__all__ = ["Problem", "EtaimMarch", "EtaimError", "FP32", "FP64", "EFIE", "CFIE"]
 
 
 def _torch():
@@ -41,7 +41,7 @@ class Problem:
     def __init__(self, xyz, tri, rwg, *, fc: float, nt: int, grid, d_near: float, dt: float = 0.0,
                  beta: float = 0.0, f_bw: float = 0.0, ng: int = 0, precision: int = FP64, batch: int = 1,
                  tol: float = 1e-6, restart: int = 50, maxit: int = 1000, flags: int = 0, sync_every: int = 1,
-                 stream=None):
+                 alpha: float = 1.0, stream=None):
         torch = _torch()
         lib = _lib.load()
         self._xyz = np.ascontiguousarray(xyz, dtype=np.float64)
@@ -54,7 +54,8 @@ class Problem:
         p = _lib.Params(fc=fc, dt=dt, beta=beta, f_bw=f_bw, nt_steps=nt, order=3,
                         grid=(c_int32 * 3)(*[int(v) for v in g]), d_near=d_near, ng=ng, precision=precision,
                         batch=batch, tol=tol, restart=restart, maxit=maxit, flags=flags,
-                        sync_every=sync_every)
+                        sync_every=sync_every, formulation=EFIE if alpha == 1.0 else CFIE,
+                        alpha=alpha)
         if stream is None and torch.cuda.is_available():
             stream = torch.cuda.current_stream()
         self.stream = stream
@@ -178,7 +179,8 @@ class Problem:
                "near": (4, np.complex128, lambda i: (i["mn"] + 1, i["nnz"])),
                "diag": (5, np.complex128, lambda i: (i["ns"],)),
                "ghat": (6, np.complex128, lambda i: (i["ng"] + 1, 2, i["grid"][2] + 1, i["grid"][1] + 1,
-                                                     i["grid"][0] + 1))}
+                                                     i["grid"][0] + 1)),
+               "curl_lambda": (7, np.float64, lambda i: (i["ns"], 4, 64))}
 
     def export(self, what: str) -> np.ndarray:
         wid, dt, shape = self._EXPORT[what]

@@ -1300,6 +1300,8 @@ __device__ __forceinline__ R wave_sum(R v) {
 //                              + sum_e val[e][m] xr[col_e][b]
 // mode 1 (delayed): y[b][k] = V[b][k] - (interp(P) + sum_{m=1}^{nmh}
 //                              val[e][m] hist[(cur-m) mod mn][col_e][b])
+// mode 2: y[b][k] += interp(P);  mode 3: y[b][k] -= interp(P)  (no near
+// zone: the CFIE's MFIE far part, lam then its curl test projection)
 // xr = the scaled columns dinv . x and hist the current history, both in
 // the working precision with the columns of one basis contiguous ([ns][B]).
 // Lane j of the wave owns stencil node j (and near-zone entries e0 + j,
@@ -1340,7 +1342,7 @@ __global__ void __launch_bounds__(256) k_interp_near(
     R w[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) w[c] = lam[(size_t)k * 256 + 64 * c + j];
-    const int e0 = rowptr[k], e1 = rowptr[k + 1];
+    const int e0 = rowptr[k], e1 = mode >= 2 ? e0 : rowptr[k + 1];
     for (int b0 = 0; b0 < B; b0 += kInterpCols) {
         const int nb = min(kInterpCols, B - b0);
         cplx<R> acc[kInterpCols];
@@ -1430,8 +1432,12 @@ __global__ void __launch_bounds__(256) k_interp_near(
             const size_t o = (size_t)(b0 + bb) * ns + k;
             if (mode == 0)
                 y[o] = zd{(double)tot.x, (double)tot.y};
-            else
+            else if (mode == 1)
                 y[o] = zd{V[o].x - (double)tot.x, V[o].y - (double)tot.y};
+            else if (mode == 2)
+                y[o] = zd{y[o].x + (double)tot.x, y[o].y + (double)tot.y};
+            else
+                y[o] = zd{y[o].x - (double)tot.x, y[o].y - (double)tot.y};
         }
     }
 }
@@ -1611,6 +1617,29 @@ __global__ void k_green_table(zd* __restrict__ G, GridDims g, int ng, double h, 
     }
 }
 
+// CFIE: G[m][0][k][j][i] = scale exp(-j k R) [T'/dt + j w T](tau) / (4 pi R)
+// (the MFIE's potential, zero at the origin), G[m][1] = 0
+__global__ void k_green_table_h(zd* __restrict__ G, GridDims g, int ng, double h, EnvKernel K, double scale) {
+    const size_t n3 = (size_t)g.N[0] * g.N[1] * g.N[2];
+    const size_t tot = (size_t)(ng + 1) * n3;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot; e += (size_t)gridDim.x * blockDim.x) {
+        const int m = (int)(e / n3);
+        const size_t r = e - (size_t)m * n3;
+        const int i = (int)(r % g.N[0]);
+        const int j = (int)((r / g.N[0]) % g.N[1]);
+        const int k = (int)(r / ((size_t)g.N[0] * g.N[1]));
+        const double R = h * sqrt((double)(i * i + j * j + k * k));
+        zd v{0, 0};
+        if (R != 0.0) {
+            zd fa, fh;
+            K.evalh(m, R, fa, fh);
+            v = (scale / (4.0 * kPi * R)) * fh;
+        }
+        G[((size_t)m * 2 + 0) * n3 + r] = v;
+        G[((size_t)m * 2 + 1) * n3 + r] = zd{0, 0};
+    }
+}
+
 // circulant embedding of one |offset| table into the padded [Lz][Ly][Lx] grid
 __global__ void k_circulant(const zd* __restrict__ tab, zd* __restrict__ out, GridDims g) {
     const size_t tot = (size_t)g.L[0] * g.L[1] * g.L[2];
@@ -1645,11 +1674,13 @@ __global__ void k_fold(const zd* __restrict__ full, zd* __restrict__ out, GridDi
 
 // Pre-correction: val[e][m] = exact[e][m] - sum_c sum_{n,n'} L[k][c][n]
 //   G_m^c[|node_n - node_n'|] L[k'][c][n'] for every near pair e = (k, k').
+// CFIE (lamH set): minus also sum_{c<3} sum_{n,n'} H[k][c][n] GH_m[..] L[k'][c][n'].
 // One wavefront per pair; lane = local node n of k.
 __global__ void __launch_bounds__(64) k_precorrect(zd* __restrict__ val, const double* __restrict__ lam,
                                                    const int* __restrict__ i0, const int* __restrict__ rowof,
                                                    const int* __restrict__ col, const zd* __restrict__ G,
-                                                   GridDims g, int mv, int nnz) {
+                                                   GridDims g, int mv, int nnz, const double* __restrict__ lamH,
+                                                   const zd* __restrict__ GH) {
     __shared__ double lk2[256];
     const int e = blockIdx.x;
     if (e >= nnz) return;
@@ -1661,9 +1692,13 @@ __global__ void __launch_bounds__(64) k_precorrect(zd* __restrict__ val, const d
     const int jx = lane & 3, jy = (lane >> 2) & 3, jz = lane >> 4;
     const int ax = i0[3 * k] + jx, ay = i0[3 * k + 1] + jy, az = i0[3 * k + 2] + jz;
     const int bx = i0[3 * k2], by = i0[3 * k2 + 1], bz = i0[3 * k2 + 2];
-    double lk[4];
+    double lk[4], hk[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int c = 0; c < 4; ++c) lk[c] = lam[(size_t)k * 256 + 64 * c + lane];
+    if (lamH) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) hk[c] = lamH[(size_t)k * 256 + 64 * c + lane];
+    }
     const size_t n3 = (size_t)g.N[0] * g.N[1] * g.N[2];
     for (int m = 0; m < mv; ++m) {
         const zd* GA = G + ((size_t)m * 2 + 0) * n3;
@@ -1679,6 +1714,10 @@ __global__ void __launch_bounds__(64) k_precorrect(zd* __restrict__ val, const d
             const double sP = lk[3] * lk2[192 + q];
             acc += sA * ga;
             acc += sP * gp;
+            if (lamH) {
+                const double sH = hk[0] * lk2[q] + hk[1] * lk2[64 + q] + hk[2] * lk2[128 + q];
+                acc += sH * GH[((size_t)m * 2) * n3 + off];
+            }
         }
         const double re = wave_sum<double>(acc.x), im = wave_sum<double>(acc.y);
         if (lane == 0) {
@@ -1691,9 +1730,12 @@ __global__ void __launch_bounds__(64) k_precorrect(zd* __restrict__ val, const d
 // Plane-wave excitation, eq. (1) with (d/dt + j w) applied:
 // V[l][b][k] = sum_{half,q} (Sq . p) [g'(tau) + j w g(tau)] exp(-j w (r.k/c + td))
 // Sq[k][h][q][3]: quadrature-weighted basis values; rq: points.
+// CFIE (Snq set): the projection is alpha (Sq . p) + (1 - alpha) (Snq . (khat x p)),
+// Snq = the weighted S x n, i.e. alpha S . E~ + (1 - alpha) S . (n x (khat x E~))
 __global__ void k_excitation(zd* __restrict__ V, const double* __restrict__ Sq, const double* __restrict__ rq,
                              const double* __restrict__ khat, const double* __restrict__ phat, int nt, int nb,
-                             int ns, double dt, double sigma, double td, double w) {
+                             int ns, double dt, double sigma, double td, double w, const double* __restrict__ Snq,
+                             double alpha) {
     const size_t tot = (size_t)nt * nb * ns;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot; e += (size_t)gridDim.x * blockDim.x) {
         const int k = (int)(e % ns);
@@ -1710,7 +1752,13 @@ __global__ void k_excitation(zd* __restrict__ V, const double* __restrict__ Sq, 
             const double tau = t - rk - td;
             const double gg = exp(-tau * tau / (2.0 * sigma * sigma));
             const double dg = -(tau / (sigma * sigma)) * gg;
-            const double proj = S[0] * ph[0] + S[1] * ph[1] + S[2] * ph[2];
+            double proj = S[0] * ph[0] + S[1] * ph[1] + S[2] * ph[2];
+            if (Snq) {
+                const double* Sn = Snq + ((size_t)k * 14 + q) * 3;
+                const double hx = kh[1] * ph[2] - kh[2] * ph[1], hy = kh[2] * ph[0] - kh[0] * ph[2],
+                             hz = kh[0] * ph[1] - kh[1] * ph[0];
+                proj = alpha * proj + (1.0 - alpha) * (Sn[0] * hx + Sn[1] * hy + Sn[2] * hz);
+            }
             const double arg = w * (rk + td);
             const double c = cos(arg), s = -sin(arg);
             // (dg + j w gg) (c + j s)

@@ -147,6 +147,29 @@ struct EnvKernel {
         fa = ph * pa;
         fp = zd{c * d[0], s * d[0]};
     }
+    // CFIE: fA as eval and fH = exp(-j k R) [T'/dt + j w T](m - R/(c dt)),
+    // the temporal factor of the MFIE's potential
+    __host__ __device__ void evalh(int m, double R, zd& fa, zd& fh) const {
+        const double tau = (double)m - R / cdt;
+        double d[4];
+        if (!cppif_eval(tau, d)) {
+            fa = {0.0, 0.0};
+            fh = {0.0, 0.0};
+            return;
+        }
+        const double c = cos(k * R), s = -sin(k * R);
+        const zd ph{c, s};
+        const zd pa{d[2] / (dt * dt) - w * w * d[0], 2.0 * w * d[1] / dt};
+        fa = ph * pa;
+        fh = ph * zd{d[1] / dt, w * d[0]};
+    }
+    // [T'/dt + j w T] at tau = m on piece m (the MFIE's Gram factor D_m)
+    __host__ __device__ zd gram(int m) const {
+        if (m < 0 || m > kQ) return zd{0.0, 0.0};
+        double d[4];
+        cppif_piece(m, 0.0, d);
+        return zd{d[1] / dt, w * d[0]};
+    }
     // value and R-derivative at R = 0+ (piece m, tau -> m-)
     __host__ __device__ void origin(int m, zd& fa0, zd& fp0, zd& dfa0, zd& dfp0) const {
         if (m < 0 || m > kQ) {

@@ -35,7 +35,10 @@ struct Geometry {
 struct Setup {
     double dt = 0, h = 0, x0[3] = {0, 0, 0}, rmax = 0, rst = 0, d_near = 0;
     int ng = 0, mn = 0, N[3] = {0, 0, 0}, L[3] = {0, 0, 0};
+    bool cfie = false;              // combined-field equation (Sec. 2.1)
+    double alpha = 1.0;             // its weight of the EFIE
     std::vector<double> lam;        // [ns][4][64] projection weights
+    std::vector<double> lamH;       // CFIE: [ns][4][64] curl test projection (component 3 zero)
     std::vector<int> i0;            // [ns][3] stencil corners
     std::vector<int> order;         // [ns] bases sorted by the Morton code of their stencil corner
     std::vector<int> rowptr, col;   // near-zone CSR (row-major, sorted columns)

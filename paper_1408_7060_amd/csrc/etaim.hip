@@ -81,6 +81,14 @@ struct etaim_ctx {
     double* lam64 = nullptr;
     int *i0 = nullptr, *korder = nullptr, *rowptr = nullptr, *col = nullptr, *rowof = nullptr, *nptr = nullptr, *nk = nullptr;
     double *Sq = nullptr, *rq = nullptr;
+    // CFIE (Sec. 2.1): the MFIE's curl test projection, its Green spectra
+    // (G^H, zero), the excitation's weighted S x n; the MFIE far part runs as
+    // a second pass of the far pipeline with these in place of the EFIE's
+    // (PassSwap), on the same anterpolated currents and history ring
+    double *lamH64 = nullptr, *Snq = nullptr;
+    zd* ghatH64 = nullptr;
+    void *lamH_r = nullptr, *ghatH_r = nullptr, *ghatHT_r = nullptr, *farH = nullptr;
+    int farH_slots = 0, farH_r0 = -1, pass = 0;
     // working-precision arrays (float or double)
     void *lam_r = nullptr, *nw_r = nullptr, *near_r = nullptr, *nearT_r = nullptr, *ghat_r = nullptr, *tw_r[3] = {};
     void* ghatT_r = nullptr;  // ky/kz-exchanged copy for the z-lines-first plane kernel
@@ -206,6 +214,28 @@ struct etaim_ctx {
 };
 
 namespace {
+
+// The CFIE's MFIE pass: while one lives, the far pipeline (Green spectra,
+// interpolation weights, time-block sums) sees the MFIE's arrays in place of
+// the EFIE's; the anterpolation, the transforms and the history ring are
+// shared.  Both passes keep their block sums of the same block (far_r0).
+struct PassSwap {
+    etaim_ctx* c;
+    explicit PassSwap(etaim_ctx* cc) : c(cc) { swap(); }
+    ~PassSwap() { swap(); }
+    void swap() {
+        std::swap(c->ghat_r, c->ghatH_r);
+        std::swap(c->ghatT_r, c->ghatHT_r);
+        std::swap(c->lam_r, c->lamH_r);
+        std::swap(c->far, c->farH);
+        std::swap(c->far_slots, c->farH_slots);
+        std::swap(c->far_r0, c->farH_r0);
+        c->pass ^= 1;
+    }
+};
+
+// the block whose time-block sums both passes hold (-1: none)
+inline void set_far_r0(etaim_ctx* c, int r0) { c->far_r0 = c->farH_r0 = r0; }
 
 // Tracing: an event pair around each launch of a class (when enabled).  A
 // class of one kernel passes the pair to the launch itself (launch_timed):
@@ -620,7 +650,7 @@ struct Ops {
         if (mode == 0 && (c->x_engine != 1 || conj_x))
             hipLaunchKernelGGL(k_prescale<R>, dim3(blocks_for(nB)), dim3(256), 0, c->stream, x, dinv, xs, c->ns, c->B,
                                conj_x, gate);
-        if (c->interp_engine == 1 && c->ntiles > 0) {
+        if (c->interp_engine == 1 && c->ntiles > 0 && mode <= 1) {
             const int gc = interp_tile_gc<R>(c);
             const int nblk = c->ntiles * ((c->B + gc - 1) / gc);
             const dim3 tg((nblk + kXcds - 1) / kXcds * kXcds);
@@ -650,10 +680,19 @@ struct Ops {
     // (xs_ready: x is given as the scaled columns in c->xs, register x stage only)
     static int apply(etaim_ctx* c, int m, const zd* x, const zd* dinv, zd* y, int conj,
                      const int* gate = nullptr, bool xs_ready = false) {
+        if (c->st.cfie && conj) return fail(ETAIM_EUNSUPPORTED, "the CFIE's transposed operators are not built");
         CHK(forward_x(c, x, dinv, 0, gate, xs_ready));
         CHK(yz_green(c, m, conj, gate));
         CHK(inverse_x(c, gate));
-        return interp_near(c, 0, x, dinv, m, 0, 0, nullptr, y, conj, 0, gate);
+        CHK(interp_near(c, 0, x, dinv, m, 0, 0, nullptr, y, conj, 0, gate));
+        if (!c->st.cfie) return ETAIM_OK;
+        // the MFIE far part, added to y (the register x stage's scaled
+        // columns are in place after the first pass)
+        PassSwap ps(c);
+        CHK(forward_x(c, x, dinv, 0, gate, xs_ready || c->x_engine == 1));
+        CHK(yz_green(c, m, conj, gate));
+        CHK(inverse_x(c, gate));
+        return interp_near(c, 2, x, dinv, m, 0, 0, nullptr, y, conj, 0, gate);
     }
     // rhs = V - sum_{m>=1} conj?(Z_m) I_{cur-m} from the rings (cur >= 1).
     // Captured into a whole-step graph (sr.sd set) the step's values come from
@@ -679,6 +718,17 @@ struct Ops {
         return ETAIM_OK;
     }
     static int delayed(etaim_ctx* c, int cur, const zd* V, zd* rhs, int conj, StepRef sr = {}, int graph_far = 0) {
+        if (c->st.cfie && conj) return fail(ETAIM_EUNSUPPORTED, "the CFIE's adjoint march is not built");
+        CHK(delayed_pass(c, cur, V, rhs, conj, sr, graph_far, 1));
+        if (!c->st.cfie) return ETAIM_OK;
+        // the MFIE far part of the history sum, subtracted from rhs
+        PassSwap ps(c);
+        return delayed_pass(c, cur, V, rhs, conj, sr, graph_far, 3);
+    }
+    // one pass of the delayed field; the interpolation in `mode` (1: rhs =
+    // V - far - near history; 3: rhs -= far)
+    static int delayed_pass(etaim_ctx* c, int cur, const zd* V, zd* rhs, int conj, StepRef sr, int graph_far,
+                            int mode) {
         const GridDims& g = c->gd;
         const int nm = std::min(c->st.ng, cur);
         const int ng = c->st.ng;
@@ -796,7 +846,7 @@ struct Ops {
         HIPCHK(hipGetLastError());
         CHK(inverse_x(c, sr.live));
         const int nmh = std::min(c->st.mn, cur);
-        return interp_near(c, 1, nullptr, nullptr, 0, cur, nmh, V, rhs, conj, 0, sr.live, sr);
+        return interp_near(c, mode, nullptr, nullptr, 0, cur, nmh, V, rhs, conj, 0, sr.live, sr);
     }
     // push the converged I_cur into the spectrum ring and the current ring
     static int commit(etaim_ctx* c, int cur, const zd* x, StepRef sr = {}) {
@@ -1335,7 +1385,7 @@ int checker_reset(etaim_ctx* c, int from) {
     etaim_ctx* k = c->check;
     HIPCHK(hipMemsetAsync(k->ring, 0, (size_t)k->st.ng * 4 * k->Np * sizeof(zd), k->stream));
     if (k->st.mn >= 1) HIPCHK(hipMemsetAsync(k->hist, 0, (size_t)k->st.mn * k->ns * sizeof(zd), k->stream));
-    k->far_r0 = -1;
+    set_far_r0(k, -1);
     k->check_next = std::max(from, 0);
     return ETAIM_OK;
 }
@@ -1411,7 +1461,7 @@ int march_impl(etaim_ctx* c, const zd* V, zd* I, etaim_stats* st, bool adjoint, 
     const int conj = adjoint ? 1 : 0;
     if (first == 0) {
         HIPCHK(hipMemsetAsync(c->ring, 0, (size_t)c->st.ng * 4 * B * c->Np * sizeof(cplx<R>), c->stream));
-        c->far_r0 = -1;  // the block sums belong to the previous history
+        set_far_r0(c, -1);  // the block sums belong to the previous history
         c->iter_hint = 0;
         if (c->st.mn >= 1) HIPCHK(hipMemsetAsync(c->hist, 0, (size_t)c->st.mn * nB * sizeof(zd), c->stream));
     }
@@ -1632,7 +1682,7 @@ int march_impl(etaim_ctx* c, const zd* V, zd* I, etaim_stats* st, bool adjoint, 
         HIPCHK(hipEventRecord(c->evg[0], c->stream));
         for (int q = a; q <= b; ++q) {
             const int far = blocked && c->far_r0 != block_start(q) ? 1 : 0;
-            if (far) c->far_r0 = block_start(q);
+            if (far) set_far_r0(c, block_start(q));
             const int pred = std::min(q, c->guess_order) >= 2 ? 1 : 0;
             hipGraphExec_t gx = nullptr;
             CHK(step_graph_get<R>(c, J, far, pred, gx));
@@ -1686,7 +1736,7 @@ int march_impl(etaim_ctx* c, const zd* V, zd* I, etaim_stats* st, bool adjoint, 
         // Its time block's sums are in place (their pass ran at or before h).
         const int h = a + done;
         ++graph_halts;
-        if (blocked) c->far_r0 = block_start(h);
+        if (blocked) set_far_r0(c, block_start(h));
         // a residual check enqueued after the halt read solutions that were not
         // computed: it is not counted, and the FP64 history refills from h on
         if (c->check) c->check->check_next = std::min(c->check->check_next, h);
@@ -1767,6 +1817,24 @@ int march_impl(etaim_ctx* c, const zd* V, zd* I, etaim_stats* st, bool adjoint, 
 template <typename R>
 int make_working(etaim_ctx* c) {
     const size_t nB = (size_t)c->B;
+    if (c->st.cfie) {
+        // the MFIE pass's interpolation weights and Green spectra
+        const size_t nl = (size_t)c->ns * 256, ngh = (size_t)(c->st.ng + 1) * 2 * c->gfold;
+        if constexpr (sizeof(R) == sizeof(double)) {
+            c->lamH_r = c->lamH64;
+            c->ghatH_r = c->ghatH64;
+        } else {
+            float* lh = nullptr;
+            zf* gh = nullptr;
+            CHK(c->alloc(lh, nl));
+            hipLaunchKernelGGL(k_real_to_r<float>, dim3(blocks_for(nl)), dim3(256), 0, c->stream, c->lamH64, lh, nl);
+            CHK(c->alloc(gh, ngh));
+            hipLaunchKernelGGL(k_to_r<float>, dim3(blocks_for(ngh)), dim3(256), 0, c->stream, c->ghatH64, gh, ngh);
+            HIPCHK(hipGetLastError());
+            c->lamH_r = lh;
+            c->ghatH_r = gh;
+        }
+    }
     if constexpr (sizeof(R) == sizeof(double)) {
         c->lam_r = c->lam64;
         c->near_r = c->near64;
@@ -1811,6 +1879,14 @@ int make_working(etaim_ctx* c) {
                            (const cplx<R>*)c->ghat_r, gt, planes, (int)n1);
         HIPCHK(hipGetLastError());
         c->ghatT_r = gt;
+        if (c->st.cfie) {
+            cplx<R>* gth = nullptr;
+            CHK(c->alloc(gth, planes * n1 * n1));
+            hipLaunchKernelGGL(k_green_transpose<R>, dim3(blocks_for(planes * n1 * n1)), dim3(256), 0, c->stream,
+                               (const cplx<R>*)c->ghatH_r, gth, planes, (int)n1);
+            HIPCHK(hipGetLastError());
+            c->ghatHT_r = gth;
+        }
     }
     for (int a = 0; a < 3; ++a) {
         const int L = c->gd.L[a];
@@ -1852,6 +1928,7 @@ int device_setup(etaim_ctx* c) {
     const int ns = c->ns;
     // FP64 arrays
     CHK(c->upload(c->lam64, s.lam));
+    if (s.cfie) CHK(c->upload(c->lamH64, s.lamH));
     CHK(c->upload(c->i0, s.i0));
     CHK(c->upload(c->korder, s.order));
     CHK(c->upload(c->rowptr, s.rowptr));
@@ -1931,13 +2008,22 @@ int device_setup(etaim_ctx* c) {
     CHK(c->alloc(gtab, (size_t)(s.ng + 1) * 2 * c->N3));
     const double w = 2.0 * kPi * c->prm.fc;
     EnvKernel K{s.dt, w, w / kC0, kC0 * s.dt};
-    const double sa = kMu0 / (4.0 * kPi), sp = 1.0 / (4.0 * kPi * eps0());
+    // the CFIE weighs the EFIE's tables by alpha and adds the MFIE's, -(1 - alpha) eta G^H
+    const double sa = s.alpha * kMu0 / (4.0 * kPi), sp = s.alpha / (4.0 * kPi * eps0());
     hipLaunchKernelGGL(k_green_table, dim3(blocks_for((size_t)(s.ng + 1) * c->N3)), dim3(256), 0, c->stream, gtab,
                        c->gd, s.ng, s.h, K, sa, sp);
     HIPCHK(hipGetLastError());
+    zd* gtabH = nullptr;
+    if (s.cfie) {
+        CHK(c->alloc(gtabH, (size_t)(s.ng + 1) * 2 * c->N3));
+        const double sh = -(1.0 - s.alpha) * std::sqrt(kMu0 / eps0());
+        hipLaunchKernelGGL(k_green_table_h, dim3(blocks_for((size_t)(s.ng + 1) * c->N3)), dim3(256), 0, c->stream,
+                           gtabH, c->gd, s.ng, s.h, K, sh);
+        HIPCHK(hipGetLastError());
+    }
     if (c->nnz > 0)
         hipLaunchKernelGGL(k_precorrect, dim3(c->nnz), dim3(64), 0, c->stream, c->near64, c->lam64, c->i0, c->rowof,
-                           c->col, gtab, c->gd, c->mv, c->nnz);
+                           c->col, gtab, c->gd, c->mv, c->nnz, (const double*)c->lamH64, (const zd*)gtabH);
     HIPCHK(hipGetLastError());
     // Green spectra: circulant embedding, full FP64 3-D FFT, fold, / Np
     CHK(c->alloc(c->ghat64, (size_t)(s.ng + 1) * 2 * c->gfold));
@@ -1955,18 +2041,25 @@ int device_setup(etaim_ctx* c) {
         CHK(c->upload(twd[a], tw64[a]));
     }
     const long long Lx = c->gd.L[0], Ly = c->gd.L[1], Lz = c->gd.L[2];
+    if (s.cfie) {
+        // the MFIE pass's spectra: G^H in slot 0, zero in slot 1 (its charge component)
+        CHK(c->alloc(c->ghatH64, (size_t)(s.ng + 1) * 2 * c->gfold));
+        HIPCHK(hipMemsetAsync(c->ghatH64, 0, (size_t)(s.ng + 1) * 2 * c->gfold * sizeof(zd), c->stream));
+    }
     for (int m = 0; m <= s.ng; ++m)
-        for (int t = 0; t < 2; ++t) {
-            hipLaunchKernelGGL(k_circulant, dim3(blocks_for(c->Np)), dim3(256), 0, c->stream,
-                               gtab + ((size_t)m * 2 + t) * c->N3, full, c->gd);
+        for (int t = 0; t < (s.cfie ? 3 : 2); ++t) {
+            // t = 0, 1: the EFIE's A and phi tables; t = 2: the MFIE's G^H
+            const zd* src = t < 2 ? gtab + ((size_t)m * 2 + t) * c->N3 : gtabH + (size_t)m * 2 * c->N3;
+            zd* dst = t < 2 ? c->ghat64 + ((size_t)m * 2 + t) * c->gfold : c->ghatH64 + (size_t)m * 2 * c->gfold;
+            hipLaunchKernelGGL(k_circulant, dim3(blocks_for(c->Np)), dim3(256), 0, c->stream, src, full, c->gd);
             CHK(launch_lines<double>(c, full, full, twd[0], c->rx, (int)Ly, (int)Lz, (int)Lx, (int)Lx, Lx, Ly * Lx, 1,
                                      Lx, Ly * Lx, 1, false));
             CHK(launch_lines<double>(c, full, full, twd[1], c->ry, (int)Lx, (int)Lz, (int)Ly, (int)Ly, 1, Ly * Lx, Lx,
                                      1, Ly * Lx, Lx, false));
             CHK(launch_lines<double>(c, full, full, twd[2], c->rz, (int)Lx, (int)Ly, (int)Lz, (int)Lz, 1, Lx,
                                      Ly * Lx, 1, Lx, Ly * Lx, false));
-            hipLaunchKernelGGL(k_fold, dim3(blocks_for(c->gfold)), dim3(256), 0, c->stream, full,
-                               c->ghat64 + ((size_t)m * 2 + t) * c->gfold, c->gd, 1.0 / (double)c->Np);
+            hipLaunchKernelGGL(k_fold, dim3(blocks_for(c->gfold)), dim3(256), 0, c->stream, full, dst, c->gd,
+                               1.0 / (double)c->Np);
             HIPCHK(hipGetLastError());
         }
     HIPCHK(hipStreamSynchronize(c->stream));
@@ -2005,13 +2098,14 @@ int device_setup(etaim_ctx* c) {
         HIPCHK(hipFree(tp));
         c->dev_bytes -= (int64_t)(tperm.size() * sizeof(int));
     }
-    // release set-up temporaries (gtab, full, twd)
-    for (void* p : {(void*)twd[2], (void*)twd[1], (void*)twd[0], (void*)full, (void*)gtab}) {
+    // release set-up temporaries (gtab, gtabH, full, twd)
+    for (void* p : {(void*)twd[2], (void*)twd[1], (void*)twd[0], (void*)full, (void*)gtab, (void*)gtabH}) {
+        if (!p) continue;
         auto it = std::find(c->allocs.begin(), c->allocs.end(), p);
         if (it != c->allocs.end()) c->allocs.erase(it);
         HIPCHK(hipFree(p));
     }
-    c->dev_bytes -= (int64_t)(((size_t)(s.ng + 1) * 2 * c->N3 + c->Np) * sizeof(zd));
+    c->dev_bytes -= (int64_t)(((size_t)(s.ng + 1) * 2 * c->N3 * (s.cfie ? 2 : 1) + c->Np) * sizeof(zd));
     // excitation / far-field quadrature data: 14 points per basis (7 per half)
     {
         const double s15 = std::sqrt(15.0);
@@ -2021,7 +2115,7 @@ int device_setup(etaim_ctx* c) {
                                  {1 - 2 * a1, a1, a1},        {a2, a2, 1 - 2 * a2}, {a2, 1 - 2 * a2, a2},
                                  {1 - 2 * a2, a2, a2}};
         const double wq[7] = {9.0 / 40.0, w1, w1, w1, w2, w2, w2};
-        std::vector<double> Sq((size_t)ns * 14 * 3), rq((size_t)ns * 14 * 3);
+        std::vector<double> Sq((size_t)ns * 14 * 3), rq((size_t)ns * 14 * 3), Snq(s.cfie ? (size_t)ns * 14 * 3 : 0);
         const Geometry& G = c->geo;
         for (int k = 0; k < ns; ++k)
             for (int h = 0; h < 2; ++h) {
@@ -2038,9 +2132,18 @@ int device_setup(etaim_ctx* c) {
                         rq[o + x] = r;
                         Sq[o + x] = wq[q] * G.area[t] * coef * (r - G.xyz[3 * (size_t)f + x]);
                     }
+                    if (s.cfie) {
+                        // weighted S x n of this half's triangle
+                        const double* nn = &G.nrm[3 * (size_t)t];
+                        const double* S = &Sq[o];
+                        Snq[o] = S[1] * nn[2] - S[2] * nn[1];
+                        Snq[o + 1] = S[2] * nn[0] - S[0] * nn[2];
+                        Snq[o + 2] = S[0] * nn[1] - S[1] * nn[0];
+                    }
                 }
             }
         CHK(c->upload(c->Sq, Sq));
+        if (s.cfie) CHK(c->upload(c->Snq, Snq));
         CHK(c->upload(c->rq, rq));
     }
     CHK(c->prec == ETAIM_FP32 ? make_working<float>(c) : make_working<double>(c));
@@ -2212,7 +2315,8 @@ int etaim_excitation_planewave(etaim_ctx* c, int32_t nb, const double* khat, con
     CHK(c->upload(d, kp));
     const size_t tot = (size_t)c->prm.nt_steps * nb * c->ns;
     hipLaunchKernelGGL(k_excitation, dim3(blocks_for(tot)), dim3(256), 0, c->stream, (zd*)V, c->Sq, c->rq, d,
-                       d + 3 * nb, c->prm.nt_steps, nb, c->ns, c->st.dt, sigma, td, 2.0 * kPi * c->prm.fc);
+                       d + 3 * nb, c->prm.nt_steps, nb, c->ns, c->st.dt, sigma, td, 2.0 * kPi * c->prm.fc,
+                       (const double*)c->Snq, c->st.alpha);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->stream));
     c->allocs.pop_back();
@@ -2236,7 +2340,8 @@ int etaim_excitation_planewave_noalloc(etaim_ctx* c, int32_t nb, const double* k
                           c->stream));
     const size_t tot = (size_t)c->prm.nt_steps * nb * c->ns;
     hipLaunchKernelGGL(k_excitation, dim3(blocks_for(tot)), dim3(256), 0, c->stream, (zd*)V, c->Sq, c->rq, d,
-                       d + 3 * (size_t)nb, c->prm.nt_steps, nb, c->ns, c->st.dt, sigma, td, 2.0 * kPi * c->prm.fc);
+                       d + 3 * (size_t)nb, c->prm.nt_steps, nb, c->ns, c->st.dt, sigma, td, 2.0 * kPi * c->prm.fc,
+                       (const double*)c->Snq, c->st.alpha);
     HIPCHK(hipGetLastError());
     // the staging is free for the next call (and the caller's host arrays) once this returns
     HIPCHK(hipStreamSynchronize(c->stream));
@@ -2261,7 +2366,7 @@ int etaim_delayed_field(etaim_ctx* c, const void* hist, void* b) {
     auto run = [&](auto tag) -> int {
         using R = decltype(tag);
         HIPCHK(hipMemsetAsync(c->ring, 0, (size_t)ng * 4 * c->B * c->Np * sizeof(cplx<R>), c->stream));
-        c->far_r0 = -1;
+        set_far_r0(c, -1);
         c->next_step = -1;  // the rings now hold the injected history
         c->check_synced = -1;
         if (c->st.mn >= 1) HIPCHK(hipMemsetAsync(c->hist, 0, (size_t)c->st.mn * nB * sizeof(zd), c->stream));
@@ -2381,7 +2486,7 @@ int etaim_state_load(etaim_ctx* c, const void* host, size_t bytes) {
     c->next_step = h.next_step;
     c->guess_p_next = std::min(h.guess_p, c->guess_order);
     c->guess_dev_next = h.guess_dev != 0 && c->guess_order >= 2;
-    c->far_r0 = -1;  // block sums are recomputed from the loaded ring
+    set_far_r0(c, -1);  // block sums are recomputed from the loaded ring
     c->iter_hint = 0;
     c->check_synced = -1;  // the residual check's FP64 history is rebuilt from I_out
     return ETAIM_OK;
@@ -2390,6 +2495,7 @@ int etaim_state_load(etaim_ctx* c, const void* host, size_t bytes) {
 int etaim_adjoint_march(etaim_ctx* c, const void* S, void* Lambda, etaim_stats* st) {
     CHK(check_ctx(c));
     if (!S || !Lambda) return fail(ETAIM_EINVAL, "null S or Lambda");
+    if (c->st.cfie) return fail(ETAIM_EUNSUPPORTED, "the CFIE's adjoint march is not built");
     // Z^H = conj(Z): every operator is complex-symmetric, so the adjoint
     // march runs the same kernels with conjugated Green spectra, near-zone
     // values and preconditioner, backward in time
@@ -2445,6 +2551,9 @@ int etaim_export(const etaim_ctx* c, int32_t what, void* host, size_t bytes) {
                                 v[mt * c->gfold + ((size_t)x * gz + z) * gy + y];
             return ETAIM_OK;
         }
+        case 7:
+            if (!s.cfie) return fail(ETAIM_EINVAL, "export 7 (curl test projection) needs the CFIE");
+            return put(s.lamH.data(), s.lamH.size() * sizeof(double), false);
         default: return fail(ETAIM_EINVAL, "unknown export id");
     }
 }

@@ -241,6 +241,16 @@ int derive_parameters(const Geometry& g, const etaim_params* p, Setup& s, std::s
         err = "precision must be ETAIM_FP64 or ETAIM_FP32";
         return ETAIM_EINVAL;
     }
+    if (p->formulation != ETAIM_EFIE && p->formulation != ETAIM_CFIE) {
+        err = "formulation must be ETAIM_EFIE or ETAIM_CFIE";
+        return ETAIM_EINVAL;
+    }
+    if (p->formulation == ETAIM_CFIE && !(p->alpha >= 0.0 && p->alpha < 1.0)) {
+        err = "the CFIE's alpha must lie in [0, 1)";
+        return ETAIM_EINVAL;
+    }
+    s.cfie = p->formulation == ETAIM_CFIE;
+    s.alpha = s.cfie ? p->alpha : 1.0;
     // largest vertex-to-vertex distance
     double best = 0.0;
 #pragma omp parallel for reduction(max : best) schedule(dynamic, 64)
@@ -353,9 +363,13 @@ int build_projection(const Geometry& g, Setup& s, std::string& err) {
         }
     const int ns = g.ns;
     s.lam.assign((size_t)ns * 256, 0.0);
+    // CFIE: the curl test projection H[k][c][n] = int ((S_k x n) x grad l_n)_c
+    // (the tested n x curl of the interpolated potential), component 3 zero
+    if (s.cfie) s.lamH.assign((size_t)ns * 256, 0.0);
 #pragma omp parallel for schedule(static)
     for (int k = 0; k < ns; ++k) {
         double* Lk = &s.lam[(size_t)k * 256];
+        double* Hk = s.cfie ? &s.lamH[(size_t)k * 256] : nullptr;
         for (int h = 0; h < 2; ++h) {
             const int t = g.t[2 * k + h];
             const int* tv = &g.tri[3 * (size_t)t];
@@ -367,25 +381,49 @@ int build_projection(const Geometry& g, Setup& s, std::string& err) {
             for (int q = 0; q < 36; ++q) {
                 const V3 r = qb[q][0] * v0 + qb[q][1] * v1 + qb[q][2] * v2;
                 const double wa = qw[q] * g.area[t];
-                double l[3][4];
+                // cubic Lagrange values l and derivatives dl (in the local
+                // coordinate u) per axis
+                double l[3][4], dl[3][4];
                 const double rr[3] = {r.x, r.y, r.z};
                 for (int a = 0; a < 3; ++a) {
                     const double u = (rr[a] - s.x0[a]) / s.h - (double)s.i0[3 * k + a];
                     for (int j = 0; j < 4; ++j) {
-                        double v = 1.0;
+                        double v = 1.0, den = 1.0, d = 0.0;
                         for (int i = 0; i < 4; ++i)
-                            if (i != j) v *= (u - i) / (double)(j - i);
-                        l[a][j] = v;
+                            if (i != j) {
+                                v *= (u - i);
+                                den *= (double)(j - i);
+                            }
+                        for (int skip = 0; skip < 4; ++skip) {
+                            if (skip == j) continue;
+                            double pr = 1.0;
+                            for (int i = 0; i < 4; ++i)
+                                if (i != j && i != skip) pr *= (u - i);
+                            d += pr;
+                        }
+                        l[a][j] = v / den;
+                        dl[a][j] = d / den;
                     }
                 }
                 const V3 S = ca * (r - vf);
                 const double comp[4] = {S.x, S.y, S.z, cp};
+                const V3 nt = {g.nrm[3 * (size_t)t], g.nrm[3 * (size_t)t + 1], g.nrm[3 * (size_t)t + 2]};
+                const V3 Sn = cross(S, nt);
                 for (int jz = 0; jz < 4; ++jz)
                     for (int jy = 0; jy < 4; ++jy)
                         for (int jx = 0; jx < 4; ++jx) {
                             const double b = wa * l[0][jx] * l[1][jy] * l[2][jz];
                             const int n = jx + 4 * (jy + 4 * jz);
                             for (int c = 0; c < 4; ++c) Lk[64 * c + n] += comp[c] * b;
+                            if (Hk) {
+                                const V3 gr = {dl[0][jx] * l[1][jy] * l[2][jz] / s.h,
+                                               l[0][jx] * dl[1][jy] * l[2][jz] / s.h,
+                                               l[0][jx] * l[1][jy] * dl[2][jz] / s.h};
+                                const V3 v = cross(Sn, gr);
+                                Hk[n] += wa * v.x;
+                                Hk[64 + n] += wa * v.y;
+                                Hk[128 + n] += wa * v.z;
+                            }
                         }
             }
         }
@@ -520,11 +558,15 @@ void exact_near_entries(const Geometry& g, const etaim_params* p, Setup& s) {
     std::vector<zd> fa0(M), fp0(M), dfa0(M), dfp0(M);
     for (int m = 0; m < M; ++m) K.origin(m, fa0[m], fp0[m], dfa0[m], dfp0[m]);
     const double sa = kMu0 / (4.0 * kPi), sp = 1.0 / (4.0 * kPi * eps0());
+    // CFIE: alpha EFIE + (1 - alpha) eta MFIE (Sec. 2.1); MFIE Gram factors D_m
+    const double al = s.alpha, bh = (1.0 - s.alpha) * std::sqrt(kMu0 / eps0());
+    std::vector<zd> gm(M);
+    for (int m = 0; m < M; ++m) gm[m] = K.gram(m);
     const size_t nnz = s.col.size();
     s.near_exact.assign(nnz * M, zd{0, 0});
 #pragma omp parallel
     {
-        std::vector<zd> IA(M), IF(M);
+        std::vector<zd> IA(M), IF(M), IH(M);
 #pragma omp for schedule(dynamic, 16)
         for (int k = 0; k < g.ns; ++k) {
             for (int e = s.rowptr[k]; e < s.rowptr[k + 1]; ++e) {
@@ -595,7 +637,38 @@ void exact_near_entries(const Geometry& g, const etaim_params* p, Setup& s) {
                         const double sg = (h == 0 ? 1.0 : -1.0) * (hh == 0 ? 1.0 : -1.0);
                         const double cA = sg * g.len[k] * g.len[kk] / (4.0 * Aa * Ab);
                         const double cP = sg * g.len[k] * g.len[kk] / (Aa * Ab);
-                        for (int m = 0; m < M; ++m) out[m] += (sa * cA) * IA[m] + (sp * cP) * IF[m];
+                        for (int m = 0; m < M; ++m) out[m] += al * ((sa * cA) * IA[m] + (sp * cP) * IF[m]);
+                        if (!s.cfie) continue;
+                        if (ta == tb) {
+                            // Gram term D_m / 2 <S_k, S_k'> on the shared triangle (exact, degree 2)
+                            double gs = 0.0;
+                            for (int q = 0; q < 7; ++q) gs += rule.w[q] * Aa * dot(ra[q] - fa, ra[q] - fb);
+                            for (int m = 0; m < M; ++m) out[m] += (bh * 0.5 * cA * gs) * gm[m];
+                            continue;  // n x (Rhat x S') = 0 on a flat triangle with itself
+                        }
+                        // - int int g'_m(R) S_k . (n_a x (Rhat x S_k')),
+                        // g'_m = -(1/4 pi) [fA/(c R) + fH/R^2]
+                        const V3 na = {g.nrm[3 * (size_t)ta], g.nrm[3 * (size_t)ta + 1], g.nrm[3 * (size_t)ta + 2]};
+                        for (int m = 0; m < M; ++m) IH[m] = zd{0, 0};
+                        for (int pq = 0; pq < 7; ++pq) {
+                            const V3 da = ra[pq] - fa;
+                            for (int qq = 0; qq < 7; ++qq) {
+                                const V3 dv = ra[pq] - rb[qq];
+                                const double R = std::sqrt(dv.x * dv.x + dv.y * dv.y + dv.z * dv.z);
+                                if (!(R > 0.0)) continue;
+                                const V3 rh = (1.0 / R) * dv;
+                                const V3 db = rb[qq] - fb;
+                                const double term = dot(da, rh) * dot(na, db) - dot(da, db) * dot(na, rh);
+                                const double W = rule.w[pq] * rule.w[qq] * (Aa * Ab);
+                                for (int m = 0; m < M; ++m) {
+                                    zd fA, fH;
+                                    K.evalh(m, R, fA, fH);
+                                    const zd gp = (-1.0 / (4.0 * kPi)) * ((1.0 / (kC0 * R)) * fA + (1.0 / (R * R)) * fH);
+                                    IH[m] += (W * term) * gp;
+                                }
+                            }
+                        }
+                        for (int m = 0; m < M; ++m) out[m] += (-bh * cA) * IH[m];
                     }
             }
         }

@@ -111,14 +111,14 @@ void put_shape(etaim_ctx* c, const Shape& s) {
     auto quad = [](int e) { return e == 1 || e == 2; };
     if (quad(c->yz_engine) != quad(s.engine)) {
         c->next_step = -1;
-        c->far_r0 = -1;
+        set_far_r0(c, -1);
     }
     c->yz_engine = s.engine;
     c->x_engine = s.xeng;
     c->guess_order = s.guess;
     c->precond = s.precond;
     c->interp_engine = s.ieng;
-    if (c->delay_block != s.dblock) c->far_r0 = -1;
+    if (c->delay_block != s.dblock) set_far_r0(c, -1);
     c->delay_block = s.dblock;
     drop_graphs(c);  // captured steps hold the old launch shapes
 }
@@ -197,9 +197,9 @@ int shape_from_c(const etaim_ctx* c, const etaim_tuning* t, Shape& s) {
 
 std::string tune_key(const etaim_ctx* c) {
     char k[256];
-    std::snprintf(k, sizeof k, "etaim-gfx950 prec=%d B=%d ns=%d nnz=%d grid=%dx%dx%d ng=%d mn=%d restart=%d",
+    std::snprintf(k, sizeof k, "etaim-gfx950 prec=%d B=%d ns=%d nnz=%d grid=%dx%dx%d ng=%d mn=%d restart=%d%s",
                   c->prec, c->B, c->ns, c->nnz, c->gd.N[0], c->gd.N[1], c->gd.N[2], c->st.ng, c->st.mn,
-                  c->prm.restart);
+                  c->prm.restart, c->st.cfie ? " cfie" : "");
     return k;
 }
 
@@ -336,7 +336,7 @@ int time_solve(etaim_ctx* c, TuneBufs& b, double& ms, int& iters) {
 template <typename R>
 int time_delayed(etaim_ctx* c, TuneBufs& b, double& ms) {
     const int ng = c->st.ng, k = 24;
-    c->far_r0 = -1;
+    set_far_r0(c, -1);
     CHK(Ops<R>::delayed(c, ng + 1, c->zero, b.y, 0));
     HIPCHK(hipEventRecord(b.e0, c->stream));
     for (int i = 0; i < k; ++i) CHK(Ops<R>::delayed(c, ng + 2 + i, c->zero, b.y, 0));
@@ -345,7 +345,7 @@ int time_delayed(etaim_ctx* c, TuneBufs& b, double& ms) {
     float t = 0;
     HIPCHK(hipEventElapsedTime(&t, b.e0, b.e1));
     ms = t / k;
-    c->far_r0 = -1;
+    set_far_r0(c, -1);
     return ETAIM_OK;
 }
 

@@ -16,9 +16,17 @@ import workloads as W
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-@pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
-def test_host_setup_under_asan_and_ubsan(tmp_path):
-    exe = tmp_path / "setup_san"
+_ENV = dict(os.environ, OMP_NUM_THREADS="4", ASAN_OPTIONS="detect_leaks=1:abort_on_error=1",
+            UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
+
+
+@pytest.fixture(scope="module")
+def driver(tmp_path_factory):
+    """The sanitized driver and the level-2 sphere's input file."""
+    if shutil.which("g++") is None:
+        pytest.skip("needs g++")
+    tmp = tmp_path_factory.mktemp("setup")
+    exe = tmp / "setup_san"
     cmd = ["g++", "-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer", "-fopenmp",
            "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-D__HIP_PLATFORM_AMD__",
            "-I/opt/rocm/include", "-I" + os.path.join(ROOT, "include"),
@@ -28,7 +36,7 @@ def test_host_setup_under_asan_and_ubsan(tmp_path):
     wl = W.SPHERE_L2
     xyz, tri, rwg = wl.mesh()
     d_near = wl.near_lambda * 299_792_458.0 / wl.f0
-    mesh = tmp_path / "mesh.bin"
+    mesh = tmp / "mesh.bin"
     with open(mesh, "wb") as f:
         np.array([len(xyz), len(tri), len(rwg)], dtype="<i4").tofile(f)
         np.ascontiguousarray(xyz, dtype="<f8").tofile(f)
@@ -36,10 +44,15 @@ def test_host_setup_under_asan_and_ubsan(tmp_path):
         np.ascontiguousarray(rwg, dtype="<i4").tofile(f)
         np.array([wl.f0, wl.beta, wl.f_bw, d_near], dtype="<f8").tofile(f)
         np.array([wl.grid], dtype="<i4").tofile(f)
-    env = dict(os.environ, OMP_NUM_THREADS="4",
-               ASAN_OPTIONS="detect_leaks=1:abort_on_error=1",
-               UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
-    r = subprocess.run([str(exe), str(mesh)], capture_output=True, text=True, env=env, timeout=600)
+    return exe, mesh, tmp
+
+
+def test_host_setup_under_asan_and_ubsan(driver):
+    exe, mesh, tmp = driver
+    wl = W.SPHERE_L2
+    xyz, tri, rwg = wl.mesh()
+    d_near = wl.near_lambda * 299_792_458.0 / wl.f0
+    r = subprocess.run([str(exe), str(mesh)], capture_output=True, text=True, env=_ENV, timeout=600)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "ERROR: AddressSanitizer" not in r.stderr and "runtime error" not in r.stderr, r.stderr
     f = r.stdout.split()
@@ -51,3 +64,33 @@ def test_host_setup_under_asan_and_ubsan(tmp_path):
     assert int(vals["ns"]) == s.ns and int(vals["nnz"]) == len(A.rows)
     assert int(vals["mn"]) == A.mn and int(vals["ng"]) == A.ng
     assert int(vals["rejected"]) == 4
+
+
+def test_host_cfie_setup_matches_the_oracle(driver):
+    """The CFIE's host set-up (alpha = 0.5), sanitized: the exact near-zone
+    entries alpha Z^E + (1 - alpha) eta Z^H of every near pair and the
+    MFIE's curl test projection equal the oracle's (rounding only)."""
+    exe, mesh, tmp = driver
+    out = tmp / "cfie.bin"
+    r = subprocess.run([str(exe), str(mesh), "0.5", str(out)], capture_output=True, text=True, env=_ENV,
+                       timeout=600)
+    assert r.returncode == 0, r.stdout + r.stderr
+    from oracle import aim, geometry, mfie, physics as ph
+    wl = W.SPHERE_L2
+    xyz, tri, rwg = wl.mesh()
+    s = geometry.Surface(xyz, tri, rwg)
+    d_near = wl.near_lambda * 299_792_458.0 / wl.f0
+    dt = ph.dt_from_beta(wl.beta, wl.f_bw)
+    A = aim.AIM(s, wl.grid, d_near, dt, wl.f0, ph.ng_from(ph.rmax_of(xyz), dt), alpha=0.5)
+    with open(out, "rb") as f:
+        nnz, mn = np.fromfile(f, "<i4", 2)
+        rowptr = np.fromfile(f, "<i4", s.ns + 1)
+        col = np.fromfile(f, "<i4", nnz)
+        near = np.fromfile(f, "<c16", nnz * (mn + 1)).reshape(nnz, mn + 1)
+        lamH = np.fromfile(f, "<f8", s.ns * 256).reshape(s.ns, 4, 64)
+    rows = np.repeat(np.arange(s.ns), np.diff(rowptr))
+    assert mn == A.mn and np.array_equal(rows, A.rows) and np.array_equal(col, A.cols)
+    assert np.abs(lamH[:, 3]).max() == 0.0
+    assert np.abs(lamH[:, :3] - A.H).max() <= 1e-13 * np.abs(A.H).max()
+    ref = mfie.cfie_pairs(s, A.rows, A.cols, list(range(mn + 1)), dt, wl.f0, 0.5)
+    assert np.abs(near.T - ref).max() <= 1e-12 * np.abs(ref).max()
