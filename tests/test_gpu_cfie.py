@@ -208,3 +208,37 @@ def test_cfie_adjoint_is_refused(torch):
     with pytest.raises(EtaimError):
         P.adjoint_march(S)
     P.close()
+
+
+def test_cfie_stability_of_the_level4_sphere_depends_on_the_time_step(torch):
+    """The bench's level-4 sphere (7680 RWG, +-10 %), one direction, FP32.
+    At the paper's oversampling beta = 1/5 the CFIE march decays after the
+    pulse while the EFIE march's growing mode is flagged.  At the bench's
+    N_g = 24 (beta = f_bw dt ~ 1/54, c dt = 9.3 cm, about one mesh edge)
+    both grow: the CFIE's damping is lost at small time steps (the oracle's
+    companion matrices of the level-2 sphere show the same, spectral radius
+    0.87 at beta = 1/5 and 1.06-1.18 at 1/10-1/40)."""
+    from paper_1408_7060_amd import Problem
+    wl = W.SPHERE_L4_BATCH
+    p = params_of(wl)
+    kh, pp = wl.incidence()
+    res = {}
+    for beta, nt in ((0.2, 200), (None, wl.nt)):
+        for alpha in (1.0, A5):
+            kw = dict(fc=wl.f0, nt=nt, grid=wl.grid, d_near=p["d_near"], precision=1, batch=1, tol=1e-5,
+                      restart=50, maxit=2000, alpha=alpha)
+            if beta:
+                kw.update(beta=beta, f_bw=wl.f_bw)
+            else:
+                kw["ng"] = wl.ng
+            P = Problem(p["xyz"], p["tri"], p["rwg"], **kw)
+            V = P.excitation(kh[:1], pp[:1], wl.sigma, wl.td)
+            I, st = P.march(V)
+            nrm = np.linalg.norm(I[:, 0].cpu().numpy(), axis=1)
+            res[beta, alpha] = (st["unstable_step"], nrm[-1] / nrm.max())
+            _say("level-4", "beta", beta, "ng", P.info["ng"], "alpha", alpha, "unstable step", st["unstable_step"],
+                 "last/peak", nrm[-1] / nrm.max())
+            P.close()
+    assert res[0.2, A5][0] == -1 and res[0.2, A5][1] < 1e-3
+    assert res[0.2, 1.0][0] >= 0
+    assert res[None, 1.0][0] >= 0 and res[None, A5][0] >= 0
