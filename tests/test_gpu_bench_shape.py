@@ -28,7 +28,7 @@ import pytest
 
 import workloads as W
 from gpu_cases import gpu_problem, params_of, rel
-from oracle import aim, geometry, kernels, zfill
+from oracle import aim, geometry, kernels, mfie, zfill
 
 pytestmark = pytest.mark.gpu
 
@@ -56,18 +56,21 @@ def _dev(torch, a):
 
 
 @functools.lru_cache(maxsize=None)
-def _oracle():
-    """(surface, AIM, params, sampled rows, near selection, near values)."""
+def _oracle(alpha=1.0):
+    """(surface, AIM, params, sampled rows, near selection, near values);
+    alpha < 1: the CFIE."""
     p = params_of(WL)
     s = geometry.Surface(p["xyz"], p["tri"], p["rwg"])
-    A = aim.AIM(s, WL.grid, p["d_near"], p["dt"], WL.f0, p["ng"])
+    A = aim.AIM(s, WL.grid, p["d_near"], p["dt"], WL.f0, p["ng"], alpha=alpha)
     rows = np.sort(W.rng(0, 6).choice(s.ns, NROWS, replace=False))
 
     def exact(r, c, ms):
+        if alpha != 1.0:
+            return mfie.cfie_pairs(s, r, c, ms, p["dt"], WL.f0, alpha)
         return zfill.assemble_pairs(s, r, c, [kernels.EnvelopeKernel(m, p["dt"], WL.f0) for m in ms])
 
     sel, vals = A.near_values_rows(exact, rows)
-    _say(f"oracle: level-4 rows {NROWS}, near pairs of those rows {int(sel.sum())}, M_n {A.mn}")
+    _say(f"oracle: level-4 rows {NROWS}, near pairs of those rows {int(sel.sum())}, M_n {A.mn}, alpha {alpha}")
     return s, A, p, rows, sel, vals
 
 
@@ -87,10 +90,10 @@ def _zx_rows(A, sel, vals, terms, rows):
 
 
 @functools.lru_cache(maxsize=None)
-def _operator_ref():
-    s, A, p, rows, sel, vals = _oracle()
+def _operator_ref(alpha=1.0):
+    s, A, p, rows, sel, vals = _oracle(alpha)
     x = W.complex_normal(43, (WL.batch, s.ns))
-    ms = list(range(A.mn + 1)) + [A.mn + 1, p["ng"]]
+    ms = list(range(A.mn + 1)) + [A.mn + 1, p["ng"]] if alpha == 1.0 else [0, 1, A.mn, p["ng"]]
     ref = {m: np.array([_zx_rows(A, sel, vals, [(m, x[c])], rows) for c in COLS]) for m in ms}
     return x, ref
 
@@ -113,8 +116,8 @@ def test_operator_at_bench_shape(torch, prec, tol, ieng):
 
 
 @functools.lru_cache(maxsize=None)
-def _delayed_ref():
-    s, A, p, rows, sel, vals = _oracle()
+def _delayed_ref(alpha=1.0):
+    s, A, p, rows, sel, vals = _oracle(alpha)
     ng = p["ng"]
     hist = W.complex_normal(44, (ng, WL.batch, s.ns))
     ref = np.array([_zx_rows(A, sel, vals, [(m, hist[m - 1, c]) for m in range(1, ng + 1)], rows) for c in COLS])
@@ -133,6 +136,29 @@ def test_delayed_field_at_bench_shape(torch, prec, tol, ieng):
     b = P.delayed_field(_dev(torch, hist)).cpu().numpy()[list(COLS)][:, rows]
     e = rel(b, ref)
     _say("bench shape delayed field", "fp32" if prec else "fp64", "rel", e)
+    assert e <= tol
+    P.close()
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-5)], ids=["fp64", "fp32"])
+def test_cfie_operator_and_delayed_field_at_bench_shape(torch, prec, tol):
+    """The CFIE (alpha = 0.5) at the same shape and setting: Z_m for m = 0, 1,
+    M_n and N_g, and the delayed field of a full history, on the sampled rows
+    (the MFIE's curl projection, near entries and second far pass live)."""
+    s, A, p, rows, sel, vals = _oracle(0.5)
+    x, ref = _operator_ref(0.5)
+    hist, dref = _delayed_ref(0.5)
+    P = gpu_problem(WL.name, precision=prec, nt=8, alpha=0.5)
+    _bench_setting(P)
+    xd = _dev(torch, x)
+    for m, r in ref.items():
+        y = P.apply_z(m, xd).cpu().numpy()[list(COLS)][:, rows]
+        e = rel(y, r)
+        _say("bench shape CFIE Z_m", "fp32" if prec else "fp64", "m", m, "rel", e)
+        assert e <= tol, (m, e)
+    b = P.delayed_field(_dev(torch, hist)).cpu().numpy()[list(COLS)][:, rows]
+    e = rel(b, dref)
+    _say("bench shape CFIE delayed field", "fp32" if prec else "fp64", "rel", e)
     assert e <= tol
     P.close()
 
