@@ -202,7 +202,7 @@ def roofline_record(dom, d, info, batch, traffic):
             "bytes_per_launch": bytes_launch, "avg_launch_ms": avg_ms, "launches": d["launches"]}
 
 
-def sweep(torch, W, FP64):
+def sweep(torch, W, FP64, alpha=1.0):
     """The ET-AIM size and bandwidth sweep of spheres (the trends of the
     paper's Figs. 2-3 without the comparison methods): every size at
     chi = 3 and 100, every chi at the smallest and the level-4 size; per
@@ -216,7 +216,7 @@ def sweep(torch, W, FP64):
     for (L, a, g, chi) in pts:
         wl = W.sweep_workload(L, a, g, chi)
         t = time.perf_counter()
-        P = make_problem(wl, FP64, 1, wl.nt, 1e-6, flags=F_CONTINUE_ON_NOCONV)
+        P = make_problem(wl, FP64, 1, wl.nt, 1e-6, flags=F_CONTINUE_ON_NOCONV, alpha=alpha)
         setup_s = time.perf_counter() - t
         kh, pp = wl.incidence()
         V = P.excitation(kh, pp, wl.sigma, wl.td)
@@ -226,7 +226,8 @@ def sweep(torch, W, FP64):
         torch.cuda.synchronize()
         wall = time.perf_counter() - t
         nt = st["steps_done"]
-        rec = {"point": wl.name, "ns": P.ns, "chi": chi, "f_c_MHz": round(wl.f0 / 1e6, 1),
+        rec = {"point": wl.name, "formulation": "EFIE" if alpha == 1.0 else f"CFIE alpha={alpha}",
+               "ns": P.ns, "chi": chi, "f_c_MHz": round(wl.f0 / 1e6, 1),
                "f_bw_MHz": round(wl.f_bw / 1e6, 2), "grid": g, "ng": P.info["ng"], "mn": P.info["mn"],
                "nnz": P.info["nnz"], "nt": nt, "gmres_iters_per_step": round(st["total_iters"] / max(nt, 1), 2),
                "ms_rhs_per_step": round(st["ms_rhs"] / max(nt, 1), 3),
@@ -282,7 +283,7 @@ def main():
     import workloads as W
     from paper_1408_7060_amd import FP32, FP64
     if args.sweep:
-        return sweep(torch, W, FP64)
+        return sweep(torch, W, FP64, args.alpha)
     from paper_1408_7060_amd._lib import F_CONTINUE_ON_NOCONV, F_GRAPH, F_IMPLICIT_STOP, F_RESIDUAL_CHECK
     # the FP64 residual check of eq. (5) every 16 steps is part of the precision form
     fl = F_CONTINUE_ON_NOCONV | F_RESIDUAL_CHECK | (0 if args.true_residual else F_IMPLICIT_STOP)
