@@ -272,6 +272,8 @@ def main():
                          "line per point")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="first copy this many MiB device-to-device (counter calibration)")
+    ap.add_argument("--no-cfie", action="store_true",
+                    help="skip the CFIE (alpha = 0.5) march of the same window that the EFIE bench adds")
     ap.add_argument("--alpha", type=float, default=1.0,
                     help="1: the EFIE the workloads state; below 1: the CFIE with this alpha (the paper's spheres: "
                          "0.5); the CPU baseline runs for the EFIE only")
@@ -496,6 +498,31 @@ def main():
         log(f"[bench] precision error (tol 1e-7 vs 1e-12, steps {first}..{nt - 1}): "
             f"{out['fp32_precision_error_dir0']['rel_l2']:.2e}")
         del V64
+    if alpha == 1.0 and not large and not args.no_cfie:
+        # the paper's sphere formulation (Sec. 2.1, Sec. 5.1: CFIE, alpha = 0.5)
+        # on the same workload, setting and window
+        Pc = make_problem(wl, FP32, wl.batch, nt, 1e-5, flags=fl, sync_every=args.sync_every, alpha=0.5)
+        if tuning:
+            Pc.set_tuning(tuning)
+        Vc = Pc.excitation(kh, pp, wl.sigma, wl.td)
+        Ic = Pc.empty(nt, wl.batch, Pc.ns)
+        _, stc0 = Pc.march(Vc, out=Ic, nsteps=first)
+        torch.cuda.synchronize()
+        c0 = time.perf_counter()
+        _, stc = Pc.march_continue(Vc, Ic, first, K)
+        torch.cuda.synchronize()
+        wc = time.perf_counter() - c0
+        nc = np.linalg.norm(Ic[:, 0].cpu().numpy(), axis=1)
+        uc = [x["unstable_step"] for x in (stc0, stc) if x["unstable_step"] >= 0]
+        out["cfie"] = {"alpha": 0.5, "time_steps_per_s": round(K / wc, 4), "ms_per_step": round(1e3 * wc / K, 3),
+                       "gmres_iters_per_step": round(stc["total_iters"] / K, 2),
+                       "unstable_step": min(uc) if uc else None,
+                       "current_growth_per_step_dir0": round((nc[nt - 1] / nc[first]) ** (1.0 / max(K - 1, 1)), 4)
+                       if nc[first] > 0 else None,
+                       "fp64_residual_check_max": stc["max_residual64"]}
+        log(f"[bench] CFIE alpha 0.5: {K / wc:.2f} steps/s, {stc['total_iters'] / K:.2f} GMRES it/step")
+        Pc.close()
+        del Ic, Vc
     if large:
         out["cpu_baseline"] = None
         out["cpu_baseline_note"] = ("not run at this size: the oracle's set-up alone (13.7 M exact near-zone "
