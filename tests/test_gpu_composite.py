@@ -76,15 +76,19 @@ def _dev(torch, a):
 
 
 @functools.lru_cache(maxsize=None)
-def _oracle(name, nrows):
-    """(surface, AIM, params, sampled rows, near selection, near values)."""
+def _oracle(name, nrows, alpha=1.0):
+    """(surface, AIM, params, sampled rows, near selection, near values);
+    alpha < 1: the CFIE."""
     wl = W.WORKLOADS[name]
     p = params_of(wl)
     s = geometry.Surface(p["xyz"], p["tri"], p["rwg"])
-    A = aim.AIM(s, wl.grid, p["d_near"], p["dt"], wl.f0, p["ng"])
+    A = aim.AIM(s, wl.grid, p["d_near"], p["dt"], wl.f0, p["ng"], alpha=alpha)
     rows = np.sort(W.rng(1, 6).choice(s.ns, nrows, replace=False))
 
     def exact(r, c, ms):
+        if alpha != 1.0:
+            from oracle import mfie
+            return mfie.cfie_pairs(s, r, c, ms, p["dt"], wl.f0, alpha)
         return zfill.assemble_pairs(s, r, c, [kernels.EnvelopeKernel(m, p["dt"], wl.f0) for m in ms])
 
     sel, vals = A.near_values_rows(exact, rows)
@@ -188,6 +192,36 @@ def test_composite_delayed_field(torch, prec, tol, yz):
     _say("composite delayed field", "fp32" if prec else "fp64", "engine", P.tuning()["yz_engine"], "rel", e,
          "rho", fac[0], "gamma", fac[1], "bound", bound)
     assert e <= bound
+    P.close()
+
+
+@pytest.mark.parametrize("yz", ENGINES, ids=ENGINE_IDS)
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-5)], ids=["fp64", "fp32"])
+def test_composite_cfie(torch, prec, tol, yz):
+    """The CFIE (alpha = 0.5) on the composite object: flat faces (coplanar
+    neighbours, whose MFIE entries vanish), edges and corners, outward
+    normals from the mesher.  Z_m for m = 0, 1 and M_n, and the delayed
+    field of an N_g-step history (FP64; FP32 where the sparse far terms'
+    conditioning allows: m <= M_n), on the sampled rows."""
+    s, A, p, rows, sel, vals = _oracle(WL.name, NROWS, 0.5)
+    x = W.complex_normal(63, (B, s.ns))
+    P = gpu_problem(WL.name, precision=prec, nt=8, batch=B, alpha=0.5)
+    _engine(P, yz)
+    xd = _dev(torch, x)
+    for m in (0, 1, A.mn):
+        r = np.array([_zx_rows(A, sel, vals, [(m, x[c])], rows) for c in range(B)])
+        y = P.apply_z(m, xd).cpu().numpy()[:, rows]
+        e = rel(y, r)
+        _say("composite CFIE Z_m", "fp32" if prec else "fp64", "engine", P.tuning()["yz_engine"], "m", m, "rel", e)
+        assert e <= tol, (m, e)
+    if not prec:
+        hist = W.complex_normal(64, (p["ng"], B, s.ns))
+        ref = np.array([_zx_rows(A, sel, vals, [(m, hist[m - 1, c]) for m in range(1, p["ng"] + 1)], rows)
+                        for c in range(2)])
+        b = P.delayed_field(_dev(torch, hist)).cpu().numpy()[:2, rows]
+        e = rel(b, ref)
+        _say("composite CFIE delayed field", "engine", P.tuning()["yz_engine"], "rel", e)
+        assert e <= tol
     P.close()
 
 
