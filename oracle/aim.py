@@ -137,7 +137,7 @@ def projection(surf: Surface, grid: Grid):
     return L, i0
 
 
-def green_tables(grid: Grid, ms, dt: float, fc: float):
+def green_tables(grid: Grid, ms, dt: float, fc: float, basis=None):
     """G^A_m, G^phi_m on |offset| tables [len(ms), Nz, Ny, Nx] (index = |d|)."""
     nx, ny, nz = grid.n
     k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
@@ -146,7 +146,7 @@ def green_tables(grid: Grid, ms, dt: float, fc: float):
     GA = np.zeros((len(ms),) + R.shape, dtype=np.complex128)
     GP = np.zeros_like(GA)
     for a, m in enumerate(ms):
-        kn = EnvelopeKernel(m, dt, fc)
+        kn = EnvelopeKernel(m, dt, fc, basis)
         fa, fp = kn.f(R)
         GA[a] = np.where(R == 0, 0.0, kn.scale_a * fa / Rs)
         GP[a] = np.where(R == 0, 0.0, kn.scale_phi * fp / Rs)
@@ -196,13 +196,18 @@ class AIM:
     """All L-B pieces for one problem (alpha = 1: EFIE; alpha < 1: CFIE)."""
 
     def __init__(self, surf: Surface, grid_n, d_near: float, dt: float, fc: float, ng: int,
-                 alpha: float = 1.0):
+                 alpha: float = 1.0, basis=None, fold_a=None):
+        """basis: None (CPPIF) or an ``oracle.blif.Blif``; with a BLIF, fold_a
+        [M-1, N_samp] folds the non-causal m = -(M-1)..-1 into m < N_samp
+        (``oracle.blif``)."""
         self.surf, self.dt, self.fc, self.ng, self.d_near = surf, dt, fc, ng, d_near
         self.alpha = float(alpha)
+        self.basis, self.fold_a = basis, fold_a
+        self.mlo = 0 if basis is None else -(basis.M - 1)
         self.grid = Grid(surf.xyz, grid_n)
         self.L, self.i0 = projection(surf, self.grid)
         self.nodes = stencil_nodes(self.grid, self.i0)
-        self.GA, self.GP = green_tables(self.grid, range(ng + 1), dt, fc)
+        self.GA, self.GP = (self._folded(t) for t in green_tables(self.grid, range(self.mlo, ng + 1), dt, fc, basis))
         self.tables = {"A": self.GA, "P": self.GP}
         a = self.alpha
         # channels: (test projection [ns,64], source component, table, coefficient)
@@ -210,13 +215,29 @@ class AIM:
         if a != 1.0:
             from . import mfie
             self.H = mfie.projection_curl(surf, self.grid, self.i0)
-            self.GH = mfie.green_table_h(self.grid, range(ng + 1), dt, fc)
+            self.GH = self._folded(mfie.green_table_h(self.grid, range(self.mlo, ng + 1), dt, fc, basis))
             self.tables["H"] = self.GH
             b = -(1.0 - a) * ETA0
             self.channels += [(self.H[:, c, :], c, "H", b) for c in range(3)]
         self.rows, self.cols = near_pairs(surf, d_near)
         self.r_max = stencil_radius(surf, self.grid, self.i0)
-        self.mn = near_depth(d_near, self.r_max, dt, ng)
+        self.mn = near_depth(d_near, self.r_max, dt, ng, cppif.Q if basis is None else basis.M)
+
+    def _folded(self, tab):
+        """Tables for m = mlo..ng -> m = 0..ng, the non-causal ones folded."""
+        if self.mlo == 0:
+            return tab
+        from . import blif
+        return blif.fold({m: tab[m - self.mlo] for m in range(self.mlo, self.ng + 1)}, self.fold_a, self.ng)
+
+    def _exact(self, zfill_pairs, rows, cols):
+        """Exact entries [M_n+1, P] (folded for a BLIF)."""
+        if self.mlo == 0:
+            return zfill_pairs(rows, cols, list(range(self.mn + 1)))
+        from . import blif
+        ms = list(range(self.mlo, self.mn + 1))
+        z = zfill_pairs(rows, cols, ms)
+        return blif.fold({m: z[i] for i, m in enumerate(ms)}, self.fold_a, self.mn)
 
     # ---- far part
     def anterpolate(self, x: np.ndarray) -> np.ndarray:
@@ -298,7 +319,7 @@ class AIM:
         sel = np.isin(self.rows, np.asarray(rows))
         rr, cc = self.rows[sel], self.cols[sel]
         ms = list(range(self.mn + 1))
-        return sel, zfill_pairs(rr, cc, ms) - self.far_pairs(ms, rr, cc)
+        return sel, self._exact(zfill_pairs, rr, cc) - self.far_pairs(ms, rr, cc)
 
     def near_rows(self, sel, vals_m: np.ndarray, x: np.ndarray, rows) -> np.ndarray:
         """(Z^near_m x) on ``rows`` from the values of ``near_values_rows``."""
@@ -350,7 +371,7 @@ class AIM:
         """Pre-corrected values [M_n+1, nnz]; ``zfill_pairs(rows, cols, ms)``
         returns the exact Z_m entries [len(ms), nnz]."""
         ms = list(range(self.mn + 1))
-        exact = zfill_pairs(self.rows, self.cols, ms)
+        exact = self._exact(zfill_pairs, self.rows, self.cols)
         far = self.far_pairs(ms, self.rows, self.cols)
         return exact - far
 

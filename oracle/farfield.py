@@ -23,13 +23,14 @@ import math
 import numpy as np
 
 from . import cppif
+from .kernels import basis_T
 from .geometry import Surface
 from .physics import C0, MU0
 from .quadrature import points, radon7
 
 
 class FarField:
-    def __init__(self, surf: Surface, dirs: np.ndarray, dt: float, fc: float):
+    def __init__(self, surf: Surface, dirs: np.ndarray, dt: float, fc: float, basis=None):
         dirs = np.atleast_2d(np.asarray(dirs, dtype=np.float64))
         self.dirs, self.dt, self.ns = dirs, dt, surf.ns
         w = 2.0 * math.pi * fc
@@ -38,8 +39,9 @@ class FarField:
         # tap range: tau' = m + d.r'/(c dt) must lie in (-1, Q]
         rad = np.abs(surf.xyz).max() * math.sqrt(3.0)
         s_max = rad / (C0 * dt)
-        self.m_lo = int(math.floor(-1.0 - s_max))
-        self.m_hi = int(math.ceil(cppif.Q + s_max))
+        lo, hi = (-1.0, cppif.Q) if basis is None else (-basis.M, basis.M)
+        self.m_lo = int(math.floor(lo - s_max))
+        self.m_hi = int(math.ceil(hi + s_max))
         taps = np.arange(self.m_lo, self.m_hi + 1)
         self.taps = taps
         F = np.zeros((len(taps), len(dirs), 3, surf.ns), dtype=np.complex128)
@@ -54,7 +56,7 @@ class FarField:
                 ph = np.exp(1j * k * dr)
                 for ti, m in enumerate(taps):
                     tau = m + dr / (C0 * dt)
-                    f = cppif.T(tau, 1) / dt + 1j * w * cppif.T(tau, 0)
+                    f = basis_T(basis, tau, 1) / dt + 1j * w * basis_T(basis, tau, 0)
                     vec = np.einsum("kp,kp,p,kpx->kx", f, ph, wq, S)      # [ns,3]
                     F[ti, d] += -(MU0 / (4.0 * math.pi)) * (proj[d] @ vec.T)
         self.F = F                                     # [taps, D, 3, ns]

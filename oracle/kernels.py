@@ -28,11 +28,25 @@ from . import cppif
 from .physics import C0, EPS0, MU0
 
 
-class EnvelopeKernel:
-    """Kernel of Z_m for one m; A-part scale mu/(4 pi), phi-part 1/(4 pi eps)."""
+def basis_T(basis, tau, d):
+    """T^(d)(tau) of the temporal basis: the CPPIF (basis None) or a BLIF."""
+    return cppif.T(tau, d) if basis is None else basis.T(tau, d)
 
-    def __init__(self, m: int, dt: float, fc: float):
-        self.m, self.dt = m, dt
+
+def basis_origin(basis, m, d):
+    """T^(d) at tau = m approached from below (R -> 0+): the CPPIF's piece m,
+    or the BLIF's smooth value (its support's right end included)."""
+    if basis is None:
+        return float(cppif.T_piece(m, m, d))
+    return float(basis.T(np.array([float(m)]), d)[0])
+
+
+class EnvelopeKernel:
+    """Kernel of Z_m for one m; A-part scale mu/(4 pi), phi-part 1/(4 pi eps).
+    basis: None for the CPPIF, or an ``oracle.blif.Blif``."""
+
+    def __init__(self, m: int, dt: float, fc: float, basis=None):
+        self.m, self.dt, self.basis = m, dt, basis
         self.w = 2.0 * math.pi * fc
         self.k = self.w / C0
         self.scale_a = MU0 / (4.0 * math.pi)
@@ -44,18 +58,17 @@ class EnvelopeKernel:
     def f(self, R):
         tau = self.m - R / (C0 * self.dt)
         ph = np.exp(-1j * self.k * R)
-        T0, T1, T2 = (cppif.T(tau, d) for d in range(3))
+        T0, T1, T2 = (basis_T(self.basis, tau, d) for d in range(3))
         return ph * self._pa(T0, T1, T2), ph * T0
 
     def f0(self):
-        m = self.m
-        T0, T1, T2 = (float(cppif.T_piece(m, m, d)) for d in range(3))
+        T0, T1, T2 = (basis_origin(self.basis, self.m, d) for d in range(3))
         return self._pa(T0, T1, T2), complex(T0)
 
     def df0(self):
         """d f / dR at R = 0+ (piece m)."""
-        m, cdt = self.m, C0 * self.dt
-        T = [float(cppif.T_piece(m, m, d)) for d in range(4)]
+        cdt = C0 * self.dt
+        T = [basis_origin(self.basis, self.m, d) for d in range(4)]
         pa = self._pa(T[0], T[1], T[2])
         dpa = self._pa(T[1], T[2], T[3])          # d/dtau of P_A
         return (-1j * self.k * pa - dpa / cdt,

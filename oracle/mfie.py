@@ -51,36 +51,38 @@ import math
 
 import numpy as np
 
-from . import cppif
+from .kernels import basis_origin, basis_T
 from .geometry import Surface
 from .physics import C0, ETA0
 from .quadrature import collapsed_gauss, points, radon7
 
 
 class MFIEKernel:
-    """g'_m(R) of the envelope MFIE for one m, and its Gram factor D_m."""
+    """g'_m(R) of the envelope MFIE for one m, and its Gram factor D_m
+    (basis: None for the CPPIF, or an ``oracle.blif.Blif``)."""
 
-    def __init__(self, m: int, dt: float, fc: float):
-        self.m, self.dt = m, dt
+    def __init__(self, m: int, dt: float, fc: float, basis=None):
+        self.m, self.dt, self.basis = m, dt, basis
         self.w = 2.0 * math.pi * fc
         self.k = self.w / C0
 
     def gp(self, R):
         tau = self.m - R / (C0 * self.dt)
-        T0, T1, T2 = (cppif.T(tau, d) for d in range(3))
+        T0, T1, T2 = (basis_T(self.basis, tau, d) for d in range(3))
         pa = T2 / self.dt ** 2 + 2j * self.w * T1 / self.dt - self.w ** 2 * T0
         dt_ = T1 / self.dt + 1j * self.w * T0
         Rs = np.where(R == 0, 1.0, R)
         return -(np.exp(-1j * self.k * R) / (4.0 * math.pi)) * (pa / (C0 * Rs) + dt_ / (Rs * Rs))
 
     def gram(self) -> complex:
-        m = self.m
-        return complex(float(cppif.T_piece(m, m, 1)) / self.dt + 1j * self.w * float(cppif.T_piece(m, m, 0)))
+        m, b = self.m, self.basis
+        return complex(basis_origin(b, m, 1) / self.dt + 1j * self.w * basis_origin(b, m, 0))
 
     def dt_factor(self, R):
         """(DT)(tau) exp(-j k R): the temporal factor of G^H (times 1/(4 pi R))."""
         tau = self.m - R / (C0 * self.dt)
-        return np.exp(-1j * self.k * R) * (cppif.T(tau, 1) / self.dt + 1j * self.w * cppif.T(tau, 0))
+        b = self.basis
+        return np.exp(-1j * self.k * R) * (basis_T(b, tau, 1) / self.dt + 1j * self.w * basis_T(b, tau, 0))
 
 
 class FDMFIEKernel:
@@ -265,7 +267,7 @@ def projection_curl(surf: Surface, grid, i0) -> np.ndarray:
     return H
 
 
-def green_table_h(grid, ms, dt: float, fc: float) -> np.ndarray:
+def green_table_h(grid, ms, dt: float, fc: float, basis=None) -> np.ndarray:
     """G^H_m on the |offset| table [len(ms), Nz, Ny, Nx] (G^H[0] = 0)."""
     nx, ny, nz = grid.n
     k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
@@ -273,15 +275,15 @@ def green_table_h(grid, ms, dt: float, fc: float) -> np.ndarray:
     Rs = np.where(R == 0, 1.0, R)
     out = np.zeros((len(ms),) + R.shape, dtype=np.complex128)
     for a, m in enumerate(ms):
-        out[a] = np.where(R == 0, 0.0, MFIEKernel(m, dt, fc).dt_factor(R) / (4.0 * math.pi * Rs))
+        out[a] = np.where(R == 0, 0.0, MFIEKernel(m, dt, fc, basis).dt_factor(R) / (4.0 * math.pi * Rs))
     return out
 
 
-def cfie_pairs(surf: Surface, rows, cols, ms, dt: float, fc: float, alpha: float) -> np.ndarray:
+def cfie_pairs(surf: Surface, rows, cols, ms, dt: float, fc: float, alpha: float, basis=None) -> np.ndarray:
     """Exact CFIE entries [len(ms), P] of basis pairs for envelope steps ms."""
     from . import kernels, zfill
-    ZE = zfill.assemble_pairs(surf, rows, cols, [kernels.EnvelopeKernel(m, dt, fc) for m in ms])
+    ZE = zfill.assemble_pairs(surf, rows, cols, [kernels.EnvelopeKernel(m, dt, fc, basis) for m in ms])
     if alpha == 1.0:
         return ZE
-    ZH = assemble_pairs(surf, rows, cols, [MFIEKernel(m, dt, fc) for m in ms])
+    ZH = assemble_pairs(surf, rows, cols, [MFIEKernel(m, dt, fc, basis) for m in ms])
     return combine(ZE, ZH, alpha)
