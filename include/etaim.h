@@ -102,6 +102,21 @@ extern "C" {
 #define ETAIM_EFIE 0
 #define ETAIM_CFIE 1
 
+/* Temporal basis (Sec. 3).  ETAIM_CPPIF: the causal cubic interpolant of
+ * order Q = 3.  ETAIM_BLIF: the band-limited interpolatory function of half
+ * width M = 3, T = sinc(tau) W(tau) on -M < tau <= M with Knab's window
+ * W = sinh(a sqrt(u)) / (sqrt(u) sinh a), u = 1 - (tau/M)^2,
+ * a = pi M (1 - 2 beta), beta = f_bw dt (f_bw is then required, with
+ * 0 < beta < 1/2).  Its M - 1 future samples are extrapolated from the last
+ * nsamp ones, I_{l+k} ~ sum_p a_kp I_{l-p}, a_k the least-squares fit of
+ * exp(j w k dt) by exp(-j w p dt) at nomega frequencies spread evenly over
+ * |w| <= 2 pi f_bw (Sec. 3.1.2 cites the scheme; this fit is the library's
+ * reading), and folded into the marching matrices:
+ * Z~_p = Z_p + sum_k a_kp Z_{-k} for p < nsamp.  N_g = floor(Rmax/(c dt) + M).
+ * The march, its operators and the far field then run unchanged. */
+#define ETAIM_CPPIF 0
+#define ETAIM_BLIF 1
+
 typedef struct etaim_ctx etaim_ctx;
 
 /* Triangle mesh of the closed PEC surface (Sec. 3, RWG on a triangular
@@ -129,7 +144,7 @@ typedef struct {
     double beta;        /* dt = beta / f_bw when dt == 0 and ng == 0 (Sec. 3) */
     double f_bw;        /* essential half bandwidth [Hz] for the beta rule */
     int32_t nt_steps;   /* N_t >= 1 */
-    int32_t order;      /* CPPIF order Q; only 3 is supported */
+    int32_t order;      /* CPPIF order Q, or BLIF half width M; only 3 is supported */
     int32_t grid[3];    /* auxiliary grid nodes per axis (>= 8 each); padded
                            FFT lengths 2*grid must be products of 2 and 3 */
     double d_near;      /* near-zone distance [m] between basis centres */
@@ -147,6 +162,11 @@ typedef struct {
     int32_t formulation; /* ETAIM_EFIE (0) or ETAIM_CFIE (1), Sec. 2.1 */
     double alpha;        /* ETAIM_CFIE: weight of the EFIE, 0 <= alpha < 1 (the paper's spheres:
                             0.5, Sec. 5.1); ignored for ETAIM_EFIE */
+    int32_t basis;       /* temporal basis: ETAIM_CPPIF (0) or ETAIM_BLIF (1) */
+    int32_t nsamp;       /* ETAIM_BLIF: past samples the future ones are extrapolated from
+                            (1..4; 0 => 3, the paper's N_samp) */
+    int32_t nomega;      /* ETAIM_BLIF: frequencies of the extrapolation's fit (nsamp..64;
+                            0 => 2 nsamp, the paper's N_omega) */
 } etaim_params;
 
 typedef struct {

@@ -13,9 +13,9 @@ from ctypes import POINTER, byref, c_double, c_int32, c_size_t, c_void_p
 import numpy as np
 
 from . import _lib
-from ._lib import CFIE, EFIE, FP32, FP64, EtaimError, Stats
+from ._lib import BLIF, CFIE, CPPIF, EFIE, FP32, FP64, EtaimError, Stats
 
-__all__ = ["Problem", "EtaimMarch", "EtaimError", "FP32", "FP64", "EFIE", "CFIE"]
+__all__ = ["Problem", "EtaimMarch", "EtaimError", "FP32", "FP64", "EFIE", "CFIE", "CPPIF", "BLIF"]
 
 
 def _torch():
@@ -41,7 +41,7 @@ class Problem:
     def __init__(self, xyz, tri, rwg, *, fc: float, nt: int, grid, d_near: float, dt: float = 0.0,
                  beta: float = 0.0, f_bw: float = 0.0, ng: int = 0, precision: int = FP64, batch: int = 1,
                  tol: float = 1e-6, restart: int = 50, maxit: int = 1000, flags: int = 0, sync_every: int = 1,
-                 alpha: float = 1.0, stream=None):
+                 alpha: float = 1.0, basis: int = 0, nsamp: int = 0, nomega: int = 0, stream=None):
         torch = _torch()
         lib = _lib.load()
         self._xyz = np.ascontiguousarray(xyz, dtype=np.float64)
@@ -55,7 +55,7 @@ class Problem:
                         grid=(c_int32 * 3)(*[int(v) for v in g]), d_near=d_near, ng=ng, precision=precision,
                         batch=batch, tol=tol, restart=restart, maxit=maxit, flags=flags,
                         sync_every=sync_every, formulation=EFIE if alpha == 1.0 else CFIE,
-                        alpha=alpha)
+                        alpha=alpha, basis=basis, nsamp=nsamp, nomega=nomega)
         if stream is None and torch.cuda.is_available():
             stream = torch.cuda.current_stream()
         self.stream = stream

@@ -11,6 +11,7 @@ LIB_PATH = os.path.join(HERE, "libetaim.so")
 OK, EINVAL, ENOMEM, EHIP, ENOCONV, ENONFINITE, EUNSTABLE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
 FP64, FP32 = 0, 1
 EFIE, CFIE = 0, 1
+CPPIF, BLIF = 0, 1
 F_CONTINUE_ON_NOCONV, F_FAIL_ON_UNSTABLE, F_GRAPH, F_IMPLICIT_STOP, F_RESIDUAL_CHECK, F_STEP_GRAPH = 1, 2, 4, 8, 16, 32
 KERNEL_CLASSES = ["anterp_x", "yz_green", "fft_x_inv", "interp_near", "yz_delayed", "yz_commit", "krylov",
                   "ring_far"]
@@ -29,7 +30,8 @@ class Params(ctypes.Structure):
                 ("nt_steps", c_int32), ("order", c_int32), ("grid", c_int32 * 3), ("d_near", c_double),
                 ("ng", c_int32), ("precision", c_int32), ("batch", c_int32), ("tol", c_double),
                 ("restart", c_int32), ("maxit", c_int32), ("flags", c_int32), ("sync_every", c_int32),
-                ("formulation", c_int32), ("alpha", c_double)]
+                ("formulation", c_int32), ("alpha", c_double), ("basis", c_int32), ("nsamp", c_int32),
+                ("nomega", c_int32)]
 
 
 class Derived(ctypes.Structure):

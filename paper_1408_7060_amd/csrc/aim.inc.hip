@@ -1593,9 +1593,10 @@ __global__ void __launch_bounds__(kTileThreads) k_interp_tile(
 // pre-correction, excitation.
 
 // G[m][t][k][j][i] for |offset| (i,j,k) < (Nx,Ny,Nz); t = 0: (mu/4pi) fA/R,
-// t = 1: (1/4 pi eps) fphi/R; zero at the origin.
+// t = 1: (1/4 pi eps) fphi/R; zero at the origin.  With a BLIF the
+// non-causal m = -1..-nk fold into m < np: G~_m = G_m + sum_k a[k-1][m] G_{-k}.
 __global__ void k_green_table(zd* __restrict__ G, GridDims g, int ng, double h, EnvKernel K, double sa,
-                              double sp) {
+                              double sp, TFold fo) {
     const size_t n3 = (size_t)g.N[0] * g.N[1] * g.N[2];
     const size_t tot = (size_t)(ng + 1) * n3;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot; e += (size_t)gridDim.x * blockDim.x) {
@@ -1611,6 +1612,12 @@ __global__ void k_green_table(zd* __restrict__ G, GridDims g, int ng, double h, 
             K.eval(m, R, fa, fp);
             a = (sa / R) * fa;
             p = (sp / R) * fp;
+            if (m < fo.np)
+                for (int kf = 1; kf <= fo.nk; ++kf) {
+                    K.eval(-kf, R, fa, fp);
+                    a += (fo.a[kf - 1][m] * sa / R) * fa;
+                    p += (fo.a[kf - 1][m] * sp / R) * fp;
+                }
         }
         G[((size_t)m * 2 + 0) * n3 + r] = a;
         G[((size_t)m * 2 + 1) * n3 + r] = p;
@@ -1619,7 +1626,8 @@ __global__ void k_green_table(zd* __restrict__ G, GridDims g, int ng, double h, 
 
 // CFIE: G[m][0][k][j][i] = scale exp(-j k R) [T'/dt + j w T](tau) / (4 pi R)
 // (the MFIE's potential, zero at the origin), G[m][1] = 0
-__global__ void k_green_table_h(zd* __restrict__ G, GridDims g, int ng, double h, EnvKernel K, double scale) {
+__global__ void k_green_table_h(zd* __restrict__ G, GridDims g, int ng, double h, EnvKernel K, double scale,
+                                TFold fo) {
     const size_t n3 = (size_t)g.N[0] * g.N[1] * g.N[2];
     const size_t tot = (size_t)(ng + 1) * n3;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot; e += (size_t)gridDim.x * blockDim.x) {
@@ -1634,6 +1642,11 @@ __global__ void k_green_table_h(zd* __restrict__ G, GridDims g, int ng, double h
             zd fa, fh;
             K.evalh(m, R, fa, fh);
             v = (scale / (4.0 * kPi * R)) * fh;
+            if (m < fo.np)
+                for (int kf = 1; kf <= fo.nk; ++kf) {
+                    K.evalh(-kf, R, fa, fh);
+                    v += (fo.a[kf - 1][m] * scale / (4.0 * kPi * R)) * fh;
+                }
         }
         G[((size_t)m * 2 + 0) * n3 + r] = v;
         G[((size_t)m * 2 + 1) * n3 + r] = zd{0, 0};
@@ -1774,7 +1787,7 @@ __global__ void k_excitation(zd* __restrict__ V, const double* __restrict__ Sq, 
 //   tau = (m_lo + tap) + d.r_q/(c dt).
 __global__ void k_farfield_taps(zd* __restrict__ F, const double* __restrict__ Sq, const double* __restrict__ rq,
                                 const double* __restrict__ dirs, int nd, int ns, int ntap, int m_lo, double dt,
-                                double w, double mu4pi) {
+                                double w, double mu4pi, TBasis tb) {
     const size_t tot = (size_t)ntap * nd * ns;
     const double kc = w / kC0, cdt = kC0 * dt;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot; e += (size_t)gridDim.x * blockDim.x) {
@@ -1788,7 +1801,7 @@ __global__ void k_farfield_taps(zd* __restrict__ F, const double* __restrict__ S
             const double* r = rq + ((size_t)k * 14 + q) * 3;
             const double dr = r[0] * u[0] + r[1] * u[1] + r[2] * u[2];
             double T[4];
-            if (!cppif_eval((double)(m_lo + tap) + dr / cdt, T)) continue;
+            if (!tb.eval((double)(m_lo + tap) + dr / cdt, T)) continue;
             const double c = cos(kc * dr), s = sin(kc * dr);
             // (T'/dt + j w T) (c + j s)
             const double fr = T[1] / dt * c - w * T[0] * s;

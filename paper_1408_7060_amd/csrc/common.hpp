@@ -125,6 +125,99 @@ __host__ __device__ inline bool cppif_eval(double tau, double d[4]) {
     return true;
 }
 
+// ---------------------------------------------------------------------------
+// Band-limited interpolatory basis (BLIF, Sec. 3 and Sec. 3.1.2) of half
+// width M: T = sinc(tau) W(tau) on -M < tau <= M, W Knab's approximate
+// prolate window sinh(a sqrt(u)) / (sqrt(u) sinh a), u = 1 - (tau/M)^2,
+// a = pi M (1 - 2 beta), beta = f_bw dt.  W is summed as its power series
+// in u (c[k] = a^(2k+1) / ((2k+1)! sinh a)), which is entire, so T and its
+// derivatives follow from the product rule; the sinc's derivatives are
+// taken in closed form, or by their Taylor series near tau = 0.
+constexpr int kBlifTerms = 24;
+
+struct TBasis {
+    int kind = 0;  // 0: CPPIF of order kQ, 1: BLIF
+    int M = kQ;    // BLIF half width
+    double c[kBlifTerms] = {};
+
+    // lower and upper ends of the support (lo < tau <= hi)
+    __host__ __device__ double lo() const { return kind == 0 ? -1.0 : -(double)M; }
+    __host__ __device__ double hi() const { return kind == 0 ? (double)kQ : (double)M; }
+
+    __host__ __device__ void blif_at(double t, double d[4]) const {
+        const double MM = (double)M * (double)M;
+        const double u = 1.0 - t * t / MM, u1 = -2.0 * t / MM, u2 = -2.0 / MM;
+        // window series and its first three u-derivatives (Horner)
+        double w0 = 0, w1 = 0, w2 = 0, w3 = 0;
+        for (int k = kBlifTerms - 1; k >= 0; --k) {
+            const double kk = (double)k;
+            w0 = w0 * u + c[k];
+            if (k >= 1) w1 = w1 * u + c[k] * kk;
+            if (k >= 2) w2 = w2 * u + c[k] * kk * (kk - 1.0);
+            if (k >= 3) w3 = w3 * u + c[k] * kk * (kk - 1.0) * (kk - 2.0);
+        }
+        const double W0 = w0, W1 = w1 * u1, W2 = w2 * u1 * u1 + w1 * u2, W3 = w3 * u1 * u1 * u1 + 3.0 * w2 * u1 * u2;
+        // sinc derivatives in tau
+        double S0, S1, S2, S3;
+        const double pi = kPi;
+        if (fabs(t) < 0.25) {
+            // sin(pi t)/(pi t) = sum_j (-1)^j (pi t)^(2j) / (2j+1)!
+            S0 = S1 = S2 = S3 = 0.0;
+            double fac = 1.0;  // (2j+1)!
+            double sgn = 1.0;
+            for (int j = 0; j < 16; ++j) {
+                const int e = 2 * j;
+                if (j > 0) fac *= (double)(e) * (double)(e + 1);
+                const double coef = sgn * pow(pi, (double)e) / fac;
+                S0 += coef * pow(t, (double)e);
+                if (e >= 1) S1 += coef * e * pow(t, (double)(e - 1));
+                if (e >= 2) S2 += coef * e * (e - 1) * pow(t, (double)(e - 2));
+                if (e >= 3) S3 += coef * e * (e - 1) * (e - 2) * pow(t, (double)(e - 3));
+                sgn = -sgn;
+            }
+        } else {
+            const double x = pi * t, sx = sin(x), cx = cos(x), x2 = x * x;
+            S0 = sx / x;
+            S1 = pi * (x * cx - sx) / x2;
+            S2 = pi * pi * (-x2 * sx - 2.0 * x * cx + 2.0 * sx) / (x2 * x);
+            S3 = pi * pi * pi * (-x2 * x * cx + 3.0 * x2 * sx + 6.0 * x * cx - 6.0 * sx) / (x2 * x2);
+        }
+        d[0] = S0 * W0;
+        d[1] = S1 * W0 + S0 * W1;
+        d[2] = S2 * W0 + 2.0 * S1 * W1 + S0 * W2;
+        d[3] = S3 * W0 + 3.0 * S2 * W1 + 3.0 * S1 * W2 + S0 * W3;
+    }
+    // T and its first three derivatives at tau (zero outside the support)
+    __host__ __device__ bool eval(double tau, double d[4]) const {
+        if (kind == 0) return cppif_eval(tau, d);
+        if (!(tau > lo() && tau <= hi())) {
+            d[0] = d[1] = d[2] = d[3] = 0.0;
+            return false;
+        }
+        blif_at(tau, d);
+        return true;
+    }
+    // T and its derivatives at tau = m approached from below (R -> 0+): the
+    // CPPIF's piece m, the BLIF's value; false where they vanish
+    __host__ __device__ bool origin(int m, double d[4]) const {
+        if (kind == 0) {
+            if (m < 0 || m > kQ) {
+                d[0] = d[1] = d[2] = d[3] = 0.0;
+                return false;
+            }
+            cppif_piece(m, 0.0, d);
+            return true;
+        }
+        return eval((double)m, d);
+    }
+};
+
+// the BLIF's fold of the non-causal m = -1..-nk into m < np (nk = 0: none)
+struct TFold {
+    int nk = 0, np = 0;
+    double a[2][4] = {};
+};
+
 // Envelope kernel factors for interaction offset m at distance R
 // (differentiated EFIE, Lorenz gauge, envelope Green function
 // delta(t - R/c) exp(-j k R)/(4 pi R), d/dt -> d/dt + j w):
@@ -133,10 +226,11 @@ __host__ __device__ inline bool cppif_eval(double tau, double d[4]) {
 // so that K_A = (mu/4pi) fA / R and K_phi = (1/(4 pi eps)) fphi / R.
 struct EnvKernel {
     double dt, w, k, cdt;
+    TBasis tb{};
     __host__ __device__ void eval(int m, double R, zd& fa, zd& fp) const {
         const double tau = (double)m - R / cdt;
         double d[4];
-        if (!cppif_eval(tau, d)) {
+        if (!tb.eval(tau, d)) {
             fa = {0.0, 0.0};
             fp = {0.0, 0.0};
             return;
@@ -152,7 +246,7 @@ struct EnvKernel {
     __host__ __device__ void evalh(int m, double R, zd& fa, zd& fh) const {
         const double tau = (double)m - R / cdt;
         double d[4];
-        if (!cppif_eval(tau, d)) {
+        if (!tb.eval(tau, d)) {
             fa = {0.0, 0.0};
             fh = {0.0, 0.0};
             return;
@@ -165,19 +259,17 @@ struct EnvKernel {
     }
     // [T'/dt + j w T] at tau = m on piece m (the MFIE's Gram factor D_m)
     __host__ __device__ zd gram(int m) const {
-        if (m < 0 || m > kQ) return zd{0.0, 0.0};
         double d[4];
-        cppif_piece(m, 0.0, d);
+        if (!tb.origin(m, d)) return zd{0.0, 0.0};
         return zd{d[1] / dt, w * d[0]};
     }
     // value and R-derivative at R = 0+ (piece m, tau -> m-)
     __host__ __device__ void origin(int m, zd& fa0, zd& fp0, zd& dfa0, zd& dfp0) const {
-        if (m < 0 || m > kQ) {
+        double d[4];
+        if (!tb.origin(m, d)) {
             fa0 = fp0 = dfa0 = dfp0 = zd{0.0, 0.0};
             return;
         }
-        double d[4];
-        cppif_piece(m, 0.0, d);
         const zd pa{d[2] / (dt * dt) - w * w * d[0], 2.0 * w * d[1] / dt};
         const zd dpa{d[3] / (dt * dt) - w * w * d[1], 2.0 * w * d[2] / dt};
         fa0 = pa;

@@ -35,6 +35,10 @@ struct Geometry {
 struct Setup {
     double dt = 0, h = 0, x0[3] = {0, 0, 0}, rmax = 0, rst = 0, d_near = 0;
     int ng = 0, mn = 0, N[3] = {0, 0, 0}, L[3] = {0, 0, 0};
+    TBasis tb{};                    // temporal basis (CPPIF, or BLIF with its window series)
+    int mlo = 0;                    // lowest m of the unfolded kernels (BLIF: -(M-1))
+    int nsamp = 0;                  // BLIF: past samples of the extrapolation
+    std::vector<double> fold_a;     // BLIF: [M-1][nsamp] extrapolation coefficients
     bool cfie = false;              // combined-field equation (Sec. 2.1)
     double alpha = 1.0;             // its weight of the EFIE
     std::vector<double> lam;        // [ns][4][64] projection weights

@@ -2008,17 +2008,26 @@ int device_setup(etaim_ctx* c) {
     CHK(c->alloc(gtab, (size_t)(s.ng + 1) * 2 * c->N3));
     const double w = 2.0 * kPi * c->prm.fc;
     EnvKernel K{s.dt, w, w / kC0, kC0 * s.dt};
+    K.tb = s.tb;
+    // the BLIF's fold of its non-causal tables (none for the CPPIF)
+    TFold fo{};
+    if (s.mlo < 0) {
+        fo.nk = -s.mlo;
+        fo.np = s.nsamp;
+        for (int kf = 0; kf < fo.nk; ++kf)
+            for (int q = 0; q < fo.np; ++q) fo.a[kf][q] = s.fold_a[(size_t)kf * s.nsamp + q];
+    }
     // the CFIE weighs the EFIE's tables by alpha and adds the MFIE's, -(1 - alpha) eta G^H
     const double sa = s.alpha * kMu0 / (4.0 * kPi), sp = s.alpha / (4.0 * kPi * eps0());
     hipLaunchKernelGGL(k_green_table, dim3(blocks_for((size_t)(s.ng + 1) * c->N3)), dim3(256), 0, c->stream, gtab,
-                       c->gd, s.ng, s.h, K, sa, sp);
+                       c->gd, s.ng, s.h, K, sa, sp, fo);
     HIPCHK(hipGetLastError());
     zd* gtabH = nullptr;
     if (s.cfie) {
         CHK(c->alloc(gtabH, (size_t)(s.ng + 1) * 2 * c->N3));
         const double sh = -(1.0 - s.alpha) * std::sqrt(kMu0 / eps0());
         hipLaunchKernelGGL(k_green_table_h, dim3(blocks_for((size_t)(s.ng + 1) * c->N3)), dim3(256), 0, c->stream,
-                           gtabH, c->gd, s.ng, s.h, K, sh);
+                           gtabH, c->gd, s.ng, s.h, K, sh, fo);
         HIPCHK(hipGetLastError());
     }
     if (c->nnz > 0)
@@ -2651,15 +2660,15 @@ int farfield_taps(etaim_ctx* c, int nd, const double* dirs, zd*& F, double*& dd,
     double rad = 0;
     for (double v : c->geo.xyz) rad = std::max(rad, std::fabs(v));
     const double smax = rad * std::sqrt(3.0) / (kC0 * c->st.dt);
-    m_lo = (int)std::floor(-1.0 - smax);
-    const int m_hi = (int)std::ceil((double)kQ + smax);
+    m_lo = (int)std::floor(c->st.tb.lo() - smax);
+    const int m_hi = (int)std::ceil(c->st.tb.hi() + smax);
     ntap = m_hi - m_lo + 1;
     std::vector<double> dv(dirs, dirs + 3 * (size_t)nd);
     CHK(c->upload(dd, dv));
     CHK(c->alloc(F, (size_t)ntap * nd * 3 * c->ns));
     const size_t tot = (size_t)ntap * nd * c->ns;
     hipLaunchKernelGGL(k_farfield_taps, dim3(blocks_for(tot)), dim3(256), 0, c->stream, F, c->Sq, c->rq, dd, nd,
-                       c->ns, ntap, m_lo, c->st.dt, 2.0 * kPi * c->prm.fc, kMu0 / (4.0 * kPi));
+                       c->ns, ntap, m_lo, c->st.dt, 2.0 * kPi * c->prm.fc, kMu0 / (4.0 * kPi), c->st.tb);
     HIPCHK(hipGetLastError());
     return ETAIM_OK;
 }

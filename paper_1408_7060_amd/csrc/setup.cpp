@@ -251,6 +251,10 @@ int derive_parameters(const Geometry& g, const etaim_params* p, Setup& s, std::s
     }
     s.cfie = p->formulation == ETAIM_CFIE;
     s.alpha = s.cfie ? p->alpha : 1.0;
+    if (p->basis != ETAIM_CPPIF && p->basis != ETAIM_BLIF) {
+        err = "basis must be ETAIM_CPPIF or ETAIM_BLIF";
+        return ETAIM_EINVAL;
+    }
     // largest vertex-to-vertex distance
     double best = 0.0;
 #pragma omp parallel for reduction(max : best) schedule(dynamic, 64)
@@ -285,6 +289,70 @@ int derive_parameters(const Geometry& g, const etaim_params* p, Setup& s, std::s
     if (s.ng < 1 || s.ng > 4096) {
         err = "history depth out of range";
         return ETAIM_EINVAL;
+    }
+    if (p->basis == ETAIM_BLIF) {
+        // the window's oversampling and the extrapolation of the M - 1 future samples
+        const int M = p->order;
+        const double beta = p->f_bw * s.dt;
+        const int ns_ = p->nsamp > 0 ? p->nsamp : 3, nw = p->nomega > 0 ? p->nomega : 2 * ns_;
+        if (!(p->f_bw > 0) || !(beta > 0.0 && beta < 0.5)) {
+            err = "the BLIF needs f_bw > 0 with 0 < f_bw dt < 1/2";
+            return ETAIM_EINVAL;
+        }
+        if (ns_ < 1 || ns_ > 4 || nw < ns_ || nw > 64 || s.ng < ns_) {
+            err = "the BLIF's extrapolation needs 1 <= nsamp <= 4, nsamp <= nomega <= 64, nsamp <= N_g";
+            return ETAIM_EINVAL;
+        }
+        s.tb.kind = 1;
+        s.tb.M = M;
+        const double a = kPi * M * (1.0 - 2.0 * beta), sha = std::sinh(a);
+        double fct = 1.0;  // (2k+1)!
+        for (int k = 0; k < kBlifTerms; ++k) {
+            if (k > 0) fct *= (double)(2 * k) * (double)(2 * k + 1);
+            s.tb.c[k] = std::pow(a, 2.0 * k + 1.0) / fct / sha;
+        }
+        s.mlo = -(M - 1);
+        s.nsamp = ns_;
+        // real least squares over the nw frequencies w dt = 2 pi beta x, x even on [-1, 1]:
+        // rows (Re, Im) of exp(-j w p dt) a = exp(j w k dt), normal equations (nsamp <= 4)
+        s.fold_a.assign((size_t)(M - 1) * ns_, 0.0);
+        for (int k = 1; k < M; ++k) {
+            double N[4][5] = {};
+            for (int q = 0; q < nw; ++q) {
+                const double x = nw == 1 ? 0.0 : -1.0 + 2.0 * q / (nw - 1);
+                const double wd = 2.0 * kPi * beta * x;
+                double re[4], im[4];
+                for (int c = 0; c < ns_; ++c) {
+                    re[c] = std::cos(wd * c);
+                    im[c] = -std::sin(wd * c);
+                }
+                const double br = std::cos(wd * k), bi = std::sin(wd * k);
+                for (int i = 0; i < ns_; ++i) {
+                    for (int j = 0; j < ns_; ++j) N[i][j] += re[i] * re[j] + im[i] * im[j];
+                    N[i][ns_] += re[i] * br + im[i] * bi;
+                }
+            }
+            // Gaussian elimination with partial pivoting
+            for (int i = 0; i < ns_; ++i) {
+                int piv = i;
+                for (int r = i + 1; r < ns_; ++r)
+                    if (std::fabs(N[r][i]) > std::fabs(N[piv][i])) piv = r;
+                for (int j = 0; j <= ns_; ++j) std::swap(N[i][j], N[piv][j]);
+                if (!(std::fabs(N[i][i]) > 0)) {
+                    err = "the BLIF's extrapolation fit is singular";
+                    return ETAIM_EINVAL;
+                }
+                for (int r = i + 1; r < ns_; ++r) {
+                    const double f = N[r][i] / N[i][i];
+                    for (int j = i; j <= ns_; ++j) N[r][j] -= f * N[i][j];
+                }
+            }
+            for (int i = ns_ - 1; i >= 0; --i) {
+                double v = N[i][ns_];
+                for (int j = i + 1; j < ns_; ++j) v -= N[i][j] * s.fold_a[(size_t)(k - 1) * ns_ + j];
+                s.fold_a[(size_t)(k - 1) * ns_ + i] = v / N[i][i];
+            }
+        }
     }
     // grid
     double lo[3], hi[3];
@@ -545,6 +613,10 @@ int build_near_zone(const Geometry& g, const etaim_params* p, Setup& s, std::str
     }
     s.rst = rst;
     s.mn = std::min(s.ng, kQ + (int)std::floor((s.d_near + 2.0 * s.rst) / (kC0 * s.dt)));
+    if (s.nsamp > s.mn + 1) {
+        err = "the BLIF's nsamp exceeds the near-zone depth M_n + 1";
+        return ETAIM_EINVAL;
+    }
     return ETAIM_OK;
 }
 
@@ -552,26 +624,30 @@ int build_near_zone(const Geometry& g, const etaim_params* p, Setup& s, std::str
 // Exact entries Z_m[k,k'] (m = 0..mn) of every near pair.
 void exact_near_entries(const Geometry& g, const etaim_params* p, Setup& s) {
     const Rule7 rule;
-    const int M = s.mn + 1;
+    // stored m = 0..mn; computed m = mlo..mn (index i <-> m = mlo + i), the
+    // BLIF's non-causal m < 0 folded into m < nsamp at the end of each pair
+    const int M = s.mn + 1, mlo = s.mlo, ME = s.mn - mlo + 1;
     const double w = 2.0 * kPi * p->fc;
     EnvKernel K{s.dt, w, w / kC0, kC0 * s.dt};
-    std::vector<zd> fa0(M), fp0(M), dfa0(M), dfp0(M);
-    for (int m = 0; m < M; ++m) K.origin(m, fa0[m], fp0[m], dfa0[m], dfp0[m]);
+    K.tb = s.tb;
+    std::vector<zd> fa0(ME), fp0(ME), dfa0(ME), dfp0(ME);
+    for (int m = 0; m < ME; ++m) K.origin(mlo + m, fa0[m], fp0[m], dfa0[m], dfp0[m]);
     const double sa = kMu0 / (4.0 * kPi), sp = 1.0 / (4.0 * kPi * eps0());
     // CFIE: alpha EFIE + (1 - alpha) eta MFIE (Sec. 2.1); MFIE Gram factors D_m
     const double al = s.alpha, bh = (1.0 - s.alpha) * std::sqrt(kMu0 / eps0());
-    std::vector<zd> gm(M);
-    for (int m = 0; m < M; ++m) gm[m] = K.gram(m);
+    std::vector<zd> gm(ME);
+    for (int m = 0; m < ME; ++m) gm[m] = K.gram(mlo + m);
     const size_t nnz = s.col.size();
     s.near_exact.assign(nnz * M, zd{0, 0});
 #pragma omp parallel
     {
-        std::vector<zd> IA(M), IF(M), IH(M);
+        std::vector<zd> IA(ME), IF(ME), IH(ME), ext(ME);
 #pragma omp for schedule(dynamic, 16)
         for (int k = 0; k < g.ns; ++k) {
             for (int e = s.rowptr[k]; e < s.rowptr[k + 1]; ++e) {
                 const int kk = s.col[e];
-                zd* out = &s.near_exact[(size_t)e * M];
+                std::fill(ext.begin(), ext.end(), zd{0, 0});
+                zd* out = ext.data();
                 for (int h = 0; h < 2; ++h)
                     for (int hh = 0; hh < 2; ++hh) {
                         const int ta = g.t[2 * k + h], tb = g.t[2 * kk + hh];
@@ -589,7 +665,7 @@ void exact_near_entries(const Geometry& g, const etaim_params* p, Setup& s) {
                             ra[q] = rule.b[q][0] * va[0] + rule.b[q][1] * va[1] + rule.b[q][2] * va[2];
                             rb[q] = rule.b[q][0] * vb[0] + rule.b[q][1] * vb[1] + rule.b[q][2] * vb[2];
                         }
-                        for (int m = 0; m < M; ++m) IA[m] = IF[m] = zd{0, 0};
+                        for (int m = 0; m < ME; ++m) IA[m] = IF[m] = zd{0, 0};
                         const double Aa = g.area[ta], Ab = g.area[tb];
                         for (int pq = 0; pq < 7; ++pq) {
                             const V3 da = ra[pq] - fa;
@@ -598,14 +674,14 @@ void exact_near_entries(const Geometry& g, const etaim_params* p, Setup& s) {
                                 const double R = std::sqrt(dv.x * dv.x + dv.y * dv.y + dv.z * dv.z);
                                 const double W = rule.w[pq] * rule.w[qq] * (Aa * Ab);
                                 const double D = dot(da, rb[qq] - fb);
-                                for (int m = 0; m < M; ++m) {
+                                for (int m = 0; m < ME; ++m) {
                                     zd ka, kp;
                                     if (touch && R == 0.0) {
                                         ka = dfa0[m];
                                         kp = dfp0[m];
                                     } else {
                                         zd fA, fP;
-                                        K.eval(m, R, fA, fP);
+                                        K.eval(mlo + m, R, fA, fP);
                                         if (touch) {
                                             fA -= fa0[m];
                                             fP -= fp0[m];
@@ -629,7 +705,7 @@ void exact_near_entries(const Geometry& g, const etaim_params* p, Setup& s) {
                                 sA += wa * dot(ra[pq] - fa, Vj);
                                 sF += wa * I0;
                             }
-                            for (int m = 0; m < M; ++m) {
+                            for (int m = 0; m < ME; ++m) {
                                 IA[m] += sA * fa0[m];
                                 IF[m] += sF * fp0[m];
                             }
@@ -637,19 +713,19 @@ void exact_near_entries(const Geometry& g, const etaim_params* p, Setup& s) {
                         const double sg = (h == 0 ? 1.0 : -1.0) * (hh == 0 ? 1.0 : -1.0);
                         const double cA = sg * g.len[k] * g.len[kk] / (4.0 * Aa * Ab);
                         const double cP = sg * g.len[k] * g.len[kk] / (Aa * Ab);
-                        for (int m = 0; m < M; ++m) out[m] += al * ((sa * cA) * IA[m] + (sp * cP) * IF[m]);
+                        for (int m = 0; m < ME; ++m) out[m] += al * ((sa * cA) * IA[m] + (sp * cP) * IF[m]);
                         if (!s.cfie) continue;
                         if (ta == tb) {
                             // Gram term D_m / 2 <S_k, S_k'> on the shared triangle (exact, degree 2)
                             double gs = 0.0;
                             for (int q = 0; q < 7; ++q) gs += rule.w[q] * Aa * dot(ra[q] - fa, ra[q] - fb);
-                            for (int m = 0; m < M; ++m) out[m] += (bh * 0.5 * cA * gs) * gm[m];
+                            for (int m = 0; m < ME; ++m) out[m] += (bh * 0.5 * cA * gs) * gm[m];
                             continue;  // n x (Rhat x S') = 0 on a flat triangle with itself
                         }
                         // - int int g'_m(R) S_k . (n_a x (Rhat x S_k')),
                         // g'_m = -(1/4 pi) [fA/(c R) + fH/R^2]
                         const V3 na = {g.nrm[3 * (size_t)ta], g.nrm[3 * (size_t)ta + 1], g.nrm[3 * (size_t)ta + 2]};
-                        for (int m = 0; m < M; ++m) IH[m] = zd{0, 0};
+                        for (int m = 0; m < ME; ++m) IH[m] = zd{0, 0};
                         for (int pq = 0; pq < 7; ++pq) {
                             const V3 da = ra[pq] - fa;
                             for (int qq = 0; qq < 7; ++qq) {
@@ -660,16 +736,22 @@ void exact_near_entries(const Geometry& g, const etaim_params* p, Setup& s) {
                                 const V3 db = rb[qq] - fb;
                                 const double term = dot(da, rh) * dot(na, db) - dot(da, db) * dot(na, rh);
                                 const double W = rule.w[pq] * rule.w[qq] * (Aa * Ab);
-                                for (int m = 0; m < M; ++m) {
+                                for (int m = 0; m < ME; ++m) {
                                     zd fA, fH;
-                                    K.evalh(m, R, fA, fH);
+                                    K.evalh(mlo + m, R, fA, fH);
                                     const zd gp = (-1.0 / (4.0 * kPi)) * ((1.0 / (kC0 * R)) * fA + (1.0 / (R * R)) * fH);
                                     IH[m] += (W * term) * gp;
                                 }
                             }
                         }
-                        for (int m = 0; m < M; ++m) out[m] += (-bh * cA) * IH[m];
+                        for (int m = 0; m < ME; ++m) out[m] += (-bh * cA) * IH[m];
                     }
+                // stored values: m = 0..mn, the non-causal ones folded in (BLIF)
+                zd* dst = &s.near_exact[(size_t)e * M];
+                for (int m = 0; m < M; ++m) dst[m] = ext[m - mlo];
+                for (int kf = 1; kf <= -mlo; ++kf)
+                    for (int q = 0; q < s.nsamp && q < M; ++q)
+                        dst[q] += s.fold_a[(size_t)(kf - 1) * s.nsamp + q] * ext[-kf - mlo];
             }
         }
     }

@@ -7,9 +7,10 @@
 // Input file (little-endian): int32 nv, nt, ns; float64 xyz[nv][3];
 // int32 tri[nt][3]; int32 rwg[ns][4]; float64 fc, beta, f_bw, d_near;
 // int32 grid.  Prints one line of summary numbers.  With two more arguments
-// (alpha, output path) the problem is the CFIE with that alpha and the
-// driver also writes, little-endian: int32 nnz, mn; int32 rowptr[ns+1],
-// col[nnz]; complex128 near_exact[nnz][mn+1]; float64 lamH[ns][4][64].
+// (alpha, output path) the problem is the CFIE with that alpha (the EFIE for
+// alpha = 1), with a third ("blif") on the BLIF basis, and the driver also
+// writes, little-endian: int32 nnz, mn; int32 rowptr[ns+1], col[nnz];
+// complex128 near_exact[nnz][mn+1]; float64 lamH[ns][4][64] (CFIE only).
 #include <cstdio>
 #include <cstdlib>
 #include <string>
@@ -22,7 +23,7 @@ using namespace etaim;
 static bool rd(FILE* f, void* p, size_t n) { return std::fread(p, 1, n, f) == n; }
 
 int main(int argc, char** argv) {
-    if (argc != 2 && argc != 4) return 2;
+    if (argc != 2 && argc != 4 && argc != 5) return 2;
     FILE* f = std::fopen(argv[1], "rb");
     if (!f) return 2;
     int32_t nv, nt, ns, grid;
@@ -50,9 +51,10 @@ int main(int argc, char** argv) {
     p.tol = 1e-6;
     p.restart = 20;
     p.maxit = 100;
-    if (argc == 4) {
-        p.formulation = ETAIM_CFIE;
+    if (argc >= 4) {
         p.alpha = std::atof(argv[2]);
+        p.formulation = p.alpha < 1.0 ? ETAIM_CFIE : ETAIM_EFIE;
+        if (argc == 5 && std::string(argv[4]) == "blif") p.basis = ETAIM_BLIF;
     }
     Geometry g;
     Setup s;
@@ -100,7 +102,7 @@ int main(int argc, char** argv) {
         Geometry g2;
         rejected += build_geometry(&m2, &r, g2, err) != 0;
     }
-    if (argc == 4) {
+    if (argc >= 4) {
         FILE* o = std::fopen(argv[3], "wb");
         if (!o) return 2;
         const int32_t nnz = (int32_t)s.col.size(), mn = s.mn;
@@ -109,7 +111,7 @@ int main(int argc, char** argv) {
         std::fwrite(s.rowptr.data(), 4, s.rowptr.size(), o);
         std::fwrite(s.col.data(), 4, s.col.size(), o);
         std::fwrite(s.near_exact.data(), sizeof(zd), s.near_exact.size(), o);
-        std::fwrite(s.lamH.data(), 8, s.lamH.size(), o);
+        if (!s.lamH.empty()) std::fwrite(s.lamH.data(), 8, s.lamH.size(), o);
         std::fclose(o);
     }
     std::printf("ns %d ng %d mn %d nnz %zu lam %.12e near %.12e sai %.12e rejected %d\n", g.ns, s.ng, s.mn,

@@ -94,3 +94,34 @@ def test_host_cfie_setup_matches_the_oracle(driver):
     assert np.abs(lamH[:, :3] - A.H).max() <= 1e-13 * np.abs(A.H).max()
     ref = mfie.cfie_pairs(s, A.rows, A.cols, list(range(mn + 1)), dt, wl.f0, 0.5)
     assert np.abs(near.T - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_host_blif_setup_matches_the_oracle(driver):
+    """The BLIF basis (M = 3, extrapolation from 3 samples fitted at 6
+    frequencies) in the host set-up, sanitized: the folded exact near-zone
+    entries of every near pair equal the oracle's (the window series, the
+    non-causal kernels, the least-squares extrapolation and the fold)."""
+    exe, mesh, tmp = driver
+    out = tmp / "blif.bin"
+    r = subprocess.run([str(exe), str(mesh), "1.0", str(out), "blif"], capture_output=True, text=True, env=_ENV,
+                       timeout=600)
+    assert r.returncode == 0, r.stdout + r.stderr
+    from oracle import aim, blif, geometry, kernels, physics as ph, zfill
+    wl = W.SPHERE_L2
+    xyz, tri, rwg = wl.mesh()
+    s = geometry.Surface(xyz, tri, rwg)
+    d_near = wl.near_lambda * 299_792_458.0 / wl.f0
+    dt = ph.dt_from_beta(wl.beta, wl.f_bw)
+    b = blif.Blif(3, wl.f_bw * dt)
+    a = blif.extrapolation(b.beta, 3, 3, 6)
+    ng = int(np.floor(ph.rmax_of(xyz) / (ph.C0 * dt) + 3))
+    A = aim.AIM(s, wl.grid, d_near, dt, wl.f0, ng, basis=b, fold_a=a)
+    with open(out, "rb") as f:
+        nnz, mn = np.fromfile(f, "<i4", 2)
+        rowptr = np.fromfile(f, "<i4", s.ns + 1)
+        col = np.fromfile(f, "<i4", nnz)
+        near = np.fromfile(f, "<c16", nnz * (mn + 1)).reshape(nnz, mn + 1)
+    assert mn == A.mn
+    ref = A._exact(lambda rr, cc, ms: zfill.assemble_pairs(
+        s, rr, cc, [kernels.EnvelopeKernel(m, dt, wl.f0, b) for m in ms]), A.rows, A.cols)
+    assert np.abs(near.T - ref).max() <= 1e-12 * np.abs(ref).max()
