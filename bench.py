@@ -62,15 +62,16 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_problem(wl, precision, batch, nt, tol, flags=1, sync_every=1, alpha=1.0):
+def make_problem(wl, precision, batch, nt, tol, flags=1, sync_every=1, alpha=1.0, basis=0):
     import workloads as W  # noqa: F401
     from paper_1408_7060_amd import Problem
     xyz, tri, rwg = wl.mesh()
     d_near = wl.near_lambda * 299_792_458.0 / wl.f0
     kw = dict(fc=wl.f0, nt=nt, grid=wl.grid, d_near=d_near, precision=precision, batch=batch, tol=tol,
-              restart=50, maxit=2000, flags=flags, sync_every=sync_every, alpha=alpha)
+              restart=50, maxit=2000, flags=flags, sync_every=sync_every, alpha=alpha, basis=basis)
     if wl.ng:
         kw["ng"] = wl.ng
+        kw["f_bw"] = wl.f_bw
     else:
         kw.update(beta=wl.beta, f_bw=wl.f_bw)
     return Problem(xyz, tri, rwg, **kw)
@@ -202,7 +203,7 @@ def roofline_record(dom, d, info, batch, traffic):
             "bytes_per_launch": bytes_launch, "avg_launch_ms": avg_ms, "launches": d["launches"]}
 
 
-def sweep(torch, W, FP64, alpha=1.0):
+def sweep(torch, W, FP64, alpha=1.0, basis=0):
     """The ET-AIM size and bandwidth sweep of spheres (the trends of the
     paper's Figs. 2-3 without the comparison methods): every size at
     chi = 3 and 100, every chi at the smallest and the level-4 size; per
@@ -216,7 +217,7 @@ def sweep(torch, W, FP64, alpha=1.0):
     for (L, a, g, chi) in pts:
         wl = W.sweep_workload(L, a, g, chi)
         t = time.perf_counter()
-        P = make_problem(wl, FP64, 1, wl.nt, 1e-6, flags=F_CONTINUE_ON_NOCONV, alpha=alpha)
+        P = make_problem(wl, FP64, 1, wl.nt, 1e-6, flags=F_CONTINUE_ON_NOCONV, alpha=alpha, basis=basis)
         setup_s = time.perf_counter() - t
         kh, pp = wl.incidence()
         V = P.excitation(kh, pp, wl.sigma, wl.td)
@@ -227,6 +228,7 @@ def sweep(torch, W, FP64, alpha=1.0):
         wall = time.perf_counter() - t
         nt = st["steps_done"]
         rec = {"point": wl.name, "formulation": "EFIE" if alpha == 1.0 else f"CFIE alpha={alpha}",
+               "basis": "BLIF M=3" if basis else "CPPIF Q=3",
                "ns": P.ns, "chi": chi, "f_c_MHz": round(wl.f0 / 1e6, 1),
                "f_bw_MHz": round(wl.f_bw / 1e6, 2), "grid": g, "ng": P.info["ng"], "mn": P.info["mn"],
                "nnz": P.info["nnz"], "nt": nt, "gmres_iters_per_step": round(st["total_iters"] / max(nt, 1), 2),
@@ -272,6 +274,9 @@ def main():
                          "line per point")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="first copy this many MiB device-to-device (counter calibration)")
+    ap.add_argument("--blif", action="store_true",
+                    help="--sweep only: the band-limited interpolatory basis (M = 3, extrapolation from 3 samples "
+                         "fitted at 6 frequencies) instead of the CPPIF")
     ap.add_argument("--no-cfie", action="store_true",
                     help="skip the CFIE (alpha = 0.5) march of the same window that the EFIE bench adds")
     ap.add_argument("--alpha", type=float, default=1.0,
@@ -285,7 +290,7 @@ def main():
     import workloads as W
     from paper_1408_7060_amd import FP32, FP64
     if args.sweep:
-        return sweep(torch, W, FP64, args.alpha)
+        return sweep(torch, W, FP64, args.alpha, 1 if args.blif else 0)
     from paper_1408_7060_amd._lib import F_CONTINUE_ON_NOCONV, F_GRAPH, F_IMPLICIT_STOP, F_RESIDUAL_CHECK
     # the FP64 residual check of eq. (5) every 16 steps is part of the precision form
     fl = F_CONTINUE_ON_NOCONV | F_RESIDUAL_CHECK | (0 if args.true_residual else F_IMPLICIT_STOP)
