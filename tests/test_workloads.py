@@ -164,3 +164,22 @@ def test_sweep_recipes():
             assert 300e6 / wl.f_bw == pytest.approx(chi, rel=1e-12)
             dt = wl.beta / wl.f_bw
             assert wl.nt * dt >= 16 * wl.sigma + 2 * radius / 299_792_458.0
+
+
+def test_plate_mesh_and_open_rwg_table():
+    """The plate: area size^2, every normal +z, n^2 squares of two
+    triangles, and RWG on the 3n^2 - 2n interior edges only (the 4n
+    boundary edges carry no basis); a closed-surface RWG table refuses it."""
+    size, edge = 1.3, 0.1
+    xyz, tri = W.plate_mesh(size, edge)
+    n = math.ceil(size / edge)
+    assert len(tri) == 2 * n * n
+    p0, p1, p2 = xyz[tri[:, 0]], xyz[tri[:, 1]], xyz[tri[:, 2]]
+    cr = np.cross(p1 - p0, p2 - p0)
+    assert np.all(cr[:, 2] > 0) and np.allclose(cr[:, :2], 0.0)
+    assert 0.5 * cr[:, 2].sum() == pytest.approx(size * size, rel=1e-12)
+    rwg = W.rwg_table(tri, open_ok=True)
+    assert len(rwg) == 3 * n * n - 2 * n
+    with pytest.raises(ValueError):
+        W.rwg_table(tri)
+    assert len(W.PLATE_1M.mesh()[2]) == 341

@@ -71,14 +71,15 @@ def icosphere(level: int, radius: float = 1.0, rotation: np.ndarray | None = Non
     return np.ascontiguousarray(xyz), np.ascontiguousarray(tri)
 
 
-def rwg_table(tri: np.ndarray) -> np.ndarray:
+def rwg_table(tri: np.ndarray, open_ok: bool = False) -> np.ndarray:
     """RWG edge table int32 [ns,4] = {t_plus, t_minus, edge_v0, edge_v1}.
 
     One row per edge shared by exactly two triangles, ordered by (v0, v1)
     with v0 < v1.  T+ is the triangle whose counter-clockwise boundary runs
     v0 -> v1, T- the one that runs v1 -> v0, so the basis current flows from
-    T+ across the edge into T-.  Raises if the mesh is not a closed,
-    consistently oriented 2-manifold.
+    T+ across the edge into T-.  Raises if the mesh is not a consistently
+    oriented 2-manifold, and, unless open_ok (a plate: its boundary edges
+    carry no basis), if it is not closed.
     """
     owner: dict[tuple[int, int], int] = {}
     for t, (a, b, c) in enumerate(np.asarray(tri)):
@@ -89,9 +90,11 @@ def rwg_table(tri: np.ndarray) -> np.ndarray:
             owner[key] = t
     rows = []
     for (p, q), t in owner.items():
+        if (q, p) not in owner:
+            if open_ok:
+                continue
+            raise ValueError(f"edge ({p},{q}) has one triangle: open surface")
         if p < q:
-            if (q, p) not in owner:
-                raise ValueError(f"edge ({p},{q}) has one triangle: open surface")
             rows.append((t, owner[(q, p)], p, q))
     rows.sort(key=lambda r: (r[2], r[3]))
     return np.array(rows, dtype=np.int32).reshape(-1, 4)
@@ -116,6 +119,23 @@ def _orient_outward(xyz, tri, centre):
     tri = tri.copy()
     tri[flip] = tri[flip][:, [0, 2, 1]]
     return tri
+
+
+def plate_mesh(size: float, edge: float):
+    """Square PEC plate of side `size` in the z = 0 plane, centred at the
+    origin: n x n squares (n = ceil(size / edge)), each split along the same
+    diagonal into two triangles, counter-clockwise about +z."""
+    n = max(1, int(math.ceil(size / edge)))
+    g = np.linspace(-size / 2, size / 2, n + 1)
+    X, Y = np.meshgrid(g, g, indexing="xy")
+    xyz = np.stack([X.ravel(), Y.ravel(), np.zeros(X.size)], axis=1)
+    vid = lambda i, j: j * (n + 1) + i  # noqa: E731
+    tri = []
+    for j in range(n):
+        for i in range(n):
+            q = (vid(i, j), vid(i + 1, j), vid(i + 1, j + 1), vid(i, j + 1))
+            tri += [(q[0], q[1], q[2]), (q[0], q[2], q[3])]
+    return xyz, np.array(tri, dtype=np.int32)
 
 
 def box_mesh(centre, size, edge):
@@ -338,6 +358,7 @@ class Workload:
     khat: tuple = (0.0, 0.0, -1.0)
     phat: tuple = (1.0, 0.0, 0.0)
     composite_seed: int | None = None
+    plate_size: float | None = None   # a square plate of this side (metres) in z = 0
     extra: dict = field(default_factory=dict)
 
     @property
@@ -355,9 +376,14 @@ class Workload:
 
     @property
     def edge(self) -> float:
+        if "edge" in self.extra:
+            return self.extra["edge"]
         return C0 / (self.f0 * (1.0 + self.frac_bw)) / 10.0
 
     def mesh(self):
+        if self.plate_size is not None:
+            xyz, tri = plate_mesh(self.plate_size, self.edge)
+            return xyz, tri, rwg_table(tri, open_ok=True)
         if self.composite_seed is not None:
             xyz, tri = composite(self.composite_seed, edge=self.edge)
             return xyz, tri, rwg_table(tri)
@@ -401,8 +427,15 @@ COMPOSITE = Workload("composite6_1GHz", level=0, radius=0.0, f0=1e9, frac_bw=0.0
 COMPOSITE_SMALL = Workload("composite6_250MHz", level=0, radius=0.0, f0=250e6, frac_bw=0.05, nt=200, grid=48,
                            near_lambda=0.25, ng=32, composite_seed=0)
 
+# plate (Sec. 5.1: the paper's plates use the EFIE, alpha = 1): a 1 m square
+# PEC plate at 300 MHz +-5 %, edge lambda_min / 10 (11 x 11 squares, 341 RWG),
+# on a 16 x 16 x 8 grid (the plate lies in z = 0, midway between two node
+# planes; 8 nodes is the grid's minimum along z)
+PLATE_1M = Workload("plate_1m_300MHz", level=0, radius=0.0, f0=300e6, frac_bw=0.05, nt=80, grid=(16, 16, 8),
+                    near_lambda=0.3, beta=0.2, plate_size=1.0)
+
 WORKLOADS = {w.name: w for w in (SPHERE_L2, SPHERE_L4, SPHERE_L4_BATCH, SPHERE_L4_ADJ, SPHERE_L3,
-                                 SPHERE_L2_NARROW, COMPOSITE, COMPOSITE_SMALL)}
+                                 SPHERE_L2_NARROW, COMPOSITE, COMPOSITE_SMALL, PLATE_1M)}
 
 # size and bandwidth sweep of spheres (ET-AIM only): the band's top fixed at
 # f_max = 300 MHz while chi = f_max / f_bw varies (f_c = f_max - f_bw), and
@@ -424,3 +457,24 @@ def sweep_workload(level: int, radius: float, grid: int, chi: float) -> Workload
     nt = int(math.ceil((16.0 * sigma + 2.0 * radius / C0) / dt)) + 4
     return Workload(f"sweep_L{level}_r{radius:g}_chi{chi:g}", level=level, radius=radius, f0=f0,
                     frac_bw=f_bw / f0, nt=nt, grid=grid, near_lambda=0.3, beta=0.2)
+
+
+# plate sweep (ET-AIM only, the EFIE): squares of 1-8 m at the sweep's bands,
+# edge about 10 cm (lambda_min / 10 at 300 MHz), grid spacing about 9 cm
+PLATE_SWEEP_SIZES = ((1.0, 16), (2.0, 24), (4.0, 48), (8.0, 96))
+
+
+def plate_sweep_workload(size: float, grid: int, chi: float) -> Workload:
+    """Plate of the sweep at one size and bandwidth: beta = 1/5, near zone
+    0.3 lambda_c, normal incidence along -z, x-polarised; the march long
+    enough for the pulse and one crossing of the plate's diagonal."""
+    f_bw = SWEEP_F_MAX / chi
+    f0 = SWEEP_F_MAX - f_bw
+    sigma = 3.0 / (2.0 * math.pi * f_bw)
+    dt = 0.2 / f_bw
+    nt = int(math.ceil((16.0 * sigma + math.sqrt(2.0) * size / C0) / dt)) + 4
+    wl = Workload(f"plate_sweep_{size:g}m_chi{chi:g}", level=0, radius=0.0, f0=f0, frac_bw=f_bw / f0, nt=nt,
+                  grid=(grid, grid, 8), near_lambda=0.3, beta=0.2, plate_size=size)
+    # the mesh edge follows the band's top, not the centre: lambda_min / 10 at 300 MHz
+    wl.extra["edge"] = C0 / SWEEP_F_MAX / 10.0
+    return wl
