@@ -203,19 +203,28 @@ def roofline_record(dom, d, info, batch, traffic):
             "bytes_per_launch": bytes_launch, "avg_launch_ms": avg_ms, "launches": d["launches"]}
 
 
-def sweep(torch, W, FP64, alpha=1.0, basis=0):
-    """The ET-AIM size and bandwidth sweep of spheres (the trends of the
-    paper's Figs. 2-3 without the comparison methods): every size at
-    chi = 3 and 100, every chi at the smallest and the level-4 size; per
+def sweep(torch, W, FP64, alpha=1.0, basis=0, plates=False):
+    """The ET-AIM size and bandwidth sweep of spheres, or of square plates
+    (the trends of the paper's Figs. 2-3 without the comparison methods):
+    every size at chi = 3 and 100, every chi at the smallest and a middle
+    size; per
     point the whole march of one incidence along -z in FP64 (GMRES tol 1e-6,
     near-zone approximate inverse), its right-hand-side, solve and commit
     time per step, iterations per step, N_t, N_g and M_n."""
     from paper_1408_7060_amd._lib import F_CONTINUE_ON_NOCONV
-    pts = [(L, a, g, chi) for (L, a, g) in W.SWEEP_SIZES for chi in (3, 100)]
-    pts += [(L, a, g, chi) for (L, a, g) in (W.SWEEP_SIZES[0], W.SWEEP_SIZES[2]) for chi in (10, 30)]
+    if plates:
+        pts = [(size, g, chi) for (size, g) in W.PLATE_SWEEP_SIZES for chi in (3, 100)]
+        pts += [(size, g, chi) for (size, g) in (W.PLATE_SWEEP_SIZES[0], W.PLATE_SWEEP_SIZES[2]) for chi in (10, 30)]
+        mk = W.plate_sweep_workload
+    else:
+        pts = [(L, a, g, chi) for (L, a, g) in W.SWEEP_SIZES for chi in (3, 100)]
+        pts += [(L, a, g, chi) for (L, a, g) in (W.SWEEP_SIZES[0], W.SWEEP_SIZES[2]) for chi in (10, 30)]
+        mk = W.sweep_workload
     torch.cuda.set_device(0)
-    for (L, a, g, chi) in pts:
-        wl = W.sweep_workload(L, a, g, chi)
+    for pt in pts:
+        chi = pt[-1]
+        wl = mk(*pt)
+        g = wl.grid
         t = time.perf_counter()
         P = make_problem(wl, FP64, 1, wl.nt, 1e-6, flags=F_CONTINUE_ON_NOCONV, alpha=alpha, basis=basis)
         setup_s = time.perf_counter() - t
@@ -274,6 +283,8 @@ def main():
                          "line per point")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="first copy this many MiB device-to-device (counter calibration)")
+    ap.add_argument("--plates", action="store_true",
+                    help="--sweep only: square plates of 1-8 m (the EFIE, as the paper's plates) instead of spheres")
     ap.add_argument("--blif", action="store_true",
                     help="--sweep only: the band-limited interpolatory basis (M = 3, extrapolation from 3 samples "
                          "fitted at 6 frequencies) instead of the CPPIF")
@@ -290,7 +301,7 @@ def main():
     import workloads as W
     from paper_1408_7060_amd import FP32, FP64
     if args.sweep:
-        return sweep(torch, W, FP64, args.alpha, 1 if args.blif else 0)
+        return sweep(torch, W, FP64, args.alpha, 1 if args.blif else 0, args.plates)
     from paper_1408_7060_amd._lib import F_CONTINUE_ON_NOCONV, F_GRAPH, F_IMPLICIT_STOP, F_RESIDUAL_CHECK
     # the FP64 residual check of eq. (5) every 16 steps is part of the precision form
     fl = F_CONTINUE_ON_NOCONV | F_RESIDUAL_CHECK | (0 if args.true_residual else F_IMPLICIT_STOP)
