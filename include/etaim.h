@@ -337,8 +337,30 @@ int etaim_adjoint_march(etaim_ctx *ctx, const void *S, void *Lambda, etaim_stats
 #define ETAIM_K_YZ_COMMIT 5   /* forward 2-D FFT into the history ring */
 #define ETAIM_K_KRYLOV 6      /* GMRES vector kernels */
 #define ETAIM_K_RING_FAR 7    /* time-block pass over the history ring (the terms a block's steps
-                                 take from history older than the block, once per block) */
+                                 take from history older than the block, once per block; with
+                                 the multilevel delay mode, each level's pass) */
 #define ETAIM_K_COUNT 8
+
+/* Delayed-field algorithm (the right-hand side of eq. (5), evaluated with
+ * blocked space-time transforms, Sec. 4; its O(log^2 N_g) temporal cost,
+ * Sec. 1 and Sec. 4).  mode 0 (default): the k-space temporal sum over the
+ * stored spectra, in time blocks of etaim_tuning.delay_block steps.  mode 1:
+ * multilevel time blocks: the lags 1..2 are summed at every step; the lags
+ * [3 * 2^k, 6 * 2^k), k = 0..4, form level k, whose share of the next
+ * 3 * 2^k steps' sums is computed once those steps' last block of history is
+ * stored, as a length-6 * 2^k temporal DFT convolution per spectrum point
+ * (overlap-save) added to a ring of per-step accumulators; equal to mode 0
+ * up to rounding.  Mode 1 is taken by the register (yz_engine 1, 2) and
+ * line-pass (3) engines in eager steps (whole-step graphs are not replayed
+ * while it is set; the LDS plane engine keeps the direct sum); it allocates
+ * (3 * 2^K + 3) spectrum slots of accumulators and the level tables on first
+ * use (K = the top level).  Changing the mode invalidates derived history
+ * sums, not the history.  Errors: EINVAL (mode not 0 or 1), EUNSUPPORTED
+ * (mode 1 with ETAIM_CFIE, or N_g > 95). */
+int etaim_set_delay_mode(etaim_ctx *ctx, int32_t mode);
+
+/* Current delay mode (host out). */
+int etaim_get_delay_mode(const etaim_ctx *ctx, int32_t *mode);
 
 /* Turn per-class kernel tracing on (1) or off (0); turning it on clears the
  * counters.  Tracing adds two event records per launch. */

@@ -199,6 +199,16 @@ class Problem:
             mask |= 1 << _lib.KERNEL_CLASSES.index(name)
         _lib.check(_lib.load().etaim_set_profiling_mask(self._h, mask if on else 0))
 
+    def set_delay_mode(self, mode: int):
+        """Delayed-field algorithm: 0 the k-space temporal sum in time blocks,
+        1 multilevel time blocks with temporal DFT convolutions."""
+        _lib.check(_lib.load().etaim_set_delay_mode(self._h, int(mode)))
+
+    def delay_mode(self) -> int:
+        v = ctypes.c_int32()
+        _lib.check(_lib.load().etaim_get_delay_mode(self._h, ctypes.byref(v)))
+        return v.value
+
     def kernel_stats(self) -> dict:
         out = {}
         lib = _lib.load()

@@ -84,6 +84,8 @@ SIGNATURES = {
                                  POINTER(c_double)]),
     "etaim_set_profiling": (c_int32, [c_void_p, c_int32]),
     "etaim_set_profiling_mask": (c_int32, [c_void_p, c_uint32]),
+    "etaim_set_delay_mode": (c_int32, [c_void_p, c_int32]),
+    "etaim_get_delay_mode": (c_int32, [c_void_p, POINTER(c_int32)]),
     "etaim_kernel_stats": (c_int32, [c_void_p, c_int32, POINTER(c_double), POINTER(c_double), POINTER(c_int64)]),
     "etaim_autotune": (c_int32, [c_void_p, c_int32, c_char_p, POINTER(Tuning)]),
     "etaim_get_tuning": (c_int32, [c_void_p, POINTER(Tuning)]),

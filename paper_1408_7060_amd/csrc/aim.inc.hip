@@ -1288,6 +1288,139 @@ __global__ void __launch_bounds__(256) k_ring_far3(const cplx<R>* __restrict__ r
     }
 }
 
+// ---------------------------------------------------------------------------
+// Multilevel time blocks of the delayed field: the temporal direction of the
+// blocked space-time transforms that evaluate the right-hand side of eq. (5)
+// (Sec. 4).  The lags m >= kMlBase of the history sum are split into levels
+// k = 0, 1, ... holding the lags [S_k, 2 S_k), S_k = kMlBase 2^k; the lags
+// below kMlBase are summed directly at each step.  Once steps e - S_k + 1
+// .. e are in the ring (e + 1 a multiple of S_k), level k forms its share of
+// the sums of the next S_k steps,
+//   acc[e + 1 + t] += sum_{u=0}^{S_k-1} G_{S_k+u} s_{e+1+t-S_k-u},  t < S_k,
+// as the valid half of a length-2S_k circular convolution (overlap-save) of
+// the window s_{e-2S_k+1 .. e} with the zero-padded lag segment: a forward
+// register DFT of the window, the product with the segment's DFT (set up
+// once, 1/(2 S_k) folded in), an inverse DFT.  Each level reads 2 of its
+// window's spectra per step and updates 2 accumulator slots per step, so a
+// step moves O(log N_g) spectra and spends O(log^2 N_g) flops per point
+// instead of N_g of each.  Window steps below 0, or older than the ring
+// (e - h >= ng: they meet only lags beyond ng), enter as zeros.  The
+// accumulator ring has na slots (step l in slot l mod na); the level-0 pass
+// also clears the slots of the steps e-2..e that the sums have consumed.
+constexpr int kMlBase = 3, kMlLevels = 5;  // S = 3, 6, 12, 24, 48: lags up to 95
+__host__ __device__ constexpr int ml_s(int k) { return kMlBase << k; }
+// first of level k's 2 S_k segment spectra in the level table
+__host__ __device__ constexpr int ml_off(int k) { return k == 0 ? 0 : ml_off(k - 1) + 2 * ml_s(k - 1); }
+
+template <typename R, int M>
+__device__ __forceinline__ void ml_dft(cplx<R> (&u)[M], bool inverse) {
+    if constexpr (M == 96) {
+        // two interleaved 48-point transforms and one radix-2 stage
+        cplx<R> ev[48], od[48];
+#pragma unroll
+        for (int n = 0; n < 48; ++n) {
+            ev[n] = u[2 * n];
+            od[n] = u[2 * n + 1];
+        }
+        dft_small<R, 48>(ev, inverse);
+        dft_small<R, 48>(od, inverse);
+#pragma unroll
+        for (int k = 0; k < 48; ++k) {
+            const cplx<R> t = tw96_mul<R>(od[k], k, inverse);
+            u[k] = ev[k] + t;
+            u[k + 48] = cplx<R>{ev[k].x - t.x, ev[k].y - t.y};
+        }
+    } else {
+        dft_small<R, M>(u, inverse);
+    }
+}
+
+// folded Green-table index of spectrum point `off` of a ring slot: plain
+// slots [bc][kx][kz][ky] (QN = 0) or parity quadrants [bc][kx][quadrant
+// rows] of a 2QN x 2QN plane (QN = N of the register engines)
+template <int QN>
+__device__ __forceinline__ size_t ml_gidx(size_t off, const GridDims& g) {
+    const int Lx = g.L[0], gx = g.N[0] + 1;
+    if constexpr (QN == 0) {
+        const int Ly = g.L[1], Lz = g.L[2];
+        const size_t plane = (size_t)Ly * Lz, pl = off / plane;
+        const int r = (int)(off - pl * plane), kz = r / Ly, ky = r - kz * Ly;
+        const int kx = (int)(pl % Lx), c = (int)((pl / Lx) & 3);
+        const int gy = g.N[1] + 1, gz = g.N[2] + 1;
+        return (((size_t)(c == 3 ? 1 : 0) * gx + fold(kx, Lx)) * gz + fold(kz, Lz)) * gy + fold(ky, Ly);
+    } else {
+        constexpr int NN = QN * QN, PP = 4 * NN, gg = QN + 1;
+        const size_t pl = off / PP;
+        const int e = (int)(off - pl * PP), qq = e / NN, rr = e - qq * NN;
+        const int kx = (int)(pl % Lx), c = (int)((pl / Lx) & 3);
+        return ((size_t)(c == 3 ? 1 : 0) * gx + fold(kx, Lx)) * (size_t)(gg * gg) +
+               fold(2 * (rr / QN) + (qq >> 1), 2 * QN) * gg + fold(2 * (rr % QN) + (qq & 1), 2 * QN);
+    }
+}
+
+// One level's pass at step e over one spectrum point per thread (slot =
+// points of a ring slot, gstride = folded points per lag of the tables);
+// sums of steps below lo are not written (a rebuild from the ring at step lo
+// passes its levels' last blocks, whose earlier steps are already consumed).
+// conj_g: the sum with conj(G) (adjoint march), as conj of the sum with G
+// over the conjugated history.
+template <typename R, int S, int QN>
+__global__ void __launch_bounds__(256) k_ml_level(const cplx<R>* __restrict__ ring, const cplx<R>* __restrict__ gam,
+                                                  cplx<R>* __restrict__ acc, GridDims g, size_t slot, size_t gstride,
+                                                  int ng, int e, int na, int conj_g, int clear, int lo) {
+    constexpr int M = 2 * S;
+    const size_t off = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (off >= slot) return;
+    const size_t gi = ml_gidx<QN>(off, g);
+    const R sg = conj_g ? R(-1) : R(1);
+    cplx<R> u[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        const int h = e - M + 1 + j;
+        cplx<R> v{0, 0};
+        if (h >= 0 && e - h < ng) v = ring[(size_t)(h % ng) * slot + off];
+        u[j] = cplx<R>{v.x, sg * v.y};
+    }
+    ml_dft<R, M>(u, false);
+#pragma unroll
+    for (int w = 0; w < M; ++w) u[w] = cmul_fma(u[w], gam[(size_t)w * gstride + gi]);
+    ml_dft<R, M>(u, true);
+#pragma unroll
+    for (int t = 0; t < S; ++t) {
+        if (e + 1 + t < lo) continue;
+        cplx<R>* a = acc + (size_t)((e + 1 + t) % na) * slot + off;
+        const cplx<R> o = *a;
+        *a = cplx<R>{o.x + u[S + t].x, o.y + sg * u[S + t].y};
+    }
+    if (clear)
+#pragma unroll
+        for (int t = 0; t < kMlBase; ++t)
+            if (e - t >= 0) acc[(size_t)((e - t) % na) * slot + off] = cplx<R>{0, 0};
+}
+
+// The level tables: gam[ml_off(k) + w][q] = (1/M) sum_{u<S} G_{S+u}[q]
+// exp(-2 pi i w u / M), M = 2 S = 2 S_k, for every folded point q, with
+// G_m = 0 beyond m = ng (FP64 arithmetic on the FP64 Green table).
+template <typename R>
+__global__ void k_ml_gamma(const zd* __restrict__ G, cplx<R>* __restrict__ gam, size_t gstride, int ng, int nlev) {
+    const size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (q >= gstride) return;
+    for (int k = 0; k < nlev; ++k) {
+        const int S = ml_s(k), M = 2 * S;
+        for (int w = 0; w < M; ++w) {
+            double re = 0, im = 0;
+            for (int u = 0; u < S && S + u <= ng; ++u) {
+                double sn, cs;
+                sincospi(-2.0 * (double)((w * u) % M) / (double)M, &sn, &cs);
+                const zd v = G[(size_t)(S + u) * gstride + q];
+                re += v.x * cs - v.y * sn;
+                im += v.x * sn + v.y * cs;
+            }
+            gam[(size_t)(ml_off(k) + w) * gstride + q] = cplx<R>{(R)(re / M), (R)(im / M)};
+        }
+    }
+}
+
 template <typename R>
 __device__ __forceinline__ R wave_sum(R v) {
 #pragma unroll

@@ -120,6 +120,12 @@ struct etaim_ctx {
     int delay_block = 6, far_slots = 0, far_r0 = -1;
     int check_cols = 0;  // FP64 companion: history steps transformed together
     void* far = nullptr;
+    // multilevel time blocks of the delayed field (delay_mode 1): level tables
+    // [ml_off(ml_levels)][2 gfold], accumulator ring [ml_na][ring slot];
+    // ml_step: the step whose sum the accumulators hold complete (-1: rebuild
+    // them from the ring), ml_conj: built with conj(G)
+    int delay_mode = 0, ml_levels = 0, ml_na = 0, ml_step = -1, ml_conj = 0;
+    void *ml_gam = nullptr, *ml_acc = nullptr;
     int* flag_h = nullptr;
     double* res_h = nullptr;  // pinned: per-column residuals [B], then per-column norms [B]
     int* pnext = nullptr;     // device: extrapolation order chosen for the next step
@@ -235,7 +241,11 @@ struct PassSwap {
 };
 
 // the block whose time-block sums both passes hold (-1: none)
-inline void set_far_r0(etaim_ctx* c, int r0) { c->far_r0 = c->farH_r0 = r0; }
+// (-1 also invalidates the multilevel accumulators: the history changed)
+inline void set_far_r0(etaim_ctx* c, int r0) {
+    c->far_r0 = c->farH_r0 = r0;
+    if (r0 < 0) c->ml_step = -1;
+}
 
 // Tracing: an event pair around each launch of a class (when enabled).  A
 // class of one kernel passes the pair to the launch itself (launch_timed):
@@ -717,6 +727,99 @@ struct Ops {
         c->far_slots = pb;
         return ETAIM_OK;
     }
+    // multilevel time blocks (delay_mode 1): eager steps of the EFIE on the
+    // register and line-pass engines, N_g within the levels' reach
+    static bool ml_on(const etaim_ctx* c, bool graph) {
+        return c->delay_mode == 1 && !graph && c->yz_engine >= 1 && !c->st.cfie && c->st.ng >= kMlBase &&
+               c->st.ng < 2 * ml_s(kMlLevels - 1);
+    }
+    // level tables from the FP64 Green spectra and the accumulator ring
+    static int ml_setup(etaim_ctx* c) {
+        if (c->ml_acc) return ETAIM_OK;
+        const int ng = c->st.ng;
+        int nlev = 0;
+        while (nlev < kMlLevels && ml_s(nlev) <= ng) ++nlev;
+        const size_t gs = 2 * c->gfold, slot = (size_t)4 * c->B * c->Np;
+        const int na = ml_s(nlev - 1) + kMlBase;
+        cplx<R>* gam = nullptr;
+        cplx<R>* acc = nullptr;
+        CHK(c->alloc(gam, (size_t)ml_off(nlev) * gs));
+        hipLaunchKernelGGL(k_ml_gamma<R>, dim3(blocks_for(gs)), dim3(256), 0, c->stream, c->ghat64, gam, gs, ng, nlev);
+        HIPCHK(hipGetLastError());
+        CHK(c->alloc(acc, (size_t)na * slot));
+        c->ml_gam = gam;
+        c->ml_acc = acc;
+        c->ml_levels = nlev;
+        c->ml_na = na;
+        c->ml_step = -1;
+        return ETAIM_OK;
+    }
+    // level k's pass at step e (clear: also zero the consumed slots e-2..e;
+    // sums of steps below lo are not written)
+    static int ml_fire(etaim_ctx* c, int k, int e, int conj, int clear, int lo) {
+        const size_t slot = (size_t)4 * c->B * c->Np, gs = 2 * c->gfold;
+        const int S = ml_s(k);
+        const double s = sizeof(cplx<R>);
+        Trace t(c, ETAIM_K_RING_FAR, (2.0 * S + 2.0 * S) * slot * s + 2.0 * S * gs * s, true);
+        const dim3 grid((unsigned)((slot + 255) / 256));
+        const cplx<R>* rg = (const cplx<R>*)ring(c);
+        const cplx<R>* gm = (const cplx<R>*)c->ml_gam + (size_t)ml_off(k) * gs;
+        cplx<R>* acc = (cplx<R>*)c->ml_acc;
+        const GridDims& g = c->gd;
+        const int qn = c->yz_engine == 3 ? 0 : quad_n(c);
+#define ETAIM_ML(SS, QQ)                                                                                         \
+    launch_timed(t, k_ml_level<R, SS, QQ>, grid, dim3(256), 0, c->stream, rg, gm, acc, g, slot, gs, c->st.ng, e, \
+                 c->ml_na, conj, clear, lo)
+#define ETAIM_ML_Q(SS)                                                                                   \
+    switch (qn) {                                                                                        \
+        case 0: ETAIM_ML(SS, 0); break;                                                                  \
+        case 16: ETAIM_ML(SS, 16); break;                                                                \
+        case 24: ETAIM_ML(SS, 24); break;                                                                \
+        case 48: ETAIM_ML(SS, 48); break;                                                                \
+        default: return fail(ETAIM_EUNSUPPORTED, "multilevel time blocks: no slot layout for this engine"); \
+    }
+        switch (k) {
+            case 0: ETAIM_ML_Q(ml_s(0)) break;
+            case 1: ETAIM_ML_Q(ml_s(1)) break;
+            case 2: ETAIM_ML_Q(ml_s(2)) break;
+            case 3: ETAIM_ML_Q(ml_s(3)) break;
+            case 4: ETAIM_ML_Q(ml_s(4)) break;
+            default: return fail(ETAIM_EINVAL, "multilevel time blocks: level out of range");
+        }
+#undef ETAIM_ML_Q
+#undef ETAIM_ML
+        HIPCHK(hipGetLastError());
+        return ETAIM_OK;
+    }
+    // bring the accumulators to step cur: the passes of the blocks that end
+    // at cur - 1 after a step cur - 1, else a rebuild from the ring (every
+    // level's last completed block before cur)
+    static int ml_advance(etaim_ctx* c, int cur, int conj) {
+        CHK(ml_setup(c));
+        if (c->ml_step >= 0 && c->ml_conj == conj) {
+            if (c->ml_step == cur) return ETAIM_OK;
+            if (c->ml_step == cur - 1) {
+                for (int k = 0; k < c->ml_levels; ++k)
+                    if (cur % ml_s(k) == 0) CHK(ml_fire(c, k, cur - 1, conj, k == 0 ? 1 : 0, 0));
+                c->ml_step = cur;
+                return ETAIM_OK;
+            }
+        }
+        // in the order the step-by-step passes would have run them (by step,
+        // then by level), so that the sums round as they do in a march
+        const size_t slot = (size_t)4 * c->B * c->Np;
+        HIPCHK(hipMemsetAsync(c->ml_acc, 0, (size_t)c->ml_na * slot * sizeof(cplx<R>), c->stream));
+        std::vector<std::pair<int, int>> order;
+        for (int k = 0; k < c->ml_levels; ++k) {
+            const int e = ml_s(k) * (cur / ml_s(k)) - 1;
+            if (e >= 0) order.emplace_back(e, k);
+        }
+        std::sort(order.begin(), order.end());
+        for (const auto& ek : order) CHK(ml_fire(c, ek.second, ek.first, conj, 0, cur));
+        c->ml_step = cur;
+        c->ml_conj = conj;
+        return ETAIM_OK;
+    }
     static int delayed(etaim_ctx* c, int cur, const zd* V, zd* rhs, int conj, StepRef sr = {}, int graph_far = 0) {
         if (c->st.cfie && conj) return fail(ETAIM_EUNSUPPORTED, "the CFIE's adjoint march is not built");
         CHK(delayed_pass(c, cur, V, rhs, conj, sr, graph_far, 1));
@@ -737,23 +840,31 @@ struct Ops {
         // older than r0 (m > j) are summed for the whole block at its first step, the
         // j terms of the block's own steps at the step itself
         const int pb = c->delay_block;
-        const bool blocked = blocks_on(c) && cur >= 1;
+        // multilevel time blocks: lags below kMlBase summed here, the rest
+        // from the step's accumulator slot
+        const bool ml = ml_on(c, graph) && cur >= 1;
+        const bool blocked = !ml && blocks_on(c) && cur >= 1;
         const int r0 = blocked ? cur - (cur - 1) % pb : 0;
         const bool far_pass = graph ? (blocked && graph_far != 0) : (blocked && c->far_r0 != r0);
         if (graph && blocked && (!c->far || c->far_slots < pb))
             return fail(ETAIM_EUNSUPPORTED, "whole-step graph: the time-block sums are not allocated");
-        const int nmx = blocked ? std::min(cur - r0, ng) : nm;
+        const int nmx = ml ? std::min(nm, kMlBase - 1) : blocked ? std::min(cur - r0, ng) : nm;
+        const cplx<R>* Fml = nullptr;
+        if (ml) {
+            CHK(ml_advance(c, cur, conj));
+            Fml = (const cplx<R>*)c->ml_acc + (size_t)(cur % c->ml_na) * 4 * c->B * c->Np;
+        }
         {
             const double s = sizeof(cplx<R>), slot_b = 4.0 * c->B * c->Np * s, green_b = 2.0 * c->gfold * s;
             double bytes = nmx * (slot_b + green_b) + 4.0 * c->B * g.L[0] * g.N[2] * g.N[1] * s;
-            if (blocked) bytes += slot_b;
+            if (blocked || ml) bytes += slot_b;
             if (c->yz_engine == 3) {
                 // the sum over the history into S (from the step's block sum with
                 // time blocks), then the inverse z and y passes
                 if (graph) return fail(ETAIM_EUNSUPPORTED, "whole-step graph: needs the register plane kernels");
                 CHK(ensure_S(c));
                 const size_t slot = (size_t)4 * c->B * c->Np;
-                const cplx<R>* Fj = nullptr;
+                const cplx<R>* Fj = Fml;
                 if (blocked) {
                     CHK(ensure_far(c, pb));
                     if (far_pass) {
@@ -786,7 +897,7 @@ struct Ops {
                 CHK(ylines_inv(c, nullptr));
             } else if (c->yz_engine >= 1) {
                 const size_t slot = (size_t)4 * c->B * c->Np;
-                const cplx<R>* Fj = nullptr;
+                const cplx<R>* Fj = Fml;
                 if (blocked) {
                     if (!graph) CHK(ensure_far(c, pb));
                     if (far_pass) {
@@ -1634,7 +1745,7 @@ int march_impl(etaim_ctx* c, const zd* V, zd* I, etaim_stats* st, bool adjoint, 
     };
     // whole-step graph replays: forward marches with the estimate stop, the
     // register engines, no tracing and no per-step growth check
-    const bool graph_mode = !adjoint && c->step_graph && !c->prof && !eager_detect &&
+    const bool graph_mode = !adjoint && c->step_graph && c->delay_mode == 0 && !c->prof && !eager_detect &&
                             (c->prm.flags & ETAIM_F_IMPLICIT_STOP) && c->yz_engine == 2 && c->x_engine == 1 &&
                             xline_n(c) > 0 && quad_n(c) > 0;
     const bool blocked = Ops<R>::blocks_on(c);
@@ -2575,6 +2686,28 @@ int etaim_set_profiling_mask(etaim_ctx* c, uint32_t classes) {
     c->prof = classes != 0;
     if (c->prof)
         for (int i = 0; i < ETAIM_K_COUNT; ++i) c->k_ms[i] = c->k_bytes[i] = 0, c->k_n[i] = 0;
+    return ETAIM_OK;
+}
+
+int etaim_set_delay_mode(etaim_ctx* c, int32_t mode) {
+    CHK(check_ctx(c));
+    if (mode != 0 && mode != 1) return fail(ETAIM_EINVAL, "delay mode must be 0 or 1");
+    if (mode == 1 && c->st.cfie) return fail(ETAIM_EUNSUPPORTED, "multilevel time blocks: built for the EFIE only");
+    if (mode == 1 && c->st.ng >= 2 * ml_s(kMlLevels - 1))
+        return fail(ETAIM_EUNSUPPORTED, "multilevel time blocks reach lags up to " +
+                                            std::to_string(2 * ml_s(kMlLevels - 1) - 1) + ", N_g is " +
+                                            std::to_string(c->st.ng));
+    if (c->delay_mode != mode) {
+        c->delay_mode = mode;
+        set_far_r0(c, -1);
+    }
+    return ETAIM_OK;
+}
+
+int etaim_get_delay_mode(const etaim_ctx* c, int32_t* mode) {
+    CHK(check_ctx(c));
+    if (!mode) return fail(ETAIM_EINVAL, "null pointer");
+    *mode = c->delay_mode;
     return ETAIM_OK;
 }
 

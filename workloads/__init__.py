@@ -434,8 +434,18 @@ COMPOSITE_SMALL = Workload("composite6_250MHz", level=0, radius=0.0, f0=250e6, f
 PLATE_1M = Workload("plate_1m_300MHz", level=0, radius=0.0, f0=300e6, frac_bw=0.05, nt=80, grid=(16, 16, 8),
                     near_lambda=0.3, beta=0.2, plate_size=1.0)
 
+# long histories for the multilevel time blocks of the delayed field: the
+# level-4 sphere with N_g = 47 (levels of 3, 6, 12 and 24 steps, the top one
+# ending inside the history) and the level-2 sphere with N_g = 95 (all five
+# levels; its near zone spans the first 81 lags)
+SPHERE_L4_NG47 = Workload("sphere_L4_r1_600MHz_ng47", level=4, radius=1.0, f0=600e6, frac_bw=0.30,
+                          nt=200, grid=48, near_lambda=0.3, ng=47, rotate_seed=0)
+SPHERE_L2_NG95 = Workload("sphere_L2_r0.5_300MHz_ng95", level=2, radius=0.5, f0=300e6, frac_bw=0.20,
+                          nt=300, grid=16, near_lambda=0.3, ng=95)
+
 WORKLOADS = {w.name: w for w in (SPHERE_L2, SPHERE_L4, SPHERE_L4_BATCH, SPHERE_L4_ADJ, SPHERE_L3,
-                                 SPHERE_L2_NARROW, COMPOSITE, COMPOSITE_SMALL, PLATE_1M)}
+                                 SPHERE_L2_NARROW, COMPOSITE, COMPOSITE_SMALL, PLATE_1M, SPHERE_L4_NG47,
+                                 SPHERE_L2_NG95)}
 
 # size and bandwidth sweep of spheres (ET-AIM only): the band's top fixed at
 # f_max = 300 MHz while chi = f_max / f_bw varies (f_c = f_max - f_bw), and
