@@ -353,8 +353,8 @@ int etaim_adjoint_march(etaim_ctx *ctx, const void *S, void *Lambda, etaim_stats
  * up to rounding.  Mode 1 is taken by the register (yz_engine 1, 2) and
  * line-pass (3) engines in eager steps (whole-step graphs are not replayed
  * while it is set; the LDS plane engine keeps the direct sum); it allocates
- * (3 * 2^K + 3) spectrum slots of accumulators and the level tables on first
- * use (K = the top level).  Changing the mode invalidates derived history
+ * 3 * 2^K spectrum slots of accumulators and the level tables on first use
+ * (K = the top level).  Changing the mode invalidates derived history
  * sums, not the history.  Errors: EINVAL (mode not 0 or 1), EUNSUPPORTED
  * (mode 1 with ETAIM_CFIE, or N_g > 95). */
 int etaim_set_delay_mode(etaim_ctx *ctx, int32_t mode);

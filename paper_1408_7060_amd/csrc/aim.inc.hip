@@ -1300,14 +1300,15 @@ __global__ void __launch_bounds__(256) k_ring_far3(const cplx<R>* __restrict__ r
 // as the valid half of a length-2S_k circular convolution (overlap-save) of
 // the window s_{e-2S_k+1 .. e} with the zero-padded lag segment: a forward
 // register DFT of the window, the product with the segment's DFT (set up
-// once, 1/(2 S_k) folded in), an inverse DFT.  Each level reads 2 of its
-// window's spectra per step and updates 2 accumulator slots per step, so a
-// step moves O(log N_g) spectra and spends O(log^2 N_g) flops per point
-// instead of N_g of each.  Window steps below 0, or older than the ring
-// (e - h >= ng: they meet only lags beyond ng), enter as zeros.  The
-// accumulator ring has na slots (step l in slot l mod na); the level-0 pass
-// also clears the slots of the steps e-2..e that the sums have consumed.
+// once, 1/(2 S_k) folded in), an inverse DFT.  A step moves O(log N_g)
+// spectra and spends O(log^2 N_g) flops per point instead of N_g of each.
+// Window steps below 0, or older than the ring (e - h >= ng: they meet only
+// lags beyond ng), enter as zeros.  The accumulator ring has na = S_top
+// slots (step l in slot l mod na): the top level's pass is the first to
+// reach every step and writes its sums, the lower levels add theirs.
 constexpr int kMlBase = 3, kMlLevels = 5;  // S = 3, 6, 12, 24, 48: lags up to 95
+// levels passed together in one sweep (their windows nest), the rest alone
+constexpr int kMlFused = 3;
 __host__ __device__ constexpr int ml_s(int k) { return kMlBase << k; }
 // first of level k's 2 S_k segment spectra in the level table
 __host__ __device__ constexpr int ml_off(int k) { return k == 0 ? 0 : ml_off(k - 1) + 2 * ml_s(k - 1); }
@@ -1358,44 +1359,67 @@ __device__ __forceinline__ size_t ml_gidx(size_t off, const GridDims& g) {
     }
 }
 
-// One level's pass at step e over one spectrum point per thread (slot =
-// points of a ring slot, gstride = folded points per lag of the tables);
-// sums of steps below lo are not written (a rebuild from the ring at step lo
-// passes its levels' last blocks, whose earlier steps are already consumed).
-// conj_g: the sum with conj(G) (adjoint march), as conj of the sum with G
-// over the conjugated history.
-template <typename R, int S, int QN>
-__global__ void __launch_bounds__(256) k_ml_level(const cplx<R>* __restrict__ ring, const cplx<R>* __restrict__ gam,
-                                                  cplx<R>* __restrict__ acc, GridDims g, size_t slot, size_t gstride,
-                                                  int ng, int e, int na, int conj_g, int clear, int lo) {
-    constexpr int M = 2 * S;
+// level K's sums from the tail of the window (its own 2 S_K steps), added
+// into out[t], t < S_K; then the next level up to K1
+template <typename R, int K, int K1, int W, int S1>
+__device__ __forceinline__ void ml_levels(const cplx<R> (&win)[W], cplx<R> (&out)[S1], const cplx<R>* __restrict__ gam,
+                                          size_t gstride, size_t gi) {
+    constexpr int S = ml_s(K), M = 2 * S;
+    cplx<R> u[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) u[j] = win[W - M + j];
+    ml_dft<R, M>(u, false);
+#pragma unroll
+    for (int w = 0; w < M; ++w) u[w] = cmul_fma(u[w], gam[(size_t)(ml_off(K) + w) * gstride + gi]);
+    ml_dft<R, M>(u, true);
+#pragma unroll
+    for (int t = 0; t < S; ++t) out[t] += u[S + t];
+    if constexpr (K < K1) ml_levels<R, K + 1, K1, W, S1>(win, out, gam, gstride, gi);
+}
+
+// The passes of levels K0..K1 at step e in one sweep, one spectrum point per
+// thread (slot = points of a ring slot, gstride = folded points per lag of
+// the tables, gam = the level table): the window of the last 2 S_K1 spectra
+// serves every level, their sums are added in registers (K0 first) and the
+// accumulator slots of steps e + 1 .. e + S_K1 are updated once (first: the
+// top level is K1, whose sums start those slots).  Sums of steps below lo
+// are not written (a rebuild from the ring at step lo passes the levels'
+// last blocks, whose earlier steps are already consumed).  conj_g: the sum
+// with conj(G) (adjoint march), as conj of the sum with G over the
+// conjugated history.
+template <typename R, int K0, int K1, int QN>
+__global__ void __launch_bounds__(256) k_ml_pass(const cplx<R>* __restrict__ ring, const cplx<R>* __restrict__ gam,
+                                                 cplx<R>* __restrict__ acc, GridDims g, size_t slot, size_t gstride,
+                                                 int ng, int e, int na, int conj_g, int first, int lo) {
+    constexpr int S1 = ml_s(K1), W = 2 * S1;
     const size_t off = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
     if (off >= slot) return;
     const size_t gi = ml_gidx<QN>(off, g);
     const R sg = conj_g ? R(-1) : R(1);
-    cplx<R> u[M];
+    cplx<R> win[W];
 #pragma unroll
-    for (int j = 0; j < M; ++j) {
-        const int h = e - M + 1 + j;
+    for (int j = 0; j < W; ++j) {
+        const int h = e - W + 1 + j;
         cplx<R> v{0, 0};
         if (h >= 0 && e - h < ng) v = ring[(size_t)(h % ng) * slot + off];
-        u[j] = cplx<R>{v.x, sg * v.y};
+        win[j] = cplx<R>{v.x, sg * v.y};
     }
-    ml_dft<R, M>(u, false);
+    cplx<R> out[S1];
 #pragma unroll
-    for (int w = 0; w < M; ++w) u[w] = cmul_fma(u[w], gam[(size_t)w * gstride + gi]);
-    ml_dft<R, M>(u, true);
+    for (int t = 0; t < S1; ++t) out[t] = cplx<R>{0, 0};
+    ml_levels<R, K0, K1, W, S1>(win, out, gam, gstride, gi);
 #pragma unroll
-    for (int t = 0; t < S; ++t) {
+    for (int t = 0; t < S1; ++t) {
         if (e + 1 + t < lo) continue;
         cplx<R>* a = acc + (size_t)((e + 1 + t) % na) * slot + off;
-        const cplx<R> o = *a;
-        *a = cplx<R>{o.x + u[S + t].x, o.y + sg * u[S + t].y};
+        const cplx<R> v{out[t].x, sg * out[t].y};
+        if (first) {
+            *a = v;
+        } else {
+            const cplx<R> o = *a;
+            *a = cplx<R>{o.x + v.x, o.y + v.y};
+        }
     }
-    if (clear)
-#pragma unroll
-        for (int t = 0; t < kMlBase; ++t)
-            if (e - t >= 0) acc[(size_t)((e - t) % na) * slot + off] = cplx<R>{0, 0};
 }
 
 // The level tables: gam[ml_off(k) + w][q] = (1/M) sum_{u<S} G_{S+u}[q]

@@ -740,7 +740,7 @@ struct Ops {
         int nlev = 0;
         while (nlev < kMlLevels && ml_s(nlev) <= ng) ++nlev;
         const size_t gs = 2 * c->gfold, slot = (size_t)4 * c->B * c->Np;
-        const int na = ml_s(nlev - 1) + kMlBase;
+        const int na = ml_s(nlev - 1);
         cplx<R>* gam = nullptr;
         cplx<R>* acc = nullptr;
         CHK(c->alloc(gam, (size_t)ml_off(nlev) * gs));
@@ -754,68 +754,94 @@ struct Ops {
         c->ml_step = -1;
         return ETAIM_OK;
     }
-    // level k's pass at step e (clear: also zero the consumed slots e-2..e;
-    // sums of steps below lo are not written)
-    static int ml_fire(etaim_ctx* c, int k, int e, int conj, int clear, int lo) {
+    // the passes of levels k0..k1 at step e in one sweep (first: k1 is the
+    // top level, whose sums start the accumulator slots; sums of steps below
+    // lo are not written)
+    static int ml_pass(etaim_ctx* c, int k0, int k1, int e, int conj, int first, int lo) {
         const size_t slot = (size_t)4 * c->B * c->Np, gs = 2 * c->gfold;
-        const int S = ml_s(k);
-        const double s = sizeof(cplx<R>);
-        Trace t(c, ETAIM_K_RING_FAR, (2.0 * S + 2.0 * S) * slot * s + 2.0 * S * gs * s, true);
+        const double s = sizeof(cplx<R>), S1 = ml_s(k1);
+        double gam_b = 0;
+        for (int k = k0; k <= k1; ++k) gam_b += 2.0 * ml_s(k) * gs * s;
+        Trace t(c, ETAIM_K_RING_FAR, (2.0 * S1 + (first ? 1.0 : 2.0) * S1) * slot * s + gam_b, true);
         const dim3 grid((unsigned)((slot + 255) / 256));
         const cplx<R>* rg = (const cplx<R>*)ring(c);
-        const cplx<R>* gm = (const cplx<R>*)c->ml_gam + (size_t)ml_off(k) * gs;
+        const cplx<R>* gm = (const cplx<R>*)c->ml_gam;
         cplx<R>* acc = (cplx<R>*)c->ml_acc;
         const GridDims& g = c->gd;
         const int qn = c->yz_engine == 3 ? 0 : quad_n(c);
-#define ETAIM_ML(SS, QQ)                                                                                         \
-    launch_timed(t, k_ml_level<R, SS, QQ>, grid, dim3(256), 0, c->stream, rg, gm, acc, g, slot, gs, c->st.ng, e, \
-                 c->ml_na, conj, clear, lo)
-#define ETAIM_ML_Q(SS)                                                                                   \
+#define ETAIM_ML(K0, K1, QQ)                                                                                        \
+    launch_timed(t, k_ml_pass<R, K0, K1, QQ>, grid, dim3(256), 0, c->stream, rg, gm, acc, g, slot, gs, c->st.ng, e, \
+                 c->ml_na, conj, first, lo)
+#define ETAIM_ML_Q(K0, K1)                                                                               \
     switch (qn) {                                                                                        \
-        case 0: ETAIM_ML(SS, 0); break;                                                                  \
-        case 16: ETAIM_ML(SS, 16); break;                                                                \
-        case 24: ETAIM_ML(SS, 24); break;                                                                \
-        case 48: ETAIM_ML(SS, 48); break;                                                                \
+        case 0: ETAIM_ML(K0, K1, 0); break;                                                              \
+        case 16: ETAIM_ML(K0, K1, 16); break;                                                            \
+        case 24: ETAIM_ML(K0, K1, 24); break;                                                            \
+        case 48: ETAIM_ML(K0, K1, 48); break;                                                            \
         default: return fail(ETAIM_EUNSUPPORTED, "multilevel time blocks: no slot layout for this engine"); \
     }
-        switch (k) {
-            case 0: ETAIM_ML_Q(ml_s(0)) break;
-            case 1: ETAIM_ML_Q(ml_s(1)) break;
-            case 2: ETAIM_ML_Q(ml_s(2)) break;
-            case 3: ETAIM_ML_Q(ml_s(3)) break;
-            case 4: ETAIM_ML_Q(ml_s(4)) break;
-            default: return fail(ETAIM_EINVAL, "multilevel time blocks: level out of range");
+        static_assert(kMlFused == 3 && kMlLevels == 5, "the pass table below covers these levels");
+        const int key = 10 * k0 + k1;
+        switch (key) {
+            case 0: ETAIM_ML_Q(0, 0) break;
+            case 1: ETAIM_ML_Q(0, 1) break;
+            case 2: ETAIM_ML_Q(0, 2) break;
+            case 33: ETAIM_ML_Q(3, 3) break;
+            case 44: ETAIM_ML_Q(4, 4) break;
+            default: return fail(ETAIM_EINVAL, "multilevel time blocks: no pass for these levels");
         }
 #undef ETAIM_ML_Q
 #undef ETAIM_ML
         HIPCHK(hipGetLastError());
         return ETAIM_OK;
     }
+    // the passes due at step e (the levels k with S_k | e + 1 among `due`, a
+    // bit per level), in a fixed order: the top level first (it starts the
+    // slots it reaches), then the fused low levels 0..kt, then the other
+    // levels upwards; a march and a rebuild run the same passes in the same
+    // order, so their sums round alike
+    static int ml_event(etaim_ctx* c, int e, unsigned due, int conj, int lo) {
+        const int top = c->ml_levels - 1;
+        const bool top_due = (due >> top) & 1u;
+        int kt = -1;
+        for (int k = 0; k < std::min(kMlFused, c->ml_levels); ++k)
+            if ((due >> k) & 1u) kt = k;
+        if (top_due && top >= kMlFused) CHK(ml_pass(c, top, top, e, conj, 1, lo));
+        if (kt >= 0) CHK(ml_pass(c, 0, kt, e, conj, top_due && kt == top ? 1 : 0, lo));
+        for (int k = kMlFused; k < top; ++k)
+            if ((due >> k) & 1u) CHK(ml_pass(c, k, k, e, conj, 0, lo));
+        return ETAIM_OK;
+    }
     // bring the accumulators to step cur: the passes of the blocks that end
     // at cur - 1 after a step cur - 1, else a rebuild from the ring (every
-    // level's last completed block before cur)
+    // level's last completed block before cur, grouped by step)
     static int ml_advance(etaim_ctx* c, int cur, int conj) {
         CHK(ml_setup(c));
         if (c->ml_step >= 0 && c->ml_conj == conj) {
             if (c->ml_step == cur) return ETAIM_OK;
             if (c->ml_step == cur - 1) {
+                unsigned due = 0;
                 for (int k = 0; k < c->ml_levels; ++k)
-                    if (cur % ml_s(k) == 0) CHK(ml_fire(c, k, cur - 1, conj, k == 0 ? 1 : 0, 0));
+                    if (cur % ml_s(k) == 0) due |= 1u << k;
+                if (due) CHK(ml_event(c, cur - 1, due, conj, 0));
                 c->ml_step = cur;
                 return ETAIM_OK;
             }
         }
-        // in the order the step-by-step passes would have run them (by step,
-        // then by level), so that the sums round as they do in a march
+        // steps before the top level's first block (cur < S_top) start from
+        // these zeros, as they do in a march begun at step 0
         const size_t slot = (size_t)4 * c->B * c->Np;
         HIPCHK(hipMemsetAsync(c->ml_acc, 0, (size_t)c->ml_na * slot * sizeof(cplx<R>), c->stream));
-        std::vector<std::pair<int, int>> order;
-        for (int k = 0; k < c->ml_levels; ++k) {
+        // level k's last block ends at e_k = S_k floor(cur / S_k) - 1; the
+        // higher the level, the earlier (S_k divides S_{k+1})
+        for (int k = c->ml_levels - 1; k >= 0; --k) {
             const int e = ml_s(k) * (cur / ml_s(k)) - 1;
-            if (e >= 0) order.emplace_back(e, k);
+            if (e < 0 || (k + 1 < c->ml_levels && e == ml_s(k + 1) * (cur / ml_s(k + 1)) - 1)) continue;
+            unsigned due = 0;
+            for (int j = 0; j < c->ml_levels; ++j)
+                if (ml_s(j) * (cur / ml_s(j)) - 1 == e) due |= 1u << j;
+            CHK(ml_event(c, e, due, conj, cur));
         }
-        std::sort(order.begin(), order.end());
-        for (const auto& ek : order) CHK(ml_fire(c, ek.second, ek.first, conj, 0, cur));
         c->ml_step = cur;
         c->ml_conj = conj;
         return ETAIM_OK;
