@@ -355,8 +355,9 @@ int etaim_adjoint_march(etaim_ctx *ctx, const void *S, void *Lambda, etaim_stats
  * while it is set; the LDS plane engine keeps the direct sum); it allocates
  * 3 * 2^K spectrum slots of accumulators and the level tables on first use
  * (K = the top level).  Changing the mode invalidates derived history
- * sums, not the history.  Errors: EINVAL (mode not 0 or 1), EUNSUPPORTED
- * (mode 1 with ETAIM_CFIE, or N_g > 95). */
+ * sums, not the history.  With ETAIM_CFIE the MFIE pass keeps level tables
+ * and accumulators of its own.  Errors: EINVAL (mode not 0 or 1),
+ * EUNSUPPORTED (mode 1 with N_g > 95). */
 int etaim_set_delay_mode(etaim_ctx *ctx, int32_t mode);
 
 /* Current delay mode (host out). */

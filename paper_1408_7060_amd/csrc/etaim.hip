@@ -123,9 +123,10 @@ struct etaim_ctx {
     // multilevel time blocks of the delayed field (delay_mode 1): level tables
     // [ml_off(ml_levels)][2 gfold], accumulator ring [ml_na][ring slot];
     // ml_step: the step whose sum the accumulators hold complete (-1: rebuild
-    // them from the ring), ml_conj: built with conj(G)
-    int delay_mode = 0, ml_levels = 0, ml_na = 0, ml_step = -1, ml_conj = 0;
-    void *ml_gam = nullptr, *ml_acc = nullptr;
+    // them from the ring), ml_conj: built with conj(G); the *H copies belong
+    // to the CFIE's MFIE pass (PassSwap exchanges them)
+    int delay_mode = 0, ml_levels = 0, ml_na = 0, ml_step = -1, ml_conj = 0, ml_stepH = -1, ml_conjH = 0;
+    void *ml_gam = nullptr, *ml_acc = nullptr, *ml_gamH = nullptr, *ml_accH = nullptr;
     int* flag_h = nullptr;
     double* res_h = nullptr;  // pinned: per-column residuals [B], then per-column norms [B]
     int* pnext = nullptr;     // device: extrapolation order chosen for the next step
@@ -236,6 +237,10 @@ struct PassSwap {
         std::swap(c->far, c->farH);
         std::swap(c->far_slots, c->farH_slots);
         std::swap(c->far_r0, c->farH_r0);
+        std::swap(c->ml_gam, c->ml_gamH);
+        std::swap(c->ml_acc, c->ml_accH);
+        std::swap(c->ml_step, c->ml_stepH);
+        std::swap(c->ml_conj, c->ml_conjH);
         c->pass ^= 1;
     }
 };
@@ -244,7 +249,7 @@ struct PassSwap {
 // (-1 also invalidates the multilevel accumulators: the history changed)
 inline void set_far_r0(etaim_ctx* c, int r0) {
     c->far_r0 = c->farH_r0 = r0;
-    if (r0 < 0) c->ml_step = -1;
+    if (r0 < 0) c->ml_step = c->ml_stepH = -1;
 }
 
 // Tracing: an event pair around each launch of a class (when enabled).  A
@@ -727,13 +732,14 @@ struct Ops {
         c->far_slots = pb;
         return ETAIM_OK;
     }
-    // multilevel time blocks (delay_mode 1): eager steps of the EFIE on the
-    // register and line-pass engines, N_g within the levels' reach
+    // multilevel time blocks (delay_mode 1): eager steps on the register and
+    // line-pass engines, N_g within the levels' reach
     static bool ml_on(const etaim_ctx* c, bool graph) {
-        return c->delay_mode == 1 && !graph && c->yz_engine >= 1 && !c->st.cfie && c->st.ng >= kMlBase &&
+        return c->delay_mode == 1 && !graph && c->yz_engine >= 1 && c->st.ng >= kMlBase &&
                c->st.ng < 2 * ml_s(kMlLevels - 1);
     }
-    // level tables from the FP64 Green spectra and the accumulator ring
+    // level tables from the FP64 Green spectra (the MFIE's in the CFIE's
+    // second pass) and the accumulator ring
     static int ml_setup(etaim_ctx* c) {
         if (c->ml_acc) return ETAIM_OK;
         const int ng = c->st.ng;
@@ -744,7 +750,8 @@ struct Ops {
         cplx<R>* gam = nullptr;
         cplx<R>* acc = nullptr;
         CHK(c->alloc(gam, (size_t)ml_off(nlev) * gs));
-        hipLaunchKernelGGL(k_ml_gamma<R>, dim3(blocks_for(gs)), dim3(256), 0, c->stream, c->ghat64, gam, gs, ng, nlev);
+        hipLaunchKernelGGL(k_ml_gamma<R>, dim3(blocks_for(gs)), dim3(256), 0, c->stream,
+                           c->pass ? c->ghatH64 : c->ghat64, gam, gs, ng, nlev);
         HIPCHK(hipGetLastError());
         CHK(c->alloc(acc, (size_t)na * slot));
         c->ml_gam = gam;
@@ -2718,7 +2725,6 @@ int etaim_set_profiling_mask(etaim_ctx* c, uint32_t classes) {
 int etaim_set_delay_mode(etaim_ctx* c, int32_t mode) {
     CHK(check_ctx(c));
     if (mode != 0 && mode != 1) return fail(ETAIM_EINVAL, "delay mode must be 0 or 1");
-    if (mode == 1 && c->st.cfie) return fail(ETAIM_EUNSUPPORTED, "multilevel time blocks: built for the EFIE only");
     if (mode == 1 && c->st.ng >= 2 * ml_s(kMlLevels - 1))
         return fail(ETAIM_EUNSUPPORTED, "multilevel time blocks reach lags up to " +
                                             std::to_string(2 * ml_s(kMlLevels - 1) - 1) + ", N_g is " +

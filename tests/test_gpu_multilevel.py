@@ -20,6 +20,7 @@ per-step accumulators and its clearing), which the march tests compare
 with the oracle-pinned direct sum of delay mode 0 on the same problem, also
 after a resume from a saved state (the accumulators are rebuilt from the
 ring) and for the adjoint march (conj(G))."""
+import dataclasses
 import functools
 import sys
 
@@ -28,7 +29,7 @@ import pytest
 
 import workloads as W
 from gpu_cases import gpu_problem, params_of, rel
-from oracle import aim, excitation, geometry, kernels, zfill
+from oracle import aim, excitation, geometry, kernels, mfie, zfill
 
 pytestmark = pytest.mark.gpu
 
@@ -63,27 +64,30 @@ def _with_engine(P, yz, xe):
 
 
 @functools.lru_cache(maxsize=None)
-def _oracle_rows(name, nrows):
-    """(AIM, params, sampled rows, near selection, exact near values of those rows)."""
+def _oracle_rows(name, nrows, alpha=1.0):
+    """(AIM, params, sampled rows, near selection, exact near values of those
+    rows); alpha < 1: the CFIE."""
     wl = W.WORKLOADS[name]
     p = params_of(wl)
     s = geometry.Surface(p["xyz"], p["tri"], p["rwg"])
-    A = aim.AIM(s, wl.grid, p["d_near"], p["dt"], wl.f0, p["ng"])
+    A = aim.AIM(s, wl.grid, p["d_near"], p["dt"], wl.f0, p["ng"], alpha=alpha)
     rows = np.sort(W.rng(0, 7).choice(s.ns, nrows, replace=False))
 
     def exact(r, c, ms):
+        if alpha != 1.0:
+            return mfie.cfie_pairs(s, r, c, ms, p["dt"], wl.f0, alpha)
         return zfill.assemble_pairs(s, r, c, [kernels.EnvelopeKernel(m, p["dt"], wl.f0) for m in ms])
 
     sel, vals = A.near_values_rows(exact, rows)
-    _say(f"oracle {name}: N_g {p['ng']}, M_n {A.mn}, rows {nrows}, near pairs {int(sel.sum())}")
+    _say(f"oracle {name}: N_g {p['ng']}, M_n {A.mn}, rows {nrows}, near pairs {int(sel.sum())}, alpha {alpha}")
     return A, p, rows, sel, vals
 
 
 @functools.lru_cache(maxsize=None)
-def _delayed_ref(name, nrows):
+def _delayed_ref(name, nrows, alpha=1.0):
     """History [N_g, 2, ns] (hist[m-1] = I_{l-m}) and the oracle's direct sum
     sum_{m=1}^{N_g} (Z^near_m + Z^FFT_m) hist[m-1] on the sampled rows."""
-    A, p, rows, sel, vals = _oracle_rows(name, nrows)
+    A, p, rows, sel, vals = _oracle_rows(name, nrows, alpha)
     ng = p["ng"]
     hist = W.complex_normal(71, (ng, 2, A.surf.ns))
     ref = []
@@ -120,6 +124,24 @@ def test_multilevel_delayed_field_matches_oracle(torch, name, nrows, prec, tol, 
     P.close()
 
 
+@pytest.mark.parametrize("engine", [(2, 1), (3, 1)], ids=["zlines", "lines"])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-5)], ids=["fp64", "fp32"])
+def test_multilevel_cfie_delayed_field_matches_oracle(torch, prec, tol, engine):
+    """The CFIE (alpha = 0.5, Sec. 2.1): the EFIE and MFIE passes each sum
+    their history with their own level tables and accumulators (N_g = 47,
+    level-4 sphere)."""
+    A, p, rows, sel, vals = _oracle_rows(L4.name, 48, 0.5)
+    hist, ref = _delayed_ref(L4.name, 48, 0.5)
+    P = gpu_problem(L4.name, precision=prec, batch=2, nt=8, alpha=0.5)
+    _with_engine(P, *engine)
+    P.set_delay_mode(1)
+    b = P.delayed_field(_dev(torch, hist)).cpu().numpy()[list(COLS)][:, rows]
+    e = rel(b, ref)
+    _say("multilevel CFIE delayed", engine, "fp32" if prec else "fp64", "rel", e)
+    assert e <= tol
+    P.close()
+
+
 def _excitation(name, nt, nb, seed):
     wl = W.WORKLOADS[name]
     p = params_of(wl)
@@ -129,9 +151,9 @@ def _excitation(name, nt, nb, seed):
     return excitation.excitation(s, nt, p["dt"], kh, pp, wl.sigma, wl.td, wl.f0)
 
 
-def _march(torch, V, mode, engine, prec=0, tol=1e-13, nt=None):
+def _march(torch, V, mode, engine, prec=0, tol=1e-13, nt=None, alpha=1.0):
     P = gpu_problem(L2.name, precision=prec, tol=tol, batch=V.shape[1], nt=nt or V.shape[0],
-                    flags=F_CONTINUE_ON_NOCONV)
+                    flags=F_CONTINUE_ON_NOCONV, alpha=alpha)
     _with_engine(P, *engine)
     P.set_delay_mode(mode)
     I, st = P.march(_dev(torch, V))
@@ -156,6 +178,19 @@ def test_multilevel_march_equals_direct_sum(torch, engine):
     e32 = rel(I32, I0)
     _say("  fp32 multilevel vs fp64 direct", e32)
     assert e32 <= 1e-4
+
+
+def test_multilevel_cfie_march_equals_direct_sum(torch):
+    """The CFIE march with multilevel sums in both passes against the CFIE
+    march with the direct sum (N_g = 95, 150 steps)."""
+    nt = 150
+    V = _excitation(L2.name, nt, 1, 84)
+    I1, _ = _march(torch, V, 1, (2, 1), alpha=0.5)
+    I0, _ = _march(torch, V, 0, (2, 1), alpha=0.5)
+    e = rel(I1, I0)
+    _say("multilevel CFIE march rel to direct", e)
+    assert np.isfinite(I1).all()
+    assert e <= 1e-10
 
 
 def test_multilevel_resume_and_adjoint(torch):
@@ -198,15 +233,19 @@ def test_multilevel_resume_and_adjoint(torch):
 
 
 def test_delay_mode_errors(torch):
-    """Mode outside 0/1: EINVAL; the CFIE: EUNSUPPORTED."""
+    """Mode outside 0/1: EINVAL; N_g beyond the levels' reach (95): EUNSUPPORTED."""
     P = gpu_problem(W.SPHERE_L2.name, nt=4)
     with pytest.raises(Exception) as ei:
         P.set_delay_mode(2)
     assert ei.value.code == -1
     assert P.delay_mode() == 0
     P.close()
-    Q = gpu_problem(W.SPHERE_L2.name, nt=4, alpha=0.5)
+    wl = dataclasses.replace(W.SPHERE_L2, name="sphere_L2_r0.5_300MHz_ng96", ng=96, nt=4)
+    W.WORKLOADS[wl.name] = wl
+    Q = gpu_problem(wl.name, nt=4)
+    assert Q.info["ng"] == 96
     with pytest.raises(Exception) as ei:
         Q.set_delay_mode(1)
     assert ei.value.code == -7
+    assert Q.delay_mode() == 0
     Q.close()
