@@ -1359,6 +1359,31 @@ __device__ __forceinline__ size_t ml_gidx(size_t off, const GridDims& g) {
     }
 }
 
+// one complex value as an 8- or 16-byte vector, for streaming (non-temporal)
+// loads and stores
+template <typename R>
+struct CVec;
+template <>
+struct CVec<float> {
+    typedef float type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct CVec<double> {
+    typedef double type __attribute__((ext_vector_type(2)));
+};
+template <typename R>
+__device__ __forceinline__ cplx<R> nt_load(const cplx<R>* p) {
+    const typename CVec<R>::type v = __builtin_nontemporal_load(reinterpret_cast<const typename CVec<R>::type*>(p));
+    return cplx<R>{v[0], v[1]};
+}
+template <typename R>
+__device__ __forceinline__ void nt_store(cplx<R>* p, cplx<R> c) {
+    typename CVec<R>::type v;
+    v[0] = c.x;
+    v[1] = c.y;
+    __builtin_nontemporal_store(v, reinterpret_cast<typename CVec<R>::type*>(p));
+}
+
 // level K's sums from the tail of the window (its own 2 S_K steps), added
 // into out[t], t < S_K; then the next level up to K1
 template <typename R, int K, int K1, int W, int S1>
@@ -1380,9 +1405,9 @@ __device__ __forceinline__ void ml_levels(const cplx<R> (&win)[W], cplx<R> (&out
 // The passes of levels K0..K1 at step e in one sweep, one spectrum point per
 // thread (slot = points of a ring slot, gstride = folded points per lag of
 // the tables, gam = the level table): the window of the last 2 S_K1 spectra
-// serves every level, their sums are added in registers (K0 first) and the
-// accumulator slots of steps e + 1 .. e + S_K1 are updated once (first: the
-// top level is K1, whose sums start those slots).  Sums of steps below lo
+// serves every level, their sums are added in registers (K0 first) to the
+// accumulator slots of steps e + 1 .. e + S_K1, which are loaded with the
+// window (first: the top level is K1, whose sums start those slots).  Sums of steps below lo
 // are not written (a rebuild from the ring at step lo passes the levels'
 // last blocks, whose earlier steps are already consumed).  conj_g: the sum
 // with conj(G) (adjoint march), as conj of the sum with G over the
@@ -1401,25 +1426,22 @@ __global__ void __launch_bounds__(256) k_ml_pass(const cplx<R>* __restrict__ rin
     for (int j = 0; j < W; ++j) {
         const int h = e - W + 1 + j;
         cplx<R> v{0, 0};
-        if (h >= 0 && e - h < ng) v = ring[(size_t)(h % ng) * slot + off];
+        if (h >= 0 && e - h < ng) v = nt_load(ring + (size_t)(h % ng) * slot + off);
         win[j] = cplx<R>{v.x, sg * v.y};
     }
+    // the accumulators, conjugated with the window where conj_g is set
     cplx<R> out[S1];
 #pragma unroll
-    for (int t = 0; t < S1; ++t) out[t] = cplx<R>{0, 0};
+    for (int t = 0; t < S1; ++t) {
+        cplx<R> a{0, 0};
+        if (!first && e + 1 + t >= lo) a = nt_load(acc + (size_t)((e + 1 + t) % na) * slot + off);
+        out[t] = cplx<R>{a.x, sg * a.y};
+    }
     ml_levels<R, K0, K1, W, S1>(win, out, gam, gstride, gi);
 #pragma unroll
-    for (int t = 0; t < S1; ++t) {
-        if (e + 1 + t < lo) continue;
-        cplx<R>* a = acc + (size_t)((e + 1 + t) % na) * slot + off;
-        const cplx<R> v{out[t].x, sg * out[t].y};
-        if (first) {
-            *a = v;
-        } else {
-            const cplx<R> o = *a;
-            *a = cplx<R>{o.x + v.x, o.y + v.y};
-        }
-    }
+    for (int t = 0; t < S1; ++t)
+        if (e + 1 + t >= lo)
+            nt_store(acc + (size_t)((e + 1 + t) % na) * slot + off, cplx<R>{out[t].x, sg * out[t].y});
 }
 
 // The level tables: gam[ml_off(k) + w][q] = (1/M) sum_{u<S} G_{S+u}[q]
