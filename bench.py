@@ -253,63 +253,72 @@ def sweep(torch, W, FP64, alpha=1.0, basis=0, plates=False):
         print(json.dumps(rec), flush=True)
 
 
-def delay_sweep(torch, W, FP32, ngs=(24, 47, 95), K=96):
+def delay_point(torch, W, FP32, ng, K=96):
     """The delayed field of the 32-direction level-4 sphere (FP32, B = 32,
-    z-lines-first plane kernels, register x lines) at longer histories: the
-    time step shrunk so that N_g = 24, 47 or 95, each marched with delay mode
-    0 (the k-space temporal sum: in time blocks of 7 steps where N_g <= 32,
-    else over all N_g stored spectra at every step) and mode 1 (multilevel
-    time blocks).  K steps are timed after N_g + 104 untimed ones (every level
-    has passed at least twice; K = 96 is two passes of the 48-step level);
-    per point the right-hand-side (delayed field) time per step from the
-    march's phase events, the HBM bytes per step and rate of the delayed-field
+    z-lines-first plane kernels, register x lines) with the time step shrunk
+    so that the history holds ng steps, marched with delay mode 0 (the
+    k-space temporal sum: in time blocks of 7 steps where N_g <= 32, else
+    over all N_g stored spectra at every step) and mode 1 (multilevel time
+    blocks).  K steps are timed after N_g + 104 untimed ones (every level has
+    passed at least twice; K = 96 is two passes of the 48-step level); per
+    mode the right-hand-side (delayed field) time per step from the march's
+    phase events, the HBM bytes per step and rate of the delayed-field
     kernels (the per-step sum and the time-block or level passes) from their
-    traced launches, GMRES iterations and the whole step."""
+    traced launches, GMRES iterations and the whole step.  Returns the two
+    records."""
     import dataclasses
     from paper_1408_7060_amd._lib import F_CONTINUE_ON_NOCONV, F_IMPLICIT_STOP
-    torch.cuda.set_device(0)
     base = W.SPHERE_L4_BATCH
-    for ng in ngs:
-        wl = dataclasses.replace(base, name=f"{base.name}_ng{ng}", ng=ng)
-        first = ng + 104
-        nt = first + K
+    wl = dataclasses.replace(base, name=f"{base.name}_ng{ng}", ng=ng)
+    first = ng + 104
+    nt = first + K
+    t = time.perf_counter()
+    P = make_problem(wl, FP32, wl.batch, nt, 1e-5, flags=F_CONTINUE_ON_NOCONV | F_IMPLICIT_STOP, sync_every=4)
+    setup_s = time.perf_counter() - t
+    kh, pp = wl.incidence()
+    V = P.excitation(kh, pp, wl.sigma, wl.td)
+    recs = []
+    for mode in (0, 1):
+        d = P.tuning()
+        d.update(yz_engine=2, x_engine=1, delay_block=7)
+        P.set_tuning(d)
+        P.set_delay_mode(mode)
+        P.set_profiling(False)
+        I, _ = P.march(V, nsteps=first)
+        P.set_profiling(True, classes=["yz_delayed", "ring_far"])
+        torch.cuda.synchronize()
         t = time.perf_counter()
-        P = make_problem(wl, FP32, wl.batch, nt, 1e-5, flags=F_CONTINUE_ON_NOCONV | F_IMPLICIT_STOP, sync_every=4)
-        setup_s = time.perf_counter() - t
-        kh, pp = wl.incidence()
-        V = P.excitation(kh, pp, wl.sigma, wl.td)
-        for mode in (0, 1):
-            d = P.tuning()
-            d.update(yz_engine=2, x_engine=1, delay_block=7)
-            P.set_tuning(d)
-            P.set_delay_mode(mode)
-            P.set_profiling(False)
-            I, _ = P.march(V, nsteps=first)
-            P.set_profiling(True, classes=["yz_delayed", "ring_far"])
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            I, st = P.march_continue(V, I, first, K)
-            torch.cuda.synchronize()
-            wall = time.perf_counter() - t
-            ks = P.kernel_stats()
-            P.set_profiling(False)
-            dms = sum(ks[c]["ms"] for c in ("yz_delayed", "ring_far"))
-            dby = sum(ks[c]["bytes"] for c in ("yz_delayed", "ring_far"))
-            rec = {"point": wl.name, "ng": P.info["ng"], "mn": P.info["mn"], "batch": wl.batch,
-                   "delay_mode": mode,
-                   "delay": ("multilevel time blocks" if mode else
-                             ("time blocks of 7" if ng <= 32 else "direct sum over N_g")),
-                   "window": [first, nt - 1], "ms_per_step": round(1e3 * wall / K, 3),
-                   "time_steps_per_s": round(K / wall, 2),
-                   "ms_rhs_per_step": round(st["ms_rhs"] / K, 3),
-                   "delayed_kernels_ms_per_step": round(dms / K, 3),
-                   "delayed_GB_per_step": round(dby / K / 1e9, 2),
-                   "delayed_GBps": round(dby / (dms / 1e3) / 1e9, 1) if dms > 0 else None,
-                   "gmres_iters_per_step": round(st["total_iters"] / K, 2), "setup_s": round(setup_s, 1)}
+        I, st = P.march_continue(V, I, first, K)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t
+        ks = P.kernel_stats()
+        P.set_profiling(False)
+        dms = sum(ks[c]["ms"] for c in ("yz_delayed", "ring_far"))
+        dby = sum(ks[c]["bytes"] for c in ("yz_delayed", "ring_far"))
+        recs.append({"point": wl.name, "ng": P.info["ng"], "mn": P.info["mn"], "batch": wl.batch,
+                     "delay_mode": mode,
+                     "delay": ("multilevel time blocks" if mode else
+                               ("time blocks of 7" if ng <= 32 else "direct sum over N_g")),
+                     "window": [first, nt - 1], "ms_per_step": round(1e3 * wall / K, 3),
+                     "time_steps_per_s": round(K / wall, 2),
+                     "ms_rhs_per_step": round(st["ms_rhs"] / K, 3),
+                     "delayed_kernels_ms_per_step": round(dms / K, 3),
+                     "delayed_GB_per_step": round(dby / K / 1e9, 2),
+                     "delayed_GBps": round(dby / (dms / 1e3) / 1e9, 1) if dms > 0 else None,
+                     "gmres_iters_per_step": round(st["total_iters"] / K, 2), "setup_s": round(setup_s, 1)})
+        del I
+    P.close()
+    del V
+    torch.cuda.empty_cache()
+    return recs
+
+
+def delay_sweep(torch, W, FP32, ngs=(24, 47, 95)):
+    """delay_point at N_g = 24, 47 and 95, one JSON line per point and mode."""
+    torch.cuda.set_device(0)
+    for ng in ngs:
+        for rec in delay_point(torch, W, FP32, ng):
             print(json.dumps(rec), flush=True)
-        P.close()
-        del V, I
-        torch.cuda.empty_cache()
 
 
 def main():
@@ -337,6 +346,8 @@ def main():
     ap.add_argument("--true-residual", action="store_true",
                     help="confirm each step's convergence with a recomputed true residual (one operator "
                          "application more per step) instead of stopping on the GMRES residual estimate")
+    ap.add_argument("--no-multilevel", action="store_true",
+                    help="skip the multilevel-time-block sub-record (the 32-direction sphere at N_g = 95)")
     ap.add_argument("--delay-sweep", action="store_true",
                     help="the delayed field of the 32-direction sphere at N_g = 24, 47, 95 with the k-space temporal "
                          "sum and with multilevel time blocks")
@@ -603,6 +614,22 @@ def main():
         log(f"[bench] CFIE alpha 0.5: {K / wc:.2f} steps/s, {stc['total_iters'] / K:.2f} GMRES it/step")
         Pc.close()
         del Ic, Vc
+    if alpha == 1.0 and not large and not args.no_multilevel:
+        # the delayed field with multilevel time blocks against the k-space
+        # temporal sum, on the same sphere with a history of 95 steps
+        torch.cuda.empty_cache()
+        r0, r1 = delay_point(torch, W, FP32, 95)
+        out["multilevel"] = {"ng": r1["ng"], "window": r1["window"],
+                             "delayed_ms_per_step": {"direct_sum": r0["delayed_kernels_ms_per_step"],
+                                                     "multilevel": r1["delayed_kernels_ms_per_step"]},
+                             "delayed_GB_per_step": {"direct_sum": r0["delayed_GB_per_step"],
+                                                     "multilevel": r1["delayed_GB_per_step"]},
+                             "time_steps_per_s": {"direct_sum": r0["time_steps_per_s"],
+                                                  "multilevel": r1["time_steps_per_s"]},
+                             "delayed_speedup": round(r0["delayed_kernels_ms_per_step"] /
+                                                      r1["delayed_kernels_ms_per_step"], 3)}
+        log(f"[bench] multilevel time blocks at N_g = 95: delayed field {r0['delayed_kernels_ms_per_step']:.2f} -> "
+            f"{r1['delayed_kernels_ms_per_step']:.2f} ms per step")
     if large:
         out["cpu_baseline"] = None
         out["cpu_baseline_note"] = ("not run at this size: the oracle's set-up alone (13.7 M exact near-zone "
