@@ -232,6 +232,42 @@ def test_multilevel_resume_and_adjoint(torch):
     P.close()
 
 
+@pytest.mark.parametrize("ng", [5, 11, 23])
+def test_multilevel_few_levels(torch, ng):
+    """N_g = 5, 11, 23: one, two and three levels, the top one inside the
+    fused low-level pass (it starts the accumulator slots there); the
+    delayed field against the oracle's direct sum on sampled rows (FP64) and
+    a 50-step march (the pulse and its first crossing) against the direct
+    sum.  Later steps are left out: at N_g = 5 the EFIE march's growing mode
+    takes over (Sec. 3.1.1) and amplifies rounding alike for any change of
+    summation order (two y/z engines of the direct sum differ by 1e-7 at
+    step 89, as the multilevel and direct sums do)."""
+    wl = dataclasses.replace(W.SPHERE_L2, name=f"sphere_L2_r0.5_300MHz_ng{ng}", ng=ng, nt=50)
+    W.WORKLOADS[wl.name] = wl
+    A, p, rows, sel, vals = _oracle_rows(wl.name, 48)
+    hist, ref = _delayed_ref(wl.name, 48)
+    P = gpu_problem(wl.name, precision=0, batch=2, nt=8)
+    _with_engine(P, 2, 1)
+    P.set_delay_mode(1)
+    b = P.delayed_field(_dev(torch, hist)).cpu().numpy()[list(COLS)][:, rows]
+    e = rel(b, ref)
+    _say("multilevel delayed N_g", ng, "rel", e)
+    assert e <= 1e-12
+    P.close()
+    V = _excitation(wl.name, 50, 2, 85)
+    out = []
+    for mode in (1, 0):
+        Q = gpu_problem(wl.name, precision=0, tol=1e-13, batch=2, nt=50, flags=F_CONTINUE_ON_NOCONV)
+        _with_engine(Q, 3, 1)
+        Q.set_delay_mode(mode)
+        I, _ = Q.march(_dev(torch, V))
+        out.append(I.cpu().numpy())
+        Q.close()
+    em = rel(out[0], out[1])
+    _say("  march rel to direct", em)
+    assert np.isfinite(out[0]).all() and em <= 1e-10
+
+
 def test_delay_mode_errors(torch):
     """Mode outside 0/1: EINVAL; N_g beyond the levels' reach (95): EUNSUPPORTED."""
     P = gpu_problem(W.SPHERE_L2.name, nt=4)
