@@ -268,6 +268,28 @@ def test_multilevel_few_levels(torch, ng):
     assert np.isfinite(out[0]).all() and em <= 1e-10
 
 
+@pytest.mark.parametrize("alpha", [1.0, 0.5], ids=["efie", "cfie"])
+def test_multilevel_blif_delayed_field(torch, alpha):
+    """The BLIF (Sec. 3, Sec. 3.1.2): its non-causal kernels are folded into
+    Z_0..Z_2, the levels take the lags from 3 on (level-2 sphere, N_g = 4:
+    one level, the top one in the fused pass), against the oracle's direct
+    sum over every row, EFIE and CFIE."""
+    from gpu_cases import oracle_aim, oracle_matvec
+    name = W.SPHERE_L2.name
+    s_, A, vals, p = oracle_aim(name, alpha, 1)
+    ng = p["ng"]
+    hist = W.complex_normal(72, (ng, 1, s_.ns))
+    ref = sum(oracle_matvec(name, m, hist[m - 1], direct=False, alpha=alpha, basis=1) for m in range(1, ng + 1))
+    P = gpu_problem(name, precision=0, alpha=alpha, basis=1)
+    _with_engine(P, 2, 1)
+    P.set_delay_mode(1)
+    b = P.delayed_field(_dev(torch, hist)).cpu().numpy()
+    e = rel(b, ref)
+    _say("multilevel BLIF delayed, alpha", alpha, "N_g", ng, "rel", e)
+    assert e <= 1e-12
+    P.close()
+
+
 def test_delay_mode_errors(torch):
     """Mode outside 0/1: EINVAL; N_g beyond the levels' reach (95): EUNSUPPORTED."""
     P = gpu_problem(W.SPHERE_L2.name, nt=4)
