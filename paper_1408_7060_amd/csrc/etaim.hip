@@ -2418,6 +2418,9 @@ int etaim_create(etaim_ctx** out, const etaim_mesh* mesh, const etaim_rwg* rwg, 
     c->rz = make_radix(c->gd.L[2]);
     c->yz_engine = quad_n(c.get()) ? 2 : 0;
     c->x_engine = xreg_ok(c.get()) ? 1 : 0;
+    // histories longer than the one-level time blocks take, within the
+    // levels' reach: multilevel time blocks
+    c->delay_mode = (c->st.ng > kFarMaxNg && c->st.ng < 2 * ml_s(kMlLevels - 1)) ? 1 : 0;
     c->N3 = (size_t)c->gd.N[0] * c->gd.N[1] * c->gd.N[2];
     c->Np = (size_t)c->gd.L[0] * c->gd.L[1] * c->gd.L[2];
     c->gfold = (size_t)(c->gd.N[0] + 1) * (c->gd.N[1] + 1) * (c->gd.N[2] + 1);

@@ -109,6 +109,7 @@ def test_multilevel_delayed_field_matches_oracle(torch, name, nrows, prec, tol, 
     hist, ref = _delayed_ref(name, nrows)
     P = gpu_problem(name, precision=prec, batch=2, nt=8)
     assert P.info["ng"] == p["ng"] and P.info["mn"] == A.mn
+    assert P.delay_mode() == 1      # the default beyond the one-level time blocks' N_g <= 32
     _with_engine(P, *engine)
     P.set_delay_mode(1)
     assert P.delay_mode() == 1
