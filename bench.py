@@ -313,8 +313,8 @@ def delay_point(torch, W, FP32, ng, K=96):
     return recs
 
 
-def delay_sweep(torch, W, FP32, ngs=(24, 47, 95)):
-    """delay_point at N_g = 24, 47 and 95, one JSON line per point and mode."""
+def delay_sweep(torch, W, FP32, ngs=(24, 47, 95, 150)):
+    """delay_point at N_g = 24, 47, 95 and 150, one JSON line per point and mode."""
     torch.cuda.set_device(0)
     for ng in ngs:
         for rec in delay_point(torch, W, FP32, ng):
@@ -349,7 +349,7 @@ def main():
     ap.add_argument("--no-multilevel", action="store_true",
                     help="skip the multilevel-time-block sub-record (the 32-direction sphere at N_g = 95)")
     ap.add_argument("--delay-sweep", action="store_true",
-                    help="the delayed field of the 32-direction sphere at N_g = 24, 47, 95 with the k-space temporal "
+                    help="the delayed field of the 32-direction sphere at N_g = 24, 47, 95, 150 with the k-space temporal "
                          "sum and with multilevel time blocks")
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the bench: the sphere size and bandwidth sweep (ET-AIM only, FP64), one JSON "

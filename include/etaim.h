@@ -345,20 +345,23 @@ int etaim_adjoint_march(etaim_ctx *ctx, const void *S, void *Lambda, etaim_stats
  * blocked space-time transforms, Sec. 4; its O(log^2 N_g) temporal cost,
  * Sec. 1 and Sec. 4).  mode 0 (the default where N_g <= 32): the k-space
  * temporal sum over the stored spectra, in time blocks of
- * etaim_tuning.delay_block steps.  mode 1 (the default where 32 < N_g <= 95):
- * multilevel time blocks: the lags 1..2 are summed at every step; the lags
- * [3 * 2^k, 6 * 2^k), k = 0..4, form level k, whose share of the next
- * 3 * 2^k steps' sums is computed once those steps' last block of history is
- * stored, as a length-6 * 2^k temporal DFT convolution per spectrum point
- * (overlap-save) added to a ring of per-step accumulators; equal to mode 0
- * up to rounding.  Mode 1 is taken by the register (yz_engine 1, 2) and
- * line-pass (3) engines in eager steps (whole-step graphs are not replayed
- * while it is set; the LDS plane engine keeps the direct sum); it allocates
- * 3 * 2^K spectrum slots of accumulators and the level tables on first use
- * (K = the top level).  Changing the mode invalidates derived history
- * sums, not the history.  With ETAIM_CFIE the MFIE pass keeps level tables
- * and accumulators of its own.  Errors: EINVAL (mode not 0 or 1),
- * EUNSUPPORTED (mode 1 with N_g > 95). */
+ * etaim_tuning.delay_block steps.  mode 1 (the default where
+ * 32 < N_g <= 1055): multilevel time blocks: the lags 1..2 are summed at
+ * every step; the lags [3 * 2^k, 6 * 2^k), k = 0..4, form level k, whose
+ * share of the next 3 * 2^k steps' sums is computed once those steps' last
+ * block of history is stored, as a length-6 * 2^k temporal DFT convolution
+ * per spectrum point (overlap-save) added to a ring of per-step
+ * accumulators; the lags from 96 on form further 48-step segments
+ * [48 (j + 1), 48 (j + 2)), j = 1..20, passed with the top level over
+ * windows 48 j steps older; equal to mode 0 up to rounding.  Mode 1 is
+ * taken by the register (yz_engine 1, 2) and line-pass (3) engines in
+ * eager steps (whole-step graphs are not replayed while it is set; the LDS
+ * plane engine keeps the direct sum); it allocates 3 * 2^K spectrum slots
+ * of accumulators (K = the top level) and the level tables on first use.
+ * Changing the mode invalidates derived history sums, not the history.
+ * With ETAIM_CFIE the MFIE pass keeps level tables and accumulators of its
+ * own.  Errors: EINVAL (mode not 0 or 1), EUNSUPPORTED (mode 1 with
+ * N_g > 1055). */
 int etaim_set_delay_mode(etaim_ctx *ctx, int32_t mode);
 
 /* Current delay mode (host out). */

@@ -1306,12 +1306,20 @@ __global__ void __launch_bounds__(256) k_ring_far3(const cplx<R>* __restrict__ r
 // lags beyond ng), enter as zeros.  The accumulator ring has na = S_top
 // slots (step l in slot l mod na): the top level's pass is the first to
 // reach every step and writes its sums, the lower levels add theirs.
+// Lags from 2 S_top = 96 on are taken by further segments of the top
+// length, segment j (j >= 1) holding the lags [S_top (j + 1), S_top (j + 2)):
+// the same overlap-save pass over a window that ends S_top j steps earlier.
 constexpr int kMlBase = 3, kMlLevels = 5;  // S = 3, 6, 12, 24, 48: lags up to 95
+constexpr int kMlExtraMax = 20;            // further 48-step segments: lags up to 1055
 // levels passed together in one sweep (their windows nest), the rest alone
 constexpr int kMlFused = 3;
 __host__ __device__ constexpr int ml_s(int k) { return kMlBase << k; }
-// first of level k's 2 S_k segment spectra in the level table
+// first of level k's 2 S_k segment spectra in the level table; the further
+// segments j >= 1 of the top length follow the five levels
 __host__ __device__ constexpr int ml_off(int k) { return k == 0 ? 0 : ml_off(k - 1) + 2 * ml_s(k - 1); }
+__host__ __device__ constexpr int ml_off_extra(int j) { return ml_off(kMlLevels) + 2 * ml_s(kMlLevels - 1) * (j - 1); }
+// the largest history the levels and the further segments reach
+__host__ __device__ constexpr int ml_max_ng() { return ml_s(kMlLevels - 1) * (kMlExtraMax + 2) - 1; }
 
 template <typename R, int M>
 __device__ __forceinline__ void ml_dft(cplx<R> (&u)[M], bool inverse) {
@@ -1404,7 +1412,9 @@ __device__ __forceinline__ void ml_levels(const cplx<R> (&win)[W], cplx<R> (&out
 
 // The passes of levels K0..K1 at step e in one sweep, one spectrum point per
 // thread (slot = points of a ring slot, gstride = folded points per lag of
-// the tables, gam = the level table): the window of the last 2 S_K1 spectra
+// the tables, gam = the level table; a further segment: K0 = K1 = the top
+// level, gam shifted so that its spectra stand where the top level's do,
+// dly = its delay S_top j): the window of the last 2 S_K1 spectra
 // serves every level, their sums are added in registers (K0 first) to the
 // accumulator slots of steps e + 1 .. e + S_K1, which are loaded with the
 // window (first: the top level is K1, whose sums start those slots).  Sums of steps below lo
@@ -1415,7 +1425,8 @@ __device__ __forceinline__ void ml_levels(const cplx<R> (&win)[W], cplx<R> (&out
 template <typename R, int K0, int K1, int QN>
 __global__ void __launch_bounds__(256) k_ml_pass(const cplx<R>* __restrict__ ring, const cplx<R>* __restrict__ gam,
                                                  cplx<R>* __restrict__ acc, GridDims g, size_t slot, size_t gstride,
-                                                 int ng, int e, int na, int conj_g, int first, int lo) {
+                                                 int ng, int e, int na, int conj_g, int first, int lo,
+                                                 int dly) {
     constexpr int S1 = ml_s(K1), W = 2 * S1;
     const size_t off = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
     if (off >= slot) return;
@@ -1424,7 +1435,7 @@ __global__ void __launch_bounds__(256) k_ml_pass(const cplx<R>* __restrict__ rin
     cplx<R> win[W];
 #pragma unroll
     for (int j = 0; j < W; ++j) {
-        const int h = e - W + 1 + j;
+        const int h = e - dly - W + 1 + j;
         cplx<R> v{0, 0};
         if (h >= 0 && e - h < ng) v = nt_load(ring + (size_t)(h % ng) * slot + off);
         win[j] = cplx<R>{v.x, sg * v.y};
@@ -1446,23 +1457,30 @@ __global__ void __launch_bounds__(256) k_ml_pass(const cplx<R>* __restrict__ rin
 
 // The level tables: gam[ml_off(k) + w][q] = (1/M) sum_{u<S} G_{S+u}[q]
 // exp(-2 pi i w u / M), M = 2 S = 2 S_k, for every folded point q, with
-// G_m = 0 beyond m = ng (FP64 arithmetic on the FP64 Green table).
+// G_m = 0 beyond m = ng (FP64 arithmetic on the FP64 Green table); the
+// further segments j at ml_off_extra(j), from G_{S_top (j + 1) + u}.
 template <typename R>
-__global__ void k_ml_gamma(const zd* __restrict__ G, cplx<R>* __restrict__ gam, size_t gstride, int ng, int nlev) {
+__global__ void k_ml_gamma(const zd* __restrict__ G, cplx<R>* __restrict__ gam, size_t gstride, int ng, int nlev,
+                           int nextra) {
     const size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
     if (q >= gstride) return;
-    for (int k = 0; k < nlev; ++k) {
-        const int S = ml_s(k), M = 2 * S;
+    // levels k < nlev (lag base S_k), then the further segments j = 1..nextra
+    // (lag base S_top (j + 1)), each 2 S spectra of its S lags
+    for (int k = 0; k < nlev + nextra; ++k) {
+        const int top = k >= nlev;
+        const int S = top ? ml_s(kMlLevels - 1) : ml_s(k), M = 2 * S;
+        const int base = top ? S * (k - nlev + 2) : S;
+        const int off = top ? ml_off_extra(k - nlev + 1) : ml_off(k);
         for (int w = 0; w < M; ++w) {
             double re = 0, im = 0;
-            for (int u = 0; u < S && S + u <= ng; ++u) {
+            for (int u = 0; u < S && base + u <= ng; ++u) {
                 double sn, cs;
                 sincospi(-2.0 * (double)((w * u) % M) / (double)M, &sn, &cs);
-                const zd v = G[(size_t)(S + u) * gstride + q];
+                const zd v = G[(size_t)(base + u) * gstride + q];
                 re += v.x * cs - v.y * sn;
                 im += v.x * sn + v.y * cs;
             }
-            gam[(size_t)(ml_off(k) + w) * gstride + q] = cplx<R>{(R)(re / M), (R)(im / M)};
+            gam[(size_t)(off + w) * gstride + q] = cplx<R>{(R)(re / M), (R)(im / M)};
         }
     }
 }

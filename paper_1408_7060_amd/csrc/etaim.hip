@@ -125,7 +125,8 @@ struct etaim_ctx {
     // ml_step: the step whose sum the accumulators hold complete (-1: rebuild
     // them from the ring), ml_conj: built with conj(G); the *H copies belong
     // to the CFIE's MFIE pass (PassSwap exchanges them)
-    int delay_mode = 0, ml_levels = 0, ml_na = 0, ml_step = -1, ml_conj = 0, ml_stepH = -1, ml_conjH = 0;
+    int delay_mode = 0, ml_levels = 0, ml_extra = 0, ml_na = 0, ml_step = -1, ml_conj = 0, ml_stepH = -1,
+        ml_conjH = 0;
     void *ml_gam = nullptr, *ml_acc = nullptr, *ml_gamH = nullptr, *ml_accH = nullptr;
     int* flag_h = nullptr;
     double* res_h = nullptr;  // pinned: per-column residuals [B], then per-column norms [B]
@@ -735,8 +736,7 @@ struct Ops {
     // multilevel time blocks (delay_mode 1): eager steps on the register and
     // line-pass engines, N_g within the levels' reach
     static bool ml_on(const etaim_ctx* c, bool graph) {
-        return c->delay_mode == 1 && !graph && c->yz_engine >= 1 && c->st.ng >= kMlBase &&
-               c->st.ng < 2 * ml_s(kMlLevels - 1);
+        return c->delay_mode == 1 && !graph && c->yz_engine >= 1 && c->st.ng >= kMlBase && c->st.ng <= ml_max_ng();
     }
     // level tables from the FP64 Green spectra (the MFIE's in the CFIE's
     // second pass) and the accumulator ring
@@ -745,26 +745,30 @@ struct Ops {
         const int ng = c->st.ng;
         int nlev = 0;
         while (nlev < kMlLevels && ml_s(nlev) <= ng) ++nlev;
+        // further top-length segments for the lags from 2 S_top on
+        const int st = ml_s(kMlLevels - 1);
+        const int nextra = nlev == kMlLevels ? std::max(0, (ng + 1 + st - 1) / st - 2) : 0;
         const size_t gs = 2 * c->gfold, slot = (size_t)4 * c->B * c->Np;
         const int na = ml_s(nlev - 1);
         cplx<R>* gam = nullptr;
         cplx<R>* acc = nullptr;
-        CHK(c->alloc(gam, (size_t)ml_off(nlev) * gs));
+        CHK(c->alloc(gam, (size_t)(nextra ? ml_off_extra(nextra + 1) : ml_off(nlev)) * gs));
         hipLaunchKernelGGL(k_ml_gamma<R>, dim3(blocks_for(gs)), dim3(256), 0, c->stream,
-                           c->pass ? c->ghatH64 : c->ghat64, gam, gs, ng, nlev);
+                           c->pass ? c->ghatH64 : c->ghat64, gam, gs, ng, nlev, nextra);
         HIPCHK(hipGetLastError());
         CHK(c->alloc(acc, (size_t)na * slot));
         c->ml_gam = gam;
         c->ml_acc = acc;
         c->ml_levels = nlev;
+        c->ml_extra = nextra;
         c->ml_na = na;
         c->ml_step = -1;
         return ETAIM_OK;
     }
     // the passes of levels k0..k1 at step e in one sweep (first: k1 is the
     // top level, whose sums start the accumulator slots; sums of steps below
-    // lo are not written)
-    static int ml_pass(etaim_ctx* c, int k0, int k1, int e, int conj, int first, int lo) {
+    // lo are not written); seg >= 1: the further top-length segment seg
+    static int ml_pass(etaim_ctx* c, int k0, int k1, int e, int conj, int first, int lo, int seg = 0) {
         const size_t slot = (size_t)4 * c->B * c->Np, gs = 2 * c->gfold;
         const double s = sizeof(cplx<R>), S1 = ml_s(k1);
         double gam_b = 0;
@@ -772,13 +776,16 @@ struct Ops {
         Trace t(c, ETAIM_K_RING_FAR, (2.0 * S1 + (first ? 1.0 : 2.0) * S1) * slot * s + gam_b, true);
         const dim3 grid((unsigned)((slot + 255) / 256));
         const cplx<R>* rg = (const cplx<R>*)ring(c);
-        const cplx<R>* gm = (const cplx<R>*)c->ml_gam;
+        // a further segment's spectra where the kernel looks for the top level's
+        const cplx<R>* gm = (const cplx<R>*)c->ml_gam +
+                            (seg ? (std::ptrdiff_t)(ml_off_extra(seg) - ml_off(kMlLevels - 1)) * (std::ptrdiff_t)gs : 0);
+        const int dly = seg * ml_s(kMlLevels - 1);
         cplx<R>* acc = (cplx<R>*)c->ml_acc;
         const GridDims& g = c->gd;
         const int qn = c->yz_engine == 3 ? 0 : quad_n(c);
 #define ETAIM_ML(K0, K1, QQ)                                                                                        \
     launch_timed(t, k_ml_pass<R, K0, K1, QQ>, grid, dim3(256), 0, c->stream, rg, gm, acc, g, slot, gs, c->st.ng, e, \
-                 c->ml_na, conj, first, lo)
+                 c->ml_na, conj, first, lo, dly)
 #define ETAIM_ML_Q(K0, K1)                                                                               \
     switch (qn) {                                                                                        \
         case 0: ETAIM_ML(K0, K1, 0); break;                                                              \
@@ -788,6 +795,8 @@ struct Ops {
         default: return fail(ETAIM_EUNSUPPORTED, "multilevel time blocks: no slot layout for this engine"); \
     }
         static_assert(kMlFused == 3 && kMlLevels == 5, "the pass table below covers these levels");
+        if (seg && (k0 != kMlLevels - 1 || k1 != kMlLevels - 1))
+            return fail(ETAIM_EINVAL, "multilevel time blocks: a further segment has the top length");
         const int key = 10 * k0 + k1;
         switch (key) {
             case 0: ETAIM_ML_Q(0, 0) break;
@@ -804,9 +813,9 @@ struct Ops {
     }
     // the passes due at step e (the levels k with S_k | e + 1 among `due`, a
     // bit per level), in a fixed order: the top level first (it starts the
-    // slots it reaches), then the fused low levels 0..kt, then the other
-    // levels upwards; a march and a rebuild run the same passes in the same
-    // order, so their sums round alike
+    // slots it reaches), the further top-length segments, then the fused low
+    // levels 0..kt, then the other levels upwards; a march and a rebuild run
+    // the same passes in the same order, so their sums round alike
     static int ml_event(etaim_ctx* c, int e, unsigned due, int conj, int lo) {
         const int top = c->ml_levels - 1;
         const bool top_due = (due >> top) & 1u;
@@ -814,6 +823,8 @@ struct Ops {
         for (int k = 0; k < std::min(kMlFused, c->ml_levels); ++k)
             if ((due >> k) & 1u) kt = k;
         if (top_due && top >= kMlFused) CHK(ml_pass(c, top, top, e, conj, 1, lo));
+        if (top_due)
+            for (int j = 1; j <= c->ml_extra; ++j) CHK(ml_pass(c, top, top, e, conj, 0, lo, j));
         if (kt >= 0) CHK(ml_pass(c, 0, kt, e, conj, top_due && kt == top ? 1 : 0, lo));
         for (int k = kMlFused; k < top; ++k)
             if ((due >> k) & 1u) CHK(ml_pass(c, k, k, e, conj, 0, lo));
@@ -2420,7 +2431,7 @@ int etaim_create(etaim_ctx** out, const etaim_mesh* mesh, const etaim_rwg* rwg, 
     c->x_engine = xreg_ok(c.get()) ? 1 : 0;
     // histories longer than the one-level time blocks take, within the
     // levels' reach: multilevel time blocks
-    c->delay_mode = (c->st.ng > kFarMaxNg && c->st.ng < 2 * ml_s(kMlLevels - 1)) ? 1 : 0;
+    c->delay_mode = (c->st.ng > kFarMaxNg && c->st.ng <= ml_max_ng()) ? 1 : 0;
     c->N3 = (size_t)c->gd.N[0] * c->gd.N[1] * c->gd.N[2];
     c->Np = (size_t)c->gd.L[0] * c->gd.L[1] * c->gd.L[2];
     c->gfold = (size_t)(c->gd.N[0] + 1) * (c->gd.N[1] + 1) * (c->gd.N[2] + 1);
@@ -2728,9 +2739,9 @@ int etaim_set_profiling_mask(etaim_ctx* c, uint32_t classes) {
 int etaim_set_delay_mode(etaim_ctx* c, int32_t mode) {
     CHK(check_ctx(c));
     if (mode != 0 && mode != 1) return fail(ETAIM_EINVAL, "delay mode must be 0 or 1");
-    if (mode == 1 && c->st.ng >= 2 * ml_s(kMlLevels - 1))
+    if (mode == 1 && c->st.ng > ml_max_ng())
         return fail(ETAIM_EUNSUPPORTED, "multilevel time blocks reach lags up to " +
-                                            std::to_string(2 * ml_s(kMlLevels - 1) - 1) + ", N_g is " +
+                                            std::to_string(ml_max_ng()) + ", N_g is " +
                                             std::to_string(c->st.ng));
     if (c->delay_mode != mode) {
         c->delay_mode = mode;

@@ -10,7 +10,9 @@ share of the next 3 2^k steps' sums is a temporal DFT convolution
 * level-4 sphere (7680 RWG, 48^3 grid), N_g = 47, M_n = 13: levels of 3, 6,
   12 and 24 steps, the top one ending inside the history (lags 24..47);
 * level-2 sphere (480 RWG, 16^3 grid), N_g = 95, M_n = 81: all five levels
-  (the top one's 96-point transforms), the near history live over 81 lags.
+  (the top one's 96-point transforms), the near history live over 81 lags;
+* the same sphere with N_g = 150: two further 48-step segments (lags
+  96..143 and 144..150) past the five levels.
 
 The oracle sums every lag directly (near and far part) on sampled rows, so
 each level's transform, its product with the lag segment's spectrum and
@@ -98,12 +100,14 @@ def _delayed_ref(name, nrows, alpha=1.0):
     return hist, np.array(ref)
 
 
-CASES = [(L4.name, 48, 0, 1e-12), (L4.name, 48, 1, 1e-5), (L2.name, 48, 0, 1e-12), (L2.name, 48, 1, 1e-5)]
+L2X = W.SPHERE_L2_NG150
+CASES = [(L4.name, 48, 0, 1e-12), (L4.name, 48, 1, 1e-5), (L2.name, 48, 0, 1e-12), (L2.name, 48, 1, 1e-5),
+         (L2X.name, 48, 0, 1e-12), (L2X.name, 48, 1, 1e-5)]
 
 
 @pytest.mark.parametrize("engine", [(2, 1), (3, 1)], ids=["zlines", "lines"])
 @pytest.mark.parametrize("name,nrows,prec,tol", CASES, ids=["L4ng47_fp64", "L4ng47_fp32", "L2ng95_fp64",
-                                                             "L2ng95_fp32"])
+                                                             "L2ng95_fp32", "L2ng150_fp64", "L2ng150_fp32"])
 def test_multilevel_delayed_field_matches_oracle(torch, name, nrows, prec, tol, engine):
     A, p, rows, sel, vals = _oracle_rows(name, nrows)
     hist, ref = _delayed_ref(name, nrows)
@@ -152,8 +156,8 @@ def _excitation(name, nt, nb, seed):
     return excitation.excitation(s, nt, p["dt"], kh, pp, wl.sigma, wl.td, wl.f0)
 
 
-def _march(torch, V, mode, engine, prec=0, tol=1e-13, nt=None, alpha=1.0):
-    P = gpu_problem(L2.name, precision=prec, tol=tol, batch=V.shape[1], nt=nt or V.shape[0],
+def _march(torch, V, mode, engine, prec=0, tol=1e-13, nt=None, alpha=1.0, name=L2.name):
+    P = gpu_problem(name, precision=prec, tol=tol, batch=V.shape[1], nt=nt or V.shape[0],
                     flags=F_CONTINUE_ON_NOCONV, alpha=alpha)
     _with_engine(P, *engine)
     P.set_delay_mode(mode)
@@ -179,6 +183,18 @@ def test_multilevel_march_equals_direct_sum(torch, engine):
     e32 = rel(I32, I0)
     _say("  fp32 multilevel vs fp64 direct", e32)
     assert e32 <= 1e-4
+
+
+def test_multilevel_past_lag_95_march_equals_direct_sum(torch):
+    """N_g = 150: the five levels and two further 48-step segments (lags
+    96..143 and 144..150) over a 250-step march."""
+    nt = 250
+    V = _excitation(L2X.name, nt, 1, 86)
+    I1, _ = _march(torch, V, 1, (3, 1), name=L2X.name)
+    I0, _ = _march(torch, V, 0, (3, 1), name=L2X.name)
+    e = rel(I1, I0)
+    _say("multilevel march N_g 150 rel to direct", e)
+    assert np.isfinite(I1).all() and e <= 1e-10
 
 
 def test_multilevel_cfie_march_equals_direct_sum(torch):
@@ -292,19 +308,10 @@ def test_multilevel_blif_delayed_field(torch, alpha):
 
 
 def test_delay_mode_errors(torch):
-    """Mode outside 0/1: EINVAL; N_g beyond the levels' reach (95): EUNSUPPORTED."""
+    """Mode outside 0/1: EINVAL, the mode unchanged."""
     P = gpu_problem(W.SPHERE_L2.name, nt=4)
     with pytest.raises(Exception) as ei:
         P.set_delay_mode(2)
     assert ei.value.code == -1
     assert P.delay_mode() == 0
     P.close()
-    wl = dataclasses.replace(W.SPHERE_L2, name="sphere_L2_r0.5_300MHz_ng96", ng=96, nt=4)
-    W.WORKLOADS[wl.name] = wl
-    Q = gpu_problem(wl.name, nt=4)
-    assert Q.info["ng"] == 96
-    with pytest.raises(Exception) as ei:
-        Q.set_delay_mode(1)
-    assert ei.value.code == -7
-    assert Q.delay_mode() == 0
-    Q.close()

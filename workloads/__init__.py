@@ -442,10 +442,13 @@ SPHERE_L4_NG47 = Workload("sphere_L4_r1_600MHz_ng47", level=4, radius=1.0, f0=60
                           nt=200, grid=48, near_lambda=0.3, ng=47, rotate_seed=0)
 SPHERE_L2_NG95 = Workload("sphere_L2_r0.5_300MHz_ng95", level=2, radius=0.5, f0=300e6, frac_bw=0.20,
                           nt=300, grid=16, near_lambda=0.3, ng=95)
+# ... and with N_g = 150: two further 48-step segments past lag 95
+SPHERE_L2_NG150 = Workload("sphere_L2_r0.5_300MHz_ng150", level=2, radius=0.5, f0=300e6, frac_bw=0.20,
+                           nt=300, grid=16, near_lambda=0.3, ng=150)
 
 WORKLOADS = {w.name: w for w in (SPHERE_L2, SPHERE_L4, SPHERE_L4_BATCH, SPHERE_L4_ADJ, SPHERE_L3,
                                  SPHERE_L2_NARROW, COMPOSITE, COMPOSITE_SMALL, PLATE_1M, SPHERE_L4_NG47,
-                                 SPHERE_L2_NG95)}
+                                 SPHERE_L2_NG95, SPHERE_L2_NG150)}
 
 # size and bandwidth sweep of spheres (ET-AIM only): the band's top fixed at
 # f_max = 300 MHz while chi = f_max / f_bw varies (f_c = f_max - f_bw), and
