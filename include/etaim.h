@@ -346,7 +346,8 @@ int etaim_adjoint_march(etaim_ctx *ctx, const void *S, void *Lambda, etaim_stats
  * Sec. 1 and Sec. 4).  mode 0 (the default where N_g <= 32): the k-space
  * temporal sum over the stored spectra, in time blocks of
  * etaim_tuning.delay_block steps.  mode 1 (the default where
- * 32 < N_g <= 1055): multilevel time blocks: the lags 1..2 are summed at
+ * 32 < N_g <= 1055 and its buffers take at most half the device memory
+ * left free by etaim_create): multilevel time blocks: the lags 1..2 are summed at
  * every step; the lags [3 * 2^k, 6 * 2^k), k = 0..4, form level k, whose
  * share of the next 3 * 2^k steps' sums is computed once those steps' last
  * block of history is stored, as a length-6 * 2^k temporal DFT convolution

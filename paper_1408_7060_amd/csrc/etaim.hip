@@ -2444,6 +2444,21 @@ int etaim_create(etaim_ctx** out, const etaim_mesh* mesh, const etaim_rwg* rwg, 
     c->stream = (hipStream_t)hip_stream;
     rc = device_setup(c.get());
     if (rc) return rc;
+    if (c->delay_mode == 1) {
+        // the multilevel buffers (accumulators of S_top slots and the level
+        // tables, per far pass) must leave room for the march's others: else
+        // the direct sum stays the default
+        const int ng = c->st.ng, st = ml_s(kMlLevels - 1);
+        int nlev = 0;
+        while (nlev < kMlLevels && ml_s(nlev) <= ng) ++nlev;
+        const int nextra = nlev == kMlLevels ? std::max(0, (ng + 1 + st - 1) / st - 2) : 0;
+        const double cs = c->prm.precision == ETAIM_FP32 ? 8.0 : 16.0;
+        const double need = (c->st.cfie ? 2.0 : 1.0) * cs *
+                            ((double)ml_s(nlev - 1) * 4.0 * c->B * c->Np +
+                             (double)(nextra ? ml_off_extra(nextra + 1) : ml_off(nlev)) * 2.0 * c->gfold);
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess || need > 0.5 * (double)fr) c->delay_mode = 0;
+    }
     *out = c.release();
     return ETAIM_OK;
 }
