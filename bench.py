@@ -313,6 +313,53 @@ def delay_point(torch, W, FP32, ng, K=96):
     return recs
 
 
+def plate_history(torch, W, FP64, sizes=((16.0, 192),), chi=3.0):
+    """The plate sweep's recipe beyond its largest size: a 16 m plate at
+    chi = 3 (N_g above the one-level time blocks' 32), its whole march in
+    FP64 on the line-pass y/z engine with the delayed field as the direct
+    sum (delay mode 0) and with multilevel time blocks (mode 1); per mode
+    the right-hand-side, solve and march time, iterations, N_g and N_t."""
+    from paper_1408_7060_amd._lib import F_CONTINUE_ON_NOCONV
+    torch.cuda.set_device(0)
+    for size, g in sizes:
+        wl = W.plate_sweep_workload(size, g, chi)
+        t = time.perf_counter()
+        P = make_problem(wl, FP64, 1, wl.nt, 1e-6, flags=F_CONTINUE_ON_NOCONV)
+        setup_s = time.perf_counter() - t
+        kh, pp = wl.incidence()
+        V = P.excitation(kh, pp, wl.sigma, wl.td)
+        # the line-pass y/z engine for both modes: the multilevel sums need an
+        # engine with a ring layout of its own (the LDS plane engine, which
+        # this grid would take by default, keeps the direct sum)
+        d = P.tuning()
+        d["yz_engine"] = 3
+        P.set_tuning(d)
+        out = {}
+        for mode in (0, 1):
+            P.set_delay_mode(mode)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            I, st = P.march(V)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t
+            out[mode] = I.cpu().numpy()
+            nt = st["steps_done"]
+            print(json.dumps({"point": wl.name, "ns": P.ns, "chi": chi, "grid": wl.grid, "ng": P.info["ng"],
+                              "mn": P.info["mn"], "nt": nt, "delay_mode": mode,
+                              "delay": "multilevel time blocks" if mode else "direct sum over N_g",
+                              "gmres_iters_per_step": round(st["total_iters"] / max(nt, 1), 2),
+                              "ms_rhs_per_step": round(st["ms_rhs"] / max(nt, 1), 3),
+                              "ms_solve_per_step": round(st["ms_solve"] / max(nt, 1), 3),
+                              "march_s": round(wall, 3), "setup_s": round(setup_s, 1)}), flush=True)
+            del I
+        d = out[1] - out[0]
+        print(json.dumps({"point": wl.name, "multilevel_vs_direct_rel_l2":
+                          float(np.linalg.norm(d) / np.linalg.norm(out[0]))}), flush=True)
+        P.close()
+        del V
+        torch.cuda.empty_cache()
+
+
 def delay_sweep(torch, W, FP32, ngs=(24, 47, 95, 150)):
     """delay_point at N_g = 24, 47, 95 and 150, one JSON line per point and mode."""
     torch.cuda.set_device(0)
@@ -348,6 +395,9 @@ def main():
                          "application more per step) instead of stopping on the GMRES residual estimate")
     ap.add_argument("--no-multilevel", action="store_true",
                     help="skip the multilevel-time-block sub-record (the 32-direction sphere at N_g = 95)")
+    ap.add_argument("--plate-history", action="store_true",
+                    help="a 16 m plate at chi = 3 (N_g > 32), marched with the direct history sum and with "
+                         "multilevel time blocks")
     ap.add_argument("--delay-sweep", action="store_true",
                     help="the delayed field of the 32-direction sphere at N_g = 24, 47, 95, 150 with the k-space temporal "
                          "sum and with multilevel time blocks")
@@ -375,6 +425,8 @@ def main():
     from paper_1408_7060_amd import FP32, FP64
     if args.delay_sweep:
         return delay_sweep(torch, W, FP32)
+    if args.plate_history:
+        return plate_history(torch, W, FP64)
     if args.sweep:
         return sweep(torch, W, FP64, args.alpha, 1 if args.blif else 0, args.plates)
     from paper_1408_7060_amd._lib import F_CONTINUE_ON_NOCONV, F_GRAPH, F_IMPLICIT_STOP, F_RESIDUAL_CHECK
