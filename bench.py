@@ -316,9 +316,9 @@ def delay_point(torch, W, FP32, ng, K=96):
 def plate_history(torch, W, FP64, sizes=((16.0, 192),), chi=3.0):
     """The plate sweep's recipe beyond its largest size: a 16 m plate at
     chi = 3 (N_g above the one-level time blocks' 32), its whole march in
-    FP64 on the line-pass y/z engine with the delayed field as the direct
-    sum (delay mode 0) and with multilevel time blocks (mode 1); per mode
-    the right-hand-side, solve and march time, iterations, N_g and N_t."""
+    FP64 (the default engines) with the delayed field as the direct sum
+    (delay mode 0) and with multilevel time blocks (mode 1); per mode the
+    right-hand-side, solve and march time, iterations, N_g and N_t."""
     from paper_1408_7060_amd._lib import F_CONTINUE_ON_NOCONV
     torch.cuda.set_device(0)
     for size, g in sizes:
@@ -328,12 +328,6 @@ def plate_history(torch, W, FP64, sizes=((16.0, 192),), chi=3.0):
         setup_s = time.perf_counter() - t
         kh, pp = wl.incidence()
         V = P.excitation(kh, pp, wl.sigma, wl.td)
-        # the line-pass y/z engine for both modes: the multilevel sums need an
-        # engine with a ring layout of its own (the LDS plane engine, which
-        # this grid would take by default, keeps the direct sum)
-        d = P.tuning()
-        d["yz_engine"] = 3
-        P.set_tuning(d)
         out = {}
         for mode in (0, 1):
             P.set_delay_mode(mode)

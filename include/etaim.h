@@ -355,9 +355,8 @@ int etaim_adjoint_march(etaim_ctx *ctx, const void *S, void *Lambda, etaim_stats
  * accumulators; the lags from 96 on form further 48-step segments
  * [48 (j + 1), 48 (j + 2)), j = 1..20, passed with the top level over
  * windows 48 j steps older; equal to mode 0 up to rounding.  Mode 1 is
- * taken by the register (yz_engine 1, 2) and line-pass (3) engines in
- * eager steps (whole-step graphs are not replayed while it is set; the LDS
- * plane engine keeps the direct sum); it allocates 3 * 2^K spectrum slots
+ * taken by every y/z engine in eager steps (whole-step graphs are not
+ * replayed while it is set); it allocates 3 * 2^K spectrum slots
  * of accumulators (K = the top level) and the level tables on first use.
  * Changing the mode invalidates derived history sums, not the history.
  * With ETAIM_CFIE the MFIE pass keeps level tables and accumulators of its

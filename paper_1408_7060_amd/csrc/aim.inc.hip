@@ -326,7 +326,8 @@ __global__ void __launch_bounds__(kPlaneThreads) k_yz_delayed(const cplx<R>* __r
                                                               const cplx<R>* __restrict__ G, cplx<R>* __restrict__ A,
                                                               const cplx<R>* __restrict__ twy_g,
                                                               const cplx<R>* __restrict__ twz_g, Radix ry, Radix rz,
-                                                              GridDims g, int ng, int cur, int nm, int conj_g) {
+                                                              GridDims g, int ng, int cur, int nm, int conj_g,
+                                                              const cplx<R>* __restrict__ Fj) {
     cplx<R>*buf, *twy, *twz;
     plane_smem<R>(g, twy_g, twz_g, buf, twy, twz);
     const int kx = blockIdx.x, bc = blockIdx.y;
@@ -340,7 +341,8 @@ __global__ void __launch_bounds__(kPlaneThreads) k_yz_delayed(const cplx<R>* __r
     for (int e = threadIdx.x; e < Lz * Ly; e += blockDim.x) {
         const int kz = e / Ly, ky = e - kz * Ly;
         const size_t gi = goff + (size_t)fold(kz, Lz) * gy + fold(ky, Ly);
-        cplx<R> acc{0, 0};
+        // Fj: the older history's part of the sum, formed beforehand
+        cplx<R> acc = Fj ? Fj[roff + e] : cplx<R>{0, 0};
         for (int m = 1; m <= nm; ++m) {
             int s = (cur - m) % ng;
             if (s < 0) s += ng;

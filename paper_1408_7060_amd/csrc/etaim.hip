@@ -733,10 +733,10 @@ struct Ops {
         c->far_slots = pb;
         return ETAIM_OK;
     }
-    // multilevel time blocks (delay_mode 1): eager steps on the register and
-    // line-pass engines, N_g within the levels' reach
+    // multilevel time blocks (delay_mode 1): eager steps, N_g within the
+    // levels' reach
     static bool ml_on(const etaim_ctx* c, bool graph) {
-        return c->delay_mode == 1 && !graph && c->yz_engine >= 1 && c->st.ng >= kMlBase && c->st.ng <= ml_max_ng();
+        return c->delay_mode == 1 && !graph && c->st.ng >= kMlBase && c->st.ng <= ml_max_ng();
     }
     // level tables from the FP64 Green spectra (the MFIE's in the CFIE's
     // second pass) and the accumulator ring
@@ -782,7 +782,9 @@ struct Ops {
         const int dly = seg * ml_s(kMlLevels - 1);
         cplx<R>* acc = (cplx<R>*)c->ml_acc;
         const GridDims& g = c->gd;
-        const int qn = c->yz_engine == 3 ? 0 : quad_n(c);
+        // parity quadrants for the register plane engines, plain slots for
+        // the LDS plane and line-pass engines
+        const int qn = c->yz_engine == 1 || c->yz_engine == 2 ? quad_n(c) : 0;
 #define ETAIM_ML(K0, K1, QQ)                                                                                        \
     launch_timed(t, k_ml_pass<R, K0, K1, QQ>, grid, dim3(256), 0, c->stream, rg, gm, acc, g, slot, gs, c->st.ng, e, \
                  c->ml_na, conj, first, lo, dly)
@@ -995,7 +997,7 @@ struct Ops {
                 Trace t(c, ETAIM_K_YZ_DELAYED, bytes, true);
                 launch_timed(t, k_yz_delayed<R>, dim3(g.L[0], 4 * c->B), dim3(kPlaneThreads), plane_lds(c), c->stream,
                              (const cplx<R>*)ring(c), ghat(c), A(c), tw(c, 1), tw(c, 2), c->ry, c->rz, g, c->st.ng,
-                             cur, nm, conj);
+                             cur, ml ? nmx : nm, conj, Fml);
             }
         }
         HIPCHK(hipGetLastError());

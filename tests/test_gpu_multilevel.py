@@ -105,7 +105,7 @@ CASES = [(L4.name, 48, 0, 1e-12), (L4.name, 48, 1, 1e-5), (L2.name, 48, 0, 1e-12
          (L2X.name, 48, 0, 1e-12), (L2X.name, 48, 1, 1e-5)]
 
 
-@pytest.mark.parametrize("engine", [(2, 1), (3, 1)], ids=["zlines", "lines"])
+@pytest.mark.parametrize("engine", [(2, 1), (3, 1), (0, 0)], ids=["zlines", "lines", "planes"])
 @pytest.mark.parametrize("name,nrows,prec,tol", CASES, ids=["L4ng47_fp64", "L4ng47_fp32", "L2ng95_fp64",
                                                              "L2ng95_fp32", "L2ng150_fp64", "L2ng150_fp32"])
 def test_multilevel_delayed_field_matches_oracle(torch, name, nrows, prec, tol, engine):
@@ -166,7 +166,7 @@ def _march(torch, V, mode, engine, prec=0, tol=1e-13, nt=None, alpha=1.0, name=L
     return I.cpu().numpy(), st
 
 
-@pytest.mark.parametrize("engine", [(2, 1), (3, 1)], ids=["zlines", "lines"])
+@pytest.mark.parametrize("engine", [(2, 1), (3, 1), (0, 0)], ids=["zlines", "lines", "planes"])
 def test_multilevel_march_equals_direct_sum(torch, engine):
     """240 steps at N_g = 95 (the accumulator ring of 51 slots wraps four
     times; every level passes at least twice past the history's length)."""
