@@ -419,7 +419,8 @@ typedef struct {
                                 step): at step r0 + j of a block the terms that read history older
                                 than r0 are summed for the whole block in one pass at r0, the j
                                 terms of the block's own steps at the step; equal to the direct sum
-                                up to rounding (default 6; used when N_g <= 32) */
+                                up to rounding (default 6; used when N_g <= 32 in delay
+                                mode 0, etaim_set_delay_mode) */
     int32_t interp_engine;   /* interpolation + near zone: 0 one wavefront per basis gathering its
                                 stencil from HBM/L2 (interp_waves bases per block), 1 by grid tiles:
                                 a block loads a tile's node box of a group of columns into LDS and
